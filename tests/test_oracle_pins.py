@@ -1,0 +1,417 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+Each test fixes one piece of the oracle to something independent: published
+known-answer values, library routines (scipy), closed forms, brute force,
+quadrature, finite differences or exact discrete identities.  These run on
+the CPU only.
+"""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import special, stats
+
+import oracle as O
+import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------------------
+# random streams
+# ---------------------------------------------------------------------------
+
+def test_philox_known_answers():
+    """Random123 known-answer vectors of Philox4x32-10 (Salmon et al., SC'11)."""
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(h, 16) for h in r]
+        out = O.philox(v[0:4], v[4:6])
+        assert list(out) == v[6:10]
+
+
+def test_uniform_bit_layout_and_range():
+    """U = ((w_a << 20 | w_b >> 12) + 1/2) 2^-52 on the Philox words of
+    counter (m_lo, m_hi, i, r>>1) under key (seed_lo, seed_hi ^ stream)."""
+    seed, stream, m, i = 0x123456789ABCDEF, 3, (7 << 32) + 11, 5
+    for r in range(6):
+        w = O.philox([m & 0xFFFFFFFF, m >> 32, i, r >> 1],
+                     [seed & 0xFFFFFFFF, (seed >> 32) ^ stream])
+        a, b = (w[2], w[3]) if r & 1 else (w[0], w[1])
+        n = (int(a) << 20) | (int(b) >> 12)
+        assert O.uniform(seed, stream, m, i, r) == (n + 0.5) * 2.0 ** -52
+    u = np.array([O.uniform(0, 0, m, 0, r) for m in range(4000) for r in range(8)])
+    assert u.min() > 0.0 and u.max() < 1.0
+    n = u.size
+    assert abs(u.mean() - 0.5) < 5 * math.sqrt(1 / 12 / n)
+    assert abs(u.var() - 1 / 12) < 5 * math.sqrt(1 / 180 / n)
+    # distinct streams / indices give distinct words
+    assert O.uniform(0, 0, 1, 0, 0) != O.uniform(0, 1, 1, 0, 0)
+    assert O.uniform(0, 0, 1, 0, 0) != O.uniform(0, 0, 1, 1, 0)
+
+
+# ---------------------------------------------------------------------------
+# laws
+# ---------------------------------------------------------------------------
+
+def test_norm_icdf_matches_scipy_ndtri():
+    us = np.concatenate([np.logspace(-300, -1, 200), np.linspace(0.01, 0.99, 199),
+                         1 - np.logspace(-15, -2, 100), [2.0 ** -53, 0.5, 1 - 2.0 ** -53]])
+    for u in us:
+        a, b = O.norm_icdf(float(u)), float(special.ndtri(u))
+        assert abs(a - b) <= 4e-15 * max(1.0, abs(b)), (u, a, b)
+
+
+def test_logistic_law_matches_scipy():
+    for u in np.linspace(1e-6, 1 - 1e-6, 101):
+        assert abs(O.logistic_icdf(u) - stats.logistic.ppf(u)) <= 1e-13 * max(1, abs(stats.logistic.ppf(u)))
+    for x in np.linspace(-30, 30, 61):
+        assert abs(O.logistic_cdf(x) - special.expit(x)) <= 2e-16
+
+
+def test_logistic_samples_characteristic_function():
+    """E[cos(aX)] = pi a / sinh(pi a) for the standard logistic law."""
+    x = O.sample_points(1, 0, 1, 0, 1 << 16)[:, 0]
+    for a in (0.5, 1.0, 2.0):
+        exact = math.pi * a / math.sinh(math.pi * a)
+        v = np.cos(a * x)
+        assert abs(v.mean() - exact) < 5 * v.std() / math.sqrt(x.size)
+    assert abs(math.pi / math.sinh(math.pi) - 0.2720290549815) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# index sets (Sec. 2.3.3)
+# ---------------------------------------------------------------------------
+
+def _hyper_count_formula(d, deg):
+    """#Gamma_H(DEG) over N^d from the prime-factorisation formula of Sec. 2.3.3."""
+    def nfactor(g, dd):  # number of ordered ways to write g as a product of dd factors >= 1
+        out, n, p = 1, g, 2
+        while p * p <= n:
+            v = 0
+            while n % p == 0:
+                n //= p
+                v += 1
+            if v:
+                out *= math.comb(v + dd - 1, dd - 1)
+            p += 1
+        if n > 1:
+            out *= dd
+        return out
+
+    def g1(dd):
+        return sum(nfactor(g, dd) for g in range(2, deg + 1)) + 1
+
+    return g1(d) + sum(math.comb(d, c) * g1(d - c) for c in range(1, d)) + 1
+
+
+def test_paper_index_set_counts():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "paper_index_set_counts.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) >= 45
+    for r in rows:
+        d, kind, deg, cnt = int(r[0]), r[1], int(r[2]), int(r[3])
+        if kind == "total":
+            assert math.comb(deg + d, d) == cnt
+            if cnt < 200_000:
+                assert O.count_set(d, "total", deg, nonneg=True) == cnt
+        else:
+            assert _hyper_count_formula(d, deg) == cnt
+            assert O.count_set(d, "hc_max", deg, nonneg=True) == cnt
+
+
+def _brute(d, kind, level):
+    out = []
+    for k in itertools.product(range(-level, level + 1), repeat=d):
+        a = [abs(v) for v in k]
+        if kind == "tensor":
+            ok = max(a) <= level
+        elif kind == "hc_max":
+            ok = math.prod(max(1, v) for v in a) <= level
+        elif kind == "hc_1p":
+            ok = math.prod(1 + v for v in a) <= level
+        else:
+            ok = sum(a) <= level
+        if ok:
+            out.append(k)
+    return out
+
+
+@pytest.mark.parametrize("d,kind,level", [(1, "tensor", 5), (2, "tensor", 4), (3, "tensor", 2),
+                                          (2, "hc_max", 4), (3, "hc_max", 6), (4, "hc_max", 3),
+                                          (2, "hc_1p", 8), (3, "hc_1p", 12), (4, "hc_1p", 6),
+                                          (3, "total", 4)])
+def test_enumeration_brute_force(d, kind, level):
+    full = _brute(d, kind, level)
+    assert O.count_set(d, kind, level) == len(full)
+    reps = O.enumerate_set(d, kind, level)
+    # representatives: zero vector plus one of each pair {k, -k}, first non-zero > 0
+    exp = sorted(k for k in full if all(v == 0 for v in k) or next(v for v in k if v) > 0)
+    got = [tuple(int(v) for v in r) for r in reps]
+    assert got == exp                      # same set, lexicographic order
+    assert 2 * len(got) - 1 == len(full)   # |Gamma| real functions
+    # the Z^d count equals sum over the N^d set of 2^{nnz}
+    nn = [k for k in full if min(k) >= 0]
+    assert sum(2 ** sum(1 for v in k if v) for k in nn) == len(full)
+    # downward closed in |k_l|
+    s = set(full)
+    for k in full:
+        for l in range(d):
+            if k[l]:
+                kk = list(k)
+                kk[l] -= 1 if k[l] > 0 else -1
+                assert tuple(kk) in s
+
+
+def test_configuration_set_sizes():
+    assert O.count_set(2, "tensor", 4) == 81
+    assert O.count_set(2, "hc_max", 4) == 49
+    assert O.count_set(6, "hc_max", 16) == 169_209
+    assert O.count_set(10, "hc_1p", 32) == 85_485
+    assert O.count_set(16, "hc_1p", 32) == 599_969
+
+
+# ---------------------------------------------------------------------------
+# basis (Lemma 2.1 / Prop. 2.2 with the Fourier basis)
+# ---------------------------------------------------------------------------
+
+def _logistic_pdf(x):
+    e = np.exp(-np.abs(x))
+    return e / (1 + e) ** 2
+
+
+@pytest.mark.parametrize("d,K,nodes", [(1, 6, 6001), (2, 2, 1201)])
+def test_orthonormality_by_quadrature(d, K, nodes):
+    """Gram matrix under nu by a trapezoid rule in x-space on [-40, 40]^d."""
+    reps = O.enumerate_set(d, "tensor", K)
+    xs = np.linspace(-40, 40, nodes)
+    wt = np.full(nodes, xs[1] - xs[0])
+    wt[0] = wt[-1] = wt[0] / 2
+    wt = wt * _logistic_pdf(xs)
+    if d == 1:
+        X = xs[:, None]
+        Wt = wt
+    else:
+        X = np.stack(np.meshgrid(xs, xs, indexing="ij"), -1).reshape(-1, 2)
+        Wt = np.outer(wt, wt).reshape(-1)
+    keep = Wt > 1e-300
+    X, Wt = X[keep], Wt[keep]
+    nf = O.nfuncs(reps)
+    # basis values from the oracle at every node (direct cos/sin)
+    Phi = np.empty((X.shape[0], nf))
+    for p in range(X.shape[0]):
+        Phi[p] = O.basis_values(reps, X[p])
+    G = Phi.T @ (Phi * Wt[:, None])
+    assert np.abs(G - np.eye(nf)).max() < 1e-10
+
+
+def _tensor_grid(d, n):
+    g = (np.arange(n) + 0.5) / n
+    U = np.stack(np.meshgrid(*([g] * d), indexing="ij"), -1).reshape(-1, d)
+    return U
+
+
+@pytest.mark.parametrize("d,K,n", [(1, 7, 16), (2, 4, 10), (3, 2, 6)])
+def test_projection_recovers_trig_polynomial(d, K, n):
+    """Discrete orthogonality on the grid u=(j+1/2)/n, n > 2K: projecting
+    s = sum c_k phi_k recovers c exactly."""
+    reps = O.enumerate_set(d, "tensor", K)
+    nf = O.nfuncs(reps)
+    c = W.synthetic_alpha(nf, 1, seed=7)[0]
+    U = _tensor_grid(d, n)
+    X = np.log(U) - np.log1p(-U)
+    s = np.array([O.basis_values(reps, x) @ c for x in X])
+    a = O.project(reps, X, s)
+    assert np.abs(a - c).max() < 1e-13
+
+
+def test_projection_matches_numpy_fft():
+    """The projection on a tensor grid equals a DFT of the samples."""
+    d, K, n = 2, 3, 9
+    reps = O.enumerate_set(d, "tensor", K)
+    rng = np.random.default_rng(1)
+    s = rng.standard_normal(n * n)
+    U = _tensor_grid(d, n)
+    X = np.log(U) - np.log1p(-U)
+    a = O.project(reps, X, s)
+    grid = s.reshape(n, n)
+    # sum_j s_j exp(-2 pi i k.(j+1/2)/n) / n^d
+    F = np.fft.fft2(grid) / n ** 2
+    for r in range(1, reps.shape[0]):
+        k = reps[r]
+        z = F[k[0] % n, k[1] % n] * np.exp(-1j * np.pi * (k[0] + k[1]) / n)
+        # alpha_cos = sqrt2 Re(sum s e^{+i th})/n^2 = sqrt2 Re(conj z), alpha_sin = sqrt2 Im(conj z)
+        assert abs(a[2 * r - 1] - math.sqrt(2) * z.real) < 1e-13
+        assert abs(a[2 * r] + math.sqrt(2) * z.imag) < 1e-13
+    assert abs(a[0] - s.mean()) < 1e-14
+
+
+def test_expansion_gradient_by_finite_differences():
+    d = 3
+    reps = O.enumerate_set(d, "hc_1p", 8)
+    alpha = W.synthetic_alpha(O.nfuncs(reps), 1, seed=3)[0]
+    x = W.logistic_points(5, d, seed=2)
+    y, g = O.evaluate(reps, alpha, x, grad=True)
+    h = 1e-5
+    for l in range(d):
+        e = np.zeros(d)
+        e[l] = h
+        fd = (O.evaluate(reps, alpha, x + e) - O.evaluate(reps, alpha, x - e)) / (2 * h)
+        assert np.abs(fd - g[:, l]).max() < 1e-7 * max(1, np.abs(g).max())
+    assert np.allclose(y, [O.basis_values(reps, xi) @ alpha for xi in x], atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# manufactured problems: h makes u solve (pde)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("driver,f_a", [("linear", 0.0), ("sin", 0.5), ("allen_cahn", 0.0),
+                                        ("zrat", -0.05)])
+def test_manufactured_source_solves_pde(driver, f_a):
+    """d_t u + b.grad u + 1/2 tr(sigma sigma^T hess u) + f(u, sigma^T grad u) = 0,
+    derivatives by central finite differences of the oracle's u."""
+    d = 3
+    rng = np.random.default_rng(0)
+    sig = (0.3 * rng.standard_normal((d, 2)) + np.eye(d, 2) * 0.5).tolist()
+    w = W.Workload(name="t", d=d, N=4, T=1.0, sigma=sig, b0=[0.1, -0.2, 0.05],
+                   b1=[-0.1, 0.2, 0.0], set_kind="tensor", level=1, M=1, driver=driver, f_a=f_a,
+                   sol_A=0.7, sol_c=0.8, sol_p=0.3, sol_w=[1.0, -0.5, 0.25])
+    S = np.array(sig)
+    for t in (0.1, 0.55):
+        for x in rng.standard_normal((3, d)):
+            u = lambda tt, xx: O.msol_u(w, tt, xx)[0]
+            h = 1e-4
+            ut = (u(t + h, x) - u(t - h, x)) / (2 * h)
+            grad = np.array([(u(t, x + h * e) - u(t, x - h * e)) / (2 * h) for e in np.eye(d)])
+            H = np.zeros((d, d))
+            hh = 1e-3
+            for a in range(d):
+                for b in range(d):
+                    ea, eb = np.eye(d)[a] * hh, np.eye(d)[b] * hh
+                    H[a, b] = (u(t, x + ea + eb) - u(t, x + ea - eb) - u(t, x - ea + eb)
+                               + u(t, x - ea - eb)) / (4 * hh * hh)
+            b = np.array(w.b0) + np.array(w.b1) * x
+            z = S.T @ grad
+            y = u(t, x)
+            if driver == "linear":
+                fnl = 0.0
+            elif driver == "sin":
+                fnl = f_a * math.sin(y)
+            elif driver == "allen_cahn":
+                fnl = y - y ** 3
+            else:
+                fnl = f_a * (z @ z) / (1 + z @ z) + y / (1 + y * y)
+            res = ut + b @ grad + 0.5 * np.trace(S @ S.T @ H) + fnl + O.msol_h(w, t, x)[0]
+            assert abs(res) < 2e-6
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 1 with a linear driver: closed-form expectation of alpha
+# ---------------------------------------------------------------------------
+
+def _c1d(a, m):
+    """c(a, m) = E[exp(i (a X + 2 pi m F(X)))] for standard logistic X,
+    by the trapezoid rule in x on [-60, 60]."""
+    xs = np.linspace(-60, 60, 240001)
+    F = special.expit(xs)
+    f = np.exp(1j * (a * xs + 2 * np.pi * m * F)) * F * (1 - F)
+    return np.trapezoid(f, xs)
+
+
+def _proj_cos_linear(reps, w_vec, p):
+    """<cos(w.x + p), phi_k>_nu for every basis function (Lemma 3.1 target)."""
+    d = len(w_vec)
+    cache = {}
+
+    def c(a, m):
+        if (a, m) not in cache:
+            cache[(a, m)] = _c1d(a, m)
+        return cache[(a, m)]
+
+    out = np.zeros(O.nfuncs(reps))
+    e = np.exp(1j * p)
+    out[0] = (e * np.prod([c(w_vec[l], 0) for l in range(d)])).real
+    for r in range(1, reps.shape[0]):
+        k = reps[r]
+        zp = e * np.prod([c(w_vec[l], int(k[l])) for l in range(d)])
+        zm = e * np.prod([c(w_vec[l], -int(k[l])) for l in range(d)])
+        out[2 * r - 1] = math.sqrt(2) * 0.5 * (zp.real + zm.real)
+        out[2 * r] = math.sqrt(2) * 0.5 * (zp.imag - zm.imag)
+    return out
+
+
+def _kappa(w, i):
+    """E[S_i | X_i = x] = A kappa_i cos(w.x+p) for f = h and zero drift
+    (Euler is exact for X = x + sigma W; E cos(w.X_j + p) decays by exp(-|s|^2 dt/2))."""
+    S = np.array(w.sigma)
+    s2 = float(np.sum((S.T @ np.array(w.sol_w)) ** 2))
+    t = w.times
+    T = t[-1]
+    k = math.exp(-s2 * (T - t[i]) / 2)
+    for j in range(i, w.N):
+        k += (s2 / 2 - w.sol_c) * math.exp(-w.sol_c * (T - t[j])) * math.exp(-s2 * (t[j] - t[i]) / 2) * (t[j + 1] - t[j])
+    return k
+
+
+@pytest.mark.parametrize("i", [9, 6])
+def test_linear_driver_unbiased_alpha(i):
+    """Lemma 3.1: E[alpha_{i,k}] = <y_i, phi_k>_nu when S is exact.  With
+    f = h(t,x) (no dependence on y) the discrete-time y_i is closed form."""
+    w = W.CFG1.with_(driver="linear", f_a=0.0, sol_p=0.2, sol_w=[1.0, 0.5])
+    reps = O.reps_for(w)
+    M = 1 << 14
+    alpha = np.zeros((w.N, O.nfuncs(reps)))
+    a, _, x, s = O.backward_step(w, reps, i, M, 0, alpha, want_x=True, want_s=True)
+    exp = w.sol_A * _kappa(w, i) * _proj_cos_linear(reps, w.sol_w, w.sol_p)
+    Phi = np.array([O.basis_values(reps, xi) for xi in x])
+    sd = (Phi * s[:, None]).std(axis=0) / math.sqrt(M)
+    assert np.all(np.abs(a - exp) <= 5 * sd + 1e-12)
+    # and the expectation is not trivially small
+    assert np.abs(exp).max() > 0.05
+
+
+def test_step_response_equals_path_response():
+    w = W.CFG1
+    reps = O.reps_for(w)
+    rng = np.random.default_rng(0)
+    alpha = W.synthetic_alpha(O.nfuncs(reps), w.N, seed=5)
+    _, _, x, s = O.backward_step(w, reps, 5, 64, 9, alpha.copy(), want_x=True, want_s=True)
+    for m in (0, 17, 63):
+        assert O.path_response(w, reps, 5, 9, m, alpha) == s[m]
+    # start points come from stream 0 through F^{-1}
+    assert x[17, 1] == O.logistic_icdf(O.uniform(9, 0, 17, 5, 1))
+
+
+# ---------------------------------------------------------------------------
+# nonlinear manufactured solve (config d=2, tensor 4)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.slow
+def test_cfg1_solve_close_to_projected_solution():
+    """The solve at t_0 approaches P_Gamma u(0,.) (Thm 2.2): its distance is
+    bounded by the Monte-Carlo spread plus an O(Delta) time-discretisation
+    allowance, and the L2 error against u sits at the projection floor."""
+    w = W.CFG1.with_(M=1 << 16)
+    reps = O.reps_for(w)
+    alpha = O.solve(w, reps)
+    exact = math.exp(-1.0) * _proj_cos_linear(reps, [1.0, 1.0], 0.0)
+    # relative projection floor ||u - P u||^2 / ||u||^2 with ||u||^2 = e^-2 E cos^2(x1+x2)
+    c2 = _c1d(2.0, 0)
+    norm2 = math.exp(-2.0) * 0.5 * (1 + (c2 * c2).real)
+    floor = 1 - (exact @ exact) / norm2
+    assert 0.15 < floor < 0.19
+    # Monte-Carlo spread of alpha_0 from the last backward step's samples
+    a2 = np.zeros_like(alpha)
+    a2[1:] = alpha[1:]
+    _, _, x, s = O.backward_step(w, reps, 0, w.M, w.seed, a2, want_x=True, want_s=True)
+    assert np.array_equal(a2[0], alpha[0])
+    Phi = np.array([O.basis_values(reps, xi) for xi in x[:4096]])
+    spread = math.sqrt(np.sum((Phi * s[:4096, None]).var(axis=0)) / w.M)
+    err = np.linalg.norm(alpha[0] - exact)
+    assert err < 5 * spread + 0.05 * np.linalg.norm(exact)
+    mse_max, mse_av, rel0 = O.errors(w, reps, alpha, n=1 << 14)
+    assert math.sqrt(floor) - 0.02 < rel0 < math.sqrt(floor + 0.05)
