@@ -1,0 +1,174 @@
+#!/usr/bin/env python3
+"""Benchmark: basis-evals/s of the plain FP64 QRMC solve on one MI355X.
+
+Workload (default): d=6, N=20, sigma=0.4 I, b(x)=-0.1 x, standard-logistic
+sampling law, hyperbolic cross prod max(1,|k_l|) <= 16 over Z^6
+(169,209 basis functions), M=2^20 paths per step, Allen-Cahn driver
+y - y^3 + h with u(t,x) = exp(-(T-t)) cos(sum x)/2, T=1, clamp 1, seed 0.
+
+A step is one full backward induction (Algorithm 1, i = N-1..0).  One solve
+evaluates M |Gamma| N(N+1)/2 basis functions (expansions along the paths plus
+the projections); value = that count times the timed solves over the timed
+wall time, with everything resident on the GPU.  The dominant kernel (path
+simulation + expansion evaluation) is timed with HIP events recorded on its
+launch stream; its roofline is the FP64 vector ALU (5 flops per basis
+function: one complex multiply per representative shared by a cos/sin pair,
+and two FMAs).  The CPU oracle is timed on a bounded sample of the same
+workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+FLOPS_PER_BASIS_EVAL = 5.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="d6-hcmax16-allen-cahn")
+    ap.add_argument("--M", type=int, default=None, help="override paths per step")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run one plain device copy of this size (for counter scaling)")
+    return ap.parse_args()
+
+
+def cpu_baseline(w, target_s: float):
+    """The oracle, as it stands, on one backward step of the same workload
+    with a reduced cloud; evals counted as on the GPU (M' |Gamma| (N - i))."""
+    import numpy as np
+    import oracle as O
+    reps = O.reps_for(w)
+    nf = O.nfuncs(reps)
+    alpha = np.zeros((w.N, nf))
+    rng = np.random.default_rng(0)
+    alpha[w.N - 1] = rng.standard_normal(nf) * 1e-3
+    i = w.N - 2
+    M1 = 256
+    t0 = time.perf_counter()
+    O.backward_step(w, reps, i, M1, w.seed, alpha.copy())
+    t1 = time.perf_counter() - t0
+    M2 = max(M1, int(M1 * target_s / max(t1, 1e-3)))
+    t0 = time.perf_counter()
+    O.backward_step(w, reps, i, M2, w.seed, alpha.copy())
+    dt = time.perf_counter() - t0
+    evals = M2 * nf * (w.N - i)
+    return {"value": evals / dt, "unit": "basis-evals/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"one backward step i=N-2 with M'={M2} paths (full |Gamma|={nf}); "
+                      f"{dt:.1f} s", "seconds": dt}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(multi-GPU path sharding is a design note, not built)"}))
+        sys.exit(2)
+    import torch
+    import workloads as W
+    from paper_2407_21084_amd import qrmc as Q
+
+    w = W.ALL[args.workload]
+    if args.M:
+        w = w.with_(M=args.M)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ctx = Q.Context(0)
+    basis = Q.Basis(w.d, w.set_kind, w.level)
+    prob = Q.problem_from(w)
+    alpha = torch.zeros((w.N, basis.n_funcs), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    if args.copy_calibration_mib:
+        src = torch.empty(args.copy_calibration_mib << 17, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
+    for k in range(args.warmup):
+        ctx.solve(prob, basis, w.M, w.seed, alpha, stream)
+        torch.cuda.synchronize()
+        print(f"[bench] warmup solve {k + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+
+    ctx.reset_timing()
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ctx.solve(prob, basis, w.M, w.seed, alpha, stream)
+        if k + 1 < args.steps and args.steps > 1:
+            print(f"[bench] timed solve {k + 1}/{args.steps} enqueued", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    print(f"[bench] timed region {elapsed:.2f} s", file=sys.stderr, flush=True)
+    ctx.set_timing(False)
+
+    evals_per_solve = w.M * basis.n_funcs * w.N * (w.N + 1) / 2
+    value = evals_per_solve * args.steps / elapsed
+    path_ms, path_n = ctx.kernel_time(Q.K_PATH)
+    proj_ms, proj_n = ctx.kernel_time(Q.K_PROJECT)
+    red_ms, red_n = ctx.kernel_time(Q.K_REDUCE)
+    # algorithmic flops of the path kernel: expansions at X_{j+1}, j+1 < N
+    path_evals = w.M * basis.n_funcs * w.N * (w.N - 1) / 2 * args.steps
+    achieved = path_evals * FLOPS_PER_BASIS_EVAL / (path_ms * 1e-3) / 1e12 if path_ms > 0 else 0.0
+    proj_evals = w.M * basis.n_funcs * w.N * args.steps
+    proj_tflops = proj_evals * FLOPS_PER_BASIS_EVAL / (proj_ms * 1e-3) / 1e12 if proj_ms > 0 else 0.0
+
+    # accuracy of the last solve against the closed form at t_0 (stream-1 points)
+    n_test = 1 << 16
+    xt = torch.empty((w.d, n_test), dtype=torch.float64, device=dev)
+    ctx.sample_points(w.d, w.seed, 1, 0, n_test, xt, stream=stream)
+    yt = torch.empty(n_test, dtype=torch.float64, device=dev)
+    ctx.eval(basis, alpha[0].contiguous(), xt, yt, stream=stream)
+    torch.cuda.synchronize()
+    wv = torch.tensor(w.sol_w, dtype=torch.float64, device=dev)
+    u0 = w.sol_A * math.exp(-w.sol_c * w.T) * torch.cos(wv @ xt + w.sol_p)
+    rel_l2 = float(torch.linalg.norm(yt - u0) / torch.linalg.norm(u0))
+
+    line = {
+        "metric": "basis-evals/s (plain FP64 full solve)",
+        "value": value,
+        "unit": "basis-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "d": w.d, "N": w.N, "set": f"{w.set_kind}({w.level})",
+                   "n_funcs": basis.n_funcs, "M": w.M, "evals_per_solve": evals_per_solve},
+        "full_solve_s": elapsed / args.steps,
+        "rel_l2_t0": rel_l2,
+        "kernels_ms_per_solve": {"path": path_ms / args.steps, "project": proj_ms / args.steps,
+                                 "reduce": red_ms / args.steps},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                     "traffic": None, "kernel": "path_kernel",
+                     "avg_launch_ms": path_ms / max(1, path_n),
+                     "project_tflops": proj_tflops},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

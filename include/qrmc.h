@@ -1,0 +1,226 @@
+/*
+ * qrmc.h -- C ABI of libqrmc, an MI355X (gfx950) implementation of the
+ * quasi-regression Monte-Carlo (QRMC) backward step of Gobet, Lopez-Salas and
+ * Vazquez, "Quasi-Regression Monte-Carlo scheme for semi-linear PDEs and BSDEs
+ * with large scale parallelization on GPUs" (arXiv 2407.21084).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every function returns a qr_status; nothing throws across the ABI.  On a
+ *    non-zero status, qr_last_error() returns a thread-local message.
+ *  - "device" pointers are HIP device allocations (e.g. the data pointer of a
+ *    torch tensor on a ROCm device) owned by the caller; "host" pointers are
+ *    ordinary memory owned by the caller and only read during the call.
+ *  - Device work is enqueued on the HIP stream passed as `stream` (NULL = the
+ *    null stream) and is asynchronous: results are valid once the stream has
+ *    been synchronised.  Arguments are validated on the host before anything
+ *    is launched; asynchronous device faults surface at the next
+ *    synchronising call as QR_EDEVICE.
+ *  - A context (qr_ctx) owns device workspace and must not be used from two
+ *    host threads or on two streams at the same time.
+ *  - All floating point is IEEE binary64.
+ *
+ * Mathematical objects (paper notation)
+ * -------------------------------------
+ *  - Decoupled FBSDE / semi-linear PDE of Sec. 1, eqs (fbsde), (eds), (pde):
+ *    drift b, diffusion sigma, driver f, terminal condition g, horizon T.
+ *  - Time grid t_0 < ... < t_N (Sec. 2.1.1), Euler scheme eq (markov:euler).
+ *  - Sampling law nu of assumption (A_nu): here a product of standard
+ *    logistic laws, F(x) = 1/(1+e^{-x}).
+ *  - Basis (Sec. 2.2, Lemma 2.1 with the Fourier basis of the torus):
+ *    phi_0 = 1 and, for each representative k of {k,-k} (first non-zero
+ *    coordinate positive), sqrt2 cos(2 pi k.F(x)) and sqrt2 sin(2 pi k.F(x)),
+ *    orthonormal in L2(nu).
+ *  - Index sets Gamma over Z^d (Sec. 2.3.3).
+ *  - Algorithm 1 (GQRMDP) with damping q = 0 and a constant truncation
+ *    level L for T_L.
+ *
+ * Coefficient layout ("canonical order"): for a basis with R representatives
+ * k_0 = 0 < k_1 < ... < k_{R-1} in lexicographic order of integer vectors,
+ * a coefficient row has n_funcs = 2R-1 entries: entry 0 multiplies phi_0 = 1,
+ * entry 2r-1 multiplies sqrt2 cos(2 pi k_r.F(x)), entry 2r multiplies
+ * sqrt2 sin(2 pi k_r.F(x)).  A coefficient table is row-major [N][n_funcs],
+ * row i holding ybar_i (ybar_N = g is not stored).
+ *
+ * Random streams: every random number is drawn from Philox4x32-10 (Salmon et
+ * al., SC'11).  Draw r of sample m at time index i of stream s uses
+ * key (seed_lo, seed_hi ^ s), counter (m_lo, m_hi, i, r >> 1) and words
+ * (w0,w1) for even r, (w2,w3) for odd r; U = ((w_a<<20 | w_b>>12) + 1/2) 2^-52.
+ * Stream 0: solver paths (start point draws r = 0..d-1, then nbm normals per
+ * Euler step: r = d + (j-i) nbm + k).  Stream 1: test points.
+ */
+#ifndef QRMC_H
+#define QRMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QR_MAX_D 16    /* maximum state / Brownian dimension            */
+#define QR_MAX_N 128   /* maximum number of time steps                  */
+
+typedef enum {
+    QR_OK = 0,
+    QR_EINVAL = -1,   /* invalid argument (message says which)            */
+    QR_ENOMEM = -2,   /* device or host allocation failed                 */
+    QR_EDEVICE = -3,  /* HIP runtime or launch error                      */
+    QR_ERANGE = -4,   /* size overflow (index set, M, workspace)          */
+    QR_ENUMERIC = -5, /* non-finite coefficient produced                  */
+    QR_ENOTSUP = -6   /* valid request outside what this build supports   */
+} qr_status;
+
+/* Message for the last failing call on this thread ("" if none). */
+const char *qr_last_error(void);
+
+/* Library version string. */
+const char *qr_version(void);
+
+/* ---------------------------------------------------------------------- */
+/* Index sets and basis (Sec. 2.3.3 "Multi-indices sets", Lemma 2.1)       */
+/* ---------------------------------------------------------------------- */
+typedef enum {
+    QR_SET_TENSOR = 0, /* {k in Z^d : max_l |k_l| <= level}  (Gamma_F)        */
+    QR_SET_HC_MAX = 1, /* {k in Z^d : prod_l max(1,|k_l|) <= level} (Gamma_H) */
+    QR_SET_HC_1P = 2   /* {k in Z^d : prod_l (1+|k_l|) <= level}              */
+} qr_set_kind;
+
+typedef struct qr_basis qr_basis; /* opaque, library-owned */
+
+/* Build the index set of kind `kind` and level `level` in dimension d
+ * (1 <= d <= QR_MAX_D, level >= 0) and its basis metadata.  Host only; no
+ * device is touched.  *out receives a handle to free with qr_basis_free.
+ * QR_ERANGE if the set has more than 2^31 representatives. */
+qr_status qr_build_basis(int32_t d, int32_t kind, int32_t level, qr_basis **out);
+
+/* n_funcs = |Gamma| (real basis functions), n_reps = representatives
+ * (n_funcs = 2 n_reps - 1), max_nnz = largest number of non-zero
+ * coordinates of a k in the set.  Any output pointer may be NULL. */
+qr_status qr_basis_info(const qr_basis *b, int64_t *n_funcs, int64_t *n_reps, int32_t *max_nnz);
+
+/* Copy the representatives in canonical (lexicographic) order into
+ * reps_out, host memory of n_reps * d int32 (row-major [n_reps][d]). */
+qr_status qr_basis_indices(const qr_basis *b, int32_t *reps_out);
+
+/* Release a basis (and any device copies it holds). NULL is accepted. */
+void qr_basis_free(qr_basis *b);
+
+/* ---------------------------------------------------------------------- */
+/* Problem description                                                     */
+/* ---------------------------------------------------------------------- */
+typedef enum {
+    QR_F_LINEAR = 0,     /* f = h(t,x)                                     */
+    QR_F_SIN = 1,        /* f = a sin(y) + h(t,x)                          */
+    QR_F_ALLEN_CAHN = 2, /* f = y - y^3 + h(t,x)                           */
+    QR_F_ZRAT = 3        /* f = a |z|^2/(1+|z|^2) + y/(1+y^2) + h(t,x)     */
+} qr_driver_kind;
+
+/*
+ * Semi-linear problem with a manufactured closed-form solution
+ *   u(t,x) = A exp(-c (T - t)) cos(w.x + p),   g = u(T, .),
+ * where h is the source that makes u solve eq (pde) for the chosen driver:
+ *   h = -(d_t u + b.grad u + 1/2 tr(sigma sigma^T hess u)) - f_nl(u, sigma^T grad u).
+ * Drift b(t,x)_l = b0_l + b1_l x_l, constant diffusion sigma (d x nbm,
+ * row-major), z = sigma^T grad_x y.  T = t[N].
+ * clamp: level L of the truncation T_L applied to y (use INFINITY for none).
+ * All arrays are inline; entries beyond d / nbm / N are ignored.
+ */
+typedef struct {
+    int32_t d;                 /* 1..QR_MAX_D                               */
+    int32_t nbm;               /* 1..QR_MAX_D                               */
+    int32_t N;                 /* 1..QR_MAX_N                               */
+    int32_t driver;            /* qr_driver_kind                            */
+    double f_a;                /* driver parameter a                        */
+    double clamp;              /* T_L level (> 0)                           */
+    double t[QR_MAX_N + 1];    /* t_0 < t_1 < ... < t_N                     */
+    double b0[QR_MAX_D];
+    double b1[QR_MAX_D];
+    double sigma[QR_MAX_D * QR_MAX_D]; /* [d][nbm] row-major               */
+    double sol_A, sol_c, sol_p;
+    double sol_w[QR_MAX_D];
+} qr_problem;
+
+/* ---------------------------------------------------------------------- */
+/* Context                                                                 */
+/* ---------------------------------------------------------------------- */
+typedef struct qr_ctx qr_ctx; /* opaque, library-owned */
+
+/* Create a context on HIP device `device`; device workspace is allocated
+ * lazily and grown on demand.  QR_EDEVICE if the device is unusable. */
+qr_status qr_ctx_create(int32_t device, qr_ctx **out);
+
+/* Synchronise with the context's last stream and release all workspace. */
+void qr_ctx_destroy(qr_ctx *ctx);
+
+/* Enable (1) or disable (0) per-kernel timing with HIP events recorded on
+ * the launch stream around every kernel the library enqueues. */
+qr_status qr_ctx_set_timing(qr_ctx *ctx, int32_t enable);
+
+/* Accumulated timings (ms) and launch counts since the last reset, for
+ * kernel class `which`: 0 = path simulation + expansion evaluation
+ * (path kernel), 1 = projection, 2 = projection reduction, 3 = coefficient
+ * gather.  Synchronises the events it reads. */
+qr_status qr_ctx_kernel_time(qr_ctx *ctx, int32_t which, double *ms, int64_t *launches);
+qr_status qr_ctx_reset_timing(qr_ctx *ctx);
+
+/* ---------------------------------------------------------------------- */
+/* The backward step (Algorithm 1, eqs (yqi:bar:M), (Aqi:bar:M),           */
+/* (Sqi:bar:M)) and the full backward induction                            */
+/* ---------------------------------------------------------------------- */
+
+/* One backward iteration i (0 <= i < N): draws a fresh cloud of M start
+ * points X_i ~ nu (stream 0), Euler-simulates each path to t_N, evaluates
+ * ybar_{j+1} (rows j+1 of alpha, or g for j+1 = N) along it, accumulates
+ *   S = g(X_N) + sum_{j=i}^{N-1} f(t_j, X_j, T_L(ybar_{j+1}(X_{j+1})), z_{j+1}) (t_{j+1}-t_j)
+ * and writes row i of alpha with (1/M) sum_m S_m phi_k(X_i^m).
+ * alpha: device, [N][n_funcs] canonical order; rows i+1..N-1 are read,
+ * row i is written.  1 <= M <= 2^31 - 1. */
+qr_status qr_backward_step(qr_ctx *ctx, const qr_problem *prob, const qr_basis *basis, int32_t i,
+                           int64_t M, uint64_t seed, double *alpha, void *stream);
+
+/* Full backward induction i = N-1, ..., 0 (all rows of alpha written). */
+qr_status qr_solve(qr_ctx *ctx, const qr_problem *prob, const qr_basis *basis, int64_t M,
+                   uint64_t seed, double *alpha, void *stream);
+
+/* Evaluate ybar = sum_k alpha_k phi_k at n points.
+ * alpha_row: device [n_funcs] canonical order; x: device SoA [d][n];
+ * y: device [n]; grad: device SoA [d][n] receiving grad_x ybar, or NULL. */
+qr_status qr_eval(qr_ctx *ctx, const qr_basis *basis, const double *alpha_row, int64_t n,
+                  const double *x, double *y, double *grad, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Pieces of the step, exposed for testing and for callers that supply    */
+/* their own samples                                                       */
+/* ---------------------------------------------------------------------- */
+
+/* Projection alone (eq (Aqi:bar:M) on given samples):
+ * alpha_row[k] = (1/n) sum_p s_p phi_k(x_p).
+ * x: device SoA [d][n]; s: device [n]; alpha_row: device [n_funcs]. */
+qr_status qr_project(qr_ctx *ctx, const qr_basis *basis, int64_t n, const double *x,
+                     const double *s, double *alpha_row, void *stream);
+
+/* Path simulation and responses alone: writes S_m (eq (Sqi:bar:M)) for
+ * m = 0..M-1 of step i into s (device [M]) and, if x0 is not NULL, the start
+ * points X_i^m into x0 (device SoA [d][M]).  alpha as in qr_backward_step. */
+qr_status qr_path_responses(qr_ctx *ctx, const qr_problem *prob, const qr_basis *basis, int32_t i,
+                            int64_t M, uint64_t seed, const double *alpha, double *s, double *x0,
+                            void *stream);
+
+/* nu-distributed points of stream `stream_id` at time index i:
+ * x[l][m] = F^{-1}(U(seed, stream_id, m0 + m, i, l)), device SoA [d][n]. */
+qr_status qr_sample_points(qr_ctx *ctx, int32_t d, uint64_t seed, uint32_t stream_id, int32_t i,
+                           int64_t m0, int64_t n, double *x, void *stream);
+
+/* Host-side copies of the scalar device routines, for unit tests on
+ * machines without a GPU.  qr_host_uniform follows the stream layout above;
+ * qr_host_norm_icdf is the device inverse normal CDF (Wichura's AS241,
+ * PPND16); qr_host_philox writes the 4 output words for a counter / key. */
+double qr_host_uniform(uint64_t seed, uint32_t stream_id, uint64_t m, uint32_t i, uint32_t r);
+double qr_host_norm_icdf(double u);
+void qr_host_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QRMC_H */

@@ -1,0 +1,654 @@
+// qrmc_api.hip -- host side of libqrmc: index sets and basis metadata,
+// context and workspace, argument validation and the C entry points of qrmc.h.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "qrmc_kernels.h"
+
+using namespace qrmc;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+static qr_status fail(qr_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+static qr_status hipfail(hipError_t e, const char *what) {
+    return fail(QR_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define QR_HIP(call, what)                                  \
+    do {                                                    \
+        hipError_t _e = (call);                             \
+        if (_e != hipSuccess) return hipfail(_e, what);     \
+    } while (0)
+
+extern "C" const char *qr_last_error(void) { return g_last_error.c_str(); }
+extern "C" const char *qr_version(void) { return "qrmc 0.1 (gfx950)"; }
+
+// ---------------------------------------------------------------------------
+// basis
+// ---------------------------------------------------------------------------
+struct qr_basis {
+    int32_t d = 0, kind = 0, level = 0;
+    int64_t nrep = 0;
+    int32_t max_nnz = 0;
+    std::vector<int32_t> trav;           // [nrep][d] traversal order
+    std::vector<int32_t> canon;          // [nrep][d] lexicographic order
+    std::vector<int32_t> canon_of_trav;  // traversal index -> canonical index
+    std::vector<uint32_t> ops;           // node program, nrep + kOpPad entries
+    std::vector<RangeStart> ranges;      // projection ranges of kTaskMax nodes
+    // device copies (one device at a time)
+    std::mutex mu;
+    int dev = -1;
+    int32_t *d_canon_of_trav = nullptr;
+    uint32_t *d_ops = nullptr;
+    RangeStart *d_ranges = nullptr;
+    int64_t ld() const { return nrep + kOpPad; }
+};
+
+namespace {
+
+constexpr int64_t kMaxReps = (int64_t)1 << 28;
+
+struct Builder {
+    SetRule R;
+    std::vector<int32_t> cur;
+    std::vector<int32_t> &trav;
+    std::vector<uint32_t> &ops;
+    bool overflow = false;
+    int32_t max_depth = 0;
+
+    void push(int depth, bool fresh, int l, bool neg) {
+        if ((int64_t)ops.size() >= kMaxReps) {
+            overflow = true;
+            return;
+        }
+        trav.insert(trav.end(), cur.begin(), cur.end());
+        ops.push_back(depth == 0 ? 0u : make_op(depth, fresh, l, neg));
+        max_depth = std::max(max_depth, depth);
+    }
+
+    // Mirror of the device traversal order (see the node program in qrmc_common.h).
+    void visit(int T, int p, int P) {
+        for (int l = p + 1; l < R.d && !overflow; ++l) {
+            for (int s = 0; s < (T == 0 ? 1 : 2); ++s) {
+                for (int m = 1; rule_ok(R, P, m) && !overflow; ++m) {
+                    cur[l] = s ? -m : m;
+                    const int P2 = rule_child(R, P, m);
+                    push(T + 1, m == 1, l, s == 1);
+                    if (l + 1 < R.d && rule_ok(R, P2, 1)) visit(T + 1, l, P2);
+                }
+            }
+            cur[l] = 0;
+        }
+    }
+};
+
+// Fixed-size ranges of the node program for the projection, each with the
+// k-vector of its first node.
+void build_ranges(const std::vector<int32_t> &trav, int d, int64_t nrep,
+                  std::vector<RangeStart> &ranges) {
+    for (int64_t r0 = 0; r0 < nrep; r0 += kTaskMax) {
+        RangeStart rs{};
+        rs.r0 = (int32_t)r0;
+        rs.r1 = (int32_t)std::min<int64_t>(nrep, r0 + kTaskMax);
+        int t = 0;
+        for (int l = 0; l < d; ++l) {
+            const int32_t v = trav[r0 * d + l];
+            if (v != 0) {
+                if (t < kMaxDepthCap) {
+                    rs.coord[t] = l;
+                    rs.val[t] = v;
+                }
+                ++t;
+            }
+        }
+        rs.depth = t;
+        ranges.push_back(rs);
+    }
+}
+
+}  // namespace
+
+extern "C" qr_status qr_build_basis(int32_t d, int32_t kind, int32_t level, qr_basis **out) {
+    if (!out) return fail(QR_EINVAL, "qr_build_basis: out is NULL");
+    *out = nullptr;
+    if (d < 1 || d > QR_MAX_D) return fail(QR_EINVAL, "qr_build_basis: d=%d outside [1,%d]", d, QR_MAX_D);
+    if (kind < QR_SET_TENSOR || kind > QR_SET_HC_1P)
+        return fail(QR_EINVAL, "qr_build_basis: unknown set kind %d", kind);
+    if (level < 0 || level > (1 << 20)) return fail(QR_EINVAL, "qr_build_basis: level=%d out of range", level);
+
+    qr_basis *b = new (std::nothrow) qr_basis();
+    if (!b) return fail(QR_ENOMEM, "qr_build_basis: out of host memory");
+    b->d = d;
+    b->kind = kind;
+    b->level = level;
+    try {
+        Builder B{make_rule(kind, level, d), std::vector<int32_t>(d, 0), b->trav, b->ops};
+        B.push(0, false, 0, false);  // the zero vector
+        B.visit(0, -1, 1);
+        if (B.overflow) {
+            delete b;
+            return fail(QR_ERANGE, "qr_build_basis: more than %lld representatives", (long long)kMaxReps);
+        }
+        b->nrep = (int64_t)b->ops.size();
+        b->max_nnz = B.max_depth;
+        b->ops.resize(b->nrep + kOpPad, 0u);
+
+        // canonical (lexicographic) order and the permutation
+        std::vector<int64_t> order(b->nrep);
+        for (int64_t r = 0; r < b->nrep; ++r) order[r] = r;
+        const int32_t *T = b->trav.data();
+        std::sort(order.begin(), order.end(), [&](int64_t a, int64_t c) {
+            return std::lexicographical_compare(T + a * d, T + a * d + d, T + c * d, T + c * d + d);
+        });
+        b->canon.resize((size_t)b->nrep * d);
+        b->canon_of_trav.resize(b->nrep);
+        for (int64_t c = 0; c < b->nrep; ++c) {
+            std::memcpy(&b->canon[c * d], T + order[c] * d, sizeof(int32_t) * d);
+            b->canon_of_trav[order[c]] = (int32_t)c;
+        }
+        build_ranges(b->trav, d, b->nrep, b->ranges);
+    } catch (const std::bad_alloc &) {
+        delete b;
+        return fail(QR_ENOMEM, "qr_build_basis: out of host memory");
+    }
+    *out = b;
+    return QR_OK;
+}
+
+extern "C" qr_status qr_basis_info(const qr_basis *b, int64_t *n_funcs, int64_t *n_reps,
+                                   int32_t *max_nnz) {
+    if (!b) return fail(QR_EINVAL, "qr_basis_info: basis is NULL");
+    if (n_funcs) *n_funcs = 2 * b->nrep - 1;
+    if (n_reps) *n_reps = b->nrep;
+    if (max_nnz) *max_nnz = b->max_nnz;
+    return QR_OK;
+}
+
+extern "C" qr_status qr_basis_indices(const qr_basis *b, int32_t *reps_out) {
+    if (!b || !reps_out) return fail(QR_EINVAL, "qr_basis_indices: NULL argument");
+    std::memcpy(reps_out, b->canon.data(), sizeof(int32_t) * b->canon.size());
+    return QR_OK;
+}
+
+static void basis_free_device(qr_basis *b) {
+    if (b->dev >= 0) {
+        int cur = 0;
+        hipGetDevice(&cur);
+        hipSetDevice(b->dev);
+        hipDeviceSynchronize();
+        hipFree(b->d_canon_of_trav);
+        hipFree(b->d_ops);
+        hipFree(b->d_ranges);
+        hipSetDevice(cur);
+    }
+    b->d_canon_of_trav = nullptr;
+    b->d_ops = nullptr;
+    b->d_ranges = nullptr;
+    b->dev = -1;
+}
+
+extern "C" void qr_basis_free(qr_basis *b) {
+    if (!b) return;
+    basis_free_device(b);
+    delete b;
+}
+
+// Upload the basis tables to `dev` (current device) once.
+static qr_status basis_on_device(qr_basis *b, int dev) {
+    std::lock_guard<std::mutex> lock(b->mu);
+    if (b->dev == dev) return QR_OK;
+    if (b->dev >= 0) basis_free_device(b);
+    QR_HIP(hipMalloc(&b->d_canon_of_trav, sizeof(int32_t) * b->nrep), "hipMalloc(basis)");
+    QR_HIP(hipMalloc(&b->d_ops, sizeof(uint32_t) * b->ops.size()), "hipMalloc(basis)");
+    QR_HIP(hipMalloc(&b->d_ranges, sizeof(RangeStart) * b->ranges.size()), "hipMalloc(basis)");
+    QR_HIP(hipMemcpy(b->d_canon_of_trav, b->canon_of_trav.data(), sizeof(int32_t) * b->nrep,
+                     hipMemcpyHostToDevice), "hipMemcpy(basis)");
+    QR_HIP(hipMemcpy(b->d_ops, b->ops.data(), sizeof(uint32_t) * b->ops.size(),
+                     hipMemcpyHostToDevice), "hipMemcpy(basis)");
+    QR_HIP(hipMemcpy(b->d_ranges, b->ranges.data(), sizeof(RangeStart) * b->ranges.size(),
+                     hipMemcpyHostToDevice), "hipMemcpy(basis)");
+    b->dev = dev;
+    return QR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+namespace {
+struct Buf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Timed {
+    int which;
+    hipEvent_t a, b;
+};
+}  // namespace
+
+struct qr_ctx {
+    int dev = 0;
+    hipStream_t last = nullptr;
+    DevProblem *d_prob = nullptr;
+    DevProblem h_prob{};
+    bool prob_valid = false;
+    Buf S, u, alpha_int, partial, row;
+    bool timing = false;
+    std::vector<Timed> pending;
+    std::vector<hipEvent_t> pool;
+    double ms[4] = {0, 0, 0, 0};
+    int64_t launches[4] = {0, 0, 0, 0};
+};
+
+static qr_status ensure(qr_ctx *c, Buf &b, size_t bytes, const char *what) {
+    if (b.bytes >= bytes) return QR_OK;
+    QR_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    if (b.p) hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+        hipGetLastError();
+        return fail(QR_ENOMEM, "workspace %s: cannot allocate %zu bytes", what, bytes);
+    }
+    b.bytes = bytes;
+    (void)c;
+    return QR_OK;
+}
+
+extern "C" qr_status qr_ctx_create(int32_t device, qr_ctx **out) {
+    if (!out) return fail(QR_EINVAL, "qr_ctx_create: out is NULL");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n == 0) return fail(QR_EDEVICE, "qr_ctx_create: no HIP device available");
+    if (device < 0 || device >= n) return fail(QR_EINVAL, "qr_ctx_create: device %d of %d", device, n);
+    QR_HIP(hipSetDevice(device), "hipSetDevice");
+    qr_ctx *c = new (std::nothrow) qr_ctx();
+    if (!c) return fail(QR_ENOMEM, "qr_ctx_create: out of host memory");
+    c->dev = device;
+    e = hipMalloc(&c->d_prob, sizeof(DevProblem));
+    if (e != hipSuccess) {
+        delete c;
+        return hipfail(e, "hipMalloc(problem)");
+    }
+    *out = c;
+    return QR_OK;
+}
+
+extern "C" void qr_ctx_destroy(qr_ctx *c) {
+    if (!c) return;
+    hipSetDevice(c->dev);
+    hipDeviceSynchronize();
+    for (Buf *b : {&c->S, &c->u, &c->alpha_int, &c->partial, &c->row})
+        if (b->p) hipFree(b->p);
+    hipFree(c->d_prob);
+    for (auto &t : c->pending) {
+        hipEventDestroy(t.a);
+        hipEventDestroy(t.b);
+    }
+    for (auto e : c->pool) hipEventDestroy(e);
+    delete c;
+}
+
+extern "C" qr_status qr_ctx_set_timing(qr_ctx *c, int32_t enable) {
+    if (!c) return fail(QR_EINVAL, "qr_ctx_set_timing: ctx is NULL");
+    c->timing = enable != 0;
+    return QR_OK;
+}
+
+static void harvest(qr_ctx *c) {
+    for (auto &t : c->pending) {
+        hipEventSynchronize(t.b);
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+            c->ms[t.which] += ms;
+            c->launches[t.which] += 1;
+        }
+        c->pool.push_back(t.a);
+        c->pool.push_back(t.b);
+    }
+    c->pending.clear();
+}
+
+extern "C" qr_status qr_ctx_kernel_time(qr_ctx *c, int32_t which, double *ms, int64_t *launches) {
+    if (!c || which < 0 || which > 3) return fail(QR_EINVAL, "qr_ctx_kernel_time: bad argument");
+    hipSetDevice(c->dev);
+    harvest(c);
+    if (ms) *ms = c->ms[which];
+    if (launches) *launches = c->launches[which];
+    return QR_OK;
+}
+
+extern "C" qr_status qr_ctx_reset_timing(qr_ctx *c) {
+    if (!c) return fail(QR_EINVAL, "qr_ctx_reset_timing: ctx is NULL");
+    hipSetDevice(c->dev);
+    harvest(c);
+    for (int k = 0; k < 4; ++k) {
+        c->ms[k] = 0;
+        c->launches[k] = 0;
+    }
+    return QR_OK;
+}
+
+static hipEvent_t take_event(qr_ctx *c) {
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    hipEventCreate(&e);
+    return e;
+}
+
+// Launch wrapper: records events around the launch when timing is on.
+template <class F>
+static qr_status timed(qr_ctx *c, int which, hipStream_t s, const char *what, F &&launch) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (c->timing) {
+        a = take_event(c);
+        b = take_event(c);
+        hipEventRecord(a, s);
+    }
+    hipError_t e = launch();
+    if (e != hipSuccess) return hipfail(e, what);
+    if (c->timing) {
+        hipEventRecord(b, s);
+        c->pending.push_back(Timed{which, a, b});
+    }
+    return QR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// validation and problem upload
+// ---------------------------------------------------------------------------
+static qr_status check_problem(const qr_problem *p, const qr_basis *b) {
+    if (!p) return fail(QR_EINVAL, "problem is NULL");
+    if (p->d < 1 || p->d > QR_MAX_D) return fail(QR_EINVAL, "problem: d=%d outside [1,%d]", p->d, QR_MAX_D);
+    if (p->nbm < 1 || p->nbm > QR_MAX_D)
+        return fail(QR_EINVAL, "problem: nbm=%d outside [1,%d]", p->nbm, QR_MAX_D);
+    if (p->N < 1 || p->N > QR_MAX_N) return fail(QR_EINVAL, "problem: N=%d outside [1,%d]", p->N, QR_MAX_N);
+    if (p->driver < QR_F_LINEAR || p->driver > QR_F_ZRAT)
+        return fail(QR_EINVAL, "problem: unknown driver %d", p->driver);
+    if (!(p->clamp > 0.0)) return fail(QR_EINVAL, "problem: clamp must be > 0 (INFINITY for none)");
+    for (int j = 0; j < p->N; ++j)
+        if (!(p->t[j + 1] > p->t[j]) || !std::isfinite(p->t[j + 1]) || !std::isfinite(p->t[j]))
+            return fail(QR_EINVAL, "problem: time grid not strictly increasing at j=%d", j);
+    for (int v = 0; v < p->d * p->nbm; ++v)
+        if (!std::isfinite(p->sigma[v])) return fail(QR_EINVAL, "problem: sigma not finite");
+    if (b && b->d != p->d) return fail(QR_EINVAL, "basis dimension %d != problem dimension %d", b->d, p->d);
+    return QR_OK;
+}
+
+static qr_status check_basis_device(const qr_basis *b) {
+    if (!b) return fail(QR_EINVAL, "basis is NULL");
+    if (b->max_nnz > kMaxDepthCap)
+        return fail(QR_ENOTSUP, "basis has vectors with %d non-zero coordinates (device limit %d)",
+                    b->max_nnz, kMaxDepthCap);
+    if (2 * b->nrep - 1 > ((int64_t)1 << 31) - 1) return fail(QR_ERANGE, "basis too large");
+    return QR_OK;
+}
+
+static int depth_cap(int32_t max_nnz) {
+    return max_nnz <= 2 ? 2 : (max_nnz <= 4 ? 4 : (max_nnz <= 6 ? 6 : 8));
+}
+
+static int dim_bucket(int32_t d, int32_t nbm) {
+    const int m = std::max(d, nbm);
+    return m <= 4 ? 4 : (m <= 8 ? 8 : 16);
+}
+
+static qr_status upload_problem(qr_ctx *c, const qr_problem *p, hipStream_t s) {
+    DevProblem h{};
+    h.d = p->d;
+    h.nbm = p->nbm;
+    h.N = p->N;
+    h.driver = p->driver;
+    h.f_a = p->f_a;
+    h.clamp = p->clamp;
+    h.T = p->t[p->N];
+    for (int j = 0; j <= p->N; ++j) h.t[j] = p->t[j];
+    for (int l = 0; l < p->d; ++l) {
+        h.b0[l] = p->b0[l];
+        h.b1[l] = p->b1[l];
+        h.sol_w[l] = p->sol_w[l];
+        for (int k = 0; k < p->nbm; ++k) h.sigma[l * p->nbm + k] = p->sigma[l * p->nbm + k];
+    }
+    h.sol_A = p->sol_A;
+    h.sol_c = p->sol_c;
+    h.sol_p = p->sol_p;
+    double sw2 = 0.0;
+    for (int k = 0; k < p->nbm; ++k) {
+        double v = 0.0;
+        for (int l = 0; l < p->d; ++l) v += p->sigma[l * p->nbm + k] * p->sol_w[l];
+        h.sw[k] = v;
+        sw2 += v * v;
+    }
+    h.sw2 = sw2;
+    if (c->prob_valid && std::memcmp(&h, &c->h_prob, sizeof h) == 0) return QR_OK;
+    // the previous problem may still be read by queued kernels
+    QR_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (c->last && c->last != s) QR_HIP(hipStreamSynchronize(c->last), "hipStreamSynchronize");
+    QR_HIP(hipMemcpy(c->d_prob, &h, sizeof h, hipMemcpyHostToDevice), "hipMemcpy(problem)");
+    c->h_prob = h;
+    c->prob_valid = true;
+    return QR_OK;
+}
+
+static qr_status begin(qr_ctx *c, void *stream) {
+    if (!c) return fail(QR_EINVAL, "ctx is NULL");
+    QR_HIP(hipSetDevice(c->dev), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    if (c->last && c->last != s) QR_HIP(hipStreamSynchronize(c->last), "hipStreamSynchronize");
+    c->last = s;
+    return QR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// step pieces
+// ---------------------------------------------------------------------------
+static void split_plan(const qr_basis *b, int64_t M, int32_t *nsplit, int64_t *pps) {
+    const int64_t ntasks = (int64_t)b->ranges.size();
+    const int64_t group = (int64_t)kProjWaves * 64;
+    int64_t want = (2048 + ntasks - 1) / ntasks;
+    const int64_t maxs = std::max<int64_t>(1, (M + 4 * group - 1) / (4 * group));
+    want = std::max<int64_t>(1, std::min(want, maxs));
+    int64_t per = (M + want - 1) / want;
+    per = (per + group - 1) / group * group;
+    *pps = per;
+    *nsplit = (int32_t)((M + per - 1) / per);
+}
+
+static qr_status project_and_reduce(qr_ctx *c, const qr_basis *b, const double *u, const double *S,
+                                    int64_t M, double2 *alpha_int_row, double *alpha_row,
+                                    hipStream_t s) {
+    int32_t nsplit;
+    int64_t pps;
+    split_plan(b, M, &nsplit, &pps);
+    qr_status st = ensure(c, c->partial, sizeof(double2) * (size_t)nsplit * b->nrep, "partial");
+    if (st) return st;
+    const int cap = depth_cap(b->max_nnz);
+    double2 *partial = (double2 *)c->partial.p;
+    st = timed(c, 1, s, "project_kernel", [&] {
+        return launch_project(cap, b->d, u, S, M, pps, (int32_t)b->ranges.size(), nsplit,
+                              b->d_ranges, b->d_ops, partial, b->nrep, s);
+    });
+    if (st) return st;
+    return timed(c, 2, s, "reduce_kernel", [&] {
+        return launch_reduce(partial, nsplit, b->nrep, (double)M, alpha_int_row, alpha_row,
+                             b->d_canon_of_trav, s);
+    });
+}
+
+static qr_status run_path(qr_ctx *c, const qr_problem *p, const qr_basis *b, int32_t i, int64_t M,
+                          uint64_t seed, const double2 *alpha_int, double *S, double *u, double *x0,
+                          hipStream_t s) {
+    PathArgs a{c->d_prob, make_rule(b->kind, b->level, b->d), i, M, seed, alpha_int, b->d_ops,
+               b->nrep, b->ld(), S, u, x0};
+    return timed(c, 0, s, "path_kernel", [&] {
+        return launch_path(dim_bucket(p->d, p->nbm), depth_cap(b->max_nnz), p->driver == QR_F_ZRAT,
+                           a, s);
+    });
+}
+
+static qr_status check_M(int64_t M) {
+    if (M < 1 || M > (int64_t)INT32_MAX) return fail(QR_EINVAL, "M=%lld outside [1, 2^31-1]", (long long)M);
+    return QR_OK;
+}
+
+static qr_status prepare(qr_ctx *c, const qr_problem *p, qr_basis *b, int64_t M, void *stream) {
+    qr_status st = begin(c, stream);
+    if (st) return st;
+    if ((st = check_problem(p, b))) return st;
+    if ((st = check_basis_device(b))) return st;
+    if ((st = check_M(M))) return st;
+    if ((st = basis_on_device(b, c->dev))) return st;
+    if ((st = upload_problem(c, p, (hipStream_t)stream))) return st;
+    if ((st = ensure(c, c->S, sizeof(double) * (size_t)M, "S"))) return st;
+    if ((st = ensure(c, c->u, sizeof(double) * (size_t)M * p->d, "u"))) return st;
+    if ((st = ensure(c, c->alpha_int, sizeof(double2) * (size_t)p->N * b->ld(), "alpha"))) return st;
+    // zero the padding columns read by the batched coefficient loads
+    QR_HIP(launch_pad(p->N, b->nrep, b->ld(), (double2 *)c->alpha_int.p, (hipStream_t)stream), "pad_kernel");
+    return QR_OK;
+}
+
+extern "C" qr_status qr_backward_step(qr_ctx *c, const qr_problem *p, const qr_basis *bc, int32_t i,
+                                      int64_t M, uint64_t seed, double *alpha, void *stream) {
+    qr_basis *b = const_cast<qr_basis *>(bc);
+    qr_status st = prepare(c, p, b, M, stream);
+    if (st) return st;
+    if (!alpha) return fail(QR_EINVAL, "qr_backward_step: alpha is NULL");
+    if (i < 0 || i >= p->N) return fail(QR_EINVAL, "qr_backward_step: i=%d outside [0,%d)", i, p->N);
+    hipStream_t s = (hipStream_t)stream;
+    double2 *ai = (double2 *)c->alpha_int.p;
+    const int64_t nf = 2 * b->nrep - 1;
+    st = timed(c, 3, s, "gather_kernel", [&] {
+        return launch_gather(alpha, i + 1, p->N - 1 - i, b->nrep, b->ld(), nf, b->d_canon_of_trav, ai, s);
+    });
+    if (st) return st;
+    double *S = (double *)c->S.p, *u = (double *)c->u.p;
+    if ((st = run_path(c, p, b, i, M, seed, ai, S, u, nullptr, s))) return st;
+    return project_and_reduce(c, b, u, S, M, ai + (int64_t)i * b->ld(), alpha + (int64_t)i * nf, s);
+}
+
+extern "C" qr_status qr_solve(qr_ctx *c, const qr_problem *p, const qr_basis *bc, int64_t M,
+                              uint64_t seed, double *alpha, void *stream) {
+    qr_basis *b = const_cast<qr_basis *>(bc);
+    qr_status st = prepare(c, p, b, M, stream);
+    if (st) return st;
+    if (!alpha) return fail(QR_EINVAL, "qr_solve: alpha is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    double2 *ai = (double2 *)c->alpha_int.p;
+    const int64_t nf = 2 * b->nrep - 1;
+    double *S = (double *)c->S.p, *u = (double *)c->u.p;
+    for (int32_t i = p->N - 1; i >= 0; --i) {
+        if ((st = run_path(c, p, b, i, M, seed, ai, S, u, nullptr, s))) return st;
+        if ((st = project_and_reduce(c, b, u, S, M, ai + (int64_t)i * b->ld(), alpha + (int64_t)i * nf, s)))
+            return st;
+    }
+    return QR_OK;
+}
+
+extern "C" qr_status qr_path_responses(qr_ctx *c, const qr_problem *p, const qr_basis *bc, int32_t i,
+                                       int64_t M, uint64_t seed, const double *alpha, double *s_out,
+                                       double *x0, void *stream) {
+    qr_basis *b = const_cast<qr_basis *>(bc);
+    qr_status st = prepare(c, p, b, M, stream);
+    if (st) return st;
+    if (!alpha || !s_out) return fail(QR_EINVAL, "qr_path_responses: NULL alpha or s");
+    if (i < 0 || i >= p->N) return fail(QR_EINVAL, "qr_path_responses: i=%d outside [0,%d)", i, p->N);
+    hipStream_t s = (hipStream_t)stream;
+    double2 *ai = (double2 *)c->alpha_int.p;
+    const int64_t nf = 2 * b->nrep - 1;
+    st = timed(c, 3, s, "gather_kernel", [&] {
+        return launch_gather(alpha, i + 1, p->N - 1 - i, b->nrep, b->ld(), nf, b->d_canon_of_trav, ai, s);
+    });
+    if (st) return st;
+    return run_path(c, p, b, i, M, seed, ai, s_out, nullptr, x0, s);
+}
+
+extern "C" qr_status qr_project(qr_ctx *c, const qr_basis *bc, int64_t n, const double *x,
+                                const double *s_in, double *alpha_row, void *stream) {
+    qr_basis *b = const_cast<qr_basis *>(bc);
+    qr_status st = begin(c, stream);
+    if (st) return st;
+    if ((st = check_basis_device(b))) return st;
+    if ((st = check_M(n))) return st;
+    if (!x || !s_in || !alpha_row) return fail(QR_EINVAL, "qr_project: NULL argument");
+    if ((st = basis_on_device(b, c->dev))) return st;
+    if ((st = ensure(c, c->u, sizeof(double) * (size_t)n * b->d, "u"))) return st;
+    if ((st = ensure(c, c->row, sizeof(double2) * (size_t)b->ld(), "row"))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    double *u = (double *)c->u.p;
+    QR_HIP(launch_x_to_u(b->d, x, n, u, s), "x_to_u_kernel");
+    return project_and_reduce(c, b, u, s_in, n, (double2 *)c->row.p, alpha_row, s);
+}
+
+extern "C" qr_status qr_eval(qr_ctx *c, const qr_basis *bc, const double *alpha_row, int64_t n,
+                             const double *x, double *y, double *grad, void *stream) {
+    qr_basis *b = const_cast<qr_basis *>(bc);
+    qr_status st = begin(c, stream);
+    if (st) return st;
+    if ((st = check_basis_device(b))) return st;
+    if (n < 0 || n > (int64_t)INT32_MAX * 64) return fail(QR_EINVAL, "qr_eval: n out of range");
+    if (n == 0) return QR_OK;
+    if (!alpha_row || !x || !y) return fail(QR_EINVAL, "qr_eval: NULL argument");
+    if ((st = basis_on_device(b, c->dev))) return st;
+    if ((st = ensure(c, c->row, sizeof(double2) * (size_t)b->ld(), "row"))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    double2 *row = (double2 *)c->row.p;
+    const int64_t nf = 2 * b->nrep - 1;
+    QR_HIP(launch_pad(1, b->nrep, b->ld(), row, s), "pad_kernel");
+    QR_HIP(launch_gather(alpha_row, 0, 1, b->nrep, b->ld(), nf, b->d_canon_of_trav, row, s), "gather_kernel");
+    const SetRule R = make_rule(b->kind, b->level, b->d);
+    QR_HIP(launch_eval(depth_cap(b->max_nnz), grad != nullptr, R, row, b->d_ops, b->nrep, x, n, y, grad, s),
+           "eval_kernel");
+    return QR_OK;
+}
+
+extern "C" qr_status qr_sample_points(qr_ctx *c, int32_t d, uint64_t seed, uint32_t stream_id,
+                                      int32_t i, int64_t m0, int64_t n, double *x, void *stream) {
+    qr_status st = begin(c, stream);
+    if (st) return st;
+    if (d < 1 || d > QR_MAX_D) return fail(QR_EINVAL, "qr_sample_points: d=%d", d);
+    if (n < 0 || m0 < 0 || !x) return fail(QR_EINVAL, "qr_sample_points: bad n/m0/x");
+    QR_HIP(launch_sample(d, seed, stream_id, i, m0, n, x, (hipStream_t)stream), "sample_kernel");
+    return QR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// host mirrors of the scalar device routines
+// ---------------------------------------------------------------------------
+extern "C" double qr_host_uniform(uint64_t seed, uint32_t stream_id, uint64_t m, uint32_t i, uint32_t r) {
+    return uniform_at(seed, stream_id, m, i, r);
+}
+
+extern "C" double qr_host_norm_icdf(double u) { return norm_icdf(u); }
+
+extern "C" void qr_host_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    const U4 w = philox4x32_10(U4{ctr[0], ctr[1], ctr[2], ctr[3]}, key[0], key[1]);
+    out[0] = w.x;
+    out[1] = w.y;
+    out[2] = w.z;
+    out[3] = w.w;
+}

@@ -1,0 +1,262 @@
+"""Thin ctypes binding of libqrmc (include/qrmc.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+Device buffers are torch tensors on a ROCm device (their data pointers are
+passed through); streams are torch streams.  If the shared library has not
+been built, importing this module raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqrmc.so")
+
+MAX_D = 16
+MAX_N = 128
+
+SET_TENSOR, SET_HC_MAX, SET_HC_1P = 0, 1, 2
+SET_KINDS = {"tensor": SET_TENSOR, "hc_max": SET_HC_MAX, "hc_1p": SET_HC_1P}
+F_LINEAR, F_SIN, F_ALLEN_CAHN, F_ZRAT = 0, 1, 2, 3
+DRIVERS = {"linear": F_LINEAR, "sin": F_SIN, "allen_cahn": F_ALLEN_CAHN, "zrat": F_ZRAT}
+
+STATUS = {0: "QR_OK", -1: "QR_EINVAL", -2: "QR_ENOMEM", -3: "QR_EDEVICE", -4: "QR_ERANGE",
+          -5: "QR_ENUMERIC", -6: "QR_ENOTSUP"}
+
+# kernel classes of qr_ctx_kernel_time
+K_PATH, K_PROJECT, K_REDUCE, K_GATHER = 0, 1, 2, 3
+
+EXPORTS = ["qr_last_error", "qr_version", "qr_build_basis", "qr_basis_info", "qr_basis_indices",
+           "qr_basis_free", "qr_ctx_create", "qr_ctx_destroy", "qr_ctx_set_timing",
+           "qr_ctx_kernel_time", "qr_ctx_reset_timing", "qr_backward_step", "qr_solve", "qr_eval",
+           "qr_project", "qr_path_responses", "qr_sample_points", "qr_host_uniform",
+           "qr_host_norm_icdf", "qr_host_philox"]
+
+
+class QrError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Problem(C.Structure):
+    _fields_ = [
+        ("d", C.c_int32), ("nbm", C.c_int32), ("N", C.c_int32), ("driver", C.c_int32),
+        ("f_a", C.c_double), ("clamp", C.c_double),
+        ("t", C.c_double * (MAX_N + 1)),
+        ("b0", C.c_double * MAX_D), ("b1", C.c_double * MAX_D),
+        ("sigma", C.c_double * (MAX_D * MAX_D)),
+        ("sol_A", C.c_double), ("sol_c", C.c_double), ("sol_p", C.c_double),
+        ("sol_w", C.c_double * MAX_D),
+    ]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: run paper_2407_21084_amd/build.py (hipcc, gfx950)")
+
+_lib = C.CDLL(LIB_PATH)
+_P, _I32, _I64, _U64, _U32, _D = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_uint32, C.c_double
+_SIGS = {
+    "qr_last_error": (C.c_char_p, []),
+    "qr_version": (C.c_char_p, []),
+    "qr_build_basis": (C.c_int, [_I32, _I32, _I32, C.POINTER(_P)]),
+    "qr_basis_info": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I32)]),
+    "qr_basis_indices": (C.c_int, [_P, _P]),
+    "qr_basis_free": (None, [_P]),
+    "qr_ctx_create": (C.c_int, [_I32, C.POINTER(_P)]),
+    "qr_ctx_destroy": (None, [_P]),
+    "qr_ctx_set_timing": (C.c_int, [_P, _I32]),
+    "qr_ctx_kernel_time": (C.c_int, [_P, _I32, C.POINTER(_D), C.POINTER(_I64)]),
+    "qr_ctx_reset_timing": (C.c_int, [_P]),
+    "qr_backward_step": (C.c_int, [_P, C.POINTER(Problem), _P, _I32, _I64, _U64, _P, _P]),
+    "qr_solve": (C.c_int, [_P, C.POINTER(Problem), _P, _I64, _U64, _P, _P]),
+    "qr_eval": (C.c_int, [_P, _P, _P, _I64, _P, _P, _P, _P]),
+    "qr_project": (C.c_int, [_P, _P, _I64, _P, _P, _P, _P]),
+    "qr_path_responses": (C.c_int, [_P, C.POINTER(Problem), _P, _I32, _I64, _U64, _P, _P, _P, _P]),
+    "qr_sample_points": (C.c_int, [_P, _I32, _U64, _U32, _I32, _I64, _I64, _P, _P]),
+    "qr_host_uniform": (_D, [_U64, _U32, _U64, _U32, _U32]),
+    "qr_host_norm_icdf": (_D, [_D]),
+    "qr_host_philox": (None, [_P, _P, _P]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def lib():
+    return _lib
+
+
+def _check(status: int) -> None:
+    if status != 0:
+        raise QrError(status, _lib.qr_last_error().decode())
+
+
+def version() -> str:
+    return _lib.qr_version().decode()
+
+
+# ---------------------------------------------------------------------------
+# host-side helpers (no device)
+# ---------------------------------------------------------------------------
+
+def host_uniform(seed, stream, m, i, r) -> float:
+    return _lib.qr_host_uniform(seed, stream, m, i, r)
+
+
+def host_norm_icdf(u: float) -> float:
+    return _lib.qr_host_norm_icdf(u)
+
+
+def host_philox(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    _lib.qr_host_philox(c.ctypes.data, k.ctypes.data, out.ctypes.data)
+    return out
+
+
+class Basis:
+    """Index set Gamma and its basis metadata (qr_build_basis)."""
+
+    def __init__(self, d: int, kind, level: int):
+        kind = SET_KINDS[kind] if isinstance(kind, str) else int(kind)
+        h = _P()
+        _check(_lib.qr_build_basis(d, kind, level, C.byref(h)))
+        self._h = h
+        self.d, self.kind, self.level = d, kind, level
+        nf, nr, mn = _I64(), _I64(), _I32()
+        _check(_lib.qr_basis_info(h, C.byref(nf), C.byref(nr), C.byref(mn)))
+        self.n_funcs, self.n_reps, self.max_nnz = nf.value, nr.value, mn.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def indices(self) -> np.ndarray:
+        out = np.zeros((self.n_reps, self.d), dtype=np.int32)
+        _check(_lib.qr_basis_indices(self._h, out.ctypes.data))
+        return out
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.qr_basis_free(h)
+            self._h = None
+
+
+def make_problem(d, N, T=None, times=None, sigma=None, b0=None, b1=None, driver="sin", f_a=0.0,
+                 sol_A=1.0, sol_c=1.0, sol_p=0.0, sol_w=None, clamp=math.inf) -> Problem:
+    sigma = np.eye(d) if sigma is None else np.asarray(sigma, dtype=np.float64)
+    nbm = sigma.shape[1]
+    if times is None:
+        times = [T * j / N for j in range(N + 1)]
+    p = Problem()
+    p.d, p.nbm, p.N = d, nbm, N
+    p.driver = DRIVERS[driver] if isinstance(driver, str) else int(driver)
+    p.f_a, p.clamp = f_a, clamp
+    for j, t in enumerate(times):
+        p.t[j] = t
+    b0 = [0.0] * d if b0 is None else b0
+    b1 = [0.0] * d if b1 is None else b1
+    sol_w = [1.0] * d if sol_w is None else sol_w
+    for l in range(d):
+        p.b0[l], p.b1[l], p.sol_w[l] = b0[l], b1[l], sol_w[l]
+        for k in range(nbm):
+            p.sigma[l * nbm + k] = sigma[l, k]
+    p.sol_A, p.sol_c, p.sol_p = sol_A, sol_c, sol_p
+    return p
+
+
+def problem_from(w) -> Problem:
+    """Marshal any object with the workload attributes (d, N, T, sigma, b0,
+    b1, driver, f_a, sol_*, clamp) into a qr_problem."""
+    return make_problem(w.d, w.N, T=w.T, sigma=w.sigma, b0=w.b0, b1=w.b1, driver=w.driver,
+                        f_a=w.f_a, sol_A=w.sol_A, sol_c=w.sol_c, sol_p=w.sol_p, sol_w=w.sol_w,
+                        clamp=w.clamp)
+
+
+# ---------------------------------------------------------------------------
+# device side
+# ---------------------------------------------------------------------------
+
+def _stream_ptr(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dptr(t) -> C.c_void_p:
+    if t is None:
+        return C.c_void_p(0)
+    import torch
+    assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous(), "float64 contiguous device tensor expected"
+    return C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """qr_ctx on one device; owns the library workspace."""
+
+    def __init__(self, device: int = 0):
+        h = _P()
+        _check(_lib.qr_ctx_create(device, C.byref(h)))
+        self._h = h
+        self.device = device
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.qr_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def set_timing(self, on: bool):
+        _check(_lib.qr_ctx_set_timing(self._h, 1 if on else 0))
+
+    def kernel_time(self, which: int):
+        ms, n = _D(), _I64()
+        _check(_lib.qr_ctx_kernel_time(self._h, which, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def reset_timing(self):
+        _check(_lib.qr_ctx_reset_timing(self._h))
+
+    # -- the method ----------------------------------------------------------
+    def backward_step(self, prob: Problem, basis: Basis, i: int, M: int, seed: int, alpha, stream=None):
+        _check(_lib.qr_backward_step(self._h, C.byref(prob), basis.handle, i, M, seed, _dptr(alpha),
+                                     _stream_ptr(stream)))
+
+    def solve(self, prob: Problem, basis: Basis, M: int, seed: int, alpha, stream=None):
+        _check(_lib.qr_solve(self._h, C.byref(prob), basis.handle, M, seed, _dptr(alpha),
+                             _stream_ptr(stream)))
+
+    def eval(self, basis: Basis, alpha_row, x, y, grad=None, stream=None):
+        n = y.shape[0]
+        _check(_lib.qr_eval(self._h, basis.handle, _dptr(alpha_row), n, _dptr(x), _dptr(y),
+                            _dptr(grad), _stream_ptr(stream)))
+
+    def project(self, basis: Basis, x, s, alpha_row, stream=None):
+        n = s.shape[0]
+        _check(_lib.qr_project(self._h, basis.handle, n, _dptr(x), _dptr(s), _dptr(alpha_row),
+                               _stream_ptr(stream)))
+
+    def path_responses(self, prob: Problem, basis: Basis, i: int, M: int, seed: int, alpha, s,
+                       x0=None, stream=None):
+        _check(_lib.qr_path_responses(self._h, C.byref(prob), basis.handle, i, M, seed, _dptr(alpha),
+                                      _dptr(s), _dptr(x0), _stream_ptr(stream)))
+
+    def sample_points(self, d: int, seed: int, stream_id: int, i: int, n: int, x, m0: int = 0,
+                      stream=None):
+        _check(_lib.qr_sample_points(self._h, d, seed, stream_id, i, m0, n, _dptr(x),
+                                     _stream_ptr(stream)))

@@ -1,0 +1,292 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Both sides consume the same Philox streams; the tolerance for FP64 results is
+relative 1e-10, applied per coefficient against max(|alpha_k|, A_k) where
+A_k = (1/M) sum |S phi_k| bounds the cancellation in the Monte-Carlo sum,
+and to the whole row in the 2-norm.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2407_21084_amd import qrmc as Q
+    ctx = Q.Context(0)
+    yield Q, ctx, torch
+    ctx.close()
+
+
+def _dev(torch, a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _host(t):
+    return t.detach().cpu().numpy()
+
+
+def _assert_alpha(gpu, ref, absum, tol=TOL, what=""):
+    scale = np.maximum(np.abs(ref), absum)
+    bad = np.abs(gpu - ref) > tol * scale + 1e-300
+    assert not bad.any(), f"{what}: {bad.sum()} coefficients off, worst {np.max(np.abs(gpu - ref) / (scale + 1e-300))}"
+    assert np.linalg.norm(gpu - ref) <= tol * np.linalg.norm(ref) + 1e-300, what
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+# ---------------------------------------------------------------------------
+# pieces
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1, 257, 5000])
+def test_sample_points(env, n):
+    Q, ctx, torch = env
+    _say(f"sample_points n={n}")
+    d = 5
+    x = torch.empty((d, n), dtype=torch.float64, device="cuda")
+    ctx.sample_points(d, 11, 1, 3, n, x, m0=17)
+    torch.cuda.synchronize()
+    ref = O.sample_points(d, 11, 1, 3, n, m0=17)
+    assert np.allclose(_host(x).T, ref, rtol=1e-14, atol=1e-14)
+
+
+@pytest.mark.parametrize("d,kind,level,n", [(2, "tensor", 4, 1), (2, "tensor", 4, 4099),
+                                            (3, "hc_1p", 12, 1000), (6, "hc_max", 16, 700),
+                                            (1, "tensor", 0, 33), (10, "hc_1p", 32, 300)])
+def test_project(env, d, kind, level, n):
+    Q, ctx, torch = env
+    _say(f"project d={d} {kind} {level} n={n}")
+    b = Q.Basis(d, kind, level)
+    reps = O.enumerate_set(d, kind, level)
+    x = W.logistic_points(n, d, seed=d + n)
+    s = W.responses(n, seed=n)
+    a = torch.empty(b.n_funcs, dtype=torch.float64, device="cuda")
+    ctx.project(b, _dev(torch, x.T), _dev(torch, s), a)
+    torch.cuda.synchronize()
+    ref, absum = O.project(reps, x, s, with_abs=True)
+    _assert_alpha(_host(a), ref, absum, what="project")
+
+
+@pytest.mark.parametrize("d,kind,level,n,grad", [(2, "tensor", 4, 1000, False), (2, "tensor", 4, 129, True),
+                                                 (6, "hc_max", 16, 300, False), (3, "hc_1p", 12, 500, True),
+                                                 (10, "hc_1p", 32, 200, True)])
+def test_eval(env, d, kind, level, n, grad):
+    Q, ctx, torch = env
+    _say(f"eval d={d} {kind} {level} n={n} grad={grad}")
+    b = Q.Basis(d, kind, level)
+    reps = O.enumerate_set(d, kind, level)
+    alpha = W.synthetic_alpha(b.n_funcs, 1, seed=3)[0]
+    x = W.logistic_points(n, d, seed=1)
+    y = torch.empty(n, dtype=torch.float64, device="cuda")
+    g = torch.empty((d, n), dtype=torch.float64, device="cuda") if grad else None
+    ctx.eval(b, _dev(torch, alpha), _dev(torch, x.T), y, g)
+    torch.cuda.synchronize()
+    if grad:
+        ry, rg = O.evaluate(reps, alpha, x, grad=True)
+        scale = np.abs(alpha).sum() * 2 * math.pi * level
+        assert np.abs(_host(g).T - rg).max() <= TOL * scale
+    else:
+        ry = O.evaluate(reps, alpha, x)
+    assert np.abs(_host(y) - ry).max() <= TOL * np.abs(alpha).sum()
+
+
+# ---------------------------------------------------------------------------
+# path responses and backward steps
+# ---------------------------------------------------------------------------
+
+def _small(w, **kw):
+    return w.with_(**kw)
+
+
+@pytest.mark.parametrize("wname,i,M", [("cfg1", 9, 1), ("cfg1", 8, 777), ("cfg1", 0, 2000),
+                                       ("cfg2", 19, 300), ("cfg2", 17, 128)])
+def test_path_responses(env, wname, i, M):
+    Q, ctx, torch = env
+    w = {"cfg1": W.CFG1, "cfg2": W.CFG2}[wname]
+    _say(f"path_responses {w.name} i={i} M={M}")
+    b = Q.Basis(w.d, w.set_kind, w.level)
+    reps = O.reps_for(w)
+    alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=7, scale=0.2)
+    s = torch.empty(M, dtype=torch.float64, device="cuda")
+    x0 = torch.empty((w.d, M), dtype=torch.float64, device="cuda")
+    ctx.path_responses(Q.problem_from(w), b, i, M, 5, _dev(torch, alpha), s, x0)
+    torch.cuda.synchronize()
+    sg, xg = _host(s), _host(x0).T
+    ms = sorted(set([0, M - 1] + list(np.random.default_rng(0).integers(0, M, 6))))
+    for m in ms:
+        ref = O.path_response(w, reps, i, 5, int(m), alpha)
+        assert abs(sg[m] - ref) <= TOL * max(1.0, abs(ref)), (m, sg[m], ref)
+        assert np.allclose(xg[m], [O.logistic_icdf(O.uniform(5, 0, int(m), i, l)) for l in range(w.d)],
+                           rtol=1e-14, atol=1e-14)
+
+
+@pytest.mark.parametrize("i", [9, 8, 4])
+def test_backward_step_cfg1(env, i):
+    Q, ctx, torch = env
+    w = W.CFG1
+    _say(f"backward_step cfg1 i={i}")
+    b = Q.Basis(w.d, w.set_kind, w.level)
+    reps = O.reps_for(w)
+    alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=11, scale=0.2)
+    a = _dev(torch, alpha)
+    ctx.backward_step(Q.problem_from(w), b, i, w.M, w.seed, a)
+    torch.cuda.synchronize()
+    ref_tab = alpha.copy()
+    ref, absum, _, _ = O.backward_step(w, reps, i, w.M, w.seed, ref_tab)
+    got = _host(a)
+    _assert_alpha(got[i], ref, absum, what=f"row {i}")
+    # other rows untouched
+    rows = [r for r in range(w.N) if r != i]
+    assert np.array_equal(got[rows], alpha[rows])
+
+
+def test_backward_step_cfg2_reduced_M(env):
+    """Full |Gamma| = 169,209 of the d=6 hyperbolic cross, M reduced so the
+    oracle finishes: steps N-1 and N-2."""
+    Q, ctx, torch = env
+    w = W.CFG2
+    b = Q.Basis(w.d, w.set_kind, w.level)
+    reps = O.reps_for(w)
+    M = 600
+    alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=13, scale=0.1, decay=0.8)
+    for i in (19, 18):
+        _say(f"backward_step cfg2 i={i} M={M}")
+        a = _dev(torch, alpha)
+        ctx.backward_step(Q.problem_from(w), b, i, M, w.seed, a)
+        torch.cuda.synchronize()
+        ref, absum, _, _ = O.backward_step(w, reps, i, M, w.seed, alpha.copy())
+        _assert_alpha(_host(a)[i], ref, absum, what=f"cfg2 row {i}")
+
+
+def test_solve_cfg1_full(env):
+    Q, ctx, torch = env
+    w = W.CFG1
+    _say("solve cfg1")
+    b = Q.Basis(w.d, w.set_kind, w.level)
+    reps = O.reps_for(w)
+    a = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device="cuda")
+    ctx.solve(Q.problem_from(w), b, w.M, w.seed, a)
+    torch.cuda.synchronize()
+    got = _host(a)
+    ref = O.solve(w, reps)
+    for i in range(w.N - 1, -1, -1):
+        _, absum, _, _ = O.backward_step(w, reps, i, w.M, w.seed, ref.copy())
+        _assert_alpha(got[i], ref[i], absum, what=f"solve row {i}")
+    # deterministic: a second solve is bit-identical
+    a2 = torch.zeros_like(a)
+    ctx.solve(Q.problem_from(w), b, w.M, w.seed, a2)
+    torch.cuda.synchronize()
+    assert torch.equal(a, a2)
+
+
+def test_solve_cfg1_error_against_closed_form(env):
+    """Relative L2 error at t_0 against u(0,.) on stream-1 test points,
+    evaluated with qr_eval, equals the oracle's figure."""
+    Q, ctx, torch = env
+    w = W.CFG1
+    b = Q.Basis(w.d, w.set_kind, w.level)
+    reps = O.reps_for(w)
+    a = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device="cuda")
+    ctx.solve(Q.problem_from(w), b, w.M, w.seed, a)
+    n = 1 << 14
+    x = torch.empty((w.d, n), dtype=torch.float64, device="cuda")
+    ctx.sample_points(w.d, w.seed, 1, 0, n, x)
+    y = torch.empty(n, dtype=torch.float64, device="cuda")
+    ctx.eval(b, a[0].contiguous(), x, y)
+    torch.cuda.synchronize()
+    xh = _host(x).T
+    u = np.exp(-1.0) * np.cos(xh[:, 0] + xh[:, 1])
+    rel = np.linalg.norm(_host(y) - u) / np.linalg.norm(u)
+    _, _, rel_oracle = O.errors(w, reps, O.solve(w, reps), seed=w.seed, n=n)
+    assert abs(rel - rel_oracle) < 1e-9
+    assert 0.3 < rel < 0.6
+
+
+def test_ragged_and_degenerate_sizes(env):
+    Q, ctx, torch = env
+    _say("degenerate sizes")
+    # N = 1, d = 1, basis with only the constant (level 0)
+    w = W.Workload(name="tiny", d=1, N=1, T=0.5, sigma=[[0.3]], b0=[0.1], b1=[0.2],
+                   set_kind="tensor", level=0, M=5, driver="allen_cahn", f_a=0.0,
+                   sol_A=0.5, sol_c=0.7, sol_p=0.1, sol_w=[1.3], clamp=0.8)
+    b = Q.Basis(1, "tensor", 0)
+    assert b.n_funcs == 1
+    a = torch.zeros((1, 1), dtype=torch.float64, device="cuda")
+    ctx.solve(Q.problem_from(w), b, w.M, 3, a)
+    torch.cuda.synchronize()
+    ref = O.solve(w, O.reps_for(w), M=5, seed=3)
+    assert abs(_host(a)[0, 0] - ref[0, 0]) <= TOL * abs(ref[0, 0])
+    # invalid: i out of range, M = 0
+    with pytest.raises(Q.QrError):
+        ctx.backward_step(Q.problem_from(w), b, 1, 5, 3, a)
+    with pytest.raises(Q.QrError):
+        ctx.solve(Q.problem_from(w), b, 0, 3, a)
+    # dimension mismatch between basis and problem
+    with pytest.raises(Q.QrError):
+        ctx.solve(Q.problem_from(W.CFG1), b, 5, 3, a)
+
+
+def test_prefix_property(env):
+    """Path m uses counters (m, i, r) only: the first M' responses of a cloud
+    of M > M' paths are those of the cloud of M' paths."""
+    Q, ctx, torch = env
+    w = W.CFG1
+    b = Q.Basis(w.d, w.set_kind, w.level)
+    alpha = _dev(torch, W.synthetic_alpha(b.n_funcs, w.N, seed=2, scale=0.2))
+    s1 = torch.empty(1000, dtype=torch.float64, device="cuda")
+    s2 = torch.empty(3333, dtype=torch.float64, device="cuda")
+    ctx.path_responses(Q.problem_from(w), b, 3, 1000, 0, alpha, s1)
+    ctx.path_responses(Q.problem_from(w), b, 3, 3333, 0, alpha, s2)
+    torch.cuda.synchronize()
+    assert torch.equal(s1, s2[:1000])
+
+
+# ---------------------------------------------------------------------------
+# the benchmarked configuration at full size (M = 2^20, |Gamma| = 169,209)
+# ---------------------------------------------------------------------------
+
+def test_cfg2_full_size_sampled(env):
+    """At full M: step N-1 coefficients for sampled k (the oracle projects its
+    own responses onto a subset of the basis), and step N-2 responses for
+    sampled paths."""
+    Q, ctx, torch = env
+    w = W.CFG2
+    b = Q.Basis(w.d, w.set_kind, w.level)
+    reps = O.reps_for(w)
+    _say("cfg2 full size: step N-1")
+    a = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device="cuda")
+    ctx.backward_step(Q.problem_from(w), b, w.N - 1, w.M, w.seed, a)
+    torch.cuda.synchronize()
+    got = _host(a)[w.N - 1]
+    rng = np.random.default_rng(1)
+    sub = np.concatenate([[0], np.sort(rng.choice(np.arange(1, reps.shape[0]), 24, replace=False))])
+    sub_reps = np.ascontiguousarray(reps[sub])
+    ref, absum, _, _ = O.backward_step(w, sub_reps, w.N - 1, w.M, w.seed,
+                                       np.zeros((w.N, 2 * len(sub) - 1)))
+    idx = [0] + [f for r in sub[1:] for f in (2 * r - 1, 2 * r)]
+    _assert_alpha(got[idx], ref, absum, what="cfg2 full N-1 sampled")
+    _say("cfg2 full size: responses of step N-2")
+    alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=17, scale=0.1, decay=0.8)
+    s = torch.empty(w.M, dtype=torch.float64, device="cuda")
+    ctx.path_responses(Q.problem_from(w), b, w.N - 2, w.M, w.seed, _dev(torch, alpha), s)
+    torch.cuda.synchronize()
+    sg = _host(s)
+    for m in [0, w.M - 1] + list(rng.integers(0, w.M, 14)):
+        ref = O.path_response(w, reps, w.N - 2, w.seed, int(m), alpha)
+        assert abs(sg[m] - ref) <= TOL * max(1.0, abs(ref)), m

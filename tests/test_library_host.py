@@ -1,0 +1,96 @@
+"""Host-side checks of libqrmc that need no GPU: the library loads and
+exports every symbol of include/qrmc.h, its host mirrors of the scalar device
+routines agree with independent references, and the index-set enumeration
+is bit-identical to the oracle's."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+from scipy import special
+
+import oracle as O
+import workloads as W
+from paper_2407_21084_amd import qrmc as Q
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def test_exports_every_declared_symbol():
+    header = open(os.path.join(ROOT, "include", "qrmc.h")).read()
+    declared = set(re.findall(r"\b(qr_[a-z_0-9]+)\s*\(", header))
+    assert len(declared) >= 18
+    for name in declared:
+        assert hasattr(Q.lib(), name), name
+    assert set(Q.EXPORTS) == declared
+    assert "gfx950" in Q.version()
+
+
+def test_host_philox_known_answers():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt"))
+            if l.strip() and not l.startswith("#")]
+    for r in rows:
+        v = [int(h, 16) for h in r]
+        assert list(Q.host_philox(v[0:4], v[4:6])) == v[6:10]
+
+
+def test_host_uniform_matches_oracle_stream():
+    """Two independent implementations of the same stream layout agree bit for bit."""
+    for seed in (0, 1, 0xDEADBEEF12345678):
+        for stream in (0, 1, 4):
+            for m in (0, 1, 12345, (1 << 33) + 7):
+                for i in (0, 9):
+                    for r in range(5):
+                        assert Q.host_uniform(seed, stream, m, i, r) == O.uniform(seed, stream, m, i, r)
+
+
+def test_host_norm_icdf_matches_scipy():
+    us = np.concatenate([np.logspace(-300, -1, 300), np.linspace(0.01, 0.99, 99),
+                         1 - np.logspace(-15, -2, 60), [2.0 ** -53, 0.5, 1 - 2.0 ** -53]])
+    for u in us:
+        a, b = Q.host_norm_icdf(float(u)), float(special.ndtri(u))
+        assert abs(a - b) <= 2e-15 * max(1.0, abs(b)), (u, a, b)
+
+
+@pytest.mark.parametrize("d,kind,level", [(1, "tensor", 6), (2, "tensor", 4), (3, "tensor", 2),
+                                          (2, "hc_max", 4), (3, "hc_max", 7), (5, "hc_max", 9),
+                                          (4, "hc_1p", 12), (6, "hc_1p", 20), (2, "tensor", 0),
+                                          (3, "hc_max", 1)])
+def test_basis_enumeration_matches_oracle(d, kind, level):
+    b = Q.Basis(d, kind, level)
+    ref = O.enumerate_set(d, kind, level)
+    assert b.n_reps == ref.shape[0]
+    assert b.n_funcs == 2 * ref.shape[0] - 1 == O.count_set(d, kind, level)
+    assert np.array_equal(b.indices(), ref)
+    assert b.max_nnz == (int(np.max(np.count_nonzero(ref, axis=1))) if ref.shape[0] else 0)
+
+
+@pytest.mark.parametrize("w", [W.CFG1, W.CFG2, W.CFG3, W.CFG5], ids=lambda w: w.name)
+def test_configuration_bases_match_oracle(w):
+    b = Q.Basis(w.d, w.set_kind, w.level)
+    ref = O.enumerate_set(w.d, w.set_kind, w.level)
+    assert np.array_equal(b.indices(), ref)
+    assert b.max_nnz <= 8
+
+
+def test_invalid_arguments_are_rejected():
+    with pytest.raises(Q.QrError) as e:
+        Q.Basis(0, "tensor", 2)
+    assert e.value.status == -1
+    with pytest.raises(Q.QrError):
+        Q.Basis(17, "tensor", 2)
+    with pytest.raises(Q.QrError):
+        Q.Basis(2, 7, 2)
+    with pytest.raises(Q.QrError):
+        Q.Basis(2, "tensor", -1)
+
+
+def test_context_without_device_reports_device_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(Q.QrError) as e:
+        Q.Context(0)
+    assert e.value.status == -3
