@@ -53,13 +53,15 @@ struct qr_basis {
     std::vector<int32_t> canon;          // [nrep][d] lexicographic order
     std::vector<int32_t> canon_of_trav;  // traversal index -> canonical index
     std::vector<uint32_t> ops;           // node program, nrep + kOpPad entries
-    std::vector<RangeStart> ranges;      // projection ranges of kTaskMax nodes
+    std::vector<TaskItem> items;         // projection task items
+    std::vector<Task> tasks;             // projection tasks of at most kTaskMax nodes
     // device copies (one device at a time)
     std::mutex mu;
     int dev = -1;
     int32_t *d_canon_of_trav = nullptr;
     uint32_t *d_ops = nullptr;
-    RangeStart *d_ranges = nullptr;
+    TaskItem *d_items = nullptr;
+    Task *d_tasks = nullptr;
     int64_t ld() const { return nrep + kOpPad; }
 };
 
@@ -72,28 +74,49 @@ struct Builder {
     std::vector<int32_t> cur;
     std::vector<int32_t> &trav;
     std::vector<uint32_t> &ops;
+    std::vector<int64_t> &subtree;
+    std::vector<TaskItem> &nodes;
     bool overflow = false;
     int32_t max_depth = 0;
 
-    void push(int depth, bool fresh, int l, bool neg) {
+    void push(int depth, bool fresh, int l, bool neg, int prod) {
         if ((int64_t)ops.size() >= kMaxReps) {
             overflow = true;
             return;
         }
         trav.insert(trav.end(), cur.begin(), cur.end());
         ops.push_back(depth == 0 ? 0u : make_op(depth, fresh, l, neg));
+        subtree.push_back(1);
+        TaskItem n{};
+        n.depth = depth;
+        n.last = depth == 0 ? -1 : l;
+        n.prod = prod;
+        n.full = 1;
+        int t = 0;
+        for (int c = 0; c < R.d; ++c) {
+            if (cur[c] != 0) {
+                if (t < kMaxDepthCap) {
+                    n.coord[t] = c;
+                    n.val[t] = cur[c];
+                }
+                ++t;
+            }
+        }
+        nodes.push_back(n);
         max_depth = std::max(max_depth, depth);
     }
 
-    // Mirror of the device traversal order (see the node program in qrmc_common.h).
+    // Mirror of the device traversal order (visit<T> in qrmc_kernels.hip).
     void visit(int T, int p, int P) {
         for (int l = p + 1; l < R.d && !overflow; ++l) {
             for (int s = 0; s < (T == 0 ? 1 : 2); ++s) {
                 for (int m = 1; rule_ok(R, P, m) && !overflow; ++m) {
                     cur[l] = s ? -m : m;
                     const int P2 = rule_child(R, P, m);
-                    push(T + 1, m == 1, l, s == 1);
+                    const int64_t me = (int64_t)subtree.size();
+                    push(T + 1, m == 1, l, s == 1, P2);
                     if (l + 1 < R.d && rule_ok(R, P2, 1)) visit(T + 1, l, P2);
+                    if (!overflow) subtree[me] = (int64_t)subtree.size() - me;
                 }
             }
             cur[l] = 0;
@@ -101,28 +124,43 @@ struct Builder {
     }
 };
 
-// Fixed-size ranges of the node program for the projection, each with the
-// k-vector of its first node.
-void build_ranges(const std::vector<int32_t> &trav, int d, int64_t nrep,
-                  std::vector<RangeStart> &ranges) {
-    for (int64_t r0 = 0; r0 < nrep; r0 += kTaskMax) {
-        RangeStart rs{};
-        rs.r0 = (int32_t)r0;
-        rs.r1 = (int32_t)std::min<int64_t>(nrep, r0 + kTaskMax);
-        int t = 0;
-        for (int l = 0; l < d; ++l) {
-            const int32_t v = trav[r0 * d + l];
-            if (v != 0) {
-                if (t < kMaxDepthCap) {
-                    rs.coord[t] = l;
-                    rs.val[t] = v;
-                }
-                ++t;
-            }
+// Cut the traversal order into tasks of at most kTaskMax consecutive nodes,
+// each a run of items (a node with its whole subtree, or a node alone when
+// its subtree exceeds kTaskMax).
+void build_tasks(const std::vector<TaskItem> &nodes, const std::vector<int64_t> &subtree,
+                 std::vector<TaskItem> &items, std::vector<Task> &tasks) {
+    const int64_t n = (int64_t)nodes.size();
+    Task cur{0, 0, 0, 0};
+    auto close = [&]() {
+        if (cur.rep_count > 0) {
+            cur.item_end = (int32_t)items.size();
+            tasks.push_back(cur);
         }
-        rs.depth = t;
-        ranges.push_back(rs);
+        cur = Task{(int32_t)items.size(), 0, 0, 0};
+    };
+    int64_t r = 0;
+    while (r < n) {
+        const int64_t sz = subtree[r];
+        if (sz <= kTaskMax - cur.rep_count) {
+            if (cur.rep_count == 0) cur.rep_begin = (int32_t)r;
+            TaskItem it = nodes[r];
+            it.full = 1;
+            items.push_back(it);
+            cur.rep_count += (int32_t)sz;
+            r += sz;
+        } else if (sz <= kTaskMax) {
+            close();
+        } else {
+            if (cur.rep_count + 1 > kTaskMax) close();
+            if (cur.rep_count == 0) cur.rep_begin = (int32_t)r;
+            TaskItem it = nodes[r];
+            it.full = 0;
+            items.push_back(it);
+            cur.rep_count += 1;
+            r += 1;
+        }
     }
+    close();
 }
 
 }  // namespace
@@ -140,15 +178,18 @@ extern "C" qr_status qr_build_basis(int32_t d, int32_t kind, int32_t level, qr_b
     b->d = d;
     b->kind = kind;
     b->level = level;
+    std::vector<int64_t> subtree;
+    std::vector<TaskItem> nodes;
     try {
-        Builder B{make_rule(kind, level, d), std::vector<int32_t>(d, 0), b->trav, b->ops};
-        B.push(0, false, 0, false);  // the zero vector
+        Builder B{make_rule(kind, level, d), std::vector<int32_t>(d, 0), b->trav, b->ops, subtree, nodes};
+        B.push(0, false, 0, false, 1);  // the zero vector
         B.visit(0, -1, 1);
         if (B.overflow) {
             delete b;
             return fail(QR_ERANGE, "qr_build_basis: more than %lld representatives", (long long)kMaxReps);
         }
         b->nrep = (int64_t)b->ops.size();
+        subtree[0] = b->nrep;
         b->max_nnz = B.max_depth;
         b->ops.resize(b->nrep + kOpPad, 0u);
 
@@ -165,7 +206,7 @@ extern "C" qr_status qr_build_basis(int32_t d, int32_t kind, int32_t level, qr_b
             std::memcpy(&b->canon[c * d], T + order[c] * d, sizeof(int32_t) * d);
             b->canon_of_trav[order[c]] = (int32_t)c;
         }
-        build_ranges(b->trav, d, b->nrep, b->ranges);
+        build_tasks(nodes, subtree, b->items, b->tasks);
     } catch (const std::bad_alloc &) {
         delete b;
         return fail(QR_ENOMEM, "qr_build_basis: out of host memory");
@@ -197,12 +238,14 @@ static void basis_free_device(qr_basis *b) {
         hipDeviceSynchronize();
         hipFree(b->d_canon_of_trav);
         hipFree(b->d_ops);
-        hipFree(b->d_ranges);
+        hipFree(b->d_items);
+        hipFree(b->d_tasks);
         hipSetDevice(cur);
     }
     b->d_canon_of_trav = nullptr;
     b->d_ops = nullptr;
-    b->d_ranges = nullptr;
+    b->d_items = nullptr;
+    b->d_tasks = nullptr;
     b->dev = -1;
 }
 
@@ -219,12 +262,15 @@ static qr_status basis_on_device(qr_basis *b, int dev) {
     if (b->dev >= 0) basis_free_device(b);
     QR_HIP(hipMalloc(&b->d_canon_of_trav, sizeof(int32_t) * b->nrep), "hipMalloc(basis)");
     QR_HIP(hipMalloc(&b->d_ops, sizeof(uint32_t) * b->ops.size()), "hipMalloc(basis)");
-    QR_HIP(hipMalloc(&b->d_ranges, sizeof(RangeStart) * b->ranges.size()), "hipMalloc(basis)");
+    QR_HIP(hipMalloc(&b->d_items, sizeof(TaskItem) * b->items.size()), "hipMalloc(basis)");
+    QR_HIP(hipMalloc(&b->d_tasks, sizeof(Task) * b->tasks.size()), "hipMalloc(basis)");
     QR_HIP(hipMemcpy(b->d_canon_of_trav, b->canon_of_trav.data(), sizeof(int32_t) * b->nrep,
                      hipMemcpyHostToDevice), "hipMemcpy(basis)");
     QR_HIP(hipMemcpy(b->d_ops, b->ops.data(), sizeof(uint32_t) * b->ops.size(),
                      hipMemcpyHostToDevice), "hipMemcpy(basis)");
-    QR_HIP(hipMemcpy(b->d_ranges, b->ranges.data(), sizeof(RangeStart) * b->ranges.size(),
+    QR_HIP(hipMemcpy(b->d_items, b->items.data(), sizeof(TaskItem) * b->items.size(),
+                     hipMemcpyHostToDevice), "hipMemcpy(basis)");
+    QR_HIP(hipMemcpy(b->d_tasks, b->tasks.data(), sizeof(Task) * b->tasks.size(),
                      hipMemcpyHostToDevice), "hipMemcpy(basis)");
     b->dev = dev;
     return QR_OK;
@@ -468,7 +514,7 @@ static qr_status begin(qr_ctx *c, void *stream) {
 // step pieces
 // ---------------------------------------------------------------------------
 static void split_plan(const qr_basis *b, int64_t M, int32_t *nsplit, int64_t *pps) {
-    const int64_t ntasks = (int64_t)b->ranges.size();
+    const int64_t ntasks = (int64_t)b->tasks.size();
     const int64_t group = (int64_t)kProjWaves * 64;
     int64_t want = (2048 + ntasks - 1) / ntasks;
     const int64_t maxs = std::max<int64_t>(1, (M + 4 * group - 1) / (4 * group));
@@ -490,8 +536,9 @@ static qr_status project_and_reduce(qr_ctx *c, const qr_basis *b, const double *
     const int cap = depth_cap(b->max_nnz);
     double2 *partial = (double2 *)c->partial.p;
     st = timed(c, 1, s, "project_kernel", [&] {
-        return launch_project(cap, b->d, u, S, M, pps, (int32_t)b->ranges.size(), nsplit,
-                              b->d_ranges, b->d_ops, partial, b->nrep, s);
+        return launch_project(cap, make_rule(b->kind, b->level, b->d), u, S, M, pps,
+                              (int32_t)b->tasks.size(), nsplit, b->d_tasks, b->d_items, partial,
+                              b->nrep, s);
     });
     if (st) return st;
     return timed(c, 2, s, "reduce_kernel", [&] {

@@ -216,4 +216,22 @@ struct RangeStart {
     int32_t val[kMaxDepthCap];
 };
 
+// Root of a run of the depth-first traversal used by the projection: the
+// node k (by its non-zero coordinates) and whether its whole subtree follows.
+struct TaskItem {
+    int32_t depth;   // number of non-zero coordinates (0: the zero vector)
+    int32_t last;    // last non-zero coordinate (-1 for the zero vector)
+    int32_t prod;    // budget product of the node
+    int32_t full;    // 1: node and all its descendants; 0: the node alone
+    int32_t coord[kMaxDepthCap];
+    int32_t val[kMaxDepthCap];
+};
+
+// A projection task: items [item_begin, item_end) covering the consecutive
+// traversal indices [rep_begin, rep_begin + rep_count).
+struct Task {
+    int32_t item_begin, item_end;
+    int32_t rep_begin, rep_count;
+};
+
 }  // namespace qrmc

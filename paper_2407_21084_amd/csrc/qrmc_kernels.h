@@ -8,7 +8,7 @@ namespace qrmc {
 constexpr int kPathBlock = 128;   // threads per block of the path / eval kernels
 constexpr int kProjWaves = 4;     // waves per block of the projection kernel
 constexpr int kProjChunk = 8;     // nodes per cross-lane reduction of the projection
-constexpr int kTaskMax = 256;     // nodes per projection range
+constexpr int kTaskMax = 256;     // nodes per projection task
 
 struct PathArgs {
     const DevProblem *P;
@@ -27,10 +27,9 @@ hipError_t launch_gather(const double *alpha, int32_t row0, int32_t nrows, int64
                          hipStream_t s);
 hipError_t launch_pad(int32_t nrows, int64_t nrep, int64_t ld, double2 *alpha_int, hipStream_t s);
 hipError_t launch_path(int db, int cap, bool grad, const PathArgs &a, hipStream_t s);
-hipError_t launch_project(int cap, int32_t d, const double *u, const double *S, int64_t M,
-                          int64_t paths_per_split, int32_t ntasks, int32_t nsplit,
-                          const RangeStart *ranges, const uint32_t *ops, double2 *partial,
-                          int64_t nrep, hipStream_t s);
+hipError_t launch_project(int cap, const SetRule &R, const double *u, const double *S, int64_t M,
+                          int64_t paths_per_split, int32_t ntasks, int32_t nsplit, const Task *tasks,
+                          const TaskItem *items, double2 *partial, int64_t nrep, hipStream_t s);
 hipError_t launch_reduce(const double2 *partial, int32_t nsplit, int64_t nrep, double M,
                          double2 *alpha_int_row, double *alpha_row,
                          const int32_t *canon_of_trav, hipStream_t s);

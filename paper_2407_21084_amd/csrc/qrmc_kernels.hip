@@ -120,6 +120,19 @@ __device__ __forceinline__ typename Sink::Acc visit(const cplx parent, const int
     return acc;
 }
 
+// Start the traversal below a node of runtime depth `depth` (< CAP).
+template <int T, int CAP, class Sink>
+__device__ __forceinline__ void visit_from(int depth, const cplx v, int p, int P, const SetRule &R,
+                                           const LaneLds &L, Sink &sink) {
+    if constexpr (T < CAP) {
+        if (depth == T) {
+            (void)visit<T, CAP>(v, p, P, R, L, sink);
+            return;
+        }
+        visit_from<T + 1, CAP>(depth, v, p, P, R, L, sink);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Expansion evaluation sink: y = sum_r a_r.x Re(e_r) + a_r.y Im(e_r) with the
 // internal coefficients a_r = (sqrt2 alpha_cos, sqrt2 alpha_sin), a_0 = (alpha_0, 0);
@@ -127,47 +140,91 @@ __device__ __forceinline__ typename Sink::Acc visit(const cplx parent, const int
 // ---------------------------------------------------------------------------
 template <bool GRAD>
 struct EvalAccT {
-    double yre, yim;
+    double y;
 };
 template <>
 struct EvalAccT<true> {
-    double yre, yim, g;
+    double y, g;
 };
 
+typedef __attribute__((address_space(3))) double lds_double;
+
+// Coefficient row staged through LDS: a ring of 4 chunks of kPathBlock nodes
+// shared by the block.  While chunk k is traversed, chunks k and k+1 are in
+// the ring and chunk k+3 is on its way into registers; at the boundary into
+// chunk k (one barrier) the block stores chunk k+2 into the slot of chunk
+// k-2 and requests chunk k+3.  All threads of the block walk the same node
+// sequence, so the barriers are uniform.  Coefficients of the next node are
+// read one node ahead.
 template <bool GRAD>
 struct EvalSink {
     static constexpr bool kGrad = GRAD;
     using Acc = EvalAccT<GRAD>;
-    const QR_CONST double *a;  // [nrep][2], read through the scalar cache
-    int idx;
+    const double2 *g;   // row in global memory
+    int64_t n;          // readable entries of the row
+    lds_double *ring;   // LDS [4 * kPathBlock][2]
+    double2 pend;       // this thread's node of the chunk in flight
+    int tid;
+    int idx;            // node about to be visited
+    double2 nxt;        // its coefficients
+
+    __device__ __forceinline__ double2 fetch(int64_t r) const {
+        return r < n ? g[r] : make_double2(0.0, 0.0);
+    }
+    __device__ __forceinline__ void start() {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) put(c * kPathBlock + tid, fetch((int64_t)c * kPathBlock + tid));
+        pend = fetch(3 * (int64_t)kPathBlock + tid);
+        __syncthreads();
+        idx = 0;
+        nxt = get(0);
+    }
+    __device__ __forceinline__ void put(int slot, const double2 v) {
+        ring[2 * slot] = v.x;
+        ring[2 * slot + 1] = v.y;
+    }
+    __device__ __forceinline__ double2 get(int slot) const {
+        return make_double2(ring[2 * slot], ring[2 * slot + 1]);
+    }
+    __device__ __forceinline__ void boundary(int k) {  // entering chunk k >= 1
+        __syncthreads();
+        put(((k + 2) & 3) * kPathBlock + tid, pend);
+        pend = fetch((int64_t)(k + 3) * kPathBlock + tid);
+    }
     __device__ __forceinline__ double node(const cplx v, Acc &acc) {
-        const double cx = a[2 * idx], cy = a[2 * idx + 1];
+        const double cx = nxt.x, cy = nxt.y;
+        acc.y = fma(cx, v.re, fma(cy, v.im, acc.y));
         ++idx;
-        acc.yre = fma(cx, v.re, acc.yre);
-        acc.yim = fma(cy, v.im, acc.yim);
+        if ((idx & (kPathBlock - 1)) == 0) boundary(idx / kPathBlock);
+        nxt = get(idx & (4 * kPathBlock - 1));
         if constexpr (GRAD) {
-            const double g = fma(cy, v.re, -(cx * v.im));
-            acc.g += g;
-            return g;
+            const double gr = fma(cy, v.re, -(cx * v.im));
+            acc.g += gr;
+            return gr;
         }
         return 0.0;
     }
     __device__ __forceinline__ static void add(Acc &a, const Acc &b) {
-        a.yre += b.yre;
-        a.yim += b.yim;
+        a.y += b.y;
         if constexpr (GRAD) a.g += b.g;
     }
 };
 
+// Expansion at the lane's point by the depth-first traversal.  Every thread of
+// the block must call it (the coefficient staging uses block barriers).
 template <int CAP, bool GRAD>
-__device__ __forceinline__ double tree_eval(const double2 *alpha_row, const SetRule &R,
-                                            const LaneLds &L) {
-    EvalSink<GRAD> s{(const QR_CONST double *)alpha_row, 0};
+__device__ __forceinline__ double tree_eval(const double2 *alpha_row, int64_t nrow, double2 *ring,
+                                            const SetRule &R, const LaneLds &L) {
+    EvalSink<GRAD> s{alpha_row, nrow, (lds_double *)ring, make_double2(0.0, 0.0),
+                     (int)threadIdx.x, 0, make_double2(0.0, 0.0)};
+    s.start();
     typename EvalSink<GRAD>::Acc root{};
     const cplx one{1.0, 0.0};
     s.node(one, root);
     const auto acc = visit<0, CAP>(one, -1, 1, R, L, s);
-    return (root.yre + root.yim) + (acc.yre + acc.yim);
+    // the ring is reused by the next call: let every wave finish reading it
+    __syncthreads();
+    return root.y + acc.y;
 }
 
 // ---------------------------------------------------------------------------
@@ -319,11 +376,17 @@ __global__ __launch_bounds__(kPathBlock) void path_kernel(
     double *__restrict__ x_out) {
     extern __shared__ double2 lds[];
     const int tid = threadIdx.x;
+    // lanes past M simulate a path too (block barriers), but store nothing
     const int64_t m = (int64_t)blockIdx.x * kPathBlock + tid;
-    if (m >= M) return;
+    const bool live = m < M;
     const int d = P0->d, nbm = P0->nbm, N = P0->N;
-    const LaneLds L{lds + tid, GRAD ? reinterpret_cast<double *>(lds + d * kPathBlock) + tid : nullptr,
+    double2 *ring = lds;
+    double2 *lane_base = lds + 4 * kPathBlock;
+    const LaneLds L{lane_base + tid,
+                    GRAD ? reinterpret_cast<double *>(lane_base + d * kPathBlock) + tid : nullptr,
                     kPathBlock};
+    // the path state waits in LDS while the traversal runs
+    double *xs = reinterpret_cast<double *>(lane_base + d * kPathBlock) + (GRAD ? d * kPathBlock : 0) + tid;
 
     PhiloxStream rs(seed, 0u, (uint64_t)m, (uint32_t)i, 0u);
     double x[DB];
@@ -332,8 +395,8 @@ __global__ __launch_bounds__(kPathBlock) void path_kernel(
         x[l] = 0.0;
         if (l < d) {
             x[l] = nl_logistic_icdf(rs.next());
-            if (u_out) u_out[l * M + m] = nl_logistic_cdf(x[l]);
-            if (x_out) x_out[l * M + m] = x[l];
+            if (live && u_out) u_out[l * M + m] = nl_logistic_cdf(x[l]);
+            if (live && x_out) x_out[l * M + m] = x[l];
         }
     }
 
@@ -373,8 +436,12 @@ __global__ __launch_bounds__(kPathBlock) void path_kernel(
                 }
             }
             const double2 *row = alpha_int + (int64_t)(j + 1) * ld;
+#pragma unroll
+            for (int l = 0; l < DB; ++l)
+                if (l < d) xs[l * kPathBlock] = x[l];
+            asm volatile("" ::: "memory");
             if constexpr (GRAD) {
-                y = tree_eval<CAP, true>(row, R, L);
+                y = tree_eval<CAP, true>(row, ld, ring, R, L);
 #pragma unroll
                 for (int l = 0; l < DB; ++l) {
                     if (l < d) {
@@ -383,8 +450,17 @@ __global__ __launch_bounds__(kPathBlock) void path_kernel(
                     }
                 }
             } else {
+#ifdef QRMC_FLAT_EVAL
                 y = flat_eval<CAP>(row, ops, nrep, L);
+#else
+                (void)ops;
+                y = tree_eval<CAP, false>(row, ld, ring, R, L);
+#endif
             }
+            asm volatile("" ::: "memory");
+#pragma unroll
+            for (int l = 0; l < DB; ++l)
+                if (l < d) x[l] = xs[l * kPathBlock];
         } else {
             y = g_term<DB>(P, x, d, GRAD ? gx : nullptr);
         }
@@ -406,16 +482,55 @@ __global__ __launch_bounds__(kPathBlock) void path_kernel(
         S = fma(f, dt, S);
     }
     S += g_term<DB>(P0, x, d, nullptr);
-    S_out[m] = S;
+    if (live) S_out[m] = S;
 }
 
 // ---------------------------------------------------------------------------
-// project_kernel: block (range of the node program, slice of paths).
-// Each wave runs 64 paths at a time through the range; node values times S
-// go to a per-wave LDS buffer and are summed over the lanes every
+// project_kernel: block (task of the traversal, slice of paths).
+// Each wave runs 64 paths at a time through the task's nodes; node values
+// times S go to a per-wave LDS buffer and are summed over the lanes every
 // kProjChunk nodes into per-wave accumulators; the block finally adds its
 // waves in a fixed order and writes the slice's partial sums.
 // ---------------------------------------------------------------------------
+struct ProjSink {
+    static constexpr bool kGrad = false;
+    struct Acc {};
+    __device__ __forceinline__ static void add(Acc &, const Acc &) {}
+    double2 *row;    // this lane's row of the wave buffer: row[c]
+    double2 *wbuf;   // wave buffer [64][kProjChunk + 1]
+    double *acc;     // wave accumulators, doubles [kTaskMax][2]
+    double s;        // this lane's response (0 for lanes past the slice)
+    int c;           // nodes in the current chunk (wave-uniform)
+    int base;        // task-local index of the chunk's first node (wave-uniform)
+    int lane;
+
+    __device__ __forceinline__ double node(const cplx v, Acc &) {
+        row[c] = make_double2(s * v.re, s * v.im);
+        if (++c == kProjChunk) flush();
+        return 0.0;
+    }
+
+    // Sum the chunk over the 64 lanes: lane q adds the 16 lanes of quarter
+    // q>>4 for value q&15 (node (q&15)>>1, component q&1); the quarters are
+    // then combined by two xor-shuffles in a fixed order.
+    __device__ __forceinline__ void flush() {
+        wave_sync();
+        const int val = lane & 15, rep = val >> 1, quarter = lane >> 4;
+        double sum = 0.0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const double2 w = wbuf[(quarter * 16 + k) * (kProjChunk + 1) + rep];
+            sum += (val & 1) ? w.y : w.x;
+        }
+        sum += __shfl_xor(sum, 16);
+        sum += __shfl_xor(sum, 32);
+        if (lane < 16 && rep < c) acc[(base + rep) * 2 + (val & 1)] += sum;
+        wave_sync();
+        base += c;
+        c = 0;
+    }
+};
+
 size_t project_lds_bytes(int32_t d) {
     return (size_t)kProjWaves *
            ((size_t)64 * (kProjChunk + 1) * sizeof(double2) + (size_t)kTaskMax * sizeof(double2) +
@@ -424,102 +539,65 @@ size_t project_lds_bytes(int32_t d) {
 
 template <int CAP>
 __global__ __launch_bounds__(kProjWaves * 64) void project_kernel(
-    const int32_t d, const double *__restrict__ u_in, const double *__restrict__ s_in,
-    const int64_t M, const int64_t paths_per_split, const RangeStart *__restrict__ ranges,
-    const uint32_t *__restrict__ ops, double2 *__restrict__ partial, const int64_t nrep) {
+    const SetRule R, const double *__restrict__ u_in, const double *__restrict__ s_in,
+    const int64_t M, const int64_t paths_per_split, const Task *__restrict__ tasks,
+    const TaskItem *__restrict__ items, double2 *__restrict__ partial, const int64_t nrep) {
     extern __shared__ double2 lds[];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int d = R.d;
     double2 *bufs = lds;
     double *accs = reinterpret_cast<double *>(lds + kProjWaves * 64 * (kProjChunk + 1));
     double2 *Es = lds + kProjWaves * 64 * (kProjChunk + 1) + kProjWaves * kTaskMax;
 
     double2 *wbuf = bufs + wave * 64 * (kProjChunk + 1);
-    double2 *row = wbuf + lane * (kProjChunk + 1);
     double *acc = accs + wave * kTaskMax * 2;
     const LaneLds L{Es + wave * d * 64 + lane, nullptr, 64};
 
-    const RangeStart rs = ranges[blockIdx.x];
-    const int count = rs.r1 - rs.r0;
+    const Task task = tasks[blockIdx.x];
     const int64_t m0 = (int64_t)blockIdx.y * paths_per_split;
     const int64_t m1 = min(M, m0 + paths_per_split);
-    const QR_CONST uint32_t *o = (const QR_CONST uint32_t *)ops;
 
     for (int r = lane; r < kTaskMax * 2; r += 64) acc[r] = 0.0;
     wave_sync();
 
+    ProjSink sink{wbuf + lane * (kProjChunk + 1), wbuf, acc, 0.0, 0, 0, lane};
     for (int64_t gb = m0 + wave * 64; gb < m1; gb += kProjWaves * 64) {
         const int64_t m = gb + lane;
         const bool live = m < m1;
-        const double sv = live ? s_in[m] : 0.0;
+        sink.s = live ? s_in[m] : 0.0;
         for (int l = 0; l < d; ++l) {
             const double u = live ? u_in[l * M + m] : 0.25;
             double sn, cs;
             sincospi(2.0 * u, &sn, &cs);
             L.E[l * 64] = make_double2(cs, sn);
         }
-        // register state after node r0, rebuilt from its k-vector
-        Flat<CAP> st;
-        st.v[0] = cplx{1.0, 0.0};
-        cplx first = st.v[0];
-#pragma unroll
-        for (int t = 1; t <= CAP; ++t) {
-            st.v[t] = cplx{0.0, 0.0};
-            st.mult[t] = cplx{1.0, 0.0};
-            if (t <= rs.depth) {
-                cplx e = L.e(rs.coord[t - 1]);
-                int n = rs.val[t - 1];
+        sink.c = 0;
+        sink.base = 0;
+        for (int it = task.item_begin; it < task.item_end; ++it) {
+            const TaskItem &I = items[it];
+            cplx v{1.0, 0.0};
+            for (int t = 0; t < I.depth; ++t) {
+                cplx e = L.e(I.coord[t]);
+                int n = I.val[t];
                 if (n < 0) {
                     e.im = -e.im;
                     n = -n;
                 }
-                st.mult[t] = e;
-                cplx w = st.v[t - 1];
-                for (int q = 0; q < n; ++q) w = cmul(w, e);
-                st.v[t] = w;
-                first = w;
+                for (int q = 0; q < n; ++q) v = cmul(v, e);
             }
+            ProjSink::Acc none;
+            sink.node(v, none);
+            if (I.full) visit_from<0, CAP>(I.depth, v, I.last, I.prod, R, L, sink);
         }
-        int c = 0, base = 0;
-        auto flush = [&]() {
-            wave_sync();
-            const int val = lane & 15, rep = val >> 1, quarter = lane >> 4;
-            double sum = 0.0;
-#pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                const double2 w = wbuf[(quarter * 16 + k) * (kProjChunk + 1) + rep];
-                sum += (val & 1) ? w.y : w.x;
-            }
-            sum += __shfl_xor(sum, 16);
-            sum += __shfl_xor(sum, 32);
-            if (lane < 16 && rep < c) acc[(base + rep) * 2 + (val & 1)] += sum;
-            wave_sync();
-            base += c;
-            c = 0;
-        };
-        row[c++] = make_double2(sv * first.re, sv * first.im);
-#pragma unroll 1
-        for (int g = 0; g < count; g += 8) {
-            uint32_t op[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) op[q] = o[rs.r0 + g + q];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                if (g + q == 0 || g + q >= count) continue;
-                flat_node<CAP>(st, op[q], L, [&](const cplx v) {
-                    row[c] = make_double2(sv * v.re, sv * v.im);
-                });
-                if (++c == kProjChunk) flush();
-            }
-        }
-        if (c) flush();
+        if (sink.c) sink.flush();
     }
     __syncthreads();
-    double *out = reinterpret_cast<double *>(partial + (int64_t)blockIdx.y * nrep + rs.r0);
-    for (int r = tid; r < count * 2; r += kProjWaves * 64) {
-        double s = 0.0;
+    double *out = reinterpret_cast<double *>(partial + (int64_t)blockIdx.y * nrep + task.rep_begin);
+    for (int r = tid; r < task.rep_count * 2; r += kProjWaves * 64) {
+        double sacc = 0.0;
 #pragma unroll
-        for (int w = 0; w < kProjWaves; ++w) s += accs[w * kTaskMax * 2 + r];
-        out[r] = s;
+        for (int w = 0; w < kProjWaves; ++w) sacc += accs[w * kTaskMax * 2 + r];
+        out[r] = sacc;
     }
 }
 
@@ -589,10 +667,15 @@ __global__ __launch_bounds__(kPathBlock) void eval_kernel(const SetRule R,
                                                           double *__restrict__ grad) {
     extern __shared__ double2 lds[];
     const int tid = threadIdx.x;
-    const int64_t p = (int64_t)blockIdx.x * kPathBlock + tid;
-    if (p >= n) return;
+    // lanes past n evaluate a dummy point (block barriers) and store nothing
+    const int64_t p0 = (int64_t)blockIdx.x * kPathBlock + tid;
+    const bool live = p0 < n;
+    const int64_t p = live ? p0 : n - 1;
     const int d = R.d;
-    const LaneLds L{lds + tid, GRAD ? reinterpret_cast<double *>(lds + d * kPathBlock) + tid : nullptr,
+    double2 *ring = lds;
+    double2 *lane_base = lds + 4 * kPathBlock;
+    const LaneLds L{lane_base + tid,
+                    GRAD ? reinterpret_cast<double *>(lane_base + d * kPathBlock) + tid : nullptr,
                     kPathBlock};
     for (int l = 0; l < d; ++l) {
         const double u = logistic_cdf(x[l * n + p]);
@@ -601,14 +684,24 @@ __global__ __launch_bounds__(kPathBlock) void eval_kernel(const SetRule R,
         L.E[l * kPathBlock] = make_double2(cs, sn);
         if constexpr (GRAD) L.G[l * kPathBlock] = 0.0;
     }
+    const int64_t ld = nrep + kOpPad;
     if constexpr (GRAD) {
-        y[p] = tree_eval<CAP, true>(alpha_int_row, R, L);
-        for (int l = 0; l < d; ++l) {
-            const double u = logistic_cdf(x[l * n + p]);
-            grad[l * n + p] = 2.0 * M_PI * L.G[l * kPathBlock] * (u * (1.0 - u));
+        const double yv = tree_eval<CAP, true>(alpha_int_row, ld, ring, R, L);
+        if (live) {
+            y[p] = yv;
+            for (int l = 0; l < d; ++l) {
+                const double u = logistic_cdf(x[l * n + p]);
+                grad[l * n + p] = 2.0 * M_PI * L.G[l * kPathBlock] * (u * (1.0 - u));
+            }
         }
     } else {
-        y[p] = flat_eval<CAP>(alpha_int_row, ops, nrep, L);
+#ifdef QRMC_FLAT_EVAL
+        const double yv = flat_eval<CAP>(alpha_int_row, ops, nrep, L);
+#else
+        (void)ops;
+        const double yv = tree_eval<CAP, false>(alpha_int_row, ld, ring, R, L);
+#endif
+        if (live) y[p] = yv;
     }
 }
 
@@ -651,7 +744,8 @@ hipError_t launch_pad(int32_t nrows, int64_t nrep, int64_t ld, double2 *alpha_in
 
 template <int DB, int CAP, bool GRAD>
 static hipError_t path_t(const PathArgs &a, hipStream_t s) {
-    const size_t lds = (size_t)a.R.d * kPathBlock * (sizeof(double2) + (GRAD ? sizeof(double) : 0));
+    const size_t lds = 4 * kPathBlock * sizeof(double2) +
+                       (size_t)a.R.d * kPathBlock * (sizeof(double2) + sizeof(double) + (GRAD ? sizeof(double) : 0));
     hipLaunchKernelGGL((path_kernel<DB, CAP, GRAD>), dim3(blocks_for(a.M, kPathBlock)),
                        dim3(kPathBlock), lds, s, a.P, a.R, a.i, a.M, a.seed, a.alpha_int, a.ops,
                        a.nrep, a.ld, a.S, a.u, a.x0);
@@ -679,10 +773,10 @@ hipError_t launch_path(int db, int cap, bool grad, const PathArgs &a, hipStream_
 }
 
 template <int CAP>
-static hipError_t project_t(int32_t d, const double *u, const double *S, int64_t M, int64_t pps,
-                            int32_t ntasks, int32_t nsplit, const RangeStart *ranges,
-                            const uint32_t *ops, double2 *partial, int64_t nrep, hipStream_t s) {
-    const size_t lds = project_lds_bytes(d);
+static hipError_t project_t(const SetRule &R, const double *u, const double *S, int64_t M, int64_t pps,
+                            int32_t ntasks, int32_t nsplit, const Task *tasks,
+                            const TaskItem *items, double2 *partial, int64_t nrep, hipStream_t s) {
+    const size_t lds = project_lds_bytes(R.d);
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void *)project_kernel<CAP>,
@@ -692,19 +786,18 @@ static hipError_t project_t(int32_t d, const double *u, const double *S, int64_t
         attr_set = true;
     }
     hipLaunchKernelGGL(project_kernel<CAP>, dim3((unsigned)ntasks, (unsigned)nsplit),
-                       dim3(kProjWaves * 64), lds, s, d, u, S, M, pps, ranges, ops, partial, nrep);
+                       dim3(kProjWaves * 64), lds, s, R, u, S, M, pps, tasks, items, partial, nrep);
     return hipGetLastError();
 }
 
-hipError_t launch_project(int cap, int32_t d, const double *u, const double *S, int64_t M,
-                          int64_t paths_per_split, int32_t ntasks, int32_t nsplit,
-                          const RangeStart *ranges, const uint32_t *ops, double2 *partial,
-                          int64_t nrep, hipStream_t s) {
+hipError_t launch_project(int cap, const SetRule &R, const double *u, const double *S, int64_t M,
+                          int64_t paths_per_split, int32_t ntasks, int32_t nsplit, const Task *tasks,
+                          const TaskItem *items, double2 *partial, int64_t nrep, hipStream_t s) {
     switch (cap) {
-    case 2: return project_t<2>(d, u, S, M, paths_per_split, ntasks, nsplit, ranges, ops, partial, nrep, s);
-    case 4: return project_t<4>(d, u, S, M, paths_per_split, ntasks, nsplit, ranges, ops, partial, nrep, s);
-    case 6: return project_t<6>(d, u, S, M, paths_per_split, ntasks, nsplit, ranges, ops, partial, nrep, s);
-    case 8: return project_t<8>(d, u, S, M, paths_per_split, ntasks, nsplit, ranges, ops, partial, nrep, s);
+    case 2: return project_t<2>(R, u, S, M, paths_per_split, ntasks, nsplit, tasks, items, partial, nrep, s);
+    case 4: return project_t<4>(R, u, S, M, paths_per_split, ntasks, nsplit, tasks, items, partial, nrep, s);
+    case 6: return project_t<6>(R, u, S, M, paths_per_split, ntasks, nsplit, tasks, items, partial, nrep, s);
+    case 8: return project_t<8>(R, u, S, M, paths_per_split, ntasks, nsplit, tasks, items, partial, nrep, s);
     }
     return hipErrorInvalidValue;
 }
@@ -720,7 +813,8 @@ hipError_t launch_reduce(const double2 *partial, int32_t nsplit, int64_t nrep, d
 template <int CAP, bool GRAD>
 static hipError_t eval_t(const SetRule &R, const double2 *a, const uint32_t *ops, int64_t nrep,
                          const double *x, int64_t n, double *y, double *g, hipStream_t s) {
-    const size_t lds = (size_t)R.d * kPathBlock * (sizeof(double2) + (GRAD ? sizeof(double) : 0));
+    const size_t lds = 4 * kPathBlock * sizeof(double2) +
+                       (size_t)R.d * kPathBlock * (sizeof(double2) + (GRAD ? sizeof(double) : 0));
     hipLaunchKernelGGL((eval_kernel<CAP, GRAD>), dim3(blocks_for(n, kPathBlock)), dim3(kPathBlock),
                        lds, s, R, a, ops, nrep, x, n, y, g);
     return hipGetLastError();

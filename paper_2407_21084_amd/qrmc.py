@@ -15,7 +15,7 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libqrmc.so")
+LIB_PATH = os.environ.get("QRMC_LIB") or os.path.join(_HERE, "libqrmc.so")
 
 MAX_D = 16
 MAX_N = 128
