@@ -71,6 +71,83 @@ def cpu_baseline(w, target_s: float):
                       f"{dt:.1f} s", "seconds": dt}
 
 
+BATCHED = "batched-256"
+
+
+def run_batched(args, torch, W, Q):
+    """The batched form: 256 instances (d ~ U{2..12}, M in {2^14..2^20},
+    level in {8,16,32}, hyperbolic cross prod(1+|k_l|), sin driver with
+    per-instance c_j) in groups of 64 sharing one cloud.  A step solves all
+    groups; evals are counted per instance (M_r |Gamma_r| N(N+1)/2)."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    insts = W.batched_instances()
+    groups = W.batched_group(insts)
+    ctx = Q.Context(0)
+    stream = torch.cuda.current_stream()
+    runs = []
+    evals = 0.0
+    for gw, inst, _ in groups:
+        b = Q.Basis(gw.d, gw.set_kind, gw.level)
+        a = torch.zeros((len(inst), gw.N, b.n_funcs), dtype=torch.float64, device=dev)
+        runs.append((gw, inst, b, a))
+        for (_, d, L, M) in inst:
+            evals += M * Q.Basis(d, gw.set_kind, L).n_funcs * gw.N * (gw.N + 1) / 2
+
+    def step():
+        for gw, inst, b, a in runs:
+            ctx.solve_batched(Q.problem_from(gw), b, inst, gw.seed, a, stream)
+
+    for k in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        print(f"[bench] warmup step {k + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    ctx.reset_timing()
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.set_timing(False)
+    path_ms, path_n = ctx.kernel_time(Q.K_PATH)
+    proj_ms, proj_n = ctx.kernel_time(Q.K_PROJECT)
+    red_ms, _ = ctx.kernel_time(Q.K_REDUCE)
+    print(f"[bench] timed region {elapsed:.2f} s", file=sys.stderr, flush=True)
+
+    # accuracy of every instance at t_0 against its closed form (stream-1 points)
+    n_test = 1 << 14
+    rels = []
+    for gw, inst, b, a in runs:
+        xt = torch.empty((gw.d, n_test), dtype=torch.float64, device=dev)
+        ctx.sample_points(gw.d, gw.seed, 1, 0, n_test, xt, stream=stream)
+        u0 = math.exp(-1.0) * torch.cos(xt[0] + xt[1])
+        yt = torch.empty(n_test, dtype=torch.float64, device=dev)
+        for r in range(len(inst)):
+            ctx.eval(b, a[r, 0].contiguous(), xt, yt, stream=stream)
+            rels.append(float(torch.linalg.norm(yt - u0) / torch.linalg.norm(u0)))
+    torch.cuda.synchronize()
+    line = {
+        "metric": "basis-evals/s (batched form, 256 instances, FP64)",
+        "value": evals * args.steps / elapsed,
+        "unit": "basis-evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": BATCHED, "instances": len(insts), "groups": len(groups),
+                   "evals_per_step": evals},
+        "full_solve_s": elapsed / args.steps,
+        "rel_l2_t0": {"median": float(np.median(rels)), "max": float(np.max(rels))},
+        "kernels_ms_per_solve": {"path": path_ms / args.steps, "project": proj_ms / args.steps,
+                                 "reduce": red_ms / args.steps},
+        "launches_per_step": {"path": path_n // max(1, args.steps), "project": proj_n // max(1, args.steps)},
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -81,6 +158,9 @@ def main():
     import workloads as W
     from paper_2407_21084_amd import qrmc as Q
 
+    if args.workload == BATCHED:
+        run_batched(args, torch, W, Q)
+        return
     w = W.ALL[args.workload]
     if args.M:
         w = w.with_(M=args.M)

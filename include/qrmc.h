@@ -89,9 +89,10 @@ typedef enum {
 typedef struct qr_basis qr_basis; /* opaque, library-owned */
 
 /* Build the index set of kind `kind` and level `level` in dimension d
- * (1 <= d <= QR_MAX_D, level >= 0) and its basis metadata.  Host only; no
- * device is touched.  *out receives a handle to free with qr_basis_free.
- * QR_ERANGE if the set has more than 2^31 representatives. */
+ * (1 <= d <= QR_MAX_D; level >= 0 for the tensor set, level >= 1 for the
+ * hyperbolic crosses, whose sets are empty below 1) and its basis metadata.
+ * Host only; no device is touched.  *out receives a handle to free with
+ * qr_basis_free.  QR_ERANGE if the set has more than 2^31 representatives. */
 qr_status qr_build_basis(int32_t d, int32_t kind, int32_t level, qr_basis **out);
 
 /* n_funcs = |Gamma| (real basis functions), n_reps = representatives
@@ -211,6 +212,40 @@ qr_status qr_path_responses(qr_ctx *ctx, const qr_problem *prob, const qr_basis 
  * x[l][m] = F^{-1}(U(seed, stream_id, m0 + m, i, l)), device SoA [d][n]. */
 qr_status qr_sample_points(qr_ctx *ctx, int32_t d, uint64_t seed, uint32_t stream_id, int32_t i,
                            int64_t m0, int64_t n, double *x, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Batched form: several PDE instances solved on one shared cloud          */
+/* ---------------------------------------------------------------------- */
+
+#define QR_MAX_BATCH 64
+
+/* One instance of a batch.  The paths of a decoupled FBSDE do not depend on
+ * the driver or the terminal condition (eqs (fbsde), (eds)), so instances
+ * that share d, nbm, the time grid, b, sigma, the sampling law and the seed
+ * can share one cloud of start points and Euler paths.  Instance r uses
+ *   - its own driver parameter f_a (the problem's driver kind),
+ *   - the first d coordinates only (1 <= d <= problem d; its solution must
+ *     not depend on the others),
+ *   - the index set of the basis' kind at its own level (<= basis level,
+ *     >= 1 for the hyperbolic crosses) restricted to vectors supported on
+ *     those d coordinates,
+ *   - the first M paths of the shared cloud (1 <= M <= the cloud size).
+ * Its coefficients equal those of qr_solve for the problem with that f_a, on
+ * that index set (embedded in the problem's d coordinates) and that M, up to
+ * summation order. */
+typedef struct {
+    double f_a;
+    int32_t d;
+    int32_t level;
+    int64_t M;
+} qr_instance;
+
+/* Solve R (1 <= R <= QR_MAX_BATCH) instances on one cloud of max_r M_r
+ * paths.  alpha: device [R][N][n_funcs] (canonical order); coefficients of
+ * functions outside an instance's index set are written as 0.  The driver
+ * must not depend on z (QR_ENOTSUP otherwise).  inst: host array of R. */
+qr_status qr_solve_batched(qr_ctx *ctx, const qr_problem *prob, const qr_basis *basis, int32_t R,
+                           const qr_instance *inst, uint64_t seed, double *alpha, void *stream);
 
 /* Host-side copies of the scalar device routines, for unit tests on
  * machines without a GPU.  qr_host_uniform follows the stream layout above;

@@ -52,17 +52,21 @@ struct qr_basis {
     std::vector<int32_t> trav;           // [nrep][d] traversal order
     std::vector<int32_t> canon;          // [nrep][d] lexicographic order
     std::vector<int32_t> canon_of_trav;  // traversal index -> canonical index
-    std::vector<uint32_t> ops;           // node program, nrep + kOpPad entries
     std::vector<TaskItem> items;         // projection task items
     std::vector<Task> tasks;             // projection tasks of at most kTaskMax nodes
     // device copies (one device at a time)
     std::mutex mu;
     int dev = -1;
     int32_t *d_canon_of_trav = nullptr;
-    uint32_t *d_ops = nullptr;
     TaskItem *d_items = nullptr;
     Task *d_tasks = nullptr;
-    int64_t ld() const { return nrep + kOpPad; }
+    int64_t ld() const { return nrep + kRowPad; }
+    // Sub-walks (same kind, d' <= d, level' <= level) built on demand for the
+    // batched form and owned by this basis.  In a sub-walk, ft maps its
+    // traversal index to the parent's, inv the parent's to its own (or -1).
+    std::vector<qr_basis *> subs;
+    std::vector<int32_t> ft, inv;
+    int32_t *d_ft = nullptr, *d_inv = nullptr;
 };
 
 namespace {
@@ -73,19 +77,17 @@ struct Builder {
     SetRule R;
     std::vector<int32_t> cur;
     std::vector<int32_t> &trav;
-    std::vector<uint32_t> &ops;
     std::vector<int64_t> &subtree;
     std::vector<TaskItem> &nodes;
     bool overflow = false;
     int32_t max_depth = 0;
 
-    void push(int depth, bool fresh, int l, bool neg, int prod) {
-        if ((int64_t)ops.size() >= kMaxReps) {
+    void push(int depth, int l, int prod) {
+        if ((int64_t)subtree.size() >= kMaxReps) {
             overflow = true;
             return;
         }
         trav.insert(trav.end(), cur.begin(), cur.end());
-        ops.push_back(depth == 0 ? 0u : make_op(depth, fresh, l, neg));
         subtree.push_back(1);
         TaskItem n{};
         n.depth = depth;
@@ -114,7 +116,7 @@ struct Builder {
                     cur[l] = s ? -m : m;
                     const int P2 = rule_child(R, P, m);
                     const int64_t me = (int64_t)subtree.size();
-                    push(T + 1, m == 1, l, s == 1, P2);
+                    push(T + 1, l, P2);
                     if (l + 1 < R.d && rule_ok(R, P2, 1)) visit(T + 1, l, P2);
                     if (!overflow) subtree[me] = (int64_t)subtree.size() - me;
                 }
@@ -172,6 +174,8 @@ extern "C" qr_status qr_build_basis(int32_t d, int32_t kind, int32_t level, qr_b
     if (kind < QR_SET_TENSOR || kind > QR_SET_HC_1P)
         return fail(QR_EINVAL, "qr_build_basis: unknown set kind %d", kind);
     if (level < 0 || level > (1 << 20)) return fail(QR_EINVAL, "qr_build_basis: level=%d out of range", level);
+    if (level < 1 && kind != QR_SET_TENSOR)
+        return fail(QR_EINVAL, "qr_build_basis: a hyperbolic cross of level %d is empty", level);
 
     qr_basis *b = new (std::nothrow) qr_basis();
     if (!b) return fail(QR_ENOMEM, "qr_build_basis: out of host memory");
@@ -181,17 +185,16 @@ extern "C" qr_status qr_build_basis(int32_t d, int32_t kind, int32_t level, qr_b
     std::vector<int64_t> subtree;
     std::vector<TaskItem> nodes;
     try {
-        Builder B{make_rule(kind, level, d), std::vector<int32_t>(d, 0), b->trav, b->ops, subtree, nodes};
-        B.push(0, false, 0, false, 1);  // the zero vector
+        Builder B{make_rule(kind, level, d), std::vector<int32_t>(d, 0), b->trav, subtree, nodes};
+        B.push(0, 0, 1);  // the zero vector
         B.visit(0, -1, 1);
         if (B.overflow) {
             delete b;
             return fail(QR_ERANGE, "qr_build_basis: more than %lld representatives", (long long)kMaxReps);
         }
-        b->nrep = (int64_t)b->ops.size();
+        b->nrep = (int64_t)subtree.size();
         subtree[0] = b->nrep;
         b->max_nnz = B.max_depth;
-        b->ops.resize(b->nrep + kOpPad, 0u);
 
         // canonical (lexicographic) order and the permutation
         std::vector<int64_t> order(b->nrep);
@@ -237,22 +240,70 @@ static void basis_free_device(qr_basis *b) {
         hipSetDevice(b->dev);
         hipDeviceSynchronize();
         hipFree(b->d_canon_of_trav);
-        hipFree(b->d_ops);
         hipFree(b->d_items);
         hipFree(b->d_tasks);
+        hipFree(b->d_ft);
+        hipFree(b->d_inv);
         hipSetDevice(cur);
     }
     b->d_canon_of_trav = nullptr;
-    b->d_ops = nullptr;
     b->d_items = nullptr;
     b->d_tasks = nullptr;
+    b->d_ft = nullptr;
+    b->d_inv = nullptr;
     b->dev = -1;
 }
 
 extern "C" void qr_basis_free(qr_basis *b) {
     if (!b) return;
+    for (qr_basis *sb : b->subs) qr_basis_free(sb);
     basis_free_device(b);
     delete b;
+}
+
+// The sub-walk of `b` for (d2, level2), built once and kept by `b`.  Its
+// traversal is the parent's traversal restricted to the vectors of the
+// smaller set (a depth-first pre-order restricted to a set closed under
+// taking the parent or previous sibling), which is checked here.
+static qr_status sub_basis(qr_basis *b, int32_t d2, int32_t level2, qr_basis **out) {
+    std::lock_guard<std::mutex> lock(b->mu);
+    for (qr_basis *sb : b->subs)
+        if (sb->d == d2 && sb->level == level2) {
+            *out = sb;
+            return QR_OK;
+        }
+    qr_basis *sb = nullptr;
+    qr_status st = qr_build_basis(d2, b->kind, level2, &sb);
+    if (st) return st;
+    try {
+        sb->ft.resize(sb->nrep);
+        sb->inv.assign(b->nrep, -1);
+        const int d = b->d;
+        int64_t j = 0;
+        for (int64_t t = 0; t < sb->nrep; ++t) {
+            const int32_t *v = &sb->trav[t * d2];
+            for (;; ++j) {
+                if (j >= b->nrep) {
+                    qr_basis_free(sb);
+                    return fail(QR_ENUMERIC, "sub-walk (d=%d, level=%d) is not a subsequence of the basis",
+                                d2, level2);
+                }
+                const int32_t *w = &b->trav[j * d];
+                bool eq = std::equal(v, v + d2, w);
+                for (int l = d2; l < d && eq; ++l) eq = w[l] == 0;
+                if (eq) break;
+            }
+            sb->ft[t] = (int32_t)j;
+            sb->inv[j] = (int32_t)t;
+            ++j;
+        }
+        b->subs.push_back(sb);
+    } catch (const std::bad_alloc &) {
+        qr_basis_free(sb);
+        return fail(QR_ENOMEM, "sub-walk: out of host memory");
+    }
+    *out = sb;
+    return QR_OK;
 }
 
 // Upload the basis tables to `dev` (current device) once.
@@ -261,17 +312,22 @@ static qr_status basis_on_device(qr_basis *b, int dev) {
     if (b->dev == dev) return QR_OK;
     if (b->dev >= 0) basis_free_device(b);
     QR_HIP(hipMalloc(&b->d_canon_of_trav, sizeof(int32_t) * b->nrep), "hipMalloc(basis)");
-    QR_HIP(hipMalloc(&b->d_ops, sizeof(uint32_t) * b->ops.size()), "hipMalloc(basis)");
     QR_HIP(hipMalloc(&b->d_items, sizeof(TaskItem) * b->items.size()), "hipMalloc(basis)");
     QR_HIP(hipMalloc(&b->d_tasks, sizeof(Task) * b->tasks.size()), "hipMalloc(basis)");
     QR_HIP(hipMemcpy(b->d_canon_of_trav, b->canon_of_trav.data(), sizeof(int32_t) * b->nrep,
-                     hipMemcpyHostToDevice), "hipMemcpy(basis)");
-    QR_HIP(hipMemcpy(b->d_ops, b->ops.data(), sizeof(uint32_t) * b->ops.size(),
                      hipMemcpyHostToDevice), "hipMemcpy(basis)");
     QR_HIP(hipMemcpy(b->d_items, b->items.data(), sizeof(TaskItem) * b->items.size(),
                      hipMemcpyHostToDevice), "hipMemcpy(basis)");
     QR_HIP(hipMemcpy(b->d_tasks, b->tasks.data(), sizeof(Task) * b->tasks.size(),
                      hipMemcpyHostToDevice), "hipMemcpy(basis)");
+    if (!b->ft.empty()) {
+        QR_HIP(hipMalloc(&b->d_ft, sizeof(int32_t) * b->ft.size()), "hipMalloc(basis)");
+        QR_HIP(hipMalloc(&b->d_inv, sizeof(int32_t) * b->inv.size()), "hipMalloc(basis)");
+        QR_HIP(hipMemcpy(b->d_ft, b->ft.data(), sizeof(int32_t) * b->ft.size(), hipMemcpyHostToDevice),
+               "hipMemcpy(basis)");
+        QR_HIP(hipMemcpy(b->d_inv, b->inv.data(), sizeof(int32_t) * b->inv.size(), hipMemcpyHostToDevice),
+               "hipMemcpy(basis)");
+    }
     b->dev = dev;
     return QR_OK;
 }
@@ -297,7 +353,8 @@ struct qr_ctx {
     DevProblem *d_prob = nullptr;
     DevProblem h_prob{};
     bool prob_valid = false;
-    Buf S, u, alpha_int, partial, row;
+    Buf S, u, alpha_int, partial, row, alpha_b;
+    DevBatch *d_batch = nullptr;
     bool timing = false;
     std::vector<Timed> pending;
     std::vector<hipEvent_t> pool;
@@ -345,9 +402,10 @@ extern "C" void qr_ctx_destroy(qr_ctx *c) {
     if (!c) return;
     hipSetDevice(c->dev);
     hipDeviceSynchronize();
-    for (Buf *b : {&c->S, &c->u, &c->alpha_int, &c->partial, &c->row})
+    for (Buf *b : {&c->S, &c->u, &c->alpha_int, &c->partial, &c->row, &c->alpha_b})
         if (b->p) hipFree(b->p);
     hipFree(c->d_prob);
+    if (c->d_batch) hipFree(c->d_batch);
     for (auto &t : c->pending) {
         hipEventDestroy(t.a);
         hipEventDestroy(t.b);
@@ -536,7 +594,7 @@ static qr_status project_and_reduce(qr_ctx *c, const qr_basis *b, const double *
     const int cap = depth_cap(b->max_nnz);
     double2 *partial = (double2 *)c->partial.p;
     st = timed(c, 1, s, "project_kernel", [&] {
-        return launch_project(cap, make_rule(b->kind, b->level, b->d), u, S, M, pps,
+        return launch_project(cap, make_walk(b->kind, b->level, b->d), u, M, S, M, pps,
                               (int32_t)b->tasks.size(), nsplit, b->d_tasks, b->d_items, partial,
                               b->nrep, s);
     });
@@ -550,8 +608,7 @@ static qr_status project_and_reduce(qr_ctx *c, const qr_basis *b, const double *
 static qr_status run_path(qr_ctx *c, const qr_problem *p, const qr_basis *b, int32_t i, int64_t M,
                           uint64_t seed, const double2 *alpha_int, double *S, double *u, double *x0,
                           hipStream_t s) {
-    PathArgs a{c->d_prob, make_rule(b->kind, b->level, b->d), i, M, seed, alpha_int, b->d_ops,
-               b->nrep, b->ld(), S, u, x0};
+    PathArgs a{c->d_prob, make_walk(b->kind, b->level, b->d), i, M, seed, alpha_int, b->ld(), S, u, x0};
     return timed(c, 0, s, "path_kernel", [&] {
         return launch_path(dim_bucket(p->d, p->nbm), depth_cap(b->max_nnz), p->driver == QR_F_ZRAT,
                            a, s);
@@ -667,8 +724,8 @@ extern "C" qr_status qr_eval(qr_ctx *c, const qr_basis *bc, const double *alpha_
     const int64_t nf = 2 * b->nrep - 1;
     QR_HIP(launch_pad(1, b->nrep, b->ld(), row, s), "pad_kernel");
     QR_HIP(launch_gather(alpha_row, 0, 1, b->nrep, b->ld(), nf, b->d_canon_of_trav, row, s), "gather_kernel");
-    const SetRule R = make_rule(b->kind, b->level, b->d);
-    QR_HIP(launch_eval(depth_cap(b->max_nnz), grad != nullptr, R, row, b->d_ops, b->nrep, x, n, y, grad, s),
+    QR_HIP(launch_eval(depth_cap(b->max_nnz), grad != nullptr, make_walk(b->kind, b->level, b->d), row, x,
+                       n, y, grad, s),
            "eval_kernel");
     return QR_OK;
 }
@@ -680,6 +737,135 @@ extern "C" qr_status qr_sample_points(qr_ctx *c, int32_t d, uint64_t seed, uint3
     if (d < 1 || d > QR_MAX_D) return fail(QR_EINVAL, "qr_sample_points: d=%d", d);
     if (n < 0 || m0 < 0 || !x) return fail(QR_EINVAL, "qr_sample_points: bad n/m0/x");
     QR_HIP(launch_sample(d, seed, stream_id, i, m0, n, x, (hipStream_t)stream), "sample_kernel");
+    return QR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batched form
+// ---------------------------------------------------------------------------
+namespace {
+struct PassPlan {
+    int32_t d = 0, level = 0;
+    int64_t M = 0;
+    qr_basis *walk = nullptr;  // sub-walk of the pass (contains every member's)
+    int64_t off = 0;           // offset of its coefficient rows in the batch buffer (double2)
+    std::vector<int32_t> members;
+};
+}  // namespace
+
+extern "C" qr_status qr_solve_batched(qr_ctx *c, const qr_problem *p, const qr_basis *bc, int32_t R,
+                                      const qr_instance *inst, uint64_t seed, double *alpha,
+                                      void *stream) {
+    qr_basis *b = const_cast<qr_basis *>(bc);
+    qr_status st = begin(c, stream);
+    if (st) return st;
+    if ((st = check_problem(p, b))) return st;
+    if ((st = check_basis_device(b))) return st;
+    if (R < 1 || R > QR_MAX_BATCH) return fail(QR_EINVAL, "qr_solve_batched: R=%d outside [1,%d]", R, QR_MAX_BATCH);
+    if (!inst || !alpha) return fail(QR_EINVAL, "qr_solve_batched: NULL instances or alpha");
+    if (p->driver == QR_F_ZRAT)
+        return fail(QR_ENOTSUP, "qr_solve_batched: the driver depends on z (gradients are not batched)");
+    int64_t Mmax = 0;
+    for (int r = 0; r < R; ++r) {
+        const qr_instance &I = inst[r];
+        if (I.d < 1 || I.d > p->d) return fail(QR_EINVAL, "instance %d: d=%d outside [1,%d]", r, I.d, p->d);
+        const int lmin = b->kind == QR_SET_TENSOR ? 0 : 1;
+        if (I.level < lmin || I.level > b->level)
+            return fail(QR_EINVAL, "instance %d: level=%d outside [%d,%d]", r, I.level, lmin, b->level);
+        if ((st = check_M(I.M))) return st;
+        if (!std::isfinite(I.f_a)) return fail(QR_EINVAL, "instance %d: f_a not finite", r);
+        Mmax = std::max(Mmax, I.M);
+    }
+    hipStream_t s = (hipStream_t)stream;
+
+    // Passes of kBatchRT instances with similar index sets and cloud sizes.
+    std::vector<int32_t> order(R);
+    for (int r = 0; r < R; ++r) order[r] = r;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t q) {
+        if (inst[a].level != inst[q].level) return inst[a].level > inst[q].level;
+        if (inst[a].d != inst[q].d) return inst[a].d > inst[q].d;
+        return inst[a].M > inst[q].M;
+    });
+    const int npass = (R + kBatchRT - 1) / kBatchRT;
+    std::vector<PassPlan> passes(npass);
+    std::vector<qr_basis *> own(R);
+    int64_t total = 0, partial_max = 0;
+    for (int ps = 0; ps < npass; ++ps) {
+        PassPlan &P = passes[ps];
+        for (int k = ps * kBatchRT; k < std::min(R, (ps + 1) * kBatchRT); ++k) {
+            const qr_instance &I = inst[order[k]];
+            P.members.push_back(order[k]);
+            P.d = std::max(P.d, I.d);
+            P.level = std::max(P.level, I.level);
+            P.M = std::max(P.M, I.M);
+        }
+        if ((st = sub_basis(b, P.d, P.level, &P.walk))) return st;
+        P.off = total;
+        total += (int64_t)p->N * P.walk->ld() * kBatchRT;
+        for (int32_t r : P.members) {
+            if ((st = sub_basis(b, inst[r].d, inst[r].level, &own[r]))) return st;
+            int32_t nsplit;
+            int64_t pps;
+            split_plan(own[r], inst[r].M, &nsplit, &pps);
+            partial_max = std::max(partial_max, (int64_t)nsplit * own[r]->nrep);
+        }
+    }
+    if ((st = basis_on_device(b, c->dev))) return st;
+    for (qr_basis *sb : b->subs)
+        if ((st = basis_on_device(sb, c->dev))) return st;
+    if ((st = upload_problem(c, p, s))) return st;
+    if ((st = ensure(c, c->S, sizeof(double) * (size_t)Mmax * kBatchRT, "S"))) return st;
+    if ((st = ensure(c, c->u, sizeof(double) * (size_t)Mmax * p->d, "u"))) return st;
+    if ((st = ensure(c, c->alpha_b, sizeof(double2) * (size_t)total, "batch coefficients"))) return st;
+    if ((st = ensure(c, c->partial, sizeof(double2) * (size_t)partial_max, "partial"))) return st;
+    if (!c->d_batch) QR_HIP(hipMalloc(&c->d_batch, sizeof(DevBatch)), "hipMalloc(batch)");
+
+    // instance parameters in pass-slot order; queued kernels may read the old ones
+    DevBatch hb{};
+    hb.R = R;
+    for (int k = 0; k < R; ++k) hb.f_a[k] = inst[order[k]].f_a;
+    QR_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    QR_HIP(hipMemcpy(c->d_batch, &hb, sizeof hb, hipMemcpyHostToDevice), "hipMemcpy(batch)");
+
+    const int64_t nf = 2 * b->nrep - 1;
+    double2 *ab = (double2 *)c->alpha_b.p;
+    double *S = (double *)c->S.p, *u = (double *)c->u.p;
+    double2 *partial = (double2 *)c->partial.p;
+    QR_HIP(launch_zero(alpha, (int64_t)R * p->N * nf, s), "zero_kernel");
+    QR_HIP(launch_zero((double *)ab, 2 * total, s), "zero_kernel");
+    const int db = dim_bucket(p->d, p->nbm);
+    for (int32_t i = p->N - 1; i >= 0; --i) {
+        for (int ps = 0; ps < npass; ++ps) {
+            const PassPlan &P = passes[ps];
+            const int64_t ld = P.walk->ld();
+            BatchArgs a{c->d_prob, p->d, c->d_batch, ps, make_walk(b->kind, P.level, P.d), i, P.M, seed,
+                        ab + P.off, ld, S, u};
+            st = timed(c, 0, s, "batched_path_kernel",
+                       [&] { return launch_batched_path(db, depth_cap(P.walk->max_nnz), a, s); });
+            if (st) return st;
+            for (size_t k = 0; k < P.members.size(); ++k) {
+                const int32_t r = P.members[k];
+                const qr_basis *ob = own[r];
+                const int64_t Mr = inst[r].M;
+                int32_t nsplit;
+                int64_t pps;
+                split_plan(ob, Mr, &nsplit, &pps);
+                st = timed(c, 1, s, "project_kernel", [&] {
+                    return launch_project(depth_cap(ob->max_nnz), make_walk(b->kind, ob->level, ob->d), u, P.M,
+                                          S + (int64_t)k * P.M, Mr, pps, (int32_t)ob->tasks.size(), nsplit,
+                                          ob->d_tasks, ob->d_items, partial, ob->nrep, s);
+                });
+                if (st) return st;
+                st = timed(c, 2, s, "reduce_batched_kernel", [&] {
+                    return launch_reduce_batched(partial, nsplit, ob->nrep, (double)Mr, ob->d_ft,
+                                                 b->d_canon_of_trav, P.walk->d_inv,
+                                                 ab + P.off + (int64_t)i * ld * kBatchRT, (int32_t)k,
+                                                 alpha + ((int64_t)r * p->N + i) * nf, s);
+                });
+                if (st) return st;
+            }
+        }
+    }
     return QR_OK;
 }
 

@@ -187,34 +187,19 @@ __host__ __device__ inline int32_t rule_child(const SetRule &R, int32_t P, int32
 
 constexpr int kMaxDepthCap = 8;
 
-// Node program.  The representatives are visited depth-first (coordinates
-// ascending, sign + before -, magnitudes ascending); every node k != 0 is its
-// predecessor times one factor e^{+-2 pi i u_l}, where the predecessor is
-// either its parent (k with the last non-zero coordinate l removed, when
-// |k_l| = 1: a new chain) or its previous sibling (|k_l| - 1: a
-// continuation).  One 32-bit op per node r >= 1:
-//   bits 0-3  depth t = number of non-zero coordinates (1..8); 0 = padding
-//   bit  4    new chain: mult_t = e^{+-2 pi i u_l}, v_t = v_{t-1} mult_t
-//             otherwise:                            v_t = v_t mult_t
-//   bits 5-8  coordinate l of a new chain
-//   bit  9    the new chain's coordinate is negative (mult_t conjugated)
-constexpr uint32_t kOpNew = 1u << 4;
-constexpr uint32_t kOpNeg = 1u << 9;
-constexpr int kOpPad = 16;  // ops and coefficient rows are padded by this many nodes
-
-__host__ __device__ inline uint32_t make_op(int depth, bool fresh, int l, bool neg) {
-    return (uint32_t)depth | (fresh ? kOpNew : 0u) | ((uint32_t)l << 5) | (neg ? kOpNeg : 0u);
-}
-
-// A range [r0, r1) of the node program together with the k-vector of its
-// first node, from which the register state after node r0 is rebuilt.
-struct RangeStart {
-    int32_t r0, r1;
-    int32_t depth;   // number of non-zero coordinates of node r0
-    int32_t pad;
-    int32_t coord[kMaxDepthCap];
-    int32_t val[kMaxDepthCap];
+// Branch-light form of the same rule used by the kernels' walk: a node with
+// budget Pb extends by magnitude m while w = Pb (m + b) <= L; its child's
+// budget is w when c = 1 (hyperbolic crosses) or stays Pb = 1 (c = 0,
+// tensor set); a child has children iff its budget <= Lc.
+struct Walk {
+    int32_t b, L, Lc, c, d;
 };
+
+__host__ __device__ inline Walk make_walk(int32_t kind, int32_t level, int32_t d) {
+    if (kind == QR_SET_TENSOR) return Walk{0, level, level, 0, d};
+    if (kind == QR_SET_HC_MAX) return Walk{0, level, level, 1, d};
+    return Walk{1, level, level / 2, 1, d};
+}
 
 // Root of a run of the depth-first traversal used by the projection: the
 // node k (by its non-zero coordinates) and whether its whole subtree follows.

@@ -6,19 +6,44 @@
 namespace qrmc {
 
 constexpr int kPathBlock = 128;   // threads per block of the path / eval kernels
+constexpr int kPathP = 2;         // paths per thread of the value-only path kernel
 constexpr int kProjWaves = 4;     // waves per block of the projection kernel
+constexpr int kProjP = 2;         // paths per lane of the projection kernel (1 where LDS is short)
 constexpr int kProjChunk = 8;     // nodes per cross-lane reduction of the projection
 constexpr int kTaskMax = 256;     // nodes per projection task
+constexpr int kRowPad = 16;       // coefficient rows are padded by this many pairs
+
+constexpr int kBatchRT = 8;       // instances per pass of the batched path kernel
+
+// Per-instance parameters of a batch (device memory, one per context).
+struct DevBatch {
+    int32_t R;
+    int32_t pad;
+    double f_a[QR_MAX_BATCH + kBatchRT];
+};
+
+struct BatchArgs {
+    const DevProblem *P;
+    int32_t d;  // problem dimension (paths are simulated in all d coordinates)
+    const DevBatch *B;
+    int32_t pass;
+    Walk W;
+    int32_t i;
+    int64_t M;
+    uint64_t seed;
+    const double2 *alpha_b;  // [N][ld][kBatchRT] of this pass
+    int64_t ld;
+    double *S, *u;  // S: [kBatchRT][M] of this pass; u: [d][M]
+};
 
 struct PathArgs {
     const DevProblem *P;
-    SetRule R;
+    Walk W;
     int32_t i;
     int64_t M;
     uint64_t seed;
     const double2 *alpha_int;  // [N][ld]
-    const uint32_t *ops;       // [nrep + kOpPad]
-    int64_t nrep, ld;
+    int64_t ld;
     double *S, *u, *x0;
 };
 
@@ -27,19 +52,27 @@ hipError_t launch_gather(const double *alpha, int32_t row0, int32_t nrows, int64
                          hipStream_t s);
 hipError_t launch_pad(int32_t nrows, int64_t nrep, int64_t ld, double2 *alpha_int, hipStream_t s);
 hipError_t launch_path(int db, int cap, bool grad, const PathArgs &a, hipStream_t s);
-hipError_t launch_project(int cap, const SetRule &R, const double *u, const double *S, int64_t M,
+hipError_t launch_project(int cap, const Walk &W, const double *u, int64_t ldu, const double *S, int64_t M,
                           int64_t paths_per_split, int32_t ntasks, int32_t nsplit, const Task *tasks,
                           const TaskItem *items, double2 *partial, int64_t nrep, hipStream_t s);
 hipError_t launch_reduce(const double2 *partial, int32_t nsplit, int64_t nrep, double M,
                          double2 *alpha_int_row, double *alpha_row,
                          const int32_t *canon_of_trav, hipStream_t s);
-hipError_t launch_eval(int cap, bool grad, const SetRule &R, const double2 *alpha_int_row,
-                       const uint32_t *ops, int64_t nrep, const double *x, int64_t n, double *y,
-                       double *grad_out, hipStream_t s);
+hipError_t launch_eval(int cap, bool grad, const Walk &W, const double2 *alpha_int_row,
+                       const double *x, int64_t n, double *y, double *grad_out, hipStream_t s);
 hipError_t launch_x_to_u(int32_t d, const double *x, int64_t n, double *u, hipStream_t s);
 hipError_t launch_sample(int32_t d, uint64_t seed, uint32_t stream_id, int32_t i, int64_t m0,
                          int64_t n, double *x, hipStream_t s);
 
-size_t project_lds_bytes(int32_t d);
+hipError_t launch_batched_path(int db, int cap, const BatchArgs &a, hipStream_t s);
+hipError_t launch_reduce_batched(const double2 *partial, int32_t nsplit, int64_t nrep_sub, double M,
+                                 const int32_t *ft, const int32_t *canon_of_trav,
+                                 const int32_t *pass_pos, double2 *alpha_b_row, int32_t slot,
+                                 double *alpha_row, hipStream_t s);
+hipError_t launch_zero(double *p, int64_t n, hipStream_t s);
+
+size_t project_lds_bytes(int32_t d, int P);
+size_t path_lds_bytes(int32_t d, bool grad, int P);
+int path_points(bool grad);
 
 }  // namespace qrmc

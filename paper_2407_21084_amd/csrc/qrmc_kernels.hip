@@ -2,35 +2,56 @@
 //
 // One backward iteration i of Algorithm 1 (GQRMDP, eqs (yqi:bar:M),
 // (Aqi:bar:M), (Sqi:bar:M)) runs as
-//   path_kernel     one thread per path: start draw X_i ~ nu, Euler steps
+//   path_kernel     P paths per thread: start draw X_i ~ nu, Euler steps
 //                   (eq (markov:euler)), expansion ybar_{j+1}(X_{j+1}) by the
 //                   basis traversal below, driver sum S_i;
-//   project_kernel  (task of basis functions) x (slice of paths): the same
-//                   traversal at X_i, S-weighted, reduced over lanes through
+//   project_kernel  (task of the traversal) x (slice of paths): the same
+//                   traversal at X_i, S-weighted, summed over lanes through
 //                   LDS, partial sums per slice;
 //   reduce_kernel   fixed-order sum over slices, scaling by 1/M.
 //
-// Basis traversal.  Every representative k != 0 is reached from a node with
-// one coordinate fewer or one unit smaller in its last non-zero coordinate,
-// so e^{2 pi i k.u} costs one complex multiplication by e^{+-2 pi i u_l}:
-// nodes are visited depth-first, coordinates l ascending, sign + before -,
-// magnitudes m ascending.  All lanes of a wave walk the same sequence of
-// nodes, so the loop bounds and the coefficient stream are wave-uniform: the
-// coefficients come through scalar loads, the per-lane values e^{2 pi i u_l}
-// sit in LDS (one 16-byte slot per lane and coordinate), and the chain of
-// values lives in registers.
+// Basis traversal.  Every representative k != 0 is its parent (k with the
+// last non-zero coordinate l removed) or its previous sibling (|k_l| - 1)
+// times one factor e^{+-2 pi i u_l}, so e^{2 pi i k.u} costs one complex
+// multiplication: nodes are visited depth-first, coordinates l ascending,
+// sign + before -, magnitudes ascending.  All lanes of a wave walk the same
+// nodes, so loop bounds and the coefficient stream are wave-uniform (scalar
+// registers and scalar loads), the per-lane factors e^{2 pi i u_l} sit in LDS
+// and the chain of values lives in registers.  A thread carries P points
+// through the walk, so the scalar control of each node is paid once for P
+// points' worth of FP64 work.
 #include "qrmc_kernels.h"
 
 namespace qrmc {
 
 #define QR_CONST __attribute__((address_space(4)))
 
-struct cplx {
-    double re, im;
+// values at the P points of a thread
+template <int P>
+struct Pts {
+    double re[P], im[P];
 };
 
-__device__ __forceinline__ cplx cmul(const cplx a, const cplx b) {
-    return cplx{fma(a.re, b.re, -(a.im * b.im)), fma(a.re, b.im, a.im * b.re)};
+template <int P>
+__device__ __forceinline__ Pts<P> cmul(const Pts<P> &a, const Pts<P> &b) {
+    Pts<P> r;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        r.re[q] = fma(a.re[q], b.re[q], -(a.im[q] * b.im[q]));
+        r.im[q] = fma(a.re[q], b.im[q], a.im[q] * b.re[q]);
+    }
+    return r;
+}
+
+template <int P>
+__device__ __forceinline__ Pts<P> unit() {
+    Pts<P> r;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        r.re[q] = 1.0;
+        r.im[q] = 0.0;
+    }
+    return r;
 }
 
 __device__ __forceinline__ void wave_sync() {
@@ -39,24 +60,35 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Per-lane LDS slots: e^{2 pi i u_l} at E[l * stride], gradient accumulators
-// (d ybar / d u_l up to 2 pi) at G[l * stride].
-struct LaneLds {
+// Per-lane LDS slots of a thread's P points: e^{2 pi i u_l} of point q at
+// E[(l P + q) stride], gradient accumulators (d ybar / d u_l up to 2 pi) at
+// G[(l P + q) stride].
+template <int P>
+struct LanePts {
     double2 *E;
     double *G;
     int stride;
-    __device__ __forceinline__ cplx e(int l) const {
-        const double2 v = E[l * stride];
-        return cplx{v.x, v.y};
+    __device__ __forceinline__ Pts<P> e(int l) const {
+        Pts<P> r;
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            const double2 v = E[(l * P + q) * stride];
+            r.re[q] = v.x;
+            r.im[q] = v.y;
+        }
+        return r;
     }
-    __device__ __forceinline__ void grad_add(int l, double g) const { G[l * stride] += g; }
+    __device__ __forceinline__ void set_e(int l, int q, double2 v) const { E[(l * P + q) * stride] = v; }
+    __device__ __forceinline__ double &g(int l, int q) const { return G[(l * P + q) * stride]; }
 };
 
-// Per-coordinate transcendental work of the path kernel.  Called O(d) times
-// per Euler step against O(|Gamma|) basis work, so they stay out of line:
-// their FP64 coefficients (which gfx9-class VOP3 cannot take as literals) are
-// then materialised per call instead of being hoisted into registers that
-// would stay live across the basis traversal.
+// ---------------------------------------------------------------------------
+// Per-coordinate transcendental work.  Called O(d) times per Euler step
+// against O(|Gamma|) basis work, so they stay out of line: their FP64
+// coefficients (which this ISA cannot take as literals in three-operand
+// instructions) are then materialised per call instead of being hoisted into
+// registers that would stay live across the basis traversal.
+// ---------------------------------------------------------------------------
 __device__ __noinline__ double nl_norm_icdf(double u) { return norm_icdf(u); }
 __device__ __noinline__ double nl_logistic_icdf(double u) { return logistic_icdf(u); }
 __device__ __noinline__ double nl_logistic_cdf(double x) { return logistic_cdf(x); }
@@ -66,14 +98,14 @@ __device__ __noinline__ double2 nl_unit_phase(double x) {
     sincospi(2.0 * logistic_cdf(x), &sn, &cs);
     return make_double2(cs, sn);
 }
-__device__ __noinline__ double2 nl_sincos_exp(double th, double a) {
-    // (sin th, exp(a)), th reduced through sincospi
+__device__ __noinline__ double2 nl_unit_phase_u(double u) {
+    // e^{2 pi i u}
     double sn, cs;
-    sincospi(th * M_1_PI, &sn, &cs);
-    (void)cs;
-    return make_double2(sn, exp(a));
+    sincospi(2.0 * u, &sn, &cs);
+    return make_double2(cs, sn);
 }
 __device__ __noinline__ double2 nl_sincos(double th) {
+    // (sin th, cos th); sincospi avoids the large-argument reduction
     double sn, cs;
     sincospi(th * M_1_PI, &sn, &cs);
     return make_double2(sn, cs);
@@ -81,236 +113,151 @@ __device__ __noinline__ double2 nl_sincos(double th) {
 __device__ __noinline__ double nl_exp(double a) { return exp(a); }
 __device__ __noinline__ double nl_sin(double a) { return sin(a); }
 
-// Children of a node at depth T (T non-zero coordinates, last one p, budget
-// product P) with value `parent`, in traversal order.  Each level keeps its
-// own accumulators (returned to the caller), which keeps the values that
-// cross loop levels few.  With gradients, `g` of the returned accumulator is
-// the sum over all visited subtrees of the sink's per-node values, from which
-// the caller applies the chain rule for its own coordinate.
-template <int T, int CAP, class Sink>
-__device__ __forceinline__ typename Sink::Acc visit(const cplx parent, const int p, const int P,
-                                                    const SetRule &R, const LaneLds &L,
-                                                    Sink &sink) {
+// ---------------------------------------------------------------------------
+// The walk.  A node with budget Pb (product of the weights of its non-zero
+// coordinates) extends along coordinate l with magnitudes m = 1, 2, ... as
+// long as w = Pb (m + b) <= L; the child's budget is w (hyperbolic crosses)
+// or stays 1 (tensor set, c = 0); the child has children iff its budget is
+// at most Lc.  See make_walk in qrmc_common.h.
+// ---------------------------------------------------------------------------
+template <int T, int CAP, int P, class Sink>
+__device__ __forceinline__ typename Sink::Acc visit(const Pts<P> &parent, const int p, const int Pb,
+                                                    const Walk &W, const LanePts<P> &L, Sink &sink) {
     typename Sink::Acc acc{};
 #pragma unroll 1
-    for (int l = p + 1; l < R.d; ++l) {
-        const cplx e = L.e(l);
-        double gl = 0.0;
+    for (int l = p + 1; l < W.d; ++l) {
+        const bool more = l + 1 < W.d;
+        [[maybe_unused]] double gl[P];
+        if constexpr (Sink::kGrad) {
+#pragma unroll
+            for (int q = 0; q < P; ++q) gl[q] = 0.0;
+        }
 #pragma unroll 1
         for (int s = 0; s < (T == 0 ? 1 : 2); ++s) {
-            const cplx es{e.re, s ? -e.im : e.im};
-            cplx v = parent;
+            // chain factor e^{+-2 pi i u_l}, re-read per sign to keep one
+            // complex value per point live instead of two
+            Pts<P> es = L.e(l);
+            if (s) {
+#pragma unroll
+                for (int q = 0; q < P; ++q) es.im[q] = -es.im[q];
+            }
+            Pts<P> v = parent;
+            [[maybe_unused]] double km = s ? -1.0 : 1.0;
 #pragma unroll 1
-            for (int m = 1; rule_ok(R, P, m); ++m) {
+            for (int w = Pb * (1 + W.b); w <= W.L; w += Pb) {
                 v = cmul(v, es);
-                double gsub = sink.node(v, acc);
-                if constexpr (T + 1 < CAP) {
-                    const int P2 = rule_child(R, P, m);
-                    if (l + 1 < R.d && rule_ok(R, P2, 1)) {
-                        const typename Sink::Acc c = visit<T + 1, CAP>(v, l, P2, R, L, sink);
-                        Sink::add(acc, c);
-                        if constexpr (Sink::kGrad) gsub += c.g;
+                if constexpr (Sink::kGrad) {
+                    double gs[P];
+                    sink.node_g(v, acc, gs);
+                    if constexpr (T + 1 < CAP) {
+                        const int child = W.c ? w : Pb;
+                        if (more && child <= W.Lc) {
+                            const typename Sink::Acc c = visit<T + 1, CAP, P>(v, l, child, W, L, sink);
+                            Sink::add(acc, c);
+#pragma unroll
+                            for (int q = 0; q < P; ++q) gs[q] += c.g[q];
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < P; ++q) gl[q] = fma(km, gs[q], gl[q]);
+                    km += s ? -1.0 : 1.0;
+                } else {
+                    sink.node(v, acc);
+                    if constexpr (T + 1 < CAP) {
+                        const int child = W.c ? w : Pb;
+                        if (more && child <= W.Lc) Sink::add(acc, visit<T + 1, CAP, P>(v, l, child, W, L, sink));
                     }
                 }
-                if constexpr (Sink::kGrad) gl = fma(s ? -(double)m : (double)m, gsub, gl);
             }
         }
-        if constexpr (Sink::kGrad) L.grad_add(l, gl);
+        if constexpr (Sink::kGrad) {
+#pragma unroll
+            for (int q = 0; q < P; ++q) L.g(l, q) += gl[q];
+        }
     }
     return acc;
 }
 
-// Start the traversal below a node of runtime depth `depth` (< CAP).
-template <int T, int CAP, class Sink>
-__device__ __forceinline__ void visit_from(int depth, const cplx v, int p, int P, const SetRule &R,
-                                           const LaneLds &L, Sink &sink) {
+// Start the walk below a node of runtime depth `depth` (< CAP).
+template <int T, int CAP, int P, class Sink>
+__device__ __forceinline__ void visit_from(int depth, const Pts<P> &v, int p, int Pb, const Walk &W,
+                                           const LanePts<P> &L, Sink &sink) {
     if constexpr (T < CAP) {
         if (depth == T) {
-            (void)visit<T, CAP>(v, p, P, R, L, sink);
+            (void)visit<T, CAP, P>(v, p, Pb, W, L, sink);
             return;
         }
-        visit_from<T + 1, CAP>(depth, v, p, P, R, L, sink);
+        visit_from<T + 1, CAP, P>(depth, v, p, Pb, W, L, sink);
     }
 }
 
 // ---------------------------------------------------------------------------
-// Expansion evaluation sink: y = sum_r a_r.x Re(e_r) + a_r.y Im(e_r) with the
-// internal coefficients a_r = (sqrt2 alpha_cos, sqrt2 alpha_sin), a_0 = (alpha_0, 0);
-// with gradients, g_r = a_r.y Re(e_r) - a_r.x Im(e_r) (d/du of the node up to 2 pi k).
+// Expansion evaluation: y = sum_r a_r.x Re(e_r) + a_r.y Im(e_r) with the
+// internal coefficients a_r = (sqrt2 alpha_cos, sqrt2 alpha_sin), a_0 =
+// (alpha_0, 0); with gradients, g_r = a_r.y Re(e_r) - a_r.x Im(e_r) (d/du of
+// the node up to 2 pi k).  The coefficient pair of the next node is requested
+// as soon as the current one is consumed, so the scalar load overlaps the
+// next node's complex multiply.
 // ---------------------------------------------------------------------------
-template <bool GRAD>
-struct EvalAccT {
-    double y;
+template <int P, bool GRAD>
+struct EvalAcc {
+    double y[P];
 };
-template <>
-struct EvalAccT<true> {
-    double y, g;
+template <int P>
+struct EvalAcc<P, true> {
+    double y[P], g[P];
 };
 
-typedef __attribute__((address_space(3))) double lds_double;
-
-// Coefficient row staged through LDS: a ring of 4 chunks of kPathBlock nodes
-// shared by the block.  While chunk k is traversed, chunks k and k+1 are in
-// the ring and chunk k+3 is on its way into registers; at the boundary into
-// chunk k (one barrier) the block stores chunk k+2 into the slot of chunk
-// k-2 and requests chunk k+3.  All threads of the block walk the same node
-// sequence, so the barriers are uniform.  Coefficients of the next node are
-// read one node ahead.
-template <bool GRAD>
+template <int P, bool GRAD>
 struct EvalSink {
     static constexpr bool kGrad = GRAD;
-    using Acc = EvalAccT<GRAD>;
-    const double2 *g;   // row in global memory
-    int64_t n;          // readable entries of the row
-    lds_double *ring;   // LDS [4 * kPathBlock][2]
-    double2 pend;       // this thread's node of the chunk in flight
-    int tid;
-    int idx;            // node about to be visited
-    double2 nxt;        // its coefficients
+    using Acc = EvalAcc<P, GRAD>;
+    const QR_CONST double *a;  // pair of the node about to be visited
+    double nx, ny;             // its coefficients (already requested)
 
-    __device__ __forceinline__ double2 fetch(int64_t r) const {
-        return r < n ? g[r] : make_double2(0.0, 0.0);
+    __device__ __forceinline__ void advance() {
+        __builtin_amdgcn_sched_barrier(0);
+        a += 2;
+        nx = a[0];
+        ny = a[1];
     }
-    __device__ __forceinline__ void start() {
+    __device__ __forceinline__ void node(const Pts<P> &v, Acc &acc) {
+        const double cx = nx, cy = ny;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) put(c * kPathBlock + tid, fetch((int64_t)c * kPathBlock + tid));
-        pend = fetch(3 * (int64_t)kPathBlock + tid);
-        __syncthreads();
-        idx = 0;
-        nxt = get(0);
+        for (int q = 0; q < P; ++q) acc.y[q] = fma(cx, v.re[q], fma(cy, v.im[q], acc.y[q]));
+        advance();
     }
-    __device__ __forceinline__ void put(int slot, const double2 v) {
-        ring[2 * slot] = v.x;
-        ring[2 * slot + 1] = v.y;
-    }
-    __device__ __forceinline__ double2 get(int slot) const {
-        return make_double2(ring[2 * slot], ring[2 * slot + 1]);
-    }
-    __device__ __forceinline__ void boundary(int k) {  // entering chunk k >= 1
-        __syncthreads();
-        put(((k + 2) & 3) * kPathBlock + tid, pend);
-        pend = fetch((int64_t)(k + 3) * kPathBlock + tid);
-    }
-    __device__ __forceinline__ double node(const cplx v, Acc &acc) {
-        const double cx = nxt.x, cy = nxt.y;
-        acc.y = fma(cx, v.re, fma(cy, v.im, acc.y));
-        ++idx;
-        if ((idx & (kPathBlock - 1)) == 0) boundary(idx / kPathBlock);
-        nxt = get(idx & (4 * kPathBlock - 1));
-        if constexpr (GRAD) {
-            const double gr = fma(cy, v.re, -(cx * v.im));
-            acc.g += gr;
-            return gr;
+    __device__ __forceinline__ void node_g(const Pts<P> &v, Acc &acc, double *gs) {
+        const double cx = nx, cy = ny;
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            acc.y[q] = fma(cx, v.re[q], fma(cy, v.im[q], acc.y[q]));
+            gs[q] = fma(cy, v.re[q], -(cx * v.im[q]));
+            if constexpr (GRAD) acc.g[q] += gs[q];
         }
-        return 0.0;
+        advance();
     }
-    __device__ __forceinline__ static void add(Acc &a, const Acc &b) {
-        a.y += b.y;
-        if constexpr (GRAD) a.g += b.g;
+    __device__ __forceinline__ static void add(Acc &x, const Acc &y) {
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            x.y[q] += y.y[q];
+            if constexpr (GRAD) x.g[q] += y.g[q];
+        }
     }
 };
 
-// Expansion at the lane's point by the depth-first traversal.  Every thread of
-// the block must call it (the coefficient staging uses block barriers).
-template <int CAP, bool GRAD>
-__device__ __forceinline__ double tree_eval(const double2 *alpha_row, int64_t nrow, double2 *ring,
-                                            const SetRule &R, const LaneLds &L) {
-    EvalSink<GRAD> s{alpha_row, nrow, (lds_double *)ring, make_double2(0.0, 0.0),
-                     (int)threadIdx.x, 0, make_double2(0.0, 0.0)};
-    s.start();
-    typename EvalSink<GRAD>::Acc root{};
-    const cplx one{1.0, 0.0};
-    s.node(one, root);
-    const auto acc = visit<0, CAP>(one, -1, 1, R, L, s);
-    // the ring is reused by the next call: let every wave finish reading it
-    __syncthreads();
-    return root.y + acc.y;
-}
-
-// ---------------------------------------------------------------------------
-// Flat node program (value-only paths): the registers v[t] hold the current
-// node value at each depth t and mult[t] the factor of the chain at depth t;
-// a uniform switch on the op's depth keeps every register index static.
-// ---------------------------------------------------------------------------
-template <int CAP>
-struct Flat {
-    cplx v[CAP + 1];
-    cplx mult[CAP + 1];
-};
-
-template <int T, int CAP>
-__device__ __forceinline__ void flat_step(Flat<CAP> &st, const uint32_t op, const LaneLds &L) {
-    if constexpr (T == 0) {
-        (void)op;
-    } else if (op & kOpNew) {
-        cplx e = L.e((int)((op >> 5) & 15u));
-        if (op & kOpNeg) e.im = -e.im;
-        st.mult[T] = e;
-        st.v[T] = cmul(st.v[T - 1], e);
-    } else {
-        st.v[T] = cmul(st.v[T], st.mult[T]);
-    }
-}
-
-// Apply `op` and hand the node value to `use`.
-template <int CAP, class F>
-__device__ __forceinline__ void flat_node(Flat<CAP> &st, const uint32_t op, const LaneLds &L, F &&use) {
-#define QR_FLAT_CASE(T)                       \
-    case T:                                   \
-        if constexpr (T <= CAP) {             \
-            flat_step<T, CAP>(st, op, L);     \
-            use(st.v[T]);                     \
-        }                                     \
-        break;
-    switch (op & 15u) {
-        QR_FLAT_CASE(0)
-        QR_FLAT_CASE(1)
-        QR_FLAT_CASE(2)
-        QR_FLAT_CASE(3)
-        QR_FLAT_CASE(4)
-        QR_FLAT_CASE(5)
-        QR_FLAT_CASE(6)
-        QR_FLAT_CASE(7)
-        QR_FLAT_CASE(8)
-    default: break;
-    }
-#undef QR_FLAT_CASE
-}
-
-// ybar at the lane's point: nodes 0..nrep-1 in groups of 8 whose ops and
-// coefficients arrive through batched scalar loads (rows padded by kOpPad).
-template <int CAP>
-__device__ __forceinline__ double flat_eval(const double2 *alpha_row, const uint32_t *ops,
-                                            const int64_t nrep, const LaneLds &L) {
+// ybar at the thread's P points (row padded by at least one pair).
+template <int CAP, int P, bool GRAD>
+__device__ __forceinline__ void tree_eval(const double2 *alpha_row, const Walk &W, const LanePts<P> &L,
+                                          double *y) {
     const QR_CONST double *a = (const QR_CONST double *)alpha_row;
-    const QR_CONST uint32_t *o = (const QR_CONST uint32_t *)ops;
-    Flat<CAP> st;
-    st.v[0] = cplx{1.0, 0.0};
+    EvalSink<P, GRAD> s{a, a[0], a[1]};
+    typename EvalSink<P, GRAD>::Acc root{};
+    const Pts<P> one = unit<P>();
+    s.node(one, root);
+    const auto acc = visit<0, CAP, P>(one, -1, 1, W, L, s);
 #pragma unroll
-    for (int t = 1; t <= CAP; ++t) {
-        st.v[t] = cplx{0.0, 0.0};
-        st.mult[t] = cplx{1.0, 0.0};
-    }
-    double yre = 0.0, yim = 0.0;
-#pragma unroll 1
-    for (int64_t r = 0; r < nrep; r += 8) {
-        uint32_t op[8];
-        double ax[8], ay[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            op[q] = o[r + q];
-            ax[q] = a[2 * (r + q)];
-            ay[q] = a[2 * (r + q) + 1];
-        }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            flat_node<CAP>(st, op[q], L, [&](const cplx v) {
-                yre = fma(ax[q], v.re, yre);
-                yim = fma(ay[q], v.im, yim);
-            });
-        }
-    }
-    return yre + yim;
+    for (int q = 0; q < P; ++q) y[q] = root.y[q] + acc.y[q];
 }
 
 // ---------------------------------------------------------------------------
@@ -336,7 +283,7 @@ __device__ __forceinline__ double h_source(const DevProblem *P, double t, const 
             bw = fma(fma(P->b1[l], x[l], P->b0[l]), P->sol_w[l], bw);
         }
     }
-    const double2 sc = nl_sincos(th);  // sincospi avoids the large-argument reduction
+    const double2 sc = nl_sincos(th);
     const double sn = sc.x, cs = sc.y;
     const double u = E * cs;
     const double gscale = -E * sn;  // grad u = gscale * w
@@ -365,133 +312,169 @@ __device__ __forceinline__ double clamp_abs(double y, double L) {
 }
 
 // ---------------------------------------------------------------------------
-// path_kernel: one thread per path of backward iteration i.
-// alpha_int rows have stride ld = nrep + kOpPad double2.
+// path_kernel: P paths per thread of backward iteration i.  Thread t of
+// block b carries paths m_q = b kPathBlock P + q kPathBlock + t.
+// alpha_int rows have stride ld >= nrep + 1 double2.
+// LDS per thread: E slots [d][P] double2, gradient slots [d][P] double
+// (GRAD), path-state slots [P][d] double.
 // ---------------------------------------------------------------------------
-template <int DB, int CAP, bool GRAD>
-__global__ __launch_bounds__(kPathBlock) void path_kernel(
-    const DevProblem *__restrict__ P0, const SetRule R, const int32_t i, const int64_t M,
-    const uint64_t seed, const double2 *__restrict__ alpha_int, const uint32_t *__restrict__ ops,
-    const int64_t nrep, const int64_t ld, double *__restrict__ S_out, double *__restrict__ u_out,
-    double *__restrict__ x_out) {
+size_t path_lds_bytes(int32_t d, bool grad, int P) {
+    return (size_t)d * kPathBlock * P * (sizeof(double2) + sizeof(double) + (grad ? sizeof(double) : 0));
+}
+
+// Three waves per SIMD: the register budget (168 VGPRs) costs a few spills
+// of values that live across the whole traversal, and the extra wave hides
+// more of the scalar coefficient loads than the spills cost.
+#ifndef QRMC_PATH_WAVES_PER_EU
+#define QRMC_PATH_WAVES_PER_EU 3
+#endif
+template <int DB, int CAP, bool GRAD, int P>
+__global__ __launch_bounds__(kPathBlock)
+__attribute__((amdgpu_waves_per_eu(QRMC_PATH_WAVES_PER_EU)))
+void path_kernel(
+    const DevProblem *__restrict__ P0, const Walk W, const int32_t i, const int64_t M,
+    const uint64_t seed, const double2 *__restrict__ alpha_int, const int64_t ld,
+    double *__restrict__ S_out, double *__restrict__ u_out, double *__restrict__ x_out) {
     extern __shared__ double2 lds[];
     const int tid = threadIdx.x;
-    // lanes past M simulate a path too (block barriers), but store nothing
-    const int64_t m = (int64_t)blockIdx.x * kPathBlock + tid;
-    const bool live = m < M;
     const int d = P0->d, nbm = P0->nbm, N = P0->N;
-    double2 *ring = lds;
-    double2 *lane_base = lds + 4 * kPathBlock;
-    const LaneLds L{lane_base + tid,
-                    GRAD ? reinterpret_cast<double *>(lane_base + d * kPathBlock) + tid : nullptr,
-                    kPathBlock};
-    // the path state waits in LDS while the traversal runs
-    double *xs = reinterpret_cast<double *>(lane_base + d * kPathBlock) + (GRAD ? d * kPathBlock : 0) + tid;
+    const LanePts<P> L{lds + tid,
+                       GRAD ? reinterpret_cast<double *>(lds + d * P * kPathBlock) + tid : nullptr,
+                       kPathBlock};
+    // path state parked in LDS while the traversal runs
+    double *xs = reinterpret_cast<double *>(lds + d * P * kPathBlock) + (GRAD ? d * P * kPathBlock : 0) + tid;
 
-    PhiloxStream rs(seed, 0u, (uint64_t)m, (uint32_t)i, 0u);
-    double x[DB];
+    const int64_t base = (int64_t)blockIdx.x * kPathBlock * P + tid;
+    double S[P];
+    // start points X_i^i = F^{-1}(U), U from stream 0 draws r = 0..d-1
 #pragma unroll
-    for (int l = 0; l < DB; ++l) {
-        x[l] = 0.0;
-        if (l < d) {
-            x[l] = nl_logistic_icdf(rs.next());
-            if (live && u_out) u_out[l * M + m] = nl_logistic_cdf(x[l]);
-            if (live && x_out) x_out[l * M + m] = x[l];
+    for (int q = 0; q < P; ++q) {
+        const int64_t m = base + (int64_t)q * kPathBlock;
+        PhiloxStream rs(seed, 0u, (uint64_t)m, (uint32_t)i, 0u);
+        for (int l = 0; l < d; ++l) {
+            const double x = nl_logistic_icdf(rs.next());
+            xs[(q * d + l) * kPathBlock] = x;
+            if (m < M) {
+                if (u_out) u_out[l * M + m] = nl_logistic_cdf(x);
+                if (x_out) x_out[l * M + m] = x;
+            }
         }
+        S[q] = 0.0;
     }
 
-    double S = 0.0;
     for (int j = i; j < N; ++j) {
         // Re-read the problem each step instead of pinning every parameter in
         // scalar registers across the basis traversal.
-        const DevProblem *__restrict__ P = P0;
-        asm volatile("" : "+s"(P));
-        const double tj = P->t[j];
-        const double dt = P->t[j + 1] - tj;
-        // the source term only needs X_j: take it before X_j is overwritten
-        const double hj = h_source<DB>(P, tj, x, d);
-        {
-            // Euler step, eq (markov:euler); one normal at a time keeps the
-            // quantile evaluations sequential (few live registers)
-            const double sq = sqrt(dt);
+        const DevProblem *__restrict__ Pj = P0;
+        asm volatile("" : "+s"(Pj));
+        const double tj = Pj->t[j];
+        const double dt = Pj->t[j + 1] - tj;
+        const double sq = sqrt(dt);
+        double hj[P];
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            const int64_t m = base + (int64_t)q * kPathBlock;
+            double x[DB];
+#pragma unroll
+            for (int l = 0; l < DB; ++l) x[l] = (l < d) ? xs[(q * d + l) * kPathBlock] : 0.0;
+            // the source term only needs X_j
+            hj[q] = h_source<DB>(Pj, tj, x, d);
+            // Euler step, eq (markov:euler): normals r = d + (j-i) nbm + k
+            PhiloxStream rs(seed, 0u, (uint64_t)m, (uint32_t)i, (uint32_t)(d + (j - i) * nbm));
 #pragma unroll
             for (int l = 0; l < DB; ++l)
-                if (l < d) x[l] = fma(fma(P->b1[l], x[l], P->b0[l]), dt, x[l]);
+                if (l < d) x[l] = fma(fma(Pj->b1[l], x[l], Pj->b0[l]), dt, x[l]);
 #pragma unroll 1
             for (int k = 0; k < nbm; ++k) {
                 const double dwk = sq * nl_norm_icdf(rs.next());
 #pragma unroll
                 for (int l = 0; l < DB; ++l)
-                    if (l < d) x[l] = fma(P->sigma[l * nbm + k], dwk, x[l]);
+                    if (l < d) x[l] = fma(Pj->sigma[l * nbm + k], dwk, x[l]);
             }
-        }
-        // x now holds X_{j+1}
-        double y, gx[DB];
-        if (j + 1 < N) {
-#pragma unroll
-            for (int l = 0; l < DB; ++l) {
-                if (l < d) {
-                    L.E[l * kPathBlock] = nl_unit_phase(x[l]);
-                    if constexpr (GRAD) L.G[l * kPathBlock] = 0.0;
-                }
-            }
-            const double2 *row = alpha_int + (int64_t)(j + 1) * ld;
 #pragma unroll
             for (int l = 0; l < DB; ++l)
-                if (l < d) xs[l * kPathBlock] = x[l];
-            asm volatile("" ::: "memory");
-            if constexpr (GRAD) {
-                y = tree_eval<CAP, true>(row, ld, ring, R, L);
+                if (l < d) xs[(q * d + l) * kPathBlock] = x[l];
+        }
+        // xs now holds X_{j+1}
+        double y[P];
+        double z2[P];
+        if (j + 1 < N) {
+            for (int l = 0; l < d; ++l) {
 #pragma unroll
-                for (int l = 0; l < DB; ++l) {
-                    if (l < d) {
-                        const double u = nl_logistic_cdf(x[l]);
-                        gx[l] = 2.0 * M_PI * L.G[l * kPathBlock] * (u * (1.0 - u));
+                for (int q = 0; q < P; ++q) {
+                    L.set_e(l, q, nl_unit_phase(xs[(q * d + l) * kPathBlock]));
+                    if constexpr (GRAD) L.g(l, q) = 0.0;
+                }
+            }
+            tree_eval<CAP, P, GRAD>(alpha_int + (int64_t)(j + 1) * ld, W, L, y);
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                z2[q] = 0.0;
+                if constexpr (GRAD) {
+                    double gx[DB];
+#pragma unroll
+                    for (int l = 0; l < DB; ++l) {
+                        gx[l] = 0.0;
+                        if (l < d) {
+                            const double u = nl_logistic_cdf(xs[(q * d + l) * kPathBlock]);
+                            gx[l] = 2.0 * M_PI * L.g(l, q) * (u * (1.0 - u));
+                        }
+                    }
+                    for (int k = 0; k < nbm; ++k) {
+                        double zk = 0.0;
+#pragma unroll
+                        for (int l = 0; l < DB; ++l)
+                            if (l < d) zk = fma(Pj->sigma[l * nbm + k], gx[l], zk);
+                        z2[q] = fma(zk, zk, z2[q]);
                     }
                 }
-            } else {
-#ifdef QRMC_FLAT_EVAL
-                y = flat_eval<CAP>(row, ops, nrep, L);
-#else
-                (void)ops;
-                y = tree_eval<CAP, false>(row, ld, ring, R, L);
-#endif
             }
-            asm volatile("" ::: "memory");
-#pragma unroll
-            for (int l = 0; l < DB; ++l)
-                if (l < d) x[l] = xs[l * kPathBlock];
         } else {
-            y = g_term<DB>(P, x, d, GRAD ? gx : nullptr);
-        }
-        y = clamp_abs(y, P->clamp);
-        double z2 = 0.0;
-        if constexpr (GRAD) {
 #pragma unroll
-            for (int k = 0; k < DB; ++k) {
-                if (k < nbm) {
-                    double zk = 0.0;
+            for (int q = 0; q < P; ++q) {
+                double x[DB], gx[DB];
 #pragma unroll
-                    for (int l = 0; l < DB; ++l)
-                        if (l < d) zk = fma(P->sigma[l * nbm + k], gx[l], zk);
-                    z2 = fma(zk, zk, z2);
+                for (int l = 0; l < DB; ++l) x[l] = (l < d) ? xs[(q * d + l) * kPathBlock] : 0.0;
+                y[q] = g_term<DB>(Pj, x, d, GRAD ? gx : nullptr);
+                z2[q] = 0.0;
+                if constexpr (GRAD) {
+                    for (int k = 0; k < nbm; ++k) {
+                        double zk = 0.0;
+#pragma unroll
+                        for (int l = 0; l < DB; ++l)
+                            if (l < d) zk = fma(Pj->sigma[l * nbm + k], gx[l], zk);
+                        z2[q] = fma(zk, zk, z2[q]);
+                    }
                 }
             }
         }
-        const double f = fnl(P, y, z2) + hj;
-        S = fma(f, dt, S);
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            const double yq = clamp_abs(y[q], Pj->clamp);
+            const double f = fnl(Pj, yq, z2[q]) + hj[q];
+            S[q] = fma(f, dt, S[q]);
+        }
     }
-    S += g_term<DB>(P0, x, d, nullptr);
-    if (live) S_out[m] = S;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const int64_t m = base + (int64_t)q * kPathBlock;
+        double x[DB];
+#pragma unroll
+        for (int l = 0; l < DB; ++l) x[l] = (l < d) ? xs[(q * d + l) * kPathBlock] : 0.0;
+        const double Sq = S[q] + g_term<DB>(P0, x, d, nullptr);
+        if (m < M) S_out[m] = Sq;
+    }
 }
 
 // ---------------------------------------------------------------------------
-// project_kernel: block (task of the traversal, slice of paths).
-// Each wave runs 64 paths at a time through the task's nodes; node values
-// times S go to a per-wave LDS buffer and are summed over the lanes every
-// kProjChunk nodes into per-wave accumulators; the block finally adds its
-// waves in a fixed order and writes the slice's partial sums.
+// project_kernel: block (task of the traversal, slice of paths).  Each wave
+// runs 64 P paths at a time through the task's nodes (P per lane); per node,
+// a lane writes the S-weighted sum of its points' values to a per-wave LDS
+// buffer, which is summed over the lanes every kProjChunk nodes into
+// per-wave accumulators; the block finally adds its waves in a fixed order
+// and writes the slice's partial sums.
 // ---------------------------------------------------------------------------
+template <int P>
 struct ProjSink {
     static constexpr bool kGrad = false;
     struct Acc {};
@@ -499,15 +482,20 @@ struct ProjSink {
     double2 *row;    // this lane's row of the wave buffer: row[c]
     double2 *wbuf;   // wave buffer [64][kProjChunk + 1]
     double *acc;     // wave accumulators, doubles [kTaskMax][2]
-    double s;        // this lane's response (0 for lanes past the slice)
+    double s[P];     // the lane's responses (0 for paths past the slice)
     int c;           // nodes in the current chunk (wave-uniform)
     int base;        // task-local index of the chunk's first node (wave-uniform)
     int lane;
 
-    __device__ __forceinline__ double node(const cplx v, Acc &) {
-        row[c] = make_double2(s * v.re, s * v.im);
+    __device__ __forceinline__ void node(const Pts<P> &v, Acc &) {
+        double re = 0.0, im = 0.0;
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            re = fma(s[q], v.re[q], re);
+            im = fma(s[q], v.im[q], im);
+        }
+        row[c] = make_double2(re, im);
         if (++c == kProjChunk) flush();
-        return 0.0;
     }
 
     // Sum the chunk over the 64 lanes: lane q adds the 16 lanes of quarter
@@ -531,27 +519,27 @@ struct ProjSink {
     }
 };
 
-size_t project_lds_bytes(int32_t d) {
+size_t project_lds_bytes(int32_t d, int P) {
     return (size_t)kProjWaves *
            ((size_t)64 * (kProjChunk + 1) * sizeof(double2) + (size_t)kTaskMax * sizeof(double2) +
-            (size_t)d * 64 * sizeof(double2));
+            (size_t)d * 64 * P * sizeof(double2));
 }
 
-template <int CAP>
+template <int CAP, int P>
 __global__ __launch_bounds__(kProjWaves * 64) void project_kernel(
-    const SetRule R, const double *__restrict__ u_in, const double *__restrict__ s_in,
+    const Walk W, const double *__restrict__ u_in, const int64_t ldu, const double *__restrict__ s_in,
     const int64_t M, const int64_t paths_per_split, const Task *__restrict__ tasks,
     const TaskItem *__restrict__ items, double2 *__restrict__ partial, const int64_t nrep) {
     extern __shared__ double2 lds[];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int d = R.d;
+    const int d = W.d;
     double2 *bufs = lds;
     double *accs = reinterpret_cast<double *>(lds + kProjWaves * 64 * (kProjChunk + 1));
     double2 *Es = lds + kProjWaves * 64 * (kProjChunk + 1) + kProjWaves * kTaskMax;
 
     double2 *wbuf = bufs + wave * 64 * (kProjChunk + 1);
     double *acc = accs + wave * kTaskMax * 2;
-    const LaneLds L{Es + wave * d * 64 + lane, nullptr, 64};
+    const LanePts<P> L{Es + wave * d * P * 64 + lane, nullptr, 64};
 
     const Task task = tasks[blockIdx.x];
     const int64_t m0 = (int64_t)blockIdx.y * paths_per_split;
@@ -560,34 +548,37 @@ __global__ __launch_bounds__(kProjWaves * 64) void project_kernel(
     for (int r = lane; r < kTaskMax * 2; r += 64) acc[r] = 0.0;
     wave_sync();
 
-    ProjSink sink{wbuf + lane * (kProjChunk + 1), wbuf, acc, 0.0, 0, 0, lane};
-    for (int64_t gb = m0 + wave * 64; gb < m1; gb += kProjWaves * 64) {
-        const int64_t m = gb + lane;
-        const bool live = m < m1;
-        sink.s = live ? s_in[m] : 0.0;
-        for (int l = 0; l < d; ++l) {
-            const double u = live ? u_in[l * M + m] : 0.25;
-            double sn, cs;
-            sincospi(2.0 * u, &sn, &cs);
-            L.E[l * 64] = make_double2(cs, sn);
+    ProjSink<P> sink;
+    sink.row = wbuf + lane * (kProjChunk + 1);
+    sink.wbuf = wbuf;
+    sink.acc = acc;
+    sink.lane = lane;
+    for (int64_t gb = m0 + wave * 64 * P; gb < m1; gb += kProjWaves * 64 * P) {
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            const int64_t m = gb + q * 64 + lane;
+            const bool live = m < m1;
+            sink.s[q] = live ? s_in[m] : 0.0;
+            for (int l = 0; l < d; ++l) L.set_e(l, q, nl_unit_phase_u(live ? u_in[l * ldu + m] : 0.25));
         }
         sink.c = 0;
         sink.base = 0;
         for (int it = task.item_begin; it < task.item_end; ++it) {
             const TaskItem &I = items[it];
-            cplx v{1.0, 0.0};
+            Pts<P> v = unit<P>();
             for (int t = 0; t < I.depth; ++t) {
-                cplx e = L.e(I.coord[t]);
+                Pts<P> e = L.e(I.coord[t]);
                 int n = I.val[t];
                 if (n < 0) {
-                    e.im = -e.im;
+#pragma unroll
+                    for (int q = 0; q < P; ++q) e.im[q] = -e.im[q];
                     n = -n;
                 }
-                for (int q = 0; q < n; ++q) v = cmul(v, e);
+                for (int r = 0; r < n; ++r) v = cmul(v, e);
             }
-            ProjSink::Acc none;
+            typename ProjSink<P>::Acc none;
             sink.node(v, none);
-            if (I.full) visit_from<0, CAP>(I.depth, v, I.last, I.prod, R, L, sink);
+            if (I.full) visit_from<0, CAP, P>(I.depth, v, I.last, I.prod, W, L, sink);
         }
         if (sink.c) sink.flush();
     }
@@ -658,50 +649,30 @@ __global__ void pad_kernel(int32_t nrows, int64_t nrep, int64_t ld, double2 *__r
 // eval_kernel: ybar (and its x-gradient) at given points, one thread each
 // ---------------------------------------------------------------------------
 template <int CAP, bool GRAD>
-__global__ __launch_bounds__(kPathBlock) void eval_kernel(const SetRule R,
+__global__ __launch_bounds__(kPathBlock) void eval_kernel(const Walk W,
                                                           const double2 *__restrict__ alpha_int_row,
-                                                          const uint32_t *__restrict__ ops,
-                                                          const int64_t nrep,
                                                           const double *__restrict__ x,
                                                           const int64_t n, double *__restrict__ y,
                                                           double *__restrict__ grad) {
     extern __shared__ double2 lds[];
     const int tid = threadIdx.x;
-    // lanes past n evaluate a dummy point (block barriers) and store nothing
-    const int64_t p0 = (int64_t)blockIdx.x * kPathBlock + tid;
-    const bool live = p0 < n;
-    const int64_t p = live ? p0 : n - 1;
-    const int d = R.d;
-    double2 *ring = lds;
-    double2 *lane_base = lds + 4 * kPathBlock;
-    const LaneLds L{lane_base + tid,
-                    GRAD ? reinterpret_cast<double *>(lane_base + d * kPathBlock) + tid : nullptr,
-                    kPathBlock};
+    const int64_t p = (int64_t)blockIdx.x * kPathBlock + tid;
+    if (p >= n) return;
+    const int d = W.d;
+    const LanePts<1> L{lds + tid, GRAD ? reinterpret_cast<double *>(lds + d * kPathBlock) + tid : nullptr,
+                       kPathBlock};
     for (int l = 0; l < d; ++l) {
-        const double u = logistic_cdf(x[l * n + p]);
-        double sn, cs;
-        sincospi(2.0 * u, &sn, &cs);
-        L.E[l * kPathBlock] = make_double2(cs, sn);
-        if constexpr (GRAD) L.G[l * kPathBlock] = 0.0;
+        L.set_e(l, 0, nl_unit_phase(x[l * n + p]));
+        if constexpr (GRAD) L.g(l, 0) = 0.0;
     }
-    const int64_t ld = nrep + kOpPad;
+    double yv;
+    tree_eval<CAP, 1, GRAD>(alpha_int_row, W, L, &yv);
+    y[p] = yv;
     if constexpr (GRAD) {
-        const double yv = tree_eval<CAP, true>(alpha_int_row, ld, ring, R, L);
-        if (live) {
-            y[p] = yv;
-            for (int l = 0; l < d; ++l) {
-                const double u = logistic_cdf(x[l * n + p]);
-                grad[l * n + p] = 2.0 * M_PI * L.G[l * kPathBlock] * (u * (1.0 - u));
-            }
+        for (int l = 0; l < d; ++l) {
+            const double u = logistic_cdf(x[l * n + p]);
+            grad[l * n + p] = 2.0 * M_PI * L.g(l, 0) * (u * (1.0 - u));
         }
-    } else {
-#ifdef QRMC_FLAT_EVAL
-        const double yv = flat_eval<CAP>(alpha_int_row, ops, nrep, L);
-#else
-        (void)ops;
-        const double yv = tree_eval<CAP, false>(alpha_int_row, ld, ring, R, L);
-#endif
-        if (live) y[p] = yv;
     }
 }
 
@@ -720,9 +691,213 @@ __global__ void sample_kernel(int32_t d, uint64_t seed, uint32_t stream_id, int3
 }
 
 // ---------------------------------------------------------------------------
+// Batched form: instances sharing the cloud.  One walk per path serves RT
+// instances: each node's value is contracted with RT coefficient pairs (one
+// scalar load of 16 RT bytes), so the complex multiply and the walk's scalar
+// control are shared by the RT instances.  Instance coefficients of a pass
+// are interleaved per node: row[node][RT] double2.
+// ---------------------------------------------------------------------------
+template <int RT>
+struct BatchSink {
+    static constexpr bool kGrad = false;
+    struct Acc {};             // sums live in the sink: a value-only walk needs no per-level partials
+    const QR_CONST double *a;  // pairs of the node about to be visited
+    double nx[RT], ny[RT];
+    double y[RT];
+
+    __device__ __forceinline__ void load() {
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+            nx[r] = a[2 * r];
+            ny[r] = a[2 * r + 1];
+        }
+    }
+    __device__ __forceinline__ void node(const Pts<1> &v, Acc &) {
+#pragma unroll
+        for (int r = 0; r < RT; ++r) y[r] = fma(nx[r], v.re[0], fma(ny[r], v.im[0], y[r]));
+        __builtin_amdgcn_sched_barrier(0);
+        a += 2 * RT;
+        load();
+    }
+    __device__ __forceinline__ static void add(Acc &, const Acc &) {}
+};
+
+__device__ __forceinline__ double fnl_a(int kind, double a, double y) {
+    switch (kind) {
+    case QR_F_SIN: return a * nl_sin(y);
+    case QR_F_ALLEN_CAHN: return y - y * y * y;
+    default: return 0.0;
+    }
+}
+
+// One path per thread; RT instances per launch (pass).  The part of the
+// source term h that does not involve the driver is shared; the driver
+// parameter f_a is the instance's.
+template <int DB, int CAP, int RT>
+__global__ __launch_bounds__(kPathBlock) void batched_path_kernel(
+    const DevProblem *__restrict__ P0, const DevBatch *__restrict__ B, const int32_t pass,
+    const Walk W, const int32_t i, const int64_t M, const uint64_t seed,
+    const double2 *__restrict__ alpha_b, const int64_t ld, double *__restrict__ S_out,
+    double *__restrict__ u_out) {
+    extern __shared__ double2 lds[];
+    const int tid = threadIdx.x;
+    const int64_t m = (int64_t)blockIdx.x * kPathBlock + tid;
+    if (m >= M) return;  // no block-level synchronisation below: LDS slots are per lane
+    const int d = P0->d, nbm = P0->nbm, N = P0->N;
+    const LanePts<1> L{lds + tid, nullptr, kPathBlock};
+    double *xs = reinterpret_cast<double *>(lds + d * kPathBlock) + tid;
+
+    {
+        PhiloxStream rs(seed, 0u, (uint64_t)m, (uint32_t)i, 0u);
+        for (int l = 0; l < d; ++l) {
+            const double x = nl_logistic_icdf(rs.next());
+            xs[l * kPathBlock] = x;
+            if (u_out) u_out[l * M + m] = nl_logistic_cdf(x);
+        }
+    }
+    double S[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) S[r] = 0.0;
+
+    for (int j = i; j < N; ++j) {
+        const DevProblem *__restrict__ Pj = P0;
+        asm volatile("" : "+s"(Pj));
+        const double tj = Pj->t[j];
+        const double dt = Pj->t[j + 1] - tj;
+        double x[DB];
+#pragma unroll
+        for (int l = 0; l < DB; ++l) x[l] = (l < d) ? xs[l * kPathBlock] : 0.0;
+        // source term at X_j without its driver part: -(d_t u + L u)
+        double hbase, uval;
+        {
+            const double E = Pj->sol_A * nl_exp(-Pj->sol_c * (Pj->T - tj));
+            double th = Pj->sol_p, bw = 0.0;
+#pragma unroll
+            for (int l = 0; l < DB; ++l) {
+                if (l < d) {
+                    th = fma(Pj->sol_w[l], x[l], th);
+                    bw = fma(fma(Pj->b1[l], x[l], Pj->b0[l]), Pj->sol_w[l], bw);
+                }
+            }
+            const double2 sc = nl_sincos(th);
+            uval = E * sc.y;
+            const double gscale = -E * sc.x;
+            hbase = -(Pj->sol_c * uval + gscale * bw - 0.5 * uval * Pj->sw2);
+        }
+        {
+            const double sq = sqrt(dt);
+            PhiloxStream rs(seed, 0u, (uint64_t)m, (uint32_t)i, (uint32_t)(d + (j - i) * nbm));
+#pragma unroll
+            for (int l = 0; l < DB; ++l)
+                if (l < d) x[l] = fma(fma(Pj->b1[l], x[l], Pj->b0[l]), dt, x[l]);
+#pragma unroll 1
+            for (int k = 0; k < nbm; ++k) {
+                const double dwk = sq * nl_norm_icdf(rs.next());
+#pragma unroll
+                for (int l = 0; l < DB; ++l)
+                    if (l < d) x[l] = fma(Pj->sigma[l * nbm + k], dwk, x[l]);
+            }
+#pragma unroll
+            for (int l = 0; l < DB; ++l)
+                if (l < d) xs[l * kPathBlock] = x[l];
+        }
+        double y[RT];
+        if (j + 1 < N) {
+            for (int l = 0; l < W.d; ++l) L.set_e(l, 0, nl_unit_phase(xs[l * kPathBlock]));
+            BatchSink<RT> sink;
+            sink.a = (const QR_CONST double *)(alpha_b + (int64_t)(j + 1) * ld * RT);
+#pragma unroll
+            for (int r = 0; r < RT; ++r) sink.y[r] = 0.0;
+            sink.load();
+            typename BatchSink<RT>::Acc none{};
+            const Pts<1> one = unit<1>();
+            sink.node(one, none);
+            (void)visit<0, CAP, 1>(one, -1, 1, W, L, sink);
+#pragma unroll
+            for (int r = 0; r < RT; ++r) y[r] = sink.y[r];
+        } else {
+#pragma unroll
+            for (int l = 0; l < DB; ++l) x[l] = (l < d) ? xs[l * kPathBlock] : 0.0;
+            const double g = g_term<DB>(Pj, x, d, nullptr);
+#pragma unroll
+            for (int r = 0; r < RT; ++r) y[r] = g;
+        }
+        const int kind = Pj->driver;
+        const double cl = Pj->clamp;
+        const DevBatch *__restrict__ Bj = B;
+        asm volatile("" : "+s"(Bj));
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+            const double ar = Bj->f_a[pass * RT + r];
+            const double f = fnl_a(kind, ar, clamp_abs(y[r], cl)) + (hbase - fnl_a(kind, ar, uval));
+            S[r] = fma(f, dt, S[r]);
+        }
+    }
+    double x[DB];
+#pragma unroll
+    for (int l = 0; l < DB; ++l) x[l] = (l < d) ? xs[l * kPathBlock] : 0.0;
+    const double g = g_term<DB>(P0, x, d, nullptr);
+    const int R = B->R;
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+        if (pass * RT + r < R) S_out[(int64_t)r * M + m] = S[r] + g;
+}
+
+// Row i of one instance from its slice partial sums.  The instance's own
+// index set is a sub-walk of the basis: node t of it is node ft[t] of the
+// basis traversal, which sits at pass_pos[ft[t]] in the coefficient layout of
+// the instance's pass (a walk containing the instance's).  Coefficients the
+// instance does not have stay as zero-filled.
+__global__ void reduce_batched_kernel(const double2 *__restrict__ partial, int32_t nsplit,
+                                      int64_t nrep_sub, double M, const int32_t *__restrict__ ft,
+                                      const int32_t *__restrict__ canon_of_trav,
+                                      const int32_t *__restrict__ pass_pos,
+                                      double2 *__restrict__ alpha_b_row, int32_t slot,
+                                      double *__restrict__ alpha_row) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nrep_sub) return;
+    double sx = 0.0, sy = 0.0;
+    for (int s = 0; s < nsplit; ++s) {
+        const double2 p = partial[(int64_t)s * nrep_sub + t];
+        sx += p.x;
+        sy += p.y;
+    }
+    const int64_t r = ft[t];
+    double2 *dst = alpha_b_row + (int64_t)pass_pos[r] * kBatchRT + slot;
+    if (r == 0) {
+        const double a0 = sx / M;
+        *dst = make_double2(a0, 0.0);
+        alpha_row[0] = a0;
+    } else {
+        const double mc = sx / M, ms = sy / M;
+        *dst = make_double2(2.0 * mc, 2.0 * ms);
+        const int64_t c = canon_of_trav[r];
+        alpha_row[2 * c - 1] = M_SQRT2 * mc;
+        alpha_row[2 * c] = M_SQRT2 * ms;
+    }
+}
+
+__global__ void zero_kernel(double *__restrict__ p, int64_t n) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < n) p[idx] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+static inline unsigned blocks_for(int64_t n, int64_t b) { return (unsigned)((n + b - 1) / b); }
+
+constexpr size_t kLdsDefault = 64 * 1024;   // dynamic LDS a launch gets without opting in
+constexpr size_t kLdsMax = 160 * 1024;      // LDS of one CU (gfx950)
+
+// Opt a kernel in to `bytes` of dynamic LDS (once per kernel and size).
+static hipError_t allow_lds(const void *kernel, size_t bytes, size_t &granted) {
+    if (bytes <= granted) return hipSuccess;
+    if (bytes > kLdsMax) return hipErrorInvalidValue;
+    const hipError_t e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess) granted = bytes;
+    return e;
+}
 
 hipError_t launch_gather(const double *alpha, int32_t row0, int32_t nrows, int64_t nrep, int64_t ld,
                          int64_t nfuncs, const int32_t *canon_of_trav, double2 *alpha_int,
@@ -742,13 +917,18 @@ hipError_t launch_pad(int32_t nrows, int64_t nrep, int64_t ld, double2 *alpha_in
     return hipGetLastError();
 }
 
+int path_points(bool grad) { return grad ? 1 : kPathP; }
+
 template <int DB, int CAP, bool GRAD>
 static hipError_t path_t(const PathArgs &a, hipStream_t s) {
-    const size_t lds = 4 * kPathBlock * sizeof(double2) +
-                       (size_t)a.R.d * kPathBlock * (sizeof(double2) + sizeof(double) + (GRAD ? sizeof(double) : 0));
-    hipLaunchKernelGGL((path_kernel<DB, CAP, GRAD>), dim3(blocks_for(a.M, kPathBlock)),
-                       dim3(kPathBlock), lds, s, a.P, a.R, a.i, a.M, a.seed, a.alpha_int, a.ops,
-                       a.nrep, a.ld, a.S, a.u, a.x0);
+    constexpr int P = GRAD ? 1 : kPathP;
+    const size_t lds = path_lds_bytes(a.W.d, GRAD, P);
+    static size_t granted = kLdsDefault;
+    const hipError_t e = allow_lds((const void *)path_kernel<DB, CAP, GRAD, P>, lds, granted);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((path_kernel<DB, CAP, GRAD, P>), dim3(blocks_for(a.M, (int64_t)kPathBlock * P)),
+                       dim3(kPathBlock), lds, s, a.P, a.W, a.i, a.M, a.seed, a.alpha_int, a.ld, a.S,
+                       a.u, a.x0);
     return hipGetLastError();
 }
 
@@ -772,32 +952,37 @@ hipError_t launch_path(int db, int cap, bool grad, const PathArgs &a, hipStream_
     return hipErrorInvalidValue;
 }
 
-template <int CAP>
-static hipError_t project_t(const SetRule &R, const double *u, const double *S, int64_t M, int64_t pps,
+template <int CAP, int P>
+static hipError_t project_t(const Walk &W, const double *u, int64_t ldu, const double *S, int64_t M, int64_t pps,
                             int32_t ntasks, int32_t nsplit, const Task *tasks,
                             const TaskItem *items, double2 *partial, int64_t nrep, hipStream_t s) {
-    const size_t lds = project_lds_bytes(R.d);
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)project_kernel<CAP>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)project_lds_bytes(kMaxD));
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
-    hipLaunchKernelGGL(project_kernel<CAP>, dim3((unsigned)ntasks, (unsigned)nsplit),
-                       dim3(kProjWaves * 64), lds, s, R, u, S, M, pps, tasks, items, partial, nrep);
+    const size_t lds = project_lds_bytes(W.d, P);
+    static size_t granted = kLdsDefault;
+    const hipError_t e = allow_lds((const void *)project_kernel<CAP, P>, lds, granted);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((project_kernel<CAP, P>), dim3((unsigned)ntasks, (unsigned)nsplit),
+                       dim3(kProjWaves * 64), lds, s, W, u, ldu, S, M, pps, tasks, items, partial, nrep);
     return hipGetLastError();
 }
 
-hipError_t launch_project(int cap, const SetRule &R, const double *u, const double *S, int64_t M,
+template <int CAP>
+static hipError_t project_p(const Walk &W, const double *u, int64_t ldu, const double *S, int64_t M, int64_t pps,
+                            int32_t ntasks, int32_t nsplit, const Task *tasks,
+                            const TaskItem *items, double2 *partial, int64_t nrep, hipStream_t s) {
+    // two paths per lane while their phase factors fit in LDS
+    if (project_lds_bytes(W.d, kProjP) <= kLdsMax)
+        return project_t<CAP, kProjP>(W, u, ldu, S, M, pps, ntasks, nsplit, tasks, items, partial, nrep, s);
+    return project_t<CAP, 1>(W, u, ldu, S, M, pps, ntasks, nsplit, tasks, items, partial, nrep, s);
+}
+
+hipError_t launch_project(int cap, const Walk &W, const double *u, int64_t ldu, const double *S, int64_t M,
                           int64_t paths_per_split, int32_t ntasks, int32_t nsplit, const Task *tasks,
                           const TaskItem *items, double2 *partial, int64_t nrep, hipStream_t s) {
     switch (cap) {
-    case 2: return project_t<2>(R, u, S, M, paths_per_split, ntasks, nsplit, tasks, items, partial, nrep, s);
-    case 4: return project_t<4>(R, u, S, M, paths_per_split, ntasks, nsplit, tasks, items, partial, nrep, s);
-    case 6: return project_t<6>(R, u, S, M, paths_per_split, ntasks, nsplit, tasks, items, partial, nrep, s);
-    case 8: return project_t<8>(R, u, S, M, paths_per_split, ntasks, nsplit, tasks, items, partial, nrep, s);
+    case 2: return project_p<2>(W, u, ldu, S, M, paths_per_split, ntasks, nsplit, tasks, items, partial, nrep, s);
+    case 4: return project_p<4>(W, u, ldu, S, M, paths_per_split, ntasks, nsplit, tasks, items, partial, nrep, s);
+    case 6: return project_p<6>(W, u, ldu, S, M, paths_per_split, ntasks, nsplit, tasks, items, partial, nrep, s);
+    case 8: return project_p<8>(W, u, ldu, S, M, paths_per_split, ntasks, nsplit, tasks, items, partial, nrep, s);
     }
     return hipErrorInvalidValue;
 }
@@ -811,23 +996,21 @@ hipError_t launch_reduce(const double2 *partial, int32_t nsplit, int64_t nrep, d
 }
 
 template <int CAP, bool GRAD>
-static hipError_t eval_t(const SetRule &R, const double2 *a, const uint32_t *ops, int64_t nrep,
-                         const double *x, int64_t n, double *y, double *g, hipStream_t s) {
-    const size_t lds = 4 * kPathBlock * sizeof(double2) +
-                       (size_t)R.d * kPathBlock * (sizeof(double2) + (GRAD ? sizeof(double) : 0));
+static hipError_t eval_t(const Walk &W, const double2 *a, const double *x, int64_t n, double *y,
+                         double *g, hipStream_t s) {
+    const size_t lds = (size_t)W.d * kPathBlock * (sizeof(double2) + (GRAD ? sizeof(double) : 0));
     hipLaunchKernelGGL((eval_kernel<CAP, GRAD>), dim3(blocks_for(n, kPathBlock)), dim3(kPathBlock),
-                       lds, s, R, a, ops, nrep, x, n, y, g);
+                       lds, s, W, a, x, n, y, g);
     return hipGetLastError();
 }
 
-hipError_t launch_eval(int cap, bool grad, const SetRule &R, const double2 *alpha_int_row,
-                       const uint32_t *ops, int64_t nrep, const double *x, int64_t n, double *y,
-                       double *grad_out, hipStream_t s) {
+hipError_t launch_eval(int cap, bool grad, const Walk &W, const double2 *alpha_int_row,
+                       const double *x, int64_t n, double *y, double *grad_out, hipStream_t s) {
     if (n == 0) return hipSuccess;
-#define QR_EVAL_CAP(C)                                                                   \
-    case C:                                                                              \
-        return grad ? eval_t<C, true>(R, alpha_int_row, ops, nrep, x, n, y, grad_out, s) \
-                    : eval_t<C, false>(R, alpha_int_row, ops, nrep, x, n, y, grad_out, s);
+#define QR_EVAL_CAP(C)                                                              \
+    case C:                                                                         \
+        return grad ? eval_t<C, true>(W, alpha_int_row, x, n, y, grad_out, s)       \
+                    : eval_t<C, false>(W, alpha_int_row, x, n, y, grad_out, s);
     switch (cap) {
         QR_EVAL_CAP(2)
         QR_EVAL_CAP(4)
@@ -850,6 +1033,54 @@ hipError_t launch_sample(int32_t d, uint64_t seed, uint32_t stream_id, int32_t i
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(sample_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, d, seed, stream_id,
                        i, m0, n, x);
+    return hipGetLastError();
+}
+
+
+template <int DB, int CAP>
+static hipError_t batched_t(const BatchArgs &a, hipStream_t s) {
+    const size_t lds = (size_t)a.d * kPathBlock * (sizeof(double2) + sizeof(double));
+    static size_t granted = kLdsDefault;
+    const hipError_t e = allow_lds((const void *)batched_path_kernel<DB, CAP, kBatchRT>, lds, granted);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((batched_path_kernel<DB, CAP, kBatchRT>), dim3(blocks_for(a.M, kPathBlock)),
+                       dim3(kPathBlock), lds, s, a.P, a.B, a.pass, a.W, a.i, a.M, a.seed, a.alpha_b,
+                       a.ld, a.S, a.u);
+    return hipGetLastError();
+}
+
+template <int DB>
+static hipError_t batched_cap(int cap, const BatchArgs &a, hipStream_t s) {
+    switch (cap) {
+    case 2: return batched_t<DB, 2>(a, s);
+    case 4: return batched_t<DB, 4>(a, s);
+    case 6: if constexpr (DB >= 6) return batched_t<DB, 6>(a, s); break;
+    case 8: if constexpr (DB >= 8) return batched_t<DB, 8>(a, s); break;
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_batched_path(int db, int cap, const BatchArgs &a, hipStream_t s) {
+    switch (db) {
+    case 4: return batched_cap<4>(cap, a, s);
+    case 8: return batched_cap<8>(cap, a, s);
+    case 16: return batched_cap<16>(cap, a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_reduce_batched(const double2 *partial, int32_t nsplit, int64_t nrep_sub, double M,
+                                 const int32_t *ft, const int32_t *canon_of_trav,
+                                 const int32_t *pass_pos, double2 *alpha_b_row, int32_t slot,
+                                 double *alpha_row, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_batched_kernel, dim3(blocks_for(nrep_sub, 256)), dim3(256), 0, s, partial,
+                       nsplit, nrep_sub, M, ft, canon_of_trav, pass_pos, alpha_b_row, slot, alpha_row);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(double *p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 

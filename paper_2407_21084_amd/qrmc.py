@@ -19,6 +19,7 @@ LIB_PATH = os.environ.get("QRMC_LIB") or os.path.join(_HERE, "libqrmc.so")
 
 MAX_D = 16
 MAX_N = 128
+MAX_BATCH = 64
 
 SET_TENSOR, SET_HC_MAX, SET_HC_1P = 0, 1, 2
 SET_KINDS = {"tensor": SET_TENSOR, "hc_max": SET_HC_MAX, "hc_1p": SET_HC_1P}
@@ -34,8 +35,8 @@ K_PATH, K_PROJECT, K_REDUCE, K_GATHER = 0, 1, 2, 3
 EXPORTS = ["qr_last_error", "qr_version", "qr_build_basis", "qr_basis_info", "qr_basis_indices",
            "qr_basis_free", "qr_ctx_create", "qr_ctx_destroy", "qr_ctx_set_timing",
            "qr_ctx_kernel_time", "qr_ctx_reset_timing", "qr_backward_step", "qr_solve", "qr_eval",
-           "qr_project", "qr_path_responses", "qr_sample_points", "qr_host_uniform",
-           "qr_host_norm_icdf", "qr_host_philox"]
+           "qr_project", "qr_path_responses", "qr_sample_points", "qr_solve_batched",
+           "qr_host_uniform", "qr_host_norm_icdf", "qr_host_philox"]
 
 
 class QrError(RuntimeError):
@@ -54,6 +55,11 @@ class Problem(C.Structure):
         ("sol_A", C.c_double), ("sol_c", C.c_double), ("sol_p", C.c_double),
         ("sol_w", C.c_double * MAX_D),
     ]
+
+
+class Instance(C.Structure):
+    """One instance of a batched solve (qr_instance)."""
+    _fields_ = [("f_a", C.c_double), ("d", C.c_int32), ("level", C.c_int32), ("M", C.c_int64)]
 
 
 if not os.path.exists(LIB_PATH):
@@ -79,6 +85,7 @@ _SIGS = {
     "qr_project": (C.c_int, [_P, _P, _I64, _P, _P, _P, _P]),
     "qr_path_responses": (C.c_int, [_P, C.POINTER(Problem), _P, _I32, _I64, _U64, _P, _P, _P, _P]),
     "qr_sample_points": (C.c_int, [_P, _I32, _U64, _U32, _I32, _I64, _I64, _P, _P]),
+    "qr_solve_batched": (C.c_int, [_P, C.POINTER(Problem), _P, _I32, C.POINTER(Instance), _U64, _P, _P]),
     "qr_host_uniform": (_D, [_U64, _U32, _U64, _U32, _U32]),
     "qr_host_norm_icdf": (_D, [_D]),
     "qr_host_philox": (None, [_P, _P, _P]),
@@ -259,4 +266,13 @@ class Context:
     def sample_points(self, d: int, seed: int, stream_id: int, i: int, n: int, x, m0: int = 0,
                       stream=None):
         _check(_lib.qr_sample_points(self._h, d, seed, stream_id, i, m0, n, _dptr(x),
+                                     _stream_ptr(stream)))
+
+    def solve_batched(self, prob: Problem, basis: Basis, instances, seed: int, alpha, stream=None):
+        """instances: sequence of (f_a, d, level, M); alpha: device [R][N][n_funcs]."""
+        R = len(instances)
+        arr = (Instance * max(R, 1))()
+        for r, (f_a, d, level, M) in enumerate(instances):
+            arr[r].f_a, arr[r].d, arr[r].level, arr[r].M = float(f_a), int(d), int(level), int(M)
+        _check(_lib.qr_solve_batched(self._h, C.byref(prob), basis.handle, R, arr, seed, _dptr(alpha),
                                      _stream_ptr(stream)))

@@ -290,3 +290,139 @@ def test_cfg2_full_size_sampled(env):
     for m in [0, w.M - 1] + list(rng.integers(0, w.M, 14)):
         ref = O.path_response(w, reps, w.N - 2, w.seed, int(m), alpha)
         assert abs(sg[m] - ref) <= TOL * max(1.0, abs(ref)), m
+
+
+# ---------------------------------------------------------------------------
+# batched form: instances on one shared cloud
+# ---------------------------------------------------------------------------
+
+def _embed(reps, d):
+    out = np.zeros((reps.shape[0], d), dtype=np.int32)
+    out[:, :reps.shape[1]] = reps
+    return out
+
+
+def _func_index(full_reps, sub_reps):
+    """Canonical function indices (of the full set) of the functions of sub_reps."""
+    pos = {tuple(r): c for c, r in enumerate(full_reps)}
+    idx = [0]
+    for r in sub_reps[1:]:
+        c = pos[tuple(r)]
+        idx += [2 * c - 1, 2 * c]
+    return np.array(idx)
+
+
+def _check_batched_instance(got, w, full_reps, inst, seed, rows, what):
+    """got: [N][nf] of one instance.  The oracle solves the group problem
+    with the instance's f_a on its own index set (embedded) and cloud size."""
+    f_a, d_r, level_r, M_r = inst
+    wr = w.with_(f_a=f_a)
+    reps = _embed(O.enumerate_set(d_r, w.set_kind, level_r), w.d)
+    idx = _func_index(full_reps, reps)
+    ref = O.solve(wr, reps, M=M_r, seed=seed)
+    mask = np.ones(got.shape[1], dtype=bool)
+    mask[idx] = False
+    assert not got[:, mask].any(), f"{what}: coefficients outside the instance's set are not 0"
+    for i in rows:
+        _, absum, _, _ = O.backward_step(wr, reps, i, M_r, seed, ref.copy())
+        _assert_alpha(got[i, idx], ref[i], absum, what=f"{what} row {i}")
+
+
+def test_batched_against_oracle(env):
+    """Ten instances of uneven d, level and M (two passes, the second ragged)."""
+    Q, ctx, torch = env
+    w = W.Workload(name="batch-small", d=5, N=4, T=1.0, sigma=[[0.5 if a == b else 0.0 for b in range(5)]
+                                                              for a in range(5)],
+                   b0=[0.0] * 5, b1=[0.0] * 5, set_kind="hc_1p", level=12, M=3000, driver="sin",
+                   f_a=0.5, sol_A=1.0, sol_c=1.0, sol_p=0.0, sol_w=[1.0, 1.0, 0.0, 0.0, 0.0], seed=7)
+    inst = [(0.3, 5, 12, 3000), (0.7, 2, 12, 2000), (0.5, 3, 4, 2500), (0.2, 4, 6, 1000),
+            (0.9, 5, 8, 1), (0.4, 2, 2, 700), (0.6, 5, 12, 129), (0.25, 1, 12, 3000),
+            (0.8, 3, 12, 1500), (0.35, 4, 1, 900)]
+    _say("batched: 10 small instances")
+    b = Q.Basis(w.d, w.set_kind, w.level)
+    full_reps = O.enumerate_set(w.d, w.set_kind, w.level)
+    a = torch.full((len(inst), w.N, b.n_funcs), 7.0, dtype=torch.float64, device="cuda")
+    ctx.solve_batched(Q.problem_from(w), b, inst, w.seed, a)
+    torch.cuda.synchronize()
+    got = _host(a)
+    for r, it in enumerate(inst):
+        _check_batched_instance(got[r], w, full_reps, it, w.seed, range(w.N), what=f"instance {r} {it}")
+    # deterministic
+    a2 = torch.zeros_like(a)
+    ctx.solve_batched(Q.problem_from(w), b, inst, w.seed, a2)
+    torch.cuda.synchronize()
+    assert torch.equal(a, a2)
+
+
+def test_batched_equals_unbatched_full_set(env):
+    """Instances on the whole basis give qr_solve's coefficients for their f_a."""
+    Q, ctx, torch = env
+    w = W.CFG1
+    b = Q.Basis(w.d, w.set_kind, w.level)
+    fas = [0.2, 0.5, 0.9]
+    _say("batched vs qr_solve, cfg1")
+    a = torch.zeros((len(fas), w.N, b.n_funcs), dtype=torch.float64, device="cuda")
+    ctx.solve_batched(Q.problem_from(w), b, [(f, w.d, w.level, w.M) for f in fas], w.seed, a)
+    for r, f in enumerate(fas):
+        ref = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device="cuda")
+        ctx.solve(Q.problem_from(w.with_(f_a=f)), b, w.M, w.seed, ref)
+        torch.cuda.synchronize()
+        err = (a[r] - ref).abs().max().item()
+        assert err <= TOL * ref.abs().max().item(), (f, err)
+
+
+def test_batched_invalid_arguments(env):
+    Q, ctx, torch = env
+    w = W.CFG1
+    b = Q.Basis(w.d, w.set_kind, w.level)
+    a = torch.zeros((65, w.N, b.n_funcs), dtype=torch.float64, device="cuda")
+    prob = Q.problem_from(w)
+    for bad in ([], [(0.5, 2, 4, 100)] * 65, [(0.5, 3, 4, 100)], [(0.5, 2, 5, 100)],
+                [(0.5, 2, 4, 0)], [(math.nan, 2, 4, 10)], [(0.5, 0, 4, 10)], [(0.5, 2, -1, 10)]):
+        with pytest.raises(Q.QrError):
+            ctx.solve_batched(prob, b, bad, 0, a)
+    with pytest.raises(Q.QrError) as e:
+        ctx.solve_batched(Q.problem_from(w.with_(driver="zrat")), b, [(0.5, 2, 4, 10)], 0, a)
+    assert e.value.status == -6
+
+
+def test_batched_group_full_size_sampled(env):
+    """The first group of 64 of the 256-instance workload at its real sizes
+    (d up to 12, levels 8/16/32, M up to 2^20): the last step's coefficients
+    of three instances on sampled functions, and the step before for the
+    instance with the smallest set."""
+    Q, ctx, torch = env
+    gw, inst, _ = W.batched_group(W.batched_instances())[0]
+    b = Q.Basis(gw.d, gw.set_kind, gw.level)
+    full_reps = O.enumerate_set(gw.d, gw.set_kind, gw.level)
+    _say(f"batched group 0: d={gw.d} level={gw.level} M={gw.M} R={len(inst)} n_funcs={b.n_funcs}")
+    a = torch.zeros((len(inst), gw.N, b.n_funcs), dtype=torch.float64, device="cuda")
+    ctx.solve_batched(Q.problem_from(gw), b, inst, gw.seed, a)
+    torch.cuda.synchronize()
+    sizes = [O.enumerate_set(d, gw.set_kind, L).shape[0] for _, d, L, _ in inst]
+    order = np.argsort(sizes)
+    rng = np.random.default_rng(5)
+    for r in [int(order[-1]), int(order[len(order) // 2]), int(order[0])]:
+        f_a, d_r, level_r, M_r = inst[r]
+        _say(f"  instance {r}: d={d_r} level={level_r} M={M_r} reps={sizes[r]}")
+        wr = gw.with_(f_a=f_a)
+        reps = _embed(O.enumerate_set(d_r, gw.set_kind, level_r), gw.d)
+        pick = np.concatenate([[0], np.sort(rng.choice(np.arange(1, reps.shape[0]),
+                                                       min(16, reps.shape[0] - 1), replace=False))])
+        sub = np.ascontiguousarray(reps[pick])
+        got = _host(a[r])
+        ref, absum, _, _ = O.backward_step(wr, sub, gw.N - 1, M_r, gw.seed,
+                                           np.zeros((gw.N, 2 * len(pick) - 1)))
+        _assert_alpha(got[gw.N - 1, _func_index(full_reps, sub)], ref, absum,
+                      what=f"instance {r} step N-1")
+    r = int(order[0])
+    f_a, d_r, level_r, M_r = inst[r]
+    wr = gw.with_(f_a=f_a)
+    reps = _embed(O.enumerate_set(d_r, gw.set_kind, level_r), gw.d)
+    idx = _func_index(full_reps, reps)
+    got = _host(a[r])
+    prev = np.zeros((gw.N, len(idx)))
+    prev[gw.N - 1] = got[gw.N - 1, idx]
+    _say(f"  instance {r}: step N-2 in full")
+    ref, absum, _, _ = O.backward_step(wr, reps, gw.N - 2, M_r, gw.seed, prev)
+    _assert_alpha(got[gw.N - 2, idx], ref, absum, what=f"instance {r} step N-2")

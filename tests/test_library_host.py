@@ -85,6 +85,12 @@ def test_invalid_arguments_are_rejected():
         Q.Basis(2, 7, 2)
     with pytest.raises(Q.QrError):
         Q.Basis(2, "tensor", -1)
+    # hyperbolic crosses below level 1 are empty (the oracle agrees)
+    for kind in ("hc_max", "hc_1p"):
+        assert O.count_set(3, kind, 0) == 0
+        with pytest.raises(Q.QrError):
+            Q.Basis(3, kind, 0)
+    assert Q.Basis(3, "tensor", 0).n_funcs == 1 == O.count_set(3, "tensor", 0)
 
 
 def test_context_without_device_reports_device_error():

@@ -122,6 +122,25 @@ def batched_instances(n: int = 256, seed: int = 4):
     return out
 
 
+def batched_group(instances, max_batch: int = 64):
+    """Split instances that share sigma = s I, b, N, T, the sampling law and a
+    solution depending on x1, x2 only into groups of at most max_batch.  Each
+    group is (group workload in the largest d of the group, level = largest
+    level, M = largest M; list of (f_a, d, level, M) per instance; indices)."""
+    out = []
+    for g0 in range(0, len(instances), max_batch):
+        grp = list(range(g0, min(len(instances), g0 + max_batch)))
+        ws = [instances[k] for k in grp]
+        d = max(w.d for w in ws)
+        w0 = ws[0]
+        s = w0.sigma[0][0]
+        gw = w0.with_(name=f"group{g0 // max_batch}", d=d, sigma=_diag(d, s), b0=[0.0] * d,
+                      b1=[0.0] * d, level=max(w.level for w in ws), M=max(w.M for w in ws),
+                      sol_w=_first_two(d))
+        out.append((gw, [(w.f_a, w.d, w.level, w.M) for w in ws], grp))
+    return out
+
+
 # ---------------------------------------------------------------------------
 # seeded synthetic inputs
 # ---------------------------------------------------------------------------
