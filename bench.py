@@ -29,7 +29,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
-FLOPS_PER_BASIS_EVAL = 5.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # published; packed FP32 (the second half) is not used here
+MFMA_16BIT_PEAK_TFLOPS = 2500.0  # dense bf16 / fp16
 
 
 def parse():
@@ -39,6 +40,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="d6-hcmax16-allen-cahn")
     ap.add_argument("--M", type=int, default=None, help="override paths per step")
+    ap.add_argument("--precision", default="f64", choices=["f64", "bf16", "f16"],
+                    help="arithmetic of the expansion evaluation along the paths")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -159,6 +162,8 @@ def main():
     from paper_2407_21084_amd import qrmc as Q
 
     if args.workload == BATCHED:
+        if args.precision != "f64":
+            sys.exit("the batched form runs in FP64")
         run_batched(args, torch, W, Q)
         return
     w = W.ALL[args.workload]
@@ -178,8 +183,14 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
 
+    def solve():
+        if args.precision == "f64":
+            ctx.solve(prob, basis, w.M, w.seed, alpha, stream)
+        else:
+            ctx.solve_prec(prob, basis, w.M, w.seed, args.precision, alpha, stream)
+
     for k in range(args.warmup):
-        ctx.solve(prob, basis, w.M, w.seed, alpha, stream)
+        solve()
         torch.cuda.synchronize()
         print(f"[bench] warmup solve {k + 1}/{args.warmup} done", file=sys.stderr, flush=True)
 
@@ -188,7 +199,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        ctx.solve(prob, basis, w.M, w.seed, alpha, stream)
+        solve()
         if k + 1 < args.steps and args.steps > 1:
             print(f"[bench] timed solve {k + 1}/{args.steps} enqueued", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -201,11 +212,27 @@ def main():
     path_ms, path_n = ctx.kernel_time(Q.K_PATH)
     proj_ms, proj_n = ctx.kernel_time(Q.K_PROJECT)
     red_ms, red_n = ctx.kernel_time(Q.K_REDUCE)
-    # algorithmic flops of the path kernel: expansions at X_{j+1}, j+1 < N
+    # algorithmic flops of the path kernel: expansions at X_{j+1}, j+1 < N.
+    # Per basis function: half a complex multiply of the walk (3 flops) and
+    # the contraction (2 flops per right-hand side: ybar, and with a
+    # z-dependent driver the d gradient components).
+    grad = w.driver == "zrat"
+    rhs = 1 + (w.d if grad else 0)
     path_evals = w.M * basis.n_funcs * w.N * (w.N - 1) / 2 * args.steps
-    achieved = path_evals * FLOPS_PER_BASIS_EVAL / (path_ms * 1e-3) / 1e12 if path_ms > 0 else 0.0
+    path_s = path_ms * 1e-3
+    if args.precision == "f64":
+        flops_per_eval, peak, kernel = 3.0 + 2.0 * rhs, FP64_VECTOR_PEAK_TFLOPS, "path_kernel"
+        mfma = None
+    else:
+        # walk on the FP32 vector ALU; contraction on the matrix cores
+        flops_per_eval, peak, kernel = 3.0, FP32_VECTOR_PEAK_TFLOPS, "mfma_path_kernel"
+        T = 1 if not grad else max((w.d + 4) // 4, 2 if max(w.d, w.nbm) <= 8 else 3)
+        issued = path_evals * 2.0 * 4 * T / path_s / 1e12 if path_s > 0 else 0.0
+        mfma = {"issued_tflops": issued, "useful_tflops": issued * rhs / (4 * T),
+                "peak": MFMA_16BIT_PEAK_TFLOPS}
+    achieved = path_evals * flops_per_eval / path_s / 1e12 if path_s > 0 else 0.0
     proj_evals = w.M * basis.n_funcs * w.N * args.steps
-    proj_tflops = proj_evals * FLOPS_PER_BASIS_EVAL / (proj_ms * 1e-3) / 1e12 if proj_ms > 0 else 0.0
+    proj_tflops = proj_evals * 5.0 / (proj_ms * 1e-3) / 1e12 if proj_ms > 0 else 0.0
 
     # accuracy of the last solve against the closed form at t_0 (stream-1 points)
     n_test = 1 << 16
@@ -219,7 +246,8 @@ def main():
     rel_l2 = float(torch.linalg.norm(yt - u0) / torch.linalg.norm(u0))
 
     line = {
-        "metric": "basis-evals/s (plain FP64 full solve)",
+        "metric": "basis-evals/s (plain FP64 full solve)" if args.precision == "f64"
+                  else f"basis-evals/s ({args.precision} expansion evaluation, full solve)",
         "value": value,
         "unit": "basis-evals/s",
         "n_gpus": 1,
@@ -229,7 +257,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": args.precision,
         "data": "synthetic",
         "config": {"workload": w.name, "d": w.d, "N": w.N, "set": f"{w.set_kind}({w.level})",
                    "n_funcs": basis.n_funcs, "M": w.M, "evals_per_solve": evals_per_solve},
@@ -237,12 +265,15 @@ def main():
         "rel_l2_t0": rel_l2,
         "kernels_ms_per_solve": {"path": path_ms / args.steps, "project": proj_ms / args.steps,
                                  "reduce": red_ms / args.steps},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-                     "traffic": None, "kernel": "path_kernel",
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": None, "kernel": kernel,
+                     "flops_per_eval": flops_per_eval,
                      "avg_launch_ms": path_ms / max(1, path_n),
                      "project_tflops": proj_tflops},
     }
+    if mfma:
+        line["mfma"] = mfma
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

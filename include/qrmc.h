@@ -214,6 +214,28 @@ qr_status qr_sample_points(qr_ctx *ctx, int32_t d, uint64_t seed, uint32_t strea
                            int64_t m0, int64_t n, double *x, void *stream);
 
 /* ---------------------------------------------------------------------- */
+/* Reduced-precision form                                                  */
+/* ---------------------------------------------------------------------- */
+
+/* Arithmetic of the expansion evaluation along the paths (eq (yqi:bar:M)).
+ * QR_PREC_F64: everything in FP64 (qr_solve).  QR_PREC_BF16 / QR_PREC_F16:
+ * phase reduction F(x) -> e^{2 pi i u} in FP64, the basis walk in FP32, basis
+ * values and coefficients rounded to 16 bits (bfloat16 or IEEE half) and
+ * contracted on the matrix cores with FP32 accumulation; for drivers that
+ * depend on z the d gradient components are further right-hand sides of the
+ * same contraction.  The path simulation, driver sum, projection and alpha
+ * reduction stay FP64. */
+typedef enum { QR_PREC_F64 = 0, QR_PREC_BF16 = 1, QR_PREC_F16 = 2 } qr_precision;
+
+/* qr_backward_step / qr_solve with the expansion evaluation in `precision`.
+ * Arguments and outputs as there; QR_PREC_F64 is the plain path. */
+qr_status qr_backward_step_prec(qr_ctx *ctx, const qr_problem *prob, const qr_basis *basis,
+                                int32_t i, int64_t M, uint64_t seed, int32_t precision,
+                                double *alpha, void *stream);
+qr_status qr_solve_prec(qr_ctx *ctx, const qr_problem *prob, const qr_basis *basis, int64_t M,
+                        uint64_t seed, int32_t precision, double *alpha, void *stream);
+
+/* ---------------------------------------------------------------------- */
 /* Batched form: several PDE instances solved on one shared cloud          */
 /* ---------------------------------------------------------------------- */
 

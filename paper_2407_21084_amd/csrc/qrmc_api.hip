@@ -58,6 +58,7 @@ struct qr_basis {
     std::mutex mu;
     int dev = -1;
     int32_t *d_canon_of_trav = nullptr;
+    int32_t *d_trav = nullptr;
     TaskItem *d_items = nullptr;
     Task *d_tasks = nullptr;
     int64_t ld() const { return nrep + kRowPad; }
@@ -240,6 +241,7 @@ static void basis_free_device(qr_basis *b) {
         hipSetDevice(b->dev);
         hipDeviceSynchronize();
         hipFree(b->d_canon_of_trav);
+        hipFree(b->d_trav);
         hipFree(b->d_items);
         hipFree(b->d_tasks);
         hipFree(b->d_ft);
@@ -247,6 +249,7 @@ static void basis_free_device(qr_basis *b) {
         hipSetDevice(cur);
     }
     b->d_canon_of_trav = nullptr;
+    b->d_trav = nullptr;
     b->d_items = nullptr;
     b->d_tasks = nullptr;
     b->d_ft = nullptr;
@@ -312,6 +315,9 @@ static qr_status basis_on_device(qr_basis *b, int dev) {
     if (b->dev == dev) return QR_OK;
     if (b->dev >= 0) basis_free_device(b);
     QR_HIP(hipMalloc(&b->d_canon_of_trav, sizeof(int32_t) * b->nrep), "hipMalloc(basis)");
+    QR_HIP(hipMalloc(&b->d_trav, sizeof(int32_t) * b->trav.size()), "hipMalloc(basis)");
+    QR_HIP(hipMemcpy(b->d_trav, b->trav.data(), sizeof(int32_t) * b->trav.size(), hipMemcpyHostToDevice),
+           "hipMemcpy(basis)");
     QR_HIP(hipMalloc(&b->d_items, sizeof(TaskItem) * b->items.size()), "hipMalloc(basis)");
     QR_HIP(hipMalloc(&b->d_tasks, sizeof(Task) * b->tasks.size()), "hipMalloc(basis)");
     QR_HIP(hipMemcpy(b->d_canon_of_trav, b->canon_of_trav.data(), sizeof(int32_t) * b->nrep,
@@ -353,7 +359,7 @@ struct qr_ctx {
     DevProblem *d_prob = nullptr;
     DevProblem h_prob{};
     bool prob_valid = false;
-    Buf S, u, alpha_int, partial, row, alpha_b;
+    Buf S, u, alpha_int, partial, row, alpha_b, tiles;
     DevBatch *d_batch = nullptr;
     bool timing = false;
     std::vector<Timed> pending;
@@ -402,7 +408,7 @@ extern "C" void qr_ctx_destroy(qr_ctx *c) {
     if (!c) return;
     hipSetDevice(c->dev);
     hipDeviceSynchronize();
-    for (Buf *b : {&c->S, &c->u, &c->alpha_int, &c->partial, &c->row, &c->alpha_b})
+    for (Buf *b : {&c->S, &c->u, &c->alpha_int, &c->partial, &c->row, &c->alpha_b, &c->tiles})
         if (b->p) hipFree(b->p);
     hipFree(c->d_prob);
     if (c->d_batch) hipFree(c->d_batch);
@@ -737,6 +743,99 @@ extern "C" qr_status qr_sample_points(qr_ctx *c, int32_t d, uint64_t seed, uint3
     if (d < 1 || d > QR_MAX_D) return fail(QR_EINVAL, "qr_sample_points: d=%d", d);
     if (n < 0 || m0 < 0 || !x) return fail(QR_EINVAL, "qr_sample_points: bad n/m0/x");
     QR_HIP(launch_sample(d, seed, stream_id, i, m0, n, x, (hipStream_t)stream), "sample_kernel");
+    return QR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// reduced-precision form
+// ---------------------------------------------------------------------------
+namespace {
+struct TilePlan {
+    int T;
+    int64_t ld;  // uint2 per row: one spare group for the walk's prefetch past the last group
+};
+TilePlan tile_plan(const qr_problem *p, const qr_basis *b) {
+    const bool grad = p->driver == QR_F_ZRAT;
+    const int T = mfma_tile_groups(dim_bucket(p->d, p->nbm), p->d, grad);
+    const int64_t ngroups = (b->nrep + 31) / 32;
+    return TilePlan{T, (ngroups + 1) * T * 64};
+}
+}  // namespace
+
+static qr_status prepare_prec(qr_ctx *c, const qr_problem *p, qr_basis *b, int64_t M, int32_t prec,
+                              void *stream, TilePlan *tp) {
+    if (prec != QR_PREC_BF16 && prec != QR_PREC_F16)
+        return fail(QR_EINVAL, "precision %d is not one of QR_PREC_F64/BF16/F16", prec);
+    qr_status st = prepare(c, p, b, M, stream);
+    if (st) return st;
+    *tp = tile_plan(p, b);
+    if ((st = ensure(c, c->tiles, sizeof(uint2) * (size_t)p->N * tp->ld, "coefficient tiles"))) return st;
+    // the spare groups are read ahead and never used; keep them defined
+    QR_HIP(launch_zero((double *)c->tiles.p, (int64_t)(sizeof(uint2) / sizeof(double)) * p->N * tp->ld,
+                       (hipStream_t)stream), "zero_kernel");
+    return QR_OK;
+}
+
+static qr_status pack_row(qr_ctx *c, const qr_problem *p, const qr_basis *b, int32_t prec, const TilePlan &tp,
+                          int32_t row, hipStream_t s) {
+    const double2 *ai = (const double2 *)c->alpha_int.p + (int64_t)row * b->ld();
+    uint2 *out = (uint2 *)c->tiles.p + (int64_t)row * tp.ld;
+    return timed(c, 3, s, "pack_tiles_kernel",
+                 [&] { return launch_pack_tiles(prec, ai, b->nrep, b->d_trav, p->d, tp.T, out, s); });
+}
+
+static qr_status run_mfma_path(qr_ctx *c, const qr_problem *p, const qr_basis *b, int32_t prec,
+                               const TilePlan &tp, int32_t i, int64_t M, uint64_t seed, hipStream_t s) {
+    MfmaArgs a{c->d_prob, make_walk(b->kind, b->level, b->d), i, M, seed, (const uint2 *)c->tiles.p, tp.ld,
+               (double *)c->S.p, (double *)c->u.p};
+    return timed(c, 0, s, "mfma_path_kernel", [&] {
+        return launch_mfma_path(dim_bucket(p->d, p->nbm), depth_cap(b->max_nnz), p->driver == QR_F_ZRAT, prec,
+                                a, s);
+    });
+}
+
+extern "C" qr_status qr_backward_step_prec(qr_ctx *c, const qr_problem *p, const qr_basis *bc, int32_t i,
+                                           int64_t M, uint64_t seed, int32_t prec, double *alpha,
+                                           void *stream) {
+    if (prec == QR_PREC_F64) return qr_backward_step(c, p, bc, i, M, seed, alpha, stream);
+    qr_basis *b = const_cast<qr_basis *>(bc);
+    TilePlan tp;
+    qr_status st = prepare_prec(c, p, b, M, prec, stream, &tp);
+    if (st) return st;
+    if (!alpha) return fail(QR_EINVAL, "qr_backward_step_prec: alpha is NULL");
+    if (i < 0 || i >= p->N) return fail(QR_EINVAL, "qr_backward_step_prec: i=%d outside [0,%d)", i, p->N);
+    hipStream_t s = (hipStream_t)stream;
+    double2 *ai = (double2 *)c->alpha_int.p;
+    const int64_t nf = 2 * b->nrep - 1;
+    st = timed(c, 3, s, "gather_kernel", [&] {
+        return launch_gather(alpha, i + 1, p->N - 1 - i, b->nrep, b->ld(), nf, b->d_canon_of_trav, ai, s);
+    });
+    if (st) return st;
+    for (int32_t r = i + 1; r < p->N; ++r)
+        if ((st = pack_row(c, p, b, prec, tp, r, s))) return st;
+    if ((st = run_mfma_path(c, p, b, prec, tp, i, M, seed, s))) return st;
+    return project_and_reduce(c, b, (double *)c->u.p, (double *)c->S.p, M, ai + (int64_t)i * b->ld(),
+                              alpha + (int64_t)i * nf, s);
+}
+
+extern "C" qr_status qr_solve_prec(qr_ctx *c, const qr_problem *p, const qr_basis *bc, int64_t M,
+                                   uint64_t seed, int32_t prec, double *alpha, void *stream) {
+    if (prec == QR_PREC_F64) return qr_solve(c, p, bc, M, seed, alpha, stream);
+    qr_basis *b = const_cast<qr_basis *>(bc);
+    TilePlan tp;
+    qr_status st = prepare_prec(c, p, b, M, prec, stream, &tp);
+    if (st) return st;
+    if (!alpha) return fail(QR_EINVAL, "qr_solve_prec: alpha is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    double2 *ai = (double2 *)c->alpha_int.p;
+    const int64_t nf = 2 * b->nrep - 1;
+    for (int32_t i = p->N - 1; i >= 0; --i) {
+        if ((st = run_mfma_path(c, p, b, prec, tp, i, M, seed, s))) return st;
+        if ((st = project_and_reduce(c, b, (double *)c->u.p, (double *)c->S.p, M, ai + (int64_t)i * b->ld(),
+                                     alpha + (int64_t)i * nf, s)))
+            return st;
+        if (i > 0 && (st = pack_row(c, p, b, prec, tp, i, s))) return st;
+    }
     return QR_OK;
 }
 

@@ -7,10 +7,20 @@ namespace qrmc {
 
 constexpr int kPathBlock = 128;   // threads per block of the path / eval kernels
 constexpr int kPathP = 2;         // paths per thread of the value-only path kernel
-constexpr int kProjWaves = 4;     // waves per block of the projection kernel
+// Projection shape (compile-time tunables).
+#ifndef QRMC_PROJ_WAVES
+#define QRMC_PROJ_WAVES 4
+#endif
+#ifndef QRMC_PROJ_CHUNK
+#define QRMC_PROJ_CHUNK 4
+#endif
+#ifndef QRMC_TASK_MAX
+#define QRMC_TASK_MAX 128
+#endif
+constexpr int kProjWaves = QRMC_PROJ_WAVES;  // waves per block of the projection kernel
 constexpr int kProjP = 2;         // paths per lane of the projection kernel (1 where LDS is short)
-constexpr int kProjChunk = 8;     // nodes per cross-lane reduction of the projection
-constexpr int kTaskMax = 256;     // nodes per projection task
+constexpr int kProjChunk = QRMC_PROJ_CHUNK;  // nodes per cross-lane reduction of the projection
+constexpr int kTaskMax = QRMC_TASK_MAX;      // nodes per projection task
 constexpr int kRowPad = 16;       // coefficient rows are padded by this many pairs
 
 constexpr int kBatchRT = 8;       // instances per pass of the batched path kernel
@@ -34,6 +44,20 @@ struct BatchArgs {
     const double2 *alpha_b;  // [N][ld][kBatchRT] of this pass
     int64_t ld;
     double *S, *u;  // S: [kBatchRT][M] of this pass; u: [d][M]
+};
+
+// Reduced-precision path kernel.  The coefficient tiles of row j are at
+// tiles + j tile_ld (uint2 units); a row holds ceil(nrep / 32) groups of
+// T x 64 uint2 (T = mfma_tile_groups).
+struct MfmaArgs {
+    const DevProblem *P;
+    Walk W;
+    int32_t i;
+    int64_t M;
+    uint64_t seed;
+    const uint2 *tiles;
+    int64_t tile_ld;
+    double *S, *u;
 };
 
 struct PathArgs {
@@ -72,6 +96,11 @@ hipError_t launch_reduce_batched(const double2 *partial, int32_t nsplit, int64_t
 hipError_t launch_zero(double *p, int64_t n, hipStream_t s);
 
 size_t project_lds_bytes(int32_t d, int P);
+size_t mfma_path_lds_bytes(int32_t d);
+hipError_t launch_mfma_path(int db, int cap, bool grad, int prec, const MfmaArgs &a, hipStream_t s);
+int mfma_tile_groups(int db, int d, bool grad);
+hipError_t launch_pack_tiles(int prec, const double2 *alpha_int_row, int64_t nrep, const int32_t *trav,
+                             int32_t d, int32_t T, uint2 *out, hipStream_t s);
 size_t path_lds_bytes(int32_t d, bool grad, int P);
 int path_points(bool grad);
 

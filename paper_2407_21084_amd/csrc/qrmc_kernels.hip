@@ -26,15 +26,16 @@ namespace qrmc {
 
 #define QR_CONST __attribute__((address_space(4)))
 
-// values at the P points of a thread
-template <int P>
+// values at the P points of a thread, in FP64 (R = double) or, for the
+// reduced-precision form, FP32 (R = float)
+template <int P, class R = double>
 struct Pts {
-    double re[P], im[P];
+    R re[P], im[P];
 };
 
-template <int P>
-__device__ __forceinline__ Pts<P> cmul(const Pts<P> &a, const Pts<P> &b) {
-    Pts<P> r;
+template <int P, class R>
+__device__ __forceinline__ Pts<P, R> cmul(const Pts<P, R> &a, const Pts<P, R> &b) {
+    Pts<P, R> r;
 #pragma unroll
     for (int q = 0; q < P; ++q) {
         r.re[q] = fma(a.re[q], b.re[q], -(a.im[q] * b.im[q]));
@@ -43,9 +44,9 @@ __device__ __forceinline__ Pts<P> cmul(const Pts<P> &a, const Pts<P> &b) {
     return r;
 }
 
-template <int P>
-__device__ __forceinline__ Pts<P> unit() {
-    Pts<P> r;
+template <int P, class R = double>
+__device__ __forceinline__ Pts<P, R> unit() {
+    Pts<P, R> r;
 #pragma unroll
     for (int q = 0; q < P; ++q) {
         r.re[q] = 1.0;
@@ -63,23 +64,35 @@ __device__ __forceinline__ void wave_sync() {
 // Per-lane LDS slots of a thread's P points: e^{2 pi i u_l} of point q at
 // E[(l P + q) stride], gradient accumulators (d ybar / d u_l up to 2 pi) at
 // G[(l P + q) stride].
-template <int P>
+template <class R>
+struct Cplx;
+template <>
+struct Cplx<double> {
+    using T = double2;
+};
+template <>
+struct Cplx<float> {
+    using T = float2;
+};
+
+template <int P, class R = double>
 struct LanePts {
-    double2 *E;
-    double *G;
+    using C2 = typename Cplx<R>::T;
+    C2 *E;
+    R *G;
     int stride;
-    __device__ __forceinline__ Pts<P> e(int l) const {
-        Pts<P> r;
+    __device__ __forceinline__ Pts<P, R> e(int l) const {
+        Pts<P, R> r;
 #pragma unroll
         for (int q = 0; q < P; ++q) {
-            const double2 v = E[(l * P + q) * stride];
+            const C2 v = E[(l * P + q) * stride];
             r.re[q] = v.x;
             r.im[q] = v.y;
         }
         return r;
     }
-    __device__ __forceinline__ void set_e(int l, int q, double2 v) const { E[(l * P + q) * stride] = v; }
-    __device__ __forceinline__ double &g(int l, int q) const { return G[(l * P + q) * stride]; }
+    __device__ __forceinline__ void set_e(int l, int q, C2 v) const { E[(l * P + q) * stride] = v; }
+    __device__ __forceinline__ R &g(int l, int q) const { return G[(l * P + q) * stride]; }
 };
 
 // ---------------------------------------------------------------------------
@@ -120,14 +133,14 @@ __device__ __noinline__ double nl_sin(double a) { return sin(a); }
 // or stays 1 (tensor set, c = 0); the child has children iff its budget is
 // at most Lc.  See make_walk in qrmc_common.h.
 // ---------------------------------------------------------------------------
-template <int T, int CAP, int P, class Sink>
-__device__ __forceinline__ typename Sink::Acc visit(const Pts<P> &parent, const int p, const int Pb,
-                                                    const Walk &W, const LanePts<P> &L, Sink &sink) {
+template <int T, int CAP, int P, class R, class Sink>
+__device__ __forceinline__ typename Sink::Acc visit(const Pts<P, R> &parent, const int p, const int Pb,
+                                                    const Walk &W, const LanePts<P, R> &L, Sink &sink) {
     typename Sink::Acc acc{};
 #pragma unroll 1
     for (int l = p + 1; l < W.d; ++l) {
         const bool more = l + 1 < W.d;
-        [[maybe_unused]] double gl[P];
+        [[maybe_unused]] R gl[P];
         if constexpr (Sink::kGrad) {
 #pragma unroll
             for (int q = 0; q < P; ++q) gl[q] = 0.0;
@@ -136,18 +149,18 @@ __device__ __forceinline__ typename Sink::Acc visit(const Pts<P> &parent, const 
         for (int s = 0; s < (T == 0 ? 1 : 2); ++s) {
             // chain factor e^{+-2 pi i u_l}, re-read per sign to keep one
             // complex value per point live instead of two
-            Pts<P> es = L.e(l);
+            Pts<P, R> es = L.e(l);
             if (s) {
 #pragma unroll
                 for (int q = 0; q < P; ++q) es.im[q] = -es.im[q];
             }
-            Pts<P> v = parent;
-            [[maybe_unused]] double km = s ? -1.0 : 1.0;
+            Pts<P, R> v = parent;
+            [[maybe_unused]] R km = s ? -1.0 : 1.0;
 #pragma unroll 1
             for (int w = Pb * (1 + W.b); w <= W.L; w += Pb) {
                 v = cmul(v, es);
                 if constexpr (Sink::kGrad) {
-                    double gs[P];
+                    R gs[P];
                     sink.node_g(v, acc, gs);
                     if constexpr (T + 1 < CAP) {
                         const int child = W.c ? w : Pb;
@@ -179,9 +192,9 @@ __device__ __forceinline__ typename Sink::Acc visit(const Pts<P> &parent, const 
 }
 
 // Start the walk below a node of runtime depth `depth` (< CAP).
-template <int T, int CAP, int P, class Sink>
-__device__ __forceinline__ void visit_from(int depth, const Pts<P> &v, int p, int Pb, const Walk &W,
-                                           const LanePts<P> &L, Sink &sink) {
+template <int T, int CAP, int P, class R, class Sink>
+__device__ __forceinline__ void visit_from(int depth, const Pts<P, R> &v, int p, int Pb, const Walk &W,
+                                           const LanePts<P, R> &L, Sink &sink) {
     if constexpr (T < CAP) {
         if (depth == T) {
             (void)visit<T, CAP, P>(v, p, Pb, W, L, sink);
@@ -498,21 +511,23 @@ struct ProjSink {
         if (++c == kProjChunk) flush();
     }
 
-    // Sum the chunk over the 64 lanes: lane q adds the 16 lanes of quarter
-    // q>>4 for value q&15 (node (q&15)>>1, component q&1); the quarters are
-    // then combined by two xor-shuffles in a fixed order.
+    // Sum the chunk over the 64 lanes.  With V = 2 kProjChunk values (node,
+    // component), lane q adds the V lanes of group q / V for value q % V;
+    // the groups are then combined by xor-shuffles in a fixed order.
     __device__ __forceinline__ void flush() {
+        constexpr int V = 2 * kProjChunk;
+        static_assert(64 % V == 0, "chunk must divide the wave");
         wave_sync();
-        const int val = lane & 15, rep = val >> 1, quarter = lane >> 4;
+        const int val = lane % V, rep = val >> 1, grp = lane / V;
         double sum = 0.0;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const double2 w = wbuf[(quarter * 16 + k) * (kProjChunk + 1) + rep];
+        for (int k = 0; k < V; ++k) {
+            const double2 w = wbuf[(grp * V + k) * (kProjChunk + 1) + rep];
             sum += (val & 1) ? w.y : w.x;
         }
-        sum += __shfl_xor(sum, 16);
-        sum += __shfl_xor(sum, 32);
-        if (lane < 16 && rep < c) acc[(base + rep) * 2 + (val & 1)] += sum;
+#pragma unroll
+        for (int o = V; o < 64; o <<= 1) sum += __shfl_xor(sum, o);
+        if (lane < V && rep < c) acc[(base + rep) * 2 + (val & 1)] += sum;
         wave_sync();
         base += c;
         c = 0;
@@ -688,6 +703,247 @@ __global__ void sample_kernel(int32_t d, uint64_t seed, uint32_t stream_id, int3
     if (p >= n) return;
     PhiloxStream rs(seed, stream_id, (uint64_t)(m0 + p), (uint32_t)i, 0u);
     for (int l = 0; l < d; ++l) x[l * n + p] = logistic_icdf(rs.next());
+}
+
+// ---------------------------------------------------------------------------
+// Reduced-precision form.  The walk runs in FP32 from phase factors reduced
+// in FP64; each node's value is rounded to 16 bits (bf16 or f16) and parked
+// in this lane's LDS slots; every kMfmaGroup nodes the group is contracted
+// on the matrix cores with the row's coefficient tiles, accumulating in FP32.
+//
+// v_mfma_f32_4x4x4_16b: 16 blocks of D(4x4) += A(4x4) B(4x4).  Lane
+// l = 4b + j holds B[b][k][j] (k = 0..3) and receives D[b][i][j] (i = 0..3).
+// Here B = basis values: block b = pair of nodes (k = Re, Im of node 2b,
+// Re, Im of node 2b+1) at the lane's own path (column j, so lane l is path
+// l), and A = coefficients of that pair for 4 right-hand sides (rows i),
+// broadcast from block b's lanes (CBSZ 4, ABID b) to all blocks.  D rows are
+// right-hand sides: 0 = ybar, 1 + l = d ybar / d u_l.  T groups of 4
+// right-hand sides take T instructions per pair.
+// ---------------------------------------------------------------------------
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 h16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2_t __attribute__((ext_vector_type(2)));
+
+template <int PREC>
+__device__ __forceinline__ uint32_t pack16x2(float a, float b) {
+    if constexpr (PREC == QR_PREC_BF16) {
+        const bf16x2_t v = {(__bf16)a, (__bf16)b};
+        return __builtin_bit_cast(uint32_t, v);
+    } else {
+        const f16x2_t v = {(_Float16)a, (_Float16)b};
+        return __builtin_bit_cast(uint32_t, v);
+    }
+}
+
+template <int PREC, int ABID>
+__device__ __forceinline__ f32x4 mfma_pair(uint2 a, uint2 b, f32x4 c) {
+    if constexpr (PREC == QR_PREC_BF16)
+        return __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(__builtin_bit_cast(s16x4, a),
+                                                      __builtin_bit_cast(s16x4, b), c, 4, ABID, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_4x4x4f16(__builtin_bit_cast(h16x4, a),
+                                                  __builtin_bit_cast(h16x4, b), c, 4, ABID, 0);
+}
+
+constexpr int kMfmaGroup = 32;  // nodes per contraction group (16 pairs)
+
+template <int PREC, int T>
+struct MfmaSink {
+    static constexpr bool kGrad = false;
+    struct Acc {};
+    uint32_t *stage;       // this lane's 16-bit pairs: stage[(node pair) 128 + half], lane offset applied
+    const uint2 *tiles;    // coefficient tiles of the next group: [T][64] uint2, lane offset applied
+    uint2 a[T];            // this lane's A operands of the current group
+    f32x4 acc[T];
+    int c;                 // nodes of the current group so far (wave-uniform)
+
+    __device__ __forceinline__ void load_tiles() {
+#pragma unroll
+        for (int t = 0; t < T; ++t) a[t] = tiles[t * 64];
+        tiles += T * 64;
+    }
+    template <int B>
+    __device__ __forceinline__ void pair() {
+        const uint2 b = *reinterpret_cast<const uint2 *>(stage + B * 128);
+#pragma unroll
+        for (int t = 0; t < T; ++t) acc[t] = mfma_pair<PREC, B>(a[t], b, acc[t]);
+    }
+    template <int B>
+    __device__ __forceinline__ void pairs() {
+        if constexpr (B < kMfmaGroup / 2) {
+            pair<B>();
+            pairs<B + 1>();
+        }
+    }
+    __device__ __forceinline__ void flush() {
+        pairs<0>();
+        load_tiles();
+        c = 0;
+    }
+    __device__ __forceinline__ void node(const Pts<1, float> &v, Acc &) {
+        // the counter is the same in every lane: keep it (and the offset) scalar
+        const int cu = __builtin_amdgcn_readfirstlane(c);
+        stage[(cu >> 1) * 128 + (cu & 1)] = pack16x2<PREC>(v.re[0], v.im[0]);
+        c = cu + 1;
+        if (c == kMfmaGroup) flush();
+    }
+    __device__ __forceinline__ static void add(Acc &, const Acc &) {}
+};
+
+template <int DB, int CAP, bool GRAD, int T, int PREC>
+__global__ __launch_bounds__(kPathBlock) void mfma_path_kernel(
+    const DevProblem *__restrict__ P0, const Walk W, const int32_t i, const int64_t M,
+    const uint64_t seed, const uint2 *__restrict__ tiles, const int64_t tile_ld,
+    double *__restrict__ S_out, double *__restrict__ u_out) {
+    // T groups of 4 right-hand sides: 1 (ybar) or 1 + d <= 4 T (with gradients)
+    extern __shared__ double2 lds[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int d = P0->d, nbm = P0->nbm, N = P0->N;
+    // LDS: staged pairs [waves][16][64] uint2 | phase factors [d][128] float2 | path state [d][128] double
+    uint32_t *stage = reinterpret_cast<uint32_t *>(lds) + wave * (kMfmaGroup / 2) * 128;
+    float2 *E = reinterpret_cast<float2 *>(reinterpret_cast<uint2 *>(lds) + (kPathBlock / 64) * (kMfmaGroup / 2) * 64);
+    double *xs = reinterpret_cast<double *>(E + d * kPathBlock) + tid;
+    const LanePts<1, float> L{E + tid, nullptr, kPathBlock};
+    // stale slots of a partial group meet zero coefficients: keep them finite
+    for (int k = 0; k < kMfmaGroup; ++k) stage[(k >> 1) * 128 + 2 * lane + (k & 1)] = 0u;
+
+    const int64_t m = (int64_t)blockIdx.x * kPathBlock + tid;  // paths past M run on and are not stored
+    {
+        PhiloxStream rs(seed, 0u, (uint64_t)m, (uint32_t)i, 0u);
+        for (int l = 0; l < d; ++l) {
+            const double x = nl_logistic_icdf(rs.next());
+            xs[l * kPathBlock] = x;
+            if (u_out && m < M) u_out[l * M + m] = nl_logistic_cdf(x);
+        }
+    }
+    double S = 0.0;
+    for (int j = i; j < N; ++j) {
+        const DevProblem *__restrict__ Pj = P0;
+        asm volatile("" : "+s"(Pj));
+        const double tj = Pj->t[j];
+        const double dt = Pj->t[j + 1] - tj;
+        double hj;
+        {
+            double x[DB];
+#pragma unroll
+            for (int l = 0; l < DB; ++l) x[l] = (l < d) ? xs[l * kPathBlock] : 0.0;
+            hj = h_source<DB>(Pj, tj, x, d);
+            const double sq = sqrt(dt);
+            PhiloxStream rs(seed, 0u, (uint64_t)m, (uint32_t)i, (uint32_t)(d + (j - i) * nbm));
+#pragma unroll
+            for (int l = 0; l < DB; ++l)
+                if (l < d) x[l] = fma(fma(Pj->b1[l], x[l], Pj->b0[l]), dt, x[l]);
+#pragma unroll 1
+            for (int k = 0; k < nbm; ++k) {
+                const double dwk = sq * nl_norm_icdf(rs.next());
+#pragma unroll
+                for (int l = 0; l < DB; ++l)
+                    if (l < d) x[l] = fma(Pj->sigma[l * nbm + k], dwk, x[l]);
+            }
+#pragma unroll
+            for (int l = 0; l < DB; ++l)
+                if (l < d) xs[l * kPathBlock] = x[l];
+        }
+        double y, z2 = 0.0;
+        if (j + 1 < N) {
+            for (int l = 0; l < d; ++l) {
+                const double2 e = nl_unit_phase(xs[l * kPathBlock]);
+                L.set_e(l, 0, make_float2((float)e.x, (float)e.y));
+            }
+            MfmaSink<PREC, T> sink;
+            sink.stage = stage + 2 * lane;
+            sink.tiles = tiles + (int64_t)(j + 1) * tile_ld + lane;
+            sink.c = 0;
+#pragma unroll
+            for (int t = 0; t < T; ++t) sink.acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+            sink.load_tiles();
+            typename MfmaSink<PREC, T>::Acc none{};
+            const Pts<1, float> one = unit<1, float>();
+            sink.node(one, none);
+            (void)visit<0, CAP, 1>(one, -1, 1, W, L, sink);
+            if (sink.c) sink.template pairs<0>();
+            y = (double)sink.acc[0][0];
+            if constexpr (GRAD) {
+                double gx[DB];
+#pragma unroll
+                for (int l = 0; l < DB; ++l) {
+                    gx[l] = 0.0;
+                    if (l < d) {
+                        const double u = nl_logistic_cdf(xs[l * kPathBlock]);
+                        gx[l] = (double)sink.acc[(l + 1) / 4][(l + 1) % 4] * (u * (1.0 - u));
+                    }
+                }
+                for (int k = 0; k < nbm; ++k) {
+                    double zk = 0.0;
+#pragma unroll
+                    for (int l = 0; l < DB; ++l)
+                        if (l < d) zk = fma(Pj->sigma[l * nbm + k], gx[l], zk);
+                    z2 = fma(zk, zk, z2);
+                }
+            }
+        } else {
+            double x[DB], gx[DB];
+#pragma unroll
+            for (int l = 0; l < DB; ++l) x[l] = (l < d) ? xs[l * kPathBlock] : 0.0;
+            y = g_term<DB>(Pj, x, d, GRAD ? gx : nullptr);
+            if constexpr (GRAD) {
+                for (int k = 0; k < nbm; ++k) {
+                    double zk = 0.0;
+#pragma unroll
+                    for (int l = 0; l < DB; ++l)
+                        if (l < d) zk = fma(Pj->sigma[l * nbm + k], gx[l], zk);
+                    z2 = fma(zk, zk, z2);
+                }
+            }
+        }
+        S = fma(fnl(Pj, clamp_abs(y, Pj->clamp), z2) + hj, dt, S);
+    }
+    double x[DB];
+#pragma unroll
+    for (int l = 0; l < DB; ++l) x[l] = (l < d) ? xs[l * kPathBlock] : 0.0;
+    const double Sm = S + g_term<DB>(P0, x, d, nullptr);
+    if (m < M) S_out[m] = Sm;
+}
+
+size_t mfma_path_lds_bytes(int32_t d) {
+    return (size_t)(kPathBlock / 64) * (kMfmaGroup / 2) * 64 * sizeof(uint2) +
+           (size_t)d * kPathBlock * (sizeof(float2) + sizeof(double));
+}
+
+// Coefficient tiles of one row: tile[g][t][lane] holds, for lane 4b + r, the
+// 16-bit coefficients of right-hand side 4t + r on nodes 32g + 2b and
+// 32g + 2b + 1: (Re, Im) weights, ybar = sum a.x Re + a.y Im and
+// d ybar / d u_l = sum 2 pi k_l (a.y Re - a.x Im).  Nodes past nrep and
+// right-hand sides past d are zero.
+template <int PREC>
+__global__ void pack_tiles_kernel(const double2 *__restrict__ alpha_int_row, int64_t nrep,
+                                  const int32_t *__restrict__ trav, int32_t d, int32_t T,
+                                  int64_t ngroups, uint2 *__restrict__ out) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= ngroups * T * 64) return;
+    const int lane = (int)(idx % 64), t = (int)((idx / 64) % T);
+    const int64_t g = idx / (64 * T);
+    const int b = lane >> 2, rhs = 4 * t + (lane & 3);
+    uint32_t w[2];
+    for (int h = 0; h < 2; ++h) {
+        const int64_t n = g * kMfmaGroup + 2 * b + h;
+        double cr = 0.0, ci = 0.0;
+        if (n < nrep) {
+            const double2 a = alpha_int_row[n];
+            if (rhs == 0) {
+                cr = a.x;
+                ci = a.y;
+            } else if (rhs <= d) {
+                const double k2p = 2.0 * M_PI * (double)trav[n * d + rhs - 1];
+                cr = k2p * a.y;
+                ci = -k2p * a.x;
+            }
+        }
+        w[h] = pack16x2<PREC>((float)cr, (float)ci);
+    }
+    out[idx] = make_uint2(w[0], w[1]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1081,6 +1337,81 @@ hipError_t launch_reduce_batched(const double2 *partial, int32_t nsplit, int64_t
 hipError_t launch_zero(double *p, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(zero_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+template <int DB, int CAP, bool GRAD, int T, int PREC>
+static hipError_t mfma_path_t(const MfmaArgs &a, hipStream_t s) {
+    const size_t lds = mfma_path_lds_bytes(a.W.d);
+    static size_t granted = kLdsDefault;
+    const hipError_t e = allow_lds((const void *)mfma_path_kernel<DB, CAP, GRAD, T, PREC>, lds, granted);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((mfma_path_kernel<DB, CAP, GRAD, T, PREC>), dim3(blocks_for(a.M, kPathBlock)),
+                       dim3(kPathBlock), lds, s, a.P, a.W, a.i, a.M, a.seed, a.tiles, a.tile_ld, a.S, a.u);
+    return hipGetLastError();
+}
+
+template <int DB, bool GRAD, int T, int PREC>
+static hipError_t mfma_path_cap(int cap, const MfmaArgs &a, hipStream_t s) {
+    switch (cap) {
+    case 2: return mfma_path_t<DB, 2, GRAD, T, PREC>(a, s);
+    case 4: return mfma_path_t<DB, 4, GRAD, T, PREC>(a, s);
+    case 6: if constexpr (DB >= 6) return mfma_path_t<DB, 6, GRAD, T, PREC>(a, s); break;
+    case 8: if constexpr (DB >= 8) return mfma_path_t<DB, 8, GRAD, T, PREC>(a, s); break;
+    }
+    return hipErrorInvalidValue;
+}
+
+// right-hand-side groups: the smallest T with 1 + d <= 4 T among those the
+// dimension bucket instantiates (value only: T = 1)
+int mfma_tile_groups(int db, int d, bool grad) {
+    if (!grad) return 1;
+    const int T = (d + 4) / 4;
+    const int lo = db <= 8 ? 2 : 3;
+    return T < lo ? lo : T;
+}
+
+template <int DB, int PREC>
+static hipError_t mfma_path_g(int cap, bool grad, int T, const MfmaArgs &a, hipStream_t s) {
+    if (!grad) return mfma_path_cap<DB, false, 1, PREC>(cap, a, s);
+    if constexpr (DB == 4) {
+        if (T == 2) return mfma_path_cap<4, true, 2, PREC>(cap, a, s);
+    } else if constexpr (DB == 8) {
+        if (T == 2) return mfma_path_cap<8, true, 2, PREC>(cap, a, s);
+        if (T == 3) return mfma_path_cap<8, true, 3, PREC>(cap, a, s);
+    } else {
+        if (T == 3) return mfma_path_cap<16, true, 3, PREC>(cap, a, s);
+        if (T == 4) return mfma_path_cap<16, true, 4, PREC>(cap, a, s);
+        if (T == 5) return mfma_path_cap<16, true, 5, PREC>(cap, a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_mfma_path(int db, int cap, bool grad, int prec, const MfmaArgs &a, hipStream_t s) {
+    if (prec != QR_PREC_BF16 && prec != QR_PREC_F16) return hipErrorInvalidValue;
+    const bool bf = prec == QR_PREC_BF16;
+    const int T = mfma_tile_groups(db, a.W.d, grad);
+    switch (db) {
+    case 4: return bf ? mfma_path_g<4, QR_PREC_BF16>(cap, grad, T, a, s) : mfma_path_g<4, QR_PREC_F16>(cap, grad, T, a, s);
+    case 8: return bf ? mfma_path_g<8, QR_PREC_BF16>(cap, grad, T, a, s) : mfma_path_g<8, QR_PREC_F16>(cap, grad, T, a, s);
+    case 16: return bf ? mfma_path_g<16, QR_PREC_BF16>(cap, grad, T, a, s) : mfma_path_g<16, QR_PREC_F16>(cap, grad, T, a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+
+hipError_t launch_pack_tiles(int prec, const double2 *alpha_int_row, int64_t nrep, const int32_t *trav,
+                             int32_t d, int32_t T, uint2 *out, hipStream_t s) {
+    const int64_t ngroups = (nrep + kMfmaGroup - 1) / kMfmaGroup;
+    const int64_t total = ngroups * T * 64;
+    if (prec == QR_PREC_BF16)
+        hipLaunchKernelGGL(pack_tiles_kernel<QR_PREC_BF16>, dim3(blocks_for(total, 256)), dim3(256), 0, s,
+                           alpha_int_row, nrep, trav, d, T, ngroups, out);
+    else if (prec == QR_PREC_F16)
+        hipLaunchKernelGGL(pack_tiles_kernel<QR_PREC_F16>, dim3(blocks_for(total, 256)), dim3(256), 0, s,
+                           alpha_int_row, nrep, trav, d, T, ngroups, out);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

@@ -29,13 +29,17 @@ DRIVERS = {"linear": F_LINEAR, "sin": F_SIN, "allen_cahn": F_ALLEN_CAHN, "zrat":
 STATUS = {0: "QR_OK", -1: "QR_EINVAL", -2: "QR_ENOMEM", -3: "QR_EDEVICE", -4: "QR_ERANGE",
           -5: "QR_ENUMERIC", -6: "QR_ENOTSUP"}
 
+PREC_F64, PREC_BF16, PREC_F16 = 0, 1, 2
+PRECISIONS = {"f64": PREC_F64, "bf16": PREC_BF16, "f16": PREC_F16}
+
 # kernel classes of qr_ctx_kernel_time
 K_PATH, K_PROJECT, K_REDUCE, K_GATHER = 0, 1, 2, 3
 
 EXPORTS = ["qr_last_error", "qr_version", "qr_build_basis", "qr_basis_info", "qr_basis_indices",
            "qr_basis_free", "qr_ctx_create", "qr_ctx_destroy", "qr_ctx_set_timing",
            "qr_ctx_kernel_time", "qr_ctx_reset_timing", "qr_backward_step", "qr_solve", "qr_eval",
-           "qr_project", "qr_path_responses", "qr_sample_points", "qr_solve_batched",
+           "qr_project", "qr_path_responses", "qr_sample_points", "qr_backward_step_prec",
+           "qr_solve_prec", "qr_solve_batched",
            "qr_host_uniform", "qr_host_norm_icdf", "qr_host_philox"]
 
 
@@ -85,6 +89,8 @@ _SIGS = {
     "qr_project": (C.c_int, [_P, _P, _I64, _P, _P, _P, _P]),
     "qr_path_responses": (C.c_int, [_P, C.POINTER(Problem), _P, _I32, _I64, _U64, _P, _P, _P, _P]),
     "qr_sample_points": (C.c_int, [_P, _I32, _U64, _U32, _I32, _I64, _I64, _P, _P]),
+    "qr_backward_step_prec": (C.c_int, [_P, C.POINTER(Problem), _P, _I32, _I64, _U64, _I32, _P, _P]),
+    "qr_solve_prec": (C.c_int, [_P, C.POINTER(Problem), _P, _I64, _U64, _I32, _P, _P]),
     "qr_solve_batched": (C.c_int, [_P, C.POINTER(Problem), _P, _I32, C.POINTER(Instance), _U64, _P, _P]),
     "qr_host_uniform": (_D, [_U64, _U32, _U64, _U32, _U32]),
     "qr_host_norm_icdf": (_D, [_D]),
@@ -247,6 +253,17 @@ class Context:
     def solve(self, prob: Problem, basis: Basis, M: int, seed: int, alpha, stream=None):
         _check(_lib.qr_solve(self._h, C.byref(prob), basis.handle, M, seed, _dptr(alpha),
                              _stream_ptr(stream)))
+
+    def backward_step_prec(self, prob: Problem, basis: Basis, i: int, M: int, seed: int, precision,
+                           alpha, stream=None):
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        _check(_lib.qr_backward_step_prec(self._h, C.byref(prob), basis.handle, i, M, seed, prec,
+                                          _dptr(alpha), _stream_ptr(stream)))
+
+    def solve_prec(self, prob: Problem, basis: Basis, M: int, seed: int, precision, alpha, stream=None):
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        _check(_lib.qr_solve_prec(self._h, C.byref(prob), basis.handle, M, seed, prec, _dptr(alpha),
+                                  _stream_ptr(stream)))
 
     def eval(self, basis: Basis, alpha_row, x, y, grad=None, stream=None):
         n = y.shape[0]
