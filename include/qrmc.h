@@ -236,6 +236,68 @@ qr_status qr_solve_prec(qr_ctx *ctx, const qr_problem *prob, const qr_basis *bas
                         uint64_t seed, int32_t precision, double *alpha, void *stream);
 
 /* ---------------------------------------------------------------------- */
+/* Learned form: a network surrogate of ybar_j per time index              */
+/* ---------------------------------------------------------------------- */
+
+/* The surrogate (not part of the paper's method): features f in R^16 ->
+ * h1 = silu(W1 f + b1) (256) -> h2 = silu(W2 h1 + b2) (256) -> w3 . h2 + b3,
+ * silu(z) = z / (1 + e^-z).  Parameters: one FP32 vector, blocks in the order
+ * W1 [256][16] (row = output unit), b1 [256], W2 [256][256], b2 [256],
+ * w3 [256], b3 [1].  Products run on the matrix cores with bfloat16 operands
+ * and FP32 accumulation.  Features of a state x: 2 F(x_l) - 1 for l < d and
+ * 0 up to 16 (d <= 16). */
+#define QR_MLP_IN 16
+#define QR_MLP_HIDDEN 256
+#define QR_MLP_NPARAMS (QR_MLP_HIDDEN * QR_MLP_IN + QR_MLP_HIDDEN + QR_MLP_HIDDEN * QR_MLP_HIDDEN + \
+                        QR_MLP_HIDDEN + QR_MLP_HIDDEN + 1)
+#define QR_MLP_MAX_BATCH 65536
+
+/* Fan-in uniform initialisation (biases 0) from Philox stream 2 of seed.
+ * params: device [QR_MLP_NPARAMS]. */
+qr_status qr_mlp_init(qr_ctx *ctx, float *params, uint64_t seed, void *stream);
+/* feat[p][l] (device [n][16]) from x (device SoA [d][n]), 1 <= d <= 16. */
+qr_status qr_mlp_features(qr_ctx *ctx, int32_t d, int64_t n, const double *x, float *feat, void *stream);
+/* y[p] (device [n]) = network(feat[p]); any n >= 0 (processed in chunks). */
+qr_status qr_mlp_forward(qr_ctx *ctx, const float *params, int64_t n, const float *feat, float *y,
+                         void *stream);
+/* Mean squared error over n <= QR_MLP_MAX_BATCH pairs and its gradient:
+ * grad (device [QR_MLP_NPARAMS]) is overwritten, *loss (host) receives the
+ * loss after the stream has completed the work. */
+qr_status qr_mlp_loss_grad(qr_ctx *ctx, const float *params, int64_t n, const float *feat,
+                           const float *target, float *grad, double *loss, void *stream);
+/* One bias-corrected Adam step (beta1 0.9, beta2 0.999, eps 1e-8) number
+ * `step` >= 1 on device vectors params, m, v given grad. */
+qr_status qr_mlp_adam(qr_ctx *ctx, float *params, const float *grad, float *m, float *v, int64_t step,
+                      float lr, void *stream);
+
+typedef struct {
+    int64_t train_points;   /* pairs (X, ybar_j(X)) per time index, X from stream 2 */
+    int64_t heldout_points; /* held-out pairs, X from stream 3 */
+    int32_t epochs;         /* passes over the training pairs */
+    int32_t batch;          /* pairs per Adam step, <= QR_MLP_MAX_BATCH */
+    float lr;               /* Adam step size */
+    double gate;            /* use the surrogate iff its held-out relative L2 error <= gate */
+} qr_learn_opts;
+
+typedef struct {
+    double heldout_rel_l2;  /* ||surrogate - ybar_j|| / ||ybar_j|| on the held-out points */
+    double train_loss;      /* mean squared error of the last epoch (normalised targets) */
+    int32_t trained;        /* a surrogate was fitted for this time index */
+    int32_t used;           /* it replaced the expansion along the paths */
+} qr_learn_report;
+
+/* qr_solve (the driver must not depend on z) where, after row j of alpha is
+ * known (1 <= j <= N-1), a surrogate of ybar_j is fitted on the method's own
+ * pairs and, if it passes the gate, evaluated along the paths instead of
+ * the |Gamma|-term expansion; otherwise the expansion is used (and is the
+ * result).  report: host [N], entry j for time index j.  The surrogate only
+ * changes how ybar_j is evaluated at X_j; the path simulation, projection
+ * and alpha reduction are those of qr_solve. */
+qr_status qr_solve_learned(qr_ctx *ctx, const qr_problem *prob, const qr_basis *basis, int64_t M,
+                           uint64_t seed, const qr_learn_opts *opts, double *alpha,
+                           qr_learn_report *report, void *stream);
+
+/* ---------------------------------------------------------------------- */
 /* Batched form: several PDE instances solved on one shared cloud          */
 /* ---------------------------------------------------------------------- */
 

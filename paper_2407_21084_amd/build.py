@@ -1,6 +1,6 @@
 """Build step of libqrmc.so: hipcc for gfx950, in-tree.
 
-The two translation units (kernels, host API) are compiled in parallel and
+The translation units (kernels, network kernels, host API) are compiled in parallel and
 linked into ``paper_2407_21084_amd/libqrmc.so``.  Packed FP32 instructions are
 disabled for the device code (``-packed-fp32-ops``).
 """
@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libqrmc.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["qrmc_kernels.hip", "qrmc_api.hip"]
+SOURCES = ["qrmc_kernels.hip", "qrmc_mlp.hip", "qrmc_api.hip"]
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wno-unused-result",
          "-Wno-unused-value", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", INCLUDE, "-I", CSRC]

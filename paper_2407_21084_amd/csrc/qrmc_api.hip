@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "qrmc_kernels.h"
+#include "qrmc_mlp.h"
 
 using namespace qrmc;
 
@@ -360,6 +361,11 @@ struct qr_ctx {
     DevProblem h_prob{};
     bool prob_valid = false;
     Buf S, u, alpha_int, partial, row, alpha_b, tiles;
+    // surrogate network workspace: activations of up to kMlpChunk rows
+    Buf mf, mz1, mh1, mz2, mh2, mdz, mdh, my, mdy, mpart, mwork, mcwork;
+    // learned solve: cloud state, per-step source term, expansion values,
+    // surrogate parameters per time index, Adam state, training pairs
+    Buf lx, lh, ly, lparams, lgrad, lm, lv, ltx, ltt, ltf, lff, lhx, lht, lhf, lhy;
     DevBatch *d_batch = nullptr;
     bool timing = false;
     std::vector<Timed> pending;
@@ -408,7 +414,10 @@ extern "C" void qr_ctx_destroy(qr_ctx *c) {
     if (!c) return;
     hipSetDevice(c->dev);
     hipDeviceSynchronize();
-    for (Buf *b : {&c->S, &c->u, &c->alpha_int, &c->partial, &c->row, &c->alpha_b, &c->tiles})
+    for (Buf *b : {&c->S, &c->u, &c->alpha_int, &c->partial, &c->row, &c->alpha_b, &c->tiles, &c->mf, &c->mz1,
+                   &c->mh1, &c->mz2, &c->mh2, &c->mdz, &c->mdh, &c->my, &c->mdy, &c->mpart, &c->mwork,
+                   &c->mcwork, &c->lx, &c->lh, &c->ly, &c->lparams, &c->lgrad, &c->lm, &c->lv, &c->ltx, &c->ltt,
+                   &c->ltf, &c->lff, &c->lhx, &c->lht, &c->lhf, &c->lhy})
         if (b->p) hipFree(b->p);
     hipFree(c->d_prob);
     if (c->d_batch) hipFree(c->d_batch);
@@ -835,6 +844,305 @@ extern "C" qr_status qr_solve_prec(qr_ctx *c, const qr_problem *p, const qr_basi
                                      alpha + (int64_t)i * nf, s)))
             return st;
         if (i > 0 && (st = pack_row(c, p, b, prec, tp, i, s))) return st;
+    }
+    return QR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// surrogate network (learned form)
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int64_t kMlpChunk = QR_MLP_MAX_BATCH;       // rows of the activation workspace
+constexpr int64_t kGemmWork = (int64_t)64 * kMlpHid * kMlpHid;  // split-K partials (floats)
+}  // namespace
+
+// room for two partial sums per block of 256 over n items
+static qr_status ensure_partials(qr_ctx *c, int64_t n) {
+    return ensure(c, c->mpart, sizeof(double) * (size_t)(2 * ((n + 255) / 256) + 2), "partials");
+}
+
+static qr_status mlp_workspace(qr_ctx *c, int64_t rows) {
+    qr_status st;
+    const size_t act = sizeof(float) * (size_t)rows * kMlpHid;
+    if ((st = ensure(c, c->mf, sizeof(float) * (size_t)rows * kMlpIn, "network features"))) return st;
+    for (Buf *b : {&c->mz1, &c->mh1, &c->mz2, &c->mh2, &c->mdz, &c->mdh})
+        if ((st = ensure(c, *b, act, "network activations"))) return st;
+    if ((st = ensure(c, c->my, sizeof(float) * (size_t)rows, "network outputs"))) return st;
+    if ((st = ensure(c, c->mdy, sizeof(float) * (size_t)rows, "network outputs"))) return st;
+    if ((st = ensure_partials(c, rows))) return st;
+    if ((st = ensure(c, c->mwork, sizeof(float) * (size_t)kGemmWork, "gemm workspace"))) return st;
+    if ((st = ensure(c, c->mcwork, sizeof(float) * (size_t)kColsumWork, "column sums"))) return st;
+    return QR_OK;
+}
+
+// forward pass of n <= kMlpChunk rows; leaves Z1, H1, Z2, H2 in the workspace
+static hipError_t mlp_fwd(qr_ctx *c, const float *th, int64_t n, const float *f, float *y, hipStream_t s) {
+    float *Z1 = (float *)c->mz1.p, *H1 = (float *)c->mh1.p, *Z2 = (float *)c->mz2.p, *H2 = (float *)c->mh2.p;
+    float *w = (float *)c->mwork.p;
+    hipError_t e;
+    const int N = (int)n;
+    // Z1 = F W1^T: B(k, j) = W1[j][k]
+    if ((e = launch_gemm(N, kMlpHid, kMlpIn, f, kMlpIn, 1, th + kOffW1, 1, kMlpIn, Z1, kMlpHid, false, w, kGemmWork, s)))
+        return e;
+    if ((e = launch_bias_silu(n, kMlpHid, Z1, th + kOffB1, H1, s))) return e;
+    if ((e = launch_gemm(N, kMlpHid, kMlpHid, H1, kMlpHid, 1, th + kOffW2, 1, kMlpHid, Z2, kMlpHid, false, w,
+                         kGemmWork, s)))
+        return e;
+    if ((e = launch_bias_silu(n, kMlpHid, Z2, th + kOffB2, H2, s))) return e;
+    return launch_out_layer(n, kMlpHid, H2, th + kOffW3, th + kOffB3, y, s);
+}
+
+// loss partials into mpart, gradient into g (all blocks overwritten)
+static hipError_t mlp_bwd(qr_ctx *c, const float *th, int64_t n, const float *f, const float *t, float *g,
+                          hipStream_t s) {
+    hipError_t e;
+    if ((e = mlp_fwd(c, th, n, f, (float *)c->my.p, s))) return e;
+    float *Z1 = (float *)c->mz1.p, *H1 = (float *)c->mh1.p, *Z2 = (float *)c->mz2.p, *H2 = (float *)c->mh2.p;
+    float *dZ = (float *)c->mdz.p, *dH = (float *)c->mdh.p, *dy = (float *)c->mdy.p;
+    float *w = (float *)c->mwork.p, *cw = (float *)c->mcwork.p;
+    const int N = (int)n;
+    if ((e = launch_loss(n, (float *)c->my.p, t, dy, (double *)c->mpart.p, s))) return e;
+    if ((e = launch_colsum(n, kMlpHid, H2, dy, g + kOffW3, cw, s))) return e;
+    if ((e = launch_colsum(n, 1, dy, nullptr, g + kOffB3, cw, s))) return e;
+    if ((e = launch_dz_out(n, kMlpHid, dy, th + kOffW3, Z2, dZ, s))) return e;
+    // dW2 = dZ^T H1
+    if ((e = launch_gemm(kMlpHid, kMlpHid, N, dZ, 1, kMlpHid, H1, kMlpHid, 1, g + kOffW2, kMlpHid, false, w,
+                         kGemmWork, s)))
+        return e;
+    if ((e = launch_colsum(n, kMlpHid, dZ, nullptr, g + kOffB2, cw, s))) return e;
+    // dH1 = dZ W2, then through silu'
+    if ((e = launch_gemm(N, kMlpHid, kMlpHid, dZ, kMlpHid, 1, th + kOffW2, kMlpHid, 1, dH, kMlpHid, false, w,
+                         kGemmWork, s)))
+        return e;
+    if ((e = launch_dsilu(n, kMlpHid, Z1, dH, s))) return e;
+    // dW1 = dZ1^T F
+    if ((e = launch_gemm(kMlpHid, kMlpIn, N, dH, 1, kMlpHid, f, kMlpIn, 1, g + kOffW1, kMlpIn, false, w, kGemmWork,
+                         s)))
+        return e;
+    return launch_colsum(n, kMlpHid, dH, nullptr, g + kOffB1, cw, s);
+}
+
+static qr_status read_partials(qr_ctx *c, int64_t nblocks, int stride, double *out, hipStream_t s) {
+    std::vector<double> h((size_t)nblocks * stride);
+    QR_HIP(hipMemcpyAsync(h.data(), c->mpart.p, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s),
+           "hipMemcpyAsync(partials)");
+    QR_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    for (int k = 0; k < stride; ++k) out[k] = 0.0;
+    for (int64_t b = 0; b < nblocks; ++b)
+        for (int k = 0; k < stride; ++k) out[k] += h[(size_t)b * stride + k];
+    return QR_OK;
+}
+
+extern "C" qr_status qr_mlp_init(qr_ctx *c, float *params, uint64_t seed, void *stream) {
+    qr_status st = begin(c, stream);
+    if (st) return st;
+    if (!params) return fail(QR_EINVAL, "qr_mlp_init: params is NULL");
+    QR_HIP(launch_mlp_init(params, seed, (hipStream_t)stream), "mlp_init_kernel");
+    return QR_OK;
+}
+
+extern "C" qr_status qr_mlp_features(qr_ctx *c, int32_t d, int64_t n, const double *x, float *feat, void *stream) {
+    qr_status st = begin(c, stream);
+    if (st) return st;
+    if (d < 1 || d > kMlpIn) return fail(QR_EINVAL, "qr_mlp_features: d=%d outside [1,%d]", d, kMlpIn);
+    if (n < 0) return fail(QR_EINVAL, "qr_mlp_features: n < 0");
+    if (n == 0) return QR_OK;
+    if (!x || !feat) return fail(QR_EINVAL, "qr_mlp_features: NULL argument");
+    QR_HIP(launch_features(d, n, x, n, feat, (hipStream_t)stream), "features_kernel");
+    return QR_OK;
+}
+
+extern "C" qr_status qr_mlp_forward(qr_ctx *c, const float *params, int64_t n, const float *feat, float *y,
+                                    void *stream) {
+    qr_status st = begin(c, stream);
+    if (st) return st;
+    if (n < 0) return fail(QR_EINVAL, "qr_mlp_forward: n < 0");
+    if (n == 0) return QR_OK;
+    if (!params || !feat || !y) return fail(QR_EINVAL, "qr_mlp_forward: NULL argument");
+    if ((st = mlp_workspace(c, std::min(n, kMlpChunk)))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    for (int64_t p0 = 0; p0 < n; p0 += kMlpChunk) {
+        const int64_t k = std::min(kMlpChunk, n - p0);
+        QR_HIP(mlp_fwd(c, params, k, feat + p0 * kMlpIn, y + p0, s), "mlp forward");
+    }
+    return QR_OK;
+}
+
+extern "C" qr_status qr_mlp_loss_grad(qr_ctx *c, const float *params, int64_t n, const float *feat,
+                                      const float *target, float *grad, double *loss, void *stream) {
+    qr_status st = begin(c, stream);
+    if (st) return st;
+    if (n < 1 || n > kMlpChunk) return fail(QR_EINVAL, "qr_mlp_loss_grad: n=%lld outside [1,%lld]", (long long)n,
+                                            (long long)kMlpChunk);
+    if (!params || !feat || !target || !grad) return fail(QR_EINVAL, "qr_mlp_loss_grad: NULL argument");
+    if ((st = mlp_workspace(c, n))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    QR_HIP(mlp_bwd(c, params, n, feat, target, grad, s), "mlp backward");
+    if (loss) {
+        double sum;
+        if ((st = read_partials(c, (n + 255) / 256, 1, &sum, s))) return st;
+        *loss = sum / (double)n;
+    }
+    return QR_OK;
+}
+
+extern "C" qr_status qr_mlp_adam(qr_ctx *c, float *params, const float *grad, float *m, float *v, int64_t step,
+                                 float lr, void *stream) {
+    qr_status st = begin(c, stream);
+    if (st) return st;
+    if (!params || !grad || !m || !v) return fail(QR_EINVAL, "qr_mlp_adam: NULL argument");
+    if (step < 1) return fail(QR_EINVAL, "qr_mlp_adam: step must be >= 1");
+    if (!(lr > 0.f)) return fail(QR_EINVAL, "qr_mlp_adam: lr must be > 0");
+    QR_HIP(launch_adam(kMlpParams, params, grad, m, v, step, lr, (hipStream_t)stream), "adam_kernel");
+    return QR_OK;
+}
+
+// Fit the surrogate of ybar_j (row j of alpha_int) for time index j.
+static qr_status fit_surrogate(qr_ctx *c, const qr_problem *p, const qr_basis *b, int32_t j, uint64_t seed,
+                              const qr_learn_opts *o, float *th, double *mu, double *sigma,
+                              qr_learn_report *rep, hipStream_t s) {
+    qr_status st;
+    const int d = p->d;
+    const int64_t nt = o->train_points, nh = o->heldout_points;
+    double *tx = (double *)c->ltx.p, *tt = (double *)c->ltt.p, *hx = (double *)c->lhx.p, *ht = (double *)c->lht.p;
+    float *tf = (float *)c->ltf.p, *ff = (float *)c->lff.p, *hf = (float *)c->lhf.p, *hy = (float *)c->lhy.p;
+    const double2 *row = (const double2 *)c->alpha_int.p + (int64_t)j * b->ld();
+    const Walk W = make_walk(b->kind, b->level, b->d);
+    const int cap = depth_cap(b->max_nnz);
+    // pairs (X, ybar_j(X)): training from stream 2, held-out from stream 3, at time index j
+    QR_HIP(launch_sample(d, seed, 2u, j, 0, nt, tx, s), "sample_kernel");
+    QR_HIP(launch_sample(d, seed, 3u, j, 0, nh, hx, s), "sample_kernel");
+    st = timed(c, 0, s, "eval_kernel", [&] { return launch_eval(cap, false, W, row, tx, nt, tt, nullptr, s); });
+    if (st) return st;
+    st = timed(c, 0, s, "eval_kernel", [&] { return launch_eval(cap, false, W, row, hx, nh, ht, nullptr, s); });
+    if (st) return st;
+    // targets normalised by their mean and standard deviation
+    QR_HIP(launch_moments(nt, tt, (double *)c->mpart.p, s), "moments_kernel");
+    double mom[2];
+    if ((st = read_partials(c, (nt + 255) / 256, 2, mom, s))) return st;
+    const double mean = mom[0] / (double)nt;
+    double var = mom[1] / (double)nt - mean * mean;
+    const double sd = var > 1e-300 ? std::sqrt(var) : 1.0;
+    *mu = mean;
+    *sigma = sd;
+    QR_HIP(launch_to_float(nt, tt, mean, 1.0 / sd, tf, s), "to_float_kernel");
+    QR_HIP(launch_features(d, nt, tx, nt, ff, s), "features_kernel");
+    QR_HIP(launch_features(d, nh, hx, nh, hf, s), "features_kernel");
+    // Adam over mini-batches in a fixed order
+    QR_HIP(launch_mlp_init(th, seed ^ (0x9E3779B97F4A7C15ull * (uint64_t)(j + 1)), s), "mlp_init_kernel");
+    QR_HIP(launch_zero((double *)c->lm.p, kMlpParams / 2 + 1, s), "zero_kernel");
+    QR_HIP(launch_zero((double *)c->lv.p, kMlpParams / 2 + 1, s), "zero_kernel");
+    float *g = (float *)c->lgrad.p, *m = (float *)c->lm.p, *v = (float *)c->lv.p;
+    const int64_t B = o->batch, nb = nt / B;
+    int64_t step = 0;
+    double last = 0.0;
+    for (int e = 0; e < o->epochs; ++e) {
+        double ep = 0.0;
+        for (int64_t bi = 0; bi < nb; ++bi) {
+            QR_HIP(mlp_bwd(c, th, B, ff + bi * B * kMlpIn, tf + bi * B, g, s), "mlp backward");
+            QR_HIP(launch_adam(kMlpParams, th, g, m, v, ++step, o->lr, s), "adam_kernel");
+            if (e + 1 == o->epochs) {
+                double l;
+                if ((st = read_partials(c, (B + 255) / 256, 1, &l, s))) return st;
+                ep += l / (double)B;
+            }
+        }
+        if (e + 1 == o->epochs) last = ep / (double)nb;
+    }
+    // held-out error against the expansion
+    for (int64_t p0 = 0; p0 < nh; p0 += kMlpChunk) {
+        const int64_t k = std::min(kMlpChunk, nh - p0);
+        QR_HIP(mlp_fwd(c, th, k, hf + p0 * kMlpIn, hy + p0, s), "mlp forward");
+    }
+    QR_HIP(launch_heldout(nh, hy, ht, mean, sd, (double *)c->mpart.p, s), "heldout_kernel");
+    double ab[2];
+    if ((st = read_partials(c, (nh + 255) / 256, 2, ab, s))) return st;
+    rep->heldout_rel_l2 = ab[1] > 0.0 ? std::sqrt(ab[0] / ab[1]) : INFINITY;
+    rep->train_loss = last;
+    rep->trained = 1;
+    rep->used = rep->heldout_rel_l2 <= o->gate ? 1 : 0;
+    return QR_OK;
+}
+
+extern "C" qr_status qr_solve_learned(qr_ctx *c, const qr_problem *p, const qr_basis *bc, int64_t M,
+                                      uint64_t seed, const qr_learn_opts *o, double *alpha,
+                                      qr_learn_report *report, void *stream) {
+    qr_basis *b = const_cast<qr_basis *>(bc);
+    if (!o || !report) return fail(QR_EINVAL, "qr_solve_learned: NULL opts or report");
+    if (o->epochs < 0 || o->batch < 64 || o->batch > QR_MLP_MAX_BATCH || o->train_points < o->batch ||
+        o->heldout_points < 1 || !(o->lr > 0.f) || !(o->gate >= 0.0))
+        return fail(QR_EINVAL, "qr_solve_learned: invalid options (epochs >= 0, 64 <= batch <= %d, "
+                               "train_points >= batch, heldout_points >= 1, lr > 0, gate >= 0)", QR_MLP_MAX_BATCH);
+    qr_status st = prepare(c, p, b, M, stream);
+    if (st) return st;
+    if (!alpha) return fail(QR_EINVAL, "qr_solve_learned: alpha is NULL");
+    if (p->driver == QR_F_ZRAT)
+        return fail(QR_ENOTSUP, "qr_solve_learned: the driver depends on z (the surrogate has no gradient)");
+    hipStream_t s = (hipStream_t)stream;
+    const int d = p->d, N = p->N;
+    const int64_t nt = o->train_points, nh = o->heldout_points;
+    const int64_t chunk = std::min(M, kMlpChunk);
+    if ((st = mlp_workspace(c, std::max(chunk, std::min<int64_t>(std::max<int64_t>(o->batch, nh), kMlpChunk)))))
+        return st;
+    // partial sums over the training pairs (moments) and the held-out pairs
+    if ((st = ensure_partials(c, std::max(nt, nh)))) return st;
+    if ((st = ensure(c, c->lx, sizeof(double) * (size_t)d * M, "cloud state"))) return st;
+    if ((st = ensure(c, c->lh, sizeof(double) * (size_t)M, "source term"))) return st;
+    if ((st = ensure(c, c->ly, sizeof(double) * (size_t)M, "expansion values"))) return st;
+    if ((st = ensure(c, c->lparams, sizeof(float) * (size_t)N * kMlpParams, "surrogate parameters"))) return st;
+    for (Buf *bb : {&c->lgrad, &c->lm, &c->lv})
+        if ((st = ensure(c, *bb, sizeof(float) * (size_t)(kMlpParams + 1), "Adam state"))) return st;
+    if ((st = ensure(c, c->ltx, sizeof(double) * (size_t)d * nt, "training pairs"))) return st;
+    if ((st = ensure(c, c->ltt, sizeof(double) * (size_t)nt, "training pairs"))) return st;
+    if ((st = ensure(c, c->ltf, sizeof(float) * (size_t)nt, "training pairs"))) return st;
+    if ((st = ensure(c, c->lff, sizeof(float) * (size_t)nt * kMlpIn, "training pairs"))) return st;
+    if ((st = ensure(c, c->lhx, sizeof(double) * (size_t)d * nh, "held-out pairs"))) return st;
+    if ((st = ensure(c, c->lht, sizeof(double) * (size_t)nh, "held-out pairs"))) return st;
+    if ((st = ensure(c, c->lhf, sizeof(float) * (size_t)nh * kMlpIn, "held-out pairs"))) return st;
+    if ((st = ensure(c, c->lhy, sizeof(float) * (size_t)nh, "held-out pairs"))) return st;
+
+    std::vector<double> mu(N, 0.0), sg(N, 1.0);
+    for (int j = 0; j < N; ++j) report[j] = qr_learn_report{0.0, 0.0, 0, 0};
+    const int db = dim_bucket(p->d, p->nbm);
+    const int cap = depth_cap(b->max_nnz);
+    const Walk W = make_walk(b->kind, b->level, b->d);
+    double *x = (double *)c->lx.p, *H = (double *)c->lh.p, *y = (double *)c->ly.p;
+    double *S = (double *)c->S.p, *u = (double *)c->u.p;
+    double2 *ai = (double2 *)c->alpha_int.p;
+    float *params = (float *)c->lparams.p;
+    const int64_t nf = 2 * b->nrep - 1;
+    for (int32_t i = N - 1; i >= 0; --i) {
+        QR_HIP(launch_sm_start(c->d_prob, i, M, seed, x, u, S, s), "sm_start_kernel");
+        for (int32_t j = i; j < N; ++j) {
+            QR_HIP(launch_sm_euler(db, c->d_prob, i, j, M, seed, x, H, s), "sm_euler_kernel");
+            if (j + 1 == N) {
+                QR_HIP(launch_sm_final(db, c->d_prob, M, x, H, S, s), "sm_final_kernel");
+            } else if (report[j + 1].used) {
+                const float *th = params + (int64_t)(j + 1) * kMlpParams;
+                for (int64_t m0 = 0; m0 < M; m0 += kMlpChunk) {
+                    const int64_t k = std::min(kMlpChunk, M - m0);
+                    QR_HIP(launch_features(d, k, x + m0, M, (float *)c->mf.p, s), "features_kernel");
+                    st = timed(c, 0, s, "mlp forward",
+                               [&] { return mlp_fwd(c, th, k, (const float *)c->mf.p, (float *)c->my.p, s); });
+                    if (st) return st;
+                    QR_HIP(launch_sm_accum(c->d_prob, j, m0, k, nullptr, (const float *)c->my.p, mu[j + 1],
+                                           sg[j + 1], H, S, s),
+                           "sm_accum_kernel");
+                }
+            } else {
+                const double2 *row = ai + (int64_t)(j + 1) * b->ld();
+                st = timed(c, 0, s, "eval_kernel", [&] { return launch_eval(cap, false, W, row, x, M, y, nullptr, s); });
+                if (st) return st;
+                QR_HIP(launch_sm_accum(c->d_prob, j, 0, M, y, nullptr, 0.0, 1.0, H, S, s), "sm_accum_kernel");
+            }
+        }
+        if ((st = project_and_reduce(c, b, u, S, M, ai + (int64_t)i * b->ld(), alpha + (int64_t)i * nf, s)))
+            return st;
+        if (i >= 1 && o->epochs > 0) {
+            if ((st = fit_surrogate(c, p, b, i, seed, o, params + (int64_t)i * kMlpParams, &mu[i], &sg[i], &report[i],
+                                    s)))
+                return st;
+        }
     }
     return QR_OK;
 }

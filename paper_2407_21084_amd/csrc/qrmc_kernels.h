@@ -96,6 +96,17 @@ hipError_t launch_reduce_batched(const double2 *partial, int32_t nsplit, int64_t
 hipError_t launch_zero(double *p, int64_t n, hipStream_t s);
 
 size_t project_lds_bytes(int32_t d, int P);
+
+// step-major path simulation (learned form); x, u SoA [d][M]
+hipError_t launch_sm_start(const DevProblem *P, int32_t i, int64_t M, uint64_t seed, double *x, double *u,
+                           double *S, hipStream_t s);
+hipError_t launch_sm_euler(int db, const DevProblem *P, int32_t i, int32_t j, int64_t M, uint64_t seed, double *x,
+                           double *H, hipStream_t s);
+hipError_t launch_sm_accum(const DevProblem *P, int32_t j, int64_t m0, int64_t n, const double *y64,
+                           const float *y32, double mu, double sigma, const double *H, double *S, hipStream_t s);
+hipError_t launch_sm_final(int db, const DevProblem *P, int64_t M, const double *x, const double *H, double *S,
+                           hipStream_t s);
+hipError_t launch_moments(int64_t n, const double *t, double *partial, hipStream_t s);
 size_t mfma_path_lds_bytes(int32_t d);
 hipError_t launch_mfma_path(int db, int cap, bool grad, int prec, const MfmaArgs &a, hipStream_t s);
 int mfma_tile_groups(int db, int d, bool grad);

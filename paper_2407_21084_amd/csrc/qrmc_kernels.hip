@@ -947,6 +947,103 @@ __global__ void pack_tiles_kernel(const double2 *__restrict__ alpha_int_row, int
 }
 
 // ---------------------------------------------------------------------------
+// Step-major path simulation (learned form).  The cloud's states live in
+// HBM and the paths advance one time step per launch, so that ybar_{j+1}
+// can be evaluated for the whole cloud at once, by the expansion
+// (eval_kernel) or by the surrogate network.  Random numbers and arithmetic
+// are those of path_kernel, step by step.
+// ---------------------------------------------------------------------------
+__global__ void sm_start_kernel(const DevProblem *__restrict__ P0, int32_t i, int64_t M, uint64_t seed,
+                                double *__restrict__ x, double *__restrict__ u, double *__restrict__ S) {
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    PhiloxStream rs(seed, 0u, (uint64_t)m, (uint32_t)i, 0u);
+    for (int l = 0; l < P0->d; ++l) {
+        const double xv = nl_logistic_icdf(rs.next());
+        x[l * M + m] = xv;
+        u[l * M + m] = nl_logistic_cdf(xv);
+    }
+    S[m] = 0.0;
+}
+
+// X_j -> X_{j+1} in place; H = h(t_j, X_j)
+template <int DB>
+__global__ void sm_euler_kernel(const DevProblem *__restrict__ P0, int32_t i, int32_t j, int64_t M,
+                                uint64_t seed, double *__restrict__ xg, double *__restrict__ H) {
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    const int d = P0->d, nbm = P0->nbm;
+    const double tj = P0->t[j], dt = P0->t[j + 1] - tj, sq = sqrt(dt);
+    double x[DB];
+#pragma unroll
+    for (int l = 0; l < DB; ++l) x[l] = (l < d) ? xg[l * M + m] : 0.0;
+    H[m] = h_source<DB>(P0, tj, x, d);
+    PhiloxStream rs(seed, 0u, (uint64_t)m, (uint32_t)i, (uint32_t)(d + (j - i) * nbm));
+#pragma unroll
+    for (int l = 0; l < DB; ++l)
+        if (l < d) x[l] = fma(fma(P0->b1[l], x[l], P0->b0[l]), dt, x[l]);
+    for (int k = 0; k < nbm; ++k) {
+        const double dwk = sq * nl_norm_icdf(rs.next());
+#pragma unroll
+        for (int l = 0; l < DB; ++l)
+            if (l < d) x[l] = fma(P0->sigma[l * nbm + k], dwk, x[l]);
+    }
+#pragma unroll
+    for (int l = 0; l < DB; ++l)
+        if (l < d) xg[l * M + m] = x[l];
+}
+
+// S += (f(T_L(y)) + H) dt with y = y64 (expansion) or mu + sigma y32
+// (surrogate), over paths [m0, m0 + n)
+__global__ void sm_accum_kernel(const DevProblem *__restrict__ P0, int32_t j, int64_t m0, int64_t n,
+                                const double *__restrict__ y64, const float *__restrict__ y32, double mu,
+                                double sigma, const double *__restrict__ H, double *__restrict__ S) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int64_t m = m0 + k;
+    const double dt = P0->t[j + 1] - P0->t[j];
+    const double y = y64 ? y64[k] : mu + sigma * (double)y32[k];
+    S[m] = fma(fnl(P0, clamp_abs(y, P0->clamp), 0.0) + H[m], dt, S[m]);
+}
+
+// the last step: y = g(X_N), then S += g(X_N)
+template <int DB>
+__global__ void sm_final_kernel(const DevProblem *__restrict__ P0, int64_t M, const double *__restrict__ xg,
+                                const double *__restrict__ H, double *__restrict__ S) {
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    const int d = P0->d, j = P0->N - 1;
+    const double dt = P0->t[j + 1] - P0->t[j];
+    double x[DB];
+#pragma unroll
+    for (int l = 0; l < DB; ++l) x[l] = (l < d) ? xg[l * M + m] : 0.0;
+    const double g = g_term<DB>(P0, x, d, nullptr);
+    const double Sj = fma(fnl(P0, clamp_abs(g, P0->clamp), 0.0) + H[m], dt, S[m]);
+    S[m] = Sj + g;
+}
+
+// first two moments of t (partials per block of 256: sum, sum of squares)
+__global__ void moments_kernel(int64_t n, const double *__restrict__ t, double *__restrict__ partial) {
+    __shared__ double ra[256], rb[256];
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const double v = p < n ? t[p] : 0.0;
+    ra[threadIdx.x] = v;
+    rb[threadIdx.x] = v * v;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            ra[threadIdx.x] += ra[threadIdx.x + o];
+            rb[threadIdx.x] += rb[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = ra[0];
+        partial[2 * blockIdx.x + 1] = rb[0];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Batched form: instances sharing the cloud.  One walk per path serves RT
 // instances: each node's value is contracted with RT coefficient pairs (one
 // scalar load of 16 RT bytes), so the complex multiply and the walk's scalar
@@ -1412,6 +1509,47 @@ hipError_t launch_pack_tiles(int prec, const double2 *alpha_int_row, int64_t nre
                            alpha_int_row, nrep, trav, d, T, ngroups, out);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+static inline unsigned sm_blocks(int64_t n) { return blocks_for(n, 256); }
+
+hipError_t launch_sm_start(const DevProblem *P, int32_t i, int64_t M, uint64_t seed, double *x, double *u,
+                           double *S, hipStream_t s) {
+    hipLaunchKernelGGL(sm_start_kernel, dim3(sm_blocks(M)), dim3(256), 0, s, P, i, M, seed, x, u, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_sm_euler(int db, const DevProblem *P, int32_t i, int32_t j, int64_t M, uint64_t seed, double *x,
+                           double *H, hipStream_t s) {
+    switch (db) {
+    case 4: hipLaunchKernelGGL(sm_euler_kernel<4>, dim3(sm_blocks(M)), dim3(256), 0, s, P, i, j, M, seed, x, H); break;
+    case 8: hipLaunchKernelGGL(sm_euler_kernel<8>, dim3(sm_blocks(M)), dim3(256), 0, s, P, i, j, M, seed, x, H); break;
+    case 16: hipLaunchKernelGGL(sm_euler_kernel<16>, dim3(sm_blocks(M)), dim3(256), 0, s, P, i, j, M, seed, x, H); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sm_accum(const DevProblem *P, int32_t j, int64_t m0, int64_t n, const double *y64,
+                           const float *y32, double mu, double sigma, const double *H, double *S, hipStream_t s) {
+    hipLaunchKernelGGL(sm_accum_kernel, dim3(sm_blocks(n)), dim3(256), 0, s, P, j, m0, n, y64, y32, mu, sigma, H, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_sm_final(int db, const DevProblem *P, int64_t M, const double *x, const double *H, double *S,
+                           hipStream_t s) {
+    switch (db) {
+    case 4: hipLaunchKernelGGL(sm_final_kernel<4>, dim3(sm_blocks(M)), dim3(256), 0, s, P, M, x, H, S); break;
+    case 8: hipLaunchKernelGGL(sm_final_kernel<8>, dim3(sm_blocks(M)), dim3(256), 0, s, P, M, x, H, S); break;
+    case 16: hipLaunchKernelGGL(sm_final_kernel<16>, dim3(sm_blocks(M)), dim3(256), 0, s, P, M, x, H, S); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(int64_t n, const double *t, double *partial, hipStream_t s) {
+    hipLaunchKernelGGL(moments_kernel, dim3(sm_blocks(n)), dim3(256), 0, s, n, t, partial);
     return hipGetLastError();
 }
 

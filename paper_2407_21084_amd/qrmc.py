@@ -20,6 +20,9 @@ LIB_PATH = os.environ.get("QRMC_LIB") or os.path.join(_HERE, "libqrmc.so")
 MAX_D = 16
 MAX_N = 128
 MAX_BATCH = 64
+MLP_IN, MLP_HIDDEN = 16, 256
+MLP_NPARAMS = MLP_HIDDEN * MLP_IN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
+MLP_MAX_BATCH = 65536
 
 SET_TENSOR, SET_HC_MAX, SET_HC_1P = 0, 1, 2
 SET_KINDS = {"tensor": SET_TENSOR, "hc_max": SET_HC_MAX, "hc_1p": SET_HC_1P}
@@ -39,7 +42,8 @@ EXPORTS = ["qr_last_error", "qr_version", "qr_build_basis", "qr_basis_info", "qr
            "qr_basis_free", "qr_ctx_create", "qr_ctx_destroy", "qr_ctx_set_timing",
            "qr_ctx_kernel_time", "qr_ctx_reset_timing", "qr_backward_step", "qr_solve", "qr_eval",
            "qr_project", "qr_path_responses", "qr_sample_points", "qr_backward_step_prec",
-           "qr_solve_prec", "qr_solve_batched",
+           "qr_solve_prec", "qr_mlp_init", "qr_mlp_features", "qr_mlp_forward", "qr_mlp_loss_grad",
+           "qr_mlp_adam", "qr_solve_learned", "qr_solve_batched",
            "qr_host_uniform", "qr_host_norm_icdf", "qr_host_philox"]
 
 
@@ -64,6 +68,18 @@ class Problem(C.Structure):
 class Instance(C.Structure):
     """One instance of a batched solve (qr_instance)."""
     _fields_ = [("f_a", C.c_double), ("d", C.c_int32), ("level", C.c_int32), ("M", C.c_int64)]
+
+
+class LearnOpts(C.Structure):
+    """Options of the learned form (qr_learn_opts)."""
+    _fields_ = [("train_points", C.c_int64), ("heldout_points", C.c_int64), ("epochs", C.c_int32),
+                ("batch", C.c_int32), ("lr", C.c_float), ("gate", C.c_double)]
+
+
+class LearnReport(C.Structure):
+    """Per-time-index outcome of the learned form (qr_learn_report)."""
+    _fields_ = [("heldout_rel_l2", C.c_double), ("train_loss", C.c_double), ("trained", C.c_int32),
+                ("used", C.c_int32)]
 
 
 if not os.path.exists(LIB_PATH):
@@ -91,6 +107,13 @@ _SIGS = {
     "qr_sample_points": (C.c_int, [_P, _I32, _U64, _U32, _I32, _I64, _I64, _P, _P]),
     "qr_backward_step_prec": (C.c_int, [_P, C.POINTER(Problem), _P, _I32, _I64, _U64, _I32, _P, _P]),
     "qr_solve_prec": (C.c_int, [_P, C.POINTER(Problem), _P, _I64, _U64, _I32, _P, _P]),
+    "qr_mlp_init": (C.c_int, [_P, _P, _U64, _P]),
+    "qr_mlp_features": (C.c_int, [_P, _I32, _I64, _P, _P, _P]),
+    "qr_mlp_forward": (C.c_int, [_P, _P, _I64, _P, _P, _P]),
+    "qr_mlp_loss_grad": (C.c_int, [_P, _P, _I64, _P, _P, _P, C.POINTER(_D), _P]),
+    "qr_mlp_adam": (C.c_int, [_P, _P, _P, _P, _P, _I64, C.c_float, _P]),
+    "qr_solve_learned": (C.c_int, [_P, C.POINTER(Problem), _P, _I64, _U64, C.POINTER(LearnOpts), _P,
+                                   C.POINTER(LearnReport), _P]),
     "qr_solve_batched": (C.c_int, [_P, C.POINTER(Problem), _P, _I32, C.POINTER(Instance), _U64, _P, _P]),
     "qr_host_uniform": (_D, [_U64, _U32, _U64, _U32, _U32]),
     "qr_host_norm_icdf": (_D, [_D]),
@@ -213,6 +236,14 @@ def _dptr(t) -> C.c_void_p:
     return C.c_void_p(t.data_ptr())
 
 
+def _fptr(t) -> C.c_void_p:
+    if t is None:
+        return C.c_void_p(0)
+    import torch
+    assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous(), "float32 contiguous device tensor expected"
+    return C.c_void_p(t.data_ptr())
+
+
 class Context:
     """qr_ctx on one device; owns the library workspace."""
 
@@ -293,3 +324,34 @@ class Context:
             arr[r].f_a, arr[r].d, arr[r].level, arr[r].M = float(f_a), int(d), int(level), int(M)
         _check(_lib.qr_solve_batched(self._h, C.byref(prob), basis.handle, R, arr, seed, _dptr(alpha),
                                      _stream_ptr(stream)))
+
+    # -- learned form ---------------------------------------------------------
+    def mlp_init(self, params, seed: int, stream=None):
+        _check(_lib.qr_mlp_init(self._h, _fptr(params), seed, _stream_ptr(stream)))
+
+    def mlp_features(self, d: int, x, feat, stream=None):
+        n = feat.shape[0]
+        _check(_lib.qr_mlp_features(self._h, d, n, _dptr(x), _fptr(feat), _stream_ptr(stream)))
+
+    def mlp_forward(self, params, feat, y, stream=None):
+        _check(_lib.qr_mlp_forward(self._h, _fptr(params), y.shape[0], _fptr(feat), _fptr(y), _stream_ptr(stream)))
+
+    def mlp_loss_grad(self, params, feat, target, grad, stream=None) -> float:
+        loss = _D()
+        _check(_lib.qr_mlp_loss_grad(self._h, _fptr(params), target.shape[0], _fptr(feat), _fptr(target),
+                                     _fptr(grad), C.byref(loss), _stream_ptr(stream)))
+        return loss.value
+
+    def mlp_adam(self, params, grad, m, v, step: int, lr: float, stream=None):
+        _check(_lib.qr_mlp_adam(self._h, _fptr(params), _fptr(grad), _fptr(m), _fptr(v), step, lr,
+                                _stream_ptr(stream)))
+
+    def solve_learned(self, prob: Problem, basis: Basis, M: int, seed: int, alpha, train_points=1 << 18,
+                      heldout_points=1 << 16, epochs=8, batch=8192, lr=1e-3, gate=1e-3, stream=None):
+        """Returns the per-time-index reports as a list of dicts."""
+        o = LearnOpts(train_points, heldout_points, epochs, batch, lr, gate)
+        rep = (LearnReport * prob.N)()
+        _check(_lib.qr_solve_learned(self._h, C.byref(prob), basis.handle, M, seed, C.byref(o), _dptr(alpha),
+                                     rep, _stream_ptr(stream)))
+        return [{"heldout_rel_l2": r.heldout_rel_l2, "train_loss": r.train_loss, "trained": bool(r.trained),
+                 "used": bool(r.used)} for r in rep]
