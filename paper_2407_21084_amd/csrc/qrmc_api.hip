@@ -62,7 +62,7 @@ struct qr_basis {
     int32_t *d_trav = nullptr;
     TaskItem *d_items = nullptr;
     Task *d_tasks = nullptr;
-    int64_t ld() const { return nrep + kRowPad; }
+    int64_t ld() const { return coef_ld(nrep); }
     // Sub-walks (same kind, d' <= d, level' <= level) built on demand for the
     // batched form and owned by this basis.  In a sub-walk, ft maps its
     // traversal index to the parent's, inv the parent's to its own (or -1).
@@ -360,7 +360,7 @@ struct qr_ctx {
     DevProblem *d_prob = nullptr;
     DevProblem h_prob{};
     bool prob_valid = false;
-    Buf S, u, alpha_int, partial, row, alpha_b, tiles;
+    Buf S, u, alpha_int, partial, row, alpha_b, tiles, xstate;
     // surrogate network workspace: activations of up to kMlpChunk rows
     Buf mf, mz1, mh1, mz2, mh2, mdz, mdh, my, mdy, mpart, mwork, mcwork;
     // learned solve: cloud state, per-step source term, expansion values,
@@ -414,7 +414,8 @@ extern "C" void qr_ctx_destroy(qr_ctx *c) {
     if (!c) return;
     hipSetDevice(c->dev);
     hipDeviceSynchronize();
-    for (Buf *b : {&c->S, &c->u, &c->alpha_int, &c->partial, &c->row, &c->alpha_b, &c->tiles, &c->mf, &c->mz1,
+    for (Buf *b : {&c->S, &c->u, &c->alpha_int, &c->partial, &c->row, &c->alpha_b, &c->tiles, &c->xstate, &c->mf,
+                   &c->mz1,
                    &c->mh1, &c->mz2, &c->mh2, &c->mdz, &c->mdh, &c->my, &c->mdy, &c->mpart, &c->mwork,
                    &c->mcwork, &c->lx, &c->lh, &c->ly, &c->lparams, &c->lgrad, &c->lm, &c->lv, &c->ltx, &c->ltt,
                    &c->ltf, &c->lff, &c->lhx, &c->lht, &c->lhf, &c->lhy})
@@ -598,7 +599,7 @@ static void split_plan(const qr_basis *b, int64_t M, int32_t *nsplit, int64_t *p
     *nsplit = (int32_t)((M + per - 1) / per);
 }
 
-static qr_status project_and_reduce(qr_ctx *c, const qr_basis *b, const double *u, const double *S,
+static qr_status project_and_reduce(qr_ctx *c, const qr_basis *b, const double2 *u, const double *S,
                                     int64_t M, double2 *alpha_int_row, double *alpha_row,
                                     hipStream_t s) {
     int32_t nsplit;
@@ -621,9 +622,14 @@ static qr_status project_and_reduce(qr_ctx *c, const qr_basis *b, const double *
 }
 
 static qr_status run_path(qr_ctx *c, const qr_problem *p, const qr_basis *b, int32_t i, int64_t M,
-                          uint64_t seed, const double2 *alpha_int, double *S, double *u, double *x0,
+                          uint64_t seed, const double2 *alpha_int, double *S, double2 *u, double *x0,
                           hipStream_t s) {
-    PathArgs a{c->d_prob, make_walk(b->kind, b->level, b->d), i, M, seed, alpha_int, b->ld(), S, u, x0};
+    const bool grad = p->driver == QR_F_ZRAT;
+    const int64_t ldx = path_state_ld(M, grad);
+    qr_status st = ensure(c, c->xstate, sizeof(double) * (size_t)p->d * ldx, "path state");
+    if (st) return st;
+    PathArgs a{c->d_prob, make_walk(b->kind, b->level, b->d), i, M, seed, alpha_int, b->ld(), S, u, x0,
+               (double *)c->xstate.p, ldx};
     return timed(c, 0, s, "path_kernel", [&] {
         return launch_path(dim_bucket(p->d, p->nbm), depth_cap(b->max_nnz), p->driver == QR_F_ZRAT,
                            a, s);
@@ -644,7 +650,7 @@ static qr_status prepare(qr_ctx *c, const qr_problem *p, qr_basis *b, int64_t M,
     if ((st = basis_on_device(b, c->dev))) return st;
     if ((st = upload_problem(c, p, (hipStream_t)stream))) return st;
     if ((st = ensure(c, c->S, sizeof(double) * (size_t)M, "S"))) return st;
-    if ((st = ensure(c, c->u, sizeof(double) * (size_t)M * p->d, "u"))) return st;
+    if ((st = ensure(c, c->u, sizeof(double2) * (size_t)M * p->d, "phase factors"))) return st;
     if ((st = ensure(c, c->alpha_int, sizeof(double2) * (size_t)p->N * b->ld(), "alpha"))) return st;
     // zero the padding columns read by the batched coefficient loads
     QR_HIP(launch_pad(p->N, b->nrep, b->ld(), (double2 *)c->alpha_int.p, (hipStream_t)stream), "pad_kernel");
@@ -665,7 +671,8 @@ extern "C" qr_status qr_backward_step(qr_ctx *c, const qr_problem *p, const qr_b
         return launch_gather(alpha, i + 1, p->N - 1 - i, b->nrep, b->ld(), nf, b->d_canon_of_trav, ai, s);
     });
     if (st) return st;
-    double *S = (double *)c->S.p, *u = (double *)c->u.p;
+    double *S = (double *)c->S.p;
+    double2 *u = (double2 *)c->u.p;
     if ((st = run_path(c, p, b, i, M, seed, ai, S, u, nullptr, s))) return st;
     return project_and_reduce(c, b, u, S, M, ai + (int64_t)i * b->ld(), alpha + (int64_t)i * nf, s);
 }
@@ -679,7 +686,8 @@ extern "C" qr_status qr_solve(qr_ctx *c, const qr_problem *p, const qr_basis *bc
     hipStream_t s = (hipStream_t)stream;
     double2 *ai = (double2 *)c->alpha_int.p;
     const int64_t nf = 2 * b->nrep - 1;
-    double *S = (double *)c->S.p, *u = (double *)c->u.p;
+    double *S = (double *)c->S.p;
+    double2 *u = (double2 *)c->u.p;
     for (int32_t i = p->N - 1; i >= 0; --i) {
         if ((st = run_path(c, p, b, i, M, seed, ai, S, u, nullptr, s))) return st;
         if ((st = project_and_reduce(c, b, u, S, M, ai + (int64_t)i * b->ld(), alpha + (int64_t)i * nf, s)))
@@ -715,11 +723,11 @@ extern "C" qr_status qr_project(qr_ctx *c, const qr_basis *bc, int64_t n, const 
     if ((st = check_M(n))) return st;
     if (!x || !s_in || !alpha_row) return fail(QR_EINVAL, "qr_project: NULL argument");
     if ((st = basis_on_device(b, c->dev))) return st;
-    if ((st = ensure(c, c->u, sizeof(double) * (size_t)n * b->d, "u"))) return st;
+    if ((st = ensure(c, c->u, sizeof(double2) * (size_t)n * b->d, "phase factors"))) return st;
     if ((st = ensure(c, c->row, sizeof(double2) * (size_t)b->ld(), "row"))) return st;
     hipStream_t s = (hipStream_t)stream;
-    double *u = (double *)c->u.p;
-    QR_HIP(launch_x_to_u(b->d, x, n, u, s), "x_to_u_kernel");
+    double2 *u = (double2 *)c->u.p;
+    QR_HIP(launch_x_to_e(b->d, x, n, u, s), "x_to_e_kernel");
     return project_and_reduce(c, b, u, s_in, n, (double2 *)c->row.p, alpha_row, s);
 }
 
@@ -796,7 +804,7 @@ static qr_status pack_row(qr_ctx *c, const qr_problem *p, const qr_basis *b, int
 static qr_status run_mfma_path(qr_ctx *c, const qr_problem *p, const qr_basis *b, int32_t prec,
                                const TilePlan &tp, int32_t i, int64_t M, uint64_t seed, hipStream_t s) {
     MfmaArgs a{c->d_prob, make_walk(b->kind, b->level, b->d), i, M, seed, (const uint2 *)c->tiles.p, tp.ld,
-               (double *)c->S.p, (double *)c->u.p};
+               (double *)c->S.p, (double2 *)c->u.p};
     return timed(c, 0, s, "mfma_path_kernel", [&] {
         return launch_mfma_path(dim_bucket(p->d, p->nbm), depth_cap(b->max_nnz), p->driver == QR_F_ZRAT, prec,
                                 a, s);
@@ -823,7 +831,7 @@ extern "C" qr_status qr_backward_step_prec(qr_ctx *c, const qr_problem *p, const
     for (int32_t r = i + 1; r < p->N; ++r)
         if ((st = pack_row(c, p, b, prec, tp, r, s))) return st;
     if ((st = run_mfma_path(c, p, b, prec, tp, i, M, seed, s))) return st;
-    return project_and_reduce(c, b, (double *)c->u.p, (double *)c->S.p, M, ai + (int64_t)i * b->ld(),
+    return project_and_reduce(c, b, (double2 *)c->u.p, (double *)c->S.p, M, ai + (int64_t)i * b->ld(),
                               alpha + (int64_t)i * nf, s);
 }
 
@@ -840,7 +848,7 @@ extern "C" qr_status qr_solve_prec(qr_ctx *c, const qr_problem *p, const qr_basi
     const int64_t nf = 2 * b->nrep - 1;
     for (int32_t i = p->N - 1; i >= 0; --i) {
         if ((st = run_mfma_path(c, p, b, prec, tp, i, M, seed, s))) return st;
-        if ((st = project_and_reduce(c, b, (double *)c->u.p, (double *)c->S.p, M, ai + (int64_t)i * b->ld(),
+        if ((st = project_and_reduce(c, b, (double2 *)c->u.p, (double *)c->S.p, M, ai + (int64_t)i * b->ld(),
                                      alpha + (int64_t)i * nf, s)))
             return st;
         if (i > 0 && (st = pack_row(c, p, b, prec, tp, i, s))) return st;
@@ -1107,7 +1115,8 @@ extern "C" qr_status qr_solve_learned(qr_ctx *c, const qr_problem *p, const qr_b
     const int cap = depth_cap(b->max_nnz);
     const Walk W = make_walk(b->kind, b->level, b->d);
     double *x = (double *)c->lx.p, *H = (double *)c->lh.p, *y = (double *)c->ly.p;
-    double *S = (double *)c->S.p, *u = (double *)c->u.p;
+    double *S = (double *)c->S.p;
+    double2 *u = (double2 *)c->u.p;
     double2 *ai = (double2 *)c->alpha_int.p;
     float *params = (float *)c->lparams.p;
     const int64_t nf = 2 * b->nrep - 1;
@@ -1222,7 +1231,7 @@ extern "C" qr_status qr_solve_batched(qr_ctx *c, const qr_problem *p, const qr_b
         if ((st = basis_on_device(sb, c->dev))) return st;
     if ((st = upload_problem(c, p, s))) return st;
     if ((st = ensure(c, c->S, sizeof(double) * (size_t)Mmax * kBatchRT, "S"))) return st;
-    if ((st = ensure(c, c->u, sizeof(double) * (size_t)Mmax * p->d, "u"))) return st;
+    if ((st = ensure(c, c->u, sizeof(double2) * (size_t)Mmax * p->d, "phase factors"))) return st;
     if ((st = ensure(c, c->alpha_b, sizeof(double2) * (size_t)total, "batch coefficients"))) return st;
     if ((st = ensure(c, c->partial, sizeof(double2) * (size_t)partial_max, "partial"))) return st;
     if (!c->d_batch) QR_HIP(hipMalloc(&c->d_batch, sizeof(DevBatch)), "hipMalloc(batch)");
@@ -1236,7 +1245,8 @@ extern "C" qr_status qr_solve_batched(qr_ctx *c, const qr_problem *p, const qr_b
 
     const int64_t nf = 2 * b->nrep - 1;
     double2 *ab = (double2 *)c->alpha_b.p;
-    double *S = (double *)c->S.p, *u = (double *)c->u.p;
+    double *S = (double *)c->S.p;
+    double2 *u = (double2 *)c->u.p;
     double2 *partial = (double2 *)c->partial.p;
     QR_HIP(launch_zero(alpha, (int64_t)R * p->N * nf, s), "zero_kernel");
     QR_HIP(launch_zero((double *)ab, 2 * total, s), "zero_kernel");

@@ -21,7 +21,9 @@ constexpr int kProjWaves = QRMC_PROJ_WAVES;  // waves per block of the projectio
 constexpr int kProjP = 2;         // paths per lane of the projection kernel (1 where LDS is short)
 constexpr int kProjChunk = QRMC_PROJ_CHUNK;  // nodes per cross-lane reduction of the projection
 constexpr int kTaskMax = QRMC_TASK_MAX;      // nodes per projection task
-constexpr int kRowPad = 16;       // coefficient rows are padded by this many pairs
+// coefficient rows (double2, traversal order) are zero-padded to whole
+// 64-node chunks plus two chunks of read-ahead
+__host__ __device__ constexpr int64_t coef_ld(int64_t nrep) { return ((nrep + 63) / 64 + 2) * 64; }
 
 constexpr int kBatchRT = 8;       // instances per pass of the batched path kernel
 
@@ -43,7 +45,8 @@ struct BatchArgs {
     uint64_t seed;
     const double2 *alpha_b;  // [N][ld][kBatchRT] of this pass
     int64_t ld;
-    double *S, *u;  // S: [kBatchRT][M] of this pass; u: [d][M]
+    double *S;   // [kBatchRT][M] of this pass
+    double2 *e;  // start-point phase factors e^{2 pi i F(x_l)}, [d][M]
 };
 
 // Reduced-precision path kernel.  The coefficient tiles of row j are at
@@ -57,7 +60,8 @@ struct MfmaArgs {
     uint64_t seed;
     const uint2 *tiles;
     int64_t tile_ld;
-    double *S, *u;
+    double *S;
+    double2 *e;  // start-point phase factors, [d][M]
 };
 
 struct PathArgs {
@@ -68,7 +72,11 @@ struct PathArgs {
     uint64_t seed;
     const double2 *alpha_int;  // [N][ld]
     int64_t ld;
-    double *S, *u, *x0;
+    double *S;
+    double2 *e;  // start-point phase factors e^{2 pi i F(x_l)}, [d][M]
+    double *x0;
+    double *xs;   // path state [d][ldx], ldx >= path_state_ld(M, grad)
+    int64_t ldx;
 };
 
 hipError_t launch_gather(const double *alpha, int32_t row0, int32_t nrows, int64_t nrep, int64_t ld,
@@ -76,7 +84,7 @@ hipError_t launch_gather(const double *alpha, int32_t row0, int32_t nrows, int64
                          hipStream_t s);
 hipError_t launch_pad(int32_t nrows, int64_t nrep, int64_t ld, double2 *alpha_int, hipStream_t s);
 hipError_t launch_path(int db, int cap, bool grad, const PathArgs &a, hipStream_t s);
-hipError_t launch_project(int cap, const Walk &W, const double *u, int64_t ldu, const double *S, int64_t M,
+hipError_t launch_project(int cap, const Walk &W, const double2 *e, int64_t lde, const double *S, int64_t M,
                           int64_t paths_per_split, int32_t ntasks, int32_t nsplit, const Task *tasks,
                           const TaskItem *items, double2 *partial, int64_t nrep, hipStream_t s);
 hipError_t launch_reduce(const double2 *partial, int32_t nsplit, int64_t nrep, double M,
@@ -84,7 +92,7 @@ hipError_t launch_reduce(const double2 *partial, int32_t nsplit, int64_t nrep, d
                          const int32_t *canon_of_trav, hipStream_t s);
 hipError_t launch_eval(int cap, bool grad, const Walk &W, const double2 *alpha_int_row,
                        const double *x, int64_t n, double *y, double *grad_out, hipStream_t s);
-hipError_t launch_x_to_u(int32_t d, const double *x, int64_t n, double *u, hipStream_t s);
+hipError_t launch_x_to_e(int32_t d, const double *x, int64_t n, double2 *e, hipStream_t s);
 hipError_t launch_sample(int32_t d, uint64_t seed, uint32_t stream_id, int32_t i, int64_t m0,
                          int64_t n, double *x, hipStream_t s);
 
@@ -98,7 +106,7 @@ hipError_t launch_zero(double *p, int64_t n, hipStream_t s);
 size_t project_lds_bytes(int32_t d, int P);
 
 // step-major path simulation (learned form); x, u SoA [d][M]
-hipError_t launch_sm_start(const DevProblem *P, int32_t i, int64_t M, uint64_t seed, double *x, double *u,
+hipError_t launch_sm_start(const DevProblem *P, int32_t i, int64_t M, uint64_t seed, double *x, double2 *e,
                            double *S, hipStream_t s);
 hipError_t launch_sm_euler(int db, const DevProblem *P, int32_t i, int32_t j, int64_t M, uint64_t seed, double *x,
                            double *H, hipStream_t s);
@@ -113,6 +121,8 @@ int mfma_tile_groups(int db, int d, bool grad);
 hipError_t launch_pack_tiles(int prec, const double2 *alpha_int_row, int64_t nrep, const int32_t *trav,
                              int32_t d, int32_t T, uint2 *out, hipStream_t s);
 size_t path_lds_bytes(int32_t d, bool grad, int P);
+// paths the path kernel's grid covers (M rounded up to whole blocks)
+int64_t path_state_ld(int64_t M, bool grad);
 int path_points(bool grad);
 
 }  // namespace qrmc

@@ -221,6 +221,54 @@ struct EvalAcc<P, true> {
     double y[P], g[P];
 };
 
+#ifndef QRMC_COEF_SCALAR
+// Coefficients arrive by vector loads, one 64-node chunk per load (lane q
+// holds the pair of node 64c + q), issued a chunk ahead of use.  When the
+// walk enters a chunk, the wave stores it to its LDS slot; each node's pair
+// is then read from there (one broadcast LDS read, requested a node ahead).
+// Vector loads and LDS reads complete in order, so the read-ahead is never
+// drained by the wait for the current pair, which is what a scalar-load
+// stream has to do on every node.
+template <int P, bool GRAD>
+struct EvalSink {
+    static constexpr bool kGrad = GRAD;
+    using Acc = EvalAcc<P, GRAD>;
+    double2 *slot;        // this wave's LDS copy of the current chunk [64]
+    const double2 *next;  // this lane's entry of the chunk after `buf`
+    double2 buf;          // this lane's entry of the next chunk
+    double2 pc;           // pair of the node about to be visited
+    int n;                // its index (wave-uniform)
+
+    __device__ __forceinline__ void init(const double2 *row, double2 *wave_slot) {
+        const int lane = __lane_id();
+        const double2 *r = row + lane;
+        slot = wave_slot;
+        slot[lane] = r[0];
+        buf = r[64];
+        next = r + 128;
+        wave_sync();
+        pc = slot[0];
+        n = 0;
+    }
+    __device__ __forceinline__ void coeff(double &cx, double &cy) const {
+        cx = pc.x;
+        cy = pc.y;
+    }
+    __device__ __forceinline__ void advance() {
+        const int nn = __builtin_amdgcn_readfirstlane(n) + 1;
+        n = nn;
+        if ((nn & 63) == 0) {
+            wave_sync();
+            slot[__lane_id()] = buf;
+            buf = *next;
+            next += 64;
+            wave_sync();
+        }
+        pc = slot[nn & 63];
+    }
+#else
+// Coefficients arrive by scalar loads, the next node's pair requested as
+// soon as the current one is consumed.
 template <int P, bool GRAD>
 struct EvalSink {
     static constexpr bool kGrad = GRAD;
@@ -228,20 +276,32 @@ struct EvalSink {
     const QR_CONST double *a;  // pair of the node about to be visited
     double nx, ny;             // its coefficients (already requested)
 
+    __device__ __forceinline__ void init(const double2 *row, double2 *) {
+        a = (const QR_CONST double *)row;
+        nx = a[0];
+        ny = a[1];
+    }
+    __device__ __forceinline__ void coeff(double &cx, double &cy) const {
+        cx = nx;
+        cy = ny;
+    }
     __device__ __forceinline__ void advance() {
         __builtin_amdgcn_sched_barrier(0);
         a += 2;
         nx = a[0];
         ny = a[1];
     }
+#endif
     __device__ __forceinline__ void node(const Pts<P> &v, Acc &acc) {
-        const double cx = nx, cy = ny;
+        double cx, cy;
+        coeff(cx, cy);
 #pragma unroll
         for (int q = 0; q < P; ++q) acc.y[q] = fma(cx, v.re[q], fma(cy, v.im[q], acc.y[q]));
         advance();
     }
     __device__ __forceinline__ void node_g(const Pts<P> &v, Acc &acc, double *gs) {
-        const double cx = nx, cy = ny;
+        double cx, cy;
+        coeff(cx, cy);
 #pragma unroll
         for (int q = 0; q < P; ++q) {
             acc.y[q] = fma(cx, v.re[q], fma(cy, v.im[q], acc.y[q]));
@@ -259,12 +319,15 @@ struct EvalSink {
     }
 };
 
-// ybar at the thread's P points (row padded by at least one pair).
+// ybar at the thread's P points.  The row is zero-padded to a whole number
+// of 64-node chunks plus two (read ahead); wave_slot is the wave's LDS chunk
+// slot (64 double2).  With vector-loaded coefficients every lane of the wave
+// must be active.
 template <int CAP, int P, bool GRAD>
-__device__ __forceinline__ void tree_eval(const double2 *alpha_row, const Walk &W, const LanePts<P> &L,
-                                          double *y) {
-    const QR_CONST double *a = (const QR_CONST double *)alpha_row;
-    EvalSink<P, GRAD> s{a, a[0], a[1]};
+__device__ __forceinline__ void tree_eval(const double2 *alpha_row, double2 *wave_slot, const Walk &W,
+                                          const LanePts<P> &L, double *y) {
+    EvalSink<P, GRAD> s;
+    s.init(alpha_row, wave_slot);
     typename EvalSink<P, GRAD>::Acc root{};
     const Pts<P> one = unit<P>();
     s.node(one, root);
@@ -327,12 +390,14 @@ __device__ __forceinline__ double clamp_abs(double y, double L) {
 // ---------------------------------------------------------------------------
 // path_kernel: P paths per thread of backward iteration i.  Thread t of
 // block b carries paths m_q = b kPathBlock P + q kPathBlock + t.
-// alpha_int rows have stride ld >= nrep + 1 double2.
+// alpha_int rows have stride ld = coef_ld(nrep) double2.
 // LDS per thread: E slots [d][P] double2, gradient slots [d][P] double
-// (GRAD), path-state slots [P][d] double.
+// (GRAD); per wave a 64-pair coefficient chunk.  The path state lives in
+// HBM (xg, [d][ldx]).
 // ---------------------------------------------------------------------------
 size_t path_lds_bytes(int32_t d, bool grad, int P) {
-    return (size_t)d * kPathBlock * P * (sizeof(double2) + sizeof(double) + (grad ? sizeof(double) : 0));
+    return (size_t)d * kPathBlock * P * (sizeof(double2) + (grad ? sizeof(double) : 0)) +
+           (size_t)(kPathBlock / 64) * 64 * sizeof(double2);
 }
 
 // Three waves per SIMD: the register budget (168 VGPRs) costs a few spills
@@ -347,17 +412,23 @@ __attribute__((amdgpu_waves_per_eu(QRMC_PATH_WAVES_PER_EU)))
 void path_kernel(
     const DevProblem *__restrict__ P0, const Walk W, const int32_t i, const int64_t M,
     const uint64_t seed, const double2 *__restrict__ alpha_int, const int64_t ld,
-    double *__restrict__ S_out, double *__restrict__ u_out, double *__restrict__ x_out) {
+    double *__restrict__ S_out, double2 *__restrict__ e_out, double *__restrict__ x_out,
+    double *__restrict__ xg, const int64_t ldx) {
     extern __shared__ double2 lds[];
     const int tid = threadIdx.x;
     const int d = P0->d, nbm = P0->nbm, N = P0->N;
     const LanePts<P> L{lds + tid,
                        GRAD ? reinterpret_cast<double *>(lds + d * P * kPathBlock) + tid : nullptr,
                        kPathBlock};
-    // path state parked in LDS while the traversal runs
-    double *xs = reinterpret_cast<double *>(lds + d * P * kPathBlock) + (GRAD ? d * P * kPathBlock : 0) + tid;
+    // coefficient chunk slot of this wave, after the per-lane slots
+    double2 *wave_slot = reinterpret_cast<double2 *>(reinterpret_cast<double *>(lds + d * P * kPathBlock) +
+                                                     (GRAD ? d * P * kPathBlock : 0)) +
+                         (tid >> 6) * 64;
 
     const int64_t base = (int64_t)blockIdx.x * kPathBlock * P + tid;
+    // path state parked in HBM ([d][ldx], this thread's points at base +
+    // q kPathBlock) while the traversal runs
+    xg += base;
     double S[P];
     // start points X_i^i = F^{-1}(U), U from stream 0 draws r = 0..d-1
 #pragma unroll
@@ -366,9 +437,9 @@ void path_kernel(
         PhiloxStream rs(seed, 0u, (uint64_t)m, (uint32_t)i, 0u);
         for (int l = 0; l < d; ++l) {
             const double x = nl_logistic_icdf(rs.next());
-            xs[(q * d + l) * kPathBlock] = x;
+            xg[l * ldx + q * kPathBlock] = x;
             if (m < M) {
-                if (u_out) u_out[l * M + m] = nl_logistic_cdf(x);
+                if (e_out) e_out[l * M + m] = nl_unit_phase(x);
                 if (x_out) x_out[l * M + m] = x;
             }
         }
@@ -389,7 +460,7 @@ void path_kernel(
             const int64_t m = base + (int64_t)q * kPathBlock;
             double x[DB];
 #pragma unroll
-            for (int l = 0; l < DB; ++l) x[l] = (l < d) ? xs[(q * d + l) * kPathBlock] : 0.0;
+            for (int l = 0; l < DB; ++l) x[l] = (l < d) ? xg[l * ldx + q * kPathBlock] : 0.0;
             // the source term only needs X_j
             hj[q] = h_source<DB>(Pj, tj, x, d);
             // Euler step, eq (markov:euler): normals r = d + (j-i) nbm + k
@@ -406,7 +477,7 @@ void path_kernel(
             }
 #pragma unroll
             for (int l = 0; l < DB; ++l)
-                if (l < d) xs[(q * d + l) * kPathBlock] = x[l];
+                if (l < d) xg[l * ldx + q * kPathBlock] = x[l];
         }
         // xs now holds X_{j+1}
         double y[P];
@@ -415,11 +486,11 @@ void path_kernel(
             for (int l = 0; l < d; ++l) {
 #pragma unroll
                 for (int q = 0; q < P; ++q) {
-                    L.set_e(l, q, nl_unit_phase(xs[(q * d + l) * kPathBlock]));
+                    L.set_e(l, q, nl_unit_phase(xg[l * ldx + q * kPathBlock]));
                     if constexpr (GRAD) L.g(l, q) = 0.0;
                 }
             }
-            tree_eval<CAP, P, GRAD>(alpha_int + (int64_t)(j + 1) * ld, W, L, y);
+            tree_eval<CAP, P, GRAD>(alpha_int + (int64_t)(j + 1) * ld, wave_slot, W, L, y);
 #pragma unroll
             for (int q = 0; q < P; ++q) {
                 z2[q] = 0.0;
@@ -429,7 +500,7 @@ void path_kernel(
                     for (int l = 0; l < DB; ++l) {
                         gx[l] = 0.0;
                         if (l < d) {
-                            const double u = nl_logistic_cdf(xs[(q * d + l) * kPathBlock]);
+                            const double u = nl_logistic_cdf(xg[l * ldx + q * kPathBlock]);
                             gx[l] = 2.0 * M_PI * L.g(l, q) * (u * (1.0 - u));
                         }
                     }
@@ -447,7 +518,7 @@ void path_kernel(
             for (int q = 0; q < P; ++q) {
                 double x[DB], gx[DB];
 #pragma unroll
-                for (int l = 0; l < DB; ++l) x[l] = (l < d) ? xs[(q * d + l) * kPathBlock] : 0.0;
+                for (int l = 0; l < DB; ++l) x[l] = (l < d) ? xg[l * ldx + q * kPathBlock] : 0.0;
                 y[q] = g_term<DB>(Pj, x, d, GRAD ? gx : nullptr);
                 z2[q] = 0.0;
                 if constexpr (GRAD) {
@@ -473,7 +544,7 @@ void path_kernel(
         const int64_t m = base + (int64_t)q * kPathBlock;
         double x[DB];
 #pragma unroll
-        for (int l = 0; l < DB; ++l) x[l] = (l < d) ? xs[(q * d + l) * kPathBlock] : 0.0;
+        for (int l = 0; l < DB; ++l) x[l] = (l < d) ? xg[l * ldx + q * kPathBlock] : 0.0;
         const double Sq = S[q] + g_term<DB>(P0, x, d, nullptr);
         if (m < M) S_out[m] = Sq;
     }
@@ -542,7 +613,7 @@ size_t project_lds_bytes(int32_t d, int P) {
 
 template <int CAP, int P>
 __global__ __launch_bounds__(kProjWaves * 64) void project_kernel(
-    const Walk W, const double *__restrict__ u_in, const int64_t ldu, const double *__restrict__ s_in,
+    const Walk W, const double2 *__restrict__ e_in, const int64_t lde, const double *__restrict__ s_in,
     const int64_t M, const int64_t paths_per_split, const Task *__restrict__ tasks,
     const TaskItem *__restrict__ items, double2 *__restrict__ partial, const int64_t nrep) {
     extern __shared__ double2 lds[];
@@ -574,7 +645,7 @@ __global__ __launch_bounds__(kProjWaves * 64) void project_kernel(
             const int64_t m = gb + q * 64 + lane;
             const bool live = m < m1;
             sink.s[q] = live ? s_in[m] : 0.0;
-            for (int l = 0; l < d; ++l) L.set_e(l, q, nl_unit_phase_u(live ? u_in[l * ldu + m] : 0.25));
+            for (int l = 0; l < d; ++l) L.set_e(l, q, live ? e_in[l * lde + m] : make_double2(1.0, 0.0));
         }
         sink.c = 0;
         sink.base = 0;
@@ -671,8 +742,9 @@ __global__ __launch_bounds__(kPathBlock) void eval_kernel(const Walk W,
                                                           double *__restrict__ grad) {
     extern __shared__ double2 lds[];
     const int tid = threadIdx.x;
-    const int64_t p = (int64_t)blockIdx.x * kPathBlock + tid;
-    if (p >= n) return;
+    const int64_t pl = (int64_t)blockIdx.x * kPathBlock + tid;
+    const bool live = pl < n;
+    const int64_t p = live ? pl : n - 1;  // every lane walks: the coefficient stream is shared by the wave
     const int d = W.d;
     const LanePts<1> L{lds + tid, GRAD ? reinterpret_cast<double *>(lds + d * kPathBlock) + tid : nullptr,
                        kPathBlock};
@@ -680,8 +752,12 @@ __global__ __launch_bounds__(kPathBlock) void eval_kernel(const Walk W,
         L.set_e(l, 0, nl_unit_phase(x[l * n + p]));
         if constexpr (GRAD) L.g(l, 0) = 0.0;
     }
+    double2 *wave_slot = reinterpret_cast<double2 *>(reinterpret_cast<double *>(lds + d * kPathBlock) +
+                                                     (GRAD ? d * kPathBlock : 0)) +
+                         (tid >> 6) * 64;
     double yv;
-    tree_eval<CAP, 1, GRAD>(alpha_int_row, W, L, &yv);
+    tree_eval<CAP, 1, GRAD>(alpha_int_row, wave_slot, W, L, &yv);
+    if (!live) return;
     y[p] = yv;
     if constexpr (GRAD) {
         for (int l = 0; l < d; ++l) {
@@ -691,10 +767,9 @@ __global__ __launch_bounds__(kPathBlock) void eval_kernel(const Walk W,
     }
 }
 
-__global__ void x_to_u_kernel(int32_t d, const double *__restrict__ x, int64_t n,
-                              double *__restrict__ u) {
+__global__ void x_to_e_kernel(int32_t d, const double *__restrict__ x, int64_t n, double2 *__restrict__ e) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx < (int64_t)d * n) u[idx] = logistic_cdf(x[idx]);
+    if (idx < (int64_t)d * n) e[idx] = nl_unit_phase(x[idx]);
 }
 
 __global__ void sample_kernel(int32_t d, uint64_t seed, uint32_t stream_id, int32_t i, int64_t m0,
@@ -796,7 +871,7 @@ template <int DB, int CAP, bool GRAD, int T, int PREC>
 __global__ __launch_bounds__(kPathBlock) void mfma_path_kernel(
     const DevProblem *__restrict__ P0, const Walk W, const int32_t i, const int64_t M,
     const uint64_t seed, const uint2 *__restrict__ tiles, const int64_t tile_ld,
-    double *__restrict__ S_out, double *__restrict__ u_out) {
+    double *__restrict__ S_out, double2 *__restrict__ e_out) {
     // T groups of 4 right-hand sides: 1 (ybar) or 1 + d <= 4 T (with gradients)
     extern __shared__ double2 lds[];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -815,7 +890,7 @@ __global__ __launch_bounds__(kPathBlock) void mfma_path_kernel(
         for (int l = 0; l < d; ++l) {
             const double x = nl_logistic_icdf(rs.next());
             xs[l * kPathBlock] = x;
-            if (u_out && m < M) u_out[l * M + m] = nl_logistic_cdf(x);
+            if (e_out && m < M) e_out[l * M + m] = nl_unit_phase(x);
         }
     }
     double S = 0.0;
@@ -954,14 +1029,14 @@ __global__ void pack_tiles_kernel(const double2 *__restrict__ alpha_int_row, int
 // are those of path_kernel, step by step.
 // ---------------------------------------------------------------------------
 __global__ void sm_start_kernel(const DevProblem *__restrict__ P0, int32_t i, int64_t M, uint64_t seed,
-                                double *__restrict__ x, double *__restrict__ u, double *__restrict__ S) {
+                                double *__restrict__ x, double2 *__restrict__ e, double *__restrict__ S) {
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= M) return;
     PhiloxStream rs(seed, 0u, (uint64_t)m, (uint32_t)i, 0u);
     for (int l = 0; l < P0->d; ++l) {
         const double xv = nl_logistic_icdf(rs.next());
         x[l * M + m] = xv;
-        u[l * M + m] = nl_logistic_cdf(xv);
+        e[l * M + m] = nl_unit_phase(xv);
     }
     S[m] = 0.0;
 }
@@ -1091,7 +1166,7 @@ __global__ __launch_bounds__(kPathBlock) void batched_path_kernel(
     const DevProblem *__restrict__ P0, const DevBatch *__restrict__ B, const int32_t pass,
     const Walk W, const int32_t i, const int64_t M, const uint64_t seed,
     const double2 *__restrict__ alpha_b, const int64_t ld, double *__restrict__ S_out,
-    double *__restrict__ u_out) {
+    double2 *__restrict__ e_out) {
     extern __shared__ double2 lds[];
     const int tid = threadIdx.x;
     const int64_t m = (int64_t)blockIdx.x * kPathBlock + tid;
@@ -1105,7 +1180,7 @@ __global__ __launch_bounds__(kPathBlock) void batched_path_kernel(
         for (int l = 0; l < d; ++l) {
             const double x = nl_logistic_icdf(rs.next());
             xs[l * kPathBlock] = x;
-            if (u_out) u_out[l * M + m] = nl_logistic_cdf(x);
+            if (e_out) e_out[l * M + m] = nl_unit_phase(x);
         }
     }
     double S[RT];
@@ -1272,6 +1347,11 @@ hipError_t launch_pad(int32_t nrows, int64_t nrep, int64_t ld, double2 *alpha_in
 
 int path_points(bool grad) { return grad ? 1 : kPathP; }
 
+int64_t path_state_ld(int64_t M, bool grad) {
+    const int64_t per = (int64_t)kPathBlock * (grad ? 1 : kPathP);
+    return (M + per - 1) / per * per;
+}
+
 template <int DB, int CAP, bool GRAD>
 static hipError_t path_t(const PathArgs &a, hipStream_t s) {
     constexpr int P = GRAD ? 1 : kPathP;
@@ -1281,7 +1361,7 @@ static hipError_t path_t(const PathArgs &a, hipStream_t s) {
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((path_kernel<DB, CAP, GRAD, P>), dim3(blocks_for(a.M, (int64_t)kPathBlock * P)),
                        dim3(kPathBlock), lds, s, a.P, a.W, a.i, a.M, a.seed, a.alpha_int, a.ld, a.S,
-                       a.u, a.x0);
+                       a.e, a.x0, a.xs, a.ldx);
     return hipGetLastError();
 }
 
@@ -1306,36 +1386,36 @@ hipError_t launch_path(int db, int cap, bool grad, const PathArgs &a, hipStream_
 }
 
 template <int CAP, int P>
-static hipError_t project_t(const Walk &W, const double *u, int64_t ldu, const double *S, int64_t M, int64_t pps,
+static hipError_t project_t(const Walk &W, const double2 *e, int64_t lde, const double *S, int64_t M, int64_t pps,
                             int32_t ntasks, int32_t nsplit, const Task *tasks,
                             const TaskItem *items, double2 *partial, int64_t nrep, hipStream_t s) {
     const size_t lds = project_lds_bytes(W.d, P);
     static size_t granted = kLdsDefault;
-    const hipError_t e = allow_lds((const void *)project_kernel<CAP, P>, lds, granted);
-    if (e != hipSuccess) return e;
+    const hipError_t err = allow_lds((const void *)project_kernel<CAP, P>, lds, granted);
+    if (err != hipSuccess) return err;
     hipLaunchKernelGGL((project_kernel<CAP, P>), dim3((unsigned)ntasks, (unsigned)nsplit),
-                       dim3(kProjWaves * 64), lds, s, W, u, ldu, S, M, pps, tasks, items, partial, nrep);
+                       dim3(kProjWaves * 64), lds, s, W, e, lde, S, M, pps, tasks, items, partial, nrep);
     return hipGetLastError();
 }
 
 template <int CAP>
-static hipError_t project_p(const Walk &W, const double *u, int64_t ldu, const double *S, int64_t M, int64_t pps,
+static hipError_t project_p(const Walk &W, const double2 *e, int64_t lde, const double *S, int64_t M, int64_t pps,
                             int32_t ntasks, int32_t nsplit, const Task *tasks,
                             const TaskItem *items, double2 *partial, int64_t nrep, hipStream_t s) {
     // two paths per lane while their phase factors fit in LDS
     if (project_lds_bytes(W.d, kProjP) <= kLdsMax)
-        return project_t<CAP, kProjP>(W, u, ldu, S, M, pps, ntasks, nsplit, tasks, items, partial, nrep, s);
-    return project_t<CAP, 1>(W, u, ldu, S, M, pps, ntasks, nsplit, tasks, items, partial, nrep, s);
+        return project_t<CAP, kProjP>(W, e, lde, S, M, pps, ntasks, nsplit, tasks, items, partial, nrep, s);
+    return project_t<CAP, 1>(W, e, lde, S, M, pps, ntasks, nsplit, tasks, items, partial, nrep, s);
 }
 
-hipError_t launch_project(int cap, const Walk &W, const double *u, int64_t ldu, const double *S, int64_t M,
+hipError_t launch_project(int cap, const Walk &W, const double2 *e, int64_t lde, const double *S, int64_t M,
                           int64_t paths_per_split, int32_t ntasks, int32_t nsplit, const Task *tasks,
                           const TaskItem *items, double2 *partial, int64_t nrep, hipStream_t s) {
     switch (cap) {
-    case 2: return project_p<2>(W, u, ldu, S, M, paths_per_split, ntasks, nsplit, tasks, items, partial, nrep, s);
-    case 4: return project_p<4>(W, u, ldu, S, M, paths_per_split, ntasks, nsplit, tasks, items, partial, nrep, s);
-    case 6: return project_p<6>(W, u, ldu, S, M, paths_per_split, ntasks, nsplit, tasks, items, partial, nrep, s);
-    case 8: return project_p<8>(W, u, ldu, S, M, paths_per_split, ntasks, nsplit, tasks, items, partial, nrep, s);
+    case 2: return project_p<2>(W, e, lde, S, M, paths_per_split, ntasks, nsplit, tasks, items, partial, nrep, s);
+    case 4: return project_p<4>(W, e, lde, S, M, paths_per_split, ntasks, nsplit, tasks, items, partial, nrep, s);
+    case 6: return project_p<6>(W, e, lde, S, M, paths_per_split, ntasks, nsplit, tasks, items, partial, nrep, s);
+    case 8: return project_p<8>(W, e, lde, S, M, paths_per_split, ntasks, nsplit, tasks, items, partial, nrep, s);
     }
     return hipErrorInvalidValue;
 }
@@ -1351,7 +1431,8 @@ hipError_t launch_reduce(const double2 *partial, int32_t nsplit, int64_t nrep, d
 template <int CAP, bool GRAD>
 static hipError_t eval_t(const Walk &W, const double2 *a, const double *x, int64_t n, double *y,
                          double *g, hipStream_t s) {
-    const size_t lds = (size_t)W.d * kPathBlock * (sizeof(double2) + (GRAD ? sizeof(double) : 0));
+    const size_t lds = (size_t)W.d * kPathBlock * (sizeof(double2) + (GRAD ? sizeof(double) : 0)) +
+                       (size_t)(kPathBlock / 64) * 64 * sizeof(double2);
     hipLaunchKernelGGL((eval_kernel<CAP, GRAD>), dim3(blocks_for(n, kPathBlock)), dim3(kPathBlock),
                        lds, s, W, a, x, n, y, g);
     return hipGetLastError();
@@ -1374,10 +1455,9 @@ hipError_t launch_eval(int cap, bool grad, const Walk &W, const double2 *alpha_i
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_x_to_u(int32_t d, const double *x, int64_t n, double *u, hipStream_t s) {
+hipError_t launch_x_to_e(int32_t d, const double *x, int64_t n, double2 *e, hipStream_t s) {
     const int64_t total = (int64_t)d * n;
-    if (total == 0) return hipSuccess;
-    hipLaunchKernelGGL(x_to_u_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, s, d, x, n, u);
+    hipLaunchKernelGGL(x_to_e_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, s, d, x, n, e);
     return hipGetLastError();
 }
 
@@ -1398,7 +1478,7 @@ static hipError_t batched_t(const BatchArgs &a, hipStream_t s) {
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((batched_path_kernel<DB, CAP, kBatchRT>), dim3(blocks_for(a.M, kPathBlock)),
                        dim3(kPathBlock), lds, s, a.P, a.B, a.pass, a.W, a.i, a.M, a.seed, a.alpha_b,
-                       a.ld, a.S, a.u);
+                       a.ld, a.S, a.e);
     return hipGetLastError();
 }
 
@@ -1444,7 +1524,7 @@ static hipError_t mfma_path_t(const MfmaArgs &a, hipStream_t s) {
     const hipError_t e = allow_lds((const void *)mfma_path_kernel<DB, CAP, GRAD, T, PREC>, lds, granted);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((mfma_path_kernel<DB, CAP, GRAD, T, PREC>), dim3(blocks_for(a.M, kPathBlock)),
-                       dim3(kPathBlock), lds, s, a.P, a.W, a.i, a.M, a.seed, a.tiles, a.tile_ld, a.S, a.u);
+                       dim3(kPathBlock), lds, s, a.P, a.W, a.i, a.M, a.seed, a.tiles, a.tile_ld, a.S, a.e);
     return hipGetLastError();
 }
 
@@ -1514,9 +1594,9 @@ hipError_t launch_pack_tiles(int prec, const double2 *alpha_int_row, int64_t nre
 
 static inline unsigned sm_blocks(int64_t n) { return blocks_for(n, 256); }
 
-hipError_t launch_sm_start(const DevProblem *P, int32_t i, int64_t M, uint64_t seed, double *x, double *u,
+hipError_t launch_sm_start(const DevProblem *P, int32_t i, int64_t M, uint64_t seed, double *x, double2 *e,
                            double *S, hipStream_t s) {
-    hipLaunchKernelGGL(sm_start_kernel, dim3(sm_blocks(M)), dim3(256), 0, s, P, i, M, seed, x, u, S);
+    hipLaunchKernelGGL(sm_start_kernel, dim3(sm_blocks(M)), dim3(256), 0, s, P, i, M, seed, x, e, S);
     return hipGetLastError();
 }
 

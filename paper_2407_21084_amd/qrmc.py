@@ -85,6 +85,12 @@ class LearnReport(C.Structure):
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: run paper_2407_21084_amd/build.py (hipcc, gfx950)")
 
+# torch ships its own HIP runtime.  Loading it first makes the library bind
+# to that same runtime (one device context per process, shared streams and
+# allocations); loaded the other way round, two runtimes would compete for
+# the device.
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIB_PATH)
 _P, _I32, _I64, _U64, _U32, _D = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_uint32, C.c_double
 _SIGS = {
