@@ -1194,32 +1194,45 @@ extern "C" qr_status qr_solve_batched(qr_ctx *c, const qr_problem *p, const qr_b
     }
     hipStream_t s = (hipStream_t)stream;
 
-    // Passes of kBatchRT instances with similar index sets and cloud sizes.
-    std::vector<int32_t> order(R);
-    for (int r = 0; r < R; ++r) order[r] = r;
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t q) {
-        if (inst[a].level != inst[q].level) return inst[a].level > inst[q].level;
-        if (inst[a].d != inst[q].d) return inst[a].d > inst[q].d;
-        return inst[a].M > inst[q].M;
-    });
-    const int npass = (R + kBatchRT - 1) / kBatchRT;
-    std::vector<PassPlan> passes(npass);
+    // Passes of up to kBatchRT instances.  A pass walks the set of its first
+    // member and simulates its cloud, so the cost of a pass is set by its
+    // first member; greedily, the costliest remaining instance opens a pass
+    // and takes along the costliest others that fit inside its envelope
+    // (d, level and M no larger), which ride at no extra walk cost.
     std::vector<qr_basis *> own(R);
-    int64_t total = 0, partial_max = 0;
-    for (int ps = 0; ps < npass; ++ps) {
-        PassPlan &P = passes[ps];
-        for (int k = ps * kBatchRT; k < std::min(R, (ps + 1) * kBatchRT); ++k) {
-            const qr_instance &I = inst[order[k]];
-            P.members.push_back(order[k]);
-            P.d = std::max(P.d, I.d);
-            P.level = std::max(P.level, I.level);
-            P.M = std::max(P.M, I.M);
+    std::vector<double> cost(R);
+    for (int r = 0; r < R; ++r) {
+        if ((st = sub_basis(b, inst[r].d, inst[r].level, &own[r]))) return st;
+        cost[r] = (double)inst[r].M * (double)own[r]->nrep;
+    }
+    std::vector<int32_t> rem(R);
+    for (int r = 0; r < R; ++r) rem[r] = r;
+    std::stable_sort(rem.begin(), rem.end(), [&](int32_t a, int32_t q) { return cost[a] > cost[q]; });
+    std::vector<PassPlan> passes;
+    while (!rem.empty()) {
+        PassPlan P;
+        const qr_instance &H = inst[rem[0]];
+        P.d = H.d;
+        P.level = H.level;
+        P.M = H.M;
+        std::vector<int32_t> left;
+        for (int32_t r : rem) {
+            const qr_instance &I = inst[r];
+            if ((int)P.members.size() < kBatchRT && I.d <= P.d && I.level <= P.level && I.M <= P.M)
+                P.members.push_back(r);
+            else
+                left.push_back(r);
         }
+        rem.swap(left);
+        passes.push_back(std::move(P));
+    }
+    const int npass = (int)passes.size();
+    int64_t total = 0, partial_max = 0;
+    for (PassPlan &P : passes) {
         if ((st = sub_basis(b, P.d, P.level, &P.walk))) return st;
         P.off = total;
         total += (int64_t)p->N * P.walk->ld() * kBatchRT;
         for (int32_t r : P.members) {
-            if ((st = sub_basis(b, inst[r].d, inst[r].level, &own[r]))) return st;
             int32_t nsplit;
             int64_t pps;
             split_plan(own[r], inst[r].M, &nsplit, &pps);
@@ -1238,8 +1251,11 @@ extern "C" qr_status qr_solve_batched(qr_ctx *c, const qr_problem *p, const qr_b
 
     // instance parameters in pass-slot order; queued kernels may read the old ones
     DevBatch hb{};
-    hb.R = R;
-    for (int k = 0; k < R; ++k) hb.f_a[k] = inst[order[k]].f_a;
+    for (int ps = 0; ps < npass; ++ps) {
+        hb.count[ps] = (int32_t)passes[ps].members.size();
+        for (size_t k = 0; k < passes[ps].members.size(); ++k)
+            hb.f_a[ps * kBatchRT + k] = inst[passes[ps].members[k]].f_a;
+    }
     QR_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
     QR_HIP(hipMemcpy(c->d_batch, &hb, sizeof hb, hipMemcpyHostToDevice), "hipMemcpy(batch)");
 

@@ -27,11 +27,11 @@ __host__ __device__ constexpr int64_t coef_ld(int64_t nrep) { return ((nrep + 63
 
 constexpr int kBatchRT = 8;       // instances per pass of the batched path kernel
 
-// Per-instance parameters of a batch (device memory, one per context).
+// Per-pass parameters of a batch (device memory, one per context): members
+// per pass and the driver parameter of slot k of pass p at f_a[p kBatchRT + k].
 struct DevBatch {
-    int32_t R;
-    int32_t pad;
-    double f_a[QR_MAX_BATCH + kBatchRT];
+    int32_t count[QR_MAX_BATCH];
+    double f_a[QR_MAX_BATCH * kBatchRT];
 };
 
 struct BatchArgs {

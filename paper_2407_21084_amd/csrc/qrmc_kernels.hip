@@ -1125,27 +1125,54 @@ __global__ void moments_kernel(int64_t n, const double *__restrict__ t, double *
 // control are shared by the RT instances.  Instance coefficients of a pass
 // are interleaved per node: row[node][RT] double2.
 // ---------------------------------------------------------------------------
+// The pass's coefficient stream (RT pairs per node, 16 RT bytes) arrives in
+// chunks of kLoads x 1 KB (kLoads 16-byte vector loads per lane) requested a
+// chunk ahead (vector loads complete in order); when the walk enters a chunk
+// the wave parks it in its LDS slot, and each node's RT pairs are broadcast
+// LDS reads.
 template <int RT>
 struct BatchSink {
     static constexpr bool kGrad = false;
-    struct Acc {};             // sums live in the sink: a value-only walk needs no per-level partials
-    const QR_CONST double *a;  // pairs of the node about to be visited
-    double nx[RT], ny[RT];
+    struct Acc {};
+    static constexpr int kLoads = 4;
+    static constexpr int kNodes = kLoads * 64 / RT;  // nodes per chunk
+    double2 *slot;        // this wave's copy of the current chunk [kNodes][RT]
+    const double2 *next;  // this lane's part of the chunk after `buf`
+    double2 buf[kLoads];  // this lane's part of the next chunk
+    int n;                // node about to be visited (wave-uniform)
     double y[RT];
 
-    __device__ __forceinline__ void load() {
+    __device__ __forceinline__ void init(const double2 *row, double2 *wave_slot) {
+        const double2 *r = row + __lane_id();
+        slot = wave_slot;
 #pragma unroll
-        for (int r = 0; r < RT; ++r) {
-            nx[r] = a[2 * r];
-            ny[r] = a[2 * r + 1];
-        }
+        for (int k = 0; k < kLoads; ++k) slot[k * 64 + __lane_id()] = r[k * 64];
+#pragma unroll
+        for (int k = 0; k < kLoads; ++k) buf[k] = r[(kLoads + k) * 64];
+        next = r + 2 * kLoads * 64;
+        n = 0;
+        wave_sync();
+#pragma unroll
+        for (int k = 0; k < RT; ++k) y[k] = 0.0;
     }
     __device__ __forceinline__ void node(const Pts<1> &v, Acc &) {
+        const int nu = __builtin_amdgcn_readfirstlane(n);
+        const double2 *p = slot + (nu % kNodes) * RT;
 #pragma unroll
-        for (int r = 0; r < RT; ++r) y[r] = fma(nx[r], v.re[0], fma(ny[r], v.im[0], y[r]));
-        __builtin_amdgcn_sched_barrier(0);
-        a += 2 * RT;
-        load();
+        for (int r = 0; r < RT; ++r) {
+            const double2 c = p[r];
+            y[r] = fma(c.x, v.re[0], fma(c.y, v.im[0], y[r]));
+        }
+        n = nu + 1;
+        if ((nu + 1) % kNodes == 0) {
+            wave_sync();
+#pragma unroll
+            for (int k = 0; k < kLoads; ++k) slot[k * 64 + __lane_id()] = buf[k];
+#pragma unroll
+            for (int k = 0; k < kLoads; ++k) buf[k] = next[k * 64];
+            next += kLoads * 64;
+            wave_sync();
+        }
     }
     __device__ __forceinline__ static void add(Acc &, const Acc &) {}
 };
@@ -1169,18 +1196,21 @@ __global__ __launch_bounds__(kPathBlock) void batched_path_kernel(
     double2 *__restrict__ e_out) {
     extern __shared__ double2 lds[];
     const int tid = threadIdx.x;
+    // paths past M run on and are not stored: every lane takes part in the
+    // wave's coefficient stream
     const int64_t m = (int64_t)blockIdx.x * kPathBlock + tid;
-    if (m >= M) return;  // no block-level synchronisation below: LDS slots are per lane
     const int d = P0->d, nbm = P0->nbm, N = P0->N;
     const LanePts<1> L{lds + tid, nullptr, kPathBlock};
     double *xs = reinterpret_cast<double *>(lds + d * kPathBlock) + tid;
+    double2 *wave_slot = reinterpret_cast<double2 *>(reinterpret_cast<double *>(lds + d * kPathBlock) + d * kPathBlock) +
+                         (tid >> 6) * (BatchSink<RT>::kLoads * 64);
 
     {
         PhiloxStream rs(seed, 0u, (uint64_t)m, (uint32_t)i, 0u);
         for (int l = 0; l < d; ++l) {
             const double x = nl_logistic_icdf(rs.next());
             xs[l * kPathBlock] = x;
-            if (e_out) e_out[l * M + m] = nl_unit_phase(x);
+            if (e_out && m < M) e_out[l * M + m] = nl_unit_phase(x);
         }
     }
     double S[RT];
@@ -1233,10 +1263,7 @@ __global__ __launch_bounds__(kPathBlock) void batched_path_kernel(
         if (j + 1 < N) {
             for (int l = 0; l < W.d; ++l) L.set_e(l, 0, nl_unit_phase(xs[l * kPathBlock]));
             BatchSink<RT> sink;
-            sink.a = (const QR_CONST double *)(alpha_b + (int64_t)(j + 1) * ld * RT);
-#pragma unroll
-            for (int r = 0; r < RT; ++r) sink.y[r] = 0.0;
-            sink.load();
+            sink.init(alpha_b + (int64_t)(j + 1) * ld * RT, wave_slot);
             typename BatchSink<RT>::Acc none{};
             const Pts<1> one = unit<1>();
             sink.node(one, none);
@@ -1265,10 +1292,10 @@ __global__ __launch_bounds__(kPathBlock) void batched_path_kernel(
 #pragma unroll
     for (int l = 0; l < DB; ++l) x[l] = (l < d) ? xs[l * kPathBlock] : 0.0;
     const double g = g_term<DB>(P0, x, d, nullptr);
-    const int R = B->R;
+    const int cnt = B->count[pass];
 #pragma unroll
     for (int r = 0; r < RT; ++r)
-        if (pass * RT + r < R) S_out[(int64_t)r * M + m] = S[r] + g;
+        if (r < cnt && m < M) S_out[(int64_t)r * M + m] = S[r] + g;
 }
 
 // Row i of one instance from its slice partial sums.  The instance's own
@@ -1472,7 +1499,8 @@ hipError_t launch_sample(int32_t d, uint64_t seed, uint32_t stream_id, int32_t i
 
 template <int DB, int CAP>
 static hipError_t batched_t(const BatchArgs &a, hipStream_t s) {
-    const size_t lds = (size_t)a.d * kPathBlock * (sizeof(double2) + sizeof(double));
+    const size_t lds = (size_t)a.d * kPathBlock * (sizeof(double2) + sizeof(double)) +
+                       (size_t)(kPathBlock / 64) * BatchSink<kBatchRT>::kLoads * 64 * sizeof(double2);
     static size_t granted = kLdsDefault;
     const hipError_t e = allow_lds((const void *)batched_path_kernel<DB, CAP, kBatchRT>, lds, granted);
     if (e != hipSuccess) return e;
