@@ -75,6 +75,82 @@ def cpu_baseline(w, target_s: float):
 
 
 BATCHED = "batched-256"
+LEARNED = "learned-d16"
+
+
+def run_learned(args, torch, W, Q):
+    """The learned form on the d=16 workload (prod(1+|k_l|) <= 32, 599,969
+    functions, Allen-Cahn driver) at a reduced cloud (--M, default 2^16):
+    the plain FP64 solve, the learned solve (surrogate per time index,
+    gate 1e-3), and the cost of one evaluation of ybar by the expansion and
+    by the network on 2^20 points."""
+    dev = torch.device("cuda:0")
+    w = W.CFG5.with_(M=args.M or (1 << 16))
+    ctx = Q.Context(0)
+    b = Q.Basis(w.d, w.set_kind, w.level)
+    prob = Q.problem_from(w)
+    stream = torch.cuda.current_stream()
+    n_test = 1 << 16
+    xt = torch.empty((w.d, n_test), dtype=torch.float64, device=dev)
+    ctx.sample_points(w.d, w.seed, 1, 0, n_test, xt, stream=stream)
+    wv = torch.tensor(w.sol_w, dtype=torch.float64, device=dev)
+    u0 = w.sol_A * math.exp(-w.sol_c * w.T) * torch.cos(wv @ xt + w.sol_p)
+
+    def rel_err(a):
+        yt = torch.empty(n_test, dtype=torch.float64, device=dev)
+        ctx.eval(b, a[0].contiguous(), xt, yt, stream=stream)
+        return float(torch.linalg.norm(yt - u0) / torch.linalg.norm(u0))
+
+    a64 = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.solve(prob, b, w.M, w.seed, a64, stream)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    print(f"[bench] plain solve {t_plain:.1f} s", file=sys.stderr, flush=True)
+    al = torch.zeros_like(a64)
+    t0 = time.perf_counter()
+    rep = ctx.solve_learned(prob, b, w.M, w.seed, al, stream=stream)
+    torch.cuda.synchronize()
+    t_learned = time.perf_counter() - t0
+    print(f"[bench] learned solve {t_learned:.1f} s", file=sys.stderr, flush=True)
+    # cost of one evaluation of ybar_j at 2^20 points: expansion vs network
+    n = 1 << 20
+    x = torch.empty((w.d, n), dtype=torch.float64, device=dev)
+    ctx.sample_points(w.d, w.seed, 1, 1, n, x, stream=stream)
+    y = torch.empty(n, dtype=torch.float64, device=dev)
+    feat = torch.empty((n, 16), dtype=torch.float32, device=dev)
+    y32 = torch.empty(n, dtype=torch.float32, device=dev)
+    th = torch.empty(Q.MLP_NPARAMS, dtype=torch.float32, device=dev)
+    ctx.mlp_init(th, 1, stream=stream)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ctx.eval(b, a64[1].contiguous(), x, y, stream=stream)            # warm
+    ctx.mlp_features(w.d, x, feat, stream=stream)
+    ctx.mlp_forward(th, feat, y32, stream=stream)
+    ev[0].record(stream)
+    ctx.eval(b, a64[1].contiguous(), x, y, stream=stream)
+    ev[1].record(stream)
+    ctx.mlp_features(w.d, x, feat, stream=stream)
+    ctx.mlp_forward(th, feat, y32, stream=stream)
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    t_exp, t_net = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+    line = {
+        "metric": "full-solve time, learned form vs plain FP64 (d=16, reduced cloud)",
+        "value": t_learned, "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": t_learned * 1e3, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64+bf16", "data": "synthetic",
+        "config": {"workload": LEARNED, "d": w.d, "N": w.N, "n_funcs": b.n_funcs, "M": w.M,
+                   "train_points": 1 << 18, "heldout_points": 1 << 16, "epochs": 8, "gate": 1e-3},
+        "plain_solve_s": t_plain, "learned_solve_s": t_learned,
+        "rel_l2_t0": {"plain": rel_err(a64), "learned": rel_err(al)},
+        "surrogates_used": sum(r["used"] for r in rep),
+        "heldout_rel_l2": {"min": min(r["heldout_rel_l2"] for r in rep[1:]),
+                           "max": max(r["heldout_rel_l2"] for r in rep[1:])},
+        "eval_2p20_points_ms": {"expansion": t_exp, "network": t_net, "ratio": t_exp / t_net},
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
 
 
 def run_batched(args, torch, W, Q):
@@ -161,6 +237,9 @@ def main():
     import workloads as W
     from paper_2407_21084_amd import qrmc as Q
 
+    if args.workload == LEARNED:
+        run_learned(args, torch, W, Q)
+        return
     if args.workload == BATCHED:
         if args.precision != "f64":
             sys.exit("the batched form runs in FP64")

@@ -212,10 +212,11 @@ __device__ __forceinline__ void visit_from(int depth, const Pts<P, R> &v, int p,
 // as soon as the current one is consumed, so the scalar load overlaps the
 // next node's complex multiply.
 // ---------------------------------------------------------------------------
+// Value-only walks keep one running sum in the sink (no per-level partial
+// sums live across the recursion); with gradients each level returns its
+// subtree's value and gradient sums, which the gradient chain needs.
 template <int P, bool GRAD>
-struct EvalAcc {
-    double y[P];
-};
+struct EvalAcc {};
 template <int P>
 struct EvalAcc<P, true> {
     double y[P], g[P];
@@ -292,11 +293,18 @@ struct EvalSink {
         ny = a[1];
     }
 #endif
+    double ysum[P];  // value-only walks: the running sum
+
     __device__ __forceinline__ void node(const Pts<P> &v, Acc &acc) {
         double cx, cy;
         coeff(cx, cy);
 #pragma unroll
-        for (int q = 0; q < P; ++q) acc.y[q] = fma(cx, v.re[q], fma(cy, v.im[q], acc.y[q]));
+        for (int q = 0; q < P; ++q) {
+            if constexpr (GRAD)
+                acc.y[q] = fma(cx, v.re[q], fma(cy, v.im[q], acc.y[q]));
+            else
+                ysum[q] = fma(cx, v.re[q], fma(cy, v.im[q], ysum[q]));
+        }
         advance();
     }
     __device__ __forceinline__ void node_g(const Pts<P> &v, Acc &acc, double *gs) {
@@ -311,10 +319,12 @@ struct EvalSink {
         advance();
     }
     __device__ __forceinline__ static void add(Acc &x, const Acc &y) {
+        if constexpr (GRAD) {
 #pragma unroll
-        for (int q = 0; q < P; ++q) {
-            x.y[q] += y.y[q];
-            if constexpr (GRAD) x.g[q] += y.g[q];
+            for (int q = 0; q < P; ++q) {
+                x.y[q] += y.y[q];
+                x.g[q] += y.g[q];
+            }
         }
     }
 };
@@ -328,12 +338,19 @@ __device__ __forceinline__ void tree_eval(const double2 *alpha_row, double2 *wav
                                           const LanePts<P> &L, double *y) {
     EvalSink<P, GRAD> s;
     s.init(alpha_row, wave_slot);
+#pragma unroll
+    for (int q = 0; q < P; ++q) s.ysum[q] = 0.0;
     typename EvalSink<P, GRAD>::Acc root{};
     const Pts<P> one = unit<P>();
     s.node(one, root);
     const auto acc = visit<0, CAP, P>(one, -1, 1, W, L, s);
 #pragma unroll
-    for (int q = 0; q < P; ++q) y[q] = root.y[q] + acc.y[q];
+    for (int q = 0; q < P; ++q) {
+        if constexpr (GRAD)
+            y[q] = root.y[q] + acc.y[q];
+        else
+            y[q] = s.ysum[q];
+    }
 }
 
 // ---------------------------------------------------------------------------
