@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--precision", default="f64", choices=["f64", "bf16", "f16"],
                     help="arithmetic of the expansion evaluation along the paths")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=30.0)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device copy of this size (for counter scaling)")
     return ap.parse_args()

@@ -9,7 +9,7 @@ constexpr int kPathBlock = 128;   // threads per block of the path / eval kernel
 constexpr int kPathP = 2;         // paths per thread of the value-only path kernel
 // Projection shape (compile-time tunables).
 #ifndef QRMC_PROJ_WAVES
-#define QRMC_PROJ_WAVES 4
+#define QRMC_PROJ_WAVES 8
 #endif
 #ifndef QRMC_PROJ_CHUNK
 #define QRMC_PROJ_CHUNK 4
@@ -103,7 +103,7 @@ hipError_t launch_reduce_batched(const double2 *partial, int32_t nsplit, int64_t
                                  double *alpha_row, hipStream_t s);
 hipError_t launch_zero(double *p, int64_t n, hipStream_t s);
 
-size_t project_lds_bytes(int32_t d, int P);
+size_t project_lds_bytes(int32_t d, int P, int waves);
 
 // step-major path simulation (learned form); x, u SoA [d][M]
 hipError_t launch_sm_start(const DevProblem *P, int32_t i, int64_t M, uint64_t seed, double *x, double2 *e,

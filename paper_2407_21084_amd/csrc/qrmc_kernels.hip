@@ -622,14 +622,14 @@ struct ProjSink {
     }
 };
 
-size_t project_lds_bytes(int32_t d, int P) {
-    return (size_t)kProjWaves *
+size_t project_lds_bytes(int32_t d, int P, int waves) {
+    return (size_t)waves *
            ((size_t)64 * (kProjChunk + 1) * sizeof(double2) + (size_t)kTaskMax * sizeof(double2) +
             (size_t)d * 64 * P * sizeof(double2));
 }
 
-template <int CAP, int P>
-__global__ __launch_bounds__(kProjWaves * 64) void project_kernel(
+template <int CAP, int P, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void project_kernel(
     const Walk W, const double2 *__restrict__ e_in, const int64_t lde, const double *__restrict__ s_in,
     const int64_t M, const int64_t paths_per_split, const Task *__restrict__ tasks,
     const TaskItem *__restrict__ items, double2 *__restrict__ partial, const int64_t nrep) {
@@ -637,8 +637,8 @@ __global__ __launch_bounds__(kProjWaves * 64) void project_kernel(
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int d = W.d;
     double2 *bufs = lds;
-    double *accs = reinterpret_cast<double *>(lds + kProjWaves * 64 * (kProjChunk + 1));
-    double2 *Es = lds + kProjWaves * 64 * (kProjChunk + 1) + kProjWaves * kTaskMax;
+    double *accs = reinterpret_cast<double *>(lds + WAVES * 64 * (kProjChunk + 1));
+    double2 *Es = lds + WAVES * 64 * (kProjChunk + 1) + WAVES * kTaskMax;
 
     double2 *wbuf = bufs + wave * 64 * (kProjChunk + 1);
     double *acc = accs + wave * kTaskMax * 2;
@@ -656,7 +656,7 @@ __global__ __launch_bounds__(kProjWaves * 64) void project_kernel(
     sink.wbuf = wbuf;
     sink.acc = acc;
     sink.lane = lane;
-    for (int64_t gb = m0 + wave * 64 * P; gb < m1; gb += kProjWaves * 64 * P) {
+    for (int64_t gb = m0 + wave * 64 * P; gb < m1; gb += WAVES * 64 * P) {
 #pragma unroll
         for (int q = 0; q < P; ++q) {
             const int64_t m = gb + q * 64 + lane;
@@ -687,10 +687,10 @@ __global__ __launch_bounds__(kProjWaves * 64) void project_kernel(
     }
     __syncthreads();
     double *out = reinterpret_cast<double *>(partial + (int64_t)blockIdx.y * nrep + task.rep_begin);
-    for (int r = tid; r < task.rep_count * 2; r += kProjWaves * 64) {
+    for (int r = tid; r < task.rep_count * 2; r += WAVES * 64) {
         double sacc = 0.0;
 #pragma unroll
-        for (int w = 0; w < kProjWaves; ++w) sacc += accs[w * kTaskMax * 2 + r];
+        for (int w = 0; w < WAVES; ++w) sacc += accs[w * kTaskMax * 2 + r];
         out[r] = sacc;
     }
 }
@@ -1429,27 +1429,31 @@ hipError_t launch_path(int db, int cap, bool grad, const PathArgs &a, hipStream_
     return hipErrorInvalidValue;
 }
 
-template <int CAP, int P>
+template <int CAP, int P, int WAVES>
 static hipError_t project_t(const Walk &W, const double2 *e, int64_t lde, const double *S, int64_t M, int64_t pps,
                             int32_t ntasks, int32_t nsplit, const Task *tasks,
                             const TaskItem *items, double2 *partial, int64_t nrep, hipStream_t s) {
-    const size_t lds = project_lds_bytes(W.d, P);
+    const size_t lds = project_lds_bytes(W.d, P, WAVES);
     static size_t granted = kLdsDefault;
-    const hipError_t err = allow_lds((const void *)project_kernel<CAP, P>, lds, granted);
+    const hipError_t err = allow_lds((const void *)project_kernel<CAP, P, WAVES>, lds, granted);
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL((project_kernel<CAP, P>), dim3((unsigned)ntasks, (unsigned)nsplit),
-                       dim3(kProjWaves * 64), lds, s, W, e, lde, S, M, pps, tasks, items, partial, nrep);
+    hipLaunchKernelGGL((project_kernel<CAP, P, WAVES>), dim3((unsigned)ntasks, (unsigned)nsplit),
+                       dim3(WAVES * 64), lds, s, W, e, lde, S, M, pps, tasks, items, partial, nrep);
     return hipGetLastError();
 }
 
+// The widest shape whose LDS fits: kProjWaves waves with two paths per lane
+// (small d), then half the waves, then one path per lane.
 template <int CAP>
 static hipError_t project_p(const Walk &W, const double2 *e, int64_t lde, const double *S, int64_t M, int64_t pps,
                             int32_t ntasks, int32_t nsplit, const Task *tasks,
                             const TaskItem *items, double2 *partial, int64_t nrep, hipStream_t s) {
-    // two paths per lane while their phase factors fit in LDS
-    if (project_lds_bytes(W.d, kProjP) <= kLdsMax)
-        return project_t<CAP, kProjP>(W, e, lde, S, M, pps, ntasks, nsplit, tasks, items, partial, nrep, s);
-    return project_t<CAP, 1>(W, e, lde, S, M, pps, ntasks, nsplit, tasks, items, partial, nrep, s);
+    constexpr int Wb = kProjWaves, Wh = kProjWaves / 2 > 0 ? kProjWaves / 2 : 1;
+    if (project_lds_bytes(W.d, kProjP, Wb) <= kLdsMax)
+        return project_t<CAP, kProjP, Wb>(W, e, lde, S, M, pps, ntasks, nsplit, tasks, items, partial, nrep, s);
+    if (project_lds_bytes(W.d, kProjP, Wh) <= kLdsMax)
+        return project_t<CAP, kProjP, Wh>(W, e, lde, S, M, pps, ntasks, nsplit, tasks, items, partial, nrep, s);
+    return project_t<CAP, 1, Wh>(W, e, lde, S, M, pps, ntasks, nsplit, tasks, items, partial, nrep, s);
 }
 
 hipError_t launch_project(int cap, const Walk &W, const double2 *e, int64_t lde, const double *S, int64_t M,
