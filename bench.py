@@ -85,7 +85,7 @@ def run_learned(args, torch, W, Q):
     gate 1e-3), and the cost of one evaluation of ybar by the expansion and
     by the network on 2^20 points."""
     dev = torch.device("cuda:0")
-    w = W.CFG5.with_(M=args.M or (1 << 16))
+    w = W.D16_HC1P32.with_(M=args.M or (1 << 16))
     ctx = Q.Context(0)
     b = Q.Basis(w.d, w.set_kind, w.level)
     prob = Q.problem_from(w)
@@ -230,7 +230,7 @@ def run_batched(args, torch, W, Q):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 "
                                    "(multi-GPU path sharding is a design note, not built)"}))
         sys.exit(2)
     import torch

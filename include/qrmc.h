@@ -68,7 +68,7 @@ typedef enum {
     QR_EDEVICE = -3,  /* HIP runtime or launch error                      */
     QR_ERANGE = -4,   /* size overflow (index set, M, workspace)          */
     QR_ENUMERIC = -5, /* non-finite coefficient produced                  */
-    QR_ENOTSUP = -6   /* valid request outside what this build supports   */
+    QR_ENOTSUP = -6   /* valid request outside what this library supports */
 } qr_status;
 
 /* Message for the last failing call on this thread ("" if none). */

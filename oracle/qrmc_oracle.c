@@ -27,9 +27,9 @@
  *   - index sets Gamma_F / Gamma_H: Sec. 2.3.3 "Multi-indices sets"
  *   - error indicators MSE_max / MSE_av: Sec. 5, eq (mse)
  *
- * Readings where the problem statement used here departs from the paper's own
- * experiments (sampling law, basis, index sets, driver, random generator) are
- * listed in the design doc of the repository; the short form is:
+ * Where the problem statement used here departs from the paper's own
+ * experiments (sampling law, basis, index sets, driver, random generator),
+ * it is read as follows:
  *   - nu is a product of standard logistic laws, F(x) = 1/(1+e^-x);
  *   - the basis is the real Fourier basis on the torus composed with F:
  *     phi_0 = 1, and for each representative k (first non-zero coordinate

@@ -156,7 +156,7 @@ def test_learned_solve_with_closed_gate_is_the_plain_solve(env):
     """Gate 0: every surrogate is fitted and rejected, and the step-major
     learned pipeline reproduces qr_solve."""
     Q, ctx, torch = env
-    w = W.CFG1
+    w = W.D2_TENSOR4
     b = Q.Basis(w.d, w.set_kind, w.level)
     a = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device="cuda")
     rep = ctx.solve_learned(Q.problem_from(w), b, w.M, w.seed, a, train_points=1 << 12, heldout_points=1 << 10,
@@ -183,7 +183,7 @@ def test_learned_solve_uses_the_surrogate_where_it_passes(env):
     driver is 0.5-Lipschitz in y, so S moves by at most 0.5 T gate ||y||
     (T = 1), taken with a factor 3 of margin."""
     Q, ctx, torch = env
-    w = W.CFG1.with_(level=1)
+    w = W.D2_TENSOR4.with_(level=1)
     b = Q.Basis(w.d, w.set_kind, w.level)
     a = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device="cuda")
     gate = 5e-2

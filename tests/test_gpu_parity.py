@@ -114,11 +114,11 @@ def _small(w, **kw):
     return w.with_(**kw)
 
 
-@pytest.mark.parametrize("wname,i,M", [("cfg1", 9, 1), ("cfg1", 8, 777), ("cfg1", 0, 2000),
-                                       ("cfg2", 19, 300), ("cfg2", 17, 128)])
+@pytest.mark.parametrize("wname,i,M", [("d2", 9, 1), ("d2", 8, 777), ("d2", 0, 2000),
+                                       ("d6", 19, 300), ("d6", 17, 128)])
 def test_path_responses(env, wname, i, M):
     Q, ctx, torch = env
-    w = {"cfg1": W.CFG1, "cfg2": W.CFG2}[wname]
+    w = {"d2": W.D2_TENSOR4, "d6": W.D6_HCMAX16}[wname]
     _say(f"path_responses {w.name} i={i} M={M}")
     b = Q.Basis(w.d, w.set_kind, w.level)
     reps = O.reps_for(w)
@@ -137,10 +137,10 @@ def test_path_responses(env, wname, i, M):
 
 
 @pytest.mark.parametrize("i", [9, 8, 4])
-def test_backward_step_cfg1(env, i):
+def test_backward_step_d2_tensor(env, i):
     Q, ctx, torch = env
-    w = W.CFG1
-    _say(f"backward_step cfg1 i={i}")
+    w = W.D2_TENSOR4
+    _say(f"backward_step d2 tensor i={i}")
     b = Q.Basis(w.d, w.set_kind, w.level)
     reps = O.reps_for(w)
     alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=11, scale=0.2)
@@ -156,28 +156,28 @@ def test_backward_step_cfg1(env, i):
     assert np.array_equal(got[rows], alpha[rows])
 
 
-def test_backward_step_cfg2_reduced_M(env):
+def test_backward_step_d6_hcmax_reduced_M(env):
     """Full |Gamma| = 169,209 of the d=6 hyperbolic cross, M reduced so the
     oracle finishes: steps N-1 and N-2."""
     Q, ctx, torch = env
-    w = W.CFG2
+    w = W.D6_HCMAX16
     b = Q.Basis(w.d, w.set_kind, w.level)
     reps = O.reps_for(w)
     M = 600
     alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=13, scale=0.1, decay=0.8)
     for i in (19, 18):
-        _say(f"backward_step cfg2 i={i} M={M}")
+        _say(f"backward_step d6 hc_max i={i} M={M}")
         a = _dev(torch, alpha)
         ctx.backward_step(Q.problem_from(w), b, i, M, w.seed, a)
         torch.cuda.synchronize()
         ref, absum, _, _ = O.backward_step(w, reps, i, M, w.seed, alpha.copy())
-        _assert_alpha(_host(a)[i], ref, absum, what=f"cfg2 row {i}")
+        _assert_alpha(_host(a)[i], ref, absum, what=f"d6 hc_max row {i}")
 
 
-def test_solve_cfg1_full(env):
+def test_solve_d2_tensor_full(env):
     Q, ctx, torch = env
-    w = W.CFG1
-    _say("solve cfg1")
+    w = W.D2_TENSOR4
+    _say("solve d2 tensor")
     b = Q.Basis(w.d, w.set_kind, w.level)
     reps = O.reps_for(w)
     a = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device="cuda")
@@ -195,11 +195,11 @@ def test_solve_cfg1_full(env):
     assert torch.equal(a, a2)
 
 
-def test_solve_cfg1_error_against_closed_form(env):
+def test_solve_d2_tensor_error_against_closed_form(env):
     """Relative L2 error at t_0 against u(0,.) on stream-1 test points,
     evaluated with qr_eval, equals the oracle's figure."""
     Q, ctx, torch = env
-    w = W.CFG1
+    w = W.D2_TENSOR4
     b = Q.Basis(w.d, w.set_kind, w.level)
     reps = O.reps_for(w)
     a = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device="cuda")
@@ -239,14 +239,14 @@ def test_ragged_and_degenerate_sizes(env):
         ctx.solve(Q.problem_from(w), b, 0, 3, a)
     # dimension mismatch between basis and problem
     with pytest.raises(Q.QrError):
-        ctx.solve(Q.problem_from(W.CFG1), b, 5, 3, a)
+        ctx.solve(Q.problem_from(W.D2_TENSOR4), b, 5, 3, a)
 
 
 def test_prefix_property(env):
     """Path m uses counters (m, i, r) only: the first M' responses of a cloud
     of M > M' paths are those of the cloud of M' paths."""
     Q, ctx, torch = env
-    w = W.CFG1
+    w = W.D2_TENSOR4
     b = Q.Basis(w.d, w.set_kind, w.level)
     alpha = _dev(torch, W.synthetic_alpha(b.n_funcs, w.N, seed=2, scale=0.2))
     s1 = torch.empty(1000, dtype=torch.float64, device="cuda")
@@ -261,15 +261,15 @@ def test_prefix_property(env):
 # the benchmarked configuration at full size (M = 2^20, |Gamma| = 169,209)
 # ---------------------------------------------------------------------------
 
-def test_cfg2_full_size_sampled(env):
+def test_d6_hcmax_full_size_sampled(env):
     """At full M: step N-1 coefficients for sampled k (the oracle projects its
     own responses onto a subset of the basis), and step N-2 responses for
     sampled paths."""
     Q, ctx, torch = env
-    w = W.CFG2
+    w = W.D6_HCMAX16
     b = Q.Basis(w.d, w.set_kind, w.level)
     reps = O.reps_for(w)
-    _say("cfg2 full size: step N-1")
+    _say("d6 hc_max full size: step N-1")
     a = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device="cuda")
     ctx.backward_step(Q.problem_from(w), b, w.N - 1, w.M, w.seed, a)
     torch.cuda.synchronize()
@@ -280,8 +280,8 @@ def test_cfg2_full_size_sampled(env):
     ref, absum, _, _ = O.backward_step(w, sub_reps, w.N - 1, w.M, w.seed,
                                        np.zeros((w.N, 2 * len(sub) - 1)))
     idx = [0] + [f for r in sub[1:] for f in (2 * r - 1, 2 * r)]
-    _assert_alpha(got[idx], ref, absum, what="cfg2 full N-1 sampled")
-    _say("cfg2 full size: responses of step N-2")
+    _assert_alpha(got[idx], ref, absum, what="d6 hc_max full N-1 sampled")
+    _say("d6 hc_max full size: responses of step N-2")
     alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=17, scale=0.1, decay=0.8)
     s = torch.empty(w.M, dtype=torch.float64, device="cuda")
     ctx.path_responses(Q.problem_from(w), b, w.N - 2, w.M, w.seed, _dev(torch, alpha), s)
@@ -357,10 +357,10 @@ def test_batched_against_oracle(env):
 def test_batched_equals_unbatched_full_set(env):
     """Instances on the whole basis give qr_solve's coefficients for their f_a."""
     Q, ctx, torch = env
-    w = W.CFG1
+    w = W.D2_TENSOR4
     b = Q.Basis(w.d, w.set_kind, w.level)
     fas = [0.2, 0.5, 0.9]
-    _say("batched vs qr_solve, cfg1")
+    _say("batched vs qr_solve, d2 tensor")
     a = torch.zeros((len(fas), w.N, b.n_funcs), dtype=torch.float64, device="cuda")
     ctx.solve_batched(Q.problem_from(w), b, [(f, w.d, w.level, w.M) for f in fas], w.seed, a)
     for r, f in enumerate(fas):
@@ -373,7 +373,7 @@ def test_batched_equals_unbatched_full_set(env):
 
 def test_batched_invalid_arguments(env):
     Q, ctx, torch = env
-    w = W.CFG1
+    w = W.D2_TENSOR4
     b = Q.Basis(w.d, w.set_kind, w.level)
     a = torch.zeros((65, w.N, b.n_funcs), dtype=torch.float64, device="cuda")
     prob = Q.problem_from(w)

@@ -89,8 +89,8 @@ def test_prec_solve_value_driver(env, prec):
     """Value-only driver (one right-hand side): full solve of the d=2 tensor
     workload against the oracle row by row, and the closed-form error."""
     Q, ctx, torch = env
-    w = W.CFG1
-    _say(f"prec solve cfg1 {prec}")
+    w = W.D2_TENSOR4
+    _say(f"prec solve d2 tensor {prec}")
     b = Q.Basis(w.d, w.set_kind, w.level)
     reps = O.reps_for(w)
     a = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device="cuda")
@@ -121,8 +121,8 @@ def test_prec_full_basis_gradient_sampled(env):
     """The d=10 hyperbolic cross prod(1+|k_l|) <= 32 (85,485 functions) with
     the z-dependent driver: step N-2 at M = 2^16 in bfloat16 against the oracle."""
     Q, ctx, torch = env
-    w = W.CFG3.with_(M=1 << 16)
-    _say("prec cfg3 basis, step N-2, M=2^16")
+    w = W.D10_HC1P32_ZRAT.with_(M=1 << 16)
+    _say("prec d10 hc_1p basis, step N-2, M=2^16")
     b = Q.Basis(w.d, w.set_kind, w.level)
     reps = O.reps_for(w)
     alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=31, scale=0.1, decay=0.8)
@@ -140,7 +140,7 @@ def test_prec_full_basis_gradient_sampled(env):
 
 def test_prec_invalid_and_f64_passthrough(env):
     Q, ctx, torch = env
-    w = W.CFG1
+    w = W.D2_TENSOR4
     b = Q.Basis(w.d, w.set_kind, w.level)
     a = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device="cuda")
     with pytest.raises(Q.QrError):

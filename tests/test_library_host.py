@@ -67,7 +67,7 @@ def test_basis_enumeration_matches_oracle(d, kind, level):
     assert b.max_nnz == (int(np.max(np.count_nonzero(ref, axis=1))) if ref.shape[0] else 0)
 
 
-@pytest.mark.parametrize("w", [W.CFG1, W.CFG2, W.CFG3, W.CFG5], ids=lambda w: w.name)
+@pytest.mark.parametrize("w", [W.D2_TENSOR4, W.D6_HCMAX16, W.D10_HC1P32_ZRAT, W.D16_HC1P32], ids=lambda w: w.name)
 def test_configuration_bases_match_oracle(w):
     b = Q.Basis(w.d, w.set_kind, w.level)
     ref = O.enumerate_set(w.d, w.set_kind, w.level)

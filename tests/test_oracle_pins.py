@@ -361,7 +361,7 @@ def _kappa(w, i):
 def test_linear_driver_unbiased_alpha(i):
     """Lemma 3.1: E[alpha_{i,k}] = <y_i, phi_k>_nu when S is exact.  With
     f = h(t,x) (no dependence on y) the discrete-time y_i is closed form."""
-    w = W.CFG1.with_(driver="linear", f_a=0.0, sol_p=0.2, sol_w=[1.0, 0.5])
+    w = W.D2_TENSOR4.with_(driver="linear", f_a=0.0, sol_p=0.2, sol_w=[1.0, 0.5])
     reps = O.reps_for(w)
     M = 1 << 14
     alpha = np.zeros((w.N, O.nfuncs(reps)))
@@ -375,7 +375,7 @@ def test_linear_driver_unbiased_alpha(i):
 
 
 def test_step_response_equals_path_response():
-    w = W.CFG1
+    w = W.D2_TENSOR4
     reps = O.reps_for(w)
     rng = np.random.default_rng(0)
     alpha = W.synthetic_alpha(O.nfuncs(reps), w.N, seed=5)
@@ -391,11 +391,11 @@ def test_step_response_equals_path_response():
 # ---------------------------------------------------------------------------
 
 @pytest.mark.slow
-def test_cfg1_solve_close_to_projected_solution():
+def test_d2_tensor_solve_close_to_projected_solution():
     """The solve at t_0 approaches P_Gamma u(0,.) (Thm 2.2): its distance is
     bounded by the Monte-Carlo spread plus an O(Delta) time-discretisation
     allowance, and the L2 error against u sits at the projection floor."""
-    w = W.CFG1.with_(M=1 << 16)
+    w = W.D2_TENSOR4.with_(M=1 << 16)
     reps = O.reps_for(w)
     alpha = O.solve(w, reps)
     exact = math.exp(-1.0) * _proj_cos_linear(reps, [1.0, 1.0], 0.0)

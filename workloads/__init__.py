@@ -73,7 +73,7 @@ def _first_two(d: int) -> List[float]:
 
 # d=2, tensor |k_l|<=4 (81 functions), M=10^4, f = 0.5 sin y + h,
 # u = exp(-(T-t)) cos(x1+x2), dX = 0.5 dW.
-CFG1 = Workload(
+D2_TENSOR4 = Workload(
     name="d2-tensor4-sin", d=2, N=10, T=1.0, sigma=_diag(2, 0.5), b0=[0.0] * 2, b1=[0.0] * 2,
     set_kind="tensor", level=4, M=10_000, driver="sin", f_a=0.5,
     sol_A=1.0, sol_c=1.0, sol_p=0.0, sol_w=[1.0, 1.0])
@@ -81,7 +81,7 @@ CFG1 = Workload(
 # d=6, N=20, sigma=0.4 I, b=-0.1 x, hyperbolic cross prod max(1,|k_l|)<=16
 # (169,209 functions), M=2^20, Allen-Cahn driver y - y^3 + h,
 # u = exp(-(T-t)) cos(sum x)/2; T=1 and clamp L = 2 sup|u| = 1 are readings.
-CFG2 = Workload(
+D6_HCMAX16 = Workload(
     name="d6-hcmax16-allen-cahn", d=6, N=20, T=1.0, sigma=_diag(6, 0.4), b0=[0.0] * 6,
     b1=[-0.1] * 6, set_kind="hc_max", level=16, M=1 << 20, driver="allen_cahn", f_a=0.0,
     sol_A=0.5, sol_c=1.0, sol_p=0.0, sol_w=[1.0] * 6, clamp=1.0)
@@ -89,19 +89,19 @@ CFG2 = Workload(
 # d=10, N=30, prod (1+|k_l|)<=32 (85,485 functions; the literal max(1,.) set
 # has 1.8e8), M=2^22, f = -0.05|z|^2/(1+|z|^2) + y/(1+y^2) + h,
 # u = exp(-(T-t)) cos(x1+x2); sigma = 0.5 I, b = 0, T = 1 are readings.
-CFG3 = Workload(
+D10_HC1P32_ZRAT = Workload(
     name="d10-hc1p32-zrat", d=10, N=30, T=1.0, sigma=_diag(10, 0.5), b0=[0.0] * 10,
     b1=[0.0] * 10, set_kind="hc_1p", level=32, M=1 << 22, driver="zrat", f_a=-0.05,
     sol_A=1.0, sol_c=1.0, sol_p=0.0, sol_w=_first_two(10))
 
 # d=16, N=40, prod (1+|k_l|)<=32 (599,969 functions), M=2^22, Allen-Cahn
 # driver, u = exp(-(T-t)) cos(x1+x2), clamp L = 2.
-CFG5 = Workload(
+D16_HC1P32 = Workload(
     name="d16-hc1p32-allen-cahn", d=16, N=40, T=1.0, sigma=_diag(16, 0.5), b0=[0.0] * 16,
     b1=[0.0] * 16, set_kind="hc_1p", level=32, M=1 << 22, driver="allen_cahn", f_a=0.0,
     sol_A=1.0, sol_c=1.0, sol_p=0.0, sol_w=_first_two(16), clamp=2.0)
 
-ALL = {w.name: w for w in (CFG1, CFG2, CFG3, CFG5)}
+ALL = {w.name: w for w in (D2_TENSOR4, D6_HCMAX16, D10_HC1P32_ZRAT, D16_HC1P32)}
 
 
 def batched_instances(n: int = 256, seed: int = 4):
