@@ -200,3 +200,18 @@ def test_learned_solve_uses_the_surrogate_where_it_passes(env):
         e = _rel(got[i], r64[i])
         _say(f"  row {i}: rel change {e:.2e}")
         assert e <= 3 * gate
+
+
+def test_learned_solve_invalid_options(env):
+    Q, ctx, torch = env
+    w = W.D2_TENSOR4
+    b = Q.Basis(w.d, w.set_kind, w.level)
+    a = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device="cuda")
+    prob = Q.problem_from(w)
+    for kw in ({"batch": 32}, {"epochs": -1}, {"train_points": 100, "batch": 1024}, {"heldout_points": 0},
+               {"lr": 0.0}, {"gate": -1.0}):
+        with pytest.raises(Q.QrError):
+            ctx.solve_learned(prob, b, 100, 0, a, **kw)
+    with pytest.raises(Q.QrError) as e:
+        ctx.solve_learned(Q.problem_from(w.with_(driver="zrat")), b, 100, 0, a)
+    assert e.value.status == -6

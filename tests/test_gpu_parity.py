@@ -136,6 +136,49 @@ def test_path_responses(env, wname, i, M):
                            rtol=1e-14, atol=1e-14)
 
 
+def _zrat(d, level=12, N=4, M=3000):
+    return W.Workload(name=f"zrat-d{d}", d=d, N=N, T=1.0,
+                      sigma=[[0.5 if a == b else 0.0 for b in range(d)] for a in range(d)],
+                      b0=[0.0] * d, b1=[0.0] * d, set_kind="hc_1p", level=level, M=M, driver="zrat",
+                      f_a=-0.05, sol_A=1.0, sol_c=1.0, sol_p=0.0,
+                      sol_w=[1.0 if l < 2 else 0.0 for l in range(d)], seed=3)
+
+
+@pytest.mark.parametrize("d,i", [(3, 0), (8, 1), (13, 2)])
+def test_backward_step_gradient_driver(env, d, i):
+    """z-dependent driver: the walk carries the x-gradient of ybar (FP64)."""
+    Q, ctx, torch = env
+    w = _zrat(d)
+    _say(f"backward_step zrat d={d} i={i}")
+    b = Q.Basis(w.d, w.set_kind, w.level)
+    reps = O.reps_for(w)
+    alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=d, scale=0.2, decay=0.7)
+    a = _dev(torch, alpha)
+    ctx.backward_step(Q.problem_from(w), b, i, w.M, w.seed, a)
+    torch.cuda.synchronize()
+    ref, absum, _, _ = O.backward_step(w, reps, i, w.M, w.seed, alpha.copy())
+    _assert_alpha(_host(a)[i], ref, absum, what=f"zrat d={d} row {i}")
+
+
+@pytest.mark.parametrize("w,i", [(W.D10_HC1P32_ZRAT, 27), (W.D16_HC1P32, 38)], ids=["d10-zrat", "d16"])
+def test_path_responses_full_basis_sampled(env, w, i):
+    """The d=10 (gradient driver) and d=16 sets at their full size: responses
+    of sampled paths of a step with two expansion levels ahead."""
+    Q, ctx, torch = env
+    M = 4096
+    _say(f"path_responses {w.name} i={i} M={M}")
+    b = Q.Basis(w.d, w.set_kind, w.level)
+    reps = O.reps_for(w)
+    alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=21, scale=0.05, decay=0.8)
+    s = torch.empty(M, dtype=torch.float64, device="cuda")
+    ctx.path_responses(Q.problem_from(w), b, i, M, 9, _dev(torch, alpha), s)
+    torch.cuda.synchronize()
+    sg = _host(s)
+    for m in [0, 77, 2048, M - 1]:
+        ref = O.path_response(w, reps, i, 9, m, alpha)
+        assert abs(sg[m] - ref) <= TOL * max(1.0, abs(ref)), (m, sg[m], ref)
+
+
 @pytest.mark.parametrize("i", [9, 8, 4])
 def test_backward_step_d2_tensor(env, i):
     Q, ctx, torch = env

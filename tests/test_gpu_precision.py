@@ -64,10 +64,10 @@ def _zrat_small(d=3):
 
 
 @pytest.mark.parametrize("prec", ["bf16", "f16"])
-@pytest.mark.parametrize("d", [3, 6, 10])
+@pytest.mark.parametrize("d", [3, 6, 10, 13, 16])
 def test_prec_backward_step_gradient_driver(env, prec, d):
     """z-dependent driver: value and d gradient components as right-hand
-    sides (d = 3, 6, 10 use 2 and 3 groups of four)."""
+    sides (2, 2, 3, 4 and 5 groups of four for d = 3, 6, 10, 13, 16)."""
     Q, ctx, torch = env
     w = _zrat_small(d)
     _say(f"prec backward step zrat d={d} {prec}")
