@@ -123,6 +123,5 @@ hipError_t launch_pack_tiles(int prec, const double2 *alpha_int_row, int64_t nre
 size_t path_lds_bytes(int32_t d, bool grad, int P);
 // paths the path kernel's grid covers (M rounded up to whole blocks)
 int64_t path_state_ld(int64_t M, bool grad);
-int path_points(bool grad);
 
 }  // namespace qrmc

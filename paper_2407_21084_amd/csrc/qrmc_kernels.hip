@@ -15,16 +15,15 @@
 // times one factor e^{+-2 pi i u_l}, so e^{2 pi i k.u} costs one complex
 // multiplication: nodes are visited depth-first, coordinates l ascending,
 // sign + before -, magnitudes ascending.  All lanes of a wave walk the same
-// nodes, so loop bounds and the coefficient stream are wave-uniform (scalar
-// registers and scalar loads), the per-lane factors e^{2 pi i u_l} sit in LDS
-// and the chain of values lives in registers.  A thread carries P points
-// through the walk, so the scalar control of each node is paid once for P
-// points' worth of FP64 work.
+// nodes, so loop bounds are wave-uniform (scalar registers) and the
+// coefficient stream is shared by the wave (vector-loaded chunks parked in
+// LDS); the per-lane factors e^{2 pi i u_l} sit in LDS and the chain of
+// values lives in registers.  A thread carries P points through the walk,
+// so the scalar control of each node is paid once for P points' worth of
+// FP64 work.
 #include "qrmc_kernels.h"
 
 namespace qrmc {
-
-#define QR_CONST __attribute__((address_space(4)))
 
 // values at the P points of a thread, in FP64 (R = double) or, for the
 // reduced-precision form, FP32 (R = float)
@@ -109,12 +108,6 @@ __device__ __noinline__ double2 nl_unit_phase(double x) {
     // e^{2 pi i F(x)}
     double sn, cs;
     sincospi(2.0 * logistic_cdf(x), &sn, &cs);
-    return make_double2(cs, sn);
-}
-__device__ __noinline__ double2 nl_unit_phase_u(double u) {
-    // e^{2 pi i u}
-    double sn, cs;
-    sincospi(2.0 * u, &sn, &cs);
     return make_double2(cs, sn);
 }
 __device__ __noinline__ double2 nl_sincos(double th) {
@@ -222,7 +215,6 @@ struct EvalAcc<P, true> {
     double y[P], g[P];
 };
 
-#ifndef QRMC_COEF_SCALAR
 // Coefficients arrive by vector loads, one 64-node chunk per load (lane q
 // holds the pair of node 64c + q), issued a chunk ahead of use.  When the
 // walk enters a chunk, the wave stores it to its LDS slot; each node's pair
@@ -267,32 +259,6 @@ struct EvalSink {
         }
         pc = slot[nn & 63];
     }
-#else
-// Coefficients arrive by scalar loads, the next node's pair requested as
-// soon as the current one is consumed.
-template <int P, bool GRAD>
-struct EvalSink {
-    static constexpr bool kGrad = GRAD;
-    using Acc = EvalAcc<P, GRAD>;
-    const QR_CONST double *a;  // pair of the node about to be visited
-    double nx, ny;             // its coefficients (already requested)
-
-    __device__ __forceinline__ void init(const double2 *row, double2 *) {
-        a = (const QR_CONST double *)row;
-        nx = a[0];
-        ny = a[1];
-    }
-    __device__ __forceinline__ void coeff(double &cx, double &cy) const {
-        cx = nx;
-        cy = ny;
-    }
-    __device__ __forceinline__ void advance() {
-        __builtin_amdgcn_sched_barrier(0);
-        a += 2;
-        nx = a[0];
-        ny = a[1];
-    }
-#endif
     double ysum[P];  // value-only walks: the running sum
 
     __device__ __forceinline__ void node(const Pts<P> &v, Acc &acc) {
@@ -1389,7 +1355,6 @@ hipError_t launch_pad(int32_t nrows, int64_t nrep, int64_t ld, double2 *alpha_in
     return hipGetLastError();
 }
 
-int path_points(bool grad) { return grad ? 1 : kPathP; }
 
 int64_t path_state_ld(int64_t M, bool grad) {
     const int64_t per = (int64_t)kPathBlock * (grad ? 1 : kPathP);
