@@ -166,12 +166,15 @@ def run_batched(args, torch, W, Q):
     stream = torch.cuda.current_stream()
     runs = []
     evals = 0.0
+    path_evals_step = 0.0
     for gw, inst, _ in groups:
         b = Q.Basis(gw.d, gw.set_kind, gw.level)
         a = torch.zeros((len(inst), gw.N, b.n_funcs), dtype=torch.float64, device=dev)
         runs.append((gw, inst, b, a))
         for (_, d, L, M) in inst:
-            evals += M * Q.Basis(d, gw.set_kind, L).n_funcs * gw.N * (gw.N + 1) / 2
+            nf = Q.Basis(d, gw.set_kind, L).n_funcs
+            evals += M * nf * gw.N * (gw.N + 1) / 2
+            path_evals_step += M * nf * gw.N * (gw.N - 1) / 2
 
     def step():
         for gw, inst, b, a in runs:
@@ -193,6 +196,7 @@ def run_batched(args, torch, W, Q):
     path_ms, path_n = ctx.kernel_time(Q.K_PATH)
     proj_ms, proj_n = ctx.kernel_time(Q.K_PROJECT)
     red_ms, _ = ctx.kernel_time(Q.K_REDUCE)
+    path_evals = path_evals_step * args.steps
     print(f"[bench] timed region {elapsed:.2f} s", file=sys.stderr, flush=True)
 
     # accuracy of every instance at t_0 against its closed form (stream-1 points)
@@ -222,6 +226,13 @@ def run_batched(args, torch, W, Q):
         "kernels_ms_per_solve": {"path": path_ms / args.steps, "project": proj_ms / args.steps,
                                  "reduce": red_ms / args.steps},
         "launches_per_step": {"path": path_n // max(1, args.steps), "project": proj_n // max(1, args.steps)},
+        # algorithmic rate of the walks: 5 flops per instance basis function
+        # along the paths (useful work; passes also walk their members'
+        # envelopes)
+        "roofline": {"bound": "alu", "achieved": path_evals * 5.0 / (path_ms * 1e-3) / 1e12 if path_ms > 0 else 0.0,
+                     "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": path_evals * 5.0 / (path_ms * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS if path_ms > 0 else 0.0,
+                     "traffic": None, "kernel": "batched_path_kernel"},
     }
     print(json.dumps(line), flush=True)
     ctx.close()
@@ -353,6 +364,23 @@ def main():
     }
     if mfma:
         line["mfma"] = mfma
+    if args.precision != "f64":
+        # the plain FP64 solve of the same workload: its time, its error at
+        # t_0, and the reduced-precision coefficients' error per time step
+        a64 = torch.zeros_like(alpha)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.solve(prob, basis, w.M, w.seed, a64, stream)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t0
+        print(f"[bench] plain FP64 solve {t64:.1f} s", file=sys.stderr, flush=True)
+        y64 = torch.empty(n_test, dtype=torch.float64, device=dev)
+        ctx.eval(basis, a64[0].contiguous(), xt, y64, stream=stream)
+        torch.cuda.synchronize()
+        rows = (torch.linalg.norm(alpha - a64, dim=1) / torch.linalg.norm(a64, dim=1).clamp_min(1e-300)).tolist()
+        line["vs_f64"] = {"f64_solve_s": t64, "speedup": t64 / (elapsed / args.steps),
+                          "rel_l2_t0_f64": float(torch.linalg.norm(y64 - u0) / torch.linalg.norm(u0)),
+                          "alpha_rel_err_per_step": rows}
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

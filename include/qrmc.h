@@ -18,7 +18,9 @@
  *    synchronising call as QR_EDEVICE.
  *  - A context (qr_ctx) owns device workspace and must not be used from two
  *    host threads or on two streams at the same time.
- *  - All floating point is IEEE binary64.
+ *  - Floating-point arguments and results are IEEE binary64, except the
+ *    network entry points of the learned form (qr_mlp_*), which take binary32
+ *    parameters, features and outputs.
  *
  * Mathematical objects (paper notation)
  * -------------------------------------
@@ -47,7 +49,10 @@
  * key (seed_lo, seed_hi ^ s), counter (m_lo, m_hi, i, r >> 1) and words
  * (w0,w1) for even r, (w2,w3) for odd r; U = ((w_a<<20 | w_b>>12) + 1/2) 2^-52.
  * Stream 0: solver paths (start point draws r = 0..d-1, then nbm normals per
- * Euler step: r = d + (j-i) nbm + k).  Stream 1: test points.
+ * Euler step: r = d + (j-i) nbm + k).  Stream 1: test points.  Streams 2
+ * and 3: training and held-out points of the learned form (time index i =
+ * the time index of the fitted expansion); stream 2 also initialises the
+ * network (counter (parameter index, 0, 0)).
  */
 #ifndef QRMC_H
 #define QRMC_H
