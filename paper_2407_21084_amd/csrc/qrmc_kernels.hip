@@ -149,29 +149,55 @@ __device__ __forceinline__ typename Sink::Acc visit(const Pts<P, R> &parent, con
             }
             Pts<P, R> v = parent;
             [[maybe_unused]] R km = s ? -1.0 : 1.0;
+            if constexpr (Sink::kSplit) {
+                // Value-only sinks that ask for it: the magnitudes whose node
+                // has children (budget w for hyperbolic crosses, Pb for the
+                // tensor set, at most Lc, and a later coordinate) come first,
+                // since w grows with the magnitude; the rest of the chain, all
+                // leaves, runs without the recursion test.
+                static_assert(!Sink::kGrad, "split chains are value-only");
+                int w = Pb * (1 + W.b);
+                if constexpr (T + 1 < CAP) {
+                    const int wc = more ? (W.c ? W.Lc : (Pb <= W.Lc ? W.L : 0)) : 0;
 #pragma unroll 1
-            for (int w = Pb * (1 + W.b); w <= W.L; w += Pb) {
-                v = cmul(v, es);
-                if constexpr (Sink::kGrad) {
-                    R gs[P];
-                    sink.node_g(v, acc, gs);
-                    if constexpr (T + 1 < CAP) {
-                        const int child = W.c ? w : Pb;
-                        if (more && child <= W.Lc) {
-                            const typename Sink::Acc c = visit<T + 1, CAP, P>(v, l, child, W, L, sink);
-                            Sink::add(acc, c);
-#pragma unroll
-                            for (int q = 0; q < P; ++q) gs[q] += c.g[q];
-                        }
+                    for (; w <= W.L && w <= wc; w += Pb) {
+                        v = cmul(v, es);
+                        sink.node(v, acc);
+                        Sink::add(acc, visit<T + 1, CAP, P>(v, l, W.c ? w : Pb, W, L, sink));
                     }
-#pragma unroll
-                    for (int q = 0; q < P; ++q) gl[q] = fma(km, gs[q], gl[q]);
-                    km += s ? -1.0 : 1.0;
-                } else {
+                }
+#pragma unroll 1
+                for (; w <= W.L; w += Pb) {
+                    v = cmul(v, es);
                     sink.node(v, acc);
-                    if constexpr (T + 1 < CAP) {
-                        const int child = W.c ? w : Pb;
-                        if (more && child <= W.Lc) Sink::add(acc, visit<T + 1, CAP, P>(v, l, child, W, L, sink));
+                }
+            } else {
+                // largest magnitude whose node has children (see above)
+                [[maybe_unused]] const int wc = more ? (W.c ? W.Lc : (Pb <= W.Lc ? W.L : 0)) : 0;
+#pragma unroll 1
+                for (int w = Pb * (1 + W.b); w <= W.L; w += Pb) {
+                    v = cmul(v, es);
+                    if constexpr (Sink::kGrad) {
+                        R gs[P];
+                        sink.node_g(v, acc, gs);
+                        if constexpr (T + 1 < CAP) {
+                            if (w <= wc) {
+                                const int child = W.c ? w : Pb;
+                                const typename Sink::Acc c = visit<T + 1, CAP, P>(v, l, child, W, L, sink);
+                                Sink::add(acc, c);
+#pragma unroll
+                                for (int q = 0; q < P; ++q) gs[q] += c.g[q];
+                            }
+                        }
+#pragma unroll
+                        for (int q = 0; q < P; ++q) gl[q] = fma(km, gs[q], gl[q]);
+                        km += s ? -1.0 : 1.0;
+                    } else {
+                        sink.node(v, acc);
+                        if constexpr (T + 1 < CAP) {
+                            const int child = W.c ? w : Pb;
+                            if (more && child <= W.Lc) Sink::add(acc, visit<T + 1, CAP, P>(v, l, child, W, L, sink));
+                        }
                     }
                 }
             }
@@ -225,6 +251,7 @@ struct EvalAcc<P, true> {
 template <int P, bool GRAD>
 struct EvalSink {
     static constexpr bool kGrad = GRAD;
+    static constexpr bool kSplit = !GRAD;  // split chains carry no gradient sums
     using Acc = EvalAcc<P, GRAD>;
     double2 *slot;        // this wave's LDS copy of the current chunk [64]
     const double2 *next;  // this lane's entry of the chunk after `buf`
@@ -383,9 +410,10 @@ size_t path_lds_bytes(int32_t d, bool grad, int P) {
            (size_t)(kPathBlock / 64) * 64 * sizeof(double2);
 }
 
-// Three waves per SIMD: the register budget (168 VGPRs) costs a few spills
-// of values that live across the whole traversal, and the extra wave hides
-// more of the scalar coefficient loads than the spills cost.
+// Three waves per SIMD (168 VGPRs): a few spills of values that live across
+// the whole traversal cost less than the latency the third wave hides
+// (measured; also for the gradient walk, where 256 VGPRs and two waves were
+// slower).
 #ifndef QRMC_PATH_WAVES_PER_EU
 #define QRMC_PATH_WAVES_PER_EU 3
 #endif
@@ -544,6 +572,7 @@ void path_kernel(
 template <int P>
 struct ProjSink {
     static constexpr bool kGrad = false;
+    static constexpr bool kSplit = false;  // measured: slower at d = 10
     struct Acc {};
     __device__ __forceinline__ static void add(Acc &, const Acc &) {}
     double2 *row;    // this lane's row of the wave buffer: row[c]
@@ -810,6 +839,7 @@ constexpr int kMfmaGroup = 32;  // nodes per contraction group (16 pairs)
 template <int PREC, int T>
 struct MfmaSink {
     static constexpr bool kGrad = false;
+    static constexpr bool kSplit = true;
     struct Acc {};
     uint32_t *stage;       // this lane's 16-bit pairs: stage[(node pair) 128 + half], lane offset applied
     const uint2 *tiles;    // coefficient tiles of the next group: [T][64] uint2, lane offset applied
@@ -1116,6 +1146,7 @@ __global__ void moments_kernel(int64_t n, const double *__restrict__ t, double *
 template <int RT>
 struct BatchSink {
     static constexpr bool kGrad = false;
+    static constexpr bool kSplit = true;
     struct Acc {};
     static constexpr int kLoads = 4;
     static constexpr int kNodes = kLoads * 64 / RT;  // nodes per chunk
