@@ -54,7 +54,8 @@ struct qr_basis {
     std::vector<int32_t> canon;          // [nrep][d] lexicographic order
     std::vector<int32_t> canon_of_trav;  // traversal index -> canonical index
     std::vector<TaskItem> items;         // projection task items
-    std::vector<Task> tasks;             // projection tasks of at most kTaskMax nodes
+    std::vector<Task> tasks;             // projection tasks of at most task_max nodes
+    int32_t task_max = 0;                // proj_shape(d).task_max
     // device copies (one device at a time)
     std::mutex mu;
     int dev = -1;
@@ -128,10 +129,10 @@ struct Builder {
     }
 };
 
-// Cut the traversal order into tasks of at most kTaskMax consecutive nodes,
+// Cut the traversal order into tasks of at most task_max consecutive nodes,
 // each a run of items (a node with its whole subtree, or a node alone when
-// its subtree exceeds kTaskMax).
-void build_tasks(const std::vector<TaskItem> &nodes, const std::vector<int64_t> &subtree,
+// its subtree exceeds task_max).
+void build_tasks(const std::vector<TaskItem> &nodes, const std::vector<int64_t> &subtree, int64_t task_max,
                  std::vector<TaskItem> &items, std::vector<Task> &tasks) {
     const int64_t n = (int64_t)nodes.size();
     Task cur{0, 0, 0, 0};
@@ -145,17 +146,17 @@ void build_tasks(const std::vector<TaskItem> &nodes, const std::vector<int64_t> 
     int64_t r = 0;
     while (r < n) {
         const int64_t sz = subtree[r];
-        if (sz <= kTaskMax - cur.rep_count) {
+        if (sz <= task_max - cur.rep_count) {
             if (cur.rep_count == 0) cur.rep_begin = (int32_t)r;
             TaskItem it = nodes[r];
             it.full = 1;
             items.push_back(it);
             cur.rep_count += (int32_t)sz;
             r += sz;
-        } else if (sz <= kTaskMax) {
+        } else if (sz <= task_max) {
             close();
         } else {
-            if (cur.rep_count + 1 > kTaskMax) close();
+            if (cur.rep_count + 1 > task_max) close();
             if (cur.rep_count == 0) cur.rep_begin = (int32_t)r;
             TaskItem it = nodes[r];
             it.full = 0;
@@ -211,7 +212,8 @@ extern "C" qr_status qr_build_basis(int32_t d, int32_t kind, int32_t level, qr_b
             std::memcpy(&b->canon[c * d], T + order[c] * d, sizeof(int32_t) * d);
             b->canon_of_trav[order[c]] = (int32_t)c;
         }
-        build_tasks(nodes, subtree, b->items, b->tasks);
+        b->task_max = proj_shape(d).task_max;
+        build_tasks(nodes, subtree, b->task_max, b->items, b->tasks);
     } catch (const std::bad_alloc &) {
         delete b;
         return fail(QR_ENOMEM, "qr_build_basis: out of host memory");
@@ -589,7 +591,8 @@ static qr_status begin(qr_ctx *c, void *stream) {
 // ---------------------------------------------------------------------------
 static void split_plan(const qr_basis *b, int64_t M, int32_t *nsplit, int64_t *pps) {
     const int64_t ntasks = (int64_t)b->tasks.size();
-    const int64_t group = (int64_t)kProjWaves * 64;
+    const ProjShape sh = proj_shape(b->d);
+    const int64_t group = (int64_t)sh.waves * 64 * sh.P;
     int64_t want = (2048 + ntasks - 1) / ntasks;
     const int64_t maxs = std::max<int64_t>(1, (M + 4 * group - 1) / (4 * group));
     want = std::max<int64_t>(1, std::min(want, maxs));
@@ -611,8 +614,8 @@ static qr_status project_and_reduce(qr_ctx *c, const qr_basis *b, const double2 
     double2 *partial = (double2 *)c->partial.p;
     st = timed(c, 1, s, "project_kernel", [&] {
         return launch_project(cap, make_walk(b->kind, b->level, b->d), u, M, S, M, pps,
-                              (int32_t)b->tasks.size(), nsplit, b->d_tasks, b->d_items, partial,
-                              b->nrep, s);
+                              (int32_t)b->tasks.size(), nsplit, b->d_tasks, b->d_items, b->task_max,
+                              partial, b->nrep, s);
     });
     if (st) return st;
     return timed(c, 2, s, "reduce_kernel", [&] {
@@ -1286,7 +1289,7 @@ extern "C" qr_status qr_solve_batched(qr_ctx *c, const qr_problem *p, const qr_b
                 st = timed(c, 1, s, "project_kernel", [&] {
                     return launch_project(depth_cap(ob->max_nnz), make_walk(b->kind, ob->level, ob->d), u, P.M,
                                           S + (int64_t)k * P.M, Mr, pps, (int32_t)ob->tasks.size(), nsplit,
-                                          ob->d_tasks, ob->d_items, partial, ob->nrep, s);
+                                          ob->d_tasks, ob->d_items, ob->task_max, partial, ob->nrep, s);
                 });
                 if (st) return st;
                 st = timed(c, 2, s, "reduce_batched_kernel", [&] {

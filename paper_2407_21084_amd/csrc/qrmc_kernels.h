@@ -7,20 +7,15 @@ namespace qrmc {
 
 constexpr int kPathBlock = 128;   // threads per block of the path / eval kernels
 constexpr int kPathP = 2;         // paths per thread of the value-only path kernel
-// Projection shape (compile-time tunables).
-#ifndef QRMC_PROJ_WAVES
-#define QRMC_PROJ_WAVES 8
-#endif
-#ifndef QRMC_PROJ_CHUNK
-#define QRMC_PROJ_CHUNK 4
-#endif
-#ifndef QRMC_TASK_MAX
-#define QRMC_TASK_MAX 128
-#endif
-constexpr int kProjWaves = QRMC_PROJ_WAVES;  // waves per block of the projection kernel
-constexpr int kProjP = 2;         // paths per lane of the projection kernel (1 where LDS is short)
-constexpr int kProjChunk = QRMC_PROJ_CHUNK;  // nodes per cross-lane reduction of the projection
-constexpr int kTaskMax = QRMC_TASK_MAX;      // nodes per projection task
+// Shape of the projection kernel for a basis of dimension d: paths per lane,
+// waves per block and the largest task (consecutive traversal nodes) a block
+// accumulates.  The widest shape whose LDS (the lanes' phase factors and the
+// waves' task accumulators) fits is taken; the basis cuts its tasks to the
+// same size.
+struct ProjShape {
+    int P, waves, task_max;
+};
+ProjShape proj_shape(int32_t d);
 // coefficient rows (double2, traversal order) are zero-padded to whole
 // 64-node chunks plus two chunks of read-ahead
 __host__ __device__ constexpr int64_t coef_ld(int64_t nrep) { return ((nrep + 63) / 64 + 2) * 64; }
@@ -84,9 +79,11 @@ hipError_t launch_gather(const double *alpha, int32_t row0, int32_t nrows, int64
                          hipStream_t s);
 hipError_t launch_pad(int32_t nrows, int64_t nrep, int64_t ld, double2 *alpha_int, hipStream_t s);
 hipError_t launch_path(int db, int cap, bool grad, const PathArgs &a, hipStream_t s);
+// tasks must have been cut to proj_shape(W.d).task_max nodes (task_max is checked)
 hipError_t launch_project(int cap, const Walk &W, const double2 *e, int64_t lde, const double *S, int64_t M,
                           int64_t paths_per_split, int32_t ntasks, int32_t nsplit, const Task *tasks,
-                          const TaskItem *items, double2 *partial, int64_t nrep, hipStream_t s);
+                          const TaskItem *items, int32_t task_max, double2 *partial, int64_t nrep,
+                          hipStream_t s);
 hipError_t launch_reduce(const double2 *partial, int32_t nsplit, int64_t nrep, double M,
                          double2 *alpha_int_row, double *alpha_row,
                          const int32_t *canon_of_trav, hipStream_t s);
@@ -103,7 +100,6 @@ hipError_t launch_reduce_batched(const double2 *partial, int32_t nsplit, int64_t
                                  double *alpha_row, hipStream_t s);
 hipError_t launch_zero(double *p, int64_t n, hipStream_t s);
 
-size_t project_lds_bytes(int32_t d, int P, int waves);
 
 // step-major path simulation (learned form); x, u SoA [d][M]
 hipError_t launch_sm_start(const DevProblem *P, int32_t i, int64_t M, uint64_t seed, double *x, double2 *e,

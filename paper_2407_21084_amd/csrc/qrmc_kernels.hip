@@ -569,88 +569,148 @@ void path_kernel(
 // per-wave accumulators; the block finally adds its waves in a fixed order
 // and writes the slice's partial sums.
 // ---------------------------------------------------------------------------
+// Cross-lane sums of the projection, four nodes at a time, in registers.
+// The real and imaginary parts of a node are folded across lanes L and L^32
+// (v_permlane32_swap: one half of the wave keeps the real parts, the other the
+// imaginary ones), two such nodes across L^16 (v_permlane16_swap), two pairs
+// across the mirror lane of a row of 16 (DPP row_mirror, bit 3 differs), and
+// the three low lane bits by DPP mirrors and quad permutes.  Each lane then
+// holds the full 64-lane sum of one (node, part) of the group, the same value
+// in eight lanes.  Which one is found once per kernel by running the same folds
+// on indicator values (fold_slot), so nothing depends on which half of a swap
+// keeps which operand.  The order of every addition is fixed.
+__device__ __forceinline__ uint32_t lo32(double x) { return (uint32_t)__double_as_longlong(x); }
+__device__ __forceinline__ uint32_t hi32(double x) {
+    return (uint32_t)((uint64_t)__double_as_longlong(x) >> 32);
+}
+__device__ __forceinline__ double from32(uint32_t lo, uint32_t hi) {
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+// a kept by one half of the wave, b by the other; each lane gets its half's
+// value summed with the partner lane's
+__device__ __forceinline__ double fold32(double a, double b) {
+    const auto l = __builtin_amdgcn_permlane32_swap(lo32(a), lo32(b), false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(hi32(a), hi32(b), false, false);
+    return from32(l[0], h[0]) + from32(l[1], h[1]);
+}
+__device__ __forceinline__ double fold16(double a, double b) {
+    const auto l = __builtin_amdgcn_permlane16_swap(lo32(a), lo32(b), false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(hi32(a), hi32(b), false, false);
+    return from32(l[0], h[0]) + from32(l[1], h[1]);
+}
+constexpr int kDppRowMirror = 0x140;      // lane i <- 15 - i within a row of 16
+constexpr int kDppRowHalfMirror = 0x141;  // lane i <- 7 - i within 8
+constexpr int kDppQuadXor2 = 0x4E;        // quad_perm [2, 3, 0, 1]
+constexpr int kDppQuadXor1 = 0xB1;        // quad_perm [1, 0, 3, 2]
+template <int CTRL>
+__device__ __forceinline__ double dpp_read(double x) {
+    // every source lane of these patterns exists, so bound_ctrl never applies
+    return from32((uint32_t)__builtin_amdgcn_mov_dpp((int)lo32(x), CTRL, 0xf, 0xf, true),
+                  (uint32_t)__builtin_amdgcn_mov_dpp((int)hi32(x), CTRL, 0xf, 0xf, true));
+}
+// lanes with bit 3 clear keep a, the others b; each adds its mirror lane's
+__device__ __forceinline__ double fold8(double a, double b, bool bit3) {
+    const double send = bit3 ? a : b;
+    const double keep = bit3 ? b : a;
+    return keep + dpp_read<kDppRowMirror>(send);
+}
+// plain sum over the eight lanes that differ in bits 0..2
+__device__ __forceinline__ double fold_low(double f) {
+    f += dpp_read<kDppRowHalfMirror>(f);
+    f += dpp_read<kDppQuadXor2>(f);
+    f += dpp_read<kDppQuadXor1>(f);
+    return f;
+}
+// 2 j + part of the sum a lane holds after the folds of nodes j = 0..3
+// (indicators 2^(2j+part) entered on lane 0; every lane of the wave active)
+__device__ __forceinline__ int fold_slot(int lane) {
+    double h[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        h[j] = fold32(lane == 0 ? (double)(1 << (2 * j)) : 0.0, lane == 0 ? (double)(2 << (2 * j)) : 0.0);
+    const double f = fold_low(fold8(fold16(h[0], h[1]), fold16(h[2], h[3]), (lane >> 3) & 1));
+    return __builtin_ctz((uint32_t)f | 256u) & 7;
+}
+
 template <int P>
 struct ProjSink {
     static constexpr bool kGrad = false;
     static constexpr bool kSplit = false;  // measured: slower at d = 10
     struct Acc {};
     __device__ __forceinline__ static void add(Acc &, const Acc &) {}
-    double2 *row;    // this lane's row of the wave buffer: row[c]
-    double2 *wbuf;   // wave buffer [64][kProjChunk + 1]
-    double *acc;     // wave accumulators, doubles [kTaskMax][2]
+    double *acc;     // wave accumulators, doubles [task_max][2]
     double s[P];     // the lane's responses (0 for paths past the slice)
-    int c;           // nodes in the current chunk (wave-uniform)
-    int base;        // task-local index of the chunk's first node (wave-uniform)
-    int lane;
+    double b1, b2;   // folds of the group's first node and of its first pair
+    int c;           // nodes of the current group taken, 0..3 (wave-uniform)
+    int base;        // task-local index of the group's first node (wave-uniform)
+    int slot;        // fold_slot of this lane
+    bool lead;       // one lane of the eight holding a sum adds it to acc
+    bool bit3;
+
+    __device__ __forceinline__ void take(double re, double im) {
+        const double h = fold32(re, im);
+        if (!(c & 1)) {
+            b1 = h;
+        } else {
+            const double g = fold16(b1, h);
+            if (!(c & 2)) {
+                b2 = g;
+            } else {
+                const double f = fold_low(fold8(b2, g, bit3));
+                if (lead) acc[base * 2 + slot] += f;
+                base += 4;
+            }
+        }
+        c = (c + 1) & 3;
+    }
 
     __device__ __forceinline__ void node(const Pts<P> &v, Acc &) {
-        double re = 0.0, im = 0.0;
+        double re = s[0] * v.re[0], im = s[0] * v.im[0];
 #pragma unroll
-        for (int q = 0; q < P; ++q) {
+        for (int q = 1; q < P; ++q) {
             re = fma(s[q], v.re[q], re);
             im = fma(s[q], v.im[q], im);
         }
-        row[c] = make_double2(re, im);
-        if (++c == kProjChunk) flush();
+        take(re, im);
     }
 
-    // Sum the chunk over the 64 lanes.  With V = 2 kProjChunk values (node,
-    // component), lane q adds the V lanes of group q / V for value q % V;
-    // the groups are then combined by xor-shuffles in a fixed order.
+    // complete a partial group with zero nodes
     __device__ __forceinline__ void flush() {
-        constexpr int V = 2 * kProjChunk;
-        static_assert(64 % V == 0, "chunk must divide the wave");
-        wave_sync();
-        const int val = lane % V, rep = val >> 1, grp = lane / V;
-        double sum = 0.0;
-#pragma unroll
-        for (int k = 0; k < V; ++k) {
-            const double2 w = wbuf[(grp * V + k) * (kProjChunk + 1) + rep];
-            sum += (val & 1) ? w.y : w.x;
-        }
-#pragma unroll
-        for (int o = V; o < 64; o <<= 1) sum += __shfl_xor(sum, o);
-        if (lane < V && rep < c) acc[(base + rep) * 2 + (val & 1)] += sum;
-        wave_sync();
-        base += c;
-        c = 0;
+        while (c) take(0.0, 0.0);
     }
 };
 
-size_t project_lds_bytes(int32_t d, int P, int waves) {
-    return (size_t)waves *
-           ((size_t)64 * (kProjChunk + 1) * sizeof(double2) + (size_t)kTaskMax * sizeof(double2) +
-            (size_t)d * 64 * P * sizeof(double2));
+static size_t project_lds_bytes(int32_t d, int P, int waves, int task_max) {
+    return (size_t)waves * ((size_t)task_max * sizeof(double2) + (size_t)d * 64 * P * sizeof(double2));
 }
 
-template <int CAP, int P, int WAVES>
+template <int CAP, int P, int WAVES, int TM>
 __global__ __launch_bounds__(WAVES * 64) void project_kernel(
     const Walk W, const double2 *__restrict__ e_in, const int64_t lde, const double *__restrict__ s_in,
     const int64_t M, const int64_t paths_per_split, const Task *__restrict__ tasks,
     const TaskItem *__restrict__ items, double2 *__restrict__ partial, const int64_t nrep) {
+    static_assert(TM % 4 == 0, "groups of four nodes must tile a task");
     extern __shared__ double2 lds[];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int d = W.d;
-    double2 *bufs = lds;
-    double *accs = reinterpret_cast<double *>(lds + WAVES * 64 * (kProjChunk + 1));
-    double2 *Es = lds + WAVES * 64 * (kProjChunk + 1) + WAVES * kTaskMax;
+    double *accs = reinterpret_cast<double *>(lds);  // [WAVES][TM][2]
+    double2 *Es = lds + WAVES * TM;                 // [WAVES][d][P][64]
 
-    double2 *wbuf = bufs + wave * 64 * (kProjChunk + 1);
-    double *acc = accs + wave * kTaskMax * 2;
+    double *acc = accs + wave * TM * 2;
     const LanePts<P> L{Es + wave * d * P * 64 + lane, nullptr, 64};
 
     const Task task = tasks[blockIdx.x];
     const int64_t m0 = (int64_t)blockIdx.y * paths_per_split;
     const int64_t m1 = min(M, m0 + paths_per_split);
 
-    for (int r = lane; r < kTaskMax * 2; r += 64) acc[r] = 0.0;
+    for (int r = lane; r < TM * 2; r += 64) acc[r] = 0.0;
     wave_sync();
 
     ProjSink<P> sink;
-    sink.row = wbuf + lane * (kProjChunk + 1);
-    sink.wbuf = wbuf;
     sink.acc = acc;
-    sink.lane = lane;
+    sink.slot = fold_slot(lane);
+    sink.lead = (lane & 7) == 0;
+    sink.bit3 = (lane >> 3) & 1;
     for (int64_t gb = m0 + wave * 64 * P; gb < m1; gb += WAVES * 64 * P) {
 #pragma unroll
         for (int q = 0; q < P; ++q) {
@@ -685,7 +745,7 @@ __global__ __launch_bounds__(WAVES * 64) void project_kernel(
     for (int r = tid; r < task.rep_count * 2; r += WAVES * 64) {
         double sacc = 0.0;
 #pragma unroll
-        for (int w = 0; w < WAVES; ++w) sacc += accs[w * kTaskMax * 2 + r];
+        for (int w = 0; w < WAVES; ++w) sacc += accs[w * TM * 2 + r];
         out[r] = sacc;
     }
 }
@@ -1425,41 +1485,52 @@ hipError_t launch_path(int db, int cap, bool grad, const PathArgs &a, hipStream_
     return hipErrorInvalidValue;
 }
 
-template <int CAP, int P, int WAVES>
+template <int CAP, int P, int WAVES, int TM>
 static hipError_t project_t(const Walk &W, const double2 *e, int64_t lde, const double *S, int64_t M, int64_t pps,
                             int32_t ntasks, int32_t nsplit, const Task *tasks,
                             const TaskItem *items, double2 *partial, int64_t nrep, hipStream_t s) {
-    const size_t lds = project_lds_bytes(W.d, P, WAVES);
+    const size_t lds = project_lds_bytes(W.d, P, WAVES, TM);
     static size_t granted = kLdsDefault;
-    const hipError_t err = allow_lds((const void *)project_kernel<CAP, P, WAVES>, lds, granted);
+    const hipError_t err = allow_lds((const void *)project_kernel<CAP, P, WAVES, TM>, lds, granted);
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL((project_kernel<CAP, P, WAVES>), dim3((unsigned)ntasks, (unsigned)nsplit),
+    hipLaunchKernelGGL((project_kernel<CAP, P, WAVES, TM>), dim3((unsigned)ntasks, (unsigned)nsplit),
                        dim3(WAVES * 64), lds, s, W, e, lde, S, M, pps, tasks, items, partial, nrep);
     return hipGetLastError();
 }
 
-// The widest shape whose LDS fits: kProjWaves waves with two paths per lane
-// (small d), then half the waves, then one path per lane.
+// The shapes, widest first: eight waves with two paths per lane and tasks of
+// 256 nodes (small d), four waves with tasks of 512, then one path per lane.
+constexpr ProjShape kProjShapes[3] = {{2, 8, 256}, {2, 4, 512}, {1, 4, 512}};
+
+ProjShape proj_shape(int32_t d) {
+    for (const ProjShape &p : kProjShapes)
+        if (project_lds_bytes(d, p.P, p.waves, p.task_max) <= kLdsMax) return p;
+    return kProjShapes[2];
+}
+
 template <int CAP>
 static hipError_t project_p(const Walk &W, const double2 *e, int64_t lde, const double *S, int64_t M, int64_t pps,
-                            int32_t ntasks, int32_t nsplit, const Task *tasks,
-                            const TaskItem *items, double2 *partial, int64_t nrep, hipStream_t s) {
-    constexpr int Wb = kProjWaves, Wh = kProjWaves / 2 > 0 ? kProjWaves / 2 : 1;
-    if (project_lds_bytes(W.d, kProjP, Wb) <= kLdsMax)
-        return project_t<CAP, kProjP, Wb>(W, e, lde, S, M, pps, ntasks, nsplit, tasks, items, partial, nrep, s);
-    if (project_lds_bytes(W.d, kProjP, Wh) <= kLdsMax)
-        return project_t<CAP, kProjP, Wh>(W, e, lde, S, M, pps, ntasks, nsplit, tasks, items, partial, nrep, s);
-    return project_t<CAP, 1, Wh>(W, e, lde, S, M, pps, ntasks, nsplit, tasks, items, partial, nrep, s);
+                            int32_t ntasks, int32_t nsplit, const Task *tasks, const TaskItem *items,
+                            int32_t task_max, double2 *partial, int64_t nrep, hipStream_t s) {
+    const ProjShape p = proj_shape(W.d);
+    if (task_max != p.task_max || project_lds_bytes(W.d, p.P, p.waves, p.task_max) > kLdsMax)
+        return hipErrorInvalidValue;
+    if (p.waves == 8)
+        return project_t<CAP, 2, 8, 256>(W, e, lde, S, M, pps, ntasks, nsplit, tasks, items, partial, nrep, s);
+    if (p.P == 2)
+        return project_t<CAP, 2, 4, 512>(W, e, lde, S, M, pps, ntasks, nsplit, tasks, items, partial, nrep, s);
+    return project_t<CAP, 1, 4, 512>(W, e, lde, S, M, pps, ntasks, nsplit, tasks, items, partial, nrep, s);
 }
 
 hipError_t launch_project(int cap, const Walk &W, const double2 *e, int64_t lde, const double *S, int64_t M,
                           int64_t paths_per_split, int32_t ntasks, int32_t nsplit, const Task *tasks,
-                          const TaskItem *items, double2 *partial, int64_t nrep, hipStream_t s) {
+                          const TaskItem *items, int32_t task_max, double2 *partial, int64_t nrep,
+                          hipStream_t s) {
     switch (cap) {
-    case 2: return project_p<2>(W, e, lde, S, M, paths_per_split, ntasks, nsplit, tasks, items, partial, nrep, s);
-    case 4: return project_p<4>(W, e, lde, S, M, paths_per_split, ntasks, nsplit, tasks, items, partial, nrep, s);
-    case 6: return project_p<6>(W, e, lde, S, M, paths_per_split, ntasks, nsplit, tasks, items, partial, nrep, s);
-    case 8: return project_p<8>(W, e, lde, S, M, paths_per_split, ntasks, nsplit, tasks, items, partial, nrep, s);
+    case 2: return project_p<2>(W, e, lde, S, M, paths_per_split, ntasks, nsplit, tasks, items, task_max, partial, nrep, s);
+    case 4: return project_p<4>(W, e, lde, S, M, paths_per_split, ntasks, nsplit, tasks, items, task_max, partial, nrep, s);
+    case 6: return project_p<6>(W, e, lde, S, M, paths_per_split, ntasks, nsplit, tasks, items, task_max, partial, nrep, s);
+    case 8: return project_p<8>(W, e, lde, S, M, paths_per_split, ntasks, nsplit, tasks, items, task_max, partial, nrep, s);
     }
     return hipErrorInvalidValue;
 }
