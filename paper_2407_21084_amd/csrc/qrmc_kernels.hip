@@ -1499,8 +1499,10 @@ static hipError_t project_t(const Walk &W, const double2 *e, int64_t lde, const 
 }
 
 // The shapes, widest first: eight waves with two paths per lane and tasks of
-// 256 nodes (small d), four waves with tasks of 512, then one path per lane.
-constexpr ProjShape kProjShapes[3] = {{2, 8, 256}, {2, 4, 512}, {1, 4, 512}};
+// 512 nodes (d <= 6), four waves with tasks of 1024 (d <= 12), then one path
+// per lane.  Larger tasks were measured faster at equal occupancy: fewer
+// restarts of the walk and fewer loads of a cloud slice per node.
+constexpr ProjShape kProjShapes[3] = {{2, 8, 512}, {2, 4, 1024}, {1, 4, 1024}};
 
 ProjShape proj_shape(int32_t d) {
     for (const ProjShape &p : kProjShapes)
@@ -1516,10 +1518,10 @@ static hipError_t project_p(const Walk &W, const double2 *e, int64_t lde, const 
     if (task_max != p.task_max || project_lds_bytes(W.d, p.P, p.waves, p.task_max) > kLdsMax)
         return hipErrorInvalidValue;
     if (p.waves == 8)
-        return project_t<CAP, 2, 8, 256>(W, e, lde, S, M, pps, ntasks, nsplit, tasks, items, partial, nrep, s);
+        return project_t<CAP, 2, 8, 512>(W, e, lde, S, M, pps, ntasks, nsplit, tasks, items, partial, nrep, s);
     if (p.P == 2)
-        return project_t<CAP, 2, 4, 512>(W, e, lde, S, M, pps, ntasks, nsplit, tasks, items, partial, nrep, s);
-    return project_t<CAP, 1, 4, 512>(W, e, lde, S, M, pps, ntasks, nsplit, tasks, items, partial, nrep, s);
+        return project_t<CAP, 2, 4, 1024>(W, e, lde, S, M, pps, ntasks, nsplit, tasks, items, partial, nrep, s);
+    return project_t<CAP, 1, 4, 1024>(W, e, lde, S, M, pps, ntasks, nsplit, tasks, items, partial, nrep, s);
 }
 
 hipError_t launch_project(int cap, const Walk &W, const double2 *e, int64_t lde, const double *S, int64_t M,
