@@ -32,6 +32,40 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # published; packed FP32 (the second half) is not used here
 MFMA_16BIT_PEAK_TFLOPS = 2500.0  # dense bf16 / fp16
 
+# HBM bytes per launch of the path kernel (mean over the launches of one
+# solve), from rocprofv3 FETCH_SIZE and WRITE_SIZE counter runs of
+# `bench.py --steps 1 --warmup 0 --no-cpu-baseline --copy-calibration-mib 256`,
+# scaled by what the same counters read for the plain 256 MiB device copy in
+# that run (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  A figure holds only for the
+# kernel sources it was counted on (their SHA-256); after any change to them
+# the bench reports null until the counters are taken again.
+KERNEL_SOURCES = ("paper_2407_21084_amd/csrc/qrmc_common.h",
+                  "paper_2407_21084_amd/csrc/qrmc_kernels.h",
+                  "paper_2407_21084_amd/csrc/qrmc_kernels.hip")
+COUNTED_TRAFFIC = {
+    # (workload, precision, M): read bytes, written bytes, sources counted on
+    ("d6-hcmax16-allen-cahn", "f64", 1 << 20): (2122228003, 833937293,
+        "beebd51a12b1bd1e77b92351d1e24960912ff308660789dea9145999b16e511e"),
+}
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def counted_traffic(workload: str, precision: str, M: int):
+    """(read + written bytes per launch, detail) if counted on these sources, else (None, None)."""
+    rec = COUNTED_TRAFFIC.get((workload, precision, M))
+    if rec is None or rec[2] != kernel_sources_sha256():
+        return None, None
+    return float(rec[0] + rec[1]), {"read_bytes": rec[0], "written_bytes": rec[1],
+                                    "scaling": "FETCH_SIZE x2.0, WRITE_SIZE x1.0 (256 MiB copy)"}
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -335,6 +369,7 @@ def main():
     u0 = w.sol_A * math.exp(-w.sol_c * w.T) * torch.cos(wv @ xt + w.sol_p)
     rel_l2 = float(torch.linalg.norm(yt - u0) / torch.linalg.norm(u0))
 
+    traffic, traffic_detail = counted_traffic(w.name, args.precision, w.M)
     line = {
         "metric": "basis-evals/s (plain FP64 full solve)" if args.precision == "f64"
                   else f"basis-evals/s ({args.precision} expansion evaluation, full solve)",
@@ -357,11 +392,14 @@ def main():
                                  "reduce": red_ms / args.steps},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": None, "kernel": kernel,
+                     "traffic": traffic, "kernel": kernel,
                      "flops_per_eval": flops_per_eval,
                      "avg_launch_ms": path_ms / max(1, path_n),
                      "project_tflops": proj_tflops},
     }
+    if traffic_detail:
+        line["roofline"]["traffic_unit"] = "bytes per launch"
+        line["roofline"]["traffic_detail"] = traffic_detail
     if mfma:
         line["mfma"] = mfma
     if args.precision != "f64":
