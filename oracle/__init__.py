@@ -23,6 +23,7 @@ MAXN = 256
 
 SET_KINDS = {"tensor": 0, "hc_max": 1, "hc_1p": 2, "total": 3}
 DRIVERS = {"linear": 0, "sin": 1, "allen_cahn": 2, "zrat": 3}
+LAWS = {"logistic": 0, "student2": 1, "cauchy": 2}
 
 
 def build(force: bool = False) -> str:
@@ -35,7 +36,7 @@ def build(force: bool = False) -> str:
 class Problem(C.Structure):
     _fields_ = [
         ("d", C.c_int32), ("nbm", C.c_int32), ("N", C.c_int32), ("driver", C.c_int32),
-        ("f_a", C.c_double), ("clamp", C.c_double),
+        ("nu", C.c_int32), ("f_a", C.c_double), ("clamp", C.c_double),
         ("t", C.c_double * (MAXN + 1)),
         ("b0", C.c_double * MAXD), ("b1", C.c_double * MAXD),
         ("sigma", C.c_double * (MAXD * MAXD)),
@@ -59,16 +60,19 @@ def lib():
             "or_norm_icdf": (D, [D]),
             "or_logistic_cdf": (D, [D]),
             "or_logistic_icdf": (D, [D]),
+            "or_law_cdf": (D, [C.c_int, D]),
+            "or_law_icdf": (D, [C.c_int, D]),
+            "or_law_pdf": (D, [C.c_int, D]),
             "or_enumerate": (I64, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, P, I64]),
-            "or_basis_values": (None, [C.c_int, I64, P, P, P]),
-            "or_eval": (None, [C.c_int, I64, P, P, I64, P, P, P]),
+            "or_basis_values": (None, [C.c_int, C.c_int, I64, P, P, P]),
+            "or_eval": (None, [C.c_int, C.c_int, I64, P, P, I64, P, P, P]),
             "or_msol_u": (D, [P, D, P]),
             "or_msol_h": (D, [P, D, P]),
             "or_path_response": (D, [P, I64, P, I32, U64, U64, P]),
-            "or_project": (None, [C.c_int, I64, P, I64, P, P, P, P]),
+            "or_project": (None, [C.c_int, C.c_int, I64, P, I64, P, P, P, P]),
             "or_backward_step": (C.c_int, [P, I64, P, I32, I64, U64, P, P, P, P]),
             "or_solve": (C.c_int, [P, I64, P, I64, U64, P]),
-            "or_sample_points": (None, [C.c_int, U64, U32, I32, I64, I64, P]),
+            "or_sample_points": (None, [C.c_int, C.c_int, U64, U32, I32, I64, I64, P]),
             "or_errors": (None, [P, I64, P, P, U64, I64, P]),
             "or_num_threads": (C.c_int, []),
         }
@@ -115,6 +119,18 @@ def logistic_icdf(u: float) -> float:
     return lib().or_logistic_icdf(u)
 
 
+def law_cdf(law: str, x: float) -> float:
+    return lib().or_law_cdf(LAWS[law], x)
+
+
+def law_icdf(law: str, u: float) -> float:
+    return lib().or_law_icdf(LAWS[law], u)
+
+
+def law_pdf(law: str, x: float) -> float:
+    return lib().or_law_pdf(LAWS[law], x)
+
+
 # ---------------------------------------------------------------------------
 # index sets and basis
 # ---------------------------------------------------------------------------
@@ -138,33 +154,33 @@ def nfuncs(reps: np.ndarray) -> int:
     return 2 * reps.shape[0] - 1
 
 
-def basis_values(reps: np.ndarray, x) -> np.ndarray:
+def basis_values(reps: np.ndarray, x, law: str = "logistic") -> np.ndarray:
     x = _f64(x)
     reps = np.ascontiguousarray(reps, dtype=np.int32)
     phi = np.zeros(nfuncs(reps))
-    lib().or_basis_values(reps.shape[1], reps.shape[0], _ptr(reps), _ptr(x), _ptr(phi))
+    lib().or_basis_values(reps.shape[1], LAWS[law], reps.shape[0], _ptr(reps), _ptr(x), _ptr(phi))
     return phi
 
 
-def evaluate(reps: np.ndarray, alpha_row, x, grad: bool = False):
+def evaluate(reps: np.ndarray, alpha_row, x, grad: bool = False, law: str = "logistic"):
     reps = np.ascontiguousarray(reps, dtype=np.int32)
     x = _f64(x)
     n, d = x.shape
     y = np.zeros(n)
     g = np.zeros((n, d)) if grad else None
-    lib().or_eval(d, reps.shape[0], _ptr(reps), _ptr(_f64(alpha_row)), n, _ptr(x), _ptr(y),
+    lib().or_eval(d, LAWS[law], reps.shape[0], _ptr(reps), _ptr(_f64(alpha_row)), n, _ptr(x), _ptr(y),
                   _ptr(g) if grad else None)
     return (y, g) if grad else y
 
 
-def project(reps: np.ndarray, x, s, with_abs: bool = False):
+def project(reps: np.ndarray, x, s, with_abs: bool = False, law: str = "logistic"):
     reps = np.ascontiguousarray(reps, dtype=np.int32)
     x = _f64(x)
     s = _f64(s)
     n, d = x.shape
     a = np.zeros(nfuncs(reps))
     ab = np.zeros(nfuncs(reps))
-    lib().or_project(d, reps.shape[0], _ptr(reps), n, _ptr(x), _ptr(s), _ptr(a), _ptr(ab))
+    lib().or_project(d, LAWS[law], reps.shape[0], _ptr(reps), n, _ptr(x), _ptr(s), _ptr(a), _ptr(ab))
     return (a, ab) if with_abs else a
 
 
@@ -177,6 +193,7 @@ def problem(w) -> Problem:
     p = Problem()
     p.d, p.nbm, p.N = w.d, w.nbm, w.N
     p.driver = DRIVERS[w.driver]
+    p.nu = LAWS[w.law]
     p.f_a = w.f_a
     p.clamp = w.clamp
     for j, t in enumerate(w.times):
@@ -243,9 +260,9 @@ def solve(w, reps, M=None, seed=None) -> np.ndarray:
     return alpha
 
 
-def sample_points(d, seed, stream, i, n, m0=0) -> np.ndarray:
+def sample_points(d, seed, stream, i, n, m0=0, law: str = "logistic") -> np.ndarray:
     x = np.zeros((n, d))
-    lib().or_sample_points(d, seed, stream, i, m0, n, _ptr(x))
+    lib().or_sample_points(d, LAWS[law], seed, stream, i, m0, n, _ptr(x))
     return x
 
 

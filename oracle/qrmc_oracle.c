@@ -30,7 +30,11 @@
  * Where the problem statement used here departs from the paper's own
  * experiments (sampling law, basis, index sets, driver, random generator),
  * it is read as follows:
- *   - nu is a product of standard logistic laws, F(x) = 1/(1+e^-x);
+ *   - nu is a product of identical one-dimensional laws, chosen per problem:
+ *     the standard logistic law F(x) = 1/(1+e^-x), or one of the paper's
+ *     own two (Sec. 5): Student's t with mu = 2 in the scaling of Example
+ *     "Student's t-distribution" (density 0.5 (1+x^2)^{-3/2}) and its mu = 1
+ *     case, the Cauchy law (density 1/(pi (1+x^2)));
  *   - the basis is the real Fourier basis on the torus composed with F:
  *     phi_0 = 1, and for each representative k (first non-zero coordinate
  *     positive) sqrt2 cos(2 pi k.F(x)) and sqrt2 sin(2 pi k.F(x));
@@ -59,6 +63,7 @@ typedef struct {
     int32_t N;        /* number of time steps                              */
     int32_t driver;   /* 0: f=h, 1: a sin y + h, 2: y - y^3 + h,
                          3: a|z|^2/(1+|z|^2) + y/(1+y^2) + h              */
+    int32_t nu;       /* sampling law: 0 logistic, 1 Student mu=2, 2 Cauchy  */
     double f_a;       /* driver parameter a                                */
     double clamp;     /* truncation level L of T_L (INFINITY: none)        */
     double t[OR_MAXN + 1];          /* time grid t_0 < ... < t_N           */
@@ -153,7 +158,48 @@ double or_norm_icdf(double u)
 /* Standard logistic law: F(x) = 1/(1+e^{-x}), F^{-1}(u) = ln u - ln(1-u). */
 double or_logistic_cdf(double x) { return 1.0 / (1.0 + exp(-x)); }
 double or_logistic_icdf(double u) { return log(u) - log(1.0 - u); }
-static double or_logistic_pdf_from_cdf(double F) { return F * (1.0 - F); }
+
+/* The one-dimensional marginal nu_l of the sampling law (assumption (A_nu)),
+ * its CDF F and inverse, as functions of the law's code:
+ *   0: standard logistic, density F (1 - F);
+ *   1: Student's t with mu = 2 scaled as in Example "Student's
+ *      t-distribution" (density c_mu (1+x^2)^{-(mu+1)/2}, c_2 = 1/2), whose F
+ *      and F^{-1} are given in closed form in Sec. 5, eq (Fnui:Fnulinv):
+ *      F(x) = (x / sqrt(x^2+1) + 1) / 2, F^{-1}(u) = (u - 1/2) / sqrt(u (1-u));
+ *   2: the mu = 1 case, the Cauchy law of Sec. 5: density 1/(pi (1+x^2)),
+ *      F(x) = 1/2 + atan(x)/pi, F^{-1}(u) = tan(pi (u - 1/2)) = -cot(pi u). */
+double or_law_cdf(int nu, double x)
+{
+    switch (nu) {
+    case 0: return or_logistic_cdf(x);
+    case 1: return 0.5 * (x / sqrt(x * x + 1.0) + 1.0);
+    case 2: return 0.5 + atan(x) / M_PI;
+    }
+    return NAN;
+}
+
+double or_law_icdf(int nu, double u)
+{
+    switch (nu) {
+    case 0: return or_logistic_icdf(u);
+    case 1: return (u - 0.5) / sqrt(u * (1.0 - u));
+    /* tan(pi (u - 1/2)) = -cot(pi u), evaluated away from the pole: near
+     * u = 0 or 1 the product pi (u - 1/2) would lose the small distance to
+     * -+pi/2 to rounding */
+    case 2: return u < 0.5 ? -1.0 / tan(M_PI * u) : 1.0 / tan(M_PI * (1.0 - u));
+    }
+    return NAN;
+}
+
+double or_law_pdf(int nu, double x)
+{
+    switch (nu) {
+    case 0: { double F = or_logistic_cdf(x); return F * (1.0 - F); }
+    case 1: return 0.5 * pow(1.0 + x * x, -1.5);
+    case 2: return 1.0 / (M_PI * (1.0 + x * x));
+    }
+    return NAN;
+}
 
 /* ------------------------------------------------------------------------ */
 /* Index sets (Sec. 2.3.3), taken over Z^d (or N^d when nonneg != 0).       */
@@ -245,10 +291,10 @@ static double or_phase(const int32_t *k, const double *u, int d)
     return th - rint(th);
 }
 
-void or_basis_values(int d, int64_t nrep, const int32_t *reps, const double *x, double *phi)
+void or_basis_values(int d, int nu, int64_t nrep, const int32_t *reps, const double *x, double *phi)
 {
     double u[OR_MAXD];
-    for (int l = 0; l < d; ++l) u[l] = or_logistic_cdf(x[l]);
+    for (int l = 0; l < d; ++l) u[l] = or_law_cdf(nu, x[l]);
     phi[0] = 1.0;
     for (int64_t r = 1; r < nrep; ++r) {
         double th = 2.0 * M_PI * or_phase(reps + r * d, u, d);
@@ -258,15 +304,15 @@ void or_basis_values(int d, int64_t nrep, const int32_t *reps, const double *x, 
 }
 
 /* Expansion ybar(x) = sum_k alpha_k phi_k(x) (eq (yqi:bar:M)) and, when
- * grad != NULL, its x-gradient by the chain rule through F (dF/dx = F(1-F)).
+ * grad != NULL, its x-gradient by the chain rule through F (dF/dx = nu_l).
  * The sum runs in basis order with Neumaier compensation. */
-static double or_expansion(int d, int64_t nrep, const int32_t *reps, const double *alpha,
+static double or_expansion(int d, int nu, int64_t nrep, const int32_t *reps, const double *alpha,
                            const double *x, double *grad)
 {
     double u[OR_MAXD], dudx[OR_MAXD];
     for (int l = 0; l < d; ++l) {
-        u[l] = or_logistic_cdf(x[l]);
-        dudx[l] = or_logistic_pdf_from_cdf(u[l]);
+        u[l] = or_law_cdf(nu, x[l]);
+        dudx[l] = or_law_pdf(nu, x[l]);
     }
     double s = alpha[0], c = 0.0;
     double gs[OR_MAXD], gc[OR_MAXD];
@@ -297,12 +343,12 @@ static double or_expansion(int d, int64_t nrep, const int32_t *reps, const doubl
 }
 
 /* Evaluate ybar (and optionally grad, row-major [n][d]) at n points. */
-void or_eval(int d, int64_t nrep, const int32_t *reps, const double *alpha_row, int64_t n,
+void or_eval(int d, int nu, int64_t nrep, const int32_t *reps, const double *alpha_row, int64_t n,
              const double *x, double *y, double *grad)
 {
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t p = 0; p < n; ++p)
-        y[p] = or_expansion(d, nrep, reps, alpha_row, x + p * d, grad ? grad + p * d : NULL);
+        y[p] = or_expansion(d, nu, nrep, reps, alpha_row, x + p * d, grad ? grad + p * d : NULL);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -394,7 +440,7 @@ static int64_t or_nfuncs(int64_t nrep) { return 2 * nrep - 1; }
 static void or_start_point(const or_problem *P, uint64_t seed, int32_t i, uint64_t m, double *x)
 {
     for (int l = 0; l < P->d; ++l)
-        x[l] = or_logistic_icdf(or_uniform(seed, 0u, m, (uint32_t)i, (uint32_t)l));
+        x[l] = or_law_icdf(P->nu, or_uniform(seed, 0u, m, (uint32_t)i, (uint32_t)l));
 }
 
 /* Response S_i of eq (Sqi:bar:M) along path m, using the expansions
@@ -422,7 +468,7 @@ double or_path_response(const or_problem *P, int64_t nrep, const int32_t *reps, 
         double y;
         int need_z = (P->driver == 3);
         if (j + 1 < N) {
-            y = or_expansion(d, nrep, reps, alpha + (int64_t)(j + 1) * nf, xn,
+            y = or_expansion(d, P->nu, nrep, reps, alpha + (int64_t)(j + 1) * nf, xn,
                              need_z ? grad : NULL);
         } else {
             y = or_g(P, xn);
@@ -439,12 +485,12 @@ double or_path_response(const or_problem *P, int64_t nrep, const int32_t *reps, 
 
 /* Projection (eq (Aqi:bar:M)): alpha_k = (1/n) sum_p s_p phi_k(x_p), and the
  * scale A_k = (1/n) sum_p |s_p phi_k(x_p)|.  x is row-major [n][d]. */
-void or_project(int d, int64_t nrep, const int32_t *reps, int64_t n, const double *x,
+void or_project(int d, int nu, int64_t nrep, const int32_t *reps, int64_t n, const double *x,
                 const double *s, double *alpha, double *absum)
 {
     int64_t nf = or_nfuncs(nrep);
     double *u = (double *)malloc(sizeof(double) * (size_t)(n * d));
-    for (int64_t p = 0; p < n * d; ++p) u[p] = or_logistic_cdf(x[p]);
+    for (int64_t p = 0; p < n * d; ++p) u[p] = or_law_cdf(nu, x[p]);
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t f = 0; f < nf; ++f) {
         int64_t r = (f + 1) / 2;
@@ -487,7 +533,7 @@ int or_backward_step(const or_problem *P, int64_t nrep, const int32_t *reps, int
         or_start_point(P, seed, i, (uint64_t)m, x + m * d);
         S[m] = or_path_response(P, nrep, reps, i, seed, (uint64_t)m, alpha);
     }
-    or_project(d, nrep, reps, M, x, S, alpha + (int64_t)i * nf, absum);
+    or_project(d, P->nu, nrep, reps, M, x, S, alpha + (int64_t)i * nf, absum);
     if (x_out) memcpy(x_out, x, sizeof(double) * (size_t)(M * d));
     if (s_out) memcpy(s_out, S, sizeof(double) * (size_t)M);
     free(x);
@@ -507,13 +553,13 @@ int or_solve(const or_problem *P, int64_t nrep, const int32_t *reps, int64_t M, 
 }
 
 /* nu-distributed points (stream `stream`, time index i), row-major [n][d]. */
-void or_sample_points(int d, uint64_t seed, uint32_t stream, int32_t i, int64_t m0, int64_t n,
-                      double *x)
+void or_sample_points(int d, int nu, uint64_t seed, uint32_t stream, int32_t i, int64_t m0,
+                      int64_t n, double *x)
 {
     for (int64_t p = 0; p < n; ++p)
         for (int l = 0; l < d; ++l)
-            x[p * d + l] = or_logistic_icdf(
-                or_uniform(seed, stream, (uint64_t)(m0 + p), (uint32_t)i, (uint32_t)l));
+            x[p * d + l] = or_law_icdf(
+                nu, or_uniform(seed, stream, (uint64_t)(m0 + p), (uint32_t)i, (uint32_t)l));
 }
 
 /* Error indicators of Sec. 5, eq (mse) (natural logarithms), computed on
@@ -528,8 +574,8 @@ void or_errors(const or_problem *P, int64_t nrep, const int32_t *reps, const dou
     double *x = (double *)malloc(sizeof(double) * (size_t)(n * d));
     double *y = (double *)malloc(sizeof(double) * (size_t)n);
     for (int i = 0; i < N; ++i) {
-        or_sample_points(d, seed, 1u, i, 0, n, x);
-        or_eval(d, nrep, reps, alpha + (int64_t)i * nf, n, x, y, NULL);
+        or_sample_points(d, P->nu, seed, 1u, i, 0, n, x);
+        or_eval(d, P->nu, nrep, reps, alpha + (int64_t)i * nf, n, x, y, NULL);
         double se = 0.0, su = 0.0;
         for (int64_t p = 0; p < n; ++p) {
             double uex = or_msol_u(P, P->t[i], x + p * d);

@@ -322,14 +322,25 @@ def _c1d(a, m):
     return np.trapezoid(f, xs)
 
 
-def _proj_cos_linear(reps, w_vec, p):
+def _c1d_law(law, a, m):
+    """c(a, m) = E[exp(i (a X + 2 pi m F(X)))] for X ~ nu_l of `law`, by the
+    trapezoid rule on [-1000, 1000] with scipy's density and CDF (the tail
+    beyond carries probability < 7e-4 for Cauchy, < 1e-6 for Student)."""
+    dist, sc = LAW_SCIPY[law]
+    xs = np.linspace(-1000, 1000, 1_000_001)
+    F = dist.cdf(sc * xs)
+    f = np.exp(1j * (a * xs + 2 * np.pi * m * F)) * sc * dist.pdf(sc * xs)
+    return np.trapezoid(f, xs)
+
+
+def _proj_cos_linear(reps, w_vec, p, law="logistic"):
     """<cos(w.x + p), phi_k>_nu for every basis function (Lemma 3.1 target)."""
     d = len(w_vec)
     cache = {}
 
     def c(a, m):
         if (a, m) not in cache:
-            cache[(a, m)] = _c1d(a, m)
+            cache[(a, m)] = _c1d(a, m) if law == "logistic" else _c1d_law(law, a, m)
         return cache[(a, m)]
 
     out = np.zeros(O.nfuncs(reps))
@@ -415,3 +426,146 @@ def test_d2_tensor_solve_close_to_projected_solution():
     assert err < 5 * spread + 0.05 * np.linalg.norm(exact)
     mse_max, mse_av, rel0 = O.errors(w, reps, alpha, n=1 << 14)
     assert math.sqrt(floor) - 0.02 < rel0 < math.sqrt(floor + 0.05)
+
+
+# ---------------------------------------------------------------------------
+# sampling laws of the paper's experiments (Sec. 5): Student's t with mu = 2
+# in the scaling of Example "Student's t-distribution" (the law of X/sqrt(mu),
+# X standard t with mu degrees of freedom) and the Cauchy law (mu = 1)
+# ---------------------------------------------------------------------------
+
+LAW_SCIPY = {
+    "logistic": (stats.logistic, 1.0),
+    "student2": (stats.t(2), math.sqrt(2.0)),    # nu = law of X / sqrt(2)
+    "cauchy": (stats.cauchy, 1.0),
+}
+
+
+@pytest.mark.parametrize("law", ["logistic", "student2", "cauchy"])
+def test_law_cdf_icdf_pdf_match_scipy(law):
+    dist, s = LAW_SCIPY[law]
+    for x in np.concatenate([np.linspace(-50, 50, 201), [-1e6, -3.7, 0.0, 1e-9, 2.5, 1e6]]):
+        assert abs(O.law_cdf(law, x) - dist.cdf(s * x)) <= 1e-14, (law, x)
+        assert abs(O.law_pdf(law, x) - s * dist.pdf(s * x)) <= 1e-14 * max(1.0, s * dist.pdf(s * x))
+    # scipy's t quantile is iterative (relative error up to ~1e-11, checked
+    # against a 50-digit evaluation of the closed form); the printed closed
+    # form below pins the oracle's inverse tightly
+    for u in np.concatenate([np.linspace(1e-6, 1 - 1e-6, 101), [2.0 ** -53, 0.5, 0.75]]):
+        ref = dist.ppf(u) / s
+        assert abs(O.law_icdf(law, u) - ref) <= 1e-10 * max(1.0, abs(ref)), (law, u)
+
+
+def test_student2_closed_forms_printed_in_the_paper():
+    """Sec. 5, eq (Fnui:Fnulinv): density 0.5 (1+x^2)^{-3/2}, F(x) = (x/sqrt(x^2+1) + 1)/2 and
+    F^{-1}(u) = -+ sqrt((-u^2+u-0.25)/(u(u-1))) on (0, 1/2] and (1/2, 1)."""
+    for x in np.linspace(-20, 20, 81):
+        assert abs(O.law_pdf("student2", x) - 0.5 * (1 + x * x) ** -1.5) <= 1e-16
+        assert abs(O.law_cdf("student2", x) - 0.5 * (x / math.sqrt(x * x + 1) + 1)) <= 1e-16
+    for u in np.linspace(0.001, 0.999, 333):
+        r = math.sqrt((-u * u + u - 0.25) / (u * (u - 1)))
+        printed = -r if u <= 0.5 else r
+        assert abs(O.law_icdf("student2", u) - printed) <= 1e-13 * max(1.0, abs(printed))
+
+
+def test_cauchy_closed_forms_printed_in_the_paper():
+    """Sec. 5 (mu = 1): density 1/(pi (1+x^2)), F(x) = 0.5 + atan(x)/pi, F^{-1}(u) = tan(pi u - pi/2)."""
+    for x in np.linspace(-20, 20, 81):
+        assert abs(O.law_pdf("cauchy", x) - 1 / (math.pi * (1 + x * x))) <= 1e-16
+        assert abs(O.law_cdf("cauchy", x) - (0.5 + math.atan(x) / math.pi)) <= 1e-16
+    for u in np.linspace(0.001, 0.999, 333):
+        ref = math.tan(math.pi * u - 0.5 * math.pi)
+        assert abs(O.law_icdf("cauchy", u) - ref) <= 1e-12 * max(1.0, abs(ref))
+
+
+@pytest.mark.parametrize("law", ["student2", "cauchy"])
+def test_law_density_integrates_to_cdf(law):
+    """F(b) - F(a) equals the quadrature of the density over [a, b]."""
+    from scipy import integrate
+    for a, b in [(-5.0, 0.0), (0.0, 0.3), (-1.0, 40.0), (2.0, 200.0)]:
+        q, err = integrate.quad(lambda x: O.law_pdf(law, x), a, b, epsabs=1e-14, epsrel=1e-13)
+        assert abs((O.law_cdf(law, b) - O.law_cdf(law, a)) - q) < 1e-12
+
+
+@pytest.mark.parametrize("law", ["student2", "cauchy"])
+def test_basis_orthonormal_in_L2_nu(law):
+    """Lemma 2.1: phi_k o F is orthonormal in L2(nu); 1-D quadrature over R of
+    phi_j(x) phi_k(x) nu(x) for |k| <= 3 (substituting x = tan(theta) so the
+    heavy tails sit on a finite interval)."""
+    from scipy import integrate
+    reps = O.enumerate_set(1, "tensor", 3)
+    nf = O.nfuncs(reps)
+
+    def gram_entry(j, k):
+        def f(th):
+            x = math.tan(th)
+            phi = O.basis_values(reps, [x], law=law)
+            return phi[j] * phi[k] * O.law_pdf(law, x) / math.cos(th) ** 2
+        return integrate.quad(f, -math.pi / 2, math.pi / 2, limit=400, epsabs=1e-11)[0]
+
+    G = np.array([[gram_entry(j, k) for k in range(nf)] for j in range(nf)])
+    assert np.abs(G - np.eye(nf)).max() < 1e-8
+
+
+@pytest.mark.parametrize("law", ["student2", "cauchy"])
+def test_law_samples_kolmogorov_smirnov(law):
+    """Stream-1 points of the law pass a KS test against scipy's distribution."""
+    dist, s = LAW_SCIPY[law]
+    x = O.sample_points(2, 5, 1, 3, 1 << 14, law=law)
+    for l in range(2):
+        assert stats.kstest(s * x[:, l], dist.cdf).pvalue > 1e-3
+
+
+@pytest.mark.parametrize("law", ["student2", "cauchy"])
+def test_expansion_gradient_by_finite_differences_other_laws(law):
+    """The chain rule through F uses the law's density."""
+    d = 3
+    reps = O.enumerate_set(d, "hc_1p", 8)
+    alpha = W.synthetic_alpha(O.nfuncs(reps), 1, seed=3)[0]
+    x = W.law_points(5, d, law, seed=2)
+    y, g = O.evaluate(reps, alpha, x, grad=True, law=law)
+    for l in range(d):
+        for p in range(x.shape[0]):
+            h = 1e-6 * max(1.0, abs(x[p, l]))
+            e = np.zeros(d)
+            e[l] = h
+            fd = (O.evaluate(reps, alpha, x[p:p + 1] + e, law=law)[0]
+                  - O.evaluate(reps, alpha, x[p:p + 1] - e, law=law)[0]) / (2 * h)
+            assert abs(fd - g[p, l]) < 1e-6 * max(1, np.abs(g).max())
+    assert np.allclose(y, [O.basis_values(reps, xi, law=law) @ alpha for xi in x], atol=1e-13)
+
+
+@pytest.mark.parametrize("law", ["student2", "cauchy"])
+def test_projection_recovers_coefficients_other_laws(law):
+    """Quasi-regression (eq (Aqi:bar:M)) is unbiased under nu: with points
+    drawn from nu and responses s = sum_k c_k phi_k(x), the projection
+    converges to c (Monte-Carlo error within 6 standard errors)."""
+    reps = O.enumerate_set(2, "tensor", 2)
+    nf = O.nfuncs(reps)
+    c = W.synthetic_alpha(nf, 1, seed=9)[0]
+    X = O.sample_points(2, 7, 1, 0, 1 << 15, law=law)
+    Phi = np.array([O.basis_values(reps, x, law=law) for x in X])
+    s = Phi @ c
+    a = O.project(reps, X, s, law=law)
+    se = (Phi * s[:, None]).std(axis=0) / math.sqrt(X.shape[0])
+    assert np.all(np.abs(a - c) <= 6 * se + 1e-15)
+    assert np.allclose(a, (Phi * s[:, None]).mean(axis=0), atol=1e-13)
+
+
+@pytest.mark.parametrize("law", ["student2", "cauchy"])
+def test_linear_driver_unbiased_alpha_other_laws(law):
+    """Lemma 3.1 under the paper's own sampling laws: E[alpha_{i,k}] is the
+    L2(nu) projection of the closed-form y_i (1-D factors by quadrature
+    against scipy's density and CDF)."""
+    w = W.D2_TENSOR4.with_(driver="linear", f_a=0.0, sol_p=0.2, sol_w=[1.0, 0.5], law=law)
+    reps = O.reps_for(w)
+    M = 1 << 14
+    i = 8
+    alpha = np.zeros((w.N, O.nfuncs(reps)))
+    a, _, x, s = O.backward_step(w, reps, i, M, 0, alpha, want_x=True, want_s=True)
+    exp = w.sol_A * _kappa(w, i) * _proj_cos_linear(reps, w.sol_w, w.sol_p, law=law)
+    Phi = np.array([O.basis_values(reps, xi, law=law) for xi in x])
+    sd = (Phi * s[:, None]).std(axis=0) / math.sqrt(M)
+    assert np.all(np.abs(a - exp) <= 5 * sd + 1e-3)
+    assert np.abs(exp).max() > 0.05
+    # start points come from stream 0 through this law's F^{-1}
+    assert x[17, 1] == O.law_icdf(law, O.uniform(0, 0, 17, i, 1))

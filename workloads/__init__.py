@@ -11,7 +11,9 @@ semi-linear PDE) solved with Algorithm 1 (GQRMDP):
 * state dimension ``d`` with ``nbm`` Brownian dimensions, uniform grid
   ``t_j = j T / N`` (Sec. 2.1.1 uses N equidistant steps);
 * drift ``b(t,x)_l = b0_l + b1_l x_l``, constant diffusion ``sigma`` (d x nbm);
-* sampling law nu: product of standard logistic laws;
+* sampling law nu: product of identical one-dimensional laws, ``logistic``
+  (standard logistic, the default), ``student2`` (Student's t with mu = 2 in
+  the paper's scaling, density 0.5 (1+x^2)^{-3/2}) or ``cauchy``;
 * index set over Z^d: ``tensor`` (max |k_l| <= level), ``hc_max``
   (prod max(1,|k_l|) <= level) or ``hc_1p`` (prod (1+|k_l|) <= level);
 * driver ``f = f_nl(y, z) + h(t, x)`` where h makes the manufactured
@@ -27,6 +29,7 @@ import numpy as np
 
 SET_KINDS = {"tensor": 0, "hc_max": 1, "hc_1p": 2}
 DRIVERS = {"linear": 0, "sin": 1, "allen_cahn": 2, "zrat": 3}
+LAWS = {"logistic": 0, "student2": 1, "cauchy": 2}
 
 
 @dataclass(frozen=True)
@@ -49,6 +52,7 @@ class Workload:
     sol_w: List[float]
     clamp: float = math.inf
     seed: int = 0
+    law: str = "logistic"
     notes: str = ""
 
     @property
@@ -159,6 +163,20 @@ def logistic_points(n: int, d: int, seed: int) -> np.ndarray:
     (numpy's own generator; independent of the method's Philox streams)."""
     rng = np.random.default_rng(seed)
     return rng.logistic(0.0, 1.0, size=(n, d))
+
+
+def law_points(n: int, d: int, law: str, seed: int) -> np.ndarray:
+    """n points of the product law ``law``, row-major [n][d] (numpy's own
+    generators: logistic, Student's t with 2 degrees of freedom divided by
+    sqrt 2, standard Cauchy; independent of the method's Philox streams)."""
+    rng = np.random.default_rng(seed)
+    if law == "logistic":
+        return rng.logistic(0.0, 1.0, size=(n, d))
+    if law == "student2":
+        return rng.standard_t(2.0, size=(n, d)) / math.sqrt(2.0)
+    if law == "cauchy":
+        return rng.standard_cauchy(size=(n, d))
+    raise ValueError(f"unknown law {law!r}")
 
 
 def responses(n: int, seed: int) -> np.ndarray:
