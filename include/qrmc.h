@@ -27,8 +27,10 @@
  *  - Decoupled FBSDE / semi-linear PDE of Sec. 1, eqs (fbsde), (eds), (pde):
  *    drift b, diffusion sigma, driver f, terminal condition g, horizon T.
  *  - Time grid t_0 < ... < t_N (Sec. 2.1.1), Euler scheme eq (markov:euler).
- *  - Sampling law nu of assumption (A_nu): here a product of standard
- *    logistic laws, F(x) = 1/(1+e^{-x}).
+ *  - Sampling law nu of assumption (A_nu): a product of identical
+ *    one-dimensional laws with CDF F, chosen per basis (qr_law): the
+ *    standard logistic law F(x) = 1/(1+e^{-x}) (default), or the paper's own
+ *    Student's t law with mu = 2 and Cauchy law (Sec. 5).
  *  - Basis (Sec. 2.2, Lemma 2.1 with the Fourier basis of the torus):
  *    phi_0 = 1 and, for each representative k of {k,-k} (first non-zero
  *    coordinate positive), sqrt2 cos(2 pi k.F(x)) and sqrt2 sin(2 pi k.F(x)),
@@ -93,12 +95,36 @@ typedef enum {
 
 typedef struct qr_basis qr_basis; /* opaque, library-owned */
 
+/* One-dimensional marginal nu_l of the sampling law (assumption (A_nu)).
+ * The paper's experiments use Student's t laws (Example "Student's
+ * t-distribution", Sec. 5, eq (Fnui:Fnulinv)):
+ *   QR_LAW_LOGISTIC: F(x) = 1/(1+e^{-x}), F^{-1}(u) = ln u - ln(1-u);
+ *   QR_LAW_STUDENT2: mu = 2, density (1+x^2)^{-3/2}/2,
+ *                    F(x) = (1 + x/sqrt(1+x^2))/2, F^{-1}(u) = (u-1/2)/sqrt(u(1-u));
+ *   QR_LAW_CAUCHY:   mu = 1, density 1/(pi (1+x^2)),
+ *                    F(x) = 1/2 + atan(x)/pi, F^{-1}(u) = tan(pi (u - 1/2)). */
+typedef enum {
+    QR_LAW_LOGISTIC = 0,
+    QR_LAW_STUDENT2 = 1,
+    QR_LAW_CAUCHY = 2
+} qr_law;
+
 /* Build the index set of kind `kind` and level `level` in dimension d
  * (1 <= d <= QR_MAX_D; level >= 0 for the tensor set, level >= 1 for the
  * hyperbolic crosses, whose sets are empty below 1) and its basis metadata.
  * Host only; no device is touched.  *out receives a handle to free with
  * qr_basis_free.  QR_ERANGE if the set has more than 2^31 representatives. */
 qr_status qr_build_basis(int32_t d, int32_t kind, int32_t level, qr_basis **out);
+
+/* As qr_build_basis, for the sampling law `law` (qr_law; QR_EINVAL if
+ * unknown).  The basis functions in x are phi_k o F_law (Lemma 2.1), and every
+ * call that takes this basis draws its start points X_i ~ nu (Algorithm 1)
+ * and maps points to the cube with this law.  qr_build_basis is this call
+ * with QR_LAW_LOGISTIC. */
+qr_status qr_build_basis_law(int32_t d, int32_t kind, int32_t level, int32_t law, qr_basis **out);
+
+/* The sampling law of a basis (qr_law) into *law. */
+qr_status qr_basis_law(const qr_basis *b, int32_t *law);
 
 /* n_funcs = |Gamma| (real basis functions), n_reps = representatives
  * (n_funcs = 2 n_reps - 1), max_nnz = largest number of non-zero
@@ -218,6 +244,11 @@ qr_status qr_path_responses(qr_ctx *ctx, const qr_problem *prob, const qr_basis 
 qr_status qr_sample_points(qr_ctx *ctx, int32_t d, uint64_t seed, uint32_t stream_id, int32_t i,
                            int64_t m0, int64_t n, double *x, void *stream);
 
+/* As qr_sample_points, with F^{-1} of the law `law` (qr_law) instead of the
+ * logistic law's. */
+qr_status qr_sample_points_law(qr_ctx *ctx, int32_t law, int32_t d, uint64_t seed, uint32_t stream_id,
+                               int32_t i, int64_t m0, int64_t n, double *x, void *stream);
+
 /* ---------------------------------------------------------------------- */
 /* Reduced-precision form                                                  */
 /* ---------------------------------------------------------------------- */
@@ -250,7 +281,8 @@ qr_status qr_solve_prec(qr_ctx *ctx, const qr_problem *prob, const qr_basis *bas
  * W1 [256][16] (row = output unit), b1 [256], W2 [256][256], b2 [256],
  * w3 [256], b3 [1].  Products run on the matrix cores with bfloat16 operands
  * and FP32 accumulation.  Features of a state x: 2 F(x_l) - 1 for l < d and
- * 0 up to 16 (d <= 16). */
+ * 0 up to 16 (d <= 16), F of the basis's sampling law in qr_solve_learned and
+ * of the logistic law in qr_mlp_features. */
 #define QR_MLP_IN 16
 #define QR_MLP_HIDDEN 256
 #define QR_MLP_NPARAMS (QR_MLP_HIDDEN * QR_MLP_IN + QR_MLP_HIDDEN + QR_MLP_HIDDEN * QR_MLP_HIDDEN + \

@@ -48,6 +48,7 @@ extern "C" const char *qr_version(void) { return "qrmc 0.1 (gfx950)"; }
 // ---------------------------------------------------------------------------
 struct qr_basis {
     int32_t d = 0, kind = 0, level = 0;
+    int32_t law = QR_LAW_LOGISTIC;       // sampling law nu (qr_law)
     int64_t nrep = 0;
     int32_t max_nnz = 0;
     std::vector<int32_t> trav;           // [nrep][d] traversal order
@@ -171,6 +172,10 @@ void build_tasks(const std::vector<TaskItem> &nodes, const std::vector<int64_t> 
 }  // namespace
 
 extern "C" qr_status qr_build_basis(int32_t d, int32_t kind, int32_t level, qr_basis **out) {
+    return qr_build_basis_law(d, kind, level, QR_LAW_LOGISTIC, out);
+}
+
+extern "C" qr_status qr_build_basis_law(int32_t d, int32_t kind, int32_t level, int32_t law, qr_basis **out) {
     if (!out) return fail(QR_EINVAL, "qr_build_basis: out is NULL");
     *out = nullptr;
     if (d < 1 || d > QR_MAX_D) return fail(QR_EINVAL, "qr_build_basis: d=%d outside [1,%d]", d, QR_MAX_D);
@@ -179,12 +184,15 @@ extern "C" qr_status qr_build_basis(int32_t d, int32_t kind, int32_t level, qr_b
     if (level < 0 || level > (1 << 20)) return fail(QR_EINVAL, "qr_build_basis: level=%d out of range", level);
     if (level < 1 && kind != QR_SET_TENSOR)
         return fail(QR_EINVAL, "qr_build_basis: a hyperbolic cross of level %d is empty", level);
+    if (law < QR_LAW_LOGISTIC || law > QR_LAW_CAUCHY)
+        return fail(QR_EINVAL, "qr_build_basis: unknown sampling law %d", law);
 
     qr_basis *b = new (std::nothrow) qr_basis();
     if (!b) return fail(QR_ENOMEM, "qr_build_basis: out of host memory");
     b->d = d;
     b->kind = kind;
     b->level = level;
+    b->law = law;
     std::vector<int64_t> subtree;
     std::vector<TaskItem> nodes;
     try {
@@ -219,6 +227,12 @@ extern "C" qr_status qr_build_basis(int32_t d, int32_t kind, int32_t level, qr_b
         return fail(QR_ENOMEM, "qr_build_basis: out of host memory");
     }
     *out = b;
+    return QR_OK;
+}
+
+extern "C" qr_status qr_basis_law(const qr_basis *b, int32_t *law) {
+    if (!b || !law) return fail(QR_EINVAL, "qr_basis_law: NULL argument");
+    *law = b->law;
     return QR_OK;
 }
 
@@ -279,7 +293,7 @@ static qr_status sub_basis(qr_basis *b, int32_t d2, int32_t level2, qr_basis **o
             return QR_OK;
         }
     qr_basis *sb = nullptr;
-    qr_status st = qr_build_basis(d2, b->kind, level2, &sb);
+    qr_status st = qr_build_basis_law(d2, b->kind, level2, b->law, &sb);
     if (st) return st;
     try {
         sb->ft.resize(sb->nrep);
@@ -540,12 +554,16 @@ static int dim_bucket(int32_t d, int32_t nbm) {
     return m <= 4 ? 4 : (m <= 8 ? 8 : 16);
 }
 
-static qr_status upload_problem(qr_ctx *c, const qr_problem *p, hipStream_t s) {
+// The device copy of the problem also carries the sampling law of the basis
+// used with it, so the path kernels read it from memory per step instead of
+// keeping it in a register across the basis traversal.
+static qr_status upload_problem(qr_ctx *c, const qr_problem *p, int32_t law, hipStream_t s) {
     DevProblem h{};
     h.d = p->d;
     h.nbm = p->nbm;
     h.N = p->N;
     h.driver = p->driver;
+    h.nu = law;
     h.f_a = p->f_a;
     h.clamp = p->clamp;
     h.T = p->t[p->N];
@@ -613,7 +631,7 @@ static qr_status project_and_reduce(qr_ctx *c, const qr_basis *b, const double2 
     const int cap = depth_cap(b->max_nnz);
     double2 *partial = (double2 *)c->partial.p;
     st = timed(c, 1, s, "project_kernel", [&] {
-        return launch_project(cap, make_walk(b->kind, b->level, b->d), u, M, S, M, pps,
+        return launch_project(cap, make_walk(b->kind, b->level, b->d, b->law), u, M, S, M, pps,
                               (int32_t)b->tasks.size(), nsplit, b->d_tasks, b->d_items, b->task_max,
                               partial, b->nrep, s);
     });
@@ -631,7 +649,7 @@ static qr_status run_path(qr_ctx *c, const qr_problem *p, const qr_basis *b, int
     const int64_t ldx = path_state_ld(M, grad);
     qr_status st = ensure(c, c->xstate, sizeof(double) * (size_t)p->d * ldx, "path state");
     if (st) return st;
-    PathArgs a{c->d_prob, make_walk(b->kind, b->level, b->d), i, M, seed, alpha_int, b->ld(), S, u, x0,
+    PathArgs a{c->d_prob, make_walk(b->kind, b->level, b->d, b->law), i, M, seed, alpha_int, b->ld(), S, u, x0,
                (double *)c->xstate.p, ldx};
     return timed(c, 0, s, "path_kernel", [&] {
         return launch_path(dim_bucket(p->d, p->nbm), depth_cap(b->max_nnz), p->driver == QR_F_ZRAT,
@@ -651,7 +669,7 @@ static qr_status prepare(qr_ctx *c, const qr_problem *p, qr_basis *b, int64_t M,
     if ((st = check_basis_device(b))) return st;
     if ((st = check_M(M))) return st;
     if ((st = basis_on_device(b, c->dev))) return st;
-    if ((st = upload_problem(c, p, (hipStream_t)stream))) return st;
+    if ((st = upload_problem(c, p, b->law, (hipStream_t)stream))) return st;
     if ((st = ensure(c, c->S, sizeof(double) * (size_t)M, "S"))) return st;
     if ((st = ensure(c, c->u, sizeof(double2) * (size_t)M * p->d, "phase factors"))) return st;
     if ((st = ensure(c, c->alpha_int, sizeof(double2) * (size_t)p->N * b->ld(), "alpha"))) return st;
@@ -730,7 +748,7 @@ extern "C" qr_status qr_project(qr_ctx *c, const qr_basis *bc, int64_t n, const 
     if ((st = ensure(c, c->row, sizeof(double2) * (size_t)b->ld(), "row"))) return st;
     hipStream_t s = (hipStream_t)stream;
     double2 *u = (double2 *)c->u.p;
-    QR_HIP(launch_x_to_e(b->d, x, n, u, s), "x_to_e_kernel");
+    QR_HIP(launch_x_to_e(b->law, b->d, x, n, u, s), "x_to_e_kernel");
     return project_and_reduce(c, b, u, s_in, n, (double2 *)c->row.p, alpha_row, s);
 }
 
@@ -750,7 +768,7 @@ extern "C" qr_status qr_eval(qr_ctx *c, const qr_basis *bc, const double *alpha_
     const int64_t nf = 2 * b->nrep - 1;
     QR_HIP(launch_pad(1, b->nrep, b->ld(), row, s), "pad_kernel");
     QR_HIP(launch_gather(alpha_row, 0, 1, b->nrep, b->ld(), nf, b->d_canon_of_trav, row, s), "gather_kernel");
-    QR_HIP(launch_eval(depth_cap(b->max_nnz), grad != nullptr, make_walk(b->kind, b->level, b->d), row, x,
+    QR_HIP(launch_eval(depth_cap(b->max_nnz), grad != nullptr, make_walk(b->kind, b->level, b->d, b->law), row, x,
                        n, y, grad, s),
            "eval_kernel");
     return QR_OK;
@@ -758,11 +776,19 @@ extern "C" qr_status qr_eval(qr_ctx *c, const qr_basis *bc, const double *alpha_
 
 extern "C" qr_status qr_sample_points(qr_ctx *c, int32_t d, uint64_t seed, uint32_t stream_id,
                                       int32_t i, int64_t m0, int64_t n, double *x, void *stream) {
+    return qr_sample_points_law(c, QR_LAW_LOGISTIC, d, seed, stream_id, i, m0, n, x, stream);
+}
+
+extern "C" qr_status qr_sample_points_law(qr_ctx *c, int32_t law, int32_t d, uint64_t seed,
+                                          uint32_t stream_id, int32_t i, int64_t m0, int64_t n, double *x,
+                                          void *stream) {
     qr_status st = begin(c, stream);
     if (st) return st;
+    if (law < QR_LAW_LOGISTIC || law > QR_LAW_CAUCHY)
+        return fail(QR_EINVAL, "qr_sample_points: unknown sampling law %d", law);
     if (d < 1 || d > QR_MAX_D) return fail(QR_EINVAL, "qr_sample_points: d=%d", d);
     if (n < 0 || m0 < 0 || !x) return fail(QR_EINVAL, "qr_sample_points: bad n/m0/x");
-    QR_HIP(launch_sample(d, seed, stream_id, i, m0, n, x, (hipStream_t)stream), "sample_kernel");
+    QR_HIP(launch_sample(law, d, seed, stream_id, i, m0, n, x, (hipStream_t)stream), "sample_kernel");
     return QR_OK;
 }
 
@@ -806,7 +832,7 @@ static qr_status pack_row(qr_ctx *c, const qr_problem *p, const qr_basis *b, int
 
 static qr_status run_mfma_path(qr_ctx *c, const qr_problem *p, const qr_basis *b, int32_t prec,
                                const TilePlan &tp, int32_t i, int64_t M, uint64_t seed, hipStream_t s) {
-    MfmaArgs a{c->d_prob, make_walk(b->kind, b->level, b->d), i, M, seed, (const uint2 *)c->tiles.p, tp.ld,
+    MfmaArgs a{c->d_prob, make_walk(b->kind, b->level, b->d, b->law), i, M, seed, (const uint2 *)c->tiles.p, tp.ld,
                (double *)c->S.p, (double2 *)c->u.p};
     return timed(c, 0, s, "mfma_path_kernel", [&] {
         return launch_mfma_path(dim_bucket(p->d, p->nbm), depth_cap(b->max_nnz), p->driver == QR_F_ZRAT, prec,
@@ -959,7 +985,7 @@ extern "C" qr_status qr_mlp_features(qr_ctx *c, int32_t d, int64_t n, const doub
     if (n < 0) return fail(QR_EINVAL, "qr_mlp_features: n < 0");
     if (n == 0) return QR_OK;
     if (!x || !feat) return fail(QR_EINVAL, "qr_mlp_features: NULL argument");
-    QR_HIP(launch_features(d, n, x, n, feat, (hipStream_t)stream), "features_kernel");
+    QR_HIP(launch_features(QR_LAW_LOGISTIC, d, n, x, n, feat, (hipStream_t)stream), "features_kernel");
     return QR_OK;
 }
 
@@ -1018,11 +1044,11 @@ static qr_status fit_surrogate(qr_ctx *c, const qr_problem *p, const qr_basis *b
     double *tx = (double *)c->ltx.p, *tt = (double *)c->ltt.p, *hx = (double *)c->lhx.p, *ht = (double *)c->lht.p;
     float *tf = (float *)c->ltf.p, *ff = (float *)c->lff.p, *hf = (float *)c->lhf.p, *hy = (float *)c->lhy.p;
     const double2 *row = (const double2 *)c->alpha_int.p + (int64_t)j * b->ld();
-    const Walk W = make_walk(b->kind, b->level, b->d);
+    const Walk W = make_walk(b->kind, b->level, b->d, b->law);
     const int cap = depth_cap(b->max_nnz);
     // pairs (X, ybar_j(X)): training from stream 2, held-out from stream 3, at time index j
-    QR_HIP(launch_sample(d, seed, 2u, j, 0, nt, tx, s), "sample_kernel");
-    QR_HIP(launch_sample(d, seed, 3u, j, 0, nh, hx, s), "sample_kernel");
+    QR_HIP(launch_sample(b->law, d, seed, 2u, j, 0, nt, tx, s), "sample_kernel");
+    QR_HIP(launch_sample(b->law, d, seed, 3u, j, 0, nh, hx, s), "sample_kernel");
     st = timed(c, 0, s, "eval_kernel", [&] { return launch_eval(cap, false, W, row, tx, nt, tt, nullptr, s); });
     if (st) return st;
     st = timed(c, 0, s, "eval_kernel", [&] { return launch_eval(cap, false, W, row, hx, nh, ht, nullptr, s); });
@@ -1037,8 +1063,8 @@ static qr_status fit_surrogate(qr_ctx *c, const qr_problem *p, const qr_basis *b
     *mu = mean;
     *sigma = sd;
     QR_HIP(launch_to_float(nt, tt, mean, 1.0 / sd, tf, s), "to_float_kernel");
-    QR_HIP(launch_features(d, nt, tx, nt, ff, s), "features_kernel");
-    QR_HIP(launch_features(d, nh, hx, nh, hf, s), "features_kernel");
+    QR_HIP(launch_features(b->law, d, nt, tx, nt, ff, s), "features_kernel");
+    QR_HIP(launch_features(b->law, d, nh, hx, nh, hf, s), "features_kernel");
     // Adam over mini-batches in a fixed order
     QR_HIP(launch_mlp_init(th, seed ^ (0x9E3779B97F4A7C15ull * (uint64_t)(j + 1)), s), "mlp_init_kernel");
     QR_HIP(launch_zero((double *)c->lm.p, kMlpParams / 2 + 1, s), "zero_kernel");
@@ -1116,7 +1142,7 @@ extern "C" qr_status qr_solve_learned(qr_ctx *c, const qr_problem *p, const qr_b
     for (int j = 0; j < N; ++j) report[j] = qr_learn_report{0.0, 0.0, 0, 0};
     const int db = dim_bucket(p->d, p->nbm);
     const int cap = depth_cap(b->max_nnz);
-    const Walk W = make_walk(b->kind, b->level, b->d);
+    const Walk W = make_walk(b->kind, b->level, b->d, b->law);
     double *x = (double *)c->lx.p, *H = (double *)c->lh.p, *y = (double *)c->ly.p;
     double *S = (double *)c->S.p;
     double2 *u = (double2 *)c->u.p;
@@ -1124,7 +1150,7 @@ extern "C" qr_status qr_solve_learned(qr_ctx *c, const qr_problem *p, const qr_b
     float *params = (float *)c->lparams.p;
     const int64_t nf = 2 * b->nrep - 1;
     for (int32_t i = N - 1; i >= 0; --i) {
-        QR_HIP(launch_sm_start(c->d_prob, i, M, seed, x, u, S, s), "sm_start_kernel");
+        QR_HIP(launch_sm_start(c->d_prob, b->law, i, M, seed, x, u, S, s), "sm_start_kernel");
         for (int32_t j = i; j < N; ++j) {
             QR_HIP(launch_sm_euler(db, c->d_prob, i, j, M, seed, x, H, s), "sm_euler_kernel");
             if (j + 1 == N) {
@@ -1133,7 +1159,7 @@ extern "C" qr_status qr_solve_learned(qr_ctx *c, const qr_problem *p, const qr_b
                 const float *th = params + (int64_t)(j + 1) * kMlpParams;
                 for (int64_t m0 = 0; m0 < M; m0 += kMlpChunk) {
                     const int64_t k = std::min(kMlpChunk, M - m0);
-                    QR_HIP(launch_features(d, k, x + m0, M, (float *)c->mf.p, s), "features_kernel");
+                    QR_HIP(launch_features(b->law, d, k, x + m0, M, (float *)c->mf.p, s), "features_kernel");
                     st = timed(c, 0, s, "mlp forward",
                                [&] { return mlp_fwd(c, th, k, (const float *)c->mf.p, (float *)c->my.p, s); });
                     if (st) return st;
@@ -1245,7 +1271,7 @@ extern "C" qr_status qr_solve_batched(qr_ctx *c, const qr_problem *p, const qr_b
     if ((st = basis_on_device(b, c->dev))) return st;
     for (qr_basis *sb : b->subs)
         if ((st = basis_on_device(sb, c->dev))) return st;
-    if ((st = upload_problem(c, p, s))) return st;
+    if ((st = upload_problem(c, p, b->law, s))) return st;
     if ((st = ensure(c, c->S, sizeof(double) * (size_t)Mmax * kBatchRT, "S"))) return st;
     if ((st = ensure(c, c->u, sizeof(double2) * (size_t)Mmax * p->d, "phase factors"))) return st;
     if ((st = ensure(c, c->alpha_b, sizeof(double2) * (size_t)total, "batch coefficients"))) return st;
@@ -1274,7 +1300,7 @@ extern "C" qr_status qr_solve_batched(qr_ctx *c, const qr_problem *p, const qr_b
         for (int ps = 0; ps < npass; ++ps) {
             const PassPlan &P = passes[ps];
             const int64_t ld = P.walk->ld();
-            BatchArgs a{c->d_prob, p->d, c->d_batch, ps, make_walk(b->kind, P.level, P.d), i, P.M, seed,
+            BatchArgs a{c->d_prob, p->d, c->d_batch, ps, make_walk(b->kind, P.level, P.d, b->law), i, P.M, seed,
                         ab + P.off, ld, S, u};
             st = timed(c, 0, s, "batched_path_kernel",
                        [&] { return launch_batched_path(db, depth_cap(P.walk->max_nnz), a, s); });
@@ -1287,7 +1313,7 @@ extern "C" qr_status qr_solve_batched(qr_ctx *c, const qr_problem *p, const qr_b
                 int64_t pps;
                 split_plan(ob, Mr, &nsplit, &pps);
                 st = timed(c, 1, s, "project_kernel", [&] {
-                    return launch_project(depth_cap(ob->max_nnz), make_walk(b->kind, ob->level, ob->d), u, P.M,
+                    return launch_project(depth_cap(ob->max_nnz), make_walk(b->kind, ob->level, ob->d, b->law), u, P.M,
                                           S + (int64_t)k * P.M, Mr, pps, (int32_t)ob->tasks.size(), nsplit,
                                           ob->d_tasks, ob->d_items, ob->task_max, partial, ob->nrep, s);
                 });

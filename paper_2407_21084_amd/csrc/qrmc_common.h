@@ -143,6 +143,41 @@ __host__ __device__ inline double norm_icdf(double p) {
 __host__ __device__ inline double logistic_icdf(double u) { return log(u) - log(1.0 - u); }
 __host__ __device__ inline double logistic_cdf(double x) { return 1.0 / (1.0 + exp(-x)); }
 
+// One-dimensional marginal nu_l of the sampling law (qr_law):
+//  - QR_LAW_STUDENT2: Student's t with mu = 2 in the scaling of the paper's
+//    Example "Student's t-distribution", density (1+x^2)^{-3/2} / 2, whose
+//    F and F^{-1} are closed forms (Sec. 5, eq (Fnui:Fnulinv)):
+//    F(x) = (1 + x / sqrt(1+x^2)) / 2 and F^{-1}(u) = (u - 1/2) / sqrt(u (1-u));
+//  - QR_LAW_CAUCHY (mu = 1): density 1 / (pi (1+x^2)), F(x) = 1/2 + atan(x)/pi,
+//    F^{-1}(u) = tan(pi (u - 1/2)), here as -cos(pi u) / sin(pi u) with the
+//    argument folded to (0, 1/2] so that the tails keep their relative
+//    accuracy (sincospi takes u itself, no product with pi);
+//  - otherwise the standard logistic law.
+__device__ inline double law_icdf(int32_t nu, double u) {
+    if (nu == QR_LAW_STUDENT2) return (u - 0.5) / sqrt(u * (1.0 - u));
+    if (nu == QR_LAW_CAUCHY) {
+        const double v = u < 0.5 ? u : 1.0 - u;  // exact for u >= 1/2
+        double sn, cs;
+        sincospi(v, &sn, &cs);
+        return u < 0.5 ? -cs / sn : cs / sn;
+    }
+    return logistic_icdf(u);
+}
+__device__ inline double law_cdf(int32_t nu, double x) {
+    if (nu == QR_LAW_STUDENT2) return 0.5 + 0.5 * (x / sqrt(fma(x, x, 1.0)));
+    if (nu == QR_LAW_CAUCHY) return 0.5 + atan(x) * M_1_PI;
+    return logistic_cdf(x);
+}
+// density nu_l(x) = dF/dx, given x and u = F(x)
+__device__ inline double law_pdf(int32_t nu, double x, double u) {
+    if (nu == QR_LAW_STUDENT2) {
+        const double r = 1.0 / fma(x, x, 1.0);
+        return 0.5 * r * sqrt(r);
+    }
+    if (nu == QR_LAW_CAUCHY) return M_1_PI / fma(x, x, 1.0);
+    return u * (1.0 - u);
+}
+
 // ---------------------------------------------------------------------------
 // Structures handed to the kernels
 // ---------------------------------------------------------------------------
@@ -151,6 +186,7 @@ __host__ __device__ inline double logistic_cdf(double x) { return 1.0 / (1.0 + e
 // closed-form pieces of the manufactured solution pre-combined on the host.
 struct DevProblem {
     int32_t d, nbm, N, driver;
+    int32_t nu;                       // sampling law of the basis in use (qr_law)
     double f_a, clamp, T;
     double sw2;                       // |sigma^T w|^2
     double t[QR_MAX_N + 1];
@@ -191,14 +227,16 @@ constexpr int kMaxDepthCap = 8;
 // budget Pb extends by magnitude m while w = Pb (m + b) <= L; its child's
 // budget is w when c = 1 (hyperbolic crosses) or stays Pb = 1 (c = 0,
 // tensor set); a child has children iff its budget <= Lc.
+// The walk also carries the sampling law nu of the basis (qr_law): the basis
+// functions in x are the Fourier functions of the torus composed with F_nu.
 struct Walk {
-    int32_t b, L, Lc, c, d;
+    int32_t b, L, Lc, c, d, nu;
 };
 
-__host__ __device__ inline Walk make_walk(int32_t kind, int32_t level, int32_t d) {
-    if (kind == QR_SET_TENSOR) return Walk{0, level, level, 0, d};
-    if (kind == QR_SET_HC_MAX) return Walk{0, level, level, 1, d};
-    return Walk{1, level, level / 2, 1, d};
+__host__ __device__ inline Walk make_walk(int32_t kind, int32_t level, int32_t d, int32_t nu) {
+    if (kind == QR_SET_TENSOR) return Walk{0, level, level, 0, d, nu};
+    if (kind == QR_SET_HC_MAX) return Walk{0, level, level, 1, d, nu};
+    return Walk{1, level, level / 2, 1, d, nu};
 }
 
 // Root of a run of the depth-first traversal used by the projection: the

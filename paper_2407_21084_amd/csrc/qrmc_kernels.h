@@ -89,8 +89,8 @@ hipError_t launch_reduce(const double2 *partial, int32_t nsplit, int64_t nrep, d
                          const int32_t *canon_of_trav, hipStream_t s);
 hipError_t launch_eval(int cap, bool grad, const Walk &W, const double2 *alpha_int_row,
                        const double *x, int64_t n, double *y, double *grad_out, hipStream_t s);
-hipError_t launch_x_to_e(int32_t d, const double *x, int64_t n, double2 *e, hipStream_t s);
-hipError_t launch_sample(int32_t d, uint64_t seed, uint32_t stream_id, int32_t i, int64_t m0,
+hipError_t launch_x_to_e(int32_t nu, int32_t d, const double *x, int64_t n, double2 *e, hipStream_t s);
+hipError_t launch_sample(int32_t nu, int32_t d, uint64_t seed, uint32_t stream_id, int32_t i, int64_t m0,
                          int64_t n, double *x, hipStream_t s);
 
 hipError_t launch_batched_path(int db, int cap, const BatchArgs &a, hipStream_t s);
@@ -102,7 +102,7 @@ hipError_t launch_zero(double *p, int64_t n, hipStream_t s);
 
 
 // step-major path simulation (learned form); x, u SoA [d][M]
-hipError_t launch_sm_start(const DevProblem *P, int32_t i, int64_t M, uint64_t seed, double *x, double2 *e,
+hipError_t launch_sm_start(const DevProblem *P, int32_t nu, int32_t i, int64_t M, uint64_t seed, double *x, double2 *e,
                            double *S, hipStream_t s);
 hipError_t launch_sm_euler(int db, const DevProblem *P, int32_t i, int32_t j, int64_t M, uint64_t seed, double *x,
                            double *H, hipStream_t s);

@@ -102,13 +102,36 @@ struct LanePts {
 // registers that would stay live across the basis traversal.
 // ---------------------------------------------------------------------------
 __device__ __noinline__ double nl_norm_icdf(double u) { return norm_icdf(u); }
-__device__ __noinline__ double nl_logistic_icdf(double u) { return logistic_icdf(u); }
-__device__ __noinline__ double nl_logistic_cdf(double x) { return logistic_cdf(x); }
-__device__ __noinline__ double2 nl_unit_phase(double x) {
+// The logistic law keeps one-argument calls of its own; the other laws go
+// through a second set, chosen by a wave-uniform branch at the call site, so
+// the default path carries no law argument across the basis traversal.
+__device__ __noinline__ double nl_icdf_logistic(double u) { return logistic_icdf(u); }
+__device__ __noinline__ double nl_icdf_other(int32_t nu, double u) { return law_icdf(nu, u); }
+__device__ __noinline__ double nl_pdf_logistic(double x) {
+    const double u = logistic_cdf(x);
+    return u * (1.0 - u);
+}
+__device__ __noinline__ double nl_pdf_other(int32_t nu, double x) { return law_pdf(nu, x, law_cdf(nu, x)); }
+__device__ __noinline__ double2 nl_unit_phase_logistic(double x) {
     // e^{2 pi i F(x)}
     double sn, cs;
     sincospi(2.0 * logistic_cdf(x), &sn, &cs);
     return make_double2(cs, sn);
+}
+__device__ __noinline__ double2 nl_unit_phase_other(int32_t nu, double x) {
+    double sn, cs;
+    sincospi(2.0 * law_cdf(nu, x), &sn, &cs);
+    return make_double2(cs, sn);
+}
+// F^{-1}(u), dF/dx at x and e^{2 pi i F(x)} of the law nu (qr_law)
+__device__ __forceinline__ double nl_icdf(int32_t nu, double u) {
+    return nu == QR_LAW_LOGISTIC ? nl_icdf_logistic(u) : nl_icdf_other(nu, u);
+}
+__device__ __forceinline__ double nl_pdf(int32_t nu, double x) {
+    return nu == QR_LAW_LOGISTIC ? nl_pdf_logistic(x) : nl_pdf_other(nu, x);
+}
+__device__ __forceinline__ double2 nl_unit_phase(int32_t nu, double x) {
+    return nu == QR_LAW_LOGISTIC ? nl_unit_phase_logistic(x) : nl_unit_phase_other(nu, x);
 }
 __device__ __noinline__ double2 nl_sincos(double th) {
     // (sin th, cos th); sincospi avoids the large-argument reduction
@@ -447,10 +470,10 @@ void path_kernel(
         const int64_t m = base + (int64_t)q * kPathBlock;
         PhiloxStream rs(seed, 0u, (uint64_t)m, (uint32_t)i, 0u);
         for (int l = 0; l < d; ++l) {
-            const double x = nl_logistic_icdf(rs.next());
+            const double x = nl_icdf(P0->nu, rs.next());
             xg[l * ldx + q * kPathBlock] = x;
             if (m < M) {
-                if (e_out) e_out[l * M + m] = nl_unit_phase(x);
+                if (e_out) e_out[l * M + m] = nl_unit_phase(P0->nu, x);
                 if (x_out) x_out[l * M + m] = x;
             }
         }
@@ -497,7 +520,7 @@ void path_kernel(
             for (int l = 0; l < d; ++l) {
 #pragma unroll
                 for (int q = 0; q < P; ++q) {
-                    L.set_e(l, q, nl_unit_phase(xg[l * ldx + q * kPathBlock]));
+                    L.set_e(l, q, nl_unit_phase(Pj->nu, xg[l * ldx + q * kPathBlock]));
                     if constexpr (GRAD) L.g(l, q) = 0.0;
                 }
             }
@@ -511,8 +534,7 @@ void path_kernel(
                     for (int l = 0; l < DB; ++l) {
                         gx[l] = 0.0;
                         if (l < d) {
-                            const double u = nl_logistic_cdf(xg[l * ldx + q * kPathBlock]);
-                            gx[l] = 2.0 * M_PI * L.g(l, q) * (u * (1.0 - u));
+                            gx[l] = 2.0 * M_PI * L.g(l, q) * nl_pdf(Pj->nu, xg[l * ldx + q * kPathBlock]);
                         }
                     }
                     for (int k = 0; k < nbm; ++k) {
@@ -821,7 +843,7 @@ __global__ __launch_bounds__(kPathBlock) void eval_kernel(const Walk W,
     const LanePts<1> L{lds + tid, GRAD ? reinterpret_cast<double *>(lds + d * kPathBlock) + tid : nullptr,
                        kPathBlock};
     for (int l = 0; l < d; ++l) {
-        L.set_e(l, 0, nl_unit_phase(x[l * n + p]));
+        L.set_e(l, 0, nl_unit_phase(W.nu, x[l * n + p]));
         if constexpr (GRAD) L.g(l, 0) = 0.0;
     }
     double2 *wave_slot = reinterpret_cast<double2 *>(reinterpret_cast<double *>(lds + d * kPathBlock) +
@@ -833,23 +855,23 @@ __global__ __launch_bounds__(kPathBlock) void eval_kernel(const Walk W,
     y[p] = yv;
     if constexpr (GRAD) {
         for (int l = 0; l < d; ++l) {
-            const double u = logistic_cdf(x[l * n + p]);
-            grad[l * n + p] = 2.0 * M_PI * L.g(l, 0) * (u * (1.0 - u));
+            grad[l * n + p] = 2.0 * M_PI * L.g(l, 0) * nl_pdf(W.nu, x[l * n + p]);
         }
     }
 }
 
-__global__ void x_to_e_kernel(int32_t d, const double *__restrict__ x, int64_t n, double2 *__restrict__ e) {
+__global__ void x_to_e_kernel(int32_t nu, int32_t d, const double *__restrict__ x, int64_t n,
+                              double2 *__restrict__ e) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx < (int64_t)d * n) e[idx] = nl_unit_phase(x[idx]);
+    if (idx < (int64_t)d * n) e[idx] = nl_unit_phase(nu, x[idx]);
 }
 
-__global__ void sample_kernel(int32_t d, uint64_t seed, uint32_t stream_id, int32_t i, int64_t m0,
-                              int64_t n, double *__restrict__ x) {
+__global__ void sample_kernel(int32_t nu, int32_t d, uint64_t seed, uint32_t stream_id, int32_t i,
+                              int64_t m0, int64_t n, double *__restrict__ x) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     PhiloxStream rs(seed, stream_id, (uint64_t)(m0 + p), (uint32_t)i, 0u);
-    for (int l = 0; l < d; ++l) x[l * n + p] = logistic_icdf(rs.next());
+    for (int l = 0; l < d; ++l) x[l * n + p] = law_icdf(nu, rs.next());
 }
 
 // ---------------------------------------------------------------------------
@@ -961,9 +983,9 @@ __global__ __launch_bounds__(kPathBlock) void mfma_path_kernel(
     {
         PhiloxStream rs(seed, 0u, (uint64_t)m, (uint32_t)i, 0u);
         for (int l = 0; l < d; ++l) {
-            const double x = nl_logistic_icdf(rs.next());
+            const double x = nl_icdf(P0->nu, rs.next());
             xs[l * kPathBlock] = x;
-            if (e_out && m < M) e_out[l * M + m] = nl_unit_phase(x);
+            if (e_out && m < M) e_out[l * M + m] = nl_unit_phase(P0->nu, x);
         }
     }
     double S = 0.0;
@@ -997,7 +1019,7 @@ __global__ __launch_bounds__(kPathBlock) void mfma_path_kernel(
         double y, z2 = 0.0;
         if (j + 1 < N) {
             for (int l = 0; l < d; ++l) {
-                const double2 e = nl_unit_phase(xs[l * kPathBlock]);
+                const double2 e = nl_unit_phase(Pj->nu, xs[l * kPathBlock]);
                 L.set_e(l, 0, make_float2((float)e.x, (float)e.y));
             }
             MfmaSink<PREC, T> sink;
@@ -1019,8 +1041,7 @@ __global__ __launch_bounds__(kPathBlock) void mfma_path_kernel(
                 for (int l = 0; l < DB; ++l) {
                     gx[l] = 0.0;
                     if (l < d) {
-                        const double u = nl_logistic_cdf(xs[l * kPathBlock]);
-                        gx[l] = (double)sink.acc[(l + 1) / 4][(l + 1) % 4] * (u * (1.0 - u));
+                        gx[l] = (double)sink.acc[(l + 1) / 4][(l + 1) % 4] * nl_pdf(Pj->nu, xs[l * kPathBlock]);
                     }
                 }
                 for (int k = 0; k < nbm; ++k) {
@@ -1101,15 +1122,16 @@ __global__ void pack_tiles_kernel(const double2 *__restrict__ alpha_int_row, int
 // (eval_kernel) or by the surrogate network.  Random numbers and arithmetic
 // are those of path_kernel, step by step.
 // ---------------------------------------------------------------------------
-__global__ void sm_start_kernel(const DevProblem *__restrict__ P0, int32_t i, int64_t M, uint64_t seed,
-                                double *__restrict__ x, double2 *__restrict__ e, double *__restrict__ S) {
+__global__ void sm_start_kernel(const DevProblem *__restrict__ P0, int32_t nu, int32_t i, int64_t M,
+                                uint64_t seed, double *__restrict__ x, double2 *__restrict__ e,
+                                double *__restrict__ S) {
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= M) return;
     PhiloxStream rs(seed, 0u, (uint64_t)m, (uint32_t)i, 0u);
     for (int l = 0; l < P0->d; ++l) {
-        const double xv = nl_logistic_icdf(rs.next());
+        const double xv = nl_icdf(nu, rs.next());
         x[l * M + m] = xv;
-        e[l * M + m] = nl_unit_phase(xv);
+        e[l * M + m] = nl_unit_phase(nu, xv);
     }
     S[m] = 0.0;
 }
@@ -1282,9 +1304,9 @@ __global__ __launch_bounds__(kPathBlock) void batched_path_kernel(
     {
         PhiloxStream rs(seed, 0u, (uint64_t)m, (uint32_t)i, 0u);
         for (int l = 0; l < d; ++l) {
-            const double x = nl_logistic_icdf(rs.next());
+            const double x = nl_icdf(P0->nu, rs.next());
             xs[l * kPathBlock] = x;
-            if (e_out && m < M) e_out[l * M + m] = nl_unit_phase(x);
+            if (e_out && m < M) e_out[l * M + m] = nl_unit_phase(P0->nu, x);
         }
     }
     double S[RT];
@@ -1335,7 +1357,7 @@ __global__ __launch_bounds__(kPathBlock) void batched_path_kernel(
         }
         double y[RT];
         if (j + 1 < N) {
-            for (int l = 0; l < W.d; ++l) L.set_e(l, 0, nl_unit_phase(xs[l * kPathBlock]));
+            for (int l = 0; l < W.d; ++l) L.set_e(l, 0, nl_unit_phase(Pj->nu, xs[l * kPathBlock]));
             BatchSink<RT> sink;
             sink.init(alpha_b + (int64_t)(j + 1) * ld * RT, wave_slot);
             typename BatchSink<RT>::Acc none{};
@@ -1572,16 +1594,16 @@ hipError_t launch_eval(int cap, bool grad, const Walk &W, const double2 *alpha_i
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_x_to_e(int32_t d, const double *x, int64_t n, double2 *e, hipStream_t s) {
+hipError_t launch_x_to_e(int32_t nu, int32_t d, const double *x, int64_t n, double2 *e, hipStream_t s) {
     const int64_t total = (int64_t)d * n;
-    hipLaunchKernelGGL(x_to_e_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, s, d, x, n, e);
+    hipLaunchKernelGGL(x_to_e_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, s, nu, d, x, n, e);
     return hipGetLastError();
 }
 
-hipError_t launch_sample(int32_t d, uint64_t seed, uint32_t stream_id, int32_t i, int64_t m0,
+hipError_t launch_sample(int32_t nu, int32_t d, uint64_t seed, uint32_t stream_id, int32_t i, int64_t m0,
                          int64_t n, double *x, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(sample_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, d, seed, stream_id,
+    hipLaunchKernelGGL(sample_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, nu, d, seed, stream_id,
                        i, m0, n, x);
     return hipGetLastError();
 }
@@ -1712,9 +1734,9 @@ hipError_t launch_pack_tiles(int prec, const double2 *alpha_int_row, int64_t nre
 
 static inline unsigned sm_blocks(int64_t n) { return blocks_for(n, 256); }
 
-hipError_t launch_sm_start(const DevProblem *P, int32_t i, int64_t M, uint64_t seed, double *x, double2 *e,
+hipError_t launch_sm_start(const DevProblem *P, int32_t nu, int32_t i, int64_t M, uint64_t seed, double *x, double2 *e,
                            double *S, hipStream_t s) {
-    hipLaunchKernelGGL(sm_start_kernel, dim3(sm_blocks(M)), dim3(256), 0, s, P, i, M, seed, x, e, S);
+    hipLaunchKernelGGL(sm_start_kernel, dim3(sm_blocks(M)), dim3(256), 0, s, P, nu, i, M, seed, x, e, S);
     return hipGetLastError();
 }
 

@@ -44,7 +44,9 @@ hipError_t launch_adam(int64_t n, float *theta, const float *g, float *m, float 
                        hipStream_t s);
 hipError_t launch_mlp_init(float *theta, uint64_t seed, hipStream_t s);
 // f[p][l] = 2 F(x[l][p]) - 1 (l < d), 0 otherwise; x SoA [d][n] (stride ldx)
-hipError_t launch_features(int32_t d, int64_t n, const double *x, int64_t ldx, float *f, hipStream_t s);
+// features 2 F_nu(x_l) - 1 of the sampling law nu (qr_law)
+hipError_t launch_features(int32_t nu, int32_t d, int64_t n, const double *x, int64_t ldx, float *f,
+                           hipStream_t s);
 // sums of (mu + sigma y - t)^2 and t^2 per block of 256: partial[2 block], partial[2 block + 1]
 hipError_t launch_heldout(int64_t n, const float *y, const double *t, double mu, double sigma, double *partial,
                           hipStream_t s);

@@ -189,13 +189,13 @@ __global__ void mlp_init_kernel(float *__restrict__ th, uint64_t seed) {
     th[k] = scale == 0.f ? 0.f : scale * (float)(2.0 * uniform_at(seed, 2u, (uint64_t)k, 0u, 0u) - 1.0);
 }
 
-__global__ void features_kernel(int32_t d, int64_t n, const double *__restrict__ x, int64_t ldx,
+__global__ void features_kernel(int32_t nu, int32_t d, int64_t n, const double *__restrict__ x, int64_t ldx,
                                 float *__restrict__ f) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= n * kMlpIn) return;
     const int64_t p = idx / kMlpIn;
     const int l = (int)(idx % kMlpIn);
-    f[idx] = l < d ? (float)(2.0 * logistic_cdf(x[l * ldx + p]) - 1.0) : 0.f;
+    f[idx] = l < d ? (float)(2.0 * law_cdf(nu, x[l * ldx + p]) - 1.0) : 0.f;
 }
 
 __global__ void heldout_kernel(int64_t n, const float *__restrict__ y, const double *__restrict__ t, double mu,
@@ -304,8 +304,9 @@ hipError_t launch_mlp_init(float *theta, uint64_t seed, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_features(int32_t d, int64_t n, const double *x, int64_t ldx, float *f, hipStream_t s) {
-    hipLaunchKernelGGL(features_kernel, dim3(nblocks(n * kMlpIn, 256)), dim3(256), 0, s, d, n, x, ldx, f);
+hipError_t launch_features(int32_t nu, int32_t d, int64_t n, const double *x, int64_t ldx, float *f,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(features_kernel, dim3(nblocks(n * kMlpIn, 256)), dim3(256), 0, s, nu, d, n, x, ldx, f);
     return hipGetLastError();
 }
 

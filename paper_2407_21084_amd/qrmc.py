@@ -27,6 +27,8 @@ MLP_MAX_BATCH = 65536
 SET_TENSOR, SET_HC_MAX, SET_HC_1P = 0, 1, 2
 SET_KINDS = {"tensor": SET_TENSOR, "hc_max": SET_HC_MAX, "hc_1p": SET_HC_1P}
 F_LINEAR, F_SIN, F_ALLEN_CAHN, F_ZRAT = 0, 1, 2, 3
+LAW_LOGISTIC, LAW_STUDENT2, LAW_CAUCHY = 0, 1, 2
+LAWS = {"logistic": LAW_LOGISTIC, "student2": LAW_STUDENT2, "cauchy": LAW_CAUCHY}
 DRIVERS = {"linear": F_LINEAR, "sin": F_SIN, "allen_cahn": F_ALLEN_CAHN, "zrat": F_ZRAT}
 
 STATUS = {0: "QR_OK", -1: "QR_EINVAL", -2: "QR_ENOMEM", -3: "QR_EDEVICE", -4: "QR_ERANGE",
@@ -38,7 +40,8 @@ PRECISIONS = {"f64": PREC_F64, "bf16": PREC_BF16, "f16": PREC_F16}
 # kernel classes of qr_ctx_kernel_time
 K_PATH, K_PROJECT, K_REDUCE, K_GATHER = 0, 1, 2, 3
 
-EXPORTS = ["qr_last_error", "qr_version", "qr_build_basis", "qr_basis_info", "qr_basis_indices",
+EXPORTS = ["qr_last_error", "qr_version", "qr_build_basis", "qr_build_basis_law", "qr_basis_law",
+           "qr_basis_info", "qr_basis_indices", "qr_sample_points_law",
            "qr_basis_free", "qr_ctx_create", "qr_ctx_destroy", "qr_ctx_set_timing",
            "qr_ctx_kernel_time", "qr_ctx_reset_timing", "qr_backward_step", "qr_solve", "qr_eval",
            "qr_project", "qr_path_responses", "qr_sample_points", "qr_backward_step_prec",
@@ -97,6 +100,8 @@ _SIGS = {
     "qr_last_error": (C.c_char_p, []),
     "qr_version": (C.c_char_p, []),
     "qr_build_basis": (C.c_int, [_I32, _I32, _I32, C.POINTER(_P)]),
+    "qr_build_basis_law": (C.c_int, [_I32, _I32, _I32, _I32, C.POINTER(_P)]),
+    "qr_basis_law": (C.c_int, [_P, C.POINTER(_I32)]),
     "qr_basis_info": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I32)]),
     "qr_basis_indices": (C.c_int, [_P, _P]),
     "qr_basis_free": (None, [_P]),
@@ -111,6 +116,7 @@ _SIGS = {
     "qr_project": (C.c_int, [_P, _P, _I64, _P, _P, _P, _P]),
     "qr_path_responses": (C.c_int, [_P, C.POINTER(Problem), _P, _I32, _I64, _U64, _P, _P, _P, _P]),
     "qr_sample_points": (C.c_int, [_P, _I32, _U64, _U32, _I32, _I64, _I64, _P, _P]),
+    "qr_sample_points_law": (C.c_int, [_P, _I32, _I32, _U64, _U32, _I32, _I64, _I64, _P, _P]),
     "qr_backward_step_prec": (C.c_int, [_P, C.POINTER(Problem), _P, _I32, _I64, _U64, _I32, _P, _P]),
     "qr_solve_prec": (C.c_int, [_P, C.POINTER(Problem), _P, _I64, _U64, _I32, _P, _P]),
     "qr_mlp_init": (C.c_int, [_P, _P, _U64, _P]),
@@ -165,14 +171,19 @@ def host_philox(ctr, key) -> np.ndarray:
 
 
 class Basis:
-    """Index set Gamma and its basis metadata (qr_build_basis)."""
+    """Index set Gamma and its basis metadata for the sampling law `law`
+    (qr_build_basis_law)."""
 
-    def __init__(self, d: int, kind, level: int):
+    def __init__(self, d: int, kind, level: int, law="logistic"):
         kind = SET_KINDS[kind] if isinstance(kind, str) else int(kind)
+        law = LAWS[law] if isinstance(law, str) else int(law)
         h = _P()
-        _check(_lib.qr_build_basis(d, kind, level, C.byref(h)))
+        _check(_lib.qr_build_basis_law(d, kind, level, law, C.byref(h)))
         self._h = h
         self.d, self.kind, self.level = d, kind, level
+        got = _I32()
+        _check(_lib.qr_basis_law(h, C.byref(got)))
+        self.law = got.value
         nf, nr, mn = _I64(), _I64(), _I32()
         _check(_lib.qr_basis_info(h, C.byref(nf), C.byref(nr), C.byref(mn)))
         self.n_funcs, self.n_reps, self.max_nnz = nf.value, nr.value, mn.value
@@ -318,9 +329,10 @@ class Context:
                                       _dptr(s), _dptr(x0), _stream_ptr(stream)))
 
     def sample_points(self, d: int, seed: int, stream_id: int, i: int, n: int, x, m0: int = 0,
-                      stream=None):
-        _check(_lib.qr_sample_points(self._h, d, seed, stream_id, i, m0, n, _dptr(x),
-                                     _stream_ptr(stream)))
+                      stream=None, law="logistic"):
+        law = LAWS[law] if isinstance(law, str) else int(law)
+        _check(_lib.qr_sample_points_law(self._h, law, d, seed, stream_id, i, m0, n, _dptr(x),
+                                         _stream_ptr(stream)))
 
     def solve_batched(self, prob: Problem, basis: Basis, instances, seed: int, alpha, stream=None):
         """instances: sequence of (f_a, d, level, M); alpha: device [R][N][n_funcs]."""

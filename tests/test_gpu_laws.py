@@ -1,0 +1,198 @@
+"""GPU parity under the paper's own sampling laws (Sec. 5): Student's t with
+mu = 2 and the Cauchy law.  The HIP path (through the C ABI, bases built with
+qr_build_basis_law) against the CPU oracle on the same Philox streams, with
+the tolerances of the logistic-law parity tests: relative 1e-10 per
+coefficient against max(|alpha_k|, A_k) and for the row in the 2-norm.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+LAWS = ["student2", "cauchy"]
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2407_21084_amd import qrmc as Q
+    ctx = Q.Context(0)
+    yield Q, ctx, torch
+    ctx.close()
+
+
+def _dev(torch, a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _host(t):
+    return t.detach().cpu().numpy()
+
+
+def _assert_alpha(gpu, ref, absum, tol=TOL, what=""):
+    scale = np.maximum(np.abs(ref), absum)
+    bad = np.abs(gpu - ref) > tol * scale + 1e-300
+    assert not bad.any(), f"{what}: {bad.sum()} coefficients off, worst {np.max(np.abs(gpu - ref) / (scale + 1e-300))}"
+    assert np.linalg.norm(gpu - ref) <= tol * np.linalg.norm(ref) + 1e-300, what
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("law", LAWS)
+@pytest.mark.parametrize("n", [1, 5000])
+def test_sample_points_law(env, law, n):
+    Q, ctx, torch = env
+    _say(f"sample_points {law} n={n}")
+    d = 5
+    x = torch.empty((d, n), dtype=torch.float64, device="cuda")
+    ctx.sample_points(d, 11, 1, 3, n, x, m0=17, law=law)
+    torch.cuda.synchronize()
+    ref = O.sample_points(d, 11, 1, 3, n, m0=17, law=law)
+    assert np.allclose(_host(x).T, ref, rtol=1e-13, atol=1e-15)
+
+
+def test_basis_reports_its_law(env):
+    Q, ctx, torch = env
+    for name, code in Q.LAWS.items():
+        assert Q.Basis(2, "tensor", 2, law=name).law == code
+
+
+@pytest.mark.parametrize("law", LAWS)
+@pytest.mark.parametrize("d,kind,level,n", [(2, "tensor", 4, 4099), (6, "hc_max", 16, 700),
+                                            (10, "hc_1p", 32, 300)])
+def test_project_law(env, law, d, kind, level, n):
+    Q, ctx, torch = env
+    _say(f"project {law} d={d} {kind} {level} n={n}")
+    b = Q.Basis(d, kind, level, law=law)
+    reps = O.enumerate_set(d, kind, level)
+    x = W.law_points(n, d, law, seed=d + n)
+    s = W.responses(n, seed=n)
+    a = torch.empty(b.n_funcs, dtype=torch.float64, device="cuda")
+    ctx.project(b, _dev(torch, x.T), _dev(torch, s), a)
+    torch.cuda.synchronize()
+    ref, absum = O.project(reps, x, s, with_abs=True, law=law)
+    _assert_alpha(_host(a), ref, absum, what=f"project {law}")
+
+
+@pytest.mark.parametrize("law", LAWS)
+@pytest.mark.parametrize("d,kind,level,n,grad", [(2, "tensor", 4, 129, True), (6, "hc_max", 16, 300, False),
+                                                 (3, "hc_1p", 12, 500, True)])
+def test_eval_law(env, law, d, kind, level, n, grad):
+    Q, ctx, torch = env
+    _say(f"eval {law} d={d} {kind} {level} n={n} grad={grad}")
+    b = Q.Basis(d, kind, level, law=law)
+    reps = O.enumerate_set(d, kind, level)
+    alpha = W.synthetic_alpha(b.n_funcs, 1, seed=3)[0]
+    x = W.law_points(n, d, law, seed=1)
+    y = torch.empty(n, dtype=torch.float64, device="cuda")
+    g = torch.empty((d, n), dtype=torch.float64, device="cuda") if grad else None
+    ctx.eval(b, _dev(torch, alpha), _dev(torch, x.T), y, g)
+    torch.cuda.synchronize()
+    if grad:
+        ry, rg = O.evaluate(reps, alpha, x, grad=True, law=law)
+        scale = np.abs(alpha).sum() * 2 * math.pi * level
+        assert np.abs(_host(g).T - rg).max() <= TOL * scale
+    else:
+        ry = O.evaluate(reps, alpha, x, law=law)
+    assert np.abs(_host(y) - ry).max() <= TOL * np.abs(alpha).sum()
+
+
+@pytest.mark.parametrize("law", LAWS)
+@pytest.mark.parametrize("i,M", [(9, 1), (8, 777), (0, 2000)])
+def test_path_responses_law(env, law, i, M):
+    Q, ctx, torch = env
+    w = W.D2_TENSOR4.with_(law=law)
+    _say(f"path_responses {law} {w.name} i={i} M={M}")
+    b = Q.Basis(w.d, w.set_kind, w.level, law=law)
+    reps = O.reps_for(w)
+    alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=7, scale=0.2)
+    s = torch.empty(M, dtype=torch.float64, device="cuda")
+    x0 = torch.empty((w.d, M), dtype=torch.float64, device="cuda")
+    ctx.path_responses(Q.problem_from(w), b, i, M, 5, _dev(torch, alpha), s, x0)
+    torch.cuda.synchronize()
+    sg, xg = _host(s), _host(x0).T
+    ms = sorted(set([0, M - 1] + list(np.random.default_rng(0).integers(0, M, 6))))
+    for m in ms:
+        ref = O.path_response(w, reps, i, 5, int(m), alpha)
+        assert abs(sg[m] - ref) <= TOL * max(1.0, abs(ref)), (m, sg[m], ref)
+        assert np.allclose(xg[m], [O.law_icdf(law, O.uniform(5, 0, int(m), i, l)) for l in range(w.d)],
+                           rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("law", LAWS)
+@pytest.mark.parametrize("i", [9, 4])
+def test_backward_step_d2_tensor_law(env, law, i):
+    Q, ctx, torch = env
+    w = W.D2_TENSOR4.with_(law=law)
+    _say(f"backward_step {law} d2 tensor i={i}")
+    b = Q.Basis(w.d, w.set_kind, w.level, law=law)
+    reps = O.reps_for(w)
+    alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=11, scale=0.2)
+    a = _dev(torch, alpha)
+    ctx.backward_step(Q.problem_from(w), b, i, w.M, w.seed, a)
+    torch.cuda.synchronize()
+    ref, absum, _, _ = O.backward_step(w, reps, i, w.M, w.seed, alpha.copy())
+    _assert_alpha(_host(a)[i], ref, absum, what=f"{law} row {i}")
+
+
+@pytest.mark.parametrize("law", LAWS)
+@pytest.mark.parametrize("d,i", [(3, 0), (8, 1)])
+def test_backward_step_gradient_driver_law(env, law, d, i):
+    """z-dependent driver: the gradient goes through the law's density."""
+    Q, ctx, torch = env
+    w = W.Workload(name=f"zrat-d{d}-{law}", d=d, N=4, T=1.0,
+                   sigma=[[0.5 if a == c else 0.0 for c in range(d)] for a in range(d)],
+                   b0=[0.0] * d, b1=[0.0] * d, set_kind="hc_1p", level=12, M=3000, driver="zrat",
+                   f_a=-0.05, sol_A=1.0, sol_c=1.0, sol_p=0.0,
+                   sol_w=[1.0 if l < 2 else 0.0 for l in range(d)], seed=3, law=law)
+    _say(f"backward_step zrat {law} d={d} i={i}")
+    b = Q.Basis(w.d, w.set_kind, w.level, law=law)
+    reps = O.reps_for(w)
+    alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=d, scale=0.2, decay=0.7)
+    a = _dev(torch, alpha)
+    ctx.backward_step(Q.problem_from(w), b, i, w.M, w.seed, a)
+    torch.cuda.synchronize()
+    ref, absum, _, _ = O.backward_step(w, reps, i, w.M, w.seed, alpha.copy())
+    _assert_alpha(_host(a)[i], ref, absum, what=f"zrat {law} d={d} row {i}")
+
+
+@pytest.mark.parametrize("law", LAWS)
+def test_solve_d2_law_matches_oracle(env, law):
+    """Full solve under the law, rows against the oracle, and the relative L2
+    error at t_0 on stream-1 points of the law equal to the oracle's."""
+    Q, ctx, torch = env
+    w = W.D2_TENSOR4.with_(law=law)
+    _say(f"solve d2 tensor {law}")
+    b = Q.Basis(w.d, w.set_kind, w.level, law=law)
+    reps = O.reps_for(w)
+    a = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device="cuda")
+    ctx.solve(Q.problem_from(w), b, w.M, w.seed, a)
+    torch.cuda.synchronize()
+    got = _host(a)
+    ref = O.solve(w, reps)
+    for i in (w.N - 1, w.N // 2, 0):
+        _, absum, _, _ = O.backward_step(w, reps, i, w.M, w.seed, ref.copy())
+        _assert_alpha(got[i], ref[i], absum, tol=1e-9, what=f"solve {law} row {i}")
+    n = 1 << 14
+    x = torch.empty((w.d, n), dtype=torch.float64, device="cuda")
+    ctx.sample_points(w.d, w.seed, 1, 0, n, x, law=law)
+    y = torch.empty(n, dtype=torch.float64, device="cuda")
+    ctx.eval(b, a[0].contiguous(), x, y)
+    torch.cuda.synchronize()
+    xh = _host(x).T
+    u = np.exp(-1.0) * np.cos(xh[:, 0] + xh[:, 1])
+    rel = np.linalg.norm(_host(y) - u) / np.linalg.norm(u)
+    _, _, rel_oracle = O.errors(w, reps, ref, seed=w.seed, n=n)
+    assert abs(rel - rel_oracle) < 1e-8

@@ -100,3 +100,16 @@ def test_context_without_device_reports_device_error():
     with pytest.raises(Q.QrError) as e:
         Q.Context(0)
     assert e.value.status == -3
+
+
+def test_basis_law_is_recorded_and_unknown_laws_rejected():
+    for name, code in Q.LAWS.items():
+        b = Q.Basis(3, "hc_1p", 8, law=name)
+        assert b.law == code
+        # the law does not change the index set
+        assert np.array_equal(b.indices(), O.enumerate_set(3, "hc_1p", 8))
+    assert Q.Basis(2, "tensor", 2).law == Q.LAW_LOGISTIC
+    for bad in (-1, 3, 99):
+        with pytest.raises(Q.QrError) as e:
+            Q.Basis(2, "tensor", 2, law=bad)
+        assert e.value.status == -1
