@@ -196,3 +196,78 @@ def test_solve_d2_law_matches_oracle(env, law):
     rel = np.linalg.norm(_host(y) - u) / np.linalg.norm(u)
     _, _, rel_oracle = O.errors(w, reps, ref, seed=w.seed, n=n)
     assert abs(rel - rel_oracle) < 1e-8
+
+
+# ---------------------------------------------------------------------------
+# the other forms read the law from the basis too
+# ---------------------------------------------------------------------------
+
+UNIT = {"bf16": 2.0 ** -8, "f16": 2.0 ** -11}
+
+
+@pytest.mark.parametrize("law", LAWS)
+@pytest.mark.parametrize("prec", ["bf16", "f16"])
+def test_prec_backward_step_law(env, law, prec):
+    """Reduced-precision form under the law, z-dependent driver (value and
+    gradient right-hand sides): rows within 8u (relative 2-norm) of the FP64
+    oracle, the bound of the logistic-law precision tests."""
+    Q, ctx, torch = env
+    d = 3
+    w = W.Workload(name=f"zrat-d{d}-{law}", d=d, N=4, T=1.0,
+                   sigma=[[0.5 if a == c else 0.0 for c in range(d)] for a in range(d)],
+                   b0=[0.0] * d, b1=[0.0] * d, set_kind="hc_1p", level=12, M=4000, driver="zrat",
+                   f_a=-0.05, sol_A=1.0, sol_c=1.0, sol_p=0.0,
+                   sol_w=[1.0 if l < 2 else 0.0 for l in range(d)], seed=5, law=law)
+    _say(f"prec backward step {law} {prec}")
+    b = Q.Basis(w.d, w.set_kind, w.level, law=law)
+    reps = O.reps_for(w)
+    alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=d, scale=0.2, decay=0.7)
+    for i in (w.N - 2, 0):
+        a = _dev(torch, alpha)
+        ctx.backward_step_prec(Q.problem_from(w), b, i, w.M, w.seed, prec, a)
+        torch.cuda.synchronize()
+        ref, _, _, _ = O.backward_step(w, reps, i, w.M, w.seed, alpha.copy())
+        err = float(np.linalg.norm(_host(a)[i] - ref) / np.linalg.norm(ref))
+        _say(f"  row {i}: rel err {err:.3e}")
+        assert err <= 8 * UNIT[prec], (i, err)
+
+
+@pytest.mark.parametrize("law", LAWS)
+def test_batched_law_equals_unbatched(env, law):
+    """Batched instances on the whole basis under the law give qr_solve's
+    coefficients for their driver parameter, and the first matches the oracle."""
+    Q, ctx, torch = env
+    w = W.D2_TENSOR4.with_(law=law)
+    b = Q.Basis(w.d, w.set_kind, w.level, law=law)
+    fas = [0.2, 0.9]
+    _say(f"batched vs qr_solve, d2 tensor, {law}")
+    a = torch.zeros((len(fas), w.N, b.n_funcs), dtype=torch.float64, device="cuda")
+    ctx.solve_batched(Q.problem_from(w), b, [(f, w.d, w.level, w.M) for f in fas], w.seed, a)
+    for r, f in enumerate(fas):
+        ref = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device="cuda")
+        ctx.solve(Q.problem_from(w.with_(f_a=f)), b, w.M, w.seed, ref)
+        torch.cuda.synchronize()
+        err = (a[r] - ref).abs().max().item()
+        assert err <= TOL * ref.abs().max().item(), (f, err)
+    oref = O.solve(w.with_(f_a=fas[0]), O.reps_for(w))
+    got = _host(a)[0]
+    assert np.abs(got - oref).max() <= 1e-9 * np.abs(oref).max()
+
+
+@pytest.mark.parametrize("law", LAWS)
+def test_learned_law_closed_gate_is_the_plain_solve(env, law):
+    """Learned form under the law with gate 0: the surrogates (trained on the
+    law's points and features) are all rejected and the step-major pipeline
+    reproduces qr_solve."""
+    Q, ctx, torch = env
+    w = W.D2_TENSOR4.with_(law=law)
+    b = Q.Basis(w.d, w.set_kind, w.level, law=law)
+    a = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device="cuda")
+    rep = ctx.solve_learned(Q.problem_from(w), b, w.M, w.seed, a, train_points=1 << 12,
+                            heldout_points=1 << 10, epochs=1, batch=1024, gate=0.0)
+    ref = torch.zeros_like(a)
+    ctx.solve(Q.problem_from(w), b, w.M, w.seed, ref)
+    torch.cuda.synchronize()
+    assert all(not r["used"] for r in rep)
+    err = (a - ref).abs().max().item()
+    assert err <= 1e-12 * ref.abs().max().item(), err
