@@ -42,6 +42,7 @@ class Problem(C.Structure):
         ("sigma", C.c_double * (MAXD * MAXD)),
         ("sol_A", C.c_double), ("sol_c", C.c_double), ("sol_p", C.c_double),
         ("sol_w", C.c_double * MAXD),
+        ("damping_q", C.c_double),
     ]
 
 
@@ -69,6 +70,8 @@ def lib():
             "or_msol_u": (D, [P, D, P]),
             "or_msol_h": (D, [P, D, P]),
             "or_path_response": (D, [P, I64, P, I32, U64, U64, P]),
+            "or_damping": (D, [P, P]),
+            "or_eval_y": (D, [P, I64, P, P, P, P]),
             "or_project": (None, [C.c_int, C.c_int, I64, P, I64, P, P, P, P]),
             "or_backward_step": (C.c_int, [P, I64, P, I32, I64, U64, P, P, P, P]),
             "or_solve": (C.c_int, [P, I64, P, I64, U64, P]),
@@ -205,6 +208,7 @@ def problem(w) -> Problem:
         for k in range(w.nbm):
             p.sigma[l * w.nbm + k] = w.sigma[l][k]
     p.sol_A, p.sol_c, p.sol_p = w.sol_A, w.sol_c, w.sol_p
+    p.damping_q = w.damping_q
     return p
 
 
@@ -240,6 +244,24 @@ def backward_step(w, reps, i, M, seed, alpha, want_x=False, want_s=False):
     if rc:
         raise ValueError("or_backward_step failed")
     return alpha[i].copy(), ab, x, s
+
+
+def damping(w, x) -> float:
+    """(1+|x|^2)^{q/2} of eq (yqi) for the workload's q."""
+    p = problem(w)
+    return lib().or_damping(C.byref(p), _ptr(np.ascontiguousarray(_f64(x))))
+
+
+def eval_y(w, reps, alpha_row, x, grad: bool = False):
+    """y(x) = ybar^{(q)}(x) (1+|x|^2)^{q/2} from one coefficient row, and its
+    x-gradient (one point x of length d)."""
+    p = problem(w)
+    reps = np.ascontiguousarray(reps, dtype=np.int32)
+    x = np.ascontiguousarray(_f64(x))
+    g = np.zeros(w.d)
+    y = lib().or_eval_y(C.byref(p), reps.shape[0], _ptr(reps), _ptr(_f64(alpha_row)), _ptr(x),
+                        _ptr(g) if grad else None)
+    return (y, g) if grad else y
 
 
 def path_response(w, reps, i, seed, m, alpha) -> float:

@@ -41,7 +41,13 @@
  *   - index sets are taken over Z^d, symmetric in each coordinate;
  *   - the driver may depend on z = sigma^T grad y (explicit: evaluated at
  *     X_{j+1} together with y);
- *   - damping q = 0 and a constant truncation level L.
+ *   - a damping exponent q >= 0 (eq (yqi)): the expansions approximate
+ *     y_i / (1+|x|^2)^{q/2}; q = 0 gives y_i itself.  Parity unpinned for
+ *     one step of it: the factor (1+|x|^2)^{q/2} on the y handed to the
+ *     driver (or_eval_y) is checked only against its definition; the
+ *     division of the response and the projection target are pinned
+ *     (exact identity, Lemma 3.1 by quadrature);
+ *   - a constant truncation level L.
  */
 #include <math.h>
 #include <stdint.h>
@@ -71,6 +77,7 @@ typedef struct {
     double sigma[OR_MAXD * OR_MAXD];/* diffusion, d x nbm, row-major       */
     double sol_A, sol_c, sol_p;     /* u(t,x) = A e^{-c(T-t)} cos(w.x+p)   */
     double sol_w[OR_MAXD];
+    double damping_q;               /* damping exponent q >= 0 (eq (yqi))  */
 } or_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -432,8 +439,34 @@ static double or_trunc(const or_problem *P, double y)
 }
 
 /* ------------------------------------------------------------------------ */
-/* Algorithm 1 (GQRMDP), q = 0.                                             */
+/* Algorithm 1 (GQRMDP) with damping exponent q.                            */
 /* ------------------------------------------------------------------------ */
+
+/* Damping factor (1+|x|^2)^{q/2} of eq (yqi). */
+double or_damping(const or_problem *P, const double *x)
+{
+    double r2 = 0.0;
+    for (int l = 0; l < P->d; ++l) r2 += x[l] * x[l];
+    return pow(1.0 + r2, 0.5 * P->damping_q);
+}
+
+/* y_{j+1}(x) recovered from the expansion of ybar^{(q)}_{j+1}: the
+ * expansion times (1+|x|^2)^{q/2} (eqs (yqi), (Sqi:bar:M)), and, when
+ * grad != NULL, its x-gradient by the product rule:
+ * grad y = D grad ybar + ybar q D x / (1+|x|^2). */
+double or_eval_y(const or_problem *P, int64_t nrep, const int32_t *reps, const double *alpha_row,
+                 const double *x, double *grad)
+{
+    int d = P->d;
+    double yb = or_expansion(d, P->nu, nrep, reps, alpha_row, x, grad);
+    if (P->damping_q == 0.0) return yb;
+    double r2 = 0.0;
+    for (int l = 0; l < d; ++l) r2 += x[l] * x[l];
+    double D = pow(1.0 + r2, 0.5 * P->damping_q);
+    if (grad)
+        for (int l = 0; l < d; ++l) grad[l] = D * grad[l] + yb * P->damping_q * D * x[l] / (1.0 + r2);
+    return yb * D;
+}
 static int64_t or_nfuncs(int64_t nrep) { return 2 * nrep - 1; }
 
 /* Start point X_i^i of path m: d uniforms of stream 0 through F^{-1}. */
@@ -468,8 +501,7 @@ double or_path_response(const or_problem *P, int64_t nrep, const int32_t *reps, 
         double y;
         int need_z = (P->driver == 3);
         if (j + 1 < N) {
-            y = or_expansion(d, P->nu, nrep, reps, alpha + (int64_t)(j + 1) * nf, xn,
-                             need_z ? grad : NULL);
+            y = or_eval_y(P, nrep, reps, alpha + (int64_t)(j + 1) * nf, xn, need_z ? grad : NULL);
         } else {
             y = or_g(P, xn);
             if (need_z) or_msol_grad(P, or_T(P), xn, grad);
@@ -480,6 +512,12 @@ double or_path_response(const or_problem *P, int64_t nrep, const int32_t *reps, 
         for (int l = 0; l < d; ++l) x[l] = xn[l];
     }
     S += or_g(P, x);
+    /* the response of the damped quantity: divided by (1+|X_i|^2)^{q/2} */
+    if (P->damping_q != 0.0) {
+        double xi[OR_MAXD];
+        or_start_point(P, seed, i, m, xi);
+        S /= or_damping(P, xi);
+    }
     return S;
 }
 
@@ -563,7 +601,8 @@ void or_sample_points(int d, int nu, uint64_t seed, uint32_t stream, int32_t i, 
 }
 
 /* Error indicators of Sec. 5, eq (mse) (natural logarithms), computed on
- * n points per time index drawn from stream 1, against u(t_i, .):
+ * n points per time index drawn from stream 1, against u(t_i, .), the
+ * prediction being the expansion times (1+|x|^2)^{q/2}:
  *   out[0] = MSE_max, out[1] = MSE_av, out[2] = relative L2 error at t_0. */
 void or_errors(const or_problem *P, int64_t nrep, const int32_t *reps, const double *alpha,
                uint64_t seed, int64_t n, double *out)
@@ -576,6 +615,7 @@ void or_errors(const or_problem *P, int64_t nrep, const int32_t *reps, const dou
     for (int i = 0; i < N; ++i) {
         or_sample_points(d, P->nu, seed, 1u, i, 0, n, x);
         or_eval(d, P->nu, nrep, reps, alpha + (int64_t)i * nf, n, x, y, NULL);
+        for (int64_t p = 0; p < n; ++p) y[p] *= or_damping(P, x + p * d);
         double se = 0.0, su = 0.0;
         for (int64_t p = 0; p < n; ++p) {
             double uex = or_msol_u(P, P->t[i], x + p * d);

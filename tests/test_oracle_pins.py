@@ -569,3 +569,95 @@ def test_linear_driver_unbiased_alpha_other_laws(law):
     assert np.abs(exp).max() > 0.05
     # start points come from stream 0 through this law's F^{-1}
     assert x[17, 1] == O.law_icdf(law, O.uniform(0, 0, 17, i, 1))
+
+
+# ---------------------------------------------------------------------------
+# damping exponent q > 0 (eq (yqi), Algorithm 1 with (1+|x|^2)^{q/2})
+# ---------------------------------------------------------------------------
+
+def _damp(x, q):
+    return (1.0 + float(np.dot(x, x))) ** (q / 2)
+
+
+def test_damping_divides_responses_of_a_y_independent_driver():
+    """With f = h (no dependence on y), eq (Sqi:bar:M) gives S^{(q)} = S^{(0)} /
+    (1+|X_i|^2)^{q/2} path by path, X_i the start point of the path."""
+    w0 = W.D2_TENSOR4.with_(driver="linear", f_a=0.0, sol_p=0.3)
+    wq = w0.with_(damping_q=2.5)
+    reps = O.reps_for(w0)
+    alpha = W.synthetic_alpha(O.nfuncs(reps), w0.N, seed=4, scale=0.2)
+    for i, m in [(9, 0), (5, 17), (0, 333)]:
+        xi = np.array([O.logistic_icdf(O.uniform(3, 0, m, i, l)) for l in range(2)])
+        s0 = O.path_response(w0, reps, i, 3, m, alpha)
+        sq = O.path_response(wq, reps, i, 3, m, alpha)
+        assert abs(sq * _damp(xi, 2.5) - s0) <= 1e-13 * max(1.0, abs(s0)), (i, m)
+        assert abs(O.damping(wq, xi) - _damp(xi, 2.5)) <= 1e-15 * _damp(xi, 2.5)
+
+
+def test_damped_value_and_gradient():
+    """y = ybar (1+|x|^2)^{q/2} (eq (yqi)) and its gradient by finite differences."""
+    d, q = 3, 2.5
+    w = W.D2_TENSOR4.with_(d=d, sigma=[[0.5 if a == b else 0.0 for b in range(d)] for a in range(d)],
+                           b0=[0.0] * d, b1=[0.0] * d, sol_w=[1.0, 1.0, 0.0], damping_q=q,
+                           set_kind="hc_1p", level=8)
+    reps = O.enumerate_set(d, "hc_1p", 8)
+    alpha = W.synthetic_alpha(O.nfuncs(reps), 1, seed=3)[0]
+    for x in W.logistic_points(4, d, seed=8):
+        y, g = O.eval_y(w, reps, alpha, x, grad=True)
+        assert abs(y - O.evaluate(reps, alpha, x[None, :])[0] * _damp(x, q)) <= 1e-13 * max(1, abs(y))
+        for l in range(d):
+            e = np.zeros(d)
+            e[l] = 1e-6
+            fd = (O.eval_y(w, reps, alpha, x + e) - O.eval_y(w, reps, alpha, x - e)) / 2e-6
+            assert abs(fd - g[l]) < 1e-6 * max(1.0, np.abs(g).max())
+
+
+@pytest.mark.parametrize("q", [1.0, 3.0])
+def test_damped_linear_driver_unbiased_alpha(q):
+    """Lemma 3.1 with damping: E[alpha^{(q)}_{i,k}] = <y_i / (1+|x|^2)^{q/2}, phi_k>_nu
+    with the closed-form y_i of f = h; the 2-D integral by the trapezoid rule
+    in x on [-40, 40]^2 (logistic tails beyond: < 1e-17)."""
+    w = W.D2_TENSOR4.with_(driver="linear", f_a=0.0, sol_p=0.2, sol_w=[1.0, 0.5], damping_q=q)
+    reps = O.reps_for(w)
+    i, M = 7, 1 << 14
+    alpha = np.zeros((w.N, O.nfuncs(reps)))
+    a, _, x, s = O.backward_step(w, reps, i, M, 0, alpha, want_x=True, want_s=True)
+    xs = np.linspace(-40, 40, 4001)
+    wts = np.full(xs.size, xs[1] - xs[0])
+    wts[[0, -1]] *= 0.5
+    F = special.expit(xs)
+    nu = F * (1 - F)
+    X1, X2 = np.meshgrid(xs, xs, indexing="ij")
+    G = (w.sol_A * _kappa(w, i) * np.cos(w.sol_w[0] * X1 + w.sol_w[1] * X2 + w.sol_p)
+         / (1 + X1 ** 2 + X2 ** 2) ** (q / 2)) * np.outer(nu * wts, nu * wts)
+    ks = np.arange(-4, 5)
+    E = np.exp(2j * np.pi * ks[:, None] * F[None, :])          # [9][n]
+    C_ = E @ G @ E.T                                            # c(k1, k2)
+    exp = np.zeros(O.nfuncs(reps))
+    exp[0] = C_[4, 4].real
+    for r in range(1, reps.shape[0]):
+        c = C_[reps[r, 0] + 4, reps[r, 1] + 4]
+        exp[2 * r - 1] = math.sqrt(2) * c.real
+        exp[2 * r] = math.sqrt(2) * c.imag
+    Phi = np.array([O.basis_values(reps, xi) for xi in x])
+    sd = (Phi * s[:, None]).std(axis=0) / math.sqrt(M)
+    assert np.all(np.abs(a - exp) <= 5 * sd + 1e-6)
+    assert np.abs(exp).max() > 0.02
+
+
+@pytest.mark.slow
+def test_damped_nonlinear_solve_recovers_u():
+    """The damped scheme solves the same PDE: with q = 1 the prediction
+    ybar^{(q)} (1+|x|^2)^{q/2} at t_0 approximates u(0, .) about as well as
+    the undamped one.  (Here it is somewhat worse, 0.56 against 0.46: with the
+    logistic law and 81 functions, y/(1+|x|^2)^{1/2} is no easier to project
+    than y; the paper's gain from damping is an asymptotic one for Student
+    laws and large sets.)  A consistency band only: a response divided at the
+    wrong point is caught by the exact identity above, but a y fed to the
+    driver without the factor stays inside it (checked by planting both)."""
+    w = W.D2_TENSOR4.with_(M=1 << 14)
+    reps = O.reps_for(w)
+    rel0 = O.errors(w, reps, O.solve(w, reps), n=1 << 13)[2]
+    wq = w.with_(damping_q=1.0)
+    relq = O.errors(wq, reps, O.solve(wq, reps), n=1 << 13)[2]
+    assert relq < rel0 + 0.2 and relq < 0.7, (rel0, relq)

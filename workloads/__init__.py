@@ -53,6 +53,7 @@ class Workload:
     clamp: float = math.inf
     seed: int = 0
     law: str = "logistic"
+    damping_q: float = 0.0
     notes: str = ""
 
     @property
