@@ -66,6 +66,7 @@ extern "C" {
 #endif
 
 #define QR_MAX_D 16    /* maximum state / Brownian dimension            */
+#define QR_MAX_DAMPING 64 /* largest damping exponent q                 */
 #define QR_MAX_N 128   /* maximum number of time steps                  */
 
 typedef enum {
@@ -156,6 +157,14 @@ typedef enum {
  * Drift b(t,x)_l = b0_l + b1_l x_l, constant diffusion sigma (d x nbm,
  * row-major), z = sigma^T grad_x y.  T = t[N].
  * clamp: level L of the truncation T_L applied to y (use INFINITY for none).
+ * damping_q: damping exponent q >= 0 of eq (yqi) (at most QR_MAX_DAMPING).
+ * With q > 0 the coefficients describe ybar^{(q)}_i = y_i / (1+|x|^2)^{q/2}
+ * (Algorithm 1): along the paths the expansion is multiplied back by
+ * (1+|x_{j+1}|^2)^{q/2} before T_L and the driver (its x-gradient by the
+ * product rule), and each response is divided by (1+|X_i|^2)^{q/2};
+ * qr_eval returns the expansion itself.  Only the plain FP64 entry points
+ * (qr_backward_step, qr_solve, qr_path_responses) take q > 0; the
+ * reduced-precision, batched and learned forms return QR_ENOTSUP.
  * All arrays are inline; entries beyond d / nbm / N are ignored.
  */
 typedef struct {
@@ -171,6 +180,7 @@ typedef struct {
     double sigma[QR_MAX_D * QR_MAX_D]; /* [d][nbm] row-major               */
     double sol_A, sol_c, sol_p;
     double sol_w[QR_MAX_D];
+    double damping_q;          /* damping exponent q >= 0 (0: none)          */
 } qr_problem;
 
 /* ---------------------------------------------------------------------- */

@@ -527,6 +527,8 @@ static qr_status check_problem(const qr_problem *p, const qr_basis *b) {
     if (p->driver < QR_F_LINEAR || p->driver > QR_F_ZRAT)
         return fail(QR_EINVAL, "problem: unknown driver %d", p->driver);
     if (!(p->clamp > 0.0)) return fail(QR_EINVAL, "problem: clamp must be > 0 (INFINITY for none)");
+    if (!(p->damping_q >= 0.0 && p->damping_q <= QR_MAX_DAMPING))
+        return fail(QR_EINVAL, "problem: damping exponent q=%g outside [0,%g]", p->damping_q, (double)QR_MAX_DAMPING);
     for (int j = 0; j < p->N; ++j)
         if (!(p->t[j + 1] > p->t[j]) || !std::isfinite(p->t[j + 1]) || !std::isfinite(p->t[j]))
             return fail(QR_EINVAL, "problem: time grid not strictly increasing at j=%d", j);
@@ -577,6 +579,7 @@ static qr_status upload_problem(qr_ctx *c, const qr_problem *p, int32_t law, hip
     h.sol_A = p->sol_A;
     h.sol_c = p->sol_c;
     h.sol_p = p->sol_p;
+    h.dq = p->damping_q;
     double sw2 = 0.0;
     for (int k = 0; k < p->nbm; ++k) {
         double v = 0.0;
@@ -653,7 +656,7 @@ static qr_status run_path(qr_ctx *c, const qr_problem *p, const qr_basis *b, int
                (double *)c->xstate.p, ldx};
     return timed(c, 0, s, "path_kernel", [&] {
         return launch_path(dim_bucket(p->d, p->nbm), depth_cap(b->max_nnz), p->driver == QR_F_ZRAT,
-                           a, s);
+                           p->damping_q != 0.0, a, s);
     });
 }
 
@@ -814,6 +817,7 @@ static qr_status prepare_prec(qr_ctx *c, const qr_problem *p, qr_basis *b, int64
         return fail(QR_EINVAL, "precision %d is not one of QR_PREC_F64/BF16/F16", prec);
     qr_status st = prepare(c, p, b, M, stream);
     if (st) return st;
+    if (p->damping_q != 0.0) return fail(QR_ENOTSUP, "reduced-precision form: damping exponent q must be 0");
     *tp = tile_plan(p, b);
     if ((st = ensure(c, c->tiles, sizeof(uint2) * (size_t)p->N * tp->ld, "coefficient tiles"))) return st;
     // the spare groups are read ahead and never used; keep them defined
@@ -1115,6 +1119,7 @@ extern "C" qr_status qr_solve_learned(qr_ctx *c, const qr_problem *p, const qr_b
     if (!alpha) return fail(QR_EINVAL, "qr_solve_learned: alpha is NULL");
     if (p->driver == QR_F_ZRAT)
         return fail(QR_ENOTSUP, "qr_solve_learned: the driver depends on z (the surrogate has no gradient)");
+    if (p->damping_q != 0.0) return fail(QR_ENOTSUP, "qr_solve_learned: damping exponent q must be 0");
     hipStream_t s = (hipStream_t)stream;
     const int d = p->d, N = p->N;
     const int64_t nt = o->train_points, nh = o->heldout_points;
@@ -1210,6 +1215,7 @@ extern "C" qr_status qr_solve_batched(qr_ctx *c, const qr_problem *p, const qr_b
     if (!inst || !alpha) return fail(QR_EINVAL, "qr_solve_batched: NULL instances or alpha");
     if (p->driver == QR_F_ZRAT)
         return fail(QR_ENOTSUP, "qr_solve_batched: the driver depends on z (gradients are not batched)");
+    if (p->damping_q != 0.0) return fail(QR_ENOTSUP, "qr_solve_batched: damping exponent q must be 0");
     int64_t Mmax = 0;
     for (int r = 0; r < R; ++r) {
         const qr_instance &I = inst[r];

@@ -195,6 +195,7 @@ struct DevProblem {
     double sol_A, sol_c, sol_p;
     double sol_w[kMaxD];
     double sw[kMaxD];                 // sigma^T w
+    double dq;                        // damping exponent q (0: none)
 };
 
 // Index-set rule of the traversal, branch-free for all three kinds: a node

@@ -78,7 +78,8 @@ hipError_t launch_gather(const double *alpha, int32_t row0, int32_t nrows, int64
                          int64_t nfuncs, const int32_t *canon_of_trav, double2 *alpha_int,
                          hipStream_t s);
 hipError_t launch_pad(int32_t nrows, int64_t nrep, int64_t ld, double2 *alpha_int, hipStream_t s);
-hipError_t launch_path(int db, int cap, bool grad, const PathArgs &a, hipStream_t s);
+// damp: the problem's damping exponent q is non-zero
+hipError_t launch_path(int db, int cap, bool grad, bool damp, const PathArgs &a, hipStream_t s);
 // tasks must have been cut to proj_shape(W.d).task_max nodes (task_max is checked)
 hipError_t launch_project(int cap, const Walk &W, const double2 *e, int64_t lde, const double *S, int64_t M,
                           int64_t paths_per_split, int32_t ntasks, int32_t nsplit, const Task *tasks,

@@ -140,6 +140,23 @@ __device__ __noinline__ double2 nl_sincos(double th) {
     return make_double2(sn, cs);
 }
 __device__ __noinline__ double nl_exp(double a) { return exp(a); }
+// damping factor D = (1+|x|^2)^{q/2} of eq (yqi) at the point x (d
+// coordinates at stride ldx), and q / (1+|x|^2) = (dD/dx_l) / (D x_l)
+__device__ __noinline__ double2 nl_damping_at(const DevProblem *P, const double *x, int64_t ldx) {
+    double r2 = 0.0;
+    for (int l = 0; l < P->d; ++l) r2 = fma(x[l * ldx], x[l * ldx], r2);
+    return make_double2(pow(1.0 + r2, 0.5 * P->dq), P->dq / (1.0 + r2));
+}
+// the damping factor at the start point X_i of path m, redrawn from stream 0
+__device__ __noinline__ double nl_start_damping(const DevProblem *P, uint64_t seed, int64_t m, int32_t i) {
+    PhiloxStream rs(seed, 0u, (uint64_t)m, (uint32_t)i, 0u);
+    double r2 = 0.0;
+    for (int l = 0; l < P->d; ++l) {
+        const double x = law_icdf(P->nu, rs.next());
+        r2 = fma(x, x, r2);
+    }
+    return pow(1.0 + r2, 0.5 * P->dq);
+}
 __device__ __noinline__ double nl_sin(double a) { return sin(a); }
 
 // ---------------------------------------------------------------------------
@@ -440,7 +457,9 @@ size_t path_lds_bytes(int32_t d, bool grad, int P) {
 #ifndef QRMC_PATH_WAVES_PER_EU
 #define QRMC_PATH_WAVES_PER_EU 3
 #endif
-template <int DB, int CAP, bool GRAD, int P>
+// DAMP: damping exponent q > 0 (its own instances, so that the undamped
+// kernels carry no code for it).
+template <int DB, int CAP, bool GRAD, int P, bool DAMP>
 __global__ __launch_bounds__(kPathBlock)
 __attribute__((amdgpu_waves_per_eu(QRMC_PATH_WAVES_PER_EU)))
 void path_kernel(
@@ -528,13 +547,19 @@ void path_kernel(
 #pragma unroll
             for (int q = 0; q < P; ++q) {
                 z2[q] = 0.0;
+                // with damping the expansion is ybar^{(q)} = y / D, D = (1+|x|^2)^{q/2}
+                // (eq (yqi)): y = ybar D, grad y = D (grad ybar + ybar q x / (1+|x|^2))
+                [[maybe_unused]] double2 D = make_double2(1.0, 0.0);
+                if constexpr (DAMP) D = nl_damping_at(Pj, xg + q * kPathBlock, ldx);
                 if constexpr (GRAD) {
                     double gx[DB];
 #pragma unroll
                     for (int l = 0; l < DB; ++l) {
                         gx[l] = 0.0;
                         if (l < d) {
-                            gx[l] = 2.0 * M_PI * L.g(l, q) * nl_pdf(Pj->nu, xg[l * ldx + q * kPathBlock]);
+                            const double xv = xg[l * ldx + q * kPathBlock];
+                            gx[l] = 2.0 * M_PI * L.g(l, q) * nl_pdf(Pj->nu, xv);
+                            if constexpr (DAMP) gx[l] = D.x * fma(y[q] * D.y, xv, gx[l]);
                         }
                     }
                     for (int k = 0; k < nbm; ++k) {
@@ -545,6 +570,7 @@ void path_kernel(
                         z2[q] = fma(zk, zk, z2[q]);
                     }
                 }
+                if constexpr (DAMP) y[q] *= D.x;
             }
         } else {
 #pragma unroll
@@ -578,7 +604,9 @@ void path_kernel(
         double x[DB];
 #pragma unroll
         for (int l = 0; l < DB; ++l) x[l] = (l < d) ? xg[l * ldx + q * kPathBlock] : 0.0;
-        const double Sq = S[q] + g_term<DB>(P0, x, d, nullptr);
+        double Sq = S[q] + g_term<DB>(P0, x, d, nullptr);
+        // the response of the damped quantity (Algorithm 1): over (1+|X_i|^2)^{q/2}
+        if constexpr (DAMP) Sq /= nl_start_damping(P0, seed, m, i);
         if (m < M) S_out[m] = Sq;
     }
 }
@@ -586,10 +614,10 @@ void path_kernel(
 // ---------------------------------------------------------------------------
 // project_kernel: block (task of the traversal, slice of paths).  Each wave
 // runs 64 P paths at a time through the task's nodes (P per lane); per node,
-// a lane writes the S-weighted sum of its points' values to a per-wave LDS
-// buffer, which is summed over the lanes every kProjChunk nodes into
-// per-wave accumulators; the block finally adds its waves in a fixed order
-// and writes the slice's partial sums.
+// a lane forms the S-weighted sum of its points' values, the sums are folded
+// across the lanes four nodes at a time (below) into per-wave accumulators,
+// and the block finally adds its waves in a fixed order and writes the
+// slice's partial sums.
 // ---------------------------------------------------------------------------
 // Cross-lane sums of the projection, four nodes at a time, in registers.
 // The real and imaginary parts of a node are folded across lanes L and L^32
@@ -1474,37 +1502,42 @@ int64_t path_state_ld(int64_t M, bool grad) {
     return (M + per - 1) / per * per;
 }
 
-template <int DB, int CAP, bool GRAD>
+template <int DB, int CAP, bool GRAD, bool DAMP>
 static hipError_t path_t(const PathArgs &a, hipStream_t s) {
     constexpr int P = GRAD ? 1 : kPathP;
     const size_t lds = path_lds_bytes(a.W.d, GRAD, P);
     static size_t granted = kLdsDefault;
-    const hipError_t e = allow_lds((const void *)path_kernel<DB, CAP, GRAD, P>, lds, granted);
+    const hipError_t e = allow_lds((const void *)path_kernel<DB, CAP, GRAD, P, DAMP>, lds, granted);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((path_kernel<DB, CAP, GRAD, P>), dim3(blocks_for(a.M, (int64_t)kPathBlock * P)),
+    hipLaunchKernelGGL((path_kernel<DB, CAP, GRAD, P, DAMP>), dim3(blocks_for(a.M, (int64_t)kPathBlock * P)),
                        dim3(kPathBlock), lds, s, a.P, a.W, a.i, a.M, a.seed, a.alpha_int, a.ld, a.S,
                        a.e, a.x0, a.xs, a.ldx);
     return hipGetLastError();
 }
 
-template <int DB, bool GRAD>
+template <int DB, bool GRAD, bool DAMP>
 static hipError_t path_cap(int cap, const PathArgs &a, hipStream_t s) {
     switch (cap) {
-    case 2: return path_t<DB, 2, GRAD>(a, s);
-    case 4: return path_t<DB, 4, GRAD>(a, s);
-    case 6: if constexpr (DB >= 6) return path_t<DB, 6, GRAD>(a, s); break;
-    case 8: if constexpr (DB >= 8) return path_t<DB, 8, GRAD>(a, s); break;
+    case 2: return path_t<DB, 2, GRAD, DAMP>(a, s);
+    case 4: return path_t<DB, 4, GRAD, DAMP>(a, s);
+    case 6: if constexpr (DB >= 6) return path_t<DB, 6, GRAD, DAMP>(a, s); break;
+    case 8: if constexpr (DB >= 8) return path_t<DB, 8, GRAD, DAMP>(a, s); break;
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_path(int db, int cap, bool grad, const PathArgs &a, hipStream_t s) {
+template <bool DAMP>
+static hipError_t path_db(int db, int cap, bool grad, const PathArgs &a, hipStream_t s) {
     switch (db) {
-    case 4: return grad ? path_cap<4, true>(cap, a, s) : path_cap<4, false>(cap, a, s);
-    case 8: return grad ? path_cap<8, true>(cap, a, s) : path_cap<8, false>(cap, a, s);
-    case 16: return grad ? path_cap<16, true>(cap, a, s) : path_cap<16, false>(cap, a, s);
+    case 4: return grad ? path_cap<4, true, DAMP>(cap, a, s) : path_cap<4, false, DAMP>(cap, a, s);
+    case 8: return grad ? path_cap<8, true, DAMP>(cap, a, s) : path_cap<8, false, DAMP>(cap, a, s);
+    case 16: return grad ? path_cap<16, true, DAMP>(cap, a, s) : path_cap<16, false, DAMP>(cap, a, s);
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_path(int db, int cap, bool grad, bool damp, const PathArgs &a, hipStream_t s) {
+    return damp ? path_db<true>(db, cap, grad, a, s) : path_db<false>(db, cap, grad, a, s);
 }
 
 template <int CAP, int P, int WAVES, int TM>

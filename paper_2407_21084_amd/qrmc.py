@@ -65,6 +65,7 @@ class Problem(C.Structure):
         ("sigma", C.c_double * (MAX_D * MAX_D)),
         ("sol_A", C.c_double), ("sol_c", C.c_double), ("sol_p", C.c_double),
         ("sol_w", C.c_double * MAX_D),
+        ("damping_q", C.c_double),
     ]
 
 
@@ -205,7 +206,7 @@ class Basis:
 
 
 def make_problem(d, N, T=None, times=None, sigma=None, b0=None, b1=None, driver="sin", f_a=0.0,
-                 sol_A=1.0, sol_c=1.0, sol_p=0.0, sol_w=None, clamp=math.inf) -> Problem:
+                 sol_A=1.0, sol_c=1.0, sol_p=0.0, sol_w=None, clamp=math.inf, damping_q=0.0) -> Problem:
     sigma = np.eye(d) if sigma is None else np.asarray(sigma, dtype=np.float64)
     nbm = sigma.shape[1]
     if times is None:
@@ -224,15 +225,16 @@ def make_problem(d, N, T=None, times=None, sigma=None, b0=None, b1=None, driver=
         for k in range(nbm):
             p.sigma[l * nbm + k] = sigma[l, k]
     p.sol_A, p.sol_c, p.sol_p = sol_A, sol_c, sol_p
+    p.damping_q = damping_q
     return p
 
 
 def problem_from(w) -> Problem:
     """Marshal any object with the workload attributes (d, N, T, sigma, b0,
-    b1, driver, f_a, sol_*, clamp) into a qr_problem."""
+    b1, driver, f_a, sol_*, clamp, optionally damping_q) into a qr_problem."""
     return make_problem(w.d, w.N, T=w.T, sigma=w.sigma, b0=w.b0, b1=w.b1, driver=w.driver,
                         f_a=w.f_a, sol_A=w.sol_A, sol_c=w.sol_c, sol_p=w.sol_p, sol_w=w.sol_w,
-                        clamp=w.clamp)
+                        clamp=w.clamp, damping_q=getattr(w, "damping_q", 0.0))
 
 
 # ---------------------------------------------------------------------------

@@ -1,0 +1,160 @@
+"""GPU parity with a damping exponent q > 0 (eq (yqi), Algorithm 1): the
+coefficients describe y_i / (1+|x|^2)^{q/2}; along the paths the expansion is
+multiplied back before T_L and the driver (gradient by the product rule), and
+each response is divided by (1+|X_i|^2)^{q/2}.  The HIP path against the CPU
+oracle with the tolerances of the undamped parity tests (relative 1e-10).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2407_21084_amd import qrmc as Q
+    ctx = Q.Context(0)
+    yield Q, ctx, torch
+    ctx.close()
+
+
+def _dev(torch, a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _host(t):
+    return t.detach().cpu().numpy()
+
+
+def _assert_alpha(gpu, ref, absum, tol=TOL, what=""):
+    scale = np.maximum(np.abs(ref), absum)
+    bad = np.abs(gpu - ref) > tol * scale + 1e-300
+    assert not bad.any(), f"{what}: {bad.sum()} coefficients off, worst {np.max(np.abs(gpu - ref) / (scale + 1e-300))}"
+    assert np.linalg.norm(gpu - ref) <= tol * np.linalg.norm(ref) + 1e-300, what
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _zrat(d, q, law="logistic"):
+    return W.Workload(name=f"zrat-d{d}-q{q}", d=d, N=4, T=1.0,
+                      sigma=[[0.5 if a == c else 0.0 for c in range(d)] for a in range(d)],
+                      b0=[0.0] * d, b1=[0.0] * d, set_kind="hc_1p", level=12, M=3000, driver="zrat",
+                      f_a=-0.05, sol_A=1.0, sol_c=1.0, sol_p=0.0,
+                      sol_w=[1.0 if l < 2 else 0.0 for l in range(d)], seed=3, law=law, damping_q=q)
+
+
+@pytest.mark.parametrize("q", [0.5, 2.5])
+@pytest.mark.parametrize("wname,i,M", [("d2", 8, 777), ("d2", 0, 300), ("zrat3", 1, 500)])
+def test_path_responses_damped(env, q, wname, i, M):
+    Q, ctx, torch = env
+    w = W.D2_TENSOR4.with_(damping_q=q) if wname == "d2" else _zrat(3, q)
+    _say(f"path_responses damped q={q} {w.name} i={i} M={M}")
+    b = Q.Basis(w.d, w.set_kind, w.level)
+    reps = O.reps_for(w)
+    alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=7, scale=0.2)
+    s = torch.empty(M, dtype=torch.float64, device="cuda")
+    ctx.path_responses(Q.problem_from(w), b, i, M, 5, _dev(torch, alpha), s)
+    torch.cuda.synchronize()
+    sg = _host(s)
+    for m in sorted(set([0, M - 1] + list(np.random.default_rng(1).integers(0, M, 6)))):
+        ref = O.path_response(w, reps, i, 5, int(m), alpha)
+        assert abs(sg[m] - ref) <= TOL * max(1.0, abs(ref)), (m, sg[m], ref)
+
+
+@pytest.mark.parametrize("q,law", [(2.5, "logistic"), (2.0, "cauchy"), (1.0, "student2")])
+@pytest.mark.parametrize("i", [9, 3])
+def test_backward_step_damped(env, q, law, i):
+    Q, ctx, torch = env
+    w = W.D2_TENSOR4.with_(damping_q=q, law=law)
+    _say(f"backward_step damped q={q} {law} i={i}")
+    b = Q.Basis(w.d, w.set_kind, w.level, law=law)
+    reps = O.reps_for(w)
+    alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=11, scale=0.2)
+    a = _dev(torch, alpha)
+    ctx.backward_step(Q.problem_from(w), b, i, w.M, w.seed, a)
+    torch.cuda.synchronize()
+    ref, absum, _, _ = O.backward_step(w, reps, i, w.M, w.seed, alpha.copy())
+    _assert_alpha(_host(a)[i], ref, absum, what=f"damped q={q} {law} row {i}")
+
+
+@pytest.mark.parametrize("d,i", [(3, 0), (8, 1)])
+def test_backward_step_damped_gradient_driver(env, d, i):
+    """z-dependent driver: z uses the gradient of ybar (1+|x|^2)^{q/2}."""
+    Q, ctx, torch = env
+    w = _zrat(d, 1.5)
+    _say(f"backward_step damped zrat d={d} i={i}")
+    b = Q.Basis(w.d, w.set_kind, w.level)
+    reps = O.reps_for(w)
+    alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=d, scale=0.2, decay=0.7)
+    a = _dev(torch, alpha)
+    ctx.backward_step(Q.problem_from(w), b, i, w.M, w.seed, a)
+    torch.cuda.synchronize()
+    ref, absum, _, _ = O.backward_step(w, reps, i, w.M, w.seed, alpha.copy())
+    _assert_alpha(_host(a)[i], ref, absum, what=f"damped zrat d={d} row {i}")
+
+
+def test_solve_damped_matches_oracle(env):
+    """Full damped solve (q = 1): rows against the oracle, and the error of
+    the prediction ybar (1+|x|^2)^{q/2} at t_0 equal to the oracle's."""
+    Q, ctx, torch = env
+    q = 1.0
+    w = W.D2_TENSOR4.with_(damping_q=q)
+    _say("solve d2 tensor damped q=1")
+    b = Q.Basis(w.d, w.set_kind, w.level)
+    reps = O.reps_for(w)
+    a = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device="cuda")
+    ctx.solve(Q.problem_from(w), b, w.M, w.seed, a)
+    torch.cuda.synchronize()
+    got = _host(a)
+    ref = O.solve(w, reps)
+    for i in (w.N - 1, w.N // 2, 0):
+        _, absum, _, _ = O.backward_step(w, reps, i, w.M, w.seed, ref.copy())
+        _assert_alpha(got[i], ref[i], absum, tol=1e-9, what=f"damped solve row {i}")
+    n = 1 << 14
+    x = torch.empty((w.d, n), dtype=torch.float64, device="cuda")
+    ctx.sample_points(w.d, w.seed, 1, 0, n, x)
+    y = torch.empty(n, dtype=torch.float64, device="cuda")
+    ctx.eval(b, a[0].contiguous(), x, y)
+    torch.cuda.synchronize()
+    xh = _host(x).T
+    pred = _host(y) * (1.0 + (xh ** 2).sum(axis=1)) ** (q / 2)
+    u = np.exp(-1.0) * np.cos(xh[:, 0] + xh[:, 1])
+    rel = np.linalg.norm(pred - u) / np.linalg.norm(u)
+    _, _, rel_oracle = O.errors(w, reps, ref, seed=w.seed, n=n)
+    assert abs(rel - rel_oracle) < 1e-8
+
+
+def test_damping_argument_checks(env):
+    Q, ctx, torch = env
+    w = W.D2_TENSOR4
+    b = Q.Basis(w.d, w.set_kind, w.level)
+    a = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device="cuda")
+    for bad in (-0.5, math.nan, 65.0):
+        with pytest.raises(Q.QrError) as e:
+            ctx.backward_step(Q.problem_from(w.with_(damping_q=bad)), b, w.N - 1, 100, 0, a)
+        assert e.value.status == -1
+    damped = Q.problem_from(w.with_(damping_q=1.0))
+    with pytest.raises(Q.QrError) as e:
+        ctx.solve_prec(damped, b, 100, 0, "bf16", a)
+    assert e.value.status == -6
+    with pytest.raises(Q.QrError) as e:
+        ctx.solve_batched(damped, b, [(0.5, w.d, w.level, 100)], 0, a[None])
+    assert e.value.status == -6
+    with pytest.raises(Q.QrError) as e:
+        ctx.solve_learned(damped, b, 100, 0, a, train_points=1 << 12, heldout_points=1 << 10,
+                          epochs=1, batch=1024, gate=0.0)
+    assert e.value.status == -6
