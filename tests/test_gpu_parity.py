@@ -469,3 +469,53 @@ def test_batched_group_full_size_sampled(env):
     _say(f"  instance {r}: step N-2 in full")
     ref, absum, _, _ = O.backward_step(wr, reps, gw.N - 2, M_r, gw.seed, prev)
     _assert_alpha(got[gw.N - 2, idx], ref, absum, what=f"instance {r} step N-2")
+
+
+# ---------------------------------------------------------------------------
+# the benchmark's workload at its full size (d = 6, 169,209 functions,
+# M = 2^20): the launch configurations the benchmark times, checked on
+# outputs the oracle computes one by one
+# ---------------------------------------------------------------------------
+
+def test_path_responses_bench_size_sampled(env):
+    """Step i = 0 (all 20 Euler steps and 19 expansion levels) for 2^20 paths;
+    sampled responses against the oracle's path by path."""
+    Q, ctx, torch = env
+    w = W.D6_HCMAX16
+    M, i = w.M, 0
+    _say(f"path_responses {w.name} i={i} M={M}")
+    b = Q.Basis(w.d, w.set_kind, w.level)
+    reps = O.reps_for(w)
+    alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=17, scale=0.05, decay=0.8)
+    s = torch.empty(M, dtype=torch.float64, device="cuda")
+    ctx.path_responses(Q.problem_from(w), b, i, M, w.seed, _dev(torch, alpha), s)
+    torch.cuda.synchronize()
+    sg = _host(s)
+    assert np.isfinite(sg).all()
+    for m in [0, 255, 256, 131071, 524288, M - 1]:
+        ref = O.path_response(w, reps, i, w.seed, m, alpha)
+        assert abs(sg[m] - ref) <= TOL * max(1.0, abs(ref)), (m, sg[m], ref)
+
+
+def test_project_bench_size_sampled(env):
+    """Projection of 2^20 points on the full d = 6 basis (the benchmark's
+    projection shape); sampled coefficients against the oracle, which projects
+    the same points on just the sampled representatives."""
+    Q, ctx, torch = env
+    w = W.D6_HCMAX16
+    n = w.M
+    _say(f"project {w.name} n={n}")
+    b = Q.Basis(w.d, w.set_kind, w.level)
+    reps = O.reps_for(w)
+    x = W.logistic_points(n, w.d, seed=23)
+    s = W.responses(n, seed=29)
+    a = torch.empty(b.n_funcs, dtype=torch.float64, device="cuda")
+    ctx.project(b, _dev(torch, x.T), _dev(torch, s), a)
+    torch.cuda.synchronize()
+    got = _host(a)
+    rng = np.random.default_rng(31)
+    picks = np.unique(np.concatenate([[1, 2, reps.shape[0] - 1], rng.integers(1, reps.shape[0], 9)]))
+    sub = np.concatenate([reps[:1], reps[picks]])           # the zero vector first
+    ref, absum = O.project(sub, x, s, with_abs=True)
+    idx = np.concatenate([[0], np.stack([2 * picks - 1, 2 * picks], axis=1).ravel()])
+    _assert_alpha(got[idx], ref, absum, what="bench-size projection")
