@@ -113,3 +113,17 @@ def test_basis_law_is_recorded_and_unknown_laws_rejected():
         with pytest.raises(Q.QrError) as e:
             Q.Basis(2, "tensor", 2, law=bad)
         assert e.value.status == -1
+
+
+def test_header_is_plain_c():
+    """include/qrmc.h is a C header: it compiles as C99 and as C++17 with
+    warnings as errors (no torch or C++ types in the boundary)."""
+    import shutil
+    import subprocess
+    hdr = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "qrmc.h")
+    for cc, std, lang in (("gcc", "c99", "c"), ("g++", "c++17", "c++")):
+        if shutil.which(cc) is None:
+            pytest.skip(f"{cc} not available")
+        r = subprocess.run([cc, f"-std={std}", "-Wall", "-Wextra", "-Werror", "-fsyntax-only", "-x", lang, hdr],
+                           capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr
