@@ -225,7 +225,9 @@ qr_status qr_backward_step(qr_ctx *ctx, const qr_problem *prob, const qr_basis *
 qr_status qr_solve(qr_ctx *ctx, const qr_problem *prob, const qr_basis *basis, int64_t M,
                    uint64_t seed, double *alpha, void *stream);
 
-/* Evaluate ybar = sum_k alpha_k phi_k at n points.
+/* Evaluate ybar = sum_k alpha_k phi_k at n points, phi_k = (Fourier
+ * function) o F of the basis's sampling law (with a damping exponent q > 0
+ * the caller multiplies by (1+|x|^2)^{q/2} to obtain y).
  * alpha_row: device [n_funcs] canonical order; x: device SoA [d][n];
  * y: device [n]; grad: device SoA [d][n] receiving grad_x ybar, or NULL. */
 qr_status qr_eval(qr_ctx *ctx, const qr_basis *basis, const double *alpha_row, int64_t n,
@@ -237,7 +239,7 @@ qr_status qr_eval(qr_ctx *ctx, const qr_basis *basis, const double *alpha_row, i
 /* ---------------------------------------------------------------------- */
 
 /* Projection alone (eq (Aqi:bar:M) on given samples):
- * alpha_row[k] = (1/n) sum_p s_p phi_k(x_p).
+ * alpha_row[k] = (1/n) sum_p s_p phi_k(x_p), phi_k of the basis's law.
  * x: device SoA [d][n]; s: device [n]; alpha_row: device [n_funcs]. */
 qr_status qr_project(qr_ctx *ctx, const qr_basis *basis, int64_t n, const double *x,
                      const double *s, double *alpha_row, void *stream);
