@@ -5,48 +5,16 @@ each response is divided by (1+|X_i|^2)^{q/2}.  The HIP path against the CPU
 oracle with the tolerances of the undamped parity tests (relative 1e-10).
 """
 import math
-import sys
 
 import numpy as np
 import pytest
 
 import oracle as O
 import workloads as W
+from gpu_common import env, dev, host, say, assert_alpha, TOL  # noqa: F401 (env is a fixture)
 
 pytestmark = pytest.mark.gpu
 
-TOL = 1e-10
-
-
-@pytest.fixture(scope="module")
-def env():
-    import torch
-    if not torch.cuda.is_available():
-        pytest.skip("no GPU")
-    from paper_2407_21084_amd import qrmc as Q
-    ctx = Q.Context(0)
-    yield Q, ctx, torch
-    ctx.close()
-
-
-def _dev(torch, a):
-    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
-
-
-def _host(t):
-    return t.detach().cpu().numpy()
-
-
-def _assert_alpha(gpu, ref, absum, tol=TOL, what=""):
-    scale = np.maximum(np.abs(ref), absum)
-    bad = np.abs(gpu - ref) > tol * scale + 1e-300
-    assert not bad.any(), f"{what}: {bad.sum()} coefficients off, worst {np.max(np.abs(gpu - ref) / (scale + 1e-300))}"
-    assert np.linalg.norm(gpu - ref) <= tol * np.linalg.norm(ref) + 1e-300, what
-
-
-def _say(msg):
-    print(msg, flush=True)
-    sys.stdout.flush()
 
 
 def _zrat(d, q, law="logistic"):
@@ -62,14 +30,14 @@ def _zrat(d, q, law="logistic"):
 def test_path_responses_damped(env, q, wname, i, M):
     Q, ctx, torch = env
     w = W.D2_TENSOR4.with_(damping_q=q) if wname == "d2" else _zrat(3, q)
-    _say(f"path_responses damped q={q} {w.name} i={i} M={M}")
+    say(f"path_responses damped q={q} {w.name} i={i} M={M}")
     b = Q.Basis(w.d, w.set_kind, w.level)
     reps = O.reps_for(w)
     alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=7, scale=0.2)
     s = torch.empty(M, dtype=torch.float64, device="cuda")
-    ctx.path_responses(Q.problem_from(w), b, i, M, 5, _dev(torch, alpha), s)
+    ctx.path_responses(Q.problem_from(w), b, i, M, 5, dev(torch, alpha), s)
     torch.cuda.synchronize()
-    sg = _host(s)
+    sg = host(s)
     for m in sorted(set([0, M - 1] + list(np.random.default_rng(1).integers(0, M, 6)))):
         ref = O.path_response(w, reps, i, 5, int(m), alpha)
         assert abs(sg[m] - ref) <= TOL * max(1.0, abs(ref)), (m, sg[m], ref)
@@ -80,15 +48,15 @@ def test_path_responses_damped(env, q, wname, i, M):
 def test_backward_step_damped(env, q, law, i):
     Q, ctx, torch = env
     w = W.D2_TENSOR4.with_(damping_q=q, law=law)
-    _say(f"backward_step damped q={q} {law} i={i}")
+    say(f"backward_step damped q={q} {law} i={i}")
     b = Q.Basis(w.d, w.set_kind, w.level, law=law)
     reps = O.reps_for(w)
     alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=11, scale=0.2)
-    a = _dev(torch, alpha)
+    a = dev(torch, alpha)
     ctx.backward_step(Q.problem_from(w), b, i, w.M, w.seed, a)
     torch.cuda.synchronize()
     ref, absum, _, _ = O.backward_step(w, reps, i, w.M, w.seed, alpha.copy())
-    _assert_alpha(_host(a)[i], ref, absum, what=f"damped q={q} {law} row {i}")
+    assert_alpha(host(a)[i], ref, absum, what=f"damped q={q} {law} row {i}")
 
 
 @pytest.mark.parametrize("d,i", [(3, 0), (8, 1)])
@@ -96,15 +64,15 @@ def test_backward_step_damped_gradient_driver(env, d, i):
     """z-dependent driver: z uses the gradient of ybar (1+|x|^2)^{q/2}."""
     Q, ctx, torch = env
     w = _zrat(d, 1.5)
-    _say(f"backward_step damped zrat d={d} i={i}")
+    say(f"backward_step damped zrat d={d} i={i}")
     b = Q.Basis(w.d, w.set_kind, w.level)
     reps = O.reps_for(w)
     alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=d, scale=0.2, decay=0.7)
-    a = _dev(torch, alpha)
+    a = dev(torch, alpha)
     ctx.backward_step(Q.problem_from(w), b, i, w.M, w.seed, a)
     torch.cuda.synchronize()
     ref, absum, _, _ = O.backward_step(w, reps, i, w.M, w.seed, alpha.copy())
-    _assert_alpha(_host(a)[i], ref, absum, what=f"damped zrat d={d} row {i}")
+    assert_alpha(host(a)[i], ref, absum, what=f"damped zrat d={d} row {i}")
 
 
 def test_solve_damped_matches_oracle(env):
@@ -113,25 +81,25 @@ def test_solve_damped_matches_oracle(env):
     Q, ctx, torch = env
     q = 1.0
     w = W.D2_TENSOR4.with_(damping_q=q)
-    _say("solve d2 tensor damped q=1")
+    say("solve d2 tensor damped q=1")
     b = Q.Basis(w.d, w.set_kind, w.level)
     reps = O.reps_for(w)
     a = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device="cuda")
     ctx.solve(Q.problem_from(w), b, w.M, w.seed, a)
     torch.cuda.synchronize()
-    got = _host(a)
+    got = host(a)
     ref = O.solve(w, reps)
     for i in (w.N - 1, w.N // 2, 0):
         _, absum, _, _ = O.backward_step(w, reps, i, w.M, w.seed, ref.copy())
-        _assert_alpha(got[i], ref[i], absum, tol=1e-9, what=f"damped solve row {i}")
+        assert_alpha(got[i], ref[i], absum, tol=1e-9, what=f"damped solve row {i}")
     n = 1 << 14
     x = torch.empty((w.d, n), dtype=torch.float64, device="cuda")
     ctx.sample_points(w.d, w.seed, 1, 0, n, x)
     y = torch.empty(n, dtype=torch.float64, device="cuda")
     ctx.eval(b, a[0].contiguous(), x, y)
     torch.cuda.synchronize()
-    xh = _host(x).T
-    pred = _host(y) * (1.0 + (xh ** 2).sum(axis=1)) ** (q / 2)
+    xh = host(x).T
+    pred = host(y) * (1.0 + (xh ** 2).sum(axis=1)) ** (q / 2)
     u = np.exp(-1.0) * np.cos(xh[:, 0] + xh[:, 1])
     rel = np.linalg.norm(pred - u) / np.linalg.norm(u)
     _, _, rel_oracle = O.errors(w, reps, ref, seed=w.seed, n=n)

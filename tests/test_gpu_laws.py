@@ -5,62 +5,30 @@ the tolerances of the logistic-law parity tests: relative 1e-10 per
 coefficient against max(|alpha_k|, A_k) and for the row in the 2-norm.
 """
 import math
-import sys
 
 import numpy as np
 import pytest
 
 import oracle as O
 import workloads as W
+from gpu_common import env, dev, host, say, assert_alpha, TOL  # noqa: F401 (env is a fixture)
 
 pytestmark = pytest.mark.gpu
 
-TOL = 1e-10
 LAWS = ["student2", "cauchy"]
-
-
-@pytest.fixture(scope="module")
-def env():
-    import torch
-    if not torch.cuda.is_available():
-        pytest.skip("no GPU")
-    from paper_2407_21084_amd import qrmc as Q
-    ctx = Q.Context(0)
-    yield Q, ctx, torch
-    ctx.close()
-
-
-def _dev(torch, a):
-    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
-
-
-def _host(t):
-    return t.detach().cpu().numpy()
-
-
-def _assert_alpha(gpu, ref, absum, tol=TOL, what=""):
-    scale = np.maximum(np.abs(ref), absum)
-    bad = np.abs(gpu - ref) > tol * scale + 1e-300
-    assert not bad.any(), f"{what}: {bad.sum()} coefficients off, worst {np.max(np.abs(gpu - ref) / (scale + 1e-300))}"
-    assert np.linalg.norm(gpu - ref) <= tol * np.linalg.norm(ref) + 1e-300, what
-
-
-def _say(msg):
-    print(msg, flush=True)
-    sys.stdout.flush()
 
 
 @pytest.mark.parametrize("law", LAWS)
 @pytest.mark.parametrize("n", [1, 5000])
 def test_sample_points_law(env, law, n):
     Q, ctx, torch = env
-    _say(f"sample_points {law} n={n}")
+    say(f"sample_points {law} n={n}")
     d = 5
     x = torch.empty((d, n), dtype=torch.float64, device="cuda")
     ctx.sample_points(d, 11, 1, 3, n, x, m0=17, law=law)
     torch.cuda.synchronize()
     ref = O.sample_points(d, 11, 1, 3, n, m0=17, law=law)
-    assert np.allclose(_host(x).T, ref, rtol=1e-13, atol=1e-15)
+    assert np.allclose(host(x).T, ref, rtol=1e-13, atol=1e-15)
 
 
 def test_basis_reports_its_law(env):
@@ -74,16 +42,16 @@ def test_basis_reports_its_law(env):
                                             (10, "hc_1p", 32, 300)])
 def test_project_law(env, law, d, kind, level, n):
     Q, ctx, torch = env
-    _say(f"project {law} d={d} {kind} {level} n={n}")
+    say(f"project {law} d={d} {kind} {level} n={n}")
     b = Q.Basis(d, kind, level, law=law)
     reps = O.enumerate_set(d, kind, level)
     x = W.law_points(n, d, law, seed=d + n)
     s = W.responses(n, seed=n)
     a = torch.empty(b.n_funcs, dtype=torch.float64, device="cuda")
-    ctx.project(b, _dev(torch, x.T), _dev(torch, s), a)
+    ctx.project(b, dev(torch, x.T), dev(torch, s), a)
     torch.cuda.synchronize()
     ref, absum = O.project(reps, x, s, with_abs=True, law=law)
-    _assert_alpha(_host(a), ref, absum, what=f"project {law}")
+    assert_alpha(host(a), ref, absum, what=f"project {law}")
 
 
 @pytest.mark.parametrize("law", LAWS)
@@ -91,22 +59,22 @@ def test_project_law(env, law, d, kind, level, n):
                                                  (3, "hc_1p", 12, 500, True)])
 def test_eval_law(env, law, d, kind, level, n, grad):
     Q, ctx, torch = env
-    _say(f"eval {law} d={d} {kind} {level} n={n} grad={grad}")
+    say(f"eval {law} d={d} {kind} {level} n={n} grad={grad}")
     b = Q.Basis(d, kind, level, law=law)
     reps = O.enumerate_set(d, kind, level)
     alpha = W.synthetic_alpha(b.n_funcs, 1, seed=3)[0]
     x = W.law_points(n, d, law, seed=1)
     y = torch.empty(n, dtype=torch.float64, device="cuda")
     g = torch.empty((d, n), dtype=torch.float64, device="cuda") if grad else None
-    ctx.eval(b, _dev(torch, alpha), _dev(torch, x.T), y, g)
+    ctx.eval(b, dev(torch, alpha), dev(torch, x.T), y, g)
     torch.cuda.synchronize()
     if grad:
         ry, rg = O.evaluate(reps, alpha, x, grad=True, law=law)
         scale = np.abs(alpha).sum() * 2 * math.pi * level
-        assert np.abs(_host(g).T - rg).max() <= TOL * scale
+        assert np.abs(host(g).T - rg).max() <= TOL * scale
     else:
         ry = O.evaluate(reps, alpha, x, law=law)
-    assert np.abs(_host(y) - ry).max() <= TOL * np.abs(alpha).sum()
+    assert np.abs(host(y) - ry).max() <= TOL * np.abs(alpha).sum()
 
 
 @pytest.mark.parametrize("law", LAWS)
@@ -114,15 +82,15 @@ def test_eval_law(env, law, d, kind, level, n, grad):
 def test_path_responses_law(env, law, i, M):
     Q, ctx, torch = env
     w = W.D2_TENSOR4.with_(law=law)
-    _say(f"path_responses {law} {w.name} i={i} M={M}")
+    say(f"path_responses {law} {w.name} i={i} M={M}")
     b = Q.Basis(w.d, w.set_kind, w.level, law=law)
     reps = O.reps_for(w)
     alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=7, scale=0.2)
     s = torch.empty(M, dtype=torch.float64, device="cuda")
     x0 = torch.empty((w.d, M), dtype=torch.float64, device="cuda")
-    ctx.path_responses(Q.problem_from(w), b, i, M, 5, _dev(torch, alpha), s, x0)
+    ctx.path_responses(Q.problem_from(w), b, i, M, 5, dev(torch, alpha), s, x0)
     torch.cuda.synchronize()
-    sg, xg = _host(s), _host(x0).T
+    sg, xg = host(s), host(x0).T
     ms = sorted(set([0, M - 1] + list(np.random.default_rng(0).integers(0, M, 6))))
     for m in ms:
         ref = O.path_response(w, reps, i, 5, int(m), alpha)
@@ -136,15 +104,15 @@ def test_path_responses_law(env, law, i, M):
 def test_backward_step_d2_tensor_law(env, law, i):
     Q, ctx, torch = env
     w = W.D2_TENSOR4.with_(law=law)
-    _say(f"backward_step {law} d2 tensor i={i}")
+    say(f"backward_step {law} d2 tensor i={i}")
     b = Q.Basis(w.d, w.set_kind, w.level, law=law)
     reps = O.reps_for(w)
     alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=11, scale=0.2)
-    a = _dev(torch, alpha)
+    a = dev(torch, alpha)
     ctx.backward_step(Q.problem_from(w), b, i, w.M, w.seed, a)
     torch.cuda.synchronize()
     ref, absum, _, _ = O.backward_step(w, reps, i, w.M, w.seed, alpha.copy())
-    _assert_alpha(_host(a)[i], ref, absum, what=f"{law} row {i}")
+    assert_alpha(host(a)[i], ref, absum, what=f"{law} row {i}")
 
 
 @pytest.mark.parametrize("law", LAWS)
@@ -157,15 +125,15 @@ def test_backward_step_gradient_driver_law(env, law, d, i):
                    b0=[0.0] * d, b1=[0.0] * d, set_kind="hc_1p", level=12, M=3000, driver="zrat",
                    f_a=-0.05, sol_A=1.0, sol_c=1.0, sol_p=0.0,
                    sol_w=[1.0 if l < 2 else 0.0 for l in range(d)], seed=3, law=law)
-    _say(f"backward_step zrat {law} d={d} i={i}")
+    say(f"backward_step zrat {law} d={d} i={i}")
     b = Q.Basis(w.d, w.set_kind, w.level, law=law)
     reps = O.reps_for(w)
     alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=d, scale=0.2, decay=0.7)
-    a = _dev(torch, alpha)
+    a = dev(torch, alpha)
     ctx.backward_step(Q.problem_from(w), b, i, w.M, w.seed, a)
     torch.cuda.synchronize()
     ref, absum, _, _ = O.backward_step(w, reps, i, w.M, w.seed, alpha.copy())
-    _assert_alpha(_host(a)[i], ref, absum, what=f"zrat {law} d={d} row {i}")
+    assert_alpha(host(a)[i], ref, absum, what=f"zrat {law} d={d} row {i}")
 
 
 @pytest.mark.parametrize("law", LAWS)
@@ -174,26 +142,26 @@ def test_solve_d2_law_matches_oracle(env, law):
     error at t_0 on stream-1 points of the law equal to the oracle's."""
     Q, ctx, torch = env
     w = W.D2_TENSOR4.with_(law=law)
-    _say(f"solve d2 tensor {law}")
+    say(f"solve d2 tensor {law}")
     b = Q.Basis(w.d, w.set_kind, w.level, law=law)
     reps = O.reps_for(w)
     a = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device="cuda")
     ctx.solve(Q.problem_from(w), b, w.M, w.seed, a)
     torch.cuda.synchronize()
-    got = _host(a)
+    got = host(a)
     ref = O.solve(w, reps)
     for i in (w.N - 1, w.N // 2, 0):
         _, absum, _, _ = O.backward_step(w, reps, i, w.M, w.seed, ref.copy())
-        _assert_alpha(got[i], ref[i], absum, tol=1e-9, what=f"solve {law} row {i}")
+        assert_alpha(got[i], ref[i], absum, tol=1e-9, what=f"solve {law} row {i}")
     n = 1 << 14
     x = torch.empty((w.d, n), dtype=torch.float64, device="cuda")
     ctx.sample_points(w.d, w.seed, 1, 0, n, x, law=law)
     y = torch.empty(n, dtype=torch.float64, device="cuda")
     ctx.eval(b, a[0].contiguous(), x, y)
     torch.cuda.synchronize()
-    xh = _host(x).T
+    xh = host(x).T
     u = np.exp(-1.0) * np.cos(xh[:, 0] + xh[:, 1])
-    rel = np.linalg.norm(_host(y) - u) / np.linalg.norm(u)
+    rel = np.linalg.norm(host(y) - u) / np.linalg.norm(u)
     _, _, rel_oracle = O.errors(w, reps, ref, seed=w.seed, n=n)
     assert abs(rel - rel_oracle) < 1e-8
 
@@ -218,17 +186,17 @@ def test_prec_backward_step_law(env, law, prec):
                    b0=[0.0] * d, b1=[0.0] * d, set_kind="hc_1p", level=12, M=4000, driver="zrat",
                    f_a=-0.05, sol_A=1.0, sol_c=1.0, sol_p=0.0,
                    sol_w=[1.0 if l < 2 else 0.0 for l in range(d)], seed=5, law=law)
-    _say(f"prec backward step {law} {prec}")
+    say(f"prec backward step {law} {prec}")
     b = Q.Basis(w.d, w.set_kind, w.level, law=law)
     reps = O.reps_for(w)
     alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=d, scale=0.2, decay=0.7)
     for i in (w.N - 2, 0):
-        a = _dev(torch, alpha)
+        a = dev(torch, alpha)
         ctx.backward_step_prec(Q.problem_from(w), b, i, w.M, w.seed, prec, a)
         torch.cuda.synchronize()
         ref, _, _, _ = O.backward_step(w, reps, i, w.M, w.seed, alpha.copy())
-        err = float(np.linalg.norm(_host(a)[i] - ref) / np.linalg.norm(ref))
-        _say(f"  row {i}: rel err {err:.3e}")
+        err = float(np.linalg.norm(host(a)[i] - ref) / np.linalg.norm(ref))
+        say(f"  row {i}: rel err {err:.3e}")
         assert err <= 8 * UNIT[prec], (i, err)
 
 
@@ -240,7 +208,7 @@ def test_batched_law_equals_unbatched(env, law):
     w = W.D2_TENSOR4.with_(law=law)
     b = Q.Basis(w.d, w.set_kind, w.level, law=law)
     fas = [0.2, 0.9]
-    _say(f"batched vs qr_solve, d2 tensor, {law}")
+    say(f"batched vs qr_solve, d2 tensor, {law}")
     a = torch.zeros((len(fas), w.N, b.n_funcs), dtype=torch.float64, device="cuda")
     ctx.solve_batched(Q.problem_from(w), b, [(f, w.d, w.level, w.M) for f in fas], w.seed, a)
     for r, f in enumerate(fas):
@@ -250,7 +218,7 @@ def test_batched_law_equals_unbatched(env, law):
         err = (a[r] - ref).abs().max().item()
         assert err <= TOL * ref.abs().max().item(), (f, err)
     oref = O.solve(w.with_(f_a=fas[0]), O.reps_for(w))
-    got = _host(a)[0]
+    got = host(a)[0]
     assert np.abs(got - oref).max() <= 1e-9 * np.abs(oref).max()
 
 

@@ -8,32 +8,16 @@ rare operand that rounds the other way, so outputs and gradients are
 compared with it to 2e-3 relative (2-norm per parameter block).  Against the
 exact FP64 network the bfloat16 effect itself, O(2^-8), is allowed (3e-2).
 """
-import sys
 
 import numpy as np
 import pytest
 
 import oracle as O
 import workloads as W
+from gpu_common import env, say, rel_err  # noqa: F401 (env is a fixture)
 from oracle import mlp
 
 pytestmark = pytest.mark.gpu
-
-
-@pytest.fixture(scope="module")
-def env():
-    import torch
-    if not torch.cuda.is_available():
-        pytest.skip("no GPU")
-    from paper_2407_21084_amd import qrmc as Q
-    ctx = Q.Context(0)
-    yield Q, ctx, torch
-    ctx.close()
-
-
-def _say(msg):
-    print(msg, flush=True)
-    sys.stdout.flush()
 
 
 def _f32(torch, a):
@@ -50,14 +34,10 @@ def _theta(seed):
     return mlp.pack(p).astype(np.float32).astype(np.float64)
 
 
-def _rel(a, b):
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
-
-
 @pytest.mark.parametrize("n", [1, 100, 4097])
 def test_forward_against_oracle(env, n):
     Q, ctx, torch = env
-    _say(f"mlp forward n={n}")
+    say(f"mlp forward n={n}")
     th = _theta(1)
     f = np.random.default_rng(n).uniform(-1, 1, (n, 16)).astype(np.float32).astype(np.float64)
     y = torch.empty(n, dtype=torch.float32, device="cuda")
@@ -66,15 +46,15 @@ def test_forward_against_oracle(env, n):
     got = y.cpu().numpy().astype(np.float64)
     yb, _ = mlp.forward_bf16(th, f)
     ye, _ = mlp.forward(th, f)
-    _say(f"  vs bf16-operand reference {_rel(got, yb):.2e}, vs exact {_rel(got, ye):.2e}")
-    assert _rel(got, yb) <= 2e-3
-    assert _rel(got, ye) <= 3e-2
+    say(f"  vs bf16-operand reference {rel_err(got, yb):.2e}, vs exact {rel_err(got, ye):.2e}")
+    assert rel_err(got, yb) <= 2e-3
+    assert rel_err(got, ye) <= 3e-2
 
 
 def test_loss_gradient_against_oracle(env):
     Q, ctx, torch = env
     n = 3000
-    _say("mlp loss gradient")
+    say("mlp loss gradient")
     rng = np.random.default_rng(7)
     th = _theta(2)
     f = rng.uniform(-1, 1, (n, 16)).astype(np.float32).astype(np.float64)
@@ -88,8 +68,8 @@ def test_loss_gradient_against_oracle(env):
     off = np.cumsum([0] + [int(np.prod(s)) for _, s in mlp.SIZES])
     for k, (name, _) in enumerate(mlp.SIZES):
         sl = slice(off[k], off[k + 1])
-        rb, re = _rel(got[sl], gb[sl]), _rel(got[sl], ge[sl])
-        _say(f"  {name}: vs bf16-operand {rb:.2e}, vs exact {re:.2e}")
+        rb, re = rel_err(got[sl], gb[sl]), rel_err(got[sl], ge[sl])
+        say(f"  {name}: vs bf16-operand {rb:.2e}, vs exact {re:.2e}")
         assert rb <= 2e-3, name
         assert re <= 3e-2, name
 
@@ -144,7 +124,7 @@ def test_training_fits_a_smooth_function(env):
         loss = ctx.mlp_loss_grad(th, tf, tt, g)
         first = loss if first is None else first
         ctx.mlp_adam(th, g, m, v, step, 3e-3)
-    _say(f"  loss {first:.3e} -> {loss:.3e}")
+    say(f"  loss {first:.3e} -> {loss:.3e}")
     assert loss < 2e-2 * first
 
 
@@ -164,7 +144,7 @@ def test_learned_solve_with_closed_gate_is_the_plain_solve(env):
     ref = torch.zeros_like(a)
     ctx.solve(Q.problem_from(w), b, w.M, w.seed, ref)
     torch.cuda.synchronize()
-    _say("  " + _report(rep))
+    say("  " + _report(rep))
     assert all(r["trained"] and not r["used"] for r in rep[1:]) and not rep[0]["trained"]
     err = (a - ref).abs().max().item()
     assert err <= 1e-12 * ref.abs().max().item(), err
@@ -192,13 +172,13 @@ def test_learned_solve_uses_the_surrogate_where_it_passes(env):
     ref = torch.zeros_like(a)
     ctx.solve(Q.problem_from(w), b, w.M, w.seed, ref)
     torch.cuda.synchronize()
-    _say("  " + _report(rep))
+    say("  " + _report(rep))
     used = [j for j, r in enumerate(rep) if r["used"]]
     assert used, "no surrogate passed the gate"
     got, r64 = a.cpu().numpy(), ref.cpu().numpy()
     for i in range(w.N):
-        e = _rel(got[i], r64[i])
-        _say(f"  row {i}: rel change {e:.2e}")
+        e = rel_err(got[i], r64[i])
+        say(f"  row {i}: rel change {e:.2e}")
         assert e <= 3 * gate
 
 

@@ -6,48 +6,16 @@ A_k = (1/M) sum |S phi_k| bounds the cancellation in the Monte-Carlo sum,
 and to the whole row in the 2-norm.
 """
 import math
-import sys
 
 import numpy as np
 import pytest
 
 import oracle as O
 import workloads as W
+from gpu_common import env, dev, host, say, assert_alpha, TOL  # noqa: F401 (env is a fixture)
 
 pytestmark = pytest.mark.gpu
 
-TOL = 1e-10
-
-
-@pytest.fixture(scope="module")
-def env():
-    import torch
-    if not torch.cuda.is_available():
-        pytest.skip("no GPU")
-    from paper_2407_21084_amd import qrmc as Q
-    ctx = Q.Context(0)
-    yield Q, ctx, torch
-    ctx.close()
-
-
-def _dev(torch, a):
-    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
-
-
-def _host(t):
-    return t.detach().cpu().numpy()
-
-
-def _assert_alpha(gpu, ref, absum, tol=TOL, what=""):
-    scale = np.maximum(np.abs(ref), absum)
-    bad = np.abs(gpu - ref) > tol * scale + 1e-300
-    assert not bad.any(), f"{what}: {bad.sum()} coefficients off, worst {np.max(np.abs(gpu - ref) / (scale + 1e-300))}"
-    assert np.linalg.norm(gpu - ref) <= tol * np.linalg.norm(ref) + 1e-300, what
-
-
-def _say(msg):
-    print(msg, flush=True)
-    sys.stdout.flush()
 
 
 # ---------------------------------------------------------------------------
@@ -57,13 +25,13 @@ def _say(msg):
 @pytest.mark.parametrize("n", [1, 257, 5000])
 def test_sample_points(env, n):
     Q, ctx, torch = env
-    _say(f"sample_points n={n}")
+    say(f"sample_points n={n}")
     d = 5
     x = torch.empty((d, n), dtype=torch.float64, device="cuda")
     ctx.sample_points(d, 11, 1, 3, n, x, m0=17)
     torch.cuda.synchronize()
     ref = O.sample_points(d, 11, 1, 3, n, m0=17)
-    assert np.allclose(_host(x).T, ref, rtol=1e-14, atol=1e-14)
+    assert np.allclose(host(x).T, ref, rtol=1e-14, atol=1e-14)
 
 
 @pytest.mark.parametrize("d,kind,level,n", [(2, "tensor", 4, 1), (2, "tensor", 4, 4099),
@@ -71,16 +39,16 @@ def test_sample_points(env, n):
                                             (1, "tensor", 0, 33), (10, "hc_1p", 32, 300)])
 def test_project(env, d, kind, level, n):
     Q, ctx, torch = env
-    _say(f"project d={d} {kind} {level} n={n}")
+    say(f"project d={d} {kind} {level} n={n}")
     b = Q.Basis(d, kind, level)
     reps = O.enumerate_set(d, kind, level)
     x = W.logistic_points(n, d, seed=d + n)
     s = W.responses(n, seed=n)
     a = torch.empty(b.n_funcs, dtype=torch.float64, device="cuda")
-    ctx.project(b, _dev(torch, x.T), _dev(torch, s), a)
+    ctx.project(b, dev(torch, x.T), dev(torch, s), a)
     torch.cuda.synchronize()
     ref, absum = O.project(reps, x, s, with_abs=True)
-    _assert_alpha(_host(a), ref, absum, what="project")
+    assert_alpha(host(a), ref, absum, what="project")
 
 
 @pytest.mark.parametrize("d,kind,level,n,grad", [(2, "tensor", 4, 1000, False), (2, "tensor", 4, 129, True),
@@ -88,22 +56,22 @@ def test_project(env, d, kind, level, n):
                                                  (10, "hc_1p", 32, 200, True)])
 def test_eval(env, d, kind, level, n, grad):
     Q, ctx, torch = env
-    _say(f"eval d={d} {kind} {level} n={n} grad={grad}")
+    say(f"eval d={d} {kind} {level} n={n} grad={grad}")
     b = Q.Basis(d, kind, level)
     reps = O.enumerate_set(d, kind, level)
     alpha = W.synthetic_alpha(b.n_funcs, 1, seed=3)[0]
     x = W.logistic_points(n, d, seed=1)
     y = torch.empty(n, dtype=torch.float64, device="cuda")
     g = torch.empty((d, n), dtype=torch.float64, device="cuda") if grad else None
-    ctx.eval(b, _dev(torch, alpha), _dev(torch, x.T), y, g)
+    ctx.eval(b, dev(torch, alpha), dev(torch, x.T), y, g)
     torch.cuda.synchronize()
     if grad:
         ry, rg = O.evaluate(reps, alpha, x, grad=True)
         scale = np.abs(alpha).sum() * 2 * math.pi * level
-        assert np.abs(_host(g).T - rg).max() <= TOL * scale
+        assert np.abs(host(g).T - rg).max() <= TOL * scale
     else:
         ry = O.evaluate(reps, alpha, x)
-    assert np.abs(_host(y) - ry).max() <= TOL * np.abs(alpha).sum()
+    assert np.abs(host(y) - ry).max() <= TOL * np.abs(alpha).sum()
 
 
 # ---------------------------------------------------------------------------
@@ -119,15 +87,15 @@ def _small(w, **kw):
 def test_path_responses(env, wname, i, M):
     Q, ctx, torch = env
     w = {"d2": W.D2_TENSOR4, "d6": W.D6_HCMAX16}[wname]
-    _say(f"path_responses {w.name} i={i} M={M}")
+    say(f"path_responses {w.name} i={i} M={M}")
     b = Q.Basis(w.d, w.set_kind, w.level)
     reps = O.reps_for(w)
     alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=7, scale=0.2)
     s = torch.empty(M, dtype=torch.float64, device="cuda")
     x0 = torch.empty((w.d, M), dtype=torch.float64, device="cuda")
-    ctx.path_responses(Q.problem_from(w), b, i, M, 5, _dev(torch, alpha), s, x0)
+    ctx.path_responses(Q.problem_from(w), b, i, M, 5, dev(torch, alpha), s, x0)
     torch.cuda.synchronize()
-    sg, xg = _host(s), _host(x0).T
+    sg, xg = host(s), host(x0).T
     ms = sorted(set([0, M - 1] + list(np.random.default_rng(0).integers(0, M, 6))))
     for m in ms:
         ref = O.path_response(w, reps, i, 5, int(m), alpha)
@@ -149,15 +117,15 @@ def test_backward_step_gradient_driver(env, d, i):
     """z-dependent driver: the walk carries the x-gradient of ybar (FP64)."""
     Q, ctx, torch = env
     w = _zrat(d)
-    _say(f"backward_step zrat d={d} i={i}")
+    say(f"backward_step zrat d={d} i={i}")
     b = Q.Basis(w.d, w.set_kind, w.level)
     reps = O.reps_for(w)
     alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=d, scale=0.2, decay=0.7)
-    a = _dev(torch, alpha)
+    a = dev(torch, alpha)
     ctx.backward_step(Q.problem_from(w), b, i, w.M, w.seed, a)
     torch.cuda.synchronize()
     ref, absum, _, _ = O.backward_step(w, reps, i, w.M, w.seed, alpha.copy())
-    _assert_alpha(_host(a)[i], ref, absum, what=f"zrat d={d} row {i}")
+    assert_alpha(host(a)[i], ref, absum, what=f"zrat d={d} row {i}")
 
 
 @pytest.mark.parametrize("w,i", [(W.D10_HC1P32_ZRAT, 27), (W.D16_HC1P32, 38)], ids=["d10-zrat", "d16"])
@@ -166,14 +134,14 @@ def test_path_responses_full_basis_sampled(env, w, i):
     of sampled paths of a step with two expansion levels ahead."""
     Q, ctx, torch = env
     M = 4096
-    _say(f"path_responses {w.name} i={i} M={M}")
+    say(f"path_responses {w.name} i={i} M={M}")
     b = Q.Basis(w.d, w.set_kind, w.level)
     reps = O.reps_for(w)
     alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=21, scale=0.05, decay=0.8)
     s = torch.empty(M, dtype=torch.float64, device="cuda")
-    ctx.path_responses(Q.problem_from(w), b, i, M, 9, _dev(torch, alpha), s)
+    ctx.path_responses(Q.problem_from(w), b, i, M, 9, dev(torch, alpha), s)
     torch.cuda.synchronize()
-    sg = _host(s)
+    sg = host(s)
     for m in [0, 77, 2048, M - 1]:
         ref = O.path_response(w, reps, i, 9, m, alpha)
         assert abs(sg[m] - ref) <= TOL * max(1.0, abs(ref)), (m, sg[m], ref)
@@ -183,17 +151,17 @@ def test_path_responses_full_basis_sampled(env, w, i):
 def test_backward_step_d2_tensor(env, i):
     Q, ctx, torch = env
     w = W.D2_TENSOR4
-    _say(f"backward_step d2 tensor i={i}")
+    say(f"backward_step d2 tensor i={i}")
     b = Q.Basis(w.d, w.set_kind, w.level)
     reps = O.reps_for(w)
     alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=11, scale=0.2)
-    a = _dev(torch, alpha)
+    a = dev(torch, alpha)
     ctx.backward_step(Q.problem_from(w), b, i, w.M, w.seed, a)
     torch.cuda.synchronize()
     ref_tab = alpha.copy()
     ref, absum, _, _ = O.backward_step(w, reps, i, w.M, w.seed, ref_tab)
-    got = _host(a)
-    _assert_alpha(got[i], ref, absum, what=f"row {i}")
+    got = host(a)
+    assert_alpha(got[i], ref, absum, what=f"row {i}")
     # other rows untouched
     rows = [r for r in range(w.N) if r != i]
     assert np.array_equal(got[rows], alpha[rows])
@@ -209,28 +177,28 @@ def test_backward_step_d6_hcmax_reduced_M(env):
     M = 600
     alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=13, scale=0.1, decay=0.8)
     for i in (19, 18):
-        _say(f"backward_step d6 hc_max i={i} M={M}")
-        a = _dev(torch, alpha)
+        say(f"backward_step d6 hc_max i={i} M={M}")
+        a = dev(torch, alpha)
         ctx.backward_step(Q.problem_from(w), b, i, M, w.seed, a)
         torch.cuda.synchronize()
         ref, absum, _, _ = O.backward_step(w, reps, i, M, w.seed, alpha.copy())
-        _assert_alpha(_host(a)[i], ref, absum, what=f"d6 hc_max row {i}")
+        assert_alpha(host(a)[i], ref, absum, what=f"d6 hc_max row {i}")
 
 
 def test_solve_d2_tensor_full(env):
     Q, ctx, torch = env
     w = W.D2_TENSOR4
-    _say("solve d2 tensor")
+    say("solve d2 tensor")
     b = Q.Basis(w.d, w.set_kind, w.level)
     reps = O.reps_for(w)
     a = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device="cuda")
     ctx.solve(Q.problem_from(w), b, w.M, w.seed, a)
     torch.cuda.synchronize()
-    got = _host(a)
+    got = host(a)
     ref = O.solve(w, reps)
     for i in range(w.N - 1, -1, -1):
         _, absum, _, _ = O.backward_step(w, reps, i, w.M, w.seed, ref.copy())
-        _assert_alpha(got[i], ref[i], absum, what=f"solve row {i}")
+        assert_alpha(got[i], ref[i], absum, what=f"solve row {i}")
     # deterministic: a second solve is bit-identical
     a2 = torch.zeros_like(a)
     ctx.solve(Q.problem_from(w), b, w.M, w.seed, a2)
@@ -253,9 +221,9 @@ def test_solve_d2_tensor_error_against_closed_form(env):
     y = torch.empty(n, dtype=torch.float64, device="cuda")
     ctx.eval(b, a[0].contiguous(), x, y)
     torch.cuda.synchronize()
-    xh = _host(x).T
+    xh = host(x).T
     u = np.exp(-1.0) * np.cos(xh[:, 0] + xh[:, 1])
-    rel = np.linalg.norm(_host(y) - u) / np.linalg.norm(u)
+    rel = np.linalg.norm(host(y) - u) / np.linalg.norm(u)
     _, _, rel_oracle = O.errors(w, reps, O.solve(w, reps), seed=w.seed, n=n)
     assert abs(rel - rel_oracle) < 1e-9
     assert 0.3 < rel < 0.6
@@ -263,7 +231,7 @@ def test_solve_d2_tensor_error_against_closed_form(env):
 
 def test_ragged_and_degenerate_sizes(env):
     Q, ctx, torch = env
-    _say("degenerate sizes")
+    say("degenerate sizes")
     # N = 1, d = 1, basis with only the constant (level 0)
     w = W.Workload(name="tiny", d=1, N=1, T=0.5, sigma=[[0.3]], b0=[0.1], b1=[0.2],
                    set_kind="tensor", level=0, M=5, driver="allen_cahn", f_a=0.0,
@@ -274,7 +242,7 @@ def test_ragged_and_degenerate_sizes(env):
     ctx.solve(Q.problem_from(w), b, w.M, 3, a)
     torch.cuda.synchronize()
     ref = O.solve(w, O.reps_for(w), M=5, seed=3)
-    assert abs(_host(a)[0, 0] - ref[0, 0]) <= TOL * abs(ref[0, 0])
+    assert abs(host(a)[0, 0] - ref[0, 0]) <= TOL * abs(ref[0, 0])
     # invalid: i out of range, M = 0
     with pytest.raises(Q.QrError):
         ctx.backward_step(Q.problem_from(w), b, 1, 5, 3, a)
@@ -291,7 +259,7 @@ def test_prefix_property(env):
     Q, ctx, torch = env
     w = W.D2_TENSOR4
     b = Q.Basis(w.d, w.set_kind, w.level)
-    alpha = _dev(torch, W.synthetic_alpha(b.n_funcs, w.N, seed=2, scale=0.2))
+    alpha = dev(torch, W.synthetic_alpha(b.n_funcs, w.N, seed=2, scale=0.2))
     s1 = torch.empty(1000, dtype=torch.float64, device="cuda")
     s2 = torch.empty(3333, dtype=torch.float64, device="cuda")
     ctx.path_responses(Q.problem_from(w), b, 3, 1000, 0, alpha, s1)
@@ -312,24 +280,24 @@ def test_d6_hcmax_full_size_sampled(env):
     w = W.D6_HCMAX16
     b = Q.Basis(w.d, w.set_kind, w.level)
     reps = O.reps_for(w)
-    _say("d6 hc_max full size: step N-1")
+    say("d6 hc_max full size: step N-1")
     a = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device="cuda")
     ctx.backward_step(Q.problem_from(w), b, w.N - 1, w.M, w.seed, a)
     torch.cuda.synchronize()
-    got = _host(a)[w.N - 1]
+    got = host(a)[w.N - 1]
     rng = np.random.default_rng(1)
     sub = np.concatenate([[0], np.sort(rng.choice(np.arange(1, reps.shape[0]), 24, replace=False))])
     sub_reps = np.ascontiguousarray(reps[sub])
     ref, absum, _, _ = O.backward_step(w, sub_reps, w.N - 1, w.M, w.seed,
                                        np.zeros((w.N, 2 * len(sub) - 1)))
     idx = [0] + [f for r in sub[1:] for f in (2 * r - 1, 2 * r)]
-    _assert_alpha(got[idx], ref, absum, what="d6 hc_max full N-1 sampled")
-    _say("d6 hc_max full size: responses of step N-2")
+    assert_alpha(got[idx], ref, absum, what="d6 hc_max full N-1 sampled")
+    say("d6 hc_max full size: responses of step N-2")
     alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=17, scale=0.1, decay=0.8)
     s = torch.empty(w.M, dtype=torch.float64, device="cuda")
-    ctx.path_responses(Q.problem_from(w), b, w.N - 2, w.M, w.seed, _dev(torch, alpha), s)
+    ctx.path_responses(Q.problem_from(w), b, w.N - 2, w.M, w.seed, dev(torch, alpha), s)
     torch.cuda.synchronize()
-    sg = _host(s)
+    sg = host(s)
     for m in [0, w.M - 1] + list(rng.integers(0, w.M, 14)):
         ref = O.path_response(w, reps, w.N - 2, w.seed, int(m), alpha)
         assert abs(sg[m] - ref) <= TOL * max(1.0, abs(ref)), m
@@ -368,7 +336,7 @@ def _check_batched_instance(got, w, full_reps, inst, seed, rows, what):
     assert not got[:, mask].any(), f"{what}: coefficients outside the instance's set are not 0"
     for i in rows:
         _, absum, _, _ = O.backward_step(wr, reps, i, M_r, seed, ref.copy())
-        _assert_alpha(got[i, idx], ref[i], absum, what=f"{what} row {i}")
+        assert_alpha(got[i, idx], ref[i], absum, what=f"{what} row {i}")
 
 
 def test_batched_against_oracle(env):
@@ -381,13 +349,13 @@ def test_batched_against_oracle(env):
     inst = [(0.3, 5, 12, 3000), (0.7, 2, 12, 2000), (0.5, 3, 4, 2500), (0.2, 4, 6, 1000),
             (0.9, 5, 8, 1), (0.4, 2, 2, 700), (0.6, 5, 12, 129), (0.25, 1, 12, 3000),
             (0.8, 3, 12, 1500), (0.35, 4, 1, 900)]
-    _say("batched: 10 small instances")
+    say("batched: 10 small instances")
     b = Q.Basis(w.d, w.set_kind, w.level)
     full_reps = O.enumerate_set(w.d, w.set_kind, w.level)
     a = torch.full((len(inst), w.N, b.n_funcs), 7.0, dtype=torch.float64, device="cuda")
     ctx.solve_batched(Q.problem_from(w), b, inst, w.seed, a)
     torch.cuda.synchronize()
-    got = _host(a)
+    got = host(a)
     for r, it in enumerate(inst):
         _check_batched_instance(got[r], w, full_reps, it, w.seed, range(w.N), what=f"instance {r} {it}")
     # deterministic
@@ -403,7 +371,7 @@ def test_batched_equals_unbatched_full_set(env):
     w = W.D2_TENSOR4
     b = Q.Basis(w.d, w.set_kind, w.level)
     fas = [0.2, 0.5, 0.9]
-    _say("batched vs qr_solve, d2 tensor")
+    say("batched vs qr_solve, d2 tensor")
     a = torch.zeros((len(fas), w.N, b.n_funcs), dtype=torch.float64, device="cuda")
     ctx.solve_batched(Q.problem_from(w), b, [(f, w.d, w.level, w.M) for f in fas], w.seed, a)
     for r, f in enumerate(fas):
@@ -438,7 +406,7 @@ def test_batched_group_full_size_sampled(env):
     gw, inst, _ = W.batched_group(W.batched_instances())[0]
     b = Q.Basis(gw.d, gw.set_kind, gw.level)
     full_reps = O.enumerate_set(gw.d, gw.set_kind, gw.level)
-    _say(f"batched group 0: d={gw.d} level={gw.level} M={gw.M} R={len(inst)} n_funcs={b.n_funcs}")
+    say(f"batched group 0: d={gw.d} level={gw.level} M={gw.M} R={len(inst)} n_funcs={b.n_funcs}")
     a = torch.zeros((len(inst), gw.N, b.n_funcs), dtype=torch.float64, device="cuda")
     ctx.solve_batched(Q.problem_from(gw), b, inst, gw.seed, a)
     torch.cuda.synchronize()
@@ -447,28 +415,28 @@ def test_batched_group_full_size_sampled(env):
     rng = np.random.default_rng(5)
     for r in [int(order[-1]), int(order[len(order) // 2]), int(order[0])]:
         f_a, d_r, level_r, M_r = inst[r]
-        _say(f"  instance {r}: d={d_r} level={level_r} M={M_r} reps={sizes[r]}")
+        say(f"  instance {r}: d={d_r} level={level_r} M={M_r} reps={sizes[r]}")
         wr = gw.with_(f_a=f_a)
         reps = _embed(O.enumerate_set(d_r, gw.set_kind, level_r), gw.d)
         pick = np.concatenate([[0], np.sort(rng.choice(np.arange(1, reps.shape[0]),
                                                        min(16, reps.shape[0] - 1), replace=False))])
         sub = np.ascontiguousarray(reps[pick])
-        got = _host(a[r])
+        got = host(a[r])
         ref, absum, _, _ = O.backward_step(wr, sub, gw.N - 1, M_r, gw.seed,
                                            np.zeros((gw.N, 2 * len(pick) - 1)))
-        _assert_alpha(got[gw.N - 1, _func_index(full_reps, sub)], ref, absum,
+        assert_alpha(got[gw.N - 1, _func_index(full_reps, sub)], ref, absum,
                       what=f"instance {r} step N-1")
     r = int(order[0])
     f_a, d_r, level_r, M_r = inst[r]
     wr = gw.with_(f_a=f_a)
     reps = _embed(O.enumerate_set(d_r, gw.set_kind, level_r), gw.d)
     idx = _func_index(full_reps, reps)
-    got = _host(a[r])
+    got = host(a[r])
     prev = np.zeros((gw.N, len(idx)))
     prev[gw.N - 1] = got[gw.N - 1, idx]
-    _say(f"  instance {r}: step N-2 in full")
+    say(f"  instance {r}: step N-2 in full")
     ref, absum, _, _ = O.backward_step(wr, reps, gw.N - 2, M_r, gw.seed, prev)
-    _assert_alpha(got[gw.N - 2, idx], ref, absum, what=f"instance {r} step N-2")
+    assert_alpha(got[gw.N - 2, idx], ref, absum, what=f"instance {r} step N-2")
 
 
 # ---------------------------------------------------------------------------
@@ -483,14 +451,14 @@ def test_path_responses_bench_size_sampled(env):
     Q, ctx, torch = env
     w = W.D6_HCMAX16
     M, i = w.M, 0
-    _say(f"path_responses {w.name} i={i} M={M}")
+    say(f"path_responses {w.name} i={i} M={M}")
     b = Q.Basis(w.d, w.set_kind, w.level)
     reps = O.reps_for(w)
     alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=17, scale=0.05, decay=0.8)
     s = torch.empty(M, dtype=torch.float64, device="cuda")
-    ctx.path_responses(Q.problem_from(w), b, i, M, w.seed, _dev(torch, alpha), s)
+    ctx.path_responses(Q.problem_from(w), b, i, M, w.seed, dev(torch, alpha), s)
     torch.cuda.synchronize()
-    sg = _host(s)
+    sg = host(s)
     assert np.isfinite(sg).all()
     for m in [0, 255, 256, 131071, 524288, M - 1]:
         ref = O.path_response(w, reps, i, w.seed, m, alpha)
@@ -504,18 +472,18 @@ def test_project_bench_size_sampled(env):
     Q, ctx, torch = env
     w = W.D6_HCMAX16
     n = w.M
-    _say(f"project {w.name} n={n}")
+    say(f"project {w.name} n={n}")
     b = Q.Basis(w.d, w.set_kind, w.level)
     reps = O.reps_for(w)
     x = W.logistic_points(n, w.d, seed=23)
     s = W.responses(n, seed=29)
     a = torch.empty(b.n_funcs, dtype=torch.float64, device="cuda")
-    ctx.project(b, _dev(torch, x.T), _dev(torch, s), a)
+    ctx.project(b, dev(torch, x.T), dev(torch, s), a)
     torch.cuda.synchronize()
-    got = _host(a)
+    got = host(a)
     rng = np.random.default_rng(31)
     picks = np.unique(np.concatenate([[1, 2, reps.shape[0] - 1], rng.integers(1, reps.shape[0], 9)]))
     sub = np.concatenate([reps[:1], reps[picks]])           # the zero vector first
     ref, absum = O.project(sub, x, s, with_abs=True)
     idx = np.concatenate([[0], np.stack([2 * picks - 1, 2 * picks], axis=1).ravel()])
-    _assert_alpha(got[idx], ref, absum, what="bench-size projection")
+    assert_alpha(got[idx], ref, absum, what="bench-size projection")

@@ -12,47 +12,18 @@ with REL[precision] = 8u, which leaves the rounding-error estimate a wide
 margin while still failing on any layout or indexing mistake (those give
 O(1) errors).
 """
-import math
-import sys
 
 import numpy as np
 import pytest
 
 import oracle as O
 import workloads as W
+from gpu_common import env, dev, host, say, rel_err  # noqa: F401 (env is a fixture)
 
 pytestmark = pytest.mark.gpu
 
 UNIT = {"bf16": 2.0 ** -8, "f16": 2.0 ** -11}
 REL = {p: 8 * u for p, u in UNIT.items()}
-
-
-@pytest.fixture(scope="module")
-def env():
-    import torch
-    if not torch.cuda.is_available():
-        pytest.skip("no GPU")
-    from paper_2407_21084_amd import qrmc as Q
-    ctx = Q.Context(0)
-    yield Q, ctx, torch
-    ctx.close()
-
-
-def _dev(torch, a):
-    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
-
-
-def _host(t):
-    return t.detach().cpu().numpy()
-
-
-def _say(msg):
-    print(msg, flush=True)
-    sys.stdout.flush()
-
-
-def _rel(a, b):
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
 def _zrat_small(d=3):
@@ -70,17 +41,17 @@ def test_prec_backward_step_gradient_driver(env, prec, d):
     sides (2, 2, 3, 4 and 5 groups of four for d = 3, 6, 10, 13, 16)."""
     Q, ctx, torch = env
     w = _zrat_small(d)
-    _say(f"prec backward step zrat d={d} {prec}")
+    say(f"prec backward step zrat d={d} {prec}")
     b = Q.Basis(w.d, w.set_kind, w.level)
     reps = O.reps_for(w)
     alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=d, scale=0.2, decay=0.7)
     for i in (w.N - 2, 0):
-        a = _dev(torch, alpha)
+        a = dev(torch, alpha)
         ctx.backward_step_prec(Q.problem_from(w), b, i, w.M, w.seed, prec, a)
         torch.cuda.synchronize()
         ref, _, _, _ = O.backward_step(w, reps, i, w.M, w.seed, alpha.copy())
-        err = _rel(_host(a)[i], ref)
-        _say(f"  row {i}: rel err {err:.3e} (tol {REL[prec]:.1e})")
+        err = rel_err(host(a)[i], ref)
+        say(f"  row {i}: rel err {err:.3e} (tol {REL[prec]:.1e})")
         assert err <= REL[prec], (i, err)
 
 
@@ -90,16 +61,16 @@ def test_prec_solve_value_driver(env, prec):
     workload against the oracle row by row, and the closed-form error."""
     Q, ctx, torch = env
     w = W.D2_TENSOR4
-    _say(f"prec solve d2 tensor {prec}")
+    say(f"prec solve d2 tensor {prec}")
     b = Q.Basis(w.d, w.set_kind, w.level)
     reps = O.reps_for(w)
     a = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device="cuda")
     ctx.solve_prec(Q.problem_from(w), b, w.M, w.seed, prec, a)
     torch.cuda.synchronize()
-    got = _host(a)
+    got = host(a)
     ref = O.solve(w, reps)
-    errs = [_rel(got[i], ref[i]) for i in range(w.N)]
-    _say("  per-row rel err " + " ".join(f"{e:.1e}" for e in errs))
+    errs = [rel_err(got[i], ref[i]) for i in range(w.N)]
+    say("  per-row rel err " + " ".join(f"{e:.1e}" for e in errs))
     assert max(errs) <= REL[prec]
     # error against u(0,.) at the stream-1 test points: the precision form
     # does not move the method's error
@@ -109,11 +80,11 @@ def test_prec_solve_value_driver(env, prec):
     y = torch.empty(n, dtype=torch.float64, device="cuda")
     ctx.eval(b, a[0].contiguous(), x, y)
     torch.cuda.synchronize()
-    xh = _host(x).T
+    xh = host(x).T
     u = np.exp(-1.0) * np.cos(xh[:, 0] + xh[:, 1])
-    rel = np.linalg.norm(_host(y) - u) / np.linalg.norm(u)
+    rel = np.linalg.norm(host(y) - u) / np.linalg.norm(u)
     _, _, rel64 = O.errors(w, reps, ref, seed=w.seed, n=n)
-    _say(f"  closed-form rel L2: {rel:.4f} vs FP64 {rel64:.4f}")
+    say(f"  closed-form rel L2: {rel:.4f} vs FP64 {rel64:.4f}")
     assert abs(rel - rel64) <= 0.02 * rel64
 
 
@@ -122,19 +93,19 @@ def test_prec_full_basis_gradient_sampled(env):
     the z-dependent driver: step N-2 at M = 2^16 in bfloat16 against the oracle."""
     Q, ctx, torch = env
     w = W.D10_HC1P32_ZRAT.with_(M=1 << 16)
-    _say("prec d10 hc_1p basis, step N-2, M=2^16")
+    say("prec d10 hc_1p basis, step N-2, M=2^16")
     b = Q.Basis(w.d, w.set_kind, w.level)
     reps = O.reps_for(w)
     alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=31, scale=0.1, decay=0.8)
     i = w.N - 2
     for prec in ("bf16", "f16"):
-        a = _dev(torch, alpha)
+        a = dev(torch, alpha)
         ctx.backward_step_prec(Q.problem_from(w), b, i, w.M, w.seed, prec, a)
         torch.cuda.synchronize()
         if prec == "bf16":
             ref, _, _, _ = O.backward_step(w, reps, i, w.M, w.seed, alpha.copy())
-        err = _rel(_host(a)[i], ref)
-        _say(f"  {prec}: rel err {err:.3e}")
+        err = rel_err(host(a)[i], ref)
+        say(f"  {prec}: rel err {err:.3e}")
         assert err <= REL[prec]
 
 
