@@ -133,6 +133,20 @@ __device__ __forceinline__ double nl_pdf(int32_t nu, double x) {
 __device__ __forceinline__ double2 nl_unit_phase(int32_t nu, double x) {
     return nu == QR_LAW_LOGISTIC ? nl_unit_phase_logistic(x) : nl_unit_phase_other(nu, x);
 }
+// The same with the law stated wave-uniform (readfirstlane: it is the same
+// for the whole launch), so that the choice is a scalar branch, not a
+// lane-masked one.  Measured: 2.5 % faster for the reduced-precision walk,
+// 1.2 % slower for the FP64 path kernel, which keeps the forms above.
+__device__ __forceinline__ int32_t uniform_law(int32_t nu) { return __builtin_amdgcn_readfirstlane(nu); }
+__device__ __forceinline__ double nl_icdf_u(int32_t nu, double u) {
+    return uniform_law(nu) == QR_LAW_LOGISTIC ? nl_icdf_logistic(u) : nl_icdf_other(nu, u);
+}
+__device__ __forceinline__ double nl_pdf_u(int32_t nu, double x) {
+    return uniform_law(nu) == QR_LAW_LOGISTIC ? nl_pdf_logistic(x) : nl_pdf_other(nu, x);
+}
+__device__ __forceinline__ double2 nl_unit_phase_u(int32_t nu, double x) {
+    return uniform_law(nu) == QR_LAW_LOGISTIC ? nl_unit_phase_logistic(x) : nl_unit_phase_other(nu, x);
+}
 __device__ __noinline__ double2 nl_sincos(double th) {
     // (sin th, cos th); sincospi avoids the large-argument reduction
     double sn, cs;
@@ -1011,9 +1025,9 @@ __global__ __launch_bounds__(kPathBlock) void mfma_path_kernel(
     {
         PhiloxStream rs(seed, 0u, (uint64_t)m, (uint32_t)i, 0u);
         for (int l = 0; l < d; ++l) {
-            const double x = nl_icdf(P0->nu, rs.next());
+            const double x = nl_icdf_u(P0->nu, rs.next());
             xs[l * kPathBlock] = x;
-            if (e_out && m < M) e_out[l * M + m] = nl_unit_phase(P0->nu, x);
+            if (e_out && m < M) e_out[l * M + m] = nl_unit_phase_u(P0->nu, x);
         }
     }
     double S = 0.0;
@@ -1047,7 +1061,7 @@ __global__ __launch_bounds__(kPathBlock) void mfma_path_kernel(
         double y, z2 = 0.0;
         if (j + 1 < N) {
             for (int l = 0; l < d; ++l) {
-                const double2 e = nl_unit_phase(Pj->nu, xs[l * kPathBlock]);
+                const double2 e = nl_unit_phase_u(Pj->nu, xs[l * kPathBlock]);
                 L.set_e(l, 0, make_float2((float)e.x, (float)e.y));
             }
             MfmaSink<PREC, T> sink;
@@ -1069,7 +1083,7 @@ __global__ __launch_bounds__(kPathBlock) void mfma_path_kernel(
                 for (int l = 0; l < DB; ++l) {
                     gx[l] = 0.0;
                     if (l < d) {
-                        gx[l] = (double)sink.acc[(l + 1) / 4][(l + 1) % 4] * nl_pdf(Pj->nu, xs[l * kPathBlock]);
+                        gx[l] = (double)sink.acc[(l + 1) / 4][(l + 1) % 4] * nl_pdf_u(Pj->nu, xs[l * kPathBlock]);
                     }
                 }
                 for (int k = 0; k < nbm; ++k) {
