@@ -42,11 +42,10 @@
  *   - the driver may depend on z = sigma^T grad y (explicit: evaluated at
  *     X_{j+1} together with y);
  *   - a damping exponent q >= 0 (eq (yqi)): the expansions approximate
- *     y_i / (1+|x|^2)^{q/2}; q = 0 gives y_i itself.  Parity unpinned for
- *     one step of it: the factor (1+|x|^2)^{q/2} on the y handed to the
- *     driver (or_eval_y) is checked only against its definition; the
- *     division of the response and the projection target are pinned
- *     (exact identity, Lemma 3.1 by quadrature);
+ *     y_i / (1+|x|^2)^{q/2}; q = 0 gives y_i itself.  The factor on the y
+ *     handed to the driver, the division of the response and the projection
+ *     target are each pinned (Lemma 3.1 with Gaussian moments, an exact
+ *     identity, Lemma 3.1 by quadrature);
  *   - a constant truncation level L.
  */
 #include <math.h>

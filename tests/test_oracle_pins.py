@@ -661,3 +661,62 @@ def test_damped_nonlinear_solve_recovers_u():
     wq = w.with_(damping_q=1.0)
     relq = O.errors(wq, reps, O.solve(wq, reps), n=1 << 13)[2]
     assert relq < rel0 + 0.2 and relq < 0.7, (rel0, relq)
+
+
+def test_damped_factor_on_the_driver_input_lemma31():
+    """The factor (1+|X_{j+1}|^2)^{q/2} on the y handed to the driver (eqs
+    (yqi), (Sqi:bar:M)), pinned by Lemma 3.1 with a closed form.  d = 1,
+    q = 2, zero drift, the Allen-Cahn driver, no truncation and a constant row
+    ybar_{N-1} = c: at step i = N-2 the driver input is y = c (1 + X_{N-1}^2)
+    with X_{N-1} ~ N(x, s^2), s^2 = sigma^2 dt, given X_{N-2} = x.  Solving
+    twice on the same streams, with c and with c = 0, every other term of S
+    cancels path by path, so the difference of the estimated coefficients is
+    unbiased (Lemma 3.1) for
+        < dt E[y - y^3 | x] / (1 + x^2), phi_k >_nu,
+    where E[(1+X^2)^n | x] follows from the Gaussian moments
+    E X^2 = x^2 + s^2, E X^4 = x^4 + 6 x^2 s^2 + 3 s^4,
+    E X^6 = x^6 + 15 x^4 s^2 + 45 x^2 s^4 + 15 s^6, and the inner product is a
+    1-D trapezoid integral against the logistic density.  The same target
+    without the factor, (c - c^3) dt / (1+x^2), is many standard deviations
+    away, so a y fed to the driver without it fails here."""
+    q, c = 2.0, 0.01
+    w = W.D2_TENSOR4.with_(d=1, sigma=[[0.5]], b0=[0.0], b1=[0.0], sol_w=[1.0], sol_p=0.3,
+                           driver="allen_cahn", f_a=0.0, clamp=math.inf, damping_q=q,
+                           set_kind="tensor", level=4)
+    reps = O.reps_for(w)
+    nf = O.nfuncs(reps)
+    i, M = w.N - 2, 1 << 15
+    a_c = np.zeros((w.N, nf))
+    a_c[w.N - 1, 0] = c
+    _, _, x, s_c = O.backward_step(w, reps, i, M, 0, a_c, want_x=True, want_s=True)
+    _, _, x0, s_0 = O.backward_step(w, reps, i, M, 0, np.zeros((w.N, nf)), want_x=True, want_s=True)
+    assert np.array_equal(x, x0)
+    Phi = np.array([O.basis_values(reps, xi) for xi in x])
+    ds = (s_c - s_0)[:, None] * Phi
+    est = ds.mean(axis=0)
+    sd = ds.std(axis=0) / math.sqrt(M)
+    dt = w.times[i + 1] - w.times[i]
+    s2 = 0.25 * dt
+    xs = np.linspace(-60, 60, 480001)
+    F = special.expit(xs)
+    nu = F * (1 - F)
+    X2 = xs ** 2 + s2
+    X4 = xs ** 4 + 6 * xs ** 2 * s2 + 3 * s2 ** 2
+    X6 = xs ** 6 + 15 * xs ** 4 * s2 + 45 * xs ** 2 * s2 ** 2 + 15 * s2 ** 3
+    Ey = c * (1 + X2)                              # E[y | x]
+    Ey3 = c ** 3 * (1 + 3 * X2 + 3 * X4 + X6)      # E[y^3 | x]
+    target = dt * (Ey - Ey3) / (1 + xs ** 2)
+    planted = dt * (c - c ** 3) / (1 + xs ** 2)
+
+    def proj(g):
+        out = np.zeros(nf)
+        out[0] = np.trapezoid(g * nu, xs)
+        for r in range(1, reps.shape[0]):
+            th = 2 * np.pi * reps[r, 0] * F
+            out[2 * r - 1] = math.sqrt(2) * np.trapezoid(g * np.cos(th) * nu, xs)
+            out[2 * r] = math.sqrt(2) * np.trapezoid(g * np.sin(th) * nu, xs)
+        return out
+
+    exp, wrong = proj(target), proj(planted)
+    assert np.all(np.abs(est - exp) <= 5 * sd + 1e-12), np.max(np.abs(est - exp) / sd)
+    assert abs(est[0] - wrong[0]) > 50 * sd[0]
