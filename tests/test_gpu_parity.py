@@ -303,6 +303,40 @@ def test_d6_hcmax_full_size_sampled(env):
         assert abs(sg[m] - ref) <= TOL * max(1.0, abs(ref)), m
 
 
+def test_d16_hc1p_full_size_sampled(env):
+    """The d = 16 workload at full size (599,969 functions, M = 2^22): step
+    N-1 coefficients for sampled k (the oracle projects its own responses of
+    all 2^22 paths on the sampled representatives), and step N-2 responses
+    (one 599,969-term expansion level ahead) for sampled paths."""
+    Q, ctx, torch = env
+    w = W.D16_HC1P32
+    b = Q.Basis(w.d, w.set_kind, w.level)
+    reps = O.reps_for(w)
+    assert b.n_funcs == 599969 and w.M == 1 << 22
+    say("d16 hc_1p full size: step N-1")
+    a = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device="cuda")
+    ctx.backward_step(Q.problem_from(w), b, w.N - 1, w.M, w.seed, a)
+    torch.cuda.synchronize()
+    got = host(a[w.N - 1])
+    del a
+    rng = np.random.default_rng(5)
+    sub = np.concatenate([[0], np.sort(rng.choice(np.arange(1, reps.shape[0]), 16, replace=False))])
+    ref, absum, _, _ = O.backward_step(w, np.ascontiguousarray(reps[sub]), w.N - 1, w.M, w.seed,
+                                       np.zeros((w.N, 2 * len(sub) - 1)))
+    idx = [0] + [f for r in sub[1:] for f in (2 * r - 1, 2 * r)]
+    assert_alpha(got[idx], ref, absum, what="d16 hc_1p full N-1 sampled")
+    say("d16 hc_1p full size: responses of step N-2")
+    alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=19, scale=0.05, decay=0.8)
+    s = torch.empty(w.M, dtype=torch.float64, device="cuda")
+    ctx.path_responses(Q.problem_from(w), b, w.N - 2, w.M, w.seed, dev(torch, alpha), s)
+    torch.cuda.synchronize()
+    sg = host(s)
+    assert np.isfinite(sg).all()
+    for m in [0, w.M - 1] + list(rng.integers(0, w.M, 6)):
+        ref = O.path_response(w, reps, w.N - 2, w.seed, int(m), alpha)
+        assert abs(sg[m] - ref) <= TOL * max(1.0, abs(ref)), m
+
+
 # ---------------------------------------------------------------------------
 # batched form: instances on one shared cloud
 # ---------------------------------------------------------------------------
