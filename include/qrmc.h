@@ -234,6 +234,33 @@ qr_status qr_eval(qr_ctx *ctx, const qr_basis *basis, const double *alpha_row, i
                   const double *x, double *y, double *grad, void *stream);
 
 /* ---------------------------------------------------------------------- */
+/* Evaluation without allocation                                           */
+/* ---------------------------------------------------------------------- */
+
+/* Largest coefficient-row staging of qr_eval_noalloc, in 16-byte entries
+ * (8 MiB per GPU, held from the first qr_ctx_create on that GPU until the
+ * process ends).  A basis of R representatives needs 64 (ceil(R/64) + 2)
+ * entries, so R <= 524,160. */
+#define QR_NOALLOC_ROW_MAX (1 << 19)
+
+/* Upload the basis tables to the context's device now (the set-up call of
+ * qr_eval_noalloc; any other entry point does it on first use).  May
+ * allocate device memory, once per basis and device. */
+qr_status qr_basis_upload(qr_ctx *ctx, const qr_basis *basis);
+
+/* For callers that cannot allocate (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): qr_eval with the same arguments,
+ * outputs and kernels, that calls no allocating routine.  Its only scratch,
+ * the coefficient row in the kernels' layout, is a fixed device array of
+ * QR_NOALLOC_ROW_MAX entries per GPU (QR_ERANGE for a larger basis); the
+ * basis must already be resident on the context's device (qr_basis_upload;
+ * QR_EINVAL otherwise).  Every call on a GPU uses that GPU's one array, and
+ * each call rewrites all of it that it reads: calls that overlap on one GPU
+ * (two host threads, or two streams not ordered with each other) race. */
+qr_status qr_eval_noalloc(qr_ctx *ctx, const qr_basis *basis, const double *alpha_row, int64_t n,
+                          const double *x, double *y, double *grad, void *stream);
+
+/* ---------------------------------------------------------------------- */
 /* Pieces of the step, exposed for testing and for callers that supply    */
 /* their own samples                                                       */
 /* ---------------------------------------------------------------------- */

@@ -406,6 +406,40 @@ static qr_status ensure(qr_ctx *c, Buf &b, size_t bytes, const char *what) {
     return QR_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free evaluation (qr_eval_noalloc): the caller's
+// coefficient row converted to the kernels' layout (double2, traversal order,
+// zero read-ahead chunks).  Each GPU holds its own copy of the array for the
+// life of the process.  Host code never passes `scratch` itself to a kernel
+// (on the host the name is a stand-in, not a device address): the device
+// address is looked up once per device, with that device current, and kept.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double2 scratch[QR_NOALLOC_ROW_MAX];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double2 *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Look up the device address of `scratch` on `dev` (the current device).
+static qr_status scratch_init(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(QR_ENOTSUP, "device %d: scratch table holds %d devices", dev,
+                                                   kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return QR_OK;
+    void *ptr = nullptr;
+    QR_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (!ptr) return fail(QR_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = (double2 *)ptr;
+    return QR_OK;
+}
+
+static double2 *scratch_of(int dev) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return (dev >= 0 && dev < kMaxDevices) ? g_scratch_ptr[dev] : nullptr;
+}
+
 extern "C" qr_status qr_ctx_create(int32_t device, qr_ctx **out) {
     if (!out) return fail(QR_EINVAL, "qr_ctx_create: out is NULL");
     *out = nullptr;
@@ -414,6 +448,8 @@ extern "C" qr_status qr_ctx_create(int32_t device, qr_ctx **out) {
     if (e != hipSuccess || n == 0) return fail(QR_EDEVICE, "qr_ctx_create: no HIP device available");
     if (device < 0 || device >= n) return fail(QR_EINVAL, "qr_ctx_create: device %d of %d", device, n);
     QR_HIP(hipSetDevice(device), "hipSetDevice");
+    qr_status sst = scratch_init(device);
+    if (sst) return sst;
     qr_ctx *c = new (std::nothrow) qr_ctx();
     if (!c) return fail(QR_ENOMEM, "qr_ctx_create: out of host memory");
     c->dev = device;
@@ -769,6 +805,53 @@ extern "C" qr_status qr_eval(qr_ctx *c, const qr_basis *bc, const double *alpha_
     hipStream_t s = (hipStream_t)stream;
     double2 *row = (double2 *)c->row.p;
     const int64_t nf = 2 * b->nrep - 1;
+    QR_HIP(launch_pad(1, b->nrep, b->ld(), row, s), "pad_kernel");
+    QR_HIP(launch_gather(alpha_row, 0, 1, b->nrep, b->ld(), nf, b->d_canon_of_trav, row, s), "gather_kernel");
+    QR_HIP(launch_eval(depth_cap(b->max_nnz), grad != nullptr, make_walk(b->kind, b->level, b->d, b->law), row, x,
+                       n, y, grad, s),
+           "eval_kernel");
+    return QR_OK;
+}
+
+extern "C" qr_status qr_basis_upload(qr_ctx *c, const qr_basis *bc) {
+    qr_basis *b = const_cast<qr_basis *>(bc);
+    if (!c) return fail(QR_EINVAL, "qr_basis_upload: ctx is NULL");
+    qr_status st = check_basis_device(b);
+    if (st) return st;
+    QR_HIP(hipSetDevice(c->dev), "hipSetDevice");
+    return basis_on_device(b, c->dev);
+}
+
+// qr_eval with the coefficient row staged in this device's `scratch` instead
+// of context workspace: no allocation of any kind.  The basis must already be
+// resident on the context's device (qr_basis_upload, or any earlier call with
+// it on this device).  Calls that overlap on one GPU share the scratch.
+extern "C" qr_status qr_eval_noalloc(qr_ctx *c, const qr_basis *bc, const double *alpha_row, int64_t n,
+                                     const double *x, double *y, double *grad, void *stream) {
+    const qr_basis *b = bc;
+    qr_status st = begin(c, stream);
+    if (st) return st;
+    if ((st = check_basis_device(b))) return st;
+    if (n < 0 || n > (int64_t)INT32_MAX * 64) return fail(QR_EINVAL, "qr_eval_noalloc: n out of range");
+    if (b->ld() > (int64_t)QR_NOALLOC_ROW_MAX)
+        return fail(QR_ERANGE, "qr_eval_noalloc: basis of %lld representatives needs %lld scratch entries (limit %d)",
+                    (long long)b->nrep, (long long)b->ld(), QR_NOALLOC_ROW_MAX);
+    int resident;
+    {
+        std::lock_guard<std::mutex> lock(const_cast<qr_basis *>(b)->mu);
+        resident = b->dev;
+    }
+    if (resident != c->dev)
+        return fail(QR_EINVAL, "qr_eval_noalloc: basis is not resident on device %d (call qr_basis_upload first)",
+                    c->dev);
+    if (n == 0) return QR_OK;
+    if (!alpha_row || !x || !y) return fail(QR_EINVAL, "qr_eval_noalloc: NULL argument");
+    double2 *row = scratch_of(c->dev);
+    if (!row) return fail(QR_EDEVICE, "qr_eval_noalloc: scratch of device %d not initialised", c->dev);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t nf = 2 * b->nrep - 1;
+    // the read-ahead chunks must read as zero: cleared by a kernel on every call,
+    // since the previous call may have left another basis's row there
     QR_HIP(launch_pad(1, b->nrep, b->ld(), row, s), "pad_kernel");
     QR_HIP(launch_gather(alpha_row, 0, 1, b->nrep, b->ld(), nf, b->d_canon_of_trav, row, s), "gather_kernel");
     QR_HIP(launch_eval(depth_cap(b->max_nnz), grad != nullptr, make_walk(b->kind, b->level, b->d, b->law), row, x,

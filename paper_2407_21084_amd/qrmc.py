@@ -47,6 +47,7 @@ EXPORTS = ["qr_last_error", "qr_version", "qr_build_basis", "qr_build_basis_law"
            "qr_project", "qr_path_responses", "qr_sample_points", "qr_backward_step_prec",
            "qr_solve_prec", "qr_mlp_init", "qr_mlp_features", "qr_mlp_forward", "qr_mlp_loss_grad",
            "qr_mlp_adam", "qr_solve_learned", "qr_solve_batched",
+           "qr_basis_upload", "qr_eval_noalloc",
            "qr_host_uniform", "qr_host_norm_icdf", "qr_host_philox"]
 
 
@@ -114,6 +115,8 @@ _SIGS = {
     "qr_backward_step": (C.c_int, [_P, C.POINTER(Problem), _P, _I32, _I64, _U64, _P, _P]),
     "qr_solve": (C.c_int, [_P, C.POINTER(Problem), _P, _I64, _U64, _P, _P]),
     "qr_eval": (C.c_int, [_P, _P, _P, _I64, _P, _P, _P, _P]),
+    "qr_basis_upload": (C.c_int, [_P, _P]),
+    "qr_eval_noalloc": (C.c_int, [_P, _P, _P, _I64, _P, _P, _P, _P]),
     "qr_project": (C.c_int, [_P, _P, _I64, _P, _P, _P, _P]),
     "qr_path_responses": (C.c_int, [_P, C.POINTER(Problem), _P, _I32, _I64, _U64, _P, _P, _P, _P]),
     "qr_sample_points": (C.c_int, [_P, _I32, _U64, _U32, _I32, _I64, _I64, _P, _P]),
@@ -319,6 +322,14 @@ class Context:
         n = y.shape[0]
         _check(_lib.qr_eval(self._h, basis.handle, _dptr(alpha_row), n, _dptr(x), _dptr(y),
                             _dptr(grad), _stream_ptr(stream)))
+
+    def basis_upload(self, basis: Basis):
+        _check(_lib.qr_basis_upload(self._h, basis.handle))
+
+    def eval_noalloc(self, basis: Basis, alpha_row, x, y, grad=None, stream=None):
+        n = y.shape[0]
+        _check(_lib.qr_eval_noalloc(self._h, basis.handle, _dptr(alpha_row), n, _dptr(x), _dptr(y),
+                                    _dptr(grad), _stream_ptr(stream)))
 
     def project(self, basis: Basis, x, s, alpha_row, stream=None):
         n = s.shape[0]
