@@ -302,6 +302,39 @@ qr_status qr_sample_points_law(qr_ctx *ctx, int32_t law, int32_t d, uint64_t see
  * reduction stay FP64. */
 typedef enum { QR_PREC_F64 = 0, QR_PREC_BF16 = 1, QR_PREC_F16 = 2 } qr_precision;
 
+/* Kernel of the reduced-precision form (qr_ctx_set_prec_kernel).
+ *  QR_PREC_KERNEL_WALK: the basis traversal of the FP64 path in FP32, each
+ *    basis value rounded to 16 bits and contracted with the coefficients on
+ *    the matrix cores (value and gradient right-hand sides).
+ *  QR_PREC_KERNEL_FACTORED: the coordinates are split in two blocks A | B;
+ *    every representative is (kA, kB), so the expansion at a point is
+ *    Re sum_kA e^{2 pi i kA.uA} sum_kB beta(kA,kB) e^{2 pi i kB.uB} with
+ *    beta = sqrt2 (a_c - i a_s) (beta = alpha_0 for the constant).  Over a tile
+ *    of paths the inner sums are a product of the staircase matrix beta with
+ *    the paths' e^{2 pi i kB.uB} values, run on the matrix cores with 16-bit
+ *    operands and FP32 accumulation; the factors e^{2 pi i m u_l} come from
+ *    per-path tables (phase in FP64, stored FP32).  Drivers that depend on z
+ *    are not supported (QR_ENOTSUP when forced).
+ *  QR_PREC_KERNEL_AUTO (default): the factored kernel where it applies, the
+ *    walk otherwise. */
+typedef enum {
+    QR_PREC_KERNEL_AUTO = 0,
+    QR_PREC_KERNEL_WALK = 1,
+    QR_PREC_KERNEL_FACTORED = 2
+} qr_prec_kernel;
+
+/* Choose the kernel of the reduced-precision entry points of this context
+ * (qr_prec_kernel; QR_EINVAL if unknown). */
+qr_status qr_ctx_set_prec_kernel(qr_ctx *ctx, int32_t kind);
+
+/* The factored layout of a basis (host only; built on first use): the split
+ * dA (the first dA coordinates form block A), the row tiles of 8 A-parts, the
+ * K-blocks of 16 B-parts over all B-parts, and the 16-bit coefficient blocks
+ * per time step (64 lanes x 16 bytes each).  Any output may be NULL;
+ * QR_ENOTSUP if no split qualifies. */
+qr_status qr_basis_factored(const qr_basis *basis, int32_t *split, int32_t *n_row_tiles,
+                            int32_t *n_kblocks, int64_t *n_blocks);
+
 /* qr_backward_step / qr_solve with the expansion evaluation in `precision`.
  * Arguments and outputs as there; QR_PREC_F64 is the plain path. */
 qr_status qr_backward_step_prec(qr_ctx *ctx, const qr_problem *prob, const qr_basis *basis,

@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libqrmc.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["qrmc_kernels.hip", "qrmc_mlp.hip", "qrmc_api.hip"]
+SOURCES = ["qrmc_kernels.hip", "qrmc_factored.hip", "qrmc_mlp.hip", "qrmc_api.hip"]
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wno-unused-result",
          "-Wno-unused-value", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", INCLUDE, "-I", CSRC]

@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "qrmc_factored.h"
 #include "qrmc_kernels.h"
 #include "qrmc_mlp.h"
 
@@ -71,6 +72,14 @@ struct qr_basis {
     std::vector<qr_basis *> subs;
     std::vector<int32_t> ft, inv;
     int32_t *d_ft = nullptr, *d_inv = nullptr;
+    // Factored layout of the reduced-precision form (built on first use; fac
+    // stays null if no split qualifies) and its device copy.
+    bool fac_tried = false;
+    FactorLayout *fac = nullptr;
+    FacDev d_fac{};
+    // projection tasks per template (host counts, device lists)
+    int32_t fac_ntasks[kFacTemplates] = {};
+    FacTask *d_fac_tasks[kFacTemplates] = {};
 };
 
 namespace {
@@ -263,7 +272,18 @@ static void basis_free_device(qr_basis *b) {
         hipFree(b->d_tasks);
         hipFree(b->d_ft);
         hipFree(b->d_inv);
+        hipFree((void *)b->d_fac.tiles);
+        hipFree((void *)b->d_fac.rows);
+        hipFree((void *)b->d_fac.cols);
+        hipFree((void *)b->d_fac.colnnz);
+        hipFree((void *)b->d_fac.ent);
+        for (int t = 0; t < kFacTemplates; ++t) hipFree(b->d_fac_tasks[t]);
         hipSetDevice(cur);
+    }
+    b->d_fac = FacDev{};
+    for (int t = 0; t < kFacTemplates; ++t) {
+        b->d_fac_tasks[t] = nullptr;
+        b->fac_ntasks[t] = 0;
     }
     b->d_canon_of_trav = nullptr;
     b->d_trav = nullptr;
@@ -278,6 +298,7 @@ extern "C" void qr_basis_free(qr_basis *b) {
     if (!b) return;
     for (qr_basis *sb : b->subs) qr_basis_free(sb);
     basis_free_device(b);
+    delete b->fac;
     delete b;
 }
 
@@ -355,6 +376,69 @@ static qr_status basis_on_device(qr_basis *b, int dev) {
     return QR_OK;
 }
 
+// The factored layout of a basis (host), built once; false if none qualifies.
+static bool basis_factored(qr_basis *b) {
+    std::lock_guard<std::mutex> lock(b->mu);
+    if (!b->fac_tried) {
+        b->fac_tried = true;
+        FactorLayout *L = new (std::nothrow) FactorLayout();
+        if (L && build_factor_layout(b->d, b->kind, b->level, b->canon.data(), b->nrep, kFacMaxNkb, L))
+            b->fac = L;
+        else
+            delete L;
+    }
+    return b->fac != nullptr;
+}
+
+template <class T>
+static qr_status upload_vec(T **dst, const std::vector<T> &v) {
+    QR_HIP(hipMalloc((void **)dst, sizeof(T) * std::max<size_t>(v.size(), 1)), "hipMalloc(factored layout)");
+    if (!v.empty())
+        QR_HIP(hipMemcpy(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice), "hipMemcpy(factored layout)");
+    return QR_OK;
+}
+
+// Device copy of the factored layout (the basis must be on `dev` already).
+static qr_status basis_factored_on_device(qr_basis *b) {
+    std::lock_guard<std::mutex> lock(b->mu);
+    if (!b->fac) return fail(QR_ENOTSUP, "basis has no factored layout");
+    if (b->d_fac.tiles) return QR_OK;
+    const FactorLayout &L = *b->fac;
+    FacDev F{};
+    qr_status st;
+    if ((st = upload_vec((FacTile **)&F.tiles, L.tiles))) return st;
+    if ((st = upload_vec((FacCode **)&F.rows, L.rows))) return st;
+    if ((st = upload_vec((FacCode **)&F.cols, L.cols))) return st;
+    if ((st = upload_vec((int32_t **)&F.colnnz, L.colnnz))) return st;
+    if ((st = upload_vec((int32_t **)&F.ent, L.ent))) return st;
+    F.nrt = L.nrt;
+    F.nkb = L.nkb;
+    F.TS = L.TS;
+    F.dA = L.dA;
+    F.d = L.d;
+    F.nblocks = L.nblocks;
+    std::vector<FacTask> tasks[kFacTemplates];
+    build_fac_tasks(L, tasks);
+    for (int t = 0; t < kFacTemplates; ++t) {
+        if ((st = upload_vec(&b->d_fac_tasks[t], tasks[t]))) return st;
+        b->fac_ntasks[t] = (int32_t)tasks[t].size();
+    }
+    b->d_fac = F;
+    return QR_OK;
+}
+
+extern "C" qr_status qr_basis_factored(const qr_basis *bc, int32_t *split, int32_t *n_row_tiles,
+                                       int32_t *n_kblocks, int64_t *n_blocks) {
+    qr_basis *b = const_cast<qr_basis *>(bc);
+    if (!b) return fail(QR_EINVAL, "qr_basis_factored: basis is NULL");
+    if (!basis_factored(b)) return fail(QR_ENOTSUP, "qr_basis_factored: no split of this index set qualifies");
+    if (split) *split = b->fac->dA;
+    if (n_row_tiles) *n_row_tiles = b->fac->nrt;
+    if (n_kblocks) *n_kblocks = b->fac->nkb;
+    if (n_blocks) *n_blocks = b->fac->nblocks;
+    return QR_OK;
+}
+
 // ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------
@@ -376,7 +460,8 @@ struct qr_ctx {
     DevProblem *d_prob = nullptr;
     DevProblem h_prob{};
     bool prob_valid = false;
-    Buf S, u, alpha_int, partial, row, alpha_b, tiles, xstate;
+    Buf S, u, alpha_int, partial, row, alpha_b, tiles, xstate, fcoef, fpartial;
+    int32_t prec_kernel = QR_PREC_KERNEL_AUTO;
     // surrogate network workspace: activations of up to kMlpChunk rows
     Buf mf, mz1, mh1, mz2, mh2, mdz, mdh, my, mdy, mpart, mwork, mcwork;
     // learned solve: cloud state, per-step source term, expansion values,
@@ -466,7 +551,8 @@ extern "C" void qr_ctx_destroy(qr_ctx *c) {
     if (!c) return;
     hipSetDevice(c->dev);
     hipDeviceSynchronize();
-    for (Buf *b : {&c->S, &c->u, &c->alpha_int, &c->partial, &c->row, &c->alpha_b, &c->tiles, &c->xstate, &c->mf,
+    for (Buf *b : {&c->S, &c->u, &c->alpha_int, &c->partial, &c->row, &c->alpha_b, &c->tiles, &c->xstate, &c->fcoef, &c->fpartial,
+                   &c->mf,
                    &c->mz1,
                    &c->mh1, &c->mz2, &c->mh2, &c->mdz, &c->mdh, &c->my, &c->mdy, &c->mpart, &c->mwork,
                    &c->mcwork, &c->lx, &c->lh, &c->ly, &c->lparams, &c->lgrad, &c->lm, &c->lv, &c->ltx, &c->ltt,
@@ -480,6 +566,14 @@ extern "C" void qr_ctx_destroy(qr_ctx *c) {
     }
     for (auto e : c->pool) hipEventDestroy(e);
     delete c;
+}
+
+extern "C" qr_status qr_ctx_set_prec_kernel(qr_ctx *c, int32_t kind) {
+    if (!c) return fail(QR_EINVAL, "qr_ctx_set_prec_kernel: ctx is NULL");
+    if (kind < QR_PREC_KERNEL_AUTO || kind > QR_PREC_KERNEL_FACTORED)
+        return fail(QR_EINVAL, "qr_ctx_set_prec_kernel: unknown kernel choice %d", kind);
+    c->prec_kernel = kind;
+    return QR_OK;
 }
 
 extern "C" qr_status qr_ctx_set_timing(qr_ctx *c, int32_t enable) {
@@ -927,6 +1021,81 @@ static qr_status run_mfma_path(qr_ctx *c, const qr_problem *p, const qr_basis *b
     });
 }
 
+// Whether the reduced-precision form runs the factored kernel for this
+// problem and basis (the context's choice, the driver, the basis's layout and
+// the kernel's LDS); *st is set when the choice cannot be honoured.
+static bool use_factored(qr_ctx *c, const qr_problem *p, qr_basis *b, qr_status *st) {
+    *st = QR_OK;
+    if (c->prec_kernel == QR_PREC_KERNEL_WALK) return false;
+    const bool forced = c->prec_kernel == QR_PREC_KERNEL_FACTORED;
+    const char *why = nullptr;
+    if (p->driver == QR_F_ZRAT)
+        why = "the factored kernel evaluates no gradients (z-dependent driver)";
+    else if (!basis_factored(b))
+        why = "no split of the index set qualifies for the factored kernel";
+    else {
+        const size_t lds = (size_t)fac_waves(b->d, b->fac->TS) * kFacPaths * b->d * b->fac->TS * sizeof(float2);
+        if (lds > 160 * 1024) why = "the factored kernel's tables exceed the LDS of a CU";
+    }
+    if (!why) return true;
+    if (forced) *st = fail(QR_ENOTSUP, "reduced-precision form: %s", why);
+    return false;
+}
+
+static qr_status prepare_fac(qr_ctx *c, const qr_problem *p, qr_basis *b) {
+    qr_status st = basis_factored_on_device(b);
+    if (st) return st;
+    return ensure(c, c->fcoef, sizeof(uint4) * (size_t)p->N * b->fac->nblocks * 64, "factored coefficients");
+}
+
+static qr_status fac_pack_row(qr_ctx *c, const qr_basis *b, int32_t prec, const double *alpha_row, int32_t row,
+                              hipStream_t s) {
+    uint4 *out = (uint4 *)c->fcoef.p + (size_t)row * b->fac->nblocks * 64;
+    return timed(c, 3, s, "fac_pack_kernel",
+                 [&] { return launch_fac_pack(prec, alpha_row, b->d_fac.ent, b->fac->nblocks, out, s); });
+}
+
+static qr_status run_fac_path(qr_ctx *c, const qr_problem *p, const qr_basis *b, int32_t prec, int32_t i,
+                              int64_t M, uint64_t seed, hipStream_t s) {
+    FacPathArgs a{c->d_prob, b->d_fac, i, M, seed, (const uint4 *)c->fcoef.p, (double *)c->S.p,
+                  (double2 *)c->u.p};
+    return timed(c, 0, s, "fac_path_kernel",
+                 [&] { return launch_fac_path(dim_bucket(p->d, p->nbm), prec, a, s); });
+}
+
+// Units (waves) of the factored projection: each takes a share of the paths
+// for one task; about 8192 waves in all, at least 256 paths per unit.
+static int32_t fac_units(const qr_basis *b, int64_t M) {
+    int32_t ntasks = 0;
+    for (int t = 0; t < kFacTemplates; ++t) ntasks += b->fac_ntasks[t];
+    const int waves = fac_waves(b->d, b->fac->TS);
+    int64_t u = 8192 / std::max(1, ntasks);
+    u = std::min<int64_t>(u, (M + 255) / 256);
+    u = std::max<int64_t>(1, std::min<int64_t>(u, 512));
+    return (int32_t)((u + waves - 1) / waves * waves);
+}
+
+static qr_status fac_project(qr_ctx *c, const qr_basis *b, int32_t prec, int64_t M, double *alpha_row,
+                             hipStream_t s) {
+    const int32_t units = fac_units(b, M);
+    int64_t per = (M + units - 1) / units;
+    per = (per + kFacPaths - 1) / kFacPaths * kFacPaths;
+    qr_status st = ensure(c, c->fpartial, sizeof(float) * 256 * (size_t)units * b->fac->nblocks, "factored partials");
+    if (st) return st;
+    float *partial = (float *)c->fpartial.p;
+    for (int t = 0; t < kFacTemplates; ++t) {
+        if (!b->fac_ntasks[t]) continue;
+        st = timed(c, 1, s, "fac_project_kernel", [&] {
+            return launch_fac_project(prec, t, b->d_fac, b->d_fac_tasks[t], b->fac_ntasks[t], (const double2 *)c->u.p,
+                                      (const double *)c->S.p, M, per, units, partial, s);
+        });
+        if (st) return st;
+    }
+    return timed(c, 2, s, "fac_reduce_kernel", [&] {
+        return launch_fac_reduce(partial, units, b->fac->nblocks, b->d_fac.ent, (double)M, alpha_row, s);
+    });
+}
+
 extern "C" qr_status qr_backward_step_prec(qr_ctx *c, const qr_problem *p, const qr_basis *bc, int32_t i,
                                            int64_t M, uint64_t seed, int32_t prec, double *alpha,
                                            void *stream) {
@@ -940,13 +1109,23 @@ extern "C" qr_status qr_backward_step_prec(qr_ctx *c, const qr_problem *p, const
     hipStream_t s = (hipStream_t)stream;
     double2 *ai = (double2 *)c->alpha_int.p;
     const int64_t nf = 2 * b->nrep - 1;
-    st = timed(c, 3, s, "gather_kernel", [&] {
-        return launch_gather(alpha, i + 1, p->N - 1 - i, b->nrep, b->ld(), nf, b->d_canon_of_trav, ai, s);
-    });
+    const bool fac = use_factored(c, p, b, &st);
     if (st) return st;
-    for (int32_t r = i + 1; r < p->N; ++r)
-        if ((st = pack_row(c, p, b, prec, tp, r, s))) return st;
-    if ((st = run_mfma_path(c, p, b, prec, tp, i, M, seed, s))) return st;
+    if (fac) {
+        if ((st = prepare_fac(c, p, b))) return st;
+        for (int32_t r = i + 1; r < p->N; ++r)
+            if ((st = fac_pack_row(c, b, prec, alpha + (int64_t)r * nf, r, s))) return st;
+        if ((st = run_fac_path(c, p, b, prec, i, M, seed, s))) return st;
+        return fac_project(c, b, prec, M, alpha + (int64_t)i * nf, s);
+    } else {
+        st = timed(c, 3, s, "gather_kernel", [&] {
+            return launch_gather(alpha, i + 1, p->N - 1 - i, b->nrep, b->ld(), nf, b->d_canon_of_trav, ai, s);
+        });
+        if (st) return st;
+        for (int32_t r = i + 1; r < p->N; ++r)
+            if ((st = pack_row(c, p, b, prec, tp, r, s))) return st;
+        if ((st = run_mfma_path(c, p, b, prec, tp, i, M, seed, s))) return st;
+    }
     return project_and_reduce(c, b, (double2 *)c->u.p, (double *)c->S.p, M, ai + (int64_t)i * b->ld(),
                               alpha + (int64_t)i * nf, s);
 }
@@ -962,12 +1141,20 @@ extern "C" qr_status qr_solve_prec(qr_ctx *c, const qr_problem *p, const qr_basi
     hipStream_t s = (hipStream_t)stream;
     double2 *ai = (double2 *)c->alpha_int.p;
     const int64_t nf = 2 * b->nrep - 1;
+    const bool fac = use_factored(c, p, b, &st);
+    if (st) return st;
+    if (fac && (st = prepare_fac(c, p, b))) return st;
     for (int32_t i = p->N - 1; i >= 0; --i) {
-        if ((st = run_mfma_path(c, p, b, prec, tp, i, M, seed, s))) return st;
-        if ((st = project_and_reduce(c, b, (double2 *)c->u.p, (double *)c->S.p, M, ai + (int64_t)i * b->ld(),
-                                     alpha + (int64_t)i * nf, s)))
-            return st;
-        if (i > 0 && (st = pack_row(c, p, b, prec, tp, i, s))) return st;
+        st = fac ? run_fac_path(c, p, b, prec, i, M, seed, s) : run_mfma_path(c, p, b, prec, tp, i, M, seed, s);
+        if (st) return st;
+        st = fac ? fac_project(c, b, prec, M, alpha + (int64_t)i * nf, s)
+                 : project_and_reduce(c, b, (double2 *)c->u.p, (double *)c->S.p, M, ai + (int64_t)i * b->ld(),
+                                      alpha + (int64_t)i * nf, s);
+        if (st) return st;
+        if (i > 0) {
+            st = fac ? fac_pack_row(c, b, prec, alpha + (int64_t)i * nf, i, s) : pack_row(c, p, b, prec, tp, i, s);
+            if (st) return st;
+        }
     }
     return QR_OK;
 }

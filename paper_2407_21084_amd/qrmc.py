@@ -36,6 +36,7 @@ STATUS = {0: "QR_OK", -1: "QR_EINVAL", -2: "QR_ENOMEM", -3: "QR_EDEVICE", -4: "Q
 
 PREC_F64, PREC_BF16, PREC_F16 = 0, 1, 2
 PRECISIONS = {"f64": PREC_F64, "bf16": PREC_BF16, "f16": PREC_F16}
+PREC_KERNELS = {"auto": 0, "walk": 1, "factored": 2}
 
 # kernel classes of qr_ctx_kernel_time
 K_PATH, K_PROJECT, K_REDUCE, K_GATHER = 0, 1, 2, 3
@@ -47,7 +48,7 @@ EXPORTS = ["qr_last_error", "qr_version", "qr_build_basis", "qr_build_basis_law"
            "qr_project", "qr_path_responses", "qr_sample_points", "qr_backward_step_prec",
            "qr_solve_prec", "qr_mlp_init", "qr_mlp_features", "qr_mlp_forward", "qr_mlp_loss_grad",
            "qr_mlp_adam", "qr_solve_learned", "qr_solve_batched",
-           "qr_basis_upload", "qr_eval_noalloc",
+           "qr_basis_upload", "qr_eval_noalloc", "qr_ctx_set_prec_kernel", "qr_basis_factored",
            "qr_host_uniform", "qr_host_norm_icdf", "qr_host_philox"]
 
 
@@ -116,6 +117,8 @@ _SIGS = {
     "qr_solve": (C.c_int, [_P, C.POINTER(Problem), _P, _I64, _U64, _P, _P]),
     "qr_eval": (C.c_int, [_P, _P, _P, _I64, _P, _P, _P, _P]),
     "qr_basis_upload": (C.c_int, [_P, _P]),
+    "qr_ctx_set_prec_kernel": (C.c_int, [_P, _I32]),
+    "qr_basis_factored": (C.c_int, [_P, C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I64)]),
     "qr_eval_noalloc": (C.c_int, [_P, _P, _P, _I64, _P, _P, _P, _P]),
     "qr_project": (C.c_int, [_P, _P, _I64, _P, _P, _P, _P]),
     "qr_path_responses": (C.c_int, [_P, C.POINTER(Problem), _P, _I32, _I64, _U64, _P, _P, _P, _P]),
@@ -200,6 +203,16 @@ class Basis:
         out = np.zeros((self.n_reps, self.d), dtype=np.int32)
         _check(_lib.qr_basis_indices(self._h, out.ctypes.data))
         return out
+
+    def factored(self):
+        """The factored layout of the reduced-precision form: (split, row tiles,
+        K-blocks, coefficient blocks per time step), or None if no split qualifies."""
+        sp, rt, kb, nb = _I32(), _I32(), _I32(), _I64()
+        st = _lib.qr_basis_factored(self._h, C.byref(sp), C.byref(rt), C.byref(kb), C.byref(nb))
+        if st == -6:
+            return None
+        _check(st)
+        return sp.value, rt.value, kb.value, nb.value
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -286,6 +299,10 @@ class Context:
 
     def __del__(self):
         self.close()
+
+    def set_prec_kernel(self, kind):
+        k = PREC_KERNELS[kind] if isinstance(kind, str) else int(kind)
+        _check(_lib.qr_ctx_set_prec_kernel(self._h, k))
 
     def set_timing(self, on: bool):
         _check(_lib.qr_ctx_set_timing(self._h, 1 if on else 0))
