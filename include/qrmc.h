@@ -393,18 +393,24 @@ typedef struct {
     double train_loss;      /* mean squared error of the last epoch (normalised targets) */
     int32_t trained;        /* a surrogate was fitted for this time index */
     int32_t used;           /* it replaced the expansion along the paths */
+    double target_mean;     /* the surrogate predicts (ybar_j - target_mean) / target_sd */
+    double target_sd;
 } qr_learn_report;
 
 /* qr_solve (the driver must not depend on z) where, after row j of alpha is
  * known (1 <= j <= N-1), a surrogate of ybar_j is fitted on the method's own
  * pairs and, if it passes the gate, evaluated along the paths instead of
- * the |Gamma|-term expansion; otherwise the expansion is used (and is the
- * result).  report: host [N], entry j for time index j.  The surrogate only
- * changes how ybar_j is evaluated at X_j; the path simulation, projection
- * and alpha reduction are those of qr_solve. */
+ * the |Gamma|-term expansion (ybar_j = target_mean + target_sd * network);
+ * otherwise the expansion is used (and is the result).  report: host [N],
+ * entry j for time index j.  params: device [N][QR_MLP_NPARAMS] receiving
+ * the fitted parameters of every time index (zero where none was fitted),
+ * or NULL.  The surrogate only changes how ybar_j is evaluated at X_j; the
+ * path simulation, projection and alpha reduction are those of qr_solve, and
+ * an iteration i whose later time indices all use the expansion runs
+ * qr_solve's own kernels. */
 qr_status qr_solve_learned(qr_ctx *ctx, const qr_problem *prob, const qr_basis *basis, int64_t M,
                            uint64_t seed, const qr_learn_opts *opts, double *alpha,
-                           qr_learn_report *report, void *stream);
+                           qr_learn_report *report, float *params, void *stream);
 
 /* ---------------------------------------------------------------------- */
 /* Batched form: several PDE instances solved on one shared cloud          */

@@ -75,6 +75,8 @@ def lib():
             "or_project": (None, [C.c_int, C.c_int, I64, P, I64, P, P, P, P]),
             "or_backward_step": (C.c_int, [P, I64, P, I32, I64, U64, P, P, P, P]),
             "or_solve": (C.c_int, [P, I64, P, I64, U64, P]),
+            "or_backward_step_learned": (C.c_int, [P, I64, P, I32, I64, U64, P, P, P, P, P]),
+            "or_mlp_forward": (D, [P, C.c_int, C.c_int, P]),
             "or_sample_points": (None, [C.c_int, C.c_int, U64, U32, I32, I64, I64, P]),
             "or_errors": (None, [P, I64, P, P, U64, I64, P]),
             "or_num_threads": (C.c_int, []),
@@ -244,6 +246,33 @@ def backward_step(w, reps, i, M, seed, alpha, want_x=False, want_s=False):
     if rc:
         raise ValueError("or_backward_step failed")
     return alpha[i].copy(), ab, x, s
+
+
+def mlp_forward(theta, x, law: str = "logistic") -> np.ndarray:
+    """The learned form's surrogate network (bfloat16 operands of its two
+    matrix products, exact sums) at states x [n][d], features 2 F(x_l) - 1."""
+    th = _f64(theta)
+    x = np.atleast_2d(_f64(x))
+    return np.array([lib().or_mlp_forward(_ptr(th), LAWS[law], x.shape[1], _ptr(np.ascontiguousarray(r)))
+                     for r in x])
+
+
+def backward_step_learned(w, reps, i, M, seed, alpha, nets, mu, sd):
+    """or_backward_step with surrogates: nets[j] (a parameter vector, or None
+    for the expansion) with target scaling mu[j], sd[j] replaces ybar_j along
+    the paths.  Fills alpha[i] in place; returns (alpha_row, abs_row)."""
+    p = problem(w)
+    reps = np.ascontiguousarray(reps, dtype=np.int32)
+    assert alpha.dtype == np.float64 and alpha.flags.c_contiguous
+    keep = [None if t is None else _f64(t) for t in nets]
+    ptrs = (C.c_void_p * w.N)(*[None if t is None else t.ctypes.data for t in keep])
+    mu_a, sd_a = _f64(mu), _f64(sd)
+    ab = np.zeros(nfuncs(reps))
+    rc = lib().or_backward_step_learned(C.byref(p), reps.shape[0], _ptr(reps), i, M, seed, _ptr(alpha),
+                                        _ptr(ab), ptrs, _ptr(mu_a), _ptr(sd_a))
+    if rc:
+        raise ValueError("or_backward_step_learned failed")
+    return alpha[i].copy(), ab
 
 
 def damping(w, x) -> float:

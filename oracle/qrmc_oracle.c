@@ -475,10 +475,66 @@ static void or_start_point(const or_problem *P, uint64_t seed, int32_t i, uint64
         x[l] = or_law_icdf(P->nu, or_uniform(seed, 0u, m, (uint32_t)i, (uint32_t)l));
 }
 
+/* ------------------------------------------------------------------------ */
+/* Surrogate network of the learned form (not part of the paper's method):   */
+/* features f_l = 2 F(x_l) - 1 (l < d, 0 up to 16), h1 = silu(W1 f + b1),    */
+/* h2 = silu(W2 h1 + b2), out = w3 . h2 + b3, parameters in the order W1     */
+/* [256][16] (row = output unit), b1, W2 [256][256], b2, w3, b3.  The two    */
+/* matrix products take bfloat16 operands (nearest, ties to even, from the   */
+/* binary32 value): the network's arithmetic as the learned form defines it; */
+/* the sums themselves are exact here (FP64).                                */
+/* ------------------------------------------------------------------------ */
+#define OR_MLP_IN 16
+#define OR_MLP_HID 256
+
+static double or_bf16(double a)
+{
+    float f = (float)a;
+    uint32_t u;
+    memcpy(&u, &f, sizeof u);
+    u = ((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16) << 16;
+    memcpy(&f, &u, sizeof f);
+    return (double)f;
+}
+
+static double or_silu(double z) { return z / (1.0 + exp(-z)); }
+
+double or_mlp_forward(const double *theta, int nu, int d, const double *x)
+{
+    const double *W1 = theta, *b1 = W1 + OR_MLP_HID * OR_MLP_IN, *W2 = b1 + OR_MLP_HID;
+    const double *b2 = W2 + OR_MLP_HID * OR_MLP_HID, *w3 = b2 + OR_MLP_HID, *b3 = w3 + OR_MLP_HID;
+    double f[OR_MLP_IN], h1[OR_MLP_HID], out = b3[0];
+    for (int l = 0; l < OR_MLP_IN; ++l) f[l] = l < d ? or_bf16(2.0 * or_law_cdf(nu, x[l]) - 1.0) : 0.0;
+    for (int o = 0; o < OR_MLP_HID; ++o) {
+        double z = b1[o];
+        for (int l = 0; l < OR_MLP_IN; ++l) z += or_bf16(W1[o * OR_MLP_IN + l]) * f[l];
+        h1[o] = or_bf16(or_silu(z));
+    }
+    for (int o = 0; o < OR_MLP_HID; ++o) {
+        double z = b2[o];
+        for (int k = 0; k < OR_MLP_HID; ++k) z += or_bf16(W2[o * OR_MLP_HID + k]) * h1[k];
+        out += w3[o] * or_silu(z);
+    }
+    return out;
+}
+
 /* Response S_i of eq (Sqi:bar:M) along path m, using the expansions
- * alpha rows i+1..N-1 (row j holds ybar_j; ybar_N = g). */
+ * alpha rows i+1..N-1 (row j holds ybar_j; ybar_N = g) or, for the time
+ * indices j with nets[j] != NULL (learned form), y_j(x) = mu[j] + sd[j] *
+ * network_j(x) in place of the expansion. */
+static double or_path_response_ex(const or_problem *P, int64_t nrep, const int32_t *reps, int32_t i,
+                                  uint64_t seed, uint64_t m, const double *alpha,
+                                  const double *const *nets, const double *mu, const double *sd);
+
 double or_path_response(const or_problem *P, int64_t nrep, const int32_t *reps, int32_t i,
                         uint64_t seed, uint64_t m, const double *alpha)
+{
+    return or_path_response_ex(P, nrep, reps, i, seed, m, alpha, NULL, NULL, NULL);
+}
+
+static double or_path_response_ex(const or_problem *P, int64_t nrep, const int32_t *reps, int32_t i,
+                                  uint64_t seed, uint64_t m, const double *alpha,
+                                  const double *const *nets, const double *mu, const double *sd)
 {
     int d = P->d, nbm = P->nbm, N = P->N;
     int64_t nf = or_nfuncs(nrep);
@@ -499,7 +555,9 @@ double or_path_response(const or_problem *P, int64_t nrep, const int32_t *reps, 
         }
         double y;
         int need_z = (P->driver == 3);
-        if (j + 1 < N) {
+        if (j + 1 < N && nets && nets[j + 1]) {
+            y = mu[j + 1] + sd[j + 1] * or_mlp_forward(nets[j + 1], P->nu, d, xn);
+        } else if (j + 1 < N) {
             y = or_eval_y(P, nrep, reps, alpha + (int64_t)(j + 1) * nf, xn, need_z ? grad : NULL);
         } else {
             y = or_g(P, xn);
@@ -556,6 +614,10 @@ void or_project(int d, int nu, int64_t nrep, const int32_t *reps, int64_t n, con
 /* One backward iteration i of Algorithm 1: fills alpha row i from rows
  * i+1..N-1 with a fresh cloud of M paths.  Optionally returns the start
  * points (row-major [M][d]), the responses S [M] and the scale row A [nf]. */
+int or_backward_step_learned(const or_problem *P, int64_t nrep, const int32_t *reps, int32_t i,
+                             int64_t M, uint64_t seed, double *alpha, double *absum,
+                             const double *const *nets, const double *mu, const double *sd);
+
 int or_backward_step(const or_problem *P, int64_t nrep, const int32_t *reps, int32_t i,
                      int64_t M, uint64_t seed, double *alpha, double *absum, double *x_out,
                      double *s_out)
@@ -573,6 +635,30 @@ int or_backward_step(const or_problem *P, int64_t nrep, const int32_t *reps, int
     or_project(d, P->nu, nrep, reps, M, x, S, alpha + (int64_t)i * nf, absum);
     if (x_out) memcpy(x_out, x, sizeof(double) * (size_t)(M * d));
     if (s_out) memcpy(s_out, S, sizeof(double) * (size_t)M);
+    free(x);
+    free(S);
+    return 0;
+}
+
+/* One backward iteration of the learned form: as or_backward_step, with
+ * the surrogate nets[j] (a parameter vector, or NULL for the expansion) and
+ * its target scaling mu[j], sd[j] in place of the expansion of ybar_j along
+ * the paths (arrays of N entries; entries j <= i are not read). */
+int or_backward_step_learned(const or_problem *P, int64_t nrep, const int32_t *reps, int32_t i,
+                             int64_t M, uint64_t seed, double *alpha, double *absum,
+                             const double *const *nets, const double *mu, const double *sd)
+{
+    if (i < 0 || i >= P->N || M <= 0) return -1;
+    int d = P->d;
+    int64_t nf = or_nfuncs(nrep);
+    double *x = (double *)malloc(sizeof(double) * (size_t)(M * d));
+    double *S = (double *)malloc(sizeof(double) * (size_t)M);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t m = 0; m < M; ++m) {
+        or_start_point(P, seed, i, (uint64_t)m, x + m * d);
+        S[m] = or_path_response_ex(P, nrep, reps, i, seed, (uint64_t)m, alpha, nets, mu, sd);
+    }
+    or_project(d, P->nu, nrep, reps, M, x, S, alpha + (int64_t)i * nf, absum);
     free(x);
     free(S);
     return 0;

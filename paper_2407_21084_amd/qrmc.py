@@ -85,7 +85,7 @@ class LearnOpts(C.Structure):
 class LearnReport(C.Structure):
     """Per-time-index outcome of the learned form (qr_learn_report)."""
     _fields_ = [("heldout_rel_l2", C.c_double), ("train_loss", C.c_double), ("trained", C.c_int32),
-                ("used", C.c_int32)]
+                ("used", C.c_int32), ("target_mean", C.c_double), ("target_sd", C.c_double)]
 
 
 if not os.path.exists(LIB_PATH):
@@ -132,7 +132,7 @@ _SIGS = {
     "qr_mlp_loss_grad": (C.c_int, [_P, _P, _I64, _P, _P, _P, C.POINTER(_D), _P]),
     "qr_mlp_adam": (C.c_int, [_P, _P, _P, _P, _P, _I64, C.c_float, _P]),
     "qr_solve_learned": (C.c_int, [_P, C.POINTER(Problem), _P, _I64, _U64, C.POINTER(LearnOpts), _P,
-                                   C.POINTER(LearnReport), _P]),
+                                   C.POINTER(LearnReport), _P, _P]),
     "qr_solve_batched": (C.c_int, [_P, C.POINTER(Problem), _P, _I32, C.POINTER(Instance), _U64, _P, _P]),
     "qr_host_uniform": (_D, [_U64, _U32, _U64, _U32, _U32]),
     "qr_host_norm_icdf": (_D, [_D]),
@@ -395,11 +395,12 @@ class Context:
                                 _stream_ptr(stream)))
 
     def solve_learned(self, prob: Problem, basis: Basis, M: int, seed: int, alpha, train_points=1 << 18,
-                      heldout_points=1 << 16, epochs=8, batch=8192, lr=1e-3, gate=1e-3, stream=None):
-        """Returns the per-time-index reports as a list of dicts."""
+                      heldout_points=1 << 16, epochs=8, batch=8192, lr=1e-3, gate=1e-3, params=None, stream=None):
+        """Returns the per-time-index reports as a list of dicts; params (float32
+        device [N][MLP_NPARAMS], optional) receives the fitted parameters."""
         o = LearnOpts(train_points, heldout_points, epochs, batch, lr, gate)
         rep = (LearnReport * prob.N)()
         _check(_lib.qr_solve_learned(self._h, C.byref(prob), basis.handle, M, seed, C.byref(o), _dptr(alpha),
-                                     rep, _stream_ptr(stream)))
+                                     rep, _fptr(params), _stream_ptr(stream)))
         return [{"heldout_rel_l2": r.heldout_rel_l2, "train_loss": r.train_loss, "trained": bool(r.trained),
-                 "used": bool(r.used)} for r in rep]
+                 "used": bool(r.used), "target_mean": r.target_mean, "target_sd": r.target_sd} for r in rep]

@@ -91,3 +91,54 @@ def test_bf16_network_tends_to_the_exact_one():
     yb, _ = mlp.forward_bf16(th, f)
     assert np.linalg.norm(yb - y) <= 2e-2 * np.linalg.norm(y)
     assert np.linalg.norm(yb - y) > 0
+
+
+# ---------------------------------------------------------------------------
+# the oracle's learned step (oracle/qrmc_oracle.c: or_mlp_forward,
+# or_backward_step_learned)
+# ---------------------------------------------------------------------------
+
+def test_c_network_equals_the_numpy_definition():
+    """The C oracle's network (bfloat16 operands, exact sums) equals the numpy
+    definition with the same rounding points, at states x of d <= 16
+    coordinates (features 2 F(x_l) - 1, zero-padded), and is O(2^-8) from the
+    exact network."""
+    import oracle as O
+    rng = np.random.default_rng(8)
+    th = _theta(9)
+    for d in (1, 3, 16):
+        x = rng.standard_normal((40, d)) * 2.0
+        got = O.mlp_forward(th, x)
+        ref, _ = mlp.forward_bf16(th, mlp.features(x))
+        exact, _ = mlp.forward(th, mlp.features(x))
+        assert np.allclose(got, ref, rtol=1e-13, atol=1e-15)
+        assert np.linalg.norm(got - exact) <= 2e-2 * np.linalg.norm(exact)
+
+
+def test_learned_step_with_a_constant_network_is_a_constant_expansion():
+    """A network with zero weights outputs b3, so y_j = mu_j + sd_j b3 at
+    every point: the learned step must equal the plain step whose row j is
+    the constant mu_j + sd_j b3 (alpha_0 alone).  Without networks it is the
+    plain step itself."""
+    import oracle as O
+    import workloads as W
+    w = W.D2_TENSOR4.with_(M=600, N=4)
+    reps = O.reps_for(w)
+    nf = O.nfuncs(reps)
+    alpha = W.synthetic_alpha(nf, w.N, seed=3, scale=0.2, decay=0.7)
+    const = mlp.unpack(np.zeros(mlp.NPARAMS))
+    const["b3"][0] = 0.35
+    net = mlp.pack(const)
+    mu, sd = [0.0, 0.0, -0.2, 0.0], [1.0, 1.0, 1.5, 1.0]
+    for i in (1, 0):
+        plain, _ = O.backward_step_learned(w, reps, i, w.M, w.seed, alpha.copy(), [None] * w.N, mu, sd)
+        ref, _, _, _ = O.backward_step(w, reps, i, w.M, w.seed, alpha.copy())
+        assert np.array_equal(plain, ref)
+        nets = [None, None, net, None]
+        got, _ = O.backward_step_learned(w, reps, i, w.M, w.seed, alpha.copy(), nets, mu, sd)
+        a2 = alpha.copy()
+        a2[2] = 0.0
+        a2[2, 0] = -0.2 + 1.5 * 0.35
+        want, _, _, _ = O.backward_step(w, reps, i, w.M, w.seed, a2)
+        assert np.allclose(got, want, rtol=1e-14, atol=1e-15)
+        assert not np.allclose(got, ref, rtol=1e-6)
