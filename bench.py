@@ -1,20 +1,26 @@
 #!/usr/bin/env python3
-"""Benchmark: basis-evals/s of the plain FP64 QRMC solve on one MI355X.
+"""Benchmark: full-solve time and basis-evals/s of the QRMC solve on one MI355X,
+the chosen (reduced-precision, factored) form against the plain FP64 path at
+equal L2 error.
 
 Workload (default): d=6, N=20, sigma=0.4 I, b(x)=-0.1 x, standard-logistic
 sampling law, hyperbolic cross prod max(1,|k_l|) <= 16 over Z^6
 (169,209 basis functions), M=2^20 paths per step, Allen-Cahn driver
 y - y^3 + h with u(t,x) = exp(-(T-t)) cos(sum x)/2, T=1, clamp 1, seed 0.
 
-A step is one full backward induction (Algorithm 1, i = N-1..0).  One solve
-evaluates M |Gamma| N(N+1)/2 basis functions (expansions along the paths plus
-the projections); value = that count times the timed solves over the timed
-wall time, with everything resident on the GPU.  The dominant kernel (path
-simulation + expansion evaluation) is timed with HIP events recorded on its
-launch stream; its roofline is the FP64 vector ALU (5 flops per basis
-function: one complex multiply per representative shared by a cos/sin pair,
-and two FMAs).  The CPU oracle is timed on a bounded sample of the same
-workload on the host cores.
+A step is one full backward induction (Algorithm 1, i = N-1..0) in the
+chosen form (default bfloat16: the expansion along the paths and the
+projection as products of the staircase coefficient matrix with the paths'
+basis factors on the matrix cores).  One solve evaluates M |Gamma| N(N+1)/2
+basis functions (expansions along the paths plus the projections); value =
+that count times the timed solves over the timed wall time, with everything
+resident on the GPU.  The plain FP64 solve of the same workload is timed in
+the same run; both relative L2 errors at t_0 (closed-form u on 2^16
+stream-1 points) are reported with the speed-up, and the FP64 error is split
+into the projection floor of the index set and the Monte-Carlo variance of
+the coefficients (Lemma 3.1).  The dominant kernel is timed with HIP events
+recorded on its launch stream.  The CPU oracle is timed on a bounded sample
+of the same workload on the host cores.
 """
 from __future__ import annotations
 
@@ -74,8 +80,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="d6-hcmax16-allen-cahn")
     ap.add_argument("--M", type=int, default=None, help="override paths per step")
-    ap.add_argument("--precision", default="f64", choices=["f64", "bf16", "f16"],
-                    help="arithmetic of the expansion evaluation along the paths")
+    ap.add_argument("--precision", default="bf16", choices=["f64", "bf16", "f16"],
+                    help="arithmetic of the chosen form (f64: the plain path alone)")
+    ap.add_argument("--prec-kernel", default="auto", choices=["auto", "walk", "factored"],
+                    help="kernel of the reduced-precision form")
     ap.add_argument("--law", default="logistic", choices=["logistic", "student2", "cauchy"],
                     help="sampling law nu of the basis and of the start draws")
     ap.add_argument("--damping", type=float, default=0.0,
@@ -107,9 +115,69 @@ def cpu_baseline(w, target_s: float):
     O.backward_step(w, reps, i, M2, w.seed, alpha.copy())
     dt = time.perf_counter() - t0
     evals = M2 * nf * (w.N - i)
-    return {"value": evals / dt, "unit": "basis-evals/s", "cores": O.num_threads(), "kind": "oracle",
+    rate = evals / dt
+    full = w.M * nf * w.N * (w.N + 1) / 2
+    return {"value": rate, "unit": "basis-evals/s", "cores": O.num_threads(), "kind": "oracle",
             "sample": f"one backward step i=N-2 with M'={M2} paths (full |Gamma|={nf}); "
-                      f"{dt:.1f} s", "seconds": dt}
+                      f"{dt:.1f} s", "seconds": dt, "cpu_model": cpu_model(),
+            "full_solve_s_extrapolated": full / rate,
+            "extrapolation": "linear in M |Gamma| N(N+1)/2 basis-evals at the sampled rate"}
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+# ---------------------------------------------------------------------------
+# Error split of the FP64 solve at t_0 (Lemma 3.1 / Thm 3.2): the
+# projection floor of the index set, ||u - P_Gamma u||^2 / ||u||^2 for the
+# closed-form u(0, .), and the Monte-Carlo variance of the coefficients,
+# sum_k Var(alpha_0,k) / ||u||^2.  With the orthonormal real basis,
+# sum_k phi_k(x)^2 = |Gamma| at every x, so sum_k E[(S phi_k)^2] = |Gamma| E[S^2]
+# and the variance sum is estimated by (|Gamma| mean(S^2) - ||alpha_0||^2) / M.
+# ---------------------------------------------------------------------------
+def _logistic_1d(a, mmax):
+    """c_m(a) = E[e^{i a X} e^{-2 pi i m F(X)}] for standard logistic X,
+    m = -mmax..mmax, by the trapezoid rule on [-60, 60]."""
+    import numpy as np
+    x = np.linspace(-60.0, 60.0, 240001)
+    F = 0.5 * (1.0 + np.tanh(0.5 * x))
+    dens = F * (1.0 - F)
+    m = np.arange(-mmax, mmax + 1)[:, None]
+    vals = np.exp(1j * a * x)[None, :] * np.exp(-2j * np.pi * m * F[None, :]) * dens[None, :]
+    return np.trapezoid(vals, x, axis=1)
+
+
+def projection_floor(w, reps) -> float:
+    """Relative squared L2(nu) distance of u(0, .) to the span of the basis
+    (standard logistic law, manufactured solution A e^{-c T} cos(w.x + p))."""
+    import numpy as np
+    A = w.sol_A * math.exp(-w.sol_c * w.T)
+    full = np.concatenate([reps, -reps[1:]], axis=0)
+    mmax = int(np.abs(full).max())
+    uhat = np.zeros(full.shape[0], dtype=complex)
+    for sgn in (1.0, -1.0):
+        prod = np.ones(full.shape[0], dtype=complex)
+        cache = {}
+        for l in range(w.d):
+            a = sgn * w.sol_w[l]
+            if a not in cache:
+                cache[a] = _logistic_1d(a, mmax)
+            prod *= cache[a][full[:, l] + mmax]
+        uhat += 0.5 * A * np.exp(1j * sgn * w.sol_p) * prod
+    proj2 = float(np.sum(np.abs(uhat) ** 2))
+    phi2 = 1.0
+    for l in range(w.d):
+        t = 2.0 * w.sol_w[l]
+        phi2 *= 1.0 if t == 0.0 else math.pi * t / math.sinh(math.pi * t)
+    u2 = 0.5 * A * A * (1.0 + math.cos(2.0 * w.sol_p) * phi2)
+    return max(0.0, 1.0 - proj2 / u2), u2
 
 
 BATCHED = "batched-256"
@@ -304,10 +372,13 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     ctx = Q.Context(0)
+    ctx.set_prec_kernel(args.prec_kernel)
     basis = Q.Basis(w.d, w.set_kind, w.level, law=w.law)
     prob = Q.problem_from(w)
     alpha = torch.zeros((w.N, basis.n_funcs), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
+    factored = args.precision != "f64" and args.prec_kernel != "walk" and w.driver != "zrat" \
+        and basis.factored() is not None
 
     if args.copy_calibration_mib:
         src = torch.empty(args.copy_calibration_mib << 17, dtype=torch.float64, device=dev)
@@ -344,20 +415,30 @@ def main():
     path_ms, path_n = ctx.kernel_time(Q.K_PATH)
     proj_ms, proj_n = ctx.kernel_time(Q.K_PROJECT)
     red_ms, red_n = ctx.kernel_time(Q.K_REDUCE)
-    # algorithmic flops of the path kernel: expansions at X_{j+1}, j+1 < N.
-    # Per basis function: half a complex multiply of the walk (3 flops) and
-    # the contraction (2 flops per right-hand side: ybar, and with a
-    # z-dependent driver the d gradient components).
+    # algorithmic work of the dominant kernel (expansions at X_{j+1}, j+1 < N)
     grad = w.driver == "zrat"
     rhs = 1 + (w.d if grad else 0)
+    n_reps = (basis.n_funcs + 1) // 2
     path_evals = w.M * basis.n_funcs * w.N * (w.N - 1) / 2 * args.steps
     path_s = path_ms * 1e-3
+    mfma = None
     if args.precision == "f64":
-        flops_per_eval, peak, kernel = 3.0 + 2.0 * rhs, FP64_VECTOR_PEAK_TFLOPS, "path_kernel"
-        mfma = None
+        # half a complex multiply of the walk (3 flops) and the contraction
+        # (2 flops per right-hand side) per basis function
+        flops_per_eval, peak, kernel, bound = 3.0 + 2.0 * rhs, FP64_VECTOR_PEAK_TFLOPS, "path_kernel", "alu"
+    elif factored:
+        # one complex multiply-add per representative and path on the matrix
+        # cores (8 real flops, i.e. 4 per basis function); the padding of the
+        # staircase blocks is not counted
+        flops_per_eval, peak, kernel, bound = 4.0, MFMA_16BIT_PEAK_TFLOPS, "fac_path_kernel", "mfma"
+        split, nrt, nkb, nblocks = basis.factored()
+        mfma = {"layout": {"split": split, "row_tiles": nrt, "k_blocks": nkb, "blocks_per_step": nblocks,
+                           "padding": nblocks * 128 / n_reps},
+                "issued_tflops": w.M * nblocks * 8192 * 2 * w.N * (w.N - 1) / 2 * args.steps / 16 / path_s / 1e12
+                if path_s > 0 else 0.0}
     else:
         # walk on the FP32 vector ALU; contraction on the matrix cores
-        flops_per_eval, peak, kernel = 3.0, FP32_VECTOR_PEAK_TFLOPS, "mfma_path_kernel"
+        flops_per_eval, peak, kernel, bound = 3.0, FP32_VECTOR_PEAK_TFLOPS, "mfma_path_kernel", "alu"
         T = 1 if not grad else max((w.d + 4) // 4, 2 if max(w.d, w.nbm) <= 8 else 3)
         issued = path_evals * 2.0 * 4 * T / path_s / 1e12 if path_s > 0 else 0.0
         mfma = {"issued_tflops": issued, "useful_tflops": issued * rhs / (4 * T),
@@ -370,20 +451,25 @@ def main():
     n_test = 1 << 16
     xt = torch.empty((w.d, n_test), dtype=torch.float64, device=dev)
     ctx.sample_points(w.d, w.seed, 1, 0, n_test, xt, stream=stream, law=w.law)
-    yt = torch.empty(n_test, dtype=torch.float64, device=dev)
-    ctx.eval(basis, alpha[0].contiguous(), xt, yt, stream=stream)
-    torch.cuda.synchronize()
     wv = torch.tensor(w.sol_w, dtype=torch.float64, device=dev)
     u0 = w.sol_A * math.exp(-w.sol_c * w.T) * torch.cos(wv @ xt + w.sol_p)
-    if w.damping_q:
-        # the coefficients describe y / (1+|x|^2)^{q/2}
-        yt = yt * (1.0 + (xt * xt).sum(dim=0)) ** (0.5 * w.damping_q)
-    rel_l2 = float(torch.linalg.norm(yt - u0) / torch.linalg.norm(u0))
 
+    def rel_l2_of(a):
+        yt = torch.empty(n_test, dtype=torch.float64, device=dev)
+        ctx.eval(basis, a[0].contiguous(), xt, yt, stream=stream)
+        torch.cuda.synchronize()
+        if w.damping_q:
+            # the coefficients describe y / (1+|x|^2)^{q/2}
+            yt = yt * (1.0 + (xt * xt).sum(dim=0)) ** (0.5 * w.damping_q)
+        return float(torch.linalg.norm(yt - u0) / torch.linalg.norm(u0))
+
+    rel_l2 = rel_l2_of(alpha)
     traffic, traffic_detail = counted_traffic(w.name, args.precision, w.M)
+    form = "plain FP64" if args.precision == "f64" else \
+        f"{args.precision} {'factored' if factored else 'walk'} form"
     line = {
         "metric": "basis-evals/s (plain FP64 full solve)" if args.precision == "f64"
-                  else f"basis-evals/s ({args.precision} expansion evaluation, full solve)",
+                  else f"basis-evals/s & full-solve time at fixed L2 error: {form} vs plain FP64",
         "value": value,
         "unit": "basis-evals/s",
         "n_gpus": 1,
@@ -395,13 +481,13 @@ def main():
         "vs_baseline": None,
         "dtype": args.precision,
         "data": "synthetic",
-        "config": {"workload": w.name, "d": w.d, "N": w.N, "set": f"{w.set_kind}({w.level})",
+        "config": {"workload": w.name, "form": form, "d": w.d, "N": w.N, "set": f"{w.set_kind}({w.level})",
                    "n_funcs": basis.n_funcs, "M": w.M, "evals_per_solve": evals_per_solve},
         "full_solve_s": elapsed / args.steps,
         "rel_l2_t0": rel_l2,
         "kernels_ms_per_solve": {"path": path_ms / args.steps, "project": proj_ms / args.steps,
                                  "reduce": red_ms / args.steps},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
+        "roofline": {"bound": bound, "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": traffic, "kernel": kernel,
                      "flops_per_eval": flops_per_eval,
@@ -413,9 +499,11 @@ def main():
         line["roofline"]["traffic_detail"] = traffic_detail
     if mfma:
         line["mfma"] = mfma
+    a64 = alpha
     if args.precision != "f64":
-        # the plain FP64 solve of the same workload: its time, its error at
-        # t_0, and the reduced-precision coefficients' error per time step
+        # the plain FP64 solve of the same workload: its time and its error at
+        # t_0 (the target of "equal L2 error"), and the reduced-precision
+        # coefficients' error per time step
         a64 = torch.zeros_like(alpha)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -423,13 +511,33 @@ def main():
         torch.cuda.synchronize()
         t64 = time.perf_counter() - t0
         print(f"[bench] plain FP64 solve {t64:.1f} s", file=sys.stderr, flush=True)
-        y64 = torch.empty(n_test, dtype=torch.float64, device=dev)
-        ctx.eval(basis, a64[0].contiguous(), xt, y64, stream=stream)
-        torch.cuda.synchronize()
+        rel64 = rel_l2_of(a64)
         rows = (torch.linalg.norm(alpha - a64, dim=1) / torch.linalg.norm(a64, dim=1).clamp_min(1e-300)).tolist()
-        line["vs_f64"] = {"f64_solve_s": t64, "speedup": t64 / (elapsed / args.steps),
-                          "rel_l2_t0_f64": float(torch.linalg.norm(y64 - u0) / torch.linalg.norm(u0)),
-                          "alpha_rel_err_per_step": rows}
+        line["vs_plain_fp64"] = {
+            "fp64_full_solve_s": t64, "fp64_basis_evals_per_s": evals_per_solve / t64,
+            "speedup_at_equal_error": t64 / (elapsed / args.steps),
+            "rel_l2_t0": {args.precision: rel_l2, "f64": rel64},
+            "equal_error": rel_l2 <= 1.02 * rel64,
+            "alpha_rel_err_per_step": rows}
+    if w.law == "logistic" and not w.damping_q:
+        # error split of the FP64 solve at t_0: projection floor + Monte-Carlo variance
+        floor, u2 = projection_floor(w, basis.indices())
+        s0 = torch.empty(w.M, dtype=torch.float64, device=dev)
+        ctx.path_responses(prob, basis, 0, w.M, w.seed, a64, s0, stream=stream)
+        torch.cuda.synchronize()
+        ms2 = float((s0 * s0).mean())
+        a2 = float((a64[0] * a64[0]).sum())
+        var_rel = max(0.0, (basis.n_funcs * ms2 - a2) / w.M) / u2
+        meas = line["vs_plain_fp64"]["rel_l2_t0"]["f64"] if "vs_plain_fp64" in line else rel_l2
+        line["error_split_f64"] = {
+            "rel_l2_t0_squared": meas * meas,
+            "projection_floor": floor,
+            "mc_variance": var_rel,
+            "remainder": meas * meas - floor - var_rel,
+            "note": "relative squared L2(nu) errors at t_0: ||u - P_Gamma u||^2/||u||^2 by 1-D quadrature of the "
+                    "closed form, and sum_k Var(alpha_0k)/||u||^2 = (|Gamma| mean(S^2) - ||alpha_0||^2)/(M ||u||^2) "
+                    "from the responses of step 0; the remainder holds the errors carried from later steps and "
+                    "the time discretisation"}
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

@@ -75,7 +75,7 @@ typedef enum {
     QR_ENOMEM = -2,   /* device or host allocation failed                 */
     QR_EDEVICE = -3,  /* HIP runtime or launch error                      */
     QR_ERANGE = -4,   /* size overflow (index set, M, workspace)          */
-    QR_ENUMERIC = -5, /* non-finite coefficient produced                  */
+    QR_ENUMERIC = -5, /* non-finite coefficient produced (qr_ctx_numeric_status) */
     QR_ENOTSUP = -6   /* valid request outside what this library supports */
 } qr_status;
 
@@ -198,6 +198,18 @@ void qr_ctx_destroy(qr_ctx *ctx);
 /* Enable (1) or disable (0) per-kernel timing with HIP events recorded on
  * the launch stream around every kernel the library enqueues. */
 qr_status qr_ctx_set_timing(qr_ctx *ctx, int32_t enable);
+
+/* Non-finite coefficients.  Every entry point that writes rows of alpha
+ * records on the device the largest time index i whose row came out with a
+ * NaN or infinite coefficient (for instance a driver that overflows along the
+ * paths).  The full solves (qr_solve, qr_solve_prec, qr_solve_learned,
+ * qr_solve_batched) clear the record when they start and, when their work
+ * has completed (they synchronise the stream at the end), return
+ * QR_ENUMERIC naming that time index.  qr_backward_step and
+ * qr_backward_step_prec stay asynchronous: this call synchronises the
+ * context's last stream, stores the recorded index in *step (-1 for none; step
+ * may be NULL), clears it and returns QR_ENUMERIC if one was recorded. */
+qr_status qr_ctx_numeric_status(qr_ctx *ctx, int32_t *step);
 
 /* Accumulated timings (ms) and launch counts since the last reset, for
  * kernel class `which`: 0 = path simulation + expansion evaluation

@@ -468,6 +468,9 @@ struct qr_ctx {
     // surrogate parameters per time index, Adam state, training pairs
     Buf lx, lh, ly, lparams, lgrad, lm, lv, ltx, ltt, ltf, lff, lhx, lht, lhf, lhy;
     DevBatch *d_batch = nullptr;
+    // largest time index whose coefficients came out non-finite since the
+    // last read (-1: none), raised by the reduction kernels
+    int32_t *d_bad = nullptr;
     bool timing = false;
     std::vector<Timed> pending;
     std::vector<hipEvent_t> pool;
@@ -543,6 +546,15 @@ extern "C" qr_status qr_ctx_create(int32_t device, qr_ctx **out) {
         delete c;
         return hipfail(e, "hipMalloc(problem)");
     }
+    e = hipMalloc(&c->d_bad, sizeof(int32_t));
+    if (e == hipSuccess) e = launch_set_flag(c->d_bad, -1, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        hipFree(c->d_prob);
+        if (c->d_bad) hipFree(c->d_bad);
+        delete c;
+        return hipfail(e, "hipMalloc(numeric flag)");
+    }
     *out = c;
     return QR_OK;
 }
@@ -559,6 +571,7 @@ extern "C" void qr_ctx_destroy(qr_ctx *c) {
                    &c->ltf, &c->lff, &c->lhx, &c->lht, &c->lhf, &c->lhy})
         if (b->p) hipFree(b->p);
     hipFree(c->d_prob);
+    hipFree(c->d_bad);
     if (c->d_batch) hipFree(c->d_batch);
     for (auto &t : c->pending) {
         hipEventDestroy(t.a);
@@ -737,6 +750,29 @@ static qr_status begin(qr_ctx *c, void *stream) {
     return QR_OK;
 }
 
+// The numeric flag: cleared on the stream, read after the stream completes.
+static qr_status numeric_clear(qr_ctx *c, hipStream_t s) {
+    QR_HIP(launch_set_flag(c->d_bad, -1, s), "set_flag_kernel");
+    return QR_OK;
+}
+
+static qr_status numeric_read(qr_ctx *c, hipStream_t s, int32_t *step) {
+    int32_t h = -1;
+    QR_HIP(hipMemcpyAsync(&h, c->d_bad, sizeof h, hipMemcpyDeviceToHost, s), "hipMemcpyAsync(numeric flag)");
+    QR_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (step) *step = h;
+    if (h < 0) return QR_OK;
+    qr_status st = numeric_clear(c, s);
+    if (st) return st;
+    return fail(QR_ENUMERIC, "non-finite coefficient at time index %d (latest in the backward order)", h);
+}
+
+extern "C" qr_status qr_ctx_numeric_status(qr_ctx *c, int32_t *step) {
+    if (!c) return fail(QR_EINVAL, "qr_ctx_numeric_status: ctx is NULL");
+    QR_HIP(hipSetDevice(c->dev), "hipSetDevice");
+    return numeric_read(c, c->last, step);
+}
+
 // ---------------------------------------------------------------------------
 // step pieces
 // ---------------------------------------------------------------------------
@@ -753,8 +789,10 @@ static void split_plan(const qr_basis *b, int64_t M, int32_t *nsplit, int64_t *p
     *nsplit = (int32_t)((M + per - 1) / per);
 }
 
+// step: the time index of the row (its non-finite coefficients are
+// recorded), or -1 for a projection that is not a step of the method
 static qr_status project_and_reduce(qr_ctx *c, const qr_basis *b, const double2 *u, const double *S,
-                                    int64_t M, double2 *alpha_int_row, double *alpha_row,
+                                    int64_t M, double2 *alpha_int_row, double *alpha_row, int32_t step,
                                     hipStream_t s) {
     int32_t nsplit;
     int64_t pps;
@@ -771,7 +809,7 @@ static qr_status project_and_reduce(qr_ctx *c, const qr_basis *b, const double2 
     if (st) return st;
     return timed(c, 2, s, "reduce_kernel", [&] {
         return launch_reduce(partial, nsplit, b->nrep, (double)M, alpha_int_row, alpha_row,
-                             b->d_canon_of_trav, s);
+                             b->d_canon_of_trav, step >= 0 ? c->d_bad : nullptr, step, s);
     });
 }
 
@@ -828,7 +866,7 @@ extern "C" qr_status qr_backward_step(qr_ctx *c, const qr_problem *p, const qr_b
     double *S = (double *)c->S.p;
     double2 *u = (double2 *)c->u.p;
     if ((st = run_path(c, p, b, i, M, seed, ai, S, u, nullptr, s))) return st;
-    return project_and_reduce(c, b, u, S, M, ai + (int64_t)i * b->ld(), alpha + (int64_t)i * nf, s);
+    return project_and_reduce(c, b, u, S, M, ai + (int64_t)i * b->ld(), alpha + (int64_t)i * nf, i, s);
 }
 
 extern "C" qr_status qr_solve(qr_ctx *c, const qr_problem *p, const qr_basis *bc, int64_t M,
@@ -842,12 +880,13 @@ extern "C" qr_status qr_solve(qr_ctx *c, const qr_problem *p, const qr_basis *bc
     const int64_t nf = 2 * b->nrep - 1;
     double *S = (double *)c->S.p;
     double2 *u = (double2 *)c->u.p;
+    if ((st = numeric_clear(c, s))) return st;
     for (int32_t i = p->N - 1; i >= 0; --i) {
         if ((st = run_path(c, p, b, i, M, seed, ai, S, u, nullptr, s))) return st;
-        if ((st = project_and_reduce(c, b, u, S, M, ai + (int64_t)i * b->ld(), alpha + (int64_t)i * nf, s)))
+        if ((st = project_and_reduce(c, b, u, S, M, ai + (int64_t)i * b->ld(), alpha + (int64_t)i * nf, i, s)))
             return st;
     }
-    return QR_OK;
+    return numeric_read(c, s, nullptr);
 }
 
 extern "C" qr_status qr_path_responses(qr_ctx *c, const qr_problem *p, const qr_basis *bc, int32_t i,
@@ -882,7 +921,7 @@ extern "C" qr_status qr_project(qr_ctx *c, const qr_basis *bc, int64_t n, const 
     hipStream_t s = (hipStream_t)stream;
     double2 *u = (double2 *)c->u.p;
     QR_HIP(launch_x_to_e(b->law, b->d, x, n, u, s), "x_to_e_kernel");
-    return project_and_reduce(c, b, u, s_in, n, (double2 *)c->row.p, alpha_row, s);
+    return project_and_reduce(c, b, u, s_in, n, (double2 *)c->row.p, alpha_row, -1, s);
 }
 
 extern "C" qr_status qr_eval(qr_ctx *c, const qr_basis *bc, const double *alpha_row, int64_t n,
@@ -1034,7 +1073,8 @@ static bool use_factored(qr_ctx *c, const qr_problem *p, qr_basis *b, qr_status 
     else if (!basis_factored(b))
         why = "no split of the index set qualifies for the factored kernel";
     else {
-        const size_t lds = (size_t)fac_waves(b->d, b->fac->TS) * kFacPaths * b->d * b->fac->TS * sizeof(float2);
+        const size_t lds = (size_t)fac_waves(b->d, b->fac->TS) * kFacPaths * fac_stride(b->d, b->fac->TS) *
+                           sizeof(float2);
         if (lds > 160 * 1024) why = "the factored kernel's tables exceed the LDS of a CU";
     }
     if (!why) return true;
@@ -1076,7 +1116,7 @@ static int32_t fac_units(const qr_basis *b, int64_t M) {
 }
 
 static qr_status fac_project(qr_ctx *c, const qr_basis *b, int32_t prec, int64_t M, double *alpha_row,
-                             hipStream_t s) {
+                             int32_t step, hipStream_t s) {
     const int32_t units = fac_units(b, M);
     int64_t per = (M + units - 1) / units;
     per = (per + kFacPaths - 1) / kFacPaths * kFacPaths;
@@ -1092,7 +1132,8 @@ static qr_status fac_project(qr_ctx *c, const qr_basis *b, int32_t prec, int64_t
         if (st) return st;
     }
     return timed(c, 2, s, "fac_reduce_kernel", [&] {
-        return launch_fac_reduce(partial, units, b->fac->nblocks, b->d_fac.ent, (double)M, alpha_row, s);
+        return launch_fac_reduce(partial, units, b->fac->nblocks, b->d_fac.ent, (double)M, alpha_row, c->d_bad, step,
+                                 s);
     });
 }
 
@@ -1116,7 +1157,7 @@ extern "C" qr_status qr_backward_step_prec(qr_ctx *c, const qr_problem *p, const
         for (int32_t r = i + 1; r < p->N; ++r)
             if ((st = fac_pack_row(c, b, prec, alpha + (int64_t)r * nf, r, s))) return st;
         if ((st = run_fac_path(c, p, b, prec, i, M, seed, s))) return st;
-        return fac_project(c, b, prec, M, alpha + (int64_t)i * nf, s);
+        return fac_project(c, b, prec, M, alpha + (int64_t)i * nf, i, s);
     } else {
         st = timed(c, 3, s, "gather_kernel", [&] {
             return launch_gather(alpha, i + 1, p->N - 1 - i, b->nrep, b->ld(), nf, b->d_canon_of_trav, ai, s);
@@ -1127,7 +1168,7 @@ extern "C" qr_status qr_backward_step_prec(qr_ctx *c, const qr_problem *p, const
         if ((st = run_mfma_path(c, p, b, prec, tp, i, M, seed, s))) return st;
     }
     return project_and_reduce(c, b, (double2 *)c->u.p, (double *)c->S.p, M, ai + (int64_t)i * b->ld(),
-                              alpha + (int64_t)i * nf, s);
+                              alpha + (int64_t)i * nf, i, s);
 }
 
 extern "C" qr_status qr_solve_prec(qr_ctx *c, const qr_problem *p, const qr_basis *bc, int64_t M,
@@ -1144,19 +1185,20 @@ extern "C" qr_status qr_solve_prec(qr_ctx *c, const qr_problem *p, const qr_basi
     const bool fac = use_factored(c, p, b, &st);
     if (st) return st;
     if (fac && (st = prepare_fac(c, p, b))) return st;
+    if ((st = numeric_clear(c, s))) return st;
     for (int32_t i = p->N - 1; i >= 0; --i) {
         st = fac ? run_fac_path(c, p, b, prec, i, M, seed, s) : run_mfma_path(c, p, b, prec, tp, i, M, seed, s);
         if (st) return st;
-        st = fac ? fac_project(c, b, prec, M, alpha + (int64_t)i * nf, s)
+        st = fac ? fac_project(c, b, prec, M, alpha + (int64_t)i * nf, i, s)
                  : project_and_reduce(c, b, (double2 *)c->u.p, (double *)c->S.p, M, ai + (int64_t)i * b->ld(),
-                                      alpha + (int64_t)i * nf, s);
+                                      alpha + (int64_t)i * nf, i, s);
         if (st) return st;
         if (i > 0) {
             st = fac ? fac_pack_row(c, b, prec, alpha + (int64_t)i * nf, i, s) : pack_row(c, p, b, prec, tp, i, s);
             if (st) return st;
         }
     }
-    return QR_OK;
+    return numeric_read(c, s, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1377,7 +1419,7 @@ static qr_status fit_surrogate(qr_ctx *c, const qr_problem *p, const qr_basis *b
 
 extern "C" qr_status qr_solve_learned(qr_ctx *c, const qr_problem *p, const qr_basis *bc, int64_t M,
                                       uint64_t seed, const qr_learn_opts *o, double *alpha,
-                                      qr_learn_report *report, void *stream) {
+                                      qr_learn_report *report, float *params_out, void *stream) {
     qr_basis *b = const_cast<qr_basis *>(bc);
     if (!o || !report) return fail(QR_EINVAL, "qr_solve_learned: NULL opts or report");
     if (o->epochs < 0 || o->batch < 64 || o->batch > QR_MLP_MAX_BATCH || o->train_points < o->batch ||
@@ -1401,7 +1443,8 @@ extern "C" qr_status qr_solve_learned(qr_ctx *c, const qr_problem *p, const qr_b
     if ((st = ensure(c, c->lx, sizeof(double) * (size_t)d * M, "cloud state"))) return st;
     if ((st = ensure(c, c->lh, sizeof(double) * (size_t)M, "source term"))) return st;
     if ((st = ensure(c, c->ly, sizeof(double) * (size_t)M, "expansion values"))) return st;
-    if ((st = ensure(c, c->lparams, sizeof(float) * (size_t)N * kMlpParams, "surrogate parameters"))) return st;
+    // two spare floats: the buffer is cleared in whole doubles
+    if ((st = ensure(c, c->lparams, sizeof(float) * ((size_t)N * kMlpParams + 2), "surrogate parameters"))) return st;
     for (Buf *bb : {&c->lgrad, &c->lm, &c->lv})
         if ((st = ensure(c, *bb, sizeof(float) * (size_t)(kMlpParams + 1), "Adam state"))) return st;
     if ((st = ensure(c, c->ltx, sizeof(double) * (size_t)d * nt, "training pairs"))) return st;
@@ -1414,7 +1457,7 @@ extern "C" qr_status qr_solve_learned(qr_ctx *c, const qr_problem *p, const qr_b
     if ((st = ensure(c, c->lhy, sizeof(float) * (size_t)nh, "held-out pairs"))) return st;
 
     std::vector<double> mu(N, 0.0), sg(N, 1.0);
-    for (int j = 0; j < N; ++j) report[j] = qr_learn_report{0.0, 0.0, 0, 0};
+    for (int j = 0; j < N; ++j) report[j] = qr_learn_report{0.0, 0.0, 0, 0, 0.0, 1.0};
     const int db = dim_bucket(p->d, p->nbm);
     const int cap = depth_cap(b->max_nnz);
     const Walk W = make_walk(b->kind, b->level, b->d, b->law);
@@ -1424,7 +1467,26 @@ extern "C" qr_status qr_solve_learned(qr_ctx *c, const qr_problem *p, const qr_b
     double2 *ai = (double2 *)c->alpha_int.p;
     float *params = (float *)c->lparams.p;
     const int64_t nf = 2 * b->nrep - 1;
+    // parameters of time indices without a surrogate read as zero
+    QR_HIP(launch_zero((double *)params, (int64_t)N * kMlpParams / 2 + 1, s), "zero_kernel");
+    if ((st = numeric_clear(c, s))) return st;
     for (int32_t i = N - 1; i >= 0; --i) {
+        bool any_used = false;
+        for (int32_t j = i + 1; j < N; ++j) any_used = any_used || report[j].used;
+        if (!any_used) {
+            // every later time index uses its expansion: the fused path kernel of qr_solve
+            if ((st = run_path(c, p, b, i, M, seed, ai, S, u, nullptr, s))) return st;
+            if ((st = project_and_reduce(c, b, u, S, M, ai + (int64_t)i * b->ld(), alpha + (int64_t)i * nf, i, s)))
+                return st;
+            if (i >= 1 && o->epochs > 0) {
+                if ((st = fit_surrogate(c, p, b, i, seed, o, params + (int64_t)i * kMlpParams, &mu[i], &sg[i],
+                                        &report[i], s)))
+                    return st;
+                report[i].target_mean = mu[i];
+                report[i].target_sd = sg[i];
+            }
+            continue;
+        }
         QR_HIP(launch_sm_start(c->d_prob, b->law, i, M, seed, x, u, S, s), "sm_start_kernel");
         for (int32_t j = i; j < N; ++j) {
             QR_HIP(launch_sm_euler(db, c->d_prob, i, j, M, seed, x, H, s), "sm_euler_kernel");
@@ -1449,15 +1511,20 @@ extern "C" qr_status qr_solve_learned(qr_ctx *c, const qr_problem *p, const qr_b
                 QR_HIP(launch_sm_accum(c->d_prob, j, 0, M, y, nullptr, 0.0, 1.0, H, S, s), "sm_accum_kernel");
             }
         }
-        if ((st = project_and_reduce(c, b, u, S, M, ai + (int64_t)i * b->ld(), alpha + (int64_t)i * nf, s)))
+        if ((st = project_and_reduce(c, b, u, S, M, ai + (int64_t)i * b->ld(), alpha + (int64_t)i * nf, i, s)))
             return st;
         if (i >= 1 && o->epochs > 0) {
             if ((st = fit_surrogate(c, p, b, i, seed, o, params + (int64_t)i * kMlpParams, &mu[i], &sg[i], &report[i],
                                     s)))
                 return st;
+            report[i].target_mean = mu[i];
+            report[i].target_sd = sg[i];
         }
     }
-    return QR_OK;
+    if (params_out)
+        QR_HIP(hipMemcpyAsync(params_out, params, sizeof(float) * (size_t)N * kMlpParams, hipMemcpyDeviceToDevice, s),
+               "hipMemcpyAsync(params)");
+    return numeric_read(c, s, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1572,6 +1639,7 @@ extern "C" qr_status qr_solve_batched(qr_ctx *c, const qr_problem *p, const qr_b
     QR_HIP(launch_zero(alpha, (int64_t)R * p->N * nf, s), "zero_kernel");
     QR_HIP(launch_zero((double *)ab, 2 * total, s), "zero_kernel");
     const int db = dim_bucket(p->d, p->nbm);
+    if ((st = numeric_clear(c, s))) return st;
     for (int32_t i = p->N - 1; i >= 0; --i) {
         for (int ps = 0; ps < npass; ++ps) {
             const PassPlan &P = passes[ps];
@@ -1598,13 +1666,13 @@ extern "C" qr_status qr_solve_batched(qr_ctx *c, const qr_problem *p, const qr_b
                     return launch_reduce_batched(partial, nsplit, ob->nrep, (double)Mr, ob->d_ft,
                                                  b->d_canon_of_trav, P.walk->d_inv,
                                                  ab + P.off + (int64_t)i * ld * kBatchRT, (int32_t)k,
-                                                 alpha + ((int64_t)r * p->N + i) * nf, s);
+                                                 alpha + ((int64_t)r * p->N + i) * nf, c->d_bad, i, s);
                 });
                 if (st) return st;
             }
         }
     }
-    return QR_OK;
+    return numeric_read(c, s, nullptr);
 }
 
 // ---------------------------------------------------------------------------

@@ -101,7 +101,10 @@ hipError_t launch_fac_project(int prec, int tmpl, const FacDev &F, const FacTask
                               const double2 *e, const double *S, int64_t M, int64_t per_unit, int32_t units,
                               float *partial, hipStream_t s);
 hipError_t launch_fac_reduce(const float *partial, int32_t units, int64_t nblocks, const int32_t *ent, double M,
-                             double *alpha_row, hipStream_t s);
+                             double *alpha_row, int32_t *bad, int32_t step, hipStream_t s);
+// entries of a path's tables e^{2 pi i m u_l} (l < d, m < TS) in LDS, padded
+// to an odd count so that the 16 paths of a lane group fall in distinct banks
+__host__ __device__ inline int32_t fac_stride(int32_t d, int32_t TS) { return (d * TS) | 1; }
 // waves per block of the path kernel for a table of d x TS entries per path
 int fac_waves(int32_t d, int32_t TS);
 hipError_t launch_fac_pack(int prec, const double *alpha_row, const int32_t *ent, int64_t nblocks,

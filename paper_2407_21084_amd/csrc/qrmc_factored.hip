@@ -253,10 +253,9 @@ __device__ __forceinline__ float2 fac_tab(const float2 *T, int e) {
     return make_float2(v.x, e < 0 ? -v.y : v.y);
 }
 
-// product of the first nnz factors of a code (nnz wave-uniform, >= 1; the
-// factor of element 0 is T[0] = 1)
-__device__ __forceinline__ float2 fac_value(const float2 *T, const FacCode *code, int nnz) {
-    const uint4 c = *reinterpret_cast<const uint4 *>(code);
+// product of the first nnz factors of a code (nnz wave-uniform; an unused
+// element 0 reads T[0] = 1)
+__device__ __forceinline__ float2 fac_value(const float2 *T, const uint4 c, int nnz) {
     const uint32_t wd[4] = {c.x, c.y, c.z, c.w};
     float2 v = fac_tab(T, (int)(int16_t)(wd[0] & 0xffffu));
 #pragma unroll
@@ -265,8 +264,21 @@ __device__ __forceinline__ float2 fac_value(const float2 *T, const FacCode *code
     return v;
 }
 
+// acc += blocks KB.. of a row tile (the first nk of NKB; nk wave-uniform): a
+// chain of branches that leaves at the tile's last block, each block's B
+// operand a register of the cache (constant index)
+template <int NKB, int PREC, int KB>
+__device__ __forceinline__ void fac_blocks(f32x4 &acc, const uint4 *cb, const uint4 (&eb)[NKB], int nk) {
+    if constexpr (KB < NKB) {
+        if (KB < nk) {
+            acc = fac_mfma<PREC>(cb[KB * 64], eb[KB], acc);
+            fac_blocks<NKB, PREC, KB + 1>(acc, cb, eb, nk);
+        }
+    }
+}
+
 int fac_waves(int32_t d, int32_t TS) {
-    const size_t per_wave = (size_t)kFacPaths * d * TS * sizeof(float2);
+    const size_t per_wave = (size_t)kFacPaths * fac_stride(d, TS) * sizeof(float2);
     for (int w = 4; w > 1; w /= 2)
         if (per_wave * w <= 64 * 1024) return w;
     return 1;
@@ -284,8 +296,12 @@ int fac_waves(int32_t d, int32_t TS) {
 // kept as the product's B operands; each row tile is then one product block
 // per K-block, followed by EA of the lane's two rows and Re(EA C).
 // ---------------------------------------------------------------------------
+#ifndef QRMC_FAC_WAVES_PER_EU
+#define QRMC_FAC_WAVES_PER_EU 3
+#endif
 template <int DB, int NKB, int PREC>
-__global__ __launch_bounds__(256) void fac_path_kernel(const DevProblem *__restrict__ P0, const FacDev F,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QRMC_FAC_WAVES_PER_EU)))
+void fac_path_kernel(const DevProblem *__restrict__ P0, const FacDev F,
                                                        const int32_t i, const int64_t M, const uint64_t seed,
                                                        const uint4 *__restrict__ coef, double *__restrict__ S_out,
                                                        double2 *__restrict__ e_out) {
@@ -293,7 +309,7 @@ __global__ __launch_bounds__(256) void fac_path_kernel(const DevProblem *__restr
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, p = lane & 15;
     const int d = P0->d, nbm = P0->nbm, N = P0->N;
     const int TS = F.TS;
-    float2 *T = ftab + (size_t)(wv * kFacPaths + p) * d * TS;
+    float2 *T = ftab + (size_t)(wv * kFacPaths + p) * fac_stride(d, TS);
     const int64_t m = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wv) * kFacPaths + p;
     const int nu = __builtin_amdgcn_readfirstlane(P0->nu);
 
@@ -361,29 +377,40 @@ __global__ __launch_bounds__(256) void fac_path_kernel(const DevProblem *__restr
                     uint32_t w[4];
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        const float2 v = fac_value(T, F.cols + kb * kFacCols + 4 * g + q, nz);
+                        const float2 v = fac_value(T, *reinterpret_cast<const uint4 *>(F.cols + kb * kFacCols + 4 * g + q), nz);
                         w[q] = pack16x2<PREC>(v.x, v.y);
                     }
                     eb[kb] = make_uint4(w[0], w[1], w[2], w[3]);
                 }
             }
             const uint4 *cj = coef + (size_t)(j + 1) * F.nblocks * 64 + lane;
+            const uint4 *rcode = reinterpret_cast<const uint4 *>(F.rows) + 2 * g;
             float yp = 0.0f;
+            // the first coefficient block and the lane's two row codes of a tile
+            // are loaded one tile ahead, so their latency overlaps the current tile
+            FacTile tl = F.tiles[0];
+            FacTile tn = F.tiles[F.nrt > 1 ? 1 : 0];
+            uint4 a0 = cj[tl.off * 64];
+            uint4 c0 = rcode[0], c1 = rcode[1];
 #pragma unroll 1
             for (int rt = 0; rt < F.nrt; ++rt) {
-                const FacTile tl = F.tiles[rt];
-                const uint4 *cb = cj + tl.off * 64;
-                f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-                for (int kb = 0; kb < NKB; ++kb)
-                    if (kb < tl.nkb) acc = fac_mfma<PREC>(cb[kb * 64], eb[kb], acc);
-                const FacCode *rc = F.rows + rt * kFacRows + 2 * g;
-                const float2 ea0 = fac_value(T, rc, tl.nnz);
-                const float2 ea1 = fac_value(T, rc + 1, tl.nnz);
+                const int rn = rt + 1 < F.nrt ? rt + 1 : rt;
+                const FacTile tnn = F.tiles[rt + 2 < F.nrt ? rt + 2 : rn];
+                const uint4 a0n = cj[tn.off * 64];
+                const uint4 c0n = rcode[rn * kFacRows], c1n = rcode[rn * kFacRows + 1];
+                f32x4 acc = fac_mfma<PREC>(a0, eb[0], f32x4{0.0f, 0.0f, 0.0f, 0.0f});
+                if (tl.nkb > 1) fac_blocks<NKB, PREC, 1>(acc, cj + tl.off * 64, eb, tl.nkb);
+                const float2 ea0 = fac_value(T, c0, tl.nnz);
+                const float2 ea1 = fac_value(T, c1, tl.nnz);
                 yp = fmaf(ea0.x, acc[0], yp);
                 yp = fmaf(-ea0.y, acc[1], yp);
                 yp = fmaf(ea1.x, acc[2], yp);
                 yp = fmaf(-ea1.y, acc[3], yp);
+                tl = tn;
+                tn = tnn;
+                a0 = a0n;
+                c0 = c0n;
+                c1 = c1n;
             }
             yp += __shfl_xor(yp, 16);
             yp += __shfl_xor(yp, 32);
@@ -421,7 +448,7 @@ __global__ __launch_bounds__(256) void fac_project_kernel(const FacDev F, const 
     extern __shared__ float2 ftab[];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, q = lane & 15;
     const int d = F.d, TS = F.TS;
-    const int stride = d * TS;
+    const int stride = fac_stride(d, TS);
     float2 *Tw = ftab + (size_t)wv * kFacPaths * stride;
     const FacTask task = tasks[blockIdx.x];
     const int32_t unit = blockIdx.y * (blockDim.x >> 6) + wv;
@@ -472,7 +499,7 @@ __global__ __launch_bounds__(256) void fac_project_kernel(const FacDev F, const 
                 uint32_t w[4];
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
-                    const float2 v = fac_value(Tw + (4 * g + t) * stride, F.cols + kb * kFacCols + q, nz);
+                    const float2 v = fac_value(Tw + (4 * g + t) * stride, *reinterpret_cast<const uint4 *>(F.cols + kb * kFacCols + q), nz);
                     w[t] = pack16x2<PREC>(v.x, v.y);
                 }
                 bop[kb] = make_uint4(w[0], w[1], w[2], w[3]);
@@ -481,7 +508,7 @@ __global__ __launch_bounds__(256) void fac_project_kernel(const FacDev F, const 
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (r < task.R) {
-                const FacCode *rc = F.rows + (task.rt0 + r) * kFacRows + (q >> 1);
+                const uint4 rc = *reinterpret_cast<const uint4 *>(F.rows + (task.rt0 + r) * kFacRows + (q >> 1));
                 uint32_t w[4];
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
@@ -516,7 +543,8 @@ __global__ __launch_bounds__(256) void fac_project_kernel(const FacDev F, const 
 // the canonical row: entry (rr, cc) of block b is held by lane 16 (rr / 2) + cc
 // at components 2 (rr % 2) + {0, 1} = (Re Z, Im Z).
 __global__ void fac_reduce_kernel(const float *__restrict__ partial, int32_t units, int64_t nblocks,
-                                  const int32_t *__restrict__ ent, double inv_m, double *__restrict__ alpha) {
+                                  const int32_t *__restrict__ ent, double inv_m, double *__restrict__ alpha,
+                                  int32_t *__restrict__ bad, int32_t step) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= nblocks * kFacRows * kFacCols) return;
     const int32_t rep = ent[idx];
@@ -530,6 +558,7 @@ __global__ void fac_reduce_kernel(const float *__restrict__ partial, int32_t uni
         zr += (double)src[0];
         zi += (double)src[1];
     }
+    if (bad && !(isfinite(zr) && isfinite(zi))) atomicMax(bad, step);
     if (rep == 0) {
         alpha[0] = zr * inv_m;
     } else {
@@ -555,7 +584,7 @@ hipError_t launch_fac_pack(int prec, const double *alpha_row, const int32_t *ent
 template <int DB, int NKB, int PREC>
 static hipError_t fac_path_t(const FacPathArgs &a, hipStream_t s) {
     const int waves = fac_waves(a.F.d, a.F.TS);
-    const size_t lds = (size_t)waves * kFacPaths * a.F.d * a.F.TS * sizeof(float2);
+    const size_t lds = (size_t)waves * kFacPaths * fac_stride(a.F.d, a.F.TS) * sizeof(float2);
     static size_t granted = kLdsDefault;
     const hipError_t e = allow_lds((const void *)fac_path_kernel<DB, NKB, PREC>, lds, granted);
     if (e != hipSuccess) return e;
@@ -568,7 +597,9 @@ template <int DB, int PREC>
 static hipError_t fac_path_nkb(const FacPathArgs &a, hipStream_t s) {
     if (a.F.nkb <= 4) return fac_path_t<DB, 4, PREC>(a, s);
     if (a.F.nkb <= 8) return fac_path_t<DB, 8, PREC>(a, s);
+    if (a.F.nkb <= 12) return fac_path_t<DB, 12, PREC>(a, s);
     if (a.F.nkb <= 16) return fac_path_t<DB, 16, PREC>(a, s);
+    if (a.F.nkb <= 20) return fac_path_t<DB, 20, PREC>(a, s);
     if (a.F.nkb <= kFacMaxNkb) return fac_path_t<DB, kFacMaxNkb, PREC>(a, s);
     return hipErrorInvalidValue;
 }
@@ -588,7 +619,7 @@ static hipError_t fac_project_t(const FacDev &F, const FacTask *tasks, int32_t n
                                 const double *S, int64_t M, int64_t per_unit, int32_t units, float *partial,
                                 hipStream_t s) {
     const int waves = fac_waves(F.d, F.TS);
-    const size_t lds = (size_t)waves * kFacPaths * F.d * F.TS * sizeof(float2);
+    const size_t lds = (size_t)waves * kFacPaths * fac_stride(F.d, F.TS) * sizeof(float2);
     static size_t granted = kLdsDefault;
     const hipError_t e0 = allow_lds((const void *)fac_project_kernel<R, NKBT, PREC>, lds, granted);
     if (e0 != hipSuccess) return e0;
@@ -625,11 +656,11 @@ hipError_t launch_fac_project(int prec, int tmpl, const FacDev &F, const FacTask
 }
 
 hipError_t launch_fac_reduce(const float *partial, int32_t units, int64_t nblocks, const int32_t *ent, double M,
-                             double *alpha_row, hipStream_t s) {
+                             double *alpha_row, int32_t *bad, int32_t step, hipStream_t s) {
     const int64_t total = nblocks * kFacRows * kFacCols;
     if (total == 0) return hipSuccess;
     hipLaunchKernelGGL(fac_reduce_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, s, partial, units, nblocks, ent,
-                       1.0 / M, alpha_row);
+                       1.0 / M, alpha_row, bad, step);
     return hipGetLastError();
 }
 

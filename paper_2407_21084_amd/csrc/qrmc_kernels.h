@@ -85,9 +85,11 @@ hipError_t launch_project(int cap, const Walk &W, const double2 *e, int64_t lde,
                           int64_t paths_per_split, int32_t ntasks, int32_t nsplit, const Task *tasks,
                           const TaskItem *items, int32_t task_max, double2 *partial, int64_t nrep,
                           hipStream_t s);
+// bad (device, or NULL): atomically raised to `step` if a coefficient is not finite
 hipError_t launch_reduce(const double2 *partial, int32_t nsplit, int64_t nrep, double M,
                          double2 *alpha_int_row, double *alpha_row,
-                         const int32_t *canon_of_trav, hipStream_t s);
+                         const int32_t *canon_of_trav, int32_t *bad, int32_t step, hipStream_t s);
+hipError_t launch_set_flag(int32_t *flag, int32_t v, hipStream_t s);
 hipError_t launch_eval(int cap, bool grad, const Walk &W, const double2 *alpha_int_row,
                        const double *x, int64_t n, double *y, double *grad_out, hipStream_t s);
 hipError_t launch_x_to_e(int32_t nu, int32_t d, const double *x, int64_t n, double2 *e, hipStream_t s);
@@ -98,7 +100,7 @@ hipError_t launch_batched_path(int db, int cap, const BatchArgs &a, hipStream_t 
 hipError_t launch_reduce_batched(const double2 *partial, int32_t nsplit, int64_t nrep_sub, double M,
                                  const int32_t *ft, const int32_t *canon_of_trav,
                                  const int32_t *pass_pos, double2 *alpha_b_row, int32_t slot,
-                                 double *alpha_row, hipStream_t s);
+                                 double *alpha_row, int32_t *bad, int32_t step, hipStream_t s);
 hipError_t launch_zero(double *p, int64_t n, hipStream_t s);
 
 

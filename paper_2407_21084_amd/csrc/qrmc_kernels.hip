@@ -687,7 +687,8 @@ __global__ __launch_bounds__(WAVES * 64) void project_kernel(
 __global__ void reduce_kernel(const double2 *__restrict__ partial, int32_t nsplit, int64_t nrep,
                               double M, double2 *__restrict__ alpha_int_row,
                               double *__restrict__ alpha_row,
-                              const int32_t *__restrict__ canon_of_trav) {
+                              const int32_t *__restrict__ canon_of_trav, int32_t *__restrict__ bad,
+                              int32_t step) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrep) return;
     double sx = 0.0, sy = 0.0;
@@ -696,6 +697,7 @@ __global__ void reduce_kernel(const double2 *__restrict__ partial, int32_t nspli
         sx += p.x;
         sy += p.y;
     }
+    if (bad && !(isfinite(sx) && isfinite(sy))) atomicMax(bad, step);
     if (r == 0) {
         const double a0 = sx / M;
         alpha_int_row[0] = make_double2(a0, 0.0);
@@ -1299,7 +1301,7 @@ __global__ void reduce_batched_kernel(const double2 *__restrict__ partial, int32
                                       const int32_t *__restrict__ canon_of_trav,
                                       const int32_t *__restrict__ pass_pos,
                                       double2 *__restrict__ alpha_b_row, int32_t slot,
-                                      double *__restrict__ alpha_row) {
+                                      double *__restrict__ alpha_row, int32_t *__restrict__ bad, int32_t step) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nrep_sub) return;
     double sx = 0.0, sy = 0.0;
@@ -1308,6 +1310,7 @@ __global__ void reduce_batched_kernel(const double2 *__restrict__ partial, int32
         sx += p.x;
         sy += p.y;
     }
+    if (bad && !(isfinite(sx) && isfinite(sy))) atomicMax(bad, step);
     const int64_t r = ft[t];
     double2 *dst = alpha_b_row + (int64_t)pass_pos[r] * kBatchRT + slot;
     if (r == 0) {
@@ -1447,9 +1450,16 @@ hipError_t launch_project(int cap, const Walk &W, const double2 *e, int64_t lde,
 
 hipError_t launch_reduce(const double2 *partial, int32_t nsplit, int64_t nrep, double M,
                          double2 *alpha_int_row, double *alpha_row,
-                         const int32_t *canon_of_trav, hipStream_t s) {
+                         const int32_t *canon_of_trav, int32_t *bad, int32_t step, hipStream_t s) {
     hipLaunchKernelGGL(reduce_kernel, dim3(blocks_for(nrep, 256)), dim3(256), 0, s, partial, nsplit,
-                       nrep, M, alpha_int_row, alpha_row, canon_of_trav);
+                       nrep, M, alpha_int_row, alpha_row, canon_of_trav, bad, step);
+    return hipGetLastError();
+}
+
+__global__ void set_flag_kernel(int32_t *__restrict__ flag, int32_t v) { *flag = v; }
+
+hipError_t launch_set_flag(int32_t *flag, int32_t v, hipStream_t s) {
+    hipLaunchKernelGGL(set_flag_kernel, dim3(1), dim3(1), 0, s, flag, v);
     return hipGetLastError();
 }
 
@@ -1531,9 +1541,9 @@ hipError_t launch_batched_path(int db, int cap, const BatchArgs &a, hipStream_t 
 hipError_t launch_reduce_batched(const double2 *partial, int32_t nsplit, int64_t nrep_sub, double M,
                                  const int32_t *ft, const int32_t *canon_of_trav,
                                  const int32_t *pass_pos, double2 *alpha_b_row, int32_t slot,
-                                 double *alpha_row, hipStream_t s) {
+                                 double *alpha_row, int32_t *bad, int32_t step, hipStream_t s) {
     hipLaunchKernelGGL(reduce_batched_kernel, dim3(blocks_for(nrep_sub, 256)), dim3(256), 0, s, partial,
-                       nsplit, nrep_sub, M, ft, canon_of_trav, pass_pos, alpha_b_row, slot, alpha_row);
+                       nsplit, nrep_sub, M, ft, canon_of_trav, pass_pos, alpha_b_row, slot, alpha_row, bad, step);
     return hipGetLastError();
 }
 

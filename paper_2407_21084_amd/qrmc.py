@@ -49,6 +49,7 @@ EXPORTS = ["qr_last_error", "qr_version", "qr_build_basis", "qr_build_basis_law"
            "qr_solve_prec", "qr_mlp_init", "qr_mlp_features", "qr_mlp_forward", "qr_mlp_loss_grad",
            "qr_mlp_adam", "qr_solve_learned", "qr_solve_batched",
            "qr_basis_upload", "qr_eval_noalloc", "qr_ctx_set_prec_kernel", "qr_basis_factored",
+           "qr_ctx_numeric_status",
            "qr_host_uniform", "qr_host_norm_icdf", "qr_host_philox"]
 
 
@@ -118,6 +119,7 @@ _SIGS = {
     "qr_eval": (C.c_int, [_P, _P, _P, _I64, _P, _P, _P, _P]),
     "qr_basis_upload": (C.c_int, [_P, _P]),
     "qr_ctx_set_prec_kernel": (C.c_int, [_P, _I32]),
+    "qr_ctx_numeric_status": (C.c_int, [_P, C.POINTER(_I32)]),
     "qr_basis_factored": (C.c_int, [_P, C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I32), C.POINTER(_I64)]),
     "qr_eval_noalloc": (C.c_int, [_P, _P, _P, _I64, _P, _P, _P, _P]),
     "qr_project": (C.c_int, [_P, _P, _I64, _P, _P, _P, _P]),
@@ -299,6 +301,13 @@ class Context:
 
     def __del__(self):
         self.close()
+
+    def numeric_status(self) -> int:
+        """Time index of the latest non-finite row since the last check (-1 for
+        none); raises QrError (QR_ENUMERIC) if there is one."""
+        st = _I32()
+        _check(_lib.qr_ctx_numeric_status(self._h, C.byref(st)))
+        return st.value
 
     def set_prec_kernel(self, kind):
         k = PREC_KERNELS[kind] if isinstance(kind, str) else int(kind)

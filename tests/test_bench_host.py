@@ -3,6 +3,7 @@ surface, and the counted-traffic record that is reported only for the kernel
 sources it was counted on."""
 import importlib.util
 import json
+import math
 import os
 import subprocess
 import sys
@@ -29,11 +30,32 @@ def test_defaults_and_options(monkeypatch):
     b = _bench_module()
     monkeypatch.setattr(sys, "argv", ["bench.py"])
     a = b.parse()
-    assert (a.gpus, a.steps, a.warmup, a.workload, a.precision, a.law, a.damping) == \
-        (1, 3, 1, "d6-hcmax16-allen-cahn", "f64", "logistic", 0.0)
-    monkeypatch.setattr(sys, "argv", ["bench.py", "--law", "cauchy", "--damping", "2", "--precision", "bf16"])
+    assert (a.gpus, a.steps, a.warmup, a.workload, a.precision, a.prec_kernel, a.law, a.damping) == \
+        (1, 3, 1, "d6-hcmax16-allen-cahn", "bf16", "auto", "logistic", 0.0)
+    monkeypatch.setattr(sys, "argv", ["bench.py", "--law", "cauchy", "--damping", "2", "--precision", "f64"])
     a = b.parse()
-    assert (a.law, a.damping, a.precision) == ("cauchy", 2.0, "bf16")
+    assert (a.law, a.damping, a.precision) == ("cauchy", 2.0, "f64")
+
+
+def test_projection_floor_of_the_workloads():
+    """The projection floor used in the error split: relative squared
+    distance of u(0, .) to the span of the basis.  Against values computed
+    independently when the workloads were planned (0.169 for the d = 2
+    tensor set, 0.194 for the d = 6 hyperbolic cross), ||u||^2 in closed form
+    (E cos^2 through the logistic characteristic function pi t / sinh(pi t)),
+    and the floor falling strictly with the level of nested sets."""
+    import workloads as W
+    import oracle as O
+    b = _bench_module()
+    f2, u2 = b.projection_floor(W.D2_TENSOR4, O.reps_for(W.D2_TENSOR4))
+    assert abs(f2 - 0.169) < 1e-3
+    assert abs(u2 - 0.5 * math.exp(-2.0) * (1.0 + (2 * math.pi / math.sinh(2 * math.pi)) ** 2)) < 1e-12
+    f6, _ = b.projection_floor(W.D6_HCMAX16, O.reps_for(W.D6_HCMAX16))
+    assert abs(f6 - 0.194) < 1e-3
+    floors = [b.projection_floor(W.D2_TENSOR4.with_(level=k), O.reps_for(W.D2_TENSOR4.with_(level=k)))[0]
+              for k in (1, 2, 4, 8)]
+    assert all(0.0 <= f <= 1.0 for f in floors)
+    assert all(x > y for x, y in zip(floors, floors[1:]))
 
 
 def test_counted_traffic_only_for_its_sources(monkeypatch):

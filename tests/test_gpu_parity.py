@@ -521,3 +521,36 @@ def test_project_bench_size_sampled(env):
     ref, absum = O.project(sub, x, s, with_abs=True)
     idx = np.concatenate([[0], np.stack([2 * picks - 1, 2 * picks], axis=1).ravel()])
     assert_alpha(got[idx], ref, absum, what="bench-size projection")
+
+
+# ---------------------------------------------------------------------------
+# non-finite coefficients (QR_ENUMERIC)
+# ---------------------------------------------------------------------------
+
+def test_non_finite_coefficients_are_reported(env):
+    """A manufactured solution of amplitude 1e120 makes the Allen-Cahn source
+    h = ... - (u - u^3) overflow to infinity along the paths from the first
+    iteration on: the full solves return QR_ENUMERIC naming time index N-1,
+    an asynchronous backward step leaves the record for
+    qr_ctx_numeric_status, and a finite problem afterwards reports nothing."""
+    Q, ctx, torch = env
+    w = W.D2_TENSOR4.with_(driver="allen_cahn", sol_A=1e120, clamp=math.inf, M=500)
+    b = Q.Basis(w.d, w.set_kind, w.level)
+    a = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device="cuda")
+    say("numeric flag: overflowing driver")
+    for solve in (lambda: ctx.solve(Q.problem_from(w), b, w.M, w.seed, a),
+                  lambda: ctx.solve_prec(Q.problem_from(w), b, w.M, w.seed, "bf16", a),
+                  lambda: ctx.solve_batched(Q.problem_from(w), b, [(0.0, w.d, w.level, w.M)], w.seed, a[None])):
+        with pytest.raises(Q.QrError) as e:
+            solve()
+        assert e.value.status == -5 and f"time index {w.N - 1}" in str(e.value)
+    assert ctx.numeric_status() == -1           # the solves cleared their record
+    ctx.backward_step(Q.problem_from(w), b, w.N - 1, w.M, w.seed, a)
+    with pytest.raises(Q.QrError) as e:
+        ctx.numeric_status()
+    assert e.value.status == -5
+    assert ctx.numeric_status() == -1           # read and cleared
+    ok = W.D2_TENSOR4.with_(M=500)
+    ctx.solve(Q.problem_from(ok), b, ok.M, ok.seed, a)
+    ctx.backward_step(Q.problem_from(ok), b, 0, ok.M, ok.seed, a)
+    assert ctx.numeric_status() == -1
