@@ -91,11 +91,12 @@ struct FacPathArgs {
 // largest K-block count the path kernel's instances cache
 constexpr int kFacMaxNkb = 24;
 
-// A projection task: R consecutive row tiles from rt0 (template tmpl).
+// A projection task: R consecutive row tiles from rt0, K-blocks from kb0
+// (template tmpl).
 struct FacTask {
-    int32_t rt0, R, tmpl, pad;
+    int32_t rt0, R, tmpl, kb0;
 };
-constexpr int kFacTemplates = 6;
+constexpr int kFacTemplates = 4;
 void build_fac_tasks(const FactorLayout &L, std::vector<FacTask> tasks[kFacTemplates]);
 hipError_t launch_fac_project(int prec, int tmpl, const FacDev &F, const FacTask *tasks, int32_t ntasks,
                               const double2 *e, const double *S, int64_t M, int64_t per_unit, int32_t units,

@@ -179,17 +179,24 @@ bool build_factor_layout(int32_t d, int32_t kind, int32_t level, const int32_t *
 }
 
 // Projection tasks: consecutive row tiles whose K-blocks fit one of the
-// templates (R row tiles x NKBT K-blocks, R NKBT = 32; the last template takes
-// one row tile of up to kFacMaxNkb K-blocks).  Row tiles are in order of
+// templates (R row tiles x NKBT K-blocks, R NKBT = 8 accumulator blocks per
+// wave); a row tile of more than 8 K-blocks is cut into tasks of 8 K-blocks
+// (kb0 = 0, 8, ...) of the last template.  Row tiles are in order of
 // non-increasing K-block count, so a task's first tile has the most.
-static const int kTmplR[kFacTemplates] = {32, 16, 8, 4, 2, 1};
-static const int kTmplK[kFacTemplates] = {1, 2, 4, 8, 16, kFacMaxNkb};
+static const int kTmplR[kFacTemplates] = {8, 4, 2, 1};
+static const int kTmplK[kFacTemplates] = {1, 2, 4, 8};
 
 void build_fac_tasks(const FactorLayout &L, std::vector<FacTask> tasks[kFacTemplates]) {
     for (int t = 0; t < kFacTemplates; ++t) tasks[t].clear();
+    const int last = kFacTemplates - 1;
     int32_t rt = 0;
     while (rt < L.nrt) {
         const int32_t k = L.tiles[rt].nkb;
+        if (k > kTmplK[last]) {
+            for (int32_t kb0 = 0; kb0 < k; kb0 += kTmplK[last]) tasks[last].push_back(FacTask{rt, 1, last, kb0});
+            ++rt;
+            continue;
+        }
         int t = 0;
         while (kTmplK[t] < k) ++t;
         int32_t n = 0;
@@ -202,6 +209,9 @@ void build_fac_tasks(const FactorLayout &L, std::vector<FacTask> tasks[kFacTempl
 // ---------------------------------------------------------------------------
 // Device
 // ---------------------------------------------------------------------------
+// Tables that no kernel writes while it runs, read through the constant
+// address space so that wave-uniform reads become scalar loads.
+#define CONSTANT_AS __attribute__((address_space(4)))
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
@@ -241,6 +251,25 @@ __global__ void fac_pack_kernel(const double *__restrict__ alpha, const int32_t 
         w[q] = part == 0 ? pack16x2<PREC>((float)br, (float)-bi) : pack16x2<PREC>((float)bi, (float)br);
     }
     out[idx] = make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// a row tile's record (the tile table is read-only while kernels run: read
+// through the constant address space, wave-uniform, as scalar loads)
+__device__ __forceinline__ FacTile fac_tile(const FacTile *t, int i) {
+    const FacTile CONSTANT_AS *c = (const FacTile CONSTANT_AS *)t;
+    FacTile r;
+    r.nkb = c[i].nkb;
+    r.nnz = c[i].nnz;
+    r.off = c[i].off;
+    return r;
+}
+
+// the value of the partner lane (lane ^ 1), by a DPP quad permutation
+__device__ __forceinline__ float2 swap_pair(float2 v) {
+    constexpr int kQuadSwap = 0xB1;  // quad_perm [1, 0, 3, 2]
+    const int x = __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v.x), kQuadSwap, 0xf, 0xf, true);
+    const int y = __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v.y), kQuadSwap, 0xf, 0xf, true);
+    return make_float2(__builtin_bit_cast(float, x), __builtin_bit_cast(float, y));
 }
 
 __device__ __forceinline__ float2 fcmul(float2 a, float2 b) {
@@ -373,7 +402,7 @@ void fac_path_kernel(const DevProblem *__restrict__ P0, const FacDev F,
             for (int kb = 0; kb < NKB; ++kb) {
                 eb[kb] = make_uint4(0, 0, 0, 0);
                 if (kb < F.nkb) {
-                    const int nz = F.colnnz[kb];
+                    const int nz = ((const int32_t CONSTANT_AS *)F.colnnz)[kb];
                     uint32_t w[4];
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
@@ -388,14 +417,14 @@ void fac_path_kernel(const DevProblem *__restrict__ P0, const FacDev F,
             float yp = 0.0f;
             // the first coefficient block and the lane's two row codes of a tile
             // are loaded one tile ahead, so their latency overlaps the current tile
-            FacTile tl = F.tiles[0];
-            FacTile tn = F.tiles[F.nrt > 1 ? 1 : 0];
+            FacTile tl = fac_tile(F.tiles, 0);
+            FacTile tn = fac_tile(F.tiles, F.nrt > 1 ? 1 : 0);
             uint4 a0 = cj[tl.off * 64];
             uint4 c0 = rcode[0], c1 = rcode[1];
 #pragma unroll 1
             for (int rt = 0; rt < F.nrt; ++rt) {
                 const int rn = rt + 1 < F.nrt ? rt + 1 : rt;
-                const FacTile tnn = F.tiles[rt + 2 < F.nrt ? rt + 2 : rn];
+                const FacTile tnn = fac_tile(F.tiles, rt + 2 < F.nrt ? rt + 2 : rn);
                 const uint4 a0n = cj[tn.off * 64];
                 const uint4 c0n = rcode[rn * kFacRows], c1n = rcode[rn * kFacRows + 1];
                 f32x4 acc = fac_mfma<PREC>(a0, eb[0], f32x4{0.0f, 0.0f, 0.0f, 0.0f});
@@ -452,6 +481,8 @@ __global__ __launch_bounds__(256) void fac_project_kernel(const FacDev F, const 
     float2 *Tw = ftab + (size_t)wv * kFacPaths * stride;
     const FacTask task = tasks[blockIdx.x];
     const int32_t unit = blockIdx.y * (blockDim.x >> 6) + wv;
+    // K-blocks kb0 .. kb0 + nkb[r] - 1 of row tile rt0 + r
+    const int kb0 = task.kb0;
     int nkb[R];
     int nnz[R];
 #pragma unroll
@@ -459,8 +490,9 @@ __global__ __launch_bounds__(256) void fac_project_kernel(const FacDev F, const 
         nkb[r] = 0;
         nnz[r] = 0;
         if (r < task.R) {
-            nkb[r] = F.tiles[task.rt0 + r].nkb;
-            nnz[r] = F.tiles[task.rt0 + r].nnz;
+            const FacTile tl = fac_tile(F.tiles, task.rt0 + r);
+            nkb[r] = tl.nkb - kb0 < NKBT ? tl.nkb - kb0 : NKBT;
+            nnz[r] = tl.nnz;
         }
     }
     f32x4 acc[R][NKBT];
@@ -495,11 +527,12 @@ __global__ __launch_bounds__(256) void fac_project_kernel(const FacDev F, const 
         for (int kb = 0; kb < NKBT; ++kb) {
             bop[kb] = make_uint4(0, 0, 0, 0);
             if (kb < nkb[0]) {
-                const int nz = F.colnnz[kb];
+                const int nz = ((const int32_t CONSTANT_AS *)F.colnnz)[kb0 + kb];
+                const uint4 cc = *reinterpret_cast<const uint4 *>(F.cols + (kb0 + kb) * kFacCols + q);
                 uint32_t w[4];
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
-                    const float2 v = fac_value(Tw + (4 * g + t) * stride, *reinterpret_cast<const uint4 *>(F.cols + kb * kFacCols + q), nz);
+                    const float2 v = fac_value(Tw + (4 * g + t) * stride, cc, nz);
                     w[t] = pack16x2<PREC>(v.x, v.y);
                 }
                 bop[kb] = make_uint4(w[0], w[1], w[2], w[3]);
@@ -509,10 +542,18 @@ __global__ __launch_bounds__(256) void fac_project_kernel(const FacDev F, const 
         for (int r = 0; r < R; ++r) {
             if (r < task.R) {
                 const uint4 rc = *reinterpret_cast<const uint4 *>(F.rows + (task.rt0 + r) * kFacRows + (q >> 1));
+                // lanes q and q ^ 1 need EA of the same row at the same four
+                // paths: each forms two of them and takes the other two from
+                // its partner (quad permutation [1, 0, 3, 2])
+                const int h = 2 * (q & 1);
+                const float2 m0 = fac_value(Tw + (4 * g + h) * stride, rc, nnz[r]);
+                const float2 m1 = fac_value(Tw + (4 * g + h + 1) * stride, rc, nnz[r]);
+                const float2 o0 = swap_pair(m0), o1 = swap_pair(m1);
+                const float2 eas[4] = {h ? o0 : m0, h ? o1 : m1, h ? m0 : o0, h ? m1 : o1};
                 uint32_t w[4];
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
-                    const float2 ea = fac_value(Tw + (4 * g + t) * stride, rc, nnz[r]);
+                    const float2 ea = eas[t];
                     const float wr = s4[t] * ea.x, wi = s4[t] * ea.y;
                     w[t] = (q & 1) ? pack16x2<PREC>(wi, wr) : pack16x2<PREC>(wr, -wi);
                 }
@@ -528,7 +569,7 @@ __global__ __launch_bounds__(256) void fac_project_kernel(const FacDev F, const 
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         if (r < task.R) {
-            const int64_t off = F.tiles[task.rt0 + r].off;
+            const int64_t off = fac_tile(F.tiles, task.rt0 + r).off + kb0;
 #pragma unroll
             for (int kb = 0; kb < NKBT; ++kb)
                 if (kb < nkb[r]) {
@@ -599,6 +640,7 @@ static hipError_t fac_path_nkb(const FacPathArgs &a, hipStream_t s) {
     if (a.F.nkb <= 8) return fac_path_t<DB, 8, PREC>(a, s);
     if (a.F.nkb <= 12) return fac_path_t<DB, 12, PREC>(a, s);
     if (a.F.nkb <= 16) return fac_path_t<DB, 16, PREC>(a, s);
+    if (a.F.nkb <= 18) return fac_path_t<DB, 18, PREC>(a, s);
     if (a.F.nkb <= 20) return fac_path_t<DB, 20, PREC>(a, s);
     if (a.F.nkb <= kFacMaxNkb) return fac_path_t<DB, kFacMaxNkb, PREC>(a, s);
     return hipErrorInvalidValue;
@@ -633,12 +675,10 @@ static hipError_t fac_project_p(int tmpl, const FacDev &F, const FacTask *tasks,
                                 const double *S, int64_t M, int64_t per_unit, int32_t units, float *partial,
                                 hipStream_t s) {
     switch (tmpl) {
-    case 0: return fac_project_t<32, 1, PREC>(F, tasks, ntasks, e, S, M, per_unit, units, partial, s);
-    case 1: return fac_project_t<16, 2, PREC>(F, tasks, ntasks, e, S, M, per_unit, units, partial, s);
-    case 2: return fac_project_t<8, 4, PREC>(F, tasks, ntasks, e, S, M, per_unit, units, partial, s);
-    case 3: return fac_project_t<4, 8, PREC>(F, tasks, ntasks, e, S, M, per_unit, units, partial, s);
-    case 4: return fac_project_t<2, 16, PREC>(F, tasks, ntasks, e, S, M, per_unit, units, partial, s);
-    case 5: return fac_project_t<1, kFacMaxNkb, PREC>(F, tasks, ntasks, e, S, M, per_unit, units, partial, s);
+    case 0: return fac_project_t<8, 1, PREC>(F, tasks, ntasks, e, S, M, per_unit, units, partial, s);
+    case 1: return fac_project_t<4, 2, PREC>(F, tasks, ntasks, e, S, M, per_unit, units, partial, s);
+    case 2: return fac_project_t<2, 4, PREC>(F, tasks, ntasks, e, S, M, per_unit, units, partial, s);
+    case 3: return fac_project_t<1, 8, PREC>(F, tasks, ntasks, e, S, M, per_unit, units, partial, s);
     }
     return hipErrorInvalidValue;
 }

@@ -1,7 +1,17 @@
 """Reduced-precision form, factored kernel (qr_ctx_set_prec_kernel "factored"):
-the expansion along the paths as a product of the staircase coefficient matrix
-with the paths' e^{2 pi i kB.uB} values on the matrix cores, against the FP64
-oracle on the same Philox streams, in the relative 2-norm of each alpha row.
+the expansion along the paths and the projection as products of the
+staircase coefficient matrix with the paths' basis factors on the matrix
+cores, against the FP64 oracle on the same Philox streams, in the relative
+2-norm of each alpha row.
+
+Tolerance (rounding model).  The expansion carries the error of the walk
+kernel's (about u relative to S; test_gpu_precision.py).  The projection now
+rounds W = S EA and EB to 16 bits as well: each term S phi_k(X_m) of the
+Monte-Carlo sum gets an independent relative error of rms (2/sqrt3) u, so a
+coefficient moves by about 1.15 u sqrt(sum_m (S phi_k)^2) / M, which is
+1.15 u of the row's norm when alpha is dominated by the Monte-Carlo
+variance (these rows are).  REL = 2u covers both (7.8e-3 bf16, 9.8e-4 half);
+layout or indexing mistakes give O(1) errors.
 """
 import numpy as np
 import pytest
@@ -13,7 +23,7 @@ from gpu_common import env, dev, host, say, rel_err  # noqa: F401 (env is a fixt
 pytestmark = pytest.mark.gpu
 
 UNIT = {"bf16": 2.0 ** -8, "f16": 2.0 ** -11}
-REL = {p: 8 * u for p, u in UNIT.items()}
+REL = {p: 2 * u for p, u in UNIT.items()}
 
 
 def _w(d, set_kind, level, driver, M, N=4, f_a=0.5, clamp=float("inf"), b1=0.0):
