@@ -22,7 +22,8 @@ MAXD = 16
 MAXN = 256
 
 SET_KINDS = {"tensor": 0, "hc_max": 1, "hc_1p": 2, "total": 3}
-DRIVERS = {"linear": 0, "sin": 1, "allen_cahn": 2, "zrat": 3}
+DRIVERS = {"linear": 0, "sin": 1, "allen_cahn": 2, "zrat": 3, "paper": 4}
+BASES = {"fourier": 0, "cosine": 1}
 LAWS = {"logistic": 0, "student2": 1, "cauchy": 2}
 
 
@@ -43,6 +44,7 @@ class Problem(C.Structure):
         ("sol_A", C.c_double), ("sol_c", C.c_double), ("sol_p", C.c_double),
         ("sol_w", C.c_double * MAXD),
         ("damping_q", C.c_double),
+        ("sol_B", C.c_double), ("basis", C.c_int32),
     ]
 
 
@@ -65,14 +67,14 @@ def lib():
             "or_law_icdf": (D, [C.c_int, D]),
             "or_law_pdf": (D, [C.c_int, D]),
             "or_enumerate": (I64, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, P, I64]),
-            "or_basis_values": (None, [C.c_int, C.c_int, I64, P, P, P]),
-            "or_eval": (None, [C.c_int, C.c_int, I64, P, P, I64, P, P, P]),
+            "or_basis_values": (None, [C.c_int, C.c_int, C.c_int, I64, P, P, P]),
+            "or_eval": (None, [C.c_int, C.c_int, C.c_int, I64, P, P, I64, P, P, P]),
             "or_msol_u": (D, [P, D, P]),
             "or_msol_h": (D, [P, D, P]),
             "or_path_response": (D, [P, I64, P, I32, U64, U64, P]),
             "or_damping": (D, [P, P]),
             "or_eval_y": (D, [P, I64, P, P, P, P]),
-            "or_project": (None, [C.c_int, C.c_int, I64, P, I64, P, P, P, P]),
+            "or_project": (None, [C.c_int, C.c_int, C.c_int, I64, P, I64, P, P, P, P]),
             "or_backward_step": (C.c_int, [P, I64, P, I32, I64, U64, P, P, P, P]),
             "or_solve": (C.c_int, [P, I64, P, I64, U64, P]),
             "or_backward_step_learned": (C.c_int, [P, I64, P, I32, I64, U64, P, P, P, P, P]),
@@ -155,37 +157,40 @@ def count_set(d: int, kind: str, level: int, nonneg: bool = False) -> int:
     return int(lib().or_enumerate(d, SET_KINDS[kind], level, int(nonneg), 0, None, 0))
 
 
-def nfuncs(reps: np.ndarray) -> int:
-    return 2 * reps.shape[0] - 1
+def nfuncs(reps: np.ndarray, basis: str = "fourier") -> int:
+    """Real basis functions of a set: 2 R - 1 for the Fourier basis over the
+    R representatives, one per vector for the cosine basis over N^d."""
+    return reps.shape[0] if basis == "cosine" else 2 * reps.shape[0] - 1
 
 
-def basis_values(reps: np.ndarray, x, law: str = "logistic") -> np.ndarray:
+def basis_values(reps: np.ndarray, x, law: str = "logistic", basis: str = "fourier") -> np.ndarray:
     x = _f64(x)
     reps = np.ascontiguousarray(reps, dtype=np.int32)
-    phi = np.zeros(nfuncs(reps))
-    lib().or_basis_values(reps.shape[1], LAWS[law], reps.shape[0], _ptr(reps), _ptr(x), _ptr(phi))
+    phi = np.zeros(nfuncs(reps, basis))
+    lib().or_basis_values(reps.shape[1], LAWS[law], BASES[basis], reps.shape[0], _ptr(reps), _ptr(x), _ptr(phi))
     return phi
 
 
-def evaluate(reps: np.ndarray, alpha_row, x, grad: bool = False, law: str = "logistic"):
+def evaluate(reps: np.ndarray, alpha_row, x, grad: bool = False, law: str = "logistic", basis: str = "fourier"):
     reps = np.ascontiguousarray(reps, dtype=np.int32)
     x = _f64(x)
     n, d = x.shape
     y = np.zeros(n)
     g = np.zeros((n, d)) if grad else None
-    lib().or_eval(d, LAWS[law], reps.shape[0], _ptr(reps), _ptr(_f64(alpha_row)), n, _ptr(x), _ptr(y),
-                  _ptr(g) if grad else None)
+    lib().or_eval(d, LAWS[law], BASES[basis], reps.shape[0], _ptr(reps), _ptr(_f64(alpha_row)), n, _ptr(x),
+                  _ptr(y), _ptr(g) if grad else None)
     return (y, g) if grad else y
 
 
-def project(reps: np.ndarray, x, s, with_abs: bool = False, law: str = "logistic"):
+def project(reps: np.ndarray, x, s, with_abs: bool = False, law: str = "logistic", basis: str = "fourier"):
     reps = np.ascontiguousarray(reps, dtype=np.int32)
     x = _f64(x)
     s = _f64(s)
     n, d = x.shape
-    a = np.zeros(nfuncs(reps))
-    ab = np.zeros(nfuncs(reps))
-    lib().or_project(d, LAWS[law], reps.shape[0], _ptr(reps), n, _ptr(x), _ptr(s), _ptr(a), _ptr(ab))
+    a = np.zeros(nfuncs(reps, basis))
+    ab = np.zeros(nfuncs(reps, basis))
+    lib().or_project(d, LAWS[law], BASES[basis], reps.shape[0], _ptr(reps), n, _ptr(x), _ptr(s), _ptr(a),
+                     _ptr(ab))
     return (a, ab) if with_abs else a
 
 
@@ -211,10 +216,16 @@ def problem(w) -> Problem:
             p.sigma[l * w.nbm + k] = w.sigma[l][k]
     p.sol_A, p.sol_c, p.sol_p = w.sol_A, w.sol_c, w.sol_p
     p.damping_q = w.damping_q
+    p.sol_B = w.sol_B
+    p.basis = BASES[w.basis]
     return p
 
 
 def reps_for(w) -> np.ndarray:
+    """The workload's index set: representatives over Z^d for the Fourier
+    basis, every vector of the set over N^d for the cosine basis."""
+    if w.basis == "cosine":
+        return enumerate_set(w.d, w.set_kind, w.level, nonneg=True, reps_only=False)
     return enumerate_set(w.d, w.set_kind, w.level)
 
 
@@ -236,7 +247,7 @@ def backward_step(w, reps, i, M, seed, alpha, want_x=False, want_s=False):
     p = problem(w)
     reps = np.ascontiguousarray(reps, dtype=np.int32)
     assert alpha.dtype == np.float64 and alpha.flags.c_contiguous
-    nf = nfuncs(reps)
+    nf = nfuncs(reps, w.basis)
     ab = np.zeros(nf)
     x = np.zeros((M, w.d)) if want_x else None
     s = np.zeros(M) if want_s else None
@@ -267,7 +278,7 @@ def backward_step_learned(w, reps, i, M, seed, alpha, nets, mu, sd):
     keep = [None if t is None else _f64(t) for t in nets]
     ptrs = (C.c_void_p * w.N)(*[None if t is None else t.ctypes.data for t in keep])
     mu_a, sd_a = _f64(mu), _f64(sd)
-    ab = np.zeros(nfuncs(reps))
+    ab = np.zeros(nfuncs(reps, w.basis))
     rc = lib().or_backward_step_learned(C.byref(p), reps.shape[0], _ptr(reps), i, M, seed, _ptr(alpha),
                                         _ptr(ab), ptrs, _ptr(mu_a), _ptr(sd_a))
     if rc:
@@ -303,7 +314,7 @@ def path_response(w, reps, i, seed, m, alpha) -> float:
 def solve(w, reps, M=None, seed=None) -> np.ndarray:
     p = problem(w)
     reps = np.ascontiguousarray(reps, dtype=np.int32)
-    alpha = np.zeros((w.N, nfuncs(reps)))
+    alpha = np.zeros((w.N, nfuncs(reps, w.basis)))
     rc = lib().or_solve(C.byref(p), reps.shape[0], _ptr(reps), w.M if M is None else M,
                         w.seed if seed is None else seed, _ptr(alpha))
     if rc:

@@ -46,7 +46,12 @@
  *     handed to the driver, the division of the response and the projection
  *     target are each pinned (Lemma 3.1 with Gaussian moments, an exact
  *     identity, Lemma 3.1 by quadrature);
- *   - a constant truncation level L.
+ *   - a constant truncation level L;
+ *   - the paper's own variant is also available: its cosine basis on N^d
+ *     (Lemma 2.1, eq (phi:dim:d)) over the sets Gamma_F, Gamma_H and Gamma_T
+ *     of Sec. 2.3.3, and the driver of its Sec. 5 benchmark, eq (pde2OnlyY),
+ *     f = min(1, (y - u(t,x))^2) with u = 1 + kappa + sin(lambda sum x)
+ *     e^{lambda^2 d (t-T)/2} (the family B + A e^{-c(T-t)} cos(w.x + p)).
  */
 #include <math.h>
 #include <stdint.h>
@@ -67,16 +72,19 @@ typedef struct {
     int32_t nbm;      /* Brownian dimension                                */
     int32_t N;        /* number of time steps                              */
     int32_t driver;   /* 0: f=h, 1: a sin y + h, 2: y - y^3 + h,
-                         3: a|z|^2/(1+|z|^2) + y/(1+y^2) + h              */
+                         3: a|z|^2/(1+|z|^2) + y/(1+y^2) + h,
+                         4: min(1, (y - u(t,x))^2) + h (Sec. 5)            */
     int32_t nu;       /* sampling law: 0 logistic, 1 Student mu=2, 2 Cauchy  */
     double f_a;       /* driver parameter a                                */
     double clamp;     /* truncation level L of T_L (INFINITY: none)        */
     double t[OR_MAXN + 1];          /* time grid t_0 < ... < t_N           */
     double b0[OR_MAXD], b1[OR_MAXD];/* drift b(t,x)_l = b0_l + b1_l x_l    */
     double sigma[OR_MAXD * OR_MAXD];/* diffusion, d x nbm, row-major       */
-    double sol_A, sol_c, sol_p;     /* u(t,x) = A e^{-c(T-t)} cos(w.x+p)   */
+    double sol_A, sol_c, sol_p;     /* u(t,x) = B + A e^{-c(T-t)} cos(w.x+p) */
     double sol_w[OR_MAXD];
     double damping_q;               /* damping exponent q >= 0 (eq (yqi))  */
+    double sol_B;                   /* constant offset B of u              */
+    int32_t basis;                  /* 0: Fourier on Z^d, 1: cosine on N^d */
 } or_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -297,10 +305,30 @@ static double or_phase(const int32_t *k, const double *u, int d)
     return th - rint(th);
 }
 
-void or_basis_values(int d, int nu, int64_t nrep, const int32_t *reps, const double *x, double *phi)
+/* The paper's cosine basis on N^d (Lemma 2.1 and the tensor products of
+ * eq (phi:dim:d)): phi_k(x) = prod_l c_{k_l}(F(x_l)), c_0 = 1,
+ * c_m(u) = sqrt2 cos(m pi u).  One function per vector k (reps holds all of
+ * the set, lexicographic). */
+static double or_cos_factor(int m, double u) { return m == 0 ? 1.0 : sqrt(2.0) * cos((double)m * M_PI * u); }
+
+static double or_cos_value(const int32_t *k, const double *u, int d)
+{
+    double v = 1.0;
+    for (int l = 0; l < d; ++l) v *= or_cos_factor(k[l], u[l]);
+    return v;
+}
+
+/* number of basis functions of a set of nrep vectors */
+static int64_t or_nfuncs_of(int basis, int64_t nrep) { return basis == 1 ? nrep : 2 * nrep - 1; }
+
+void or_basis_values(int d, int nu, int basis, int64_t nrep, const int32_t *reps, const double *x, double *phi)
 {
     double u[OR_MAXD];
     for (int l = 0; l < d; ++l) u[l] = or_law_cdf(nu, x[l]);
+    if (basis == 1) {
+        for (int64_t r = 0; r < nrep; ++r) phi[r] = or_cos_value(reps + r * d, u, d);
+        return;
+    }
     phi[0] = 1.0;
     for (int64_t r = 1; r < nrep; ++r) {
         double th = 2.0 * M_PI * or_phase(reps + r * d, u, d);
@@ -312,9 +340,13 @@ void or_basis_values(int d, int nu, int64_t nrep, const int32_t *reps, const dou
 /* Expansion ybar(x) = sum_k alpha_k phi_k(x) (eq (yqi:bar:M)) and, when
  * grad != NULL, its x-gradient by the chain rule through F (dF/dx = nu_l).
  * The sum runs in basis order with Neumaier compensation. */
-static double or_expansion(int d, int nu, int64_t nrep, const int32_t *reps, const double *alpha,
+static double or_expansion_cos(int d, int nu, int64_t nrep, const int32_t *reps, const double *alpha,
+                               const double *x, double *grad);
+
+static double or_expansion(int d, int nu, int basis, int64_t nrep, const int32_t *reps, const double *alpha,
                            const double *x, double *grad)
 {
+    if (basis == 1) return or_expansion_cos(d, nu, nrep, reps, alpha, x, grad);
     double u[OR_MAXD], dudx[OR_MAXD];
     for (int l = 0; l < d; ++l) {
         u[l] = or_law_cdf(nu, x[l]);
@@ -348,13 +380,50 @@ static double or_expansion(int d, int nu, int64_t nrep, const int32_t *reps, con
     return s + c;
 }
 
+/* The cosine expansion sum_k alpha_k phi_k(x) and its x-gradient:
+ * d phi_k / d x_l = (prod_{j != l} c_{k_j}(u_j)) c'_{k_l}(u_l) nu_l(x_l) with
+ * c'_m(u) = -sqrt2 m pi sin(m pi u). */
+static double or_expansion_cos(int d, int nu, int64_t nrep, const int32_t *reps, const double *alpha,
+                               const double *x, double *grad)
+{
+    double u[OR_MAXD], dudx[OR_MAXD];
+    for (int l = 0; l < d; ++l) {
+        u[l] = or_law_cdf(nu, x[l]);
+        dudx[l] = or_law_pdf(nu, x[l]);
+    }
+    double s = 0.0, c = 0.0;
+    double gs[OR_MAXD], gc[OR_MAXD];
+    for (int l = 0; l < d; ++l) { gs[l] = 0.0; gc[l] = 0.0; }
+    for (int64_t r = 0; r < nrep; ++r) {
+        const int32_t *k = reps + r * d;
+        double term = alpha[r] * or_cos_value(k, u, d);
+        double t = s + term;
+        c += (fabs(s) >= fabs(term)) ? (s - t) + term : (term - t) + s;
+        s = t;
+        if (grad) {
+            for (int l = 0; l < d; ++l) {
+                if (k[l] == 0) continue;
+                double g = alpha[r] * -sqrt(2.0) * (double)k[l] * M_PI * sin((double)k[l] * M_PI * u[l]);
+                for (int j = 0; j < d; ++j)
+                    if (j != l) g *= or_cos_factor(k[j], u[j]);
+                double tt = gs[l] + g;
+                gc[l] += (fabs(gs[l]) >= fabs(g)) ? (gs[l] - tt) + g : (g - tt) + gs[l];
+                gs[l] = tt;
+            }
+        }
+    }
+    if (grad)
+        for (int l = 0; l < d; ++l) grad[l] = (gs[l] + gc[l]) * dudx[l];
+    return s + c;
+}
+
 /* Evaluate ybar (and optionally grad, row-major [n][d]) at n points. */
-void or_eval(int d, int nu, int64_t nrep, const int32_t *reps, const double *alpha_row, int64_t n,
+void or_eval(int d, int nu, int basis, int64_t nrep, const int32_t *reps, const double *alpha_row, int64_t n,
              const double *x, double *y, double *grad)
 {
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t p = 0; p < n; ++p)
-        y[p] = or_expansion(d, nu, nrep, reps, alpha_row, x + p * d, grad ? grad + p * d : NULL);
+        y[p] = or_expansion(d, nu, basis, nrep, reps, alpha_row, x + p * d, grad ? grad + p * d : NULL);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -368,7 +437,7 @@ double or_msol_u(const or_problem *P, double t, const double *x)
 {
     double th = P->sol_p;
     for (int l = 0; l < P->d; ++l) th += P->sol_w[l] * x[l];
-    return P->sol_A * exp(-P->sol_c * (or_T(P) - t)) * cos(th);
+    return P->sol_B + P->sol_A * exp(-P->sol_c * (or_T(P) - t)) * cos(th);
 }
 
 /* gradient of u in x */
@@ -390,10 +459,16 @@ static void or_sigmaT(const or_problem *P, const double *v, double *z)
     }
 }
 
-/* nonlinear part of the driver, f = f_nl(y, z) + h(t, x) */
-static double or_fnl(const or_problem *P, double y, const double *z)
+/* nonlinear part of the driver, f = f_nl(t, x, y, z) + h(t, x); the Sec. 5
+ * benchmark's f_nl = min(1, (y - u(t,x))^2) is the only one that reads (t, x) */
+static double or_fnl(const or_problem *P, double t, const double *x, double y, const double *z)
 {
     switch (P->driver) {
+    case 4: {
+        double e = y - or_msol_u(P, t, x);
+        double e2 = e * e;
+        return e2 < 1.0 ? e2 : 1.0;
+    }
     case 0: return 0.0;
     case 1: return P->f_a * sin(y);
     case 2: return y - y * y * y;
@@ -412,17 +487,18 @@ double or_msol_h(const or_problem *P, double t, const double *x)
     double u = or_msol_u(P, t, x);
     double gu[OR_MAXD], z[OR_MAXD];
     or_msol_grad(P, t, x, gu);
-    double dt_u = P->sol_c * u;
+    /* the offset B drops out of every derivative */
+    double dt_u = P->sol_c * (u - P->sol_B);
     double b_grad = 0.0;
     for (int l = 0; l < d; ++l) b_grad += (P->b0[l] + P->b1[l] * x[l]) * gu[l];
-    /* hess u = -u w w^T, so 1/2 tr(sigma sigma^T hess u) = -1/2 u |sigma^T w|^2 */
+    /* hess u = -(u - B) w w^T, so 1/2 tr(sigma sigma^T hess u) = -1/2 (u - B) |sigma^T w|^2 */
     double sw[OR_MAXD];
     or_sigmaT(P, P->sol_w, sw);
     double sw2 = 0.0;
     for (int k = 0; k < P->nbm; ++k) sw2 += sw[k] * sw[k];
-    double diff = -0.5 * u * sw2;
+    double diff = -0.5 * (u - P->sol_B) * sw2;
     or_sigmaT(P, gu, z);
-    return -(dt_u + b_grad + diff) - or_fnl(P, u, z);
+    return -(dt_u + b_grad + diff) - or_fnl(P, t, x, u, z);
 }
 
 /* terminal condition g = u(T, .) and its gradient */
@@ -457,7 +533,7 @@ double or_eval_y(const or_problem *P, int64_t nrep, const int32_t *reps, const d
                  const double *x, double *grad)
 {
     int d = P->d;
-    double yb = or_expansion(d, P->nu, nrep, reps, alpha_row, x, grad);
+    double yb = or_expansion(d, P->nu, P->basis, nrep, reps, alpha_row, x, grad);
     if (P->damping_q == 0.0) return yb;
     double r2 = 0.0;
     for (int l = 0; l < d; ++l) r2 += x[l] * x[l];
@@ -466,7 +542,7 @@ double or_eval_y(const or_problem *P, int64_t nrep, const int32_t *reps, const d
         for (int l = 0; l < d; ++l) grad[l] = D * grad[l] + yb * P->damping_q * D * x[l] / (1.0 + r2);
     return yb * D;
 }
-static int64_t or_nfuncs(int64_t nrep) { return 2 * nrep - 1; }
+
 
 /* Start point X_i^i of path m: d uniforms of stream 0 through F^{-1}. */
 static void or_start_point(const or_problem *P, uint64_t seed, int32_t i, uint64_t m, double *x)
@@ -537,7 +613,7 @@ static double or_path_response_ex(const or_problem *P, int64_t nrep, const int32
                                   const double *const *nets, const double *mu, const double *sd)
 {
     int d = P->d, nbm = P->nbm, N = P->N;
-    int64_t nf = or_nfuncs(nrep);
+    int64_t nf = or_nfuncs_of(P->basis, nrep);
     double x[OR_MAXD], xn[OR_MAXD], dw[OR_MAXD], grad[OR_MAXD], z[OR_MAXD];
     or_start_point(P, seed, i, m, x);
     double S = 0.0;
@@ -565,7 +641,7 @@ static double or_path_response_ex(const or_problem *P, int64_t nrep, const int32
         }
         y = or_trunc(P, y);
         if (need_z) or_sigmaT(P, grad, z);
-        S += (or_fnl(P, y, z) + or_msol_h(P, P->t[j], x)) * dt;
+        S += (or_fnl(P, P->t[j], x, y, z) + or_msol_h(P, P->t[j], x)) * dt;
         for (int l = 0; l < d; ++l) x[l] = xn[l];
     }
     S += or_g(P, x);
@@ -580,20 +656,22 @@ static double or_path_response_ex(const or_problem *P, int64_t nrep, const int32
 
 /* Projection (eq (Aqi:bar:M)): alpha_k = (1/n) sum_p s_p phi_k(x_p), and the
  * scale A_k = (1/n) sum_p |s_p phi_k(x_p)|.  x is row-major [n][d]. */
-void or_project(int d, int nu, int64_t nrep, const int32_t *reps, int64_t n, const double *x,
+void or_project(int d, int nu, int basis, int64_t nrep, const int32_t *reps, int64_t n, const double *x,
                 const double *s, double *alpha, double *absum)
 {
-    int64_t nf = or_nfuncs(nrep);
+    int64_t nf = or_nfuncs_of(basis, nrep);
     double *u = (double *)malloc(sizeof(double) * (size_t)(n * d));
     for (int64_t p = 0; p < n * d; ++p) u[p] = or_law_cdf(nu, x[p]);
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t f = 0; f < nf; ++f) {
-        int64_t r = (f + 1) / 2;
+        int64_t r = basis == 1 ? f : (f + 1) / 2;
         const int32_t *k = reps + r * d;
         double sum = 0.0, comp = 0.0, asum = 0.0;
         for (int64_t p = 0; p < n; ++p) {
             double phi;
-            if (f == 0) {
+            if (basis == 1) {
+                phi = or_cos_value(k, u + p * d, d);
+            } else if (f == 0) {
                 phi = 1.0;
             } else {
                 double th = 2.0 * M_PI * or_phase(k, u + p * d, d);
@@ -624,7 +702,7 @@ int or_backward_step(const or_problem *P, int64_t nrep, const int32_t *reps, int
 {
     if (i < 0 || i >= P->N || M <= 0) return -1;
     int d = P->d;
-    int64_t nf = or_nfuncs(nrep);
+    int64_t nf = or_nfuncs_of(P->basis, nrep);
     double *x = (double *)malloc(sizeof(double) * (size_t)(M * d));
     double *S = (double *)malloc(sizeof(double) * (size_t)M);
 #pragma omp parallel for schedule(dynamic, 64)
@@ -632,7 +710,7 @@ int or_backward_step(const or_problem *P, int64_t nrep, const int32_t *reps, int
         or_start_point(P, seed, i, (uint64_t)m, x + m * d);
         S[m] = or_path_response(P, nrep, reps, i, seed, (uint64_t)m, alpha);
     }
-    or_project(d, P->nu, nrep, reps, M, x, S, alpha + (int64_t)i * nf, absum);
+    or_project(d, P->nu, P->basis, nrep, reps, M, x, S, alpha + (int64_t)i * nf, absum);
     if (x_out) memcpy(x_out, x, sizeof(double) * (size_t)(M * d));
     if (s_out) memcpy(s_out, S, sizeof(double) * (size_t)M);
     free(x);
@@ -650,7 +728,7 @@ int or_backward_step_learned(const or_problem *P, int64_t nrep, const int32_t *r
 {
     if (i < 0 || i >= P->N || M <= 0) return -1;
     int d = P->d;
-    int64_t nf = or_nfuncs(nrep);
+    int64_t nf = or_nfuncs_of(P->basis, nrep);
     double *x = (double *)malloc(sizeof(double) * (size_t)(M * d));
     double *S = (double *)malloc(sizeof(double) * (size_t)M);
 #pragma omp parallel for schedule(dynamic, 16)
@@ -658,7 +736,7 @@ int or_backward_step_learned(const or_problem *P, int64_t nrep, const int32_t *r
         or_start_point(P, seed, i, (uint64_t)m, x + m * d);
         S[m] = or_path_response_ex(P, nrep, reps, i, seed, (uint64_t)m, alpha, nets, mu, sd);
     }
-    or_project(d, P->nu, nrep, reps, M, x, S, alpha + (int64_t)i * nf, absum);
+    or_project(d, P->nu, P->basis, nrep, reps, M, x, S, alpha + (int64_t)i * nf, absum);
     free(x);
     free(S);
     return 0;
@@ -693,13 +771,13 @@ void or_errors(const or_problem *P, int64_t nrep, const int32_t *reps, const dou
                uint64_t seed, int64_t n, double *out)
 {
     int d = P->d, N = P->N;
-    int64_t nf = or_nfuncs(nrep);
+    int64_t nf = or_nfuncs_of(P->basis, nrep);
     double worst = 0.0, total = 0.0, e0 = 0.0, u0 = 0.0;
     double *x = (double *)malloc(sizeof(double) * (size_t)(n * d));
     double *y = (double *)malloc(sizeof(double) * (size_t)n);
     for (int i = 0; i < N; ++i) {
         or_sample_points(d, P->nu, seed, 1u, i, 0, n, x);
-        or_eval(d, P->nu, nrep, reps, alpha + (int64_t)i * nf, n, x, y, NULL);
+        or_eval(d, P->nu, P->basis, nrep, reps, alpha + (int64_t)i * nf, n, x, y, NULL);
         for (int64_t p = 0; p < n; ++p) y[p] *= or_damping(P, x + p * d);
         double se = 0.0, su = 0.0;
         for (int64_t p = 0; p < n; ++p) {

@@ -720,3 +720,166 @@ def test_damped_factor_on_the_driver_input_lemma31():
     exp, wrong = proj(target), proj(planted)
     assert np.all(np.abs(est - exp) <= 5 * sd + 1e-12), np.max(np.abs(est - exp) / sd)
     assert abs(est[0] - wrong[0]) > 50 * sd[0]
+
+
+# ---------------------------------------------------------------------------
+# the paper's own variant: cosine basis over N^d (Lemma 2.1, eq
+# (phi:dim:d)), the sets Gamma_F / Gamma_H / Gamma_T (Sec. 2.3.3) and the
+# benchmark of Sec. 5 (eq (pde2OnlyY))
+# ---------------------------------------------------------------------------
+
+def _student2_icdf(u):
+    return (u - 0.5) / np.sqrt(u * (1.0 - u))
+
+
+@pytest.mark.parametrize("d,kind,level", [(1, "tensor", 6), (2, "hc_max", 5), (2, "total", 4)])
+def test_cosine_basis_orthonormal_in_L2_nu(d, kind, level):
+    """Lemma 2.1: the tensor cosine functions composed with the Student
+    (mu = 2) CDF are orthonormal in L2(nu); Gauss-Legendre quadrature in
+    u = F(x) (the change of variable of the lemma's proof) with enough nodes
+    to integrate products of cos(m pi u) exactly, against the oracle's own
+    evaluation at x = F^{-1}(u)."""
+    reps = O.enumerate_set(d, kind, level, nonneg=True, reps_only=False)
+    g, wg = np.polynomial.legendre.leggauss(64)
+    g, wg = 0.5 * (g + 1.0), 0.5 * wg
+    U = np.stack(np.meshgrid(*([g] * d), indexing="ij"), -1).reshape(-1, d)
+    Wt = np.prod(np.stack(np.meshgrid(*([wg] * d), indexing="ij"), -1).reshape(-1, d), axis=1)
+    Phi = np.array([O.basis_values(reps, _student2_icdf(u), law="student2", basis="cosine") for u in U])
+    G = Phi.T @ (Phi * Wt[:, None])
+    assert np.abs(G - np.eye(reps.shape[0])).max() < 1e-12
+
+
+def test_cosine_basis_values_are_tensor_cosines():
+    """phi_k(x) = prod_l sqrt2^{[k_l > 0]} cos(k_l pi F(x_l)), retyped with
+    numpy against the oracle at random points, and phi_0 = 1."""
+    reps = O.enumerate_set(3, "hc_max", 6, nonneg=True, reps_only=False)
+    rng = np.random.default_rng(3)
+    for x in rng.standard_normal((4, 3)) * 2:
+        u = 0.5 * (1.0 + x / np.sqrt(1.0 + x * x))
+        want = np.prod(np.where(reps > 0, math.sqrt(2.0), 1.0) * np.cos(reps * np.pi * u), axis=1)
+        got = O.basis_values(reps, x, law="student2", basis="cosine")
+        assert np.allclose(got, want, rtol=1e-13, atol=1e-14)
+        assert got[0] == 1.0
+
+
+@pytest.mark.parametrize("d,K,n", [(1, 9, 12), (2, 4, 7)])
+def test_cosine_projection_recovers_and_matches_scipy_dct(d, K, n):
+    """On the midpoint grid u_j = (j + 1/2)/n, n > K, the cosines are discretely
+    orthonormal: projecting s = sum c_k phi_k recovers c exactly, and the
+    projection of arbitrary samples is the type-II DCT of the grid values."""
+    from scipy import fft
+    reps = O.enumerate_set(d, "tensor", K, nonneg=True, reps_only=False)
+    c = W.synthetic_alpha(reps.shape[0], 1, seed=5)[0]
+    U = _tensor_grid(d, n)
+    X = _student2_icdf(U)
+    s = np.array([O.basis_values(reps, x, law="student2", basis="cosine") @ c for x in X])
+    a = O.project(reps, X, s, law="student2", basis="cosine")
+    assert np.abs(a - c).max() < 1e-13
+    r = np.random.default_rng(2).standard_normal(n ** d)
+    a = O.project(reps, X, r, law="student2", basis="cosine")
+    D = fft.dctn(r.reshape([n] * d), type=2) / (2.0 ** d * n ** d)
+    for j, k in enumerate(reps):
+        # scipy's type-II DCT is 2 sum_j r_j cos(pi k (2j+1) / (2n)) along each axis
+        scale = np.prod(np.where(k > 0, math.sqrt(2.0), 1.0))
+        assert abs(a[j] - scale * D[tuple(k)]) < 1e-13
+
+
+def test_cosine_expansion_gradient_by_finite_differences():
+    reps = O.enumerate_set(3, "total", 5, nonneg=True, reps_only=False)
+    alpha = W.synthetic_alpha(reps.shape[0], 1, seed=8)[0]
+    x = np.random.default_rng(6).standard_normal((5, 3))
+    y, g = O.evaluate(reps, alpha, x, grad=True, law="student2", basis="cosine")
+    h = 1e-5
+    for l in range(3):
+        e = np.eye(3)[l] * h
+        fd = (O.evaluate(reps, alpha, x + e, law="student2", basis="cosine")
+              - O.evaluate(reps, alpha, x - e, law="student2", basis="cosine")) / (2 * h)
+        assert np.abs(fd - g[:, l]).max() < 1e-7 * max(1.0, np.abs(g).max())
+
+
+@pytest.mark.parametrize("d", [1, 3])
+def test_paper_benchmark_solution_solves_its_pde(d):
+    """Sec. 5: u = 1 + kappa + sin(lambda sum x) e^{lambda^2 d (t-T)/2} solves
+    d_t u + Laplace(u)/2 + f(t, x, u) = 0 with f = min(1, (y - u)^2), so the
+    manufactured source of the paper's problem (dX = dW) vanishes; and the
+    oracle's u is that closed form (retyped) and its g = u(T, .)."""
+    w = W.paper_benchmark(d, 10, "hc_max", 4, 10)
+    lam, kappa = 1.0 / math.sqrt(d), 0.6
+    rng = np.random.default_rng(1)
+    for t in (0.0, 0.4, 1.0):
+        for x in rng.standard_normal((3, d)):
+            want = 1.0 + kappa + math.sin(lam * x.sum()) * math.exp(lam * lam * d * (t - 1.0) / 2.0)
+            assert abs(O.msol_u(w, t, x)[0] - want) < 1e-14
+            assert abs(O.msol_h(w, t, x)[0]) < 1e-14
+            u = lambda tt, xx: O.msol_u(w, tt, xx)[0]
+            h = 1e-4
+            ut = (u(t + h, x) - u(t - h, x)) / (2 * h)
+            lap = sum((u(t, x + 1e-3 * e) - 2 * u(t, x) + u(t, x - 1e-3 * e)) / 1e-6 for e in np.eye(d))
+            assert abs(ut + 0.5 * lap) < 1e-5
+    # with another diffusion the source is no longer zero and still makes u a solution
+    w2 = w.with_(sigma=[[0.7 if a == b else 0.0 for b in range(d)] for a in range(d)])
+    x = rng.standard_normal(d)
+    u = lambda tt, xx: O.msol_u(w2, tt, xx)[0]
+    ut = (u(0.3 + 1e-4, x) - u(0.3 - 1e-4, x)) / 2e-4
+    lap = sum((u(0.3, x + 1e-3 * e) - 2 * u(0.3, x) + u(0.3, x - 1e-3 * e)) / 1e-6 for e in np.eye(d))
+    assert abs(ut + 0.5 * 0.49 * lap + O.msol_h(w2, 0.3, x)[0]) < 1e-5
+
+
+def test_paper_d1_accuracy_table_first_row():
+    """Table d1_accuracy, first row: d = 1, Delta = 0.05, K = 100, M = 2 10^4,
+    q = 0, 50 independent runs; the paper prints the 99 % confidence interval
+    [1.578, 1.667] for ybar_0(0), with u(0, 0) = 1.6.  Fifty runs of the
+    oracle (seeds 0..49): the 99 % interval of their mean (Student t, 49
+    degrees of freedom) must contain 1.6 and overlap the printed one, and
+    the run-to-run spread must match the printed interval's width (its
+    standard deviation, 0.089 sqrt(50) / (2 * 2.68) = 0.117, within a factor 1.5)."""
+    w0 = W.PAPER_D1
+    reps = O.reps_for(w0)
+    assert reps.shape[0] == 101 and w0.N == 20 and w0.M == 20_000
+    assert abs(O.msol_u(w0, 0.0, [0.0])[0] - 1.6) < 1e-15
+    ys = []
+    for s in range(50):
+        a = O.solve(w0.with_(seed=s), reps)
+        ys.append(O.evaluate(reps, a[0], np.zeros((1, 1)), law="student2", basis="cosine")[0])
+    ys = np.array(ys)
+    m, sd = ys.mean(), ys.std(ddof=1)
+    half = 2.68 * sd / math.sqrt(50)
+    lo, hi = m - half, m + half
+    assert lo <= 1.6 <= hi, (lo, hi)
+    assert lo <= 1.667 and hi >= 1.578, (lo, hi)
+    sd_paper = 0.089 * math.sqrt(50) / (2 * 2.68)
+    assert sd_paper / 1.5 <= sd <= 1.5 * sd_paper, sd
+
+
+def test_paper_driver_lemma31_one_step():
+    """The benchmark driver f = min(1, (y - u(t, x))^2) on one Euler step
+    (d = 1, N = 1, dX = dW, amplitude 3 so that the square often exceeds 1
+    and the min clips it): Lemma 3.1 gives E alpha_0,k = E[S phi_k(X_0)] with
+    S = f(t_0, X_0, g(X_1)) dt + g(X_1), X_1 = X_0 + sqrt(dt) Z; the double
+    integral over X_0 ~ nu (Gauss-Legendre in u = F(x)) and Z (Gauss-Hermite)
+    must hold every Monte-Carlo coefficient within 5 standard deviations,
+    and the same without the min must not."""
+    w = W.paper_benchmark(1, 1, "tensor", 6, 200_000).with_(sol_A=3.0)
+    reps = O.reps_for(w)
+    a, absum, x0, s = O.backward_step(w, reps, 0, w.M, w.seed, np.zeros((1, reps.shape[0])),
+                                      want_x=True, want_s=True)
+    phi = np.array([O.basis_values(reps, x, law="student2", basis="cosine") for x in x0])
+    sd = (s[:, None] * phi).std(axis=0) / math.sqrt(w.M)
+    gl, gw = np.polynomial.legendre.leggauss(400)
+    u0, wu = 0.5 * (gl + 1.0), 0.5 * gw
+    xs = _student2_icdf(u0)
+    gh, ghw = np.polynomial.hermite_e.hermegauss(80)
+    ghw = ghw / math.sqrt(2 * math.pi)
+    dt, lam, c = 1.0, 1.0, 0.5
+    u_t0 = 1.6 + 3.0 * np.sin(lam * xs) * math.exp(-c)
+    def g(x):
+        return 1.6 + 3.0 * np.sin(lam * x)
+    x1 = xs[:, None] + math.sqrt(dt) * gh[None, :]
+    sq = (g(x1) - u_t0[:, None]) ** 2
+    for clip, must_pass in ((True, True), (False, False)):
+        f = np.minimum(1.0, sq) if clip else sq
+        ES = ((f * dt + g(x1)) * ghw[None, :]).sum(axis=1)              # E[S | X_0]
+        cos_k = np.array([np.where(k > 0, math.sqrt(2.0), 1.0)[0] * np.cos(k[0] * math.pi * u0) for k in reps])
+        want = (cos_k * (ES * wu)[None, :]).sum(axis=1)
+        ok = np.all(np.abs(a - want) <= 5 * sd)
+        assert ok == must_pass, (clip, np.max(np.abs(a - want) / sd))

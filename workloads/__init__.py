@@ -27,8 +27,9 @@ from typing import List
 
 import numpy as np
 
-SET_KINDS = {"tensor": 0, "hc_max": 1, "hc_1p": 2}
-DRIVERS = {"linear": 0, "sin": 1, "allen_cahn": 2, "zrat": 3}
+SET_KINDS = {"tensor": 0, "hc_max": 1, "hc_1p": 2, "total": 3}
+DRIVERS = {"linear": 0, "sin": 1, "allen_cahn": 2, "zrat": 3, "paper": 4}
+BASES = {"fourier": 0, "cosine": 1}
 LAWS = {"logistic": 0, "student2": 1, "cauchy": 2}
 
 
@@ -54,6 +55,8 @@ class Workload:
     seed: int = 0
     law: str = "logistic"
     damping_q: float = 0.0
+    basis: str = "fourier"      # "cosine": the paper's cosine basis over N^d
+    sol_B: float = 0.0          # constant offset of the manufactured solution
     notes: str = ""
 
     @property
@@ -106,7 +109,26 @@ D16_HC1P32 = Workload(
     b1=[0.0] * 16, set_kind="hc_1p", level=32, M=1 << 22, driver="allen_cahn", f_a=0.0,
     sol_A=1.0, sol_c=1.0, sol_p=0.0, sol_w=_first_two(16), clamp=2.0)
 
-ALL = {w.name: w for w in (D2_TENSOR4, D6_HCMAX16, D10_HC1P32_ZRAT, D16_HC1P32)}
+# The benchmark of the paper's Sec. 5 (eq (pde2OnlyY)), d = 1: dX = dW,
+# f = min(1, (y - u)^2), g = u(T, .) with u = 1 + kappa + sin(lambda x)
+# e^{lambda^2 d (t-T)/2}, kappa = 0.6, lambda = 1/sqrt(d) = 1, T = 1, the
+# Student (mu = 2) sampling law and the cosine basis of Gamma_F(K), K = 100
+# (101 functions), Delta = 0.05 (N = 20), M = 2 10^4, q = 0: the first row of
+# the paper's d = 1 accuracy table (u(0, 0) = 1.6).  sin(theta) is written as
+# cos(theta - pi/2).
+def paper_benchmark(d: int, N: int, set_kind: str, level: int, M: int, kappa: float = 0.6,
+                    seed: int = 0) -> Workload:
+    lam = 1.0 / math.sqrt(d)
+    return Workload(
+        name=f"paper-d{d}-{set_kind}{level}", d=d, N=N, T=1.0, sigma=_diag(d, 1.0), b0=[0.0] * d,
+        b1=[0.0] * d, set_kind=set_kind, level=level, M=M, driver="paper", f_a=0.0,
+        sol_A=1.0, sol_c=0.5 * lam * lam * d, sol_p=-0.5 * math.pi, sol_w=[lam] * d, seed=seed,
+        law="student2", basis="cosine", sol_B=1.0 + kappa)
+
+
+PAPER_D1 = paper_benchmark(1, 20, "tensor", 100, 20_000)
+
+ALL = {w.name: w for w in (D2_TENSOR4, D6_HCMAX16, D10_HC1P32_ZRAT, D16_HC1P32, PAPER_D1)}
 
 
 def batched_instances(n: int = 256, seed: int = 4):
