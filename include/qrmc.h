@@ -91,7 +91,8 @@ const char *qr_version(void);
 typedef enum {
     QR_SET_TENSOR = 0, /* {k in Z^d : max_l |k_l| <= level}  (Gamma_F)        */
     QR_SET_HC_MAX = 1, /* {k in Z^d : prod_l max(1,|k_l|) <= level} (Gamma_H) */
-    QR_SET_HC_1P = 2   /* {k in Z^d : prod_l (1+|k_l|) <= level}              */
+    QR_SET_HC_1P = 2,  /* {k in Z^d : prod_l (1+|k_l|) <= level}              */
+    QR_SET_TOTAL = 3   /* {k in Z^d : sum_l |k_l| <= level}   (Gamma_T)       */
 } qr_set_kind;
 
 typedef struct qr_basis qr_basis; /* opaque, library-owned */
@@ -111,8 +112,9 @@ typedef enum {
 } qr_law;
 
 /* Build the index set of kind `kind` and level `level` in dimension d
- * (1 <= d <= QR_MAX_D; level >= 0 for the tensor set, level >= 1 for the
- * hyperbolic crosses, whose sets are empty below 1) and its basis metadata.
+ * (1 <= d <= QR_MAX_D; level >= 0 for the tensor and total-degree sets,
+ * level >= 1 for the hyperbolic crosses, whose sets are empty below 1) and
+ * its basis metadata.
  * Host only; no device is touched.  *out receives a handle to free with
  * qr_basis_free.  QR_ERANGE if the set has more than 2^31 representatives. */
 qr_status qr_build_basis(int32_t d, int32_t kind, int32_t level, qr_basis **out);
@@ -127,13 +129,41 @@ qr_status qr_build_basis_law(int32_t d, int32_t kind, int32_t level, int32_t law
 /* The sampling law of a basis (qr_law) into *law. */
 qr_status qr_basis_law(const qr_basis *b, int32_t *law);
 
+/* Family of basis functions of a qr_basis. */
+typedef enum {
+    QR_BASIS_FOURIER = 0, /* the Fourier functions above, over Z^d          */
+    QR_BASIS_COSINE = 1   /* the paper's cosine functions over N^d (below)  */
+} qr_basis_family;
+
+/* The paper's own basis (Sec. 2.2, Lemma 2.1, eq (nu_basis_functions) with
+ * the cosine system of L2([0,1]), and eq (phi:dim:d)): for k in N^d,
+ *   phi_k(x) = prod_l c_{k_l}(F(x_l)),  c_0 = 1,  c_m(u) = sqrt2 cos(m pi u),
+ * orthonormal in L2(nu), over the index set {k in N^d : k in Gamma} with Gamma
+ * of kind `kind` (Gamma_F, Gamma_H, the (1+|k|) cross or Gamma_T; Sec. 2.3.3)
+ * and level `level`, limits as in qr_build_basis_law.  A coefficient row of
+ * this basis has n_funcs = #(Gamma over N^d) entries, entry c multiplying
+ * phi_k for the c-th vector k in lexicographic order (qr_basis_indices).
+ * Every entry point that takes a basis accepts this one except the batched
+ * and learned forms (QR_ENOTSUP).  The kernels evaluate and project it
+ * through the identity, for a vector k with n non-zero coordinates,
+ *   phi_k(x) = 2^{1 - n/2} sum cos(pi k'.F(x))   (n >= 1),
+ * the sum over the 2^{n-1} vectors k' of Z^d with |k'_l| = k_l and first
+ * non-zero coordinate positive: the Fourier walk over the Z^d set of the same
+ * kind and level at half the frequency. */
+qr_status qr_build_basis_cos(int32_t d, int32_t kind, int32_t level, int32_t law, qr_basis **out);
+
+/* The family of a basis (qr_basis_family) into *family. */
+qr_status qr_basis_family_of(const qr_basis *b, int32_t *family);
+
 /* n_funcs = |Gamma| (real basis functions), n_reps = representatives
- * (n_funcs = 2 n_reps - 1), max_nnz = largest number of non-zero
- * coordinates of a k in the set.  Any output pointer may be NULL. */
+ * (n_funcs = 2 n_reps - 1; for a cosine basis n_reps = n_funcs, the vectors
+ * of N^d), max_nnz = largest number of non-zero coordinates of a k in the
+ * set.  Any output pointer may be NULL. */
 qr_status qr_basis_info(const qr_basis *b, int64_t *n_funcs, int64_t *n_reps, int32_t *max_nnz);
 
 /* Copy the representatives in canonical (lexicographic) order into
- * reps_out, host memory of n_reps * d int32 (row-major [n_reps][d]). */
+ * reps_out, host memory of n_reps * d int32 (row-major [n_reps][d]); for a
+ * cosine basis the vectors of N^d in the order of its coefficient rows. */
 qr_status qr_basis_indices(const qr_basis *b, int32_t *reps_out);
 
 /* Release a basis (and any device copies it holds). NULL is accepted. */
@@ -146,12 +176,13 @@ typedef enum {
     QR_F_LINEAR = 0,     /* f = h(t,x)                                     */
     QR_F_SIN = 1,        /* f = a sin(y) + h(t,x)                          */
     QR_F_ALLEN_CAHN = 2, /* f = y - y^3 + h(t,x)                           */
-    QR_F_ZRAT = 3        /* f = a |z|^2/(1+|z|^2) + y/(1+y^2) + h(t,x)     */
+    QR_F_ZRAT = 3,       /* f = a |z|^2/(1+|z|^2) + y/(1+y^2) + h(t,x)     */
+    QR_F_PAPER = 4       /* f = min(1, (y - u(t,x))^2) + h(t,x)            */
 } qr_driver_kind;
 
 /*
  * Semi-linear problem with a manufactured closed-form solution
- *   u(t,x) = A exp(-c (T - t)) cos(w.x + p),   g = u(T, .),
+ *   u(t,x) = B + A exp(-c (T - t)) cos(w.x + p),   g = u(T, .),
  * where h is the source that makes u solve eq (pde) for the chosen driver:
  *   h = -(d_t u + b.grad u + 1/2 tr(sigma sigma^T hess u)) - f_nl(u, sigma^T grad u).
  * Drift b(t,x)_l = b0_l + b1_l x_l, constant diffusion sigma (d x nbm,
@@ -162,7 +193,13 @@ typedef enum {
  * (Algorithm 1): along the paths the expansion is multiplied back by
  * (1+|x_{j+1}|^2)^{q/2} before T_L and the driver (its x-gradient by the
  * product rule), and each response is divided by (1+|X_i|^2)^{q/2};
- * qr_eval returns the expansion itself.  Only the plain FP64 entry points
+ * qr_eval returns the expansion itself.
+ * QR_F_PAPER is the driver of the paper's Sec. 5 benchmark, eq (pde2OnlyY):
+ * with B = 1 + kappa, A = 1, c = lambda^2 d / 2, w = (lambda, ..., lambda)
+ * and p = -pi/2, u = 1 + kappa + sin(lambda sum_l x_l) e^{lambda^2 d (t - T)/2}
+ * solves the PDE with b = 0, sigma = I, h = 0 (the quadratic term vanishes on
+ * u itself, and h computed from the formula above is zero up to rounding).
+ * The paths read u(t_j, X_j) at the start of each step.  Only the plain FP64 entry points
  * (qr_backward_step, qr_solve, qr_path_responses) take q > 0; the
  * reduced-precision, batched and learned forms return QR_ENOTSUP.
  * All arrays are inline; entries beyond d / nbm / N are ignored.
@@ -181,6 +218,7 @@ typedef struct {
     double sol_A, sol_c, sol_p;
     double sol_w[QR_MAX_D];
     double damping_q;          /* damping exponent q >= 0 (0: none)          */
+    double sol_B;              /* constant offset B of u (0 for the family)  */
 } qr_problem;
 
 /* ---------------------------------------------------------------------- */

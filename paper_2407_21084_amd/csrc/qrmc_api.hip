@@ -80,6 +80,25 @@ struct qr_basis {
     // projection tasks per template (host counts, device lists)
     int32_t fac_ntasks[kFacTemplates] = {};
     FacTask *d_fac_tasks[kFacTemplates] = {};
+    // Cosine basis over N^d (qr_build_basis_cos).  Everything above describes
+    // its carrier, the Z^d basis of the same kind and level walked at half
+    // frequency, whose coefficient rows ("carrier rows", Fourier canonical
+    // layout) the kernels use; the caller's rows hold one coefficient per
+    // vector of N^d.
+    bool cos = false;
+    int64_t ncos = 0;
+    std::vector<int32_t> cvec;        // [ncos][d] vectors of N^d, lexicographic
+    std::vector<int32_t> cos_of_rep;  // carrier representative (canonical) -> vector of N^d
+    std::vector<double> rep_scale;    // 2^{(1-n)/2}, n = non-zero coordinates (1 for k = 0)
+    std::vector<int32_t> fold_off;    // [ncos + 1]: the representatives of vector c are
+    std::vector<int32_t> fold_idx;    //   fold_idx[fold_off[c] .. fold_off[c+1])
+    int32_t *d_cos_of_rep = nullptr, *d_fold_off = nullptr, *d_fold_idx = nullptr;
+    double *d_rep_scale = nullptr;
+    // coefficients per row: the caller's layout, and the carrier's
+    int64_t nf() const { return cos ? ncos : 2 * nrep - 1; }
+    int64_t nfc() const { return 2 * nrep - 1; }
+    // law code of the kernels: the law, plus the half-frequency flag
+    int32_t code() const { return law | (cos ? kLawHalf : 0); }
 };
 
 namespace {
@@ -188,10 +207,10 @@ extern "C" qr_status qr_build_basis_law(int32_t d, int32_t kind, int32_t level, 
     if (!out) return fail(QR_EINVAL, "qr_build_basis: out is NULL");
     *out = nullptr;
     if (d < 1 || d > QR_MAX_D) return fail(QR_EINVAL, "qr_build_basis: d=%d outside [1,%d]", d, QR_MAX_D);
-    if (kind < QR_SET_TENSOR || kind > QR_SET_HC_1P)
+    if (kind < QR_SET_TENSOR || kind > QR_SET_TOTAL)
         return fail(QR_EINVAL, "qr_build_basis: unknown set kind %d", kind);
     if (level < 0 || level > (1 << 20)) return fail(QR_EINVAL, "qr_build_basis: level=%d out of range", level);
-    if (level < 1 && kind != QR_SET_TENSOR)
+    if (level < 1 && (kind == QR_SET_HC_MAX || kind == QR_SET_HC_1P))
         return fail(QR_EINVAL, "qr_build_basis: a hyperbolic cross of level %d is empty", level);
     if (law < QR_LAW_LOGISTIC || law > QR_LAW_CAUCHY)
         return fail(QR_EINVAL, "qr_build_basis: unknown sampling law %d", law);
@@ -239,24 +258,91 @@ extern "C" qr_status qr_build_basis_law(int32_t d, int32_t kind, int32_t level, 
     return QR_OK;
 }
 
+// The cosine basis over N^d: its carrier (the Z^d set of the same kind and
+// level, whose set rules depend on |k_l| only, so that {|k'| : k' in it} is
+// exactly the N^d set) and the maps between the two coefficient layouts.
+extern "C" qr_status qr_build_basis_cos(int32_t d, int32_t kind, int32_t level, int32_t law, qr_basis **out) {
+    qr_status st = qr_build_basis_law(d, kind, level, law, out);
+    if (st) return st;
+    qr_basis *b = *out;
+    try {
+        const int64_t R = b->nrep;
+        const int32_t *K = b->canon.data();
+        std::vector<int32_t> absv((size_t)R * d);
+        for (int64_t i = 0; i < R * d; ++i) absv[i] = std::abs(K[i]);
+        std::vector<int64_t> order(R);
+        for (int64_t r = 0; r < R; ++r) order[r] = r;
+        const int32_t *A = absv.data();
+        auto less = [&](int64_t a, int64_t c) {
+            return std::lexicographical_compare(A + a * d, A + a * d + d, A + c * d, A + c * d + d);
+        };
+        std::stable_sort(order.begin(), order.end(), less);
+        b->cos_of_rep.assign(R, -1);
+        b->rep_scale.assign(R, 1.0);
+        b->fold_off.clear();
+        b->fold_idx.clear();
+        b->cvec.clear();
+        for (int64_t q = 0; q < R; ++q) {
+            const int64_t r = order[q];
+            if (q == 0 || less(order[q - 1], r)) {
+                b->fold_off.push_back((int32_t)b->fold_idx.size());
+                b->cvec.insert(b->cvec.end(), A + r * d, A + r * d + d);
+            }
+            int n = 0;
+            for (int l = 0; l < d; ++l) n += A[r * d + l] != 0;
+            b->cos_of_rep[r] = (int32_t)(b->fold_off.size() - 1);
+            // 2^{(1-n)/2}: exact power of two for odd n, sqrt2 times one for even n
+            b->rep_scale[r] = n == 0 ? 1.0 : ((n & 1) ? std::ldexp(1.0, (1 - n) / 2) : std::ldexp(M_SQRT2, -n / 2));
+            b->fold_idx.push_back((int32_t)r);
+        }
+        b->ncos = (int64_t)b->fold_off.size();
+        b->fold_off.push_back((int32_t)b->fold_idx.size());
+        // every vector of N^d in the set has 2^{n-1} representatives (1 for k = 0)
+        for (int64_t c = 0; c < b->ncos; ++c) {
+            int n = 0;
+            for (int l = 0; l < d; ++l) n += b->cvec[c * d + l] != 0;
+            const int64_t want = n == 0 ? 1 : ((int64_t)1 << (n - 1));
+            if (b->fold_off[c + 1] - b->fold_off[c] != want) {
+                qr_basis_free(b);
+                *out = nullptr;
+                return fail(QR_ENUMERIC, "qr_build_basis_cos: vector %lld has %d representatives, expected %lld",
+                            (long long)c, b->fold_off[c + 1] - b->fold_off[c], (long long)want);
+            }
+        }
+    } catch (const std::bad_alloc &) {
+        qr_basis_free(b);
+        *out = nullptr;
+        return fail(QR_ENOMEM, "qr_build_basis_cos: out of host memory");
+    }
+    b->cos = true;
+    return QR_OK;
+}
+
 extern "C" qr_status qr_basis_law(const qr_basis *b, int32_t *law) {
     if (!b || !law) return fail(QR_EINVAL, "qr_basis_law: NULL argument");
     *law = b->law;
     return QR_OK;
 }
 
+extern "C" qr_status qr_basis_family_of(const qr_basis *b, int32_t *family) {
+    if (!b || !family) return fail(QR_EINVAL, "qr_basis_family_of: NULL argument");
+    *family = b->cos ? QR_BASIS_COSINE : QR_BASIS_FOURIER;
+    return QR_OK;
+}
+
 extern "C" qr_status qr_basis_info(const qr_basis *b, int64_t *n_funcs, int64_t *n_reps,
                                    int32_t *max_nnz) {
     if (!b) return fail(QR_EINVAL, "qr_basis_info: basis is NULL");
-    if (n_funcs) *n_funcs = 2 * b->nrep - 1;
-    if (n_reps) *n_reps = b->nrep;
+    if (n_funcs) *n_funcs = b->nf();
+    if (n_reps) *n_reps = b->cos ? b->ncos : b->nrep;
     if (max_nnz) *max_nnz = b->max_nnz;
     return QR_OK;
 }
 
 extern "C" qr_status qr_basis_indices(const qr_basis *b, int32_t *reps_out) {
     if (!b || !reps_out) return fail(QR_EINVAL, "qr_basis_indices: NULL argument");
-    std::memcpy(reps_out, b->canon.data(), sizeof(int32_t) * b->canon.size());
+    const std::vector<int32_t> &v = b->cos ? b->cvec : b->canon;
+    std::memcpy(reps_out, v.data(), sizeof(int32_t) * v.size());
     return QR_OK;
 }
 
@@ -278,8 +364,16 @@ static void basis_free_device(qr_basis *b) {
         hipFree((void *)b->d_fac.colnnz);
         hipFree((void *)b->d_fac.ent);
         for (int t = 0; t < kFacTemplates; ++t) hipFree(b->d_fac_tasks[t]);
+        hipFree(b->d_cos_of_rep);
+        hipFree(b->d_fold_off);
+        hipFree(b->d_fold_idx);
+        hipFree(b->d_rep_scale);
         hipSetDevice(cur);
     }
+    b->d_cos_of_rep = nullptr;
+    b->d_fold_off = nullptr;
+    b->d_fold_idx = nullptr;
+    b->d_rep_scale = nullptr;
     b->d_fac = FacDev{};
     for (int t = 0; t < kFacTemplates; ++t) {
         b->d_fac_tasks[t] = nullptr;
@@ -347,6 +441,14 @@ static qr_status sub_basis(qr_basis *b, int32_t d2, int32_t level2, qr_basis **o
     return QR_OK;
 }
 
+template <class T>
+static qr_status upload_vec(T **dst, const std::vector<T> &v) {
+    QR_HIP(hipMalloc((void **)dst, sizeof(T) * std::max<size_t>(v.size(), 1)), "hipMalloc(basis tables)");
+    if (!v.empty())
+        QR_HIP(hipMemcpy(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice), "hipMemcpy(basis tables)");
+    return QR_OK;
+}
+
 // Upload the basis tables to `dev` (current device) once.
 static qr_status basis_on_device(qr_basis *b, int dev) {
     std::lock_guard<std::mutex> lock(b->mu);
@@ -372,6 +474,13 @@ static qr_status basis_on_device(qr_basis *b, int dev) {
         QR_HIP(hipMemcpy(b->d_inv, b->inv.data(), sizeof(int32_t) * b->inv.size(), hipMemcpyHostToDevice),
                "hipMemcpy(basis)");
     }
+    if (b->cos) {
+        qr_status st;
+        if ((st = upload_vec(&b->d_cos_of_rep, b->cos_of_rep))) return st;
+        if ((st = upload_vec(&b->d_fold_off, b->fold_off))) return st;
+        if ((st = upload_vec(&b->d_fold_idx, b->fold_idx))) return st;
+        if ((st = upload_vec(&b->d_rep_scale, b->rep_scale))) return st;
+    }
     b->dev = dev;
     return QR_OK;
 }
@@ -388,14 +497,6 @@ static bool basis_factored(qr_basis *b) {
             delete L;
     }
     return b->fac != nullptr;
-}
-
-template <class T>
-static qr_status upload_vec(T **dst, const std::vector<T> &v) {
-    QR_HIP(hipMalloc((void **)dst, sizeof(T) * std::max<size_t>(v.size(), 1)), "hipMalloc(factored layout)");
-    if (!v.empty())
-        QR_HIP(hipMemcpy(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice), "hipMemcpy(factored layout)");
-    return QR_OK;
 }
 
 // Device copy of the factored layout (the basis must be on `dev` already).
@@ -461,6 +562,8 @@ struct qr_ctx {
     DevProblem h_prob{};
     bool prob_valid = false;
     Buf S, u, alpha_int, partial, row, alpha_b, tiles, xstate, fcoef, fpartial;
+    // cosine basis: the carrier table [N][2R-1] and one carrier row
+    Buf calpha, crow;
     int32_t prec_kernel = QR_PREC_KERNEL_AUTO;
     // surrogate network workspace: activations of up to kMlpChunk rows
     Buf mf, mz1, mh1, mz2, mh2, mdz, mdh, my, mdy, mpart, mwork, mcwork;
@@ -563,10 +666,8 @@ extern "C" void qr_ctx_destroy(qr_ctx *c) {
     if (!c) return;
     hipSetDevice(c->dev);
     hipDeviceSynchronize();
-    for (Buf *b : {&c->S, &c->u, &c->alpha_int, &c->partial, &c->row, &c->alpha_b, &c->tiles, &c->xstate, &c->fcoef, &c->fpartial,
-                   &c->mf,
-                   &c->mz1,
-                   &c->mh1, &c->mz2, &c->mh2, &c->mdz, &c->mdh, &c->my, &c->mdy, &c->mpart, &c->mwork,
+    for (Buf *b : {&c->S, &c->u, &c->alpha_int, &c->partial, &c->row, &c->alpha_b, &c->tiles, &c->xstate, &c->fcoef,
+                   &c->fpartial, &c->calpha, &c->crow, &c->mf, &c->mz1, &c->mh1, &c->mz2, &c->mh2, &c->mdz, &c->mdh, &c->my, &c->mdy, &c->mpart, &c->mwork,
                    &c->mcwork, &c->lx, &c->lh, &c->ly, &c->lparams, &c->lgrad, &c->lm, &c->lv, &c->ltx, &c->ltt,
                    &c->ltf, &c->lff, &c->lhx, &c->lht, &c->lhf, &c->lhy})
         if (b->p) hipFree(b->p);
@@ -667,8 +768,9 @@ static qr_status check_problem(const qr_problem *p, const qr_basis *b) {
     if (p->nbm < 1 || p->nbm > QR_MAX_D)
         return fail(QR_EINVAL, "problem: nbm=%d outside [1,%d]", p->nbm, QR_MAX_D);
     if (p->N < 1 || p->N > QR_MAX_N) return fail(QR_EINVAL, "problem: N=%d outside [1,%d]", p->N, QR_MAX_N);
-    if (p->driver < QR_F_LINEAR || p->driver > QR_F_ZRAT)
+    if (p->driver < QR_F_LINEAR || p->driver > QR_F_PAPER)
         return fail(QR_EINVAL, "problem: unknown driver %d", p->driver);
+    if (!std::isfinite(p->sol_B)) return fail(QR_EINVAL, "problem: offset B not finite");
     if (!(p->clamp > 0.0)) return fail(QR_EINVAL, "problem: clamp must be > 0 (INFINITY for none)");
     if (!(p->damping_q >= 0.0 && p->damping_q <= QR_MAX_DAMPING))
         return fail(QR_EINVAL, "problem: damping exponent q=%g outside [0,%g]", p->damping_q, (double)QR_MAX_DAMPING);
@@ -722,6 +824,7 @@ static qr_status upload_problem(qr_ctx *c, const qr_problem *p, int32_t law, hip
     h.sol_A = p->sol_A;
     h.sol_c = p->sol_c;
     h.sol_p = p->sol_p;
+    h.sol_B = p->sol_B;
     h.dq = p->damping_q;
     double sw2 = 0.0;
     for (int k = 0; k < p->nbm; ++k) {
@@ -802,7 +905,7 @@ static qr_status project_and_reduce(qr_ctx *c, const qr_basis *b, const double2 
     const int cap = depth_cap(b->max_nnz);
     double2 *partial = (double2 *)c->partial.p;
     st = timed(c, 1, s, "project_kernel", [&] {
-        return launch_project(cap, make_walk(b->kind, b->level, b->d, b->law), u, M, S, M, pps,
+        return launch_project(cap, make_walk(b->kind, b->level, b->d, b->code()), u, M, S, M, pps,
                               (int32_t)b->tasks.size(), nsplit, b->d_tasks, b->d_items, b->task_max,
                               partial, b->nrep, s);
     });
@@ -818,9 +921,10 @@ static qr_status run_path(qr_ctx *c, const qr_problem *p, const qr_basis *b, int
                           hipStream_t s) {
     const bool grad = p->driver == QR_F_ZRAT;
     const int64_t ldx = path_state_ld(M, grad);
-    qr_status st = ensure(c, c->xstate, sizeof(double) * (size_t)p->d * ldx, "path state");
+    // rows 0..d-1: X_j; row d: u(t_j, X_j) for the Sec. 5 driver
+    qr_status st = ensure(c, c->xstate, sizeof(double) * (size_t)(p->d + 1) * ldx, "path state");
     if (st) return st;
-    PathArgs a{c->d_prob, make_walk(b->kind, b->level, b->d, b->law), i, M, seed, alpha_int, b->ld(), S, u, x0,
+    PathArgs a{c->d_prob, make_walk(b->kind, b->level, b->d, b->code()), i, M, seed, alpha_int, b->ld(), S, u, x0,
                (double *)c->xstate.p, ldx};
     return timed(c, 0, s, "path_kernel", [&] {
         return launch_path(dim_bucket(p->d, p->nbm), depth_cap(b->max_nnz), p->driver == QR_F_ZRAT,
@@ -840,13 +944,53 @@ static qr_status prepare(qr_ctx *c, const qr_problem *p, qr_basis *b, int64_t M,
     if ((st = check_basis_device(b))) return st;
     if ((st = check_M(M))) return st;
     if ((st = basis_on_device(b, c->dev))) return st;
-    if ((st = upload_problem(c, p, b->law, (hipStream_t)stream))) return st;
+    if ((st = upload_problem(c, p, b->code(), (hipStream_t)stream))) return st;
     if ((st = ensure(c, c->S, sizeof(double) * (size_t)M, "S"))) return st;
     if ((st = ensure(c, c->u, sizeof(double2) * (size_t)M * p->d, "phase factors"))) return st;
     if ((st = ensure(c, c->alpha_int, sizeof(double2) * (size_t)p->N * b->ld(), "alpha"))) return st;
     // zero the padding columns read by the batched coefficient loads
     QR_HIP(launch_pad(p->N, b->nrep, b->ld(), (double2 *)c->alpha_int.p, (hipStream_t)stream), "pad_kernel");
     return QR_OK;
+}
+
+// The coefficient table the kernels take: the caller's for a Fourier basis;
+// for a cosine basis the context's carrier table, rows [r0, N) expanded from
+// the caller's cosine rows.
+static qr_status carrier_in(qr_ctx *c, const qr_basis *b, const double *alpha, int32_t r0, int32_t N, double **A,
+                            hipStream_t s) {
+    if (!b->cos) {
+        *A = const_cast<double *>(alpha);
+        return QR_OK;
+    }
+    qr_status st = ensure(c, c->calpha, sizeof(double) * (size_t)N * b->nfc(), "carrier coefficients");
+    if (st) return st;
+    *A = (double *)c->calpha.p;
+    if (r0 >= N) return QR_OK;
+    return timed(c, 3, s, "cos_expand_kernel", [&] {
+        return launch_cos_expand(alpha, r0, N - r0, b->ncos, b->nrep, b->d_cos_of_rep, b->d_rep_scale, *A, s);
+    });
+}
+
+// After a step has written carrier row i of A: the caller's cosine row i by
+// folding it, then carrier row i (and, if alpha_int is given, the kernels'
+// row i) replaced by the expansion of that cosine row, which is what the
+// later steps evaluate.
+static qr_status carrier_out(qr_ctx *c, const qr_basis *b, double *A, double *alpha, int32_t i, double2 *alpha_int,
+                             hipStream_t s) {
+    if (!b->cos) return QR_OK;
+    double *arow = A + (int64_t)i * b->nfc();
+    double *crow = alpha + (int64_t)i * b->ncos;
+    qr_status st = timed(c, 3, s, "cos_fold_kernel", [&] {
+        return launch_cos_fold(arow, b->ncos, b->d_fold_off, b->d_fold_idx, b->d_rep_scale, crow, s);
+    });
+    if (st) return st;
+    st = timed(c, 3, s, "cos_expand_kernel", [&] {
+        return launch_cos_expand(alpha, i, 1, b->ncos, b->nrep, b->d_cos_of_rep, b->d_rep_scale, A, s);
+    });
+    if (st || !alpha_int) return st;
+    return timed(c, 3, s, "gather_kernel", [&] {
+        return launch_gather(A, i, 1, b->nrep, b->ld(), b->nfc(), b->d_canon_of_trav, alpha_int, s);
+    });
 }
 
 extern "C" qr_status qr_backward_step(qr_ctx *c, const qr_problem *p, const qr_basis *bc, int32_t i,
@@ -858,15 +1002,18 @@ extern "C" qr_status qr_backward_step(qr_ctx *c, const qr_problem *p, const qr_b
     if (i < 0 || i >= p->N) return fail(QR_EINVAL, "qr_backward_step: i=%d outside [0,%d)", i, p->N);
     hipStream_t s = (hipStream_t)stream;
     double2 *ai = (double2 *)c->alpha_int.p;
-    const int64_t nf = 2 * b->nrep - 1;
+    const int64_t nf = b->nfc();
+    double *A;
+    if ((st = carrier_in(c, b, alpha, i + 1, p->N, &A, s))) return st;
     st = timed(c, 3, s, "gather_kernel", [&] {
-        return launch_gather(alpha, i + 1, p->N - 1 - i, b->nrep, b->ld(), nf, b->d_canon_of_trav, ai, s);
+        return launch_gather(A, i + 1, p->N - 1 - i, b->nrep, b->ld(), nf, b->d_canon_of_trav, ai, s);
     });
     if (st) return st;
     double *S = (double *)c->S.p;
     double2 *u = (double2 *)c->u.p;
     if ((st = run_path(c, p, b, i, M, seed, ai, S, u, nullptr, s))) return st;
-    return project_and_reduce(c, b, u, S, M, ai + (int64_t)i * b->ld(), alpha + (int64_t)i * nf, i, s);
+    if ((st = project_and_reduce(c, b, u, S, M, ai + (int64_t)i * b->ld(), A + (int64_t)i * nf, i, s))) return st;
+    return carrier_out(c, b, A, alpha, i, nullptr, s);
 }
 
 extern "C" qr_status qr_solve(qr_ctx *c, const qr_problem *p, const qr_basis *bc, int64_t M,
@@ -877,14 +1024,17 @@ extern "C" qr_status qr_solve(qr_ctx *c, const qr_problem *p, const qr_basis *bc
     if (!alpha) return fail(QR_EINVAL, "qr_solve: alpha is NULL");
     hipStream_t s = (hipStream_t)stream;
     double2 *ai = (double2 *)c->alpha_int.p;
-    const int64_t nf = 2 * b->nrep - 1;
+    const int64_t nf = b->nfc();
     double *S = (double *)c->S.p;
     double2 *u = (double2 *)c->u.p;
+    double *A;
+    if ((st = carrier_in(c, b, alpha, p->N, p->N, &A, s))) return st;
     if ((st = numeric_clear(c, s))) return st;
     for (int32_t i = p->N - 1; i >= 0; --i) {
         if ((st = run_path(c, p, b, i, M, seed, ai, S, u, nullptr, s))) return st;
-        if ((st = project_and_reduce(c, b, u, S, M, ai + (int64_t)i * b->ld(), alpha + (int64_t)i * nf, i, s)))
+        if ((st = project_and_reduce(c, b, u, S, M, ai + (int64_t)i * b->ld(), A + (int64_t)i * nf, i, s)))
             return st;
+        if ((st = carrier_out(c, b, A, alpha, i, ai, s))) return st;
     }
     return numeric_read(c, s, nullptr);
 }
@@ -899,9 +1049,11 @@ extern "C" qr_status qr_path_responses(qr_ctx *c, const qr_problem *p, const qr_
     if (i < 0 || i >= p->N) return fail(QR_EINVAL, "qr_path_responses: i=%d outside [0,%d)", i, p->N);
     hipStream_t s = (hipStream_t)stream;
     double2 *ai = (double2 *)c->alpha_int.p;
-    const int64_t nf = 2 * b->nrep - 1;
+    const int64_t nf = b->nfc();
+    double *A;
+    if ((st = carrier_in(c, b, alpha, i + 1, p->N, &A, s))) return st;
     st = timed(c, 3, s, "gather_kernel", [&] {
-        return launch_gather(alpha, i + 1, p->N - 1 - i, b->nrep, b->ld(), nf, b->d_canon_of_trav, ai, s);
+        return launch_gather(A, i + 1, p->N - 1 - i, b->nrep, b->ld(), nf, b->d_canon_of_trav, ai, s);
     });
     if (st) return st;
     return run_path(c, p, b, i, M, seed, ai, s_out, nullptr, x0, s);
@@ -920,8 +1072,14 @@ extern "C" qr_status qr_project(qr_ctx *c, const qr_basis *bc, int64_t n, const 
     if ((st = ensure(c, c->row, sizeof(double2) * (size_t)b->ld(), "row"))) return st;
     hipStream_t s = (hipStream_t)stream;
     double2 *u = (double2 *)c->u.p;
-    QR_HIP(launch_x_to_e(b->law, b->d, x, n, u, s), "x_to_e_kernel");
-    return project_and_reduce(c, b, u, s_in, n, (double2 *)c->row.p, alpha_row, -1, s);
+    QR_HIP(launch_x_to_e(b->code(), b->d, x, n, u, s), "x_to_e_kernel");
+    if (!b->cos) return project_and_reduce(c, b, u, s_in, n, (double2 *)c->row.p, alpha_row, -1, s);
+    if ((st = ensure(c, c->crow, sizeof(double) * (size_t)b->nfc(), "carrier row"))) return st;
+    double *crow = (double *)c->crow.p;
+    if ((st = project_and_reduce(c, b, u, s_in, n, (double2 *)c->row.p, crow, -1, s))) return st;
+    QR_HIP(launch_cos_fold(crow, b->ncos, b->d_fold_off, b->d_fold_idx, b->d_rep_scale, alpha_row, s),
+           "cos_fold_kernel");
+    return QR_OK;
 }
 
 extern "C" qr_status qr_eval(qr_ctx *c, const qr_basis *bc, const double *alpha_row, int64_t n,
@@ -937,10 +1095,17 @@ extern "C" qr_status qr_eval(qr_ctx *c, const qr_basis *bc, const double *alpha_
     if ((st = ensure(c, c->row, sizeof(double2) * (size_t)b->ld(), "row"))) return st;
     hipStream_t s = (hipStream_t)stream;
     double2 *row = (double2 *)c->row.p;
-    const int64_t nf = 2 * b->nrep - 1;
+    const int64_t nf = b->nfc();
+    if (b->cos) {
+        if ((st = ensure(c, c->crow, sizeof(double) * (size_t)nf, "carrier row"))) return st;
+        double *crow = (double *)c->crow.p;
+        QR_HIP(launch_cos_expand(alpha_row, 0, 1, b->ncos, b->nrep, b->d_cos_of_rep, b->d_rep_scale, crow, s),
+               "cos_expand_kernel");
+        alpha_row = crow;
+    }
     QR_HIP(launch_pad(1, b->nrep, b->ld(), row, s), "pad_kernel");
     QR_HIP(launch_gather(alpha_row, 0, 1, b->nrep, b->ld(), nf, b->d_canon_of_trav, row, s), "gather_kernel");
-    QR_HIP(launch_eval(depth_cap(b->max_nnz), grad != nullptr, make_walk(b->kind, b->level, b->d, b->law), row, x,
+    QR_HIP(launch_eval(depth_cap(b->max_nnz), grad != nullptr, make_walk(b->kind, b->level, b->d, b->code()), row, x,
                        n, y, grad, s),
            "eval_kernel");
     return QR_OK;
@@ -966,6 +1131,7 @@ extern "C" qr_status qr_eval_noalloc(qr_ctx *c, const qr_basis *bc, const double
     if (st) return st;
     if ((st = check_basis_device(b))) return st;
     if (n < 0 || n > (int64_t)INT32_MAX * 64) return fail(QR_EINVAL, "qr_eval_noalloc: n out of range");
+    if (b->cos) return fail(QR_ENOTSUP, "qr_eval_noalloc: the cosine basis needs a carrier row (use qr_eval)");
     if (b->ld() > (int64_t)QR_NOALLOC_ROW_MAX)
         return fail(QR_ERANGE, "qr_eval_noalloc: basis of %lld representatives needs %lld scratch entries (limit %d)",
                     (long long)b->nrep, (long long)b->ld(), QR_NOALLOC_ROW_MAX);
@@ -987,7 +1153,7 @@ extern "C" qr_status qr_eval_noalloc(qr_ctx *c, const qr_basis *bc, const double
     // since the previous call may have left another basis's row there
     QR_HIP(launch_pad(1, b->nrep, b->ld(), row, s), "pad_kernel");
     QR_HIP(launch_gather(alpha_row, 0, 1, b->nrep, b->ld(), nf, b->d_canon_of_trav, row, s), "gather_kernel");
-    QR_HIP(launch_eval(depth_cap(b->max_nnz), grad != nullptr, make_walk(b->kind, b->level, b->d, b->law), row, x,
+    QR_HIP(launch_eval(depth_cap(b->max_nnz), grad != nullptr, make_walk(b->kind, b->level, b->d, b->code()), row, x,
                        n, y, grad, s),
            "eval_kernel");
     return QR_OK;
@@ -1047,12 +1213,12 @@ static qr_status pack_row(qr_ctx *c, const qr_problem *p, const qr_basis *b, int
     const double2 *ai = (const double2 *)c->alpha_int.p + (int64_t)row * b->ld();
     uint2 *out = (uint2 *)c->tiles.p + (int64_t)row * tp.ld;
     return timed(c, 3, s, "pack_tiles_kernel",
-                 [&] { return launch_pack_tiles(prec, ai, b->nrep, b->d_trav, p->d, tp.T, out, s); });
+                 [&] { return launch_pack_tiles(prec, ai, b->nrep, b->d_trav, p->d, tp.T, b->cos, out, s); });
 }
 
 static qr_status run_mfma_path(qr_ctx *c, const qr_problem *p, const qr_basis *b, int32_t prec,
                                const TilePlan &tp, int32_t i, int64_t M, uint64_t seed, hipStream_t s) {
-    MfmaArgs a{c->d_prob, make_walk(b->kind, b->level, b->d, b->law), i, M, seed, (const uint2 *)c->tiles.p, tp.ld,
+    MfmaArgs a{c->d_prob, make_walk(b->kind, b->level, b->d, b->code()), i, M, seed, (const uint2 *)c->tiles.p, tp.ld,
                (double *)c->S.p, (double2 *)c->u.p};
     return timed(c, 0, s, "mfma_path_kernel", [&] {
         return launch_mfma_path(dim_bucket(p->d, p->nbm), depth_cap(b->max_nnz), p->driver == QR_F_ZRAT, prec,
@@ -1149,26 +1315,30 @@ extern "C" qr_status qr_backward_step_prec(qr_ctx *c, const qr_problem *p, const
     if (i < 0 || i >= p->N) return fail(QR_EINVAL, "qr_backward_step_prec: i=%d outside [0,%d)", i, p->N);
     hipStream_t s = (hipStream_t)stream;
     double2 *ai = (double2 *)c->alpha_int.p;
-    const int64_t nf = 2 * b->nrep - 1;
+    const int64_t nf = b->nfc();
     const bool fac = use_factored(c, p, b, &st);
     if (st) return st;
+    double *A;
+    if ((st = carrier_in(c, b, alpha, i + 1, p->N, &A, s))) return st;
     if (fac) {
         if ((st = prepare_fac(c, p, b))) return st;
         for (int32_t r = i + 1; r < p->N; ++r)
-            if ((st = fac_pack_row(c, b, prec, alpha + (int64_t)r * nf, r, s))) return st;
+            if ((st = fac_pack_row(c, b, prec, A + (int64_t)r * nf, r, s))) return st;
         if ((st = run_fac_path(c, p, b, prec, i, M, seed, s))) return st;
-        return fac_project(c, b, prec, M, alpha + (int64_t)i * nf, i, s);
+        if ((st = fac_project(c, b, prec, M, A + (int64_t)i * nf, i, s))) return st;
     } else {
         st = timed(c, 3, s, "gather_kernel", [&] {
-            return launch_gather(alpha, i + 1, p->N - 1 - i, b->nrep, b->ld(), nf, b->d_canon_of_trav, ai, s);
+            return launch_gather(A, i + 1, p->N - 1 - i, b->nrep, b->ld(), nf, b->d_canon_of_trav, ai, s);
         });
         if (st) return st;
         for (int32_t r = i + 1; r < p->N; ++r)
             if ((st = pack_row(c, p, b, prec, tp, r, s))) return st;
         if ((st = run_mfma_path(c, p, b, prec, tp, i, M, seed, s))) return st;
+        if ((st = project_and_reduce(c, b, (double2 *)c->u.p, (double *)c->S.p, M, ai + (int64_t)i * b->ld(),
+                                     A + (int64_t)i * nf, i, s)))
+            return st;
     }
-    return project_and_reduce(c, b, (double2 *)c->u.p, (double *)c->S.p, M, ai + (int64_t)i * b->ld(),
-                              alpha + (int64_t)i * nf, i, s);
+    return carrier_out(c, b, A, alpha, i, nullptr, s);
 }
 
 extern "C" qr_status qr_solve_prec(qr_ctx *c, const qr_problem *p, const qr_basis *bc, int64_t M,
@@ -1181,20 +1351,23 @@ extern "C" qr_status qr_solve_prec(qr_ctx *c, const qr_problem *p, const qr_basi
     if (!alpha) return fail(QR_EINVAL, "qr_solve_prec: alpha is NULL");
     hipStream_t s = (hipStream_t)stream;
     double2 *ai = (double2 *)c->alpha_int.p;
-    const int64_t nf = 2 * b->nrep - 1;
+    const int64_t nf = b->nfc();
     const bool fac = use_factored(c, p, b, &st);
     if (st) return st;
     if (fac && (st = prepare_fac(c, p, b))) return st;
+    double *A;
+    if ((st = carrier_in(c, b, alpha, p->N, p->N, &A, s))) return st;
     if ((st = numeric_clear(c, s))) return st;
     for (int32_t i = p->N - 1; i >= 0; --i) {
         st = fac ? run_fac_path(c, p, b, prec, i, M, seed, s) : run_mfma_path(c, p, b, prec, tp, i, M, seed, s);
         if (st) return st;
-        st = fac ? fac_project(c, b, prec, M, alpha + (int64_t)i * nf, i, s)
+        st = fac ? fac_project(c, b, prec, M, A + (int64_t)i * nf, i, s)
                  : project_and_reduce(c, b, (double2 *)c->u.p, (double *)c->S.p, M, ai + (int64_t)i * b->ld(),
-                                      alpha + (int64_t)i * nf, i, s);
+                                      A + (int64_t)i * nf, i, s);
         if (st) return st;
+        if ((st = carrier_out(c, b, A, alpha, i, fac ? nullptr : ai, s))) return st;
         if (i > 0) {
-            st = fac ? fac_pack_row(c, b, prec, alpha + (int64_t)i * nf, i, s) : pack_row(c, p, b, prec, tp, i, s);
+            st = fac ? fac_pack_row(c, b, prec, A + (int64_t)i * nf, i, s) : pack_row(c, p, b, prec, tp, i, s);
             if (st) return st;
         }
     }
@@ -1360,7 +1533,7 @@ static qr_status fit_surrogate(qr_ctx *c, const qr_problem *p, const qr_basis *b
     double *tx = (double *)c->ltx.p, *tt = (double *)c->ltt.p, *hx = (double *)c->lhx.p, *ht = (double *)c->lht.p;
     float *tf = (float *)c->ltf.p, *ff = (float *)c->lff.p, *hf = (float *)c->lhf.p, *hy = (float *)c->lhy.p;
     const double2 *row = (const double2 *)c->alpha_int.p + (int64_t)j * b->ld();
-    const Walk W = make_walk(b->kind, b->level, b->d, b->law);
+    const Walk W = make_walk(b->kind, b->level, b->d, b->code());
     const int cap = depth_cap(b->max_nnz);
     // pairs (X, ybar_j(X)): training from stream 2, held-out from stream 3, at time index j
     QR_HIP(launch_sample(b->law, d, seed, 2u, j, 0, nt, tx, s), "sample_kernel");
@@ -1432,6 +1605,8 @@ extern "C" qr_status qr_solve_learned(qr_ctx *c, const qr_problem *p, const qr_b
     if (p->driver == QR_F_ZRAT)
         return fail(QR_ENOTSUP, "qr_solve_learned: the driver depends on z (the surrogate has no gradient)");
     if (p->damping_q != 0.0) return fail(QR_ENOTSUP, "qr_solve_learned: damping exponent q must be 0");
+    if (b->cos) return fail(QR_ENOTSUP, "qr_solve_learned: the cosine basis is not supported");
+    if (p->driver == QR_F_PAPER) return fail(QR_ENOTSUP, "qr_solve_learned: the Sec. 5 driver is not supported");
     hipStream_t s = (hipStream_t)stream;
     const int d = p->d, N = p->N;
     const int64_t nt = o->train_points, nh = o->heldout_points;
@@ -1460,7 +1635,7 @@ extern "C" qr_status qr_solve_learned(qr_ctx *c, const qr_problem *p, const qr_b
     for (int j = 0; j < N; ++j) report[j] = qr_learn_report{0.0, 0.0, 0, 0, 0.0, 1.0};
     const int db = dim_bucket(p->d, p->nbm);
     const int cap = depth_cap(b->max_nnz);
-    const Walk W = make_walk(b->kind, b->level, b->d, b->law);
+    const Walk W = make_walk(b->kind, b->level, b->d, b->code());
     double *x = (double *)c->lx.p, *H = (double *)c->lh.p, *y = (double *)c->ly.p;
     double *S = (double *)c->S.p;
     double2 *u = (double2 *)c->u.p;
@@ -1553,6 +1728,8 @@ extern "C" qr_status qr_solve_batched(qr_ctx *c, const qr_problem *p, const qr_b
     if (p->driver == QR_F_ZRAT)
         return fail(QR_ENOTSUP, "qr_solve_batched: the driver depends on z (gradients are not batched)");
     if (p->damping_q != 0.0) return fail(QR_ENOTSUP, "qr_solve_batched: damping exponent q must be 0");
+    if (b->cos) return fail(QR_ENOTSUP, "qr_solve_batched: the cosine basis is not supported");
+    if (p->driver == QR_F_PAPER) return fail(QR_ENOTSUP, "qr_solve_batched: the Sec. 5 driver is not supported");
     int64_t Mmax = 0;
     for (int r = 0; r < R; ++r) {
         const qr_instance &I = inst[r];
@@ -1657,7 +1834,7 @@ extern "C" qr_status qr_solve_batched(qr_ctx *c, const qr_problem *p, const qr_b
                 int64_t pps;
                 split_plan(ob, Mr, &nsplit, &pps);
                 st = timed(c, 1, s, "project_kernel", [&] {
-                    return launch_project(depth_cap(ob->max_nnz), make_walk(b->kind, ob->level, ob->d, b->law), u, P.M,
+                    return launch_project(depth_cap(ob->max_nnz), make_walk(b->kind, ob->level, ob->d, b->code()), u, P.M,
                                           S + (int64_t)k * P.M, Mr, pps, (int32_t)ob->tasks.size(), nsplit,
                                           ob->d_tasks, ob->d_items, ob->task_max, partial, ob->nrep, s);
                 });

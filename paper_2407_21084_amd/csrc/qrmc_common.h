@@ -153,7 +153,14 @@ __host__ __device__ inline double logistic_cdf(double x) { return 1.0 / (1.0 + e
 //    argument folded to (0, 1/2] so that the tails keep their relative
 //    accuracy (sincospi takes u itself, no product with pi);
 //  - otherwise the standard logistic law.
+// Bit kLawHalf of a law code is not part of the law: it marks the cosine
+// basis, whose kernels take the phase factors e^{i pi F(x)} at half the
+// Fourier frequency (see nl_unit_phase); the laws below ignore it.
+constexpr int32_t kLawHalf = 8;
+constexpr int32_t kLawMask = 7;
+
 __device__ inline double law_icdf(int32_t nu, double u) {
+    nu &= kLawMask;
     if (nu == QR_LAW_STUDENT2) return (u - 0.5) / sqrt(u * (1.0 - u));
     if (nu == QR_LAW_CAUCHY) {
         const double v = u < 0.5 ? u : 1.0 - u;  // exact for u >= 1/2
@@ -164,12 +171,14 @@ __device__ inline double law_icdf(int32_t nu, double u) {
     return logistic_icdf(u);
 }
 __device__ inline double law_cdf(int32_t nu, double x) {
+    nu &= kLawMask;
     if (nu == QR_LAW_STUDENT2) return 0.5 + 0.5 * (x / sqrt(fma(x, x, 1.0)));
     if (nu == QR_LAW_CAUCHY) return 0.5 + atan(x) * M_1_PI;
     return logistic_cdf(x);
 }
 // density nu_l(x) = dF/dx, given x and u = F(x)
 __device__ inline double law_pdf(int32_t nu, double x, double u) {
+    nu &= kLawMask;
     if (nu == QR_LAW_STUDENT2) {
         const double r = 1.0 / fma(x, x, 1.0);
         return 0.5 * r * sqrt(r);
@@ -186,58 +195,66 @@ __device__ inline double law_pdf(int32_t nu, double x, double u) {
 // closed-form pieces of the manufactured solution pre-combined on the host.
 struct DevProblem {
     int32_t d, nbm, N, driver;
-    int32_t nu;                       // sampling law of the basis in use (qr_law)
+    int32_t nu;                       // law code of the basis in use (qr_law | kLawHalf)
     double f_a, clamp, T;
     double sw2;                       // |sigma^T w|^2
     double t[QR_MAX_N + 1];
     double b0[kMaxD], b1[kMaxD];
     double sigma[kMaxD * kMaxD];      // [d][nbm]
-    double sol_A, sol_c, sol_p;
+    double sol_A, sol_c, sol_p, sol_B;
     double sol_w[kMaxD];
     double sw[kMaxD];                 // sigma^T w
     double dq;                        // damping exponent q (0: none)
 };
 
-// Index-set rule of the traversal, branch-free for all three kinds: a node
-// with budget product P may take a next coordinate of magnitude m iff
-// m <= mmax and P (a m + b) <= L; its child then has budget P (a m + b).
+// Index-set rule of the traversal: a node with budget P (the root has P = 1)
+// may take a next coordinate of magnitude m iff m <= mmax and its child's
+// budget, P (a m + b) for the product rules or P + m for the sum rule
+// (add = 1), is at most L.
 //   tensor  (max |k_l| <= K):            a = 0, b = 1, mmax = K, L = 1
 //   hc_max  (prod max(1,|k_l|) <= L):    a = 1, b = 0, mmax = L
 //   hc_1p   (prod (1+|k_l|) <= L):       a = 1, b = 1, mmax = L
+//   total   (sum |k_l| <= K):            add = 1, mmax = K, L = K + 1
+//           (budget 1 + the sum so far)
 struct SetRule {
-    int32_t a, b, L, mmax, d;
+    int32_t a, b, L, mmax, d, add;
 };
 
 __host__ __device__ inline SetRule make_rule(int32_t kind, int32_t level, int32_t d) {
-    if (kind == QR_SET_TENSOR) return SetRule{0, 1, 1, level, d};
-    if (kind == QR_SET_HC_MAX) return SetRule{1, 0, level, level, d};
-    return SetRule{1, 1, level, level, d};
-}
-
-__host__ __device__ inline bool rule_ok(const SetRule &R, int32_t P, int32_t m) {
-    return (m <= R.mmax) & (P * (R.a * m + R.b) <= R.L);
+    if (kind == QR_SET_TENSOR) return SetRule{0, 1, 1, level, d, 0};
+    if (kind == QR_SET_HC_MAX) return SetRule{1, 0, level, level, d, 0};
+    if (kind == QR_SET_TOTAL) return SetRule{0, 0, level + 1, level, d, 1};
+    return SetRule{1, 1, level, level, d, 0};
 }
 
 __host__ __device__ inline int32_t rule_child(const SetRule &R, int32_t P, int32_t m) {
-    return P * (R.a * m + R.b);
+    return R.add ? P + m : P * (R.a * m + R.b);
+}
+
+__host__ __device__ inline bool rule_ok(const SetRule &R, int32_t P, int32_t m) {
+    return (m <= R.mmax) & (rule_child(R, P, m) <= R.L);
 }
 
 constexpr int kMaxDepthCap = 8;
 
 // Branch-light form of the same rule used by the kernels' walk: a node with
-// budget Pb extends by magnitude m while w = Pb (m + b) <= L; its child's
-// budget is w when c = 1 (hyperbolic crosses) or stays Pb = 1 (c = 0,
-// tensor set); a child has children iff its budget <= Lc.
-// The walk also carries the sampling law nu of the basis (qr_law): the basis
-// functions in x are the Fourier functions of the torus composed with F_nu.
+// budget Pb extends by magnitudes m = 1, 2, ... while its child's budget,
+// w = Pb (m + b) (a = 0) or w = Pb + m (a = 1, total degree), is at most L:
+// w runs from Pb (1 + b) + a in steps of (a ? 1 : Pb); the child's
+// budget is w when c = 1 (hyperbolic crosses, total degree) or stays Pb = 1
+// (c = 0, tensor set); a child has children iff its budget <= Lc.
+// The walk also carries the law code nu of the basis (qr_law, plus kLawHalf
+// for the cosine basis): the basis functions in x are the Fourier functions
+// of the torus composed with F_nu.
 struct Walk {
-    int32_t b, L, Lc, c, d, nu;
+    int32_t b, L, Lc, c, d, nu, a;
 };
 
 __host__ __device__ inline Walk make_walk(int32_t kind, int32_t level, int32_t d, int32_t nu) {
-    if (kind == QR_SET_TENSOR) return Walk{0, level, level, 0, d, nu};
-    if (kind == QR_SET_HC_MAX) return Walk{0, level, level, 1, d, nu};
-    return Walk{1, level, level / 2, 1, d, nu};
+    if (kind == QR_SET_TENSOR) return Walk{0, level, level, 0, d, nu, 0};
+    if (kind == QR_SET_HC_MAX) return Walk{0, level, level, 1, d, nu, 0};
+    if (kind == QR_SET_TOTAL) return Walk{0, level + 1, level, 1, d, nu, 1};
+    return Walk{1, level, level / 2, 1, d, nu, 0};
 }
 
 // Root of a run of the depth-first traversal used by the projection: the

@@ -37,11 +37,16 @@ __device__ __noinline__ double2 nl_unit_phase_logistic(double x) {
     sincospi(2.0 * logistic_cdf(x), &sn, &cs);
     return make_double2(cs, sn);
 }
+// e^{2 pi i F(x)}, or e^{i pi F(x)} for a law code with kLawHalf (the cosine
+// basis walks the Fourier tree at half the frequency)
 __device__ __noinline__ double2 nl_unit_phase_other(int32_t nu, double x) {
     double sn, cs;
-    sincospi(2.0 * law_cdf(nu, x), &sn, &cs);
+    sincospi(((nu & kLawHalf) ? 1.0 : 2.0) * law_cdf(nu, x), &sn, &cs);
     return make_double2(cs, sn);
 }
+// d/du of the node e^{i theta k.u} is i theta k e^{...}: theta = 2 pi, or pi
+// at half frequency
+__device__ __forceinline__ double phase_freq(int32_t nu) { return (nu & kLawHalf) ? M_PI : 2.0 * M_PI; }
 // F^{-1}(u), dF/dx at x and e^{2 pi i F(x)} of the law nu (qr_law)
 __device__ __forceinline__ double nl_icdf(int32_t nu, double u) {
     return nu == QR_LAW_LOGISTIC ? nl_icdf_logistic(u) : nl_icdf_other(nu, u);
@@ -95,17 +100,23 @@ __device__ __noinline__ double nl_sin(double a) { return sin(a); }
 // ---------------------------------------------------------------------------
 // Manufactured problem pieces (closed forms of u, g, h; see qrmc.h)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double fnl(const DevProblem *P, double y, double z2) {
+// f_nl(t, x, y, z) with z2 = |z|^2 and uc = u(t, x) (read by QR_F_PAPER only)
+__device__ __forceinline__ double fnl(const DevProblem *P, double y, double z2, double uc) {
     switch (P->driver) {
     case QR_F_SIN: return P->f_a * nl_sin(y);
     case QR_F_ALLEN_CAHN: return y - y * y * y;
     case QR_F_ZRAT: return P->f_a * z2 / (1.0 + z2) + y / (1.0 + y * y);
+    case QR_F_PAPER: {
+        const double e = y - uc;
+        return fmin(1.0, e * e);
+    }
     default: return 0.0;
     }
 }
 
+// h(t, x) into .x and u(t, x) into .y
 template <int DB>
-__device__ __forceinline__ double h_source(const DevProblem *P, double t, const double *x, int d) {
+__device__ __forceinline__ double2 h_source(const DevProblem *P, double t, const double *x, int d) {
     const double E = P->sol_A * nl_exp(-P->sol_c * (P->T - t));
     double th = P->sol_p, bw = 0.0;
 #pragma unroll
@@ -117,10 +128,11 @@ __device__ __forceinline__ double h_source(const DevProblem *P, double t, const 
     }
     const double2 sc = nl_sincos(th);
     const double sn = sc.x, cs = sc.y;
-    const double u = E * cs;
+    const double v = E * cs;         // u - B: the offset drops out of every derivative
+    const double u = v + P->sol_B;
     const double gscale = -E * sn;  // grad u = gscale * w
     const double z2 = gscale * gscale * P->sw2;
-    return -(P->sol_c * u + gscale * bw - 0.5 * u * P->sw2) - fnl(P, u, z2);
+    return make_double2(-(P->sol_c * v + gscale * bw - 0.5 * v * P->sw2) - fnl(P, u, z2, u), u);
 }
 
 template <int DB>
@@ -136,7 +148,7 @@ __device__ __forceinline__ double g_term(const DevProblem *P, const double *x, i
         for (int l = 0; l < DB; ++l)
             if (l < d) grad[l] = -P->sol_A * sn * P->sol_w[l];
     }
-    return P->sol_A * cs;
+    return fma(P->sol_A, cs, P->sol_B);
 }
 
 __device__ __forceinline__ double clamp_abs(double y, double L) {

@@ -22,6 +22,8 @@ static int32_t part_weight(int32_t kind, const int32_t *v, int n) {
             w *= std::max(1, m);
         else if (kind == QR_SET_HC_1P)
             w *= 1 + m;
+        else if (kind == QR_SET_TOTAL)
+            w += m;
     }
     return w;
 }
@@ -360,7 +362,8 @@ void fac_path_kernel(const DevProblem *__restrict__ P0, const FacDev F,
         const double tj = Pj->t[j];
         const double dt = Pj->t[j + 1] - tj;
         const double sq = sqrt(dt);
-        const double hj = h_source<DB>(Pj, tj, x, d);
+        const double2 hu = h_source<DB>(Pj, tj, x, d);
+        const double hj = hu.x, uj = hu.y;
         {
             PhiloxStream rs(seed, 0u, (uint64_t)m, (uint32_t)i, (uint32_t)(d + (j - i) * nbm));
 #pragma unroll
@@ -449,7 +452,7 @@ void fac_path_kernel(const DevProblem *__restrict__ P0, const FacDev F,
             y = g_term<DB>(Pj, x, d, nullptr);
         }
         const double yc = clamp_abs(y, Pj->clamp);
-        S = fma(fnl(Pj, yc, 0.0) + hj, dt, S);
+        S = fma(fnl(Pj, yc, 0.0, uj) + hj, dt, S);
     }
     S += g_term<DB>(P0, x, d, nullptr);
     if (g == 0 && m < M) S_out[m] = S;

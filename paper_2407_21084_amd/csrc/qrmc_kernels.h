@@ -78,6 +78,12 @@ hipError_t launch_gather(const double *alpha, int32_t row0, int32_t nrows, int64
                          int64_t nfuncs, const int32_t *canon_of_trav, double2 *alpha_int,
                          hipStream_t s);
 hipError_t launch_pad(int32_t nrows, int64_t nrep, int64_t ld, double2 *alpha_int, hipStream_t s);
+// cosine rows [row0, row0 + nrows) of acos ([.][ncos]) into carrier rows of
+// acar ([.][2 nrep - 1]); one carrier row into one cosine row
+hipError_t launch_cos_expand(const double *acos, int32_t row0, int32_t nrows, int64_t ncos, int64_t nrep,
+                             const int32_t *cos_of_rep, const double *rep_scale, double *acar, hipStream_t s);
+hipError_t launch_cos_fold(const double *acar_row, int64_t ncos, const int32_t *fold_off, const int32_t *fold_idx,
+                           const double *rep_scale, double *acos_row, hipStream_t s);
 // damp: the problem's damping exponent q is non-zero
 hipError_t launch_path(int db, int cap, bool grad, bool damp, const PathArgs &a, hipStream_t s);
 // tasks must have been cut to proj_shape(W.d).task_max nodes (task_max is checked)
@@ -117,8 +123,9 @@ hipError_t launch_moments(int64_t n, const double *t, double *partial, hipStream
 size_t mfma_path_lds_bytes(int32_t d);
 hipError_t launch_mfma_path(int db, int cap, bool grad, int prec, const MfmaArgs &a, hipStream_t s);
 int mfma_tile_groups(int db, int d, bool grad);
+// half: the cosine basis's half-frequency walk (gradient weights pi k, not 2 pi k)
 hipError_t launch_pack_tiles(int prec, const double2 *alpha_int_row, int64_t nrep, const int32_t *trav,
-                             int32_t d, int32_t T, uint2 *out, hipStream_t s);
+                             int32_t d, int32_t T, bool half, uint2 *out, hipStream_t s);
 size_t path_lds_bytes(int32_t d, bool grad, int P);
 // paths the path kernel's grid covers (M rounded up to whole blocks)
 int64_t path_state_ld(int64_t M, bool grad);

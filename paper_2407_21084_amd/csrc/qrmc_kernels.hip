@@ -93,15 +93,19 @@ struct LanePts {
 
 // ---------------------------------------------------------------------------
 // The walk.  A node with budget Pb (product of the weights of its non-zero
-// coordinates) extends along coordinate l with magnitudes m = 1, 2, ... as
-// long as w = Pb (m + b) <= L; the child's budget is w (hyperbolic crosses)
-// or stays 1 (tensor set, c = 0); the child has children iff its budget is
-// at most Lc.  See make_walk in qrmc_common.h.
+// coordinates, or 1 + their sum for the total-degree set) extends along
+// coordinate l with magnitudes m = 1, 2, ... as long as its child's budget
+// w = Pb (m + b) (or Pb + m) is at most L; the child's budget is w
+// (hyperbolic crosses, total degree) or stays 1 (tensor set, c = 0); the
+// child has children iff its budget is at most Lc.  See make_walk in
+// qrmc_common.h.
 // ---------------------------------------------------------------------------
 template <int T, int CAP, int P, class R, class Sink>
 __device__ __forceinline__ typename Sink::Acc visit(const Pts<P, R> &parent, const int p, const int Pb,
                                                     const Walk &W, const LanePts<P, R> &L, Sink &sink) {
     typename Sink::Acc acc{};
+    // (the budget step between magnitudes, W.a ? 1 : Pb, is formed at each
+    // increment: a value held across the recursion would cost registers)
 #pragma unroll 1
     for (int l = p + 1; l < W.d; ++l) {
         const bool more = l + 1 < W.d;
@@ -128,18 +132,18 @@ __device__ __forceinline__ typename Sink::Acc visit(const Pts<P, R> &parent, con
                 // since w grows with the magnitude; the rest of the chain, all
                 // leaves, runs without the recursion test.
                 static_assert(!Sink::kGrad, "split chains are value-only");
-                int w = Pb * (1 + W.b);
+                int w = Pb * (1 + W.b) + W.a;
                 if constexpr (T + 1 < CAP) {
                     const int wc = more ? (W.c ? W.Lc : (Pb <= W.Lc ? W.L : 0)) : 0;
 #pragma unroll 1
-                    for (; w <= W.L && w <= wc; w += Pb) {
+                    for (; w <= W.L && w <= wc; w += W.a ? 1 : Pb) {
                         v = cmul(v, es);
                         sink.node(v, acc);
                         Sink::add(acc, visit<T + 1, CAP, P>(v, l, W.c ? w : Pb, W, L, sink));
                     }
                 }
 #pragma unroll 1
-                for (; w <= W.L; w += Pb) {
+                for (; w <= W.L; w += W.a ? 1 : Pb) {
                     v = cmul(v, es);
                     sink.node(v, acc);
                 }
@@ -147,7 +151,7 @@ __device__ __forceinline__ typename Sink::Acc visit(const Pts<P, R> &parent, con
                 // largest magnitude whose node has children (see above)
                 [[maybe_unused]] const int wc = more ? (W.c ? W.Lc : (Pb <= W.Lc ? W.L : 0)) : 0;
 #pragma unroll 1
-                for (int w = Pb * (1 + W.b); w <= W.L; w += Pb) {
+                for (int w = Pb * (1 + W.b) + W.a; w <= W.L; w += W.a ? 1 : Pb) {
                     v = cmul(v, es);
                     if constexpr (Sink::kGrad) {
                         R gs[P];
@@ -395,8 +399,11 @@ void path_kernel(
             double x[DB];
 #pragma unroll
             for (int l = 0; l < DB; ++l) x[l] = (l < d) ? xg[l * ldx + q * kPathBlock] : 0.0;
-            // the source term only needs X_j
-            hj[q] = h_source<DB>(Pj, tj, x, d);
+            // the source term only needs X_j; the Sec. 5 driver also reads
+            // u(t_j, X_j), parked in the path state's row d
+            const double2 hu = h_source<DB>(Pj, tj, x, d);
+            hj[q] = hu.x;
+            if (Pj->driver == QR_F_PAPER) xg[d * ldx + q * kPathBlock] = hu.y;
             // Euler step, eq (markov:euler): normals r = d + (j-i) nbm + k
             PhiloxStream rs(seed, 0u, (uint64_t)m, (uint32_t)i, (uint32_t)(d + (j - i) * nbm));
 #pragma unroll
@@ -439,7 +446,7 @@ void path_kernel(
                         gx[l] = 0.0;
                         if (l < d) {
                             const double xv = xg[l * ldx + q * kPathBlock];
-                            gx[l] = 2.0 * M_PI * L.g(l, q) * nl_pdf(Pj->nu, xv);
+                            gx[l] = phase_freq(Pj->nu) * L.g(l, q) * nl_pdf(Pj->nu, xv);
                             if constexpr (DAMP) gx[l] = D.x * fma(y[q] * D.y, xv, gx[l]);
                         }
                     }
@@ -475,7 +482,8 @@ void path_kernel(
 #pragma unroll
         for (int q = 0; q < P; ++q) {
             const double yq = clamp_abs(y[q], Pj->clamp);
-            const double f = fnl(Pj, yq, z2[q]) + hj[q];
+            const double uc = Pj->driver == QR_F_PAPER ? xg[d * ldx + q * kPathBlock] : 0.0;
+            const double f = fnl(Pj, yq, z2[q], uc) + hj[q];
             S[q] = fma(f, dt, S[q]);
         }
     }
@@ -766,7 +774,7 @@ __global__ __launch_bounds__(kPathBlock) void eval_kernel(const Walk W,
     y[p] = yv;
     if constexpr (GRAD) {
         for (int l = 0; l < d; ++l) {
-            grad[l * n + p] = 2.0 * M_PI * L.g(l, 0) * nl_pdf(W.nu, x[l * n + p]);
+            grad[l * n + p] = phase_freq(W.nu) * L.g(l, 0) * nl_pdf(W.nu, x[l * n + p]);
         }
     }
 }
@@ -891,12 +899,14 @@ __global__ __launch_bounds__(kPathBlock) void mfma_path_kernel(
         asm volatile("" : "+s"(Pj));
         const double tj = Pj->t[j];
         const double dt = Pj->t[j + 1] - tj;
-        double hj;
+        double hj, uj;
         {
             double x[DB];
 #pragma unroll
             for (int l = 0; l < DB; ++l) x[l] = (l < d) ? xs[l * kPathBlock] : 0.0;
-            hj = h_source<DB>(Pj, tj, x, d);
+            const double2 hu = h_source<DB>(Pj, tj, x, d);
+            hj = hu.x;
+            uj = hu.y;
             const double sq = sqrt(dt);
             PhiloxStream rs(seed, 0u, (uint64_t)m, (uint32_t)i, (uint32_t)(d + (j - i) * nbm));
 #pragma unroll
@@ -964,7 +974,7 @@ __global__ __launch_bounds__(kPathBlock) void mfma_path_kernel(
                 }
             }
         }
-        S = fma(fnl(Pj, clamp_abs(y, Pj->clamp), z2) + hj, dt, S);
+        S = fma(fnl(Pj, clamp_abs(y, Pj->clamp), z2, uj) + hj, dt, S);
     }
     double x[DB];
 #pragma unroll
@@ -981,12 +991,13 @@ size_t mfma_path_lds_bytes(int32_t d) {
 // Coefficient tiles of one row: tile[g][t][lane] holds, for lane 4b + r, the
 // 16-bit coefficients of right-hand side 4t + r on nodes 32g + 2b and
 // 32g + 2b + 1: (Re, Im) weights, ybar = sum a.x Re + a.y Im and
-// d ybar / d u_l = sum 2 pi k_l (a.y Re - a.x Im).  Nodes past nrep and
-// right-hand sides past d are zero.
+// d ybar / d u_l = sum theta k_l (a.y Re - a.x Im), theta = 2 pi (pi for
+// the cosine basis's half-frequency walk).  Nodes past nrep and right-hand
+// sides past d are zero.
 template <int PREC>
 __global__ void pack_tiles_kernel(const double2 *__restrict__ alpha_int_row, int64_t nrep,
                                   const int32_t *__restrict__ trav, int32_t d, int32_t T,
-                                  int64_t ngroups, uint2 *__restrict__ out) {
+                                  int64_t ngroups, double theta, uint2 *__restrict__ out) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= ngroups * T * 64) return;
     const int lane = (int)(idx % 64), t = (int)((idx / 64) % T);
@@ -1002,7 +1013,7 @@ __global__ void pack_tiles_kernel(const double2 *__restrict__ alpha_int_row, int
                 cr = a.x;
                 ci = a.y;
             } else if (rhs <= d) {
-                const double k2p = 2.0 * M_PI * (double)trav[n * d + rhs - 1];
+                const double k2p = theta * (double)trav[n * d + rhs - 1];
                 cr = k2p * a.y;
                 ci = -k2p * a.x;
             }
@@ -1044,7 +1055,7 @@ __global__ void sm_euler_kernel(const DevProblem *__restrict__ P0, int32_t i, in
     double x[DB];
 #pragma unroll
     for (int l = 0; l < DB; ++l) x[l] = (l < d) ? xg[l * M + m] : 0.0;
-    H[m] = h_source<DB>(P0, tj, x, d);
+    H[m] = h_source<DB>(P0, tj, x, d).x;
     PhiloxStream rs(seed, 0u, (uint64_t)m, (uint32_t)i, (uint32_t)(d + (j - i) * nbm));
 #pragma unroll
     for (int l = 0; l < DB; ++l)
@@ -1070,7 +1081,7 @@ __global__ void sm_accum_kernel(const DevProblem *__restrict__ P0, int32_t j, in
     const int64_t m = m0 + k;
     const double dt = P0->t[j + 1] - P0->t[j];
     const double y = y64 ? y64[k] : mu + sigma * (double)y32[k];
-    S[m] = fma(fnl(P0, clamp_abs(y, P0->clamp), 0.0) + H[m], dt, S[m]);
+    S[m] = fma(fnl(P0, clamp_abs(y, P0->clamp), 0.0, 0.0) + H[m], dt, S[m]);
 }
 
 // the last step: y = g(X_N), then S += g(X_N)
@@ -1085,7 +1096,7 @@ __global__ void sm_final_kernel(const DevProblem *__restrict__ P0, int64_t M, co
 #pragma unroll
     for (int l = 0; l < DB; ++l) x[l] = (l < d) ? xg[l * M + m] : 0.0;
     const double g = g_term<DB>(P0, x, d, nullptr);
-    const double Sj = fma(fnl(P0, clamp_abs(g, P0->clamp), 0.0) + H[m], dt, S[m]);
+    const double Sj = fma(fnl(P0, clamp_abs(g, P0->clamp), 0.0, 0.0) + H[m], dt, S[m]);
     S[m] = Sj + g;
 }
 
@@ -1231,9 +1242,10 @@ __global__ __launch_bounds__(kPathBlock) void batched_path_kernel(
                 }
             }
             const double2 sc = nl_sincos(th);
-            uval = E * sc.y;
+            const double v = E * sc.y;  // u - B
             const double gscale = -E * sc.x;
-            hbase = -(Pj->sol_c * uval + gscale * bw - 0.5 * uval * Pj->sw2);
+            hbase = -(Pj->sol_c * v + gscale * bw - 0.5 * v * Pj->sw2);
+            uval = v + Pj->sol_B;
         }
         {
             const double sq = sqrt(dt);
@@ -1341,6 +1353,66 @@ hipError_t launch_gather(const double *alpha, int32_t row0, int32_t nrows, int64
     if (total == 0) return hipSuccess;
     hipLaunchKernelGGL(gather_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, s, alpha, row0,
                        nrows, nrep, ld, nfuncs, canon_of_trav, alpha_int);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Cosine basis over N^d and its carrier.  For k in N^d with n non-zero
+// coordinates, phi_k = prod_l sqrt2^{[k_l > 0]} cos(pi k_l u_l) is, by the
+// product-to-sum identity, 2^{(1-n)/2} times the sum of sqrt2 cos(pi k'.u)
+// over the 2^{n-1} representatives k' of Z^d with |k'_l| = k_l.  A cosine
+// row therefore expands to the carrier row (Fourier canonical layout at half
+// frequency) carrier[2c-1] = s_c alpha[k(c)], carrier[2c] = 0,
+// carrier[0] = alpha[0] (s_c = 2^{(1-n)/2}), and the projection of S on phi_k
+// folds from the carrier's projections on sqrt2 cos(pi k'.u):
+// alpha[k] = s_k sum_{c of k} carrier[2c-1] (fixed order).
+// ---------------------------------------------------------------------------
+__global__ void cos_expand_kernel(const double *__restrict__ acos, int32_t row0, int32_t nrows, int64_t ncos,
+                                  int64_t nrep, const int32_t *__restrict__ cos_of_rep,
+                                  const double *__restrict__ rep_scale, double *__restrict__ acar) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)nrows * nrep) return;
+    const int64_t row = row0 + idx / nrep, c = idx % nrep;
+    const double a = acos[row * ncos + cos_of_rep[c]];
+    double *dst = acar + row * (2 * nrep - 1);
+    if (c == 0) {
+        dst[0] = a;
+    } else {
+        dst[2 * c - 1] = rep_scale[c] * a;
+        dst[2 * c] = 0.0;
+    }
+}
+
+__global__ void cos_fold_kernel(const double *__restrict__ acar_row, int64_t ncos,
+                                const int32_t *__restrict__ fold_off, const int32_t *__restrict__ fold_idx,
+                                const double *__restrict__ rep_scale, double *__restrict__ acos_row) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ncos) return;
+    const int32_t b = fold_off[k], e = fold_off[k + 1];
+    const int32_t c0 = fold_idx[b];
+    if (c0 == 0) {
+        acos_row[k] = acar_row[0];
+        return;
+    }
+    double sum = 0.0;
+    for (int32_t q = b; q < e; ++q) sum += acar_row[2 * (int64_t)fold_idx[q] - 1];
+    acos_row[k] = rep_scale[c0] * sum;
+}
+
+hipError_t launch_cos_expand(const double *acos, int32_t row0, int32_t nrows, int64_t ncos, int64_t nrep,
+                             const int32_t *cos_of_rep, const double *rep_scale, double *acar, hipStream_t s) {
+    const int64_t total = (int64_t)nrows * nrep;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(cos_expand_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, s, acos, row0, nrows, ncos,
+                       nrep, cos_of_rep, rep_scale, acar);
+    return hipGetLastError();
+}
+
+hipError_t launch_cos_fold(const double *acar_row, int64_t ncos, const int32_t *fold_off, const int32_t *fold_idx,
+                           const double *rep_scale, double *acos_row, hipStream_t s) {
+    if (ncos == 0) return hipSuccess;
+    hipLaunchKernelGGL(cos_fold_kernel, dim3(blocks_for(ncos, 256)), dim3(256), 0, s, acar_row, ncos, fold_off,
+                       fold_idx, rep_scale, acos_row);
     return hipGetLastError();
 }
 
@@ -1614,15 +1686,16 @@ hipError_t launch_mfma_path(int db, int cap, bool grad, int prec, const MfmaArgs
 
 
 hipError_t launch_pack_tiles(int prec, const double2 *alpha_int_row, int64_t nrep, const int32_t *trav,
-                             int32_t d, int32_t T, uint2 *out, hipStream_t s) {
+                             int32_t d, int32_t T, bool half, uint2 *out, hipStream_t s) {
     const int64_t ngroups = (nrep + kMfmaGroup - 1) / kMfmaGroup;
     const int64_t total = ngroups * T * 64;
+    const double theta = half ? M_PI : 2.0 * M_PI;
     if (prec == QR_PREC_BF16)
         hipLaunchKernelGGL(pack_tiles_kernel<QR_PREC_BF16>, dim3(blocks_for(total, 256)), dim3(256), 0, s,
-                           alpha_int_row, nrep, trav, d, T, ngroups, out);
+                           alpha_int_row, nrep, trav, d, T, ngroups, theta, out);
     else if (prec == QR_PREC_F16)
         hipLaunchKernelGGL(pack_tiles_kernel<QR_PREC_F16>, dim3(blocks_for(total, 256)), dim3(256), 0, s,
-                           alpha_int_row, nrep, trav, d, T, ngroups, out);
+                           alpha_int_row, nrep, trav, d, T, ngroups, theta, out);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -24,12 +24,14 @@ MLP_IN, MLP_HIDDEN = 16, 256
 MLP_NPARAMS = MLP_HIDDEN * MLP_IN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
 MLP_MAX_BATCH = 65536
 
-SET_TENSOR, SET_HC_MAX, SET_HC_1P = 0, 1, 2
-SET_KINDS = {"tensor": SET_TENSOR, "hc_max": SET_HC_MAX, "hc_1p": SET_HC_1P}
-F_LINEAR, F_SIN, F_ALLEN_CAHN, F_ZRAT = 0, 1, 2, 3
+SET_TENSOR, SET_HC_MAX, SET_HC_1P, SET_TOTAL = 0, 1, 2, 3
+SET_KINDS = {"tensor": SET_TENSOR, "hc_max": SET_HC_MAX, "hc_1p": SET_HC_1P, "total": SET_TOTAL}
+F_LINEAR, F_SIN, F_ALLEN_CAHN, F_ZRAT, F_PAPER = 0, 1, 2, 3, 4
+BASIS_FOURIER, BASIS_COSINE = 0, 1
+BASES = {"fourier": BASIS_FOURIER, "cosine": BASIS_COSINE}
 LAW_LOGISTIC, LAW_STUDENT2, LAW_CAUCHY = 0, 1, 2
 LAWS = {"logistic": LAW_LOGISTIC, "student2": LAW_STUDENT2, "cauchy": LAW_CAUCHY}
-DRIVERS = {"linear": F_LINEAR, "sin": F_SIN, "allen_cahn": F_ALLEN_CAHN, "zrat": F_ZRAT}
+DRIVERS = {"linear": F_LINEAR, "sin": F_SIN, "allen_cahn": F_ALLEN_CAHN, "zrat": F_ZRAT, "paper": F_PAPER}
 
 STATUS = {0: "QR_OK", -1: "QR_EINVAL", -2: "QR_ENOMEM", -3: "QR_EDEVICE", -4: "QR_ERANGE",
           -5: "QR_ENUMERIC", -6: "QR_ENOTSUP"}
@@ -49,7 +51,7 @@ EXPORTS = ["qr_last_error", "qr_version", "qr_build_basis", "qr_build_basis_law"
            "qr_solve_prec", "qr_mlp_init", "qr_mlp_features", "qr_mlp_forward", "qr_mlp_loss_grad",
            "qr_mlp_adam", "qr_solve_learned", "qr_solve_batched",
            "qr_basis_upload", "qr_eval_noalloc", "qr_ctx_set_prec_kernel", "qr_basis_factored",
-           "qr_ctx_numeric_status",
+           "qr_ctx_numeric_status", "qr_build_basis_cos", "qr_basis_family_of",
            "qr_host_uniform", "qr_host_norm_icdf", "qr_host_philox"]
 
 
@@ -69,6 +71,7 @@ class Problem(C.Structure):
         ("sol_A", C.c_double), ("sol_c", C.c_double), ("sol_p", C.c_double),
         ("sol_w", C.c_double * MAX_D),
         ("damping_q", C.c_double),
+        ("sol_B", C.c_double),
     ]
 
 
@@ -106,6 +109,8 @@ _SIGS = {
     "qr_build_basis": (C.c_int, [_I32, _I32, _I32, C.POINTER(_P)]),
     "qr_build_basis_law": (C.c_int, [_I32, _I32, _I32, _I32, C.POINTER(_P)]),
     "qr_basis_law": (C.c_int, [_P, C.POINTER(_I32)]),
+    "qr_build_basis_cos": (C.c_int, [_I32, _I32, _I32, _I32, C.POINTER(_P)]),
+    "qr_basis_family_of": (C.c_int, [_P, C.POINTER(_I32)]),
     "qr_basis_info": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I32)]),
     "qr_basis_indices": (C.c_int, [_P, _P]),
     "qr_basis_free": (None, [_P]),
@@ -180,16 +185,22 @@ def host_philox(ctr, key) -> np.ndarray:
 
 
 class Basis:
-    """Index set Gamma and its basis metadata for the sampling law `law`
-    (qr_build_basis_law)."""
+    """Index set Gamma and its basis metadata for the sampling law `law`:
+    the Fourier functions over Z^d (qr_build_basis_law), or the paper's cosine
+    functions over N^d with basis="cosine" (qr_build_basis_cos)."""
 
-    def __init__(self, d: int, kind, level: int, law="logistic"):
+    def __init__(self, d: int, kind, level: int, law="logistic", basis="fourier"):
         kind = SET_KINDS[kind] if isinstance(kind, str) else int(kind)
         law = LAWS[law] if isinstance(law, str) else int(law)
+        basis = BASES[basis] if isinstance(basis, str) else int(basis)
         h = _P()
-        _check(_lib.qr_build_basis_law(d, kind, level, law, C.byref(h)))
+        build = _lib.qr_build_basis_cos if basis == BASIS_COSINE else _lib.qr_build_basis_law
+        _check(build(d, kind, level, law, C.byref(h)))
         self._h = h
         self.d, self.kind, self.level = d, kind, level
+        fam = _I32()
+        _check(_lib.qr_basis_family_of(h, C.byref(fam)))
+        self.family = fam.value
         got = _I32()
         _check(_lib.qr_basis_law(h, C.byref(got)))
         self.law = got.value
@@ -224,7 +235,8 @@ class Basis:
 
 
 def make_problem(d, N, T=None, times=None, sigma=None, b0=None, b1=None, driver="sin", f_a=0.0,
-                 sol_A=1.0, sol_c=1.0, sol_p=0.0, sol_w=None, clamp=math.inf, damping_q=0.0) -> Problem:
+                 sol_A=1.0, sol_c=1.0, sol_p=0.0, sol_w=None, clamp=math.inf, damping_q=0.0,
+                 sol_B=0.0) -> Problem:
     sigma = np.eye(d) if sigma is None else np.asarray(sigma, dtype=np.float64)
     nbm = sigma.shape[1]
     if times is None:
@@ -244,15 +256,16 @@ def make_problem(d, N, T=None, times=None, sigma=None, b0=None, b1=None, driver=
             p.sigma[l * nbm + k] = sigma[l, k]
     p.sol_A, p.sol_c, p.sol_p = sol_A, sol_c, sol_p
     p.damping_q = damping_q
+    p.sol_B = sol_B
     return p
 
 
 def problem_from(w) -> Problem:
     """Marshal any object with the workload attributes (d, N, T, sigma, b0,
-    b1, driver, f_a, sol_*, clamp, optionally damping_q) into a qr_problem."""
+    b1, driver, f_a, sol_*, clamp, optionally damping_q and sol_B) into a qr_problem."""
     return make_problem(w.d, w.N, T=w.T, sigma=w.sigma, b0=w.b0, b1=w.b1, driver=w.driver,
                         f_a=w.f_a, sol_A=w.sol_A, sol_c=w.sol_c, sol_p=w.sol_p, sol_w=w.sol_w,
-                        clamp=w.clamp, damping_q=getattr(w, "damping_q", 0.0))
+                        clamp=w.clamp, damping_q=getattr(w, "damping_q", 0.0), sol_B=getattr(w, "sol_B", 0.0))
 
 
 # ---------------------------------------------------------------------------

@@ -1,0 +1,246 @@
+"""The paper's own variant on the GPU: the cosine basis over N^d (Sec. 2.2,
+Lemma 2.1, eq (phi:dim:d)) on Gamma_F, Gamma_H, the (1+|k|) cross and
+Gamma_T (Sec. 2.3.3), with the Student mu = 2 law and the Sec. 5 benchmark
+driver (eq (pde2OnlyY)), against the oracle on the same Philox streams.
+
+FP64 tolerance: as every FP64 parity test (gpu_common.TOL = 1e-10 of
+max(|alpha_k|, A_k)).  The kernels reach the cosine functions through their
+Z^d carrier at half frequency, so the sums run in another order and over
+more terms than the oracle's; rounding stays at a few ulps of the terms.
+Reduced precision: the factored/walk tolerances of the Fourier basis (2u and
+u relative to the row), since the carrier rows are the kernels' input.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from gpu_common import TOL, assert_alpha, dev, env, host, rel_err, say  # noqa: F401 (env is a fixture)
+
+pytestmark = pytest.mark.gpu
+
+UNIT = {"bf16": 2.0 ** -8, "f16": 2.0 ** -11}
+
+SETS = [
+    (1, "tensor", 100, "student2"),
+    (2, "total", 6, "logistic"),
+    (3, "hc_max", 7, "cauchy"),
+    (4, "hc_1p", 12, "student2"),
+    (5, "total", 4, "student2"),
+]
+
+
+@pytest.mark.parametrize("grad", [False, True])
+@pytest.mark.parametrize("case", SETS, ids=[f"d{c[0]}-{c[1]}{c[2]}-{c[3]}" for c in SETS])
+def test_cosine_eval(env, case, grad):
+    """ybar = sum_k alpha_k phi_k and its x-gradient at points of the law."""
+    Q, ctx, torch = env
+    d, kind, level, law = case
+    say(f"cosine eval d={d} {kind}{level} {law} grad={grad}")
+    b = Q.Basis(d, kind, level, law=law, basis="cosine")
+    reps = O.enumerate_set(d, kind, level, nonneg=True, reps_only=False)
+    alpha = W.synthetic_alpha(b.n_funcs, 1, seed=5)[0]
+    n = 1000
+    x = W.law_points(n, d, law, seed=2)
+    y = torch.empty(n, dtype=torch.float64, device="cuda")
+    g = torch.empty((d, n), dtype=torch.float64, device="cuda") if grad else None
+    ctx.eval(b, dev(torch, alpha), dev(torch, x.T), y, g)
+    torch.cuda.synchronize()
+    if grad:
+        ry, rg = O.evaluate(reps, alpha, x, grad=True, law=law, basis="cosine")
+        # each term of d ybar / d u_l is bounded by |alpha_k| 2^{d/2} pi k_l
+        scale = np.abs(alpha).sum() * 2 ** (d / 2) * math.pi * level
+        assert np.abs(host(g).T - rg).max() <= TOL * scale
+    else:
+        ry = O.evaluate(reps, alpha, x, law=law, basis="cosine")
+    assert np.abs(host(y) - ry).max() <= TOL * np.abs(alpha).sum() * 2 ** (d / 2)
+
+
+@pytest.mark.parametrize("case", SETS, ids=[f"d{c[0]}-{c[1]}{c[2]}-{c[3]}" for c in SETS])
+def test_cosine_project(env, case):
+    """alpha_k = (1/n) sum_p s_p phi_k(x_p) on given samples."""
+    Q, ctx, torch = env
+    d, kind, level, law = case
+    say(f"cosine project d={d} {kind}{level} {law}")
+    b = Q.Basis(d, kind, level, law=law, basis="cosine")
+    reps = O.enumerate_set(d, kind, level, nonneg=True, reps_only=False)
+    n = 3001
+    x = W.law_points(n, d, law, seed=4)
+    s = np.random.default_rng(9).standard_normal(n)
+    a = torch.empty(b.n_funcs, dtype=torch.float64, device="cuda")
+    ctx.project(b, dev(torch, x.T), dev(torch, s), a)
+    torch.cuda.synchronize()
+    ref, absum = O.project(reps, x, s, with_abs=True, law=law, basis="cosine")
+    assert_alpha(host(a), ref, absum, what=f"project d={d} {kind}{level}")
+
+
+def _paper(d, N, kind, level, M, seed=3, law="student2"):
+    return W.paper_benchmark(d, N, kind, level, M, seed=seed).with_(law=law)
+
+
+STEPS = [
+    (1, 20, "tensor", 100, 20_000, 19),
+    (1, 20, "tensor", 100, 20_000, 17),
+    (2, 6, "total", 8, 3000, 0),
+    (3, 5, "hc_max", 9, 2500, 2),
+    (3, 5, "total", 5, 2049, 1),
+    (5, 4, "hc_1p", 12, 1500, 0),
+]
+
+
+@pytest.mark.parametrize("case", STEPS, ids=[f"d{c[0]}-{c[2]}{c[3]}-M{c[4]}-i{c[5]}" for c in STEPS])
+def test_cosine_backward_step_paper_driver(env, case):
+    """One backward iteration of the Sec. 5 benchmark (f = min(1, (y - u)^2),
+    u(t_j, X_j) read along the paths) with given later rows."""
+    Q, ctx, torch = env
+    d, N, kind, level, M, i = case
+    w = _paper(d, N, kind, level, M)
+    say(f"cosine backward_step {w.name} M={M} i={i}")
+    b = Q.Basis(w.d, w.set_kind, w.level, law=w.law, basis="cosine")
+    reps = O.reps_for(w)
+    assert b.n_funcs == reps.shape[0]
+    alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=d + i, scale=0.3)
+    alpha[:, 0] += 1.6  # rows near u, so that the min(1, .) clips only sometimes
+    a = dev(torch, alpha)
+    ctx.backward_step(Q.problem_from(w), b, i, w.M, w.seed, a)
+    torch.cuda.synchronize()
+    ref, absum, _, _ = O.backward_step(w, reps, i, w.M, w.seed, alpha.copy())
+    assert_alpha(host(a)[i], ref, absum, what=f"{w.name} row {i}")
+    # the rows it only reads are untouched
+    others = [j for j in range(w.N) if j != i]
+    assert np.array_equal(host(a)[others], alpha[others])
+
+
+@pytest.mark.parametrize("case", [(1, 20, "tensor", 100, 20_000), (3, 5, "total", 5, 3000),
+                                  (2, 6, "hc_max", 12, 4000)], ids=lambda c: f"d{c[0]}-{c[2]}{c[3]}")
+def test_cosine_solve_paper_driver(env, case):
+    """Full backward induction of the benchmark: every row against the
+    oracle's solve (each row's cancellation bound from the oracle's own step
+    on its rows)."""
+    Q, ctx, torch = env
+    d, N, kind, level, M = case
+    w = _paper(d, N, kind, level, M)
+    say(f"cosine solve {w.name} M={M}")
+    b = Q.Basis(w.d, w.set_kind, w.level, law=w.law, basis="cosine")
+    reps = O.reps_for(w)
+    a = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device="cuda")
+    ctx.solve(Q.problem_from(w), b, w.M, w.seed, a)
+    torch.cuda.synchronize()
+    got = host(a)
+    ref = O.solve(w, reps)
+    for i in sorted({w.N - 1, w.N // 2, 0}, reverse=True):
+        _, absum, _, _ = O.backward_step(w, reps, i, w.M, w.seed, ref.copy())
+        assert_alpha(got[i], ref[i], absum, what=f"solve {w.name} row {i}")
+
+
+def test_cosine_path_responses_and_fourier_total_set(env):
+    """Responses S_m of the benchmark along the paths (cosine rows expanded to
+    the carrier), and a Fourier-basis backward step on Gamma_T over Z^d."""
+    Q, ctx, torch = env
+    w = _paper(2, 6, "total", 6, 777)
+    b = Q.Basis(w.d, w.set_kind, w.level, law=w.law, basis="cosine")
+    reps = O.reps_for(w)
+    alpha = W.synthetic_alpha(b.n_funcs, w.N, seed=21, scale=0.3)
+    alpha[:, 0] += 1.6
+    i = 1
+    s = torch.empty(w.M, dtype=torch.float64, device="cuda")
+    ctx.path_responses(Q.problem_from(w), b, i, w.M, w.seed, dev(torch, alpha), s)
+    torch.cuda.synchronize()
+    ref = np.array([O.path_response(w, reps, i, w.seed, m, alpha) for m in range(w.M)])
+    assert np.abs(host(s) - ref).max() <= TOL * max(1.0, np.abs(ref).max())
+
+    wf = W.Workload(name="fourier-total", d=3, N=4, T=1.0, sigma=[[0.5 if r == c else 0.0 for c in range(3)]
+                                                                    for r in range(3)],
+                    b0=[0.0] * 3, b1=[0.0] * 3, set_kind="total", level=5, M=2500, driver="sin", f_a=0.5,
+                    sol_A=1.0, sol_c=1.0, sol_p=0.0, sol_w=[1.0, 1.0, 0.0], seed=7)
+    bf = Q.Basis(wf.d, wf.set_kind, wf.level)
+    rf = O.reps_for(wf)
+    af = W.synthetic_alpha(bf.n_funcs, wf.N, seed=8, scale=0.2)
+    t = dev(torch, af)
+    ctx.backward_step(Q.problem_from(wf), bf, 1, wf.M, wf.seed, t)
+    torch.cuda.synchronize()
+    ref, absum, _, _ = O.backward_step(wf, rf, 1, wf.M, wf.seed, af.copy())
+    assert_alpha(host(t)[1], ref, absum, what="fourier total row 1")
+
+
+@pytest.mark.parametrize("kernel", ["factored", "walk"])
+@pytest.mark.parametrize("prec", ["bf16", "f16"])
+def test_cosine_reduced_precision_solve(env, prec, kernel):
+    """The reduced-precision forms take the cosine basis through its carrier
+    rows: each row of a full solve within the form's rounding bound of the
+    FP64 oracle (2u factored, u walk; relative 2-norm of the row)."""
+    Q, ctx, torch = env
+    w = _paper(3, 5, "total", 5, 4000)
+    say(f"cosine solve {prec} {kernel} {w.name}")
+    b = Q.Basis(w.d, w.set_kind, w.level, law=w.law, basis="cosine")
+    reps = O.reps_for(w)
+    ref = O.solve(w, reps)
+    ctx.set_prec_kernel(kernel)
+    try:
+        a = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device="cuda")
+        ctx.solve_prec(Q.problem_from(w), b, w.M, w.seed, prec, a)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_prec_kernel("auto")
+    got = host(a)
+    tol = (2.0 if kernel == "factored" else 1.0) * UNIT[prec]
+    errs = [rel_err(got[i], ref[i]) for i in range(w.N)]
+    say("   per-row rel err " + " ".join(f"{e:.1e}" for e in errs))
+    assert max(errs) <= tol
+
+
+def test_cosine_unsupported_forms(env):
+    """The batched and learned forms and the allocation-free evaluation do
+    not take the cosine basis or the benchmark driver (QR_ENOTSUP)."""
+    Q, ctx, torch = env
+    w = _paper(2, 4, "tensor", 4, 256)
+    b = Q.Basis(w.d, w.set_kind, w.level, law=w.law, basis="cosine")
+    a = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device="cuda")
+    with pytest.raises(Q.QrError) as e:
+        ctx.solve_learned(Q.problem_from(w), b, w.M, w.seed, a, train_points=256, heldout_points=64,
+                          epochs=1, batch=64)
+    assert e.value.status == -6
+    ctx.basis_upload(b)
+    y = torch.empty(4, dtype=torch.float64, device="cuda")
+    with pytest.raises(Q.QrError) as e:
+        ctx.eval_noalloc(b, a[0], torch.zeros((2, 4), dtype=torch.float64, device="cuda"), y)
+    assert e.value.status == -6
+    wf = w.with_(basis="fourier")
+    bf = Q.Basis(wf.d, wf.set_kind, wf.level, law=wf.law)
+    af = torch.zeros((wf.N, bf.n_funcs), dtype=torch.float64, device="cuda")
+    with pytest.raises(Q.QrError) as e:
+        ctx.solve_batched(Q.problem_from(wf), bf, [(0.0, 2, 4, 256)], wf.seed, af)
+    assert e.value.status == -6
+
+
+def test_paper_d1_accuracy_table_on_gpu(env):
+    """Table d1_accuracy, first row, on the GPU: 50 runs (seeds 0..49) of the
+    d = 1 benchmark at Delta = 0.05, K = 100, M = 2 10^4; the 99 % interval of
+    ybar_0(0) must contain u(0, 0) = 1.6 and overlap the printed
+    [1.578, 1.667], and runs 0..4 equal the oracle's solves at ybar_0(0)."""
+    Q, ctx, torch = env
+    w0 = W.PAPER_D1
+    b = Q.Basis(w0.d, w0.set_kind, w0.level, law=w0.law, basis="cosine")
+    reps = O.reps_for(w0)
+    p = Q.problem_from(w0)
+    a = torch.zeros((w0.N, b.n_funcs), dtype=torch.float64, device="cuda")
+    x0 = torch.zeros((1, 1), dtype=torch.float64, device="cuda")
+    y = torch.empty(1, dtype=torch.float64, device="cuda")
+    ys = []
+    for s in range(50):
+        ctx.solve(p, b, w0.M, s, a)
+        ctx.eval(b, a[0], x0, y)
+        torch.cuda.synchronize()
+        ys.append(float(host(y)[0]))
+        if s < 5:
+            ref = O.solve(w0.with_(seed=s), reps)
+            yr = O.evaluate(reps, ref[0], np.zeros((1, 1)), law="student2", basis="cosine")[0]
+            assert abs(ys[-1] - yr) <= 1e-9 * abs(yr), (s, ys[-1], yr)
+    ys = np.array(ys)
+    m, sd = ys.mean(), ys.std(ddof=1)
+    half = 2.68 * sd / math.sqrt(50)
+    say(f"   ybar_0(0): mean {m:.4f}, 99% interval [{m - half:.4f}, {m + half:.4f}] (paper [1.578, 1.667])")
+    assert m - half <= 1.6 <= m + half
+    assert m - half <= 1.667 and m + half >= 1.578

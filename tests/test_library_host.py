@@ -57,7 +57,8 @@ def test_host_norm_icdf_matches_scipy():
 @pytest.mark.parametrize("d,kind,level", [(1, "tensor", 6), (2, "tensor", 4), (3, "tensor", 2),
                                           (2, "hc_max", 4), (3, "hc_max", 7), (5, "hc_max", 9),
                                           (4, "hc_1p", 12), (6, "hc_1p", 20), (2, "tensor", 0),
-                                          (3, "hc_max", 1)])
+                                          (3, "hc_max", 1), (1, "total", 5), (2, "total", 6),
+                                          (4, "total", 4), (7, "total", 3), (3, "total", 0)])
 def test_basis_enumeration_matches_oracle(d, kind, level):
     b = Q.Basis(d, kind, level)
     ref = O.enumerate_set(d, kind, level)
@@ -73,6 +74,56 @@ def test_configuration_bases_match_oracle(w):
     ref = O.enumerate_set(w.d, w.set_kind, w.level)
     assert np.array_equal(b.indices(), ref)
     assert b.max_nnz <= 8
+
+
+@pytest.mark.parametrize("d,kind,level", [(1, "tensor", 100), (2, "tensor", 4), (3, "hc_max", 7),
+                                          (5, "hc_max", 9), (4, "hc_1p", 12), (2, "total", 6),
+                                          (5, "total", 4), (3, "tensor", 0), (6, "hc_max", 16)])
+def test_cosine_basis_enumeration_matches_oracle(d, kind, level):
+    """The cosine basis over N^d (Sec. 2.2, eq (phi:dim:d)) on the sets of
+    Sec. 2.3.3: its vectors and coefficient order are the oracle's N^d
+    enumeration (lexicographic), and the paper's own cardinality of
+    Gamma_T(DEG) over N^d, binom(DEG + d, d), holds."""
+    b = Q.Basis(d, kind, level, basis="cosine")
+    ref = O.enumerate_set(d, kind, level, nonneg=True, reps_only=False)
+    assert b.family == Q.BASIS_COSINE
+    assert b.n_funcs == b.n_reps == ref.shape[0]
+    assert np.array_equal(b.indices(), ref)
+    if kind == "total":
+        assert b.n_funcs == math.comb(level + d, d)
+    # the Fourier basis of the same set is its carrier: every vector of N^d in
+    # it has 2^{n-1} representatives over Z^d (n non-zero coordinates)
+    f = Q.Basis(d, kind, level)
+    assert f.family == Q.BASIS_FOURIER
+    nnz = np.count_nonzero(ref, axis=1)
+    assert f.n_reps == 1 + int(np.sum(2.0 ** (nnz[nnz > 0] - 1)))
+
+
+def test_cosine_product_to_sum_identity():
+    """The identity the kernels evaluate the cosine basis through: for k in
+    N^d with n non-zero coordinates, prod_l c_{k_l}(u_l) (c_0 = 1,
+    c_m = sqrt2 cos(m pi u)) equals 2^{1 - n/2} times the sum of
+    cos(pi k'.u) over the vectors k' of Z^d with |k'| = k and first non-zero
+    coordinate positive; checked against the oracle's cosine basis values."""
+    rng = np.random.default_rng(3)
+    d, level = 4, 3
+    vecs = O.enumerate_set(d, "tensor", level, nonneg=True, reps_only=False)
+    x = rng.standard_normal(d)
+    u = np.array([0.5 * (1.0 + v / math.sqrt(1.0 + v * v)) for v in x])  # Student mu = 2 CDF
+    phi = O.basis_values(vecs, x, law="student2", basis="cosine")
+    for c, k in enumerate(vecs):
+        nz = np.flatnonzero(k)
+        if nz.size == 0:
+            assert phi[c] == 1.0
+            continue
+        tot = 0.0
+        for signs in range(1 << (nz.size - 1)):
+            kp = k.astype(float).copy()
+            for q in range(1, nz.size):
+                if (signs >> (q - 1)) & 1:
+                    kp[nz[q]] = -kp[nz[q]]
+            tot += math.cos(math.pi * float(kp @ u))
+        assert abs(2.0 ** (1 - nz.size / 2) * tot - phi[c]) <= 1e-12 * max(1.0, abs(phi[c])), (k, phi[c])
 
 
 def test_invalid_arguments_are_rejected():
