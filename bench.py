@@ -38,27 +38,31 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # published; packed FP32 (the second half) is not used here
 MFMA_16BIT_PEAK_TFLOPS = 2500.0  # dense bf16 / fp16
 
-# HBM bytes per launch of the path kernel (mean over the launches of one
+# HBM bytes per launch of the dominant kernel (mean over the launches of one
 # solve), from rocprofv3 FETCH_SIZE and WRITE_SIZE counter runs of
-# `bench.py --steps 1 --warmup 0 --no-cpu-baseline --copy-calibration-mib 256`,
-# scaled by what the same counters read for the plain 256 MiB device copy in
-# that run (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  A figure holds only for the
-# kernel sources it was counted on (their SHA-256); after any change to them
-# the bench reports null until the counters are taken again.
-KERNEL_SOURCES = ("paper_2407_21084_amd/csrc/qrmc_common.h",
-                  "paper_2407_21084_amd/csrc/qrmc_kernels.h",
-                  "paper_2407_21084_amd/csrc/qrmc_kernels.hip")
+# `bench.py --steps 1 --warmup 0 --no-cpu-baseline --copy-calibration-mib 256`
+# (with --precision f64 for the plain path), scaled by what the same counters
+# read for the plain 256 MiB device copy in that run (FETCH_SIZE x 2.0,
+# WRITE_SIZE x 1.0).  A figure holds only for the kernel sources it was
+# counted on (their SHA-256); after any change to them the bench reports null
+# until the counters are taken again.
+_CSRC = "paper_2407_21084_amd/csrc/"
+KERNEL_SOURCES = {
+    "f64": tuple(_CSRC + f for f in ("qrmc_common.h", "qrmc_device.h", "qrmc_kernels.h", "qrmc_kernels.hip")),
+    "factored": tuple(_CSRC + f for f in ("qrmc_common.h", "qrmc_device.h", "qrmc_factored.h",
+                                          "qrmc_factored.hip")),
+}
 COUNTED_TRAFFIC = {
     # (workload, precision, M): read bytes, written bytes, sources counted on
-    ("d6-hcmax16-allen-cahn", "f64", 1 << 20): (2139917305, 845106630,
-        "717f526063b9af1ca03372854e5f3ca83db1e863096cc5c63d01034ab0591a23"),
+    ("d6-hcmax16-allen-cahn", "bf16", 1 << 20): (1604624755, 260884121,
+        "2b8b7b3c6a29f8a8defeb3c737e45fa1afe2e3f78949faf27f21c2faf9220c8d"),
 }
 
 
-def kernel_sources_sha256() -> str:
+def kernel_sources_sha256(kind: str = "f64") -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in KERNEL_SOURCES[kind]:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -67,10 +71,50 @@ def kernel_sources_sha256() -> str:
 def counted_traffic(workload: str, precision: str, M: int):
     """(read + written bytes per launch, detail) if counted on these sources, else (None, None)."""
     rec = COUNTED_TRAFFIC.get((workload, precision, M))
-    if rec is None or rec[2] != kernel_sources_sha256():
+    if rec is None or rec[2] != kernel_sources_sha256("f64" if precision == "f64" else "factored"):
         return None, None
     return float(rec[0] + rec[1]), {"read_bytes": rec[0], "written_bytes": rec[1],
                                     "scaling": "FETCH_SIZE x2.0, WRITE_SIZE x1.0 (256 MiB copy)"}
+
+
+# The paper's own figures for its Tables d1_mse / d2_mse rows (Sec. 5): GPU
+# full-solve seconds on one GeForce GTX TITAN Black in single precision, and
+# MSE_max / MSE_av (natural log) at q = 0.  Context only: other hardware,
+# other precision, other random numbers.
+PAPER_CONTEXT = {
+    "paper-d1-tensor100": {"gpu_s": 0.09, "table": "d1_mse"},
+    "paper-d1-tensor200": {"gpu_s": 414.44, "table": "d1_mse"},
+    "paper-d2-total20": {"gpu_s": 0.33, "mse_max": -2.322, "mse_av": -2.773, "table": "d2_mse"},
+    "paper-d2-hc_max19": {"gpu_s": 0.16, "mse_max": -2.526, "mse_av": -3.062, "table": "d2_mse"},
+    "paper-d2-total25": {"gpu_s": 35.51, "mse_max": -2.869, "mse_av": -3.688, "table": "d2_mse"},
+    "paper-d2-hc_max24": {"gpu_s": 12.38, "mse_max": -2.745, "mse_av": -3.550, "table": "d2_mse"},
+    "paper-d2-total31": {"gpu_s": 2243.06, "mse_max": -2.978, "mse_av": -3.966, "table": "d2_mse"},
+    "paper-d2-hc_max30": {"gpu_s": 662.54, "mse_max": -2.898, "mse_av": -3.770, "table": "d2_mse"},
+}
+
+
+def paper_indicators(ctx, basis, w, alpha, torch, dev, stream, n=1 << 14):
+    """MSE_max and MSE_av of eq (mse) (natural logs) on n stream-1 points of
+    the law per time index against u(t_i, .), the prediction being the
+    expansion times (1+|x|^2)^{q/2}, and ybar_0 at the origin."""
+    xt = torch.empty((w.d, n), dtype=torch.float64, device=dev)
+    yt = torch.empty(n, dtype=torch.float64, device=dev)
+    wv = torch.tensor(w.sol_w, dtype=torch.float64, device=dev)
+    per = []
+    for i in range(w.N):
+        ctx.sample_points(w.d, w.seed, 1, i, n, xt, stream=stream, law=w.law)
+        ctx.eval(basis, alpha[i].contiguous(), xt, yt, stream=stream)
+        y = yt * (1.0 + (xt * xt).sum(dim=0)) ** (0.5 * w.damping_q) if w.damping_q else yt
+        t = i * w.T / w.N
+        u = w.sol_B + w.sol_A * math.exp(-w.sol_c * (w.T - t)) * torch.cos(wv @ xt + w.sol_p)
+        per.append(float(((y - u) ** 2).mean()))
+    x0 = torch.zeros((w.d, 1), dtype=torch.float64, device=dev)
+    y0 = torch.empty(1, dtype=torch.float64, device=dev)
+    ctx.eval(basis, alpha[0].contiguous(), x0, y0, stream=stream)
+    torch.cuda.synchronize()
+    return {"mse_max": math.log(max(per)), "mse_av": math.log(sum(per) / len(per)),
+            "ybar0_at_0": float(y0[0]), "u0_at_0": w.sol_B + w.sol_A * math.exp(-w.sol_c * w.T) * math.cos(w.sol_p),
+            "test_points_per_step": n}
 
 
 def parse():
@@ -200,7 +244,7 @@ def run_learned(args, torch, W, Q):
     xt = torch.empty((w.d, n_test), dtype=torch.float64, device=dev)
     ctx.sample_points(w.d, w.seed, 1, 0, n_test, xt, stream=stream)
     wv = torch.tensor(w.sol_w, dtype=torch.float64, device=dev)
-    u0 = w.sol_A * math.exp(-w.sol_c * w.T) * torch.cos(wv @ xt + w.sol_p)
+    u0 = w.sol_B + w.sol_A * math.exp(-w.sol_c * w.T) * torch.cos(wv @ xt + w.sol_p)
 
     def rel_err(a):
         yt = torch.empty(n_test, dtype=torch.float64, device=dev)
@@ -373,7 +417,7 @@ def main():
     torch.cuda.set_device(dev)
     ctx = Q.Context(0)
     ctx.set_prec_kernel(args.prec_kernel)
-    basis = Q.Basis(w.d, w.set_kind, w.level, law=w.law)
+    basis = Q.Basis(w.d, w.set_kind, w.level, law=w.law, basis=w.basis)
     prob = Q.problem_from(w)
     alpha = torch.zeros((w.N, basis.n_funcs), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
@@ -418,7 +462,7 @@ def main():
     # algorithmic work of the dominant kernel (expansions at X_{j+1}, j+1 < N)
     grad = w.driver == "zrat"
     rhs = 1 + (w.d if grad else 0)
-    n_reps = (basis.n_funcs + 1) // 2
+    n_reps = (basis.n_funcs + 1) // 2 if w.basis == "fourier" else basis.n_funcs
     path_evals = w.M * basis.n_funcs * w.N * (w.N - 1) / 2 * args.steps
     path_s = path_ms * 1e-3
     mfma = None
@@ -452,7 +496,7 @@ def main():
     xt = torch.empty((w.d, n_test), dtype=torch.float64, device=dev)
     ctx.sample_points(w.d, w.seed, 1, 0, n_test, xt, stream=stream, law=w.law)
     wv = torch.tensor(w.sol_w, dtype=torch.float64, device=dev)
-    u0 = w.sol_A * math.exp(-w.sol_c * w.T) * torch.cos(wv @ xt + w.sol_p)
+    u0 = w.sol_B + w.sol_A * math.exp(-w.sol_c * w.T) * torch.cos(wv @ xt + w.sol_p)
 
     def rel_l2_of(a):
         yt = torch.empty(n_test, dtype=torch.float64, device=dev)
@@ -519,7 +563,7 @@ def main():
             "rel_l2_t0": {args.precision: rel_l2, "f64": rel64},
             "equal_error": rel_l2 <= 1.02 * rel64,
             "alpha_rel_err_per_step": rows}
-    if w.law == "logistic" and not w.damping_q:
+    if w.law == "logistic" and not w.damping_q and w.basis == "fourier":
         # error split of the FP64 solve at t_0: projection floor + Monte-Carlo variance
         floor, u2 = projection_floor(w, basis.indices())
         s0 = torch.empty(w.M, dtype=torch.float64, device=dev)
@@ -538,6 +582,12 @@ def main():
                     "closed form, and sum_k Var(alpha_0k)/||u||^2 = (|Gamma| mean(S^2) - ||alpha_0||^2)/(M ||u||^2) "
                     "from the responses of step 0; the remainder holds the errors carried from later steps and "
                     "the time discretisation"}
+    if w.basis == "cosine":
+        line["paper_indicators"] = paper_indicators(ctx, basis, w, alpha, torch, dev, stream)
+        if a64 is not alpha:
+            line["paper_indicators_f64"] = paper_indicators(ctx, basis, w, a64, torch, dev, stream)
+        if w.name in PAPER_CONTEXT:
+            line["paper_context"] = dict(PAPER_CONTEXT[w.name], hardware="1x GeForce GTX TITAN Black, single precision")
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

@@ -233,6 +233,15 @@ qr_status qr_ctx_create(int32_t device, qr_ctx **out);
 /* Synchronise with the context's last stream and release all workspace. */
 void qr_ctx_destroy(qr_ctx *ctx);
 
+/* Cap the device workspace the context may hold (bytes; 0 = no cap, the
+ * default).  A call whose workspace would grow past the cap returns
+ * QR_ENOMEM before it allocates or launches anything; workspace already held
+ * is kept.  The basis tables (per basis, not per context) are not counted. */
+qr_status qr_ctx_set_mem_limit(qr_ctx *ctx, int64_t bytes);
+
+/* Device workspace currently held by the context, in bytes. */
+qr_status qr_ctx_mem_held(const qr_ctx *ctx, int64_t *bytes);
+
 /* Enable (1) or disable (0) per-kernel timing with HIP events recorded on
  * the launch stream around every kernel the library enqueues. */
 qr_status qr_ctx_set_timing(qr_ctx *ctx, int32_t enable);
@@ -271,9 +280,20 @@ qr_status qr_ctx_reset_timing(qr_ctx *ctx);
 qr_status qr_backward_step(qr_ctx *ctx, const qr_problem *prob, const qr_basis *basis, int32_t i,
                            int64_t M, uint64_t seed, double *alpha, void *stream);
 
-/* Full backward induction i = N-1, ..., 0 (all rows of alpha written). */
+/* Full backward induction i = N-1, ..., 0 (all rows of alpha written).
+ * Bit for bit the same rows as qr_backward_step called for i = N-1, ..., 0
+ * on one alpha table. */
 qr_status qr_solve(qr_ctx *ctx, const qr_problem *prob, const qr_basis *basis, int64_t M,
                    uint64_t seed, double *alpha, void *stream);
+
+/* Resume a backward induction (Algorithm 1) at time index i_start
+ * (0 <= i_start < N): rows i_start+1..N-1 of alpha are read as saved from an
+ * earlier run, rows i_start..0 are written.  `precision` as in qr_solve_prec.
+ * With the same problem, basis, M, seed, precision and reduced-precision
+ * kernel, the rows written equal those of the uninterrupted solve bit for
+ * bit (qr_solve and qr_solve_prec are this call with i_start = N-1). */
+qr_status qr_solve_from(qr_ctx *ctx, const qr_problem *prob, const qr_basis *basis, int32_t i_start,
+                        int64_t M, uint64_t seed, int32_t precision, double *alpha, void *stream);
 
 /* Evaluate ybar = sum_k alpha_k phi_k at n points, phi_k = (Fourier
  * function) o F of the basis's sampling law (with a damping exponent q > 0

@@ -575,6 +575,9 @@ struct qr_ctx {
     // last read (-1: none), raised by the reduction kernels
     int32_t *d_bad = nullptr;
     bool timing = false;
+    // workspace held by the buffers above, and the cap set by
+    // qr_ctx_set_mem_limit (0: none)
+    int64_t held = 0, mem_limit = 0;
     std::vector<Timed> pending;
     std::vector<hipEvent_t> pool;
     double ms[4] = {0, 0, 0, 0};
@@ -583,8 +586,13 @@ struct qr_ctx {
 
 static qr_status ensure(qr_ctx *c, Buf &b, size_t bytes, const char *what) {
     if (b.bytes >= bytes) return QR_OK;
+    if (c->mem_limit > 0 && c->held - (int64_t)b.bytes + (int64_t)bytes > c->mem_limit)
+        return fail(QR_ENOMEM, "workspace %s: %zu bytes would take the context's workspace to %lld bytes, "
+                               "over its limit of %lld", what, bytes,
+                    (long long)(c->held - (int64_t)b.bytes + (int64_t)bytes), (long long)c->mem_limit);
     QR_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
     if (b.p) hipFree(b.p);
+    c->held -= (int64_t)b.bytes;
     b.p = nullptr;
     b.bytes = 0;
     hipError_t e = hipMalloc(&b.p, bytes);
@@ -593,7 +601,7 @@ static qr_status ensure(qr_ctx *c, Buf &b, size_t bytes, const char *what) {
         return fail(QR_ENOMEM, "workspace %s: cannot allocate %zu bytes", what, bytes);
     }
     b.bytes = bytes;
-    (void)c;
+    c->held += (int64_t)bytes;
     return QR_OK;
 }
 
@@ -687,6 +695,19 @@ extern "C" qr_status qr_ctx_set_prec_kernel(qr_ctx *c, int32_t kind) {
     if (kind < QR_PREC_KERNEL_AUTO || kind > QR_PREC_KERNEL_FACTORED)
         return fail(QR_EINVAL, "qr_ctx_set_prec_kernel: unknown kernel choice %d", kind);
     c->prec_kernel = kind;
+    return QR_OK;
+}
+
+extern "C" qr_status qr_ctx_set_mem_limit(qr_ctx *c, int64_t bytes) {
+    if (!c) return fail(QR_EINVAL, "qr_ctx_set_mem_limit: ctx is NULL");
+    if (bytes < 0) return fail(QR_EINVAL, "qr_ctx_set_mem_limit: negative limit %lld", (long long)bytes);
+    c->mem_limit = bytes;
+    return QR_OK;
+}
+
+extern "C" qr_status qr_ctx_mem_held(const qr_ctx *c, int64_t *bytes) {
+    if (!c || !bytes) return fail(QR_EINVAL, "qr_ctx_mem_held: NULL argument");
+    *bytes = c->held;
     return QR_OK;
 }
 
@@ -1016,27 +1037,38 @@ extern "C" qr_status qr_backward_step(qr_ctx *c, const qr_problem *p, const qr_b
     return carrier_out(c, b, A, alpha, i, nullptr, s);
 }
 
-extern "C" qr_status qr_solve(qr_ctx *c, const qr_problem *p, const qr_basis *bc, int64_t M,
-                              uint64_t seed, double *alpha, void *stream) {
-    qr_basis *b = const_cast<qr_basis *>(bc);
+// The backward induction i = i0, ..., 0 in FP64, rows i0+1..N-1 of alpha given.
+static qr_status solve_f64_from(qr_ctx *c, const qr_problem *p, qr_basis *b, int32_t i0, int64_t M, uint64_t seed,
+                                double *alpha, void *stream) {
     qr_status st = prepare(c, p, b, M, stream);
     if (st) return st;
     if (!alpha) return fail(QR_EINVAL, "qr_solve: alpha is NULL");
+    if (i0 < 0 || i0 >= p->N) return fail(QR_EINVAL, "qr_solve_from: i_start=%d outside [0,%d)", i0, p->N);
     hipStream_t s = (hipStream_t)stream;
     double2 *ai = (double2 *)c->alpha_int.p;
     const int64_t nf = b->nfc();
     double *S = (double *)c->S.p;
     double2 *u = (double2 *)c->u.p;
     double *A;
-    if ((st = carrier_in(c, b, alpha, p->N, p->N, &A, s))) return st;
+    if ((st = carrier_in(c, b, alpha, i0 + 1, p->N, &A, s))) return st;
+    st = timed(c, 3, s, "gather_kernel", [&] {
+        return launch_gather(A, i0 + 1, p->N - 1 - i0, b->nrep, b->ld(), nf, b->d_canon_of_trav, ai, s);
+    });
+    if (st) return st;
     if ((st = numeric_clear(c, s))) return st;
-    for (int32_t i = p->N - 1; i >= 0; --i) {
+    for (int32_t i = i0; i >= 0; --i) {
         if ((st = run_path(c, p, b, i, M, seed, ai, S, u, nullptr, s))) return st;
         if ((st = project_and_reduce(c, b, u, S, M, ai + (int64_t)i * b->ld(), A + (int64_t)i * nf, i, s)))
             return st;
         if ((st = carrier_out(c, b, A, alpha, i, ai, s))) return st;
     }
     return numeric_read(c, s, nullptr);
+}
+
+extern "C" qr_status qr_solve(qr_ctx *c, const qr_problem *p, const qr_basis *bc, int64_t M,
+                              uint64_t seed, double *alpha, void *stream) {
+    if (!p) return fail(QR_EINVAL, "problem is NULL");
+    return solve_f64_from(c, p, const_cast<qr_basis *>(bc), p->N - 1, M, seed, alpha, stream);
 }
 
 extern "C" qr_status qr_path_responses(qr_ctx *c, const qr_problem *p, const qr_basis *bc, int32_t i,
@@ -1341,14 +1373,15 @@ extern "C" qr_status qr_backward_step_prec(qr_ctx *c, const qr_problem *p, const
     return carrier_out(c, b, A, alpha, i, nullptr, s);
 }
 
-extern "C" qr_status qr_solve_prec(qr_ctx *c, const qr_problem *p, const qr_basis *bc, int64_t M,
+extern "C" qr_status qr_solve_from(qr_ctx *c, const qr_problem *p, const qr_basis *bc, int32_t i0, int64_t M,
                                    uint64_t seed, int32_t prec, double *alpha, void *stream) {
-    if (prec == QR_PREC_F64) return qr_solve(c, p, bc, M, seed, alpha, stream);
+    if (prec == QR_PREC_F64) return solve_f64_from(c, p, const_cast<qr_basis *>(bc), i0, M, seed, alpha, stream);
     qr_basis *b = const_cast<qr_basis *>(bc);
     TilePlan tp;
     qr_status st = prepare_prec(c, p, b, M, prec, stream, &tp);
     if (st) return st;
     if (!alpha) return fail(QR_EINVAL, "qr_solve_prec: alpha is NULL");
+    if (i0 < 0 || i0 >= p->N) return fail(QR_EINVAL, "qr_solve_from: i_start=%d outside [0,%d)", i0, p->N);
     hipStream_t s = (hipStream_t)stream;
     double2 *ai = (double2 *)c->alpha_int.p;
     const int64_t nf = b->nfc();
@@ -1356,9 +1389,21 @@ extern "C" qr_status qr_solve_prec(qr_ctx *c, const qr_problem *p, const qr_basi
     if (st) return st;
     if (fac && (st = prepare_fac(c, p, b))) return st;
     double *A;
-    if ((st = carrier_in(c, b, alpha, p->N, p->N, &A, s))) return st;
+    if ((st = carrier_in(c, b, alpha, i0 + 1, p->N, &A, s))) return st;
+    // the given rows in the kernels' layouts
+    if (fac) {
+        for (int32_t r = i0 + 1; r < p->N; ++r)
+            if ((st = fac_pack_row(c, b, prec, A + (int64_t)r * nf, r, s))) return st;
+    } else {
+        st = timed(c, 3, s, "gather_kernel", [&] {
+            return launch_gather(A, i0 + 1, p->N - 1 - i0, b->nrep, b->ld(), nf, b->d_canon_of_trav, ai, s);
+        });
+        if (st) return st;
+        for (int32_t r = i0 + 1; r < p->N; ++r)
+            if ((st = pack_row(c, p, b, prec, tp, r, s))) return st;
+    }
     if ((st = numeric_clear(c, s))) return st;
-    for (int32_t i = p->N - 1; i >= 0; --i) {
+    for (int32_t i = i0; i >= 0; --i) {
         st = fac ? run_fac_path(c, p, b, prec, i, M, seed, s) : run_mfma_path(c, p, b, prec, tp, i, M, seed, s);
         if (st) return st;
         st = fac ? fac_project(c, b, prec, M, A + (int64_t)i * nf, i, s)
@@ -1372,6 +1417,12 @@ extern "C" qr_status qr_solve_prec(qr_ctx *c, const qr_problem *p, const qr_basi
         }
     }
     return numeric_read(c, s, nullptr);
+}
+
+extern "C" qr_status qr_solve_prec(qr_ctx *c, const qr_problem *p, const qr_basis *bc, int64_t M,
+                                   uint64_t seed, int32_t prec, double *alpha, void *stream) {
+    if (!p) return fail(QR_EINVAL, "problem is NULL");
+    return qr_solve_from(c, p, bc, p->N - 1, M, seed, prec, alpha, stream);
 }
 
 // ---------------------------------------------------------------------------

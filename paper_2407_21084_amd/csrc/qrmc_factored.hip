@@ -382,10 +382,16 @@ void fac_path_kernel(const DevProblem *__restrict__ P0, const FacDev F,
             // tables of coordinates l = 4 s + g
 #pragma unroll
             for (int s4 = 0; s4 < (DB + 3) / 4; ++s4) {
-                double xs = x[4 * s4];
-                if (4 * s4 + 1 < DB && g == 1) xs = x[4 * s4 + 1];
-                if (4 * s4 + 2 < DB && g == 2) xs = x[4 * s4 + 2];
-                if (4 * s4 + 3 < DB && g == 3) xs = x[4 * s4 + 3];
+                // lane group g takes coordinate 4 s4 + g: the candidates pass
+                // through an empty asm so that the choice stays a register
+                // select (folded into a load with a lane-dependent index, it
+                // would move the whole state x to scratch memory)
+                double c0 = x[4 * s4];
+                double c1 = 4 * s4 + 1 < DB ? x[4 * s4 + 1] : 0.0;
+                double c2 = 4 * s4 + 2 < DB ? x[4 * s4 + 2] : 0.0;
+                double c3 = 4 * s4 + 3 < DB ? x[4 * s4 + 3] : 0.0;
+                asm("" : "+v"(c0), "+v"(c1), "+v"(c2), "+v"(c3));
+                const double xs = g == 0 ? c0 : (g == 1 ? c1 : (g == 2 ? c2 : c3));
                 const int l = 4 * s4 + g;
                 if (l < d) {
                     const double2 e1 = nl_unit_phase_u(nu, xs);

@@ -712,11 +712,16 @@ __global__ void reduce_kernel(const double2 *__restrict__ partial, int32_t nspli
         if (alpha_row) alpha_row[0] = a0;
     } else {
         const double mc = sx / M, ms = sy / M;
-        alpha_int_row[r] = make_double2(2.0 * mc, 2.0 * ms);
+        // the kernels' row is formed from the rounded public coefficients,
+        // exactly as gather_kernel forms it from a stored row: a solve then
+        // equals its steps run one by one, and resumes from saved rows, bit
+        // for bit
+        const double ac = M_SQRT2 * mc, as = M_SQRT2 * ms;
+        alpha_int_row[r] = make_double2(M_SQRT2 * ac, M_SQRT2 * as);
         if (alpha_row) {
             const int64_t c = canon_of_trav[r];
-            alpha_row[2 * c - 1] = M_SQRT2 * mc;
-            alpha_row[2 * c] = M_SQRT2 * ms;
+            alpha_row[2 * c - 1] = ac;
+            alpha_row[2 * c] = as;
         }
     }
 }

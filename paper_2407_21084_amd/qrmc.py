@@ -51,7 +51,8 @@ EXPORTS = ["qr_last_error", "qr_version", "qr_build_basis", "qr_build_basis_law"
            "qr_solve_prec", "qr_mlp_init", "qr_mlp_features", "qr_mlp_forward", "qr_mlp_loss_grad",
            "qr_mlp_adam", "qr_solve_learned", "qr_solve_batched",
            "qr_basis_upload", "qr_eval_noalloc", "qr_ctx_set_prec_kernel", "qr_basis_factored",
-           "qr_ctx_numeric_status", "qr_build_basis_cos", "qr_basis_family_of",
+           "qr_ctx_numeric_status", "qr_build_basis_cos", "qr_basis_family_of", "qr_solve_from",
+           "qr_ctx_set_mem_limit", "qr_ctx_mem_held",
            "qr_host_uniform", "qr_host_norm_icdf", "qr_host_philox"]
 
 
@@ -111,6 +112,9 @@ _SIGS = {
     "qr_basis_law": (C.c_int, [_P, C.POINTER(_I32)]),
     "qr_build_basis_cos": (C.c_int, [_I32, _I32, _I32, _I32, C.POINTER(_P)]),
     "qr_basis_family_of": (C.c_int, [_P, C.POINTER(_I32)]),
+    "qr_solve_from": (C.c_int, [_P, C.POINTER(Problem), _P, _I32, _I64, _U64, _I32, _P, _P]),
+    "qr_ctx_set_mem_limit": (C.c_int, [_P, _I64]),
+    "qr_ctx_mem_held": (C.c_int, [_P, C.POINTER(_I64)]),
     "qr_basis_info": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I32)]),
     "qr_basis_indices": (C.c_int, [_P, _P]),
     "qr_basis_free": (None, [_P]),
@@ -356,6 +360,20 @@ class Context:
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         _check(_lib.qr_solve_prec(self._h, C.byref(prob), basis.handle, M, seed, prec, _dptr(alpha),
                                   _stream_ptr(stream)))
+
+    def solve_from(self, prob: Problem, basis: Basis, i_start: int, M: int, seed: int, alpha, precision="f64",
+                   stream=None):
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        _check(_lib.qr_solve_from(self._h, C.byref(prob), basis.handle, i_start, M, seed, prec, _dptr(alpha),
+                                  _stream_ptr(stream)))
+
+    def set_mem_limit(self, nbytes: int):
+        _check(_lib.qr_ctx_set_mem_limit(self._h, int(nbytes)))
+
+    def mem_held(self) -> int:
+        v = _I64()
+        _check(_lib.qr_ctx_mem_held(self._h, C.byref(v)))
+        return v.value
 
     def eval(self, basis: Basis, alpha_row, x, y, grad=None, stream=None):
         n = y.shape[0]

@@ -62,12 +62,33 @@ def test_counted_traffic_only_for_its_sources(monkeypatch):
     b = _bench_module()
     # unknown workloads or sizes carry no counted traffic
     assert b.counted_traffic("d6-hcmax16-allen-cahn", "f64", 1 << 18) == (None, None)
-    assert b.counted_traffic("d6-hcmax16-allen-cahn", "bf16", 1 << 20) == (None, None)
-    # a recorded figure is reported only while the sources hash to its value
-    key = ("d6-hcmax16-allen-cahn", "f64", 1 << 20)
-    rd, wr, sha = b.COUNTED_TRAFFIC[key]
-    monkeypatch.setattr(b, "kernel_sources_sha256", lambda: sha)
-    total, detail = b.counted_traffic(*key)
-    assert total == rd + wr and detail["read_bytes"] == rd and detail["written_bytes"] == wr
-    monkeypatch.setattr(b, "kernel_sources_sha256", lambda: "0" * 64)
-    assert b.counted_traffic(*key) == (None, None)
+    assert b.counted_traffic("d2-tensor4", "bf16", 1 << 20) == (None, None)
+    # a recorded figure is reported only while the sources of its kernel hash to its value
+    for key, kind in ((("d6-hcmax16-allen-cahn", "f64", 1 << 20), "f64"),
+                      (("d6-hcmax16-allen-cahn", "bf16", 1 << 20), "factored")):
+        sha = b.kernel_sources_sha256(kind)
+        monkeypatch.setitem(b.COUNTED_TRAFFIC, key, (1000, 300, sha))
+        total, detail = b.counted_traffic(*key)
+        assert total == 1300 and detail["read_bytes"] == 1000 and detail["written_bytes"] == 300
+        monkeypatch.setattr(b, "kernel_sources_sha256", lambda kind="f64": "0" * 64)
+        assert b.counted_traffic(*key) == (None, None)
+        monkeypatch.undo()
+    # the two kernels hash different sources
+    assert b.kernel_sources_sha256("f64") != b.kernel_sources_sha256("factored")
+
+
+def test_paper_workloads_are_the_printed_rows():
+    """The paper-variant legs are rows of Tables d1_mse / d2_mse: N = 1/Delta,
+    the printed cardinalities of the sets over N^d, and the printed M."""
+    import workloads as W
+    import oracle as O
+    b = _bench_module()
+    want = {"paper-d1-tensor100": (20, 101, 20_000), "paper-d1-tensor200": (100, 201, 2_000_000),
+            "paper-d2-total20": (20, 231, 20_000), "paper-d2-hc_max19": (20, 99, 20_000),
+            "paper-d2-total25": (50, 351, 200_000), "paper-d2-hc_max24": (50, 133, 200_000),
+            "paper-d2-total31": (100, 528, 2_000_000), "paper-d2-hc_max30": (100, 172, 2_000_000)}
+    for name, (N, card, M) in want.items():
+        w = W.ALL[name]
+        assert (w.N, O.reps_for(w).shape[0], w.M) == (N, card, M)
+        assert w.basis == "cosine" and w.law == "student2" and w.driver == "paper"
+        assert name in b.PAPER_CONTEXT

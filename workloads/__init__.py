@@ -128,7 +128,20 @@ def paper_benchmark(d: int, N: int, set_kind: str, level: int, M: int, kappa: fl
 
 PAPER_D1 = paper_benchmark(1, 20, "tensor", 100, 20_000)
 
-ALL = {w.name: w for w in (D2_TENSOR4, D6_HCMAX16, D10_HC1P32_ZRAT, D16_HC1P32, PAPER_D1)}
+# Rows of the paper's Tables d1_mse and d2_mse (Sec. 5): Delta = 1/N, the set
+# and its level, M; the cosine basis over N^d and the Student mu = 2 law.
+PAPER_TABLES = (
+    PAPER_D1,
+    paper_benchmark(1, 100, "tensor", 200, 2_000_000),
+    paper_benchmark(2, 20, "total", 20, 20_000),
+    paper_benchmark(2, 20, "hc_max", 19, 20_000),
+    paper_benchmark(2, 50, "total", 25, 200_000),
+    paper_benchmark(2, 50, "hc_max", 24, 200_000),
+    paper_benchmark(2, 100, "total", 31, 2_000_000),
+    paper_benchmark(2, 100, "hc_max", 30, 2_000_000),
+)
+
+ALL = {w.name: w for w in (D2_TENSOR4, D6_HCMAX16, D10_HC1P32_ZRAT, D16_HC1P32) + PAPER_TABLES}
 
 
 def batched_instances(n: int = 256, seed: int = 4):
