@@ -83,7 +83,8 @@ def test_paper_workloads_are_the_printed_rows():
     import workloads as W
     import oracle as O
     b = _bench_module()
-    want = {"paper-d1-tensor100": (20, 101, 20_000), "paper-d1-tensor200": (100, 201, 2_000_000),
+    want = {"paper-d1-tensor100": (20, 101, 20_000), "paper-d1-tensor150": (50, 151, 200_000),
+            "paper-d1-tensor200": (100, 201, 2_000_000),
             "paper-d2-total20": (20, 231, 20_000), "paper-d2-hc_max19": (20, 99, 20_000),
             "paper-d2-total25": (50, 351, 200_000), "paper-d2-hc_max24": (50, 133, 200_000),
             "paper-d2-total31": (100, 528, 2_000_000), "paper-d2-hc_max30": (100, 172, 2_000_000)}

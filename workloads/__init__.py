@@ -132,6 +132,7 @@ PAPER_D1 = paper_benchmark(1, 20, "tensor", 100, 20_000)
 # and its level, M; the cosine basis over N^d and the Student mu = 2 law.
 PAPER_TABLES = (
     PAPER_D1,
+    paper_benchmark(1, 50, "tensor", 150, 200_000),
     paper_benchmark(1, 100, "tensor", 200, 2_000_000),
     paper_benchmark(2, 20, "total", 20, 20_000),
     paper_benchmark(2, 20, "hc_max", 19, 20_000),
