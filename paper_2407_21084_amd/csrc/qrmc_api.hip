@@ -94,6 +94,13 @@ struct qr_basis {
     std::vector<int32_t> fold_idx;    //   fold_idx[fold_off[c] .. fold_off[c+1])
     int32_t *d_cos_of_rep = nullptr, *d_fold_off = nullptr, *d_fold_idx = nullptr;
     double *d_rep_scale = nullptr;
+    // Tasks of kPassTM nodes for the pass projection of the batched form
+    // (built on first use, for the sub-walks that passes walk).
+    bool ptasks_built = false;
+    std::vector<TaskItem> pitems;
+    std::vector<Task> ptasks;
+    TaskItem *d_pitems = nullptr;
+    Task *d_ptasks = nullptr;
     // coefficients per row: the caller's layout, and the carrier's
     int64_t nf() const { return cos ? ncos : 2 * nrep - 1; }
     int64_t nfc() const { return 2 * nrep - 1; }
@@ -364,12 +371,16 @@ static void basis_free_device(qr_basis *b) {
         hipFree((void *)b->d_fac.colnnz);
         hipFree((void *)b->d_fac.ent);
         for (int t = 0; t < kFacTemplates; ++t) hipFree(b->d_fac_tasks[t]);
+        hipFree(b->d_pitems);
+        hipFree(b->d_ptasks);
         hipFree(b->d_cos_of_rep);
         hipFree(b->d_fold_off);
         hipFree(b->d_fold_idx);
         hipFree(b->d_rep_scale);
         hipSetDevice(cur);
     }
+    b->d_pitems = nullptr;
+    b->d_ptasks = nullptr;
     b->d_cos_of_rep = nullptr;
     b->d_fold_off = nullptr;
     b->d_fold_idx = nullptr;
@@ -482,6 +493,35 @@ static qr_status basis_on_device(qr_basis *b, int dev) {
         if ((st = upload_vec(&b->d_rep_scale, b->rep_scale))) return st;
     }
     b->dev = dev;
+    return QR_OK;
+}
+
+// The pass-projection tasks of a basis on its device (host lists built once
+// by walking the set again; the basis must be resident on the device).
+static qr_status basis_pass_tasks_on_device(qr_basis *b) {
+    std::lock_guard<std::mutex> lock(b->mu);
+    if (!b->ptasks_built) {
+        try {
+            std::vector<int32_t> trav;
+            std::vector<int64_t> subtree;
+            std::vector<TaskItem> nodes;
+            Builder B{make_rule(b->kind, b->level, b->d), std::vector<int32_t>(b->d, 0), trav, subtree, nodes};
+            B.push(0, 0, 1);
+            B.visit(0, -1, 1);
+            if (B.overflow || (int64_t)subtree.size() != b->nrep)
+                return fail(QR_ENUMERIC, "pass tasks: the walk of the set changed size");
+            subtree[0] = b->nrep;
+            build_tasks(nodes, subtree, kPassTM, b->pitems, b->ptasks);
+        } catch (const std::bad_alloc &) {
+            return fail(QR_ENOMEM, "pass tasks: out of host memory");
+        }
+        b->ptasks_built = true;
+    }
+    if (!b->d_ptasks) {
+        qr_status st;
+        if ((st = upload_vec(&b->d_pitems, b->pitems))) return st;
+        if ((st = upload_vec(&b->d_ptasks, b->ptasks))) return st;
+    }
     return QR_OK;
 }
 
@@ -1763,7 +1803,28 @@ struct PassPlan {
     qr_basis *walk = nullptr;  // sub-walk of the pass (contains every member's)
     int64_t off = 0;           // offset of its coefficient rows in the batch buffer (double2)
     std::vector<int32_t> members;
+    bool shared = false;       // one projection of the pass for all members
+    int32_t nsplit = 0;        // slices of the pass projection
+    int64_t pps = 0;           // paths per slice
 };
+
+// Vector instructions per node and 128 paths of the two projections
+// (measured at d = 6): the single-response kernel, and the pass kernel for
+// all kBatchRT responses at once (its per-response cross-lane folds dominate).
+constexpr double kProjCostOwn = 35.0, kProjCostPass = 126.0;
+
+// Slices of a pass projection: as split_plan, for the pass tasks.
+void pass_split_plan(const qr_basis *w, int64_t M, int32_t *nsplit, int64_t *pps) {
+    const int64_t ntasks = std::max<int64_t>(1, (int64_t)w->ptasks.size());
+    const int64_t group = (int64_t)kPassWaves * 64 * pass_paths_per_lane(w->d);
+    int64_t want = (2048 + ntasks - 1) / ntasks;
+    const int64_t maxs = std::max<int64_t>(1, (M + 4 * group - 1) / (4 * group));
+    want = std::max<int64_t>(1, std::min(want, maxs));
+    int64_t per = (M + want - 1) / want;
+    per = (per + group - 1) / group * group;
+    *pps = per;
+    *nsplit = (int32_t)((M + per - 1) / per);
+}
 }  // namespace
 
 extern "C" qr_status qr_solve_batched(qr_ctx *c, const qr_problem *p, const qr_basis *bc, int32_t R,
@@ -1832,16 +1893,33 @@ extern "C" qr_status qr_solve_batched(qr_ctx *c, const qr_problem *p, const qr_b
         if ((st = sub_basis(b, P.d, P.level, &P.walk))) return st;
         P.off = total;
         total += (int64_t)p->N * P.walk->ld() * kBatchRT;
-        for (int32_t r : P.members) {
-            int32_t nsplit;
-            int64_t pps;
-            split_plan(own[r], inst[r].M, &nsplit, &pps);
-            partial_max = std::max(partial_max, (int64_t)nsplit * own[r]->nrep);
-        }
     }
     if ((st = basis_on_device(b, c->dev))) return st;
     for (qr_basis *sb : b->subs)
         if ((st = basis_on_device(sb, c->dev))) return st;
+    if (project_pass_lds_bytes(p->d) > (size_t)160 * 1024)
+        return fail(QR_ENOTSUP, "qr_solve_batched: the pass projection's LDS exceeds a CU at d=%d", p->d);
+    // The pass projection walks the pass's whole set over its whole cloud for
+    // every member slot; it is taken where that costs less than the members'
+    // own projections (members close to the pass's envelope), by the cost
+    // model above.
+    for (PassPlan &P : passes) {
+        double own_cost = 0.0;
+        for (int32_t r : P.members) own_cost += kProjCostOwn * (double)inst[r].M * (double)own[r]->nrep;
+        P.shared = kProjCostPass * (double)P.M * (double)P.walk->nrep < own_cost;
+        if (P.shared) {
+            if ((st = basis_pass_tasks_on_device(P.walk))) return st;
+            pass_split_plan(P.walk, P.M, &P.nsplit, &P.pps);
+            partial_max = std::max(partial_max, (int64_t)P.nsplit * P.walk->nrep * kBatchRT);
+        } else {
+            for (int32_t r : P.members) {
+                int32_t nsplit;
+                int64_t pps;
+                split_plan(own[r], inst[r].M, &nsplit, &pps);
+                partial_max = std::max(partial_max, (int64_t)nsplit * own[r]->nrep);
+            }
+        }
+    }
     if ((st = upload_problem(c, p, b->law, s))) return st;
     if ((st = ensure(c, c->S, sizeof(double) * (size_t)Mmax * kBatchRT, "S"))) return st;
     if ((st = ensure(c, c->u, sizeof(double2) * (size_t)Mmax * p->d, "phase factors"))) return st;
@@ -1853,8 +1931,10 @@ extern "C" qr_status qr_solve_batched(qr_ctx *c, const qr_problem *p, const qr_b
     DevBatch hb{};
     for (int ps = 0; ps < npass; ++ps) {
         hb.count[ps] = (int32_t)passes[ps].members.size();
-        for (size_t k = 0; k < passes[ps].members.size(); ++k)
+        for (size_t k = 0; k < passes[ps].members.size(); ++k) {
             hb.f_a[ps * kBatchRT + k] = inst[passes[ps].members[k]].f_a;
+            hb.m[ps * kBatchRT + k] = inst[passes[ps].members[k]].M;
+        }
     }
     QR_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
     QR_HIP(hipMemcpy(c->d_batch, &hb, sizeof hb, hipMemcpyHostToDevice), "hipMemcpy(batch)");
@@ -1877,23 +1957,37 @@ extern "C" qr_status qr_solve_batched(qr_ctx *c, const qr_problem *p, const qr_b
             st = timed(c, 0, s, "batched_path_kernel",
                        [&] { return launch_batched_path(db, depth_cap(P.walk->max_nnz), a, s); });
             if (st) return st;
+            if (P.shared) {
+                // one projection of the pass for all its members (the shared walk
+                // and phase factors), then each member's own coefficients from it
+                st = timed(c, 1, s, "project_pass_kernel", [&] {
+                    return launch_project_pass(depth_cap(P.walk->max_nnz), make_walk(b->kind, P.level, P.d, b->code()),
+                                               u, P.M, S, P.M, c->d_batch->m + (int64_t)ps * kBatchRT, P.pps,
+                                               (int32_t)P.walk->ptasks.size(), P.nsplit, P.walk->d_ptasks,
+                                               P.walk->d_pitems, partial, P.walk->nrep, s);
+                });
+                if (st) return st;
+            }
             for (size_t k = 0; k < P.members.size(); ++k) {
                 const int32_t r = P.members[k];
                 const qr_basis *ob = own[r];
                 const int64_t Mr = inst[r].M;
-                int32_t nsplit;
-                int64_t pps;
-                split_plan(ob, Mr, &nsplit, &pps);
-                st = timed(c, 1, s, "project_kernel", [&] {
-                    return launch_project(depth_cap(ob->max_nnz), make_walk(b->kind, ob->level, ob->d, b->code()), u, P.M,
-                                          S + (int64_t)k * P.M, Mr, pps, (int32_t)ob->tasks.size(), nsplit,
-                                          ob->d_tasks, ob->d_items, ob->task_max, partial, ob->nrep, s);
-                });
-                if (st) return st;
+                int32_t nsplit = P.nsplit;
+                if (!P.shared) {
+                    // the member's own projection: its set on its own cloud
+                    int64_t pps;
+                    split_plan(ob, Mr, &nsplit, &pps);
+                    st = timed(c, 1, s, "project_kernel", [&] {
+                        return launch_project(depth_cap(ob->max_nnz), make_walk(b->kind, ob->level, ob->d, b->code()), u,
+                                              P.M, S + (int64_t)k * P.M, Mr, pps, (int32_t)ob->tasks.size(), nsplit,
+                                              ob->d_tasks, ob->d_items, ob->task_max, partial, ob->nrep, s);
+                    });
+                    if (st) return st;
+                }
                 st = timed(c, 2, s, "reduce_batched_kernel", [&] {
-                    return launch_reduce_batched(partial, nsplit, ob->nrep, (double)Mr, ob->d_ft,
-                                                 b->d_canon_of_trav, P.walk->d_inv,
-                                                 ab + P.off + (int64_t)i * ld * kBatchRT, (int32_t)k,
+                    return launch_reduce_batched(partial, nsplit, ob->nrep, P.shared ? P.walk->nrep : ob->nrep,
+                                                 P.shared ? kBatchRT : 1, (double)Mr, ob->d_ft, b->d_canon_of_trav,
+                                                 P.walk->d_inv, ab + P.off + (int64_t)i * ld * kBatchRT, (int32_t)k,
                                                  alpha + ((int64_t)r * p->N + i) * nf, c->d_bad, i, s);
                 });
                 if (st) return st;

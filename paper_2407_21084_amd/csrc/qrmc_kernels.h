@@ -21,12 +21,16 @@ ProjShape proj_shape(int32_t d);
 __host__ __device__ constexpr int64_t coef_ld(int64_t nrep) { return ((nrep + 63) / 64 + 2) * 64; }
 
 constexpr int kBatchRT = 8;       // instances per pass of the batched path kernel
+constexpr int kPassTM = 64;       // nodes per task of the pass projection
+constexpr int kPassWaves = 4;     // waves per block of the pass projection
 
 // Per-pass parameters of a batch (device memory, one per context): members
-// per pass and the driver parameter of slot k of pass p at f_a[p kBatchRT + k].
+// per pass, the driver parameter and the cloud size of slot k of pass p at
+// f_a[p kBatchRT + k] and m[p kBatchRT + k] (m = 0 for an empty slot).
 struct DevBatch {
     int32_t count[QR_MAX_BATCH];
     double f_a[QR_MAX_BATCH * kBatchRT];
+    int64_t m[QR_MAX_BATCH * kBatchRT];
 };
 
 struct BatchArgs {
@@ -103,10 +107,20 @@ hipError_t launch_sample(int32_t nu, int32_t d, uint64_t seed, uint32_t stream_i
                          int64_t n, double *x, hipStream_t s);
 
 hipError_t launch_batched_path(int db, int cap, const BatchArgs &a, hipStream_t s);
-hipError_t launch_reduce_batched(const double2 *partial, int32_t nsplit, int64_t nrep_sub, double M,
-                                 const int32_t *ft, const int32_t *canon_of_trav,
+// partial [split][n_part][R]: R = 1, n_part = nrep_sub (the instance's own
+// projection) or the pass projection's R slots over n_part pass-walk nodes
+hipError_t launch_reduce_batched(const double2 *partial, int32_t nsplit, int64_t nrep_sub, int64_t n_part,
+                                 int32_t R, double M, const int32_t *ft, const int32_t *canon_of_trav,
                                  const int32_t *pass_pos, double2 *alpha_b_row, int32_t slot,
                                  double *alpha_row, int32_t *bad, int32_t step, hipStream_t s);
+// the projection of a pass: kBatchRT responses (S [kBatchRT][M], member r
+// using its first m_r[r] paths, m_r device) on the pass walk's tasks of
+// kPassTM nodes; partial [nsplit][nrep][kBatchRT] double2
+int pass_paths_per_lane(int32_t d);
+size_t project_pass_lds_bytes(int32_t d);
+hipError_t launch_project_pass(int cap, const Walk &W, const double2 *e, int64_t lde, const double *S, int64_t M,
+                               const int64_t *m_r, int64_t pps, int32_t ntasks, int32_t nsplit, const Task *tasks,
+                               const TaskItem *items, double2 *partial, int64_t nrep, hipStream_t s);
 hipError_t launch_zero(double *p, int64_t n, hipStream_t s);
 
 

@@ -619,6 +619,35 @@ struct ProjSink {
     }
 };
 
+// The same folds for R responses per point (the members of a batched pass on
+// their shared cloud): node n of the task and response r form the virtual node
+// n R + r, so the wave accumulators are [task_max][R][2] and a group of four
+// takes holds four responses of one node (R is a multiple of 4).
+template <int P, int R>
+struct ProjSinkR {
+    static_assert(R % 4 == 0, "groups of four takes must stay within a node");
+    static constexpr bool kGrad = false;
+    static constexpr bool kSplit = false;
+    struct Acc {};
+    __device__ __forceinline__ static void add(Acc &, const Acc &) {}
+    ProjSink<P> f;     // the fold state (f.s unused)
+    double s[R][P];    // the lane's responses per member (0 past the member's cloud)
+
+    __device__ __forceinline__ void node(const Pts<P> &v, Acc &) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            double re = s[r][0] * v.re[0], im = s[r][0] * v.im[0];
+#pragma unroll
+            for (int q = 1; q < P; ++q) {
+                re = fma(s[r][q], v.re[q], re);
+                im = fma(s[r][q], v.im[q], im);
+            }
+            f.take(re, im);
+        }
+    }
+    __device__ __forceinline__ void flush() { f.flush(); }
+};
+
 static size_t project_lds_bytes(int32_t d, int P, int waves, int task_max) {
     return (size_t)waves * ((size_t)task_max * sizeof(double2) + (size_t)d * 64 * P * sizeof(double2));
 }
@@ -685,6 +714,82 @@ __global__ __launch_bounds__(WAVES * 64) void project_kernel(
         double sacc = 0.0;
 #pragma unroll
         for (int w = 0; w < WAVES; ++w) sacc += accs[w * TM * 2 + r];
+        out[r] = sacc;
+    }
+}
+
+// project_pass_kernel: the projection of a batched pass, R members on the pass's
+// cloud at once (one walk of the pass's set and one read of the phase factors
+// per point for all members): member r's response at path m is S[r M + m]
+// for m < m_r and 0 beyond (its own cloud is the first m_r paths).  Partial
+// sums [split][node][R] (double2); the members' own nodes are picked and
+// scaled by reduce_batched_kernel.
+template <int CAP, int P, int R, int WAVES, int TM>
+__global__ __launch_bounds__(WAVES * 64) void project_pass_kernel(
+    const Walk W, const double2 *__restrict__ e_in, const int64_t lde, const double *__restrict__ s_in,
+    const int64_t M, const int64_t *__restrict__ m_r, const int64_t paths_per_split, const Task *__restrict__ tasks,
+    const TaskItem *__restrict__ items, double2 *__restrict__ partial, const int64_t nrep) {
+    static_assert(TM % 4 == 0, "groups of four nodes must tile a task");
+    extern __shared__ double2 lds[];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int d = W.d;
+    double *accs = reinterpret_cast<double *>(lds);   // [WAVES][TM][R][2]
+    double2 *Es = lds + WAVES * TM * R;              // [WAVES][d][P][64]
+
+    double *acc = accs + wave * TM * R * 2;
+    const LanePts<P> L{Es + wave * d * P * 64 + lane, nullptr, 64};
+
+    const Task task = tasks[blockIdx.x];
+    const int64_t m0 = (int64_t)blockIdx.y * paths_per_split;
+    const int64_t m1 = min(M, m0 + paths_per_split);
+    int64_t mr[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) mr[r] = m_r[r];
+
+    for (int r = lane; r < TM * R * 2; r += 64) acc[r] = 0.0;
+    wave_sync();
+
+    ProjSinkR<P, R> sink;
+    sink.f.acc = acc;
+    sink.f.slot = fold_slot(lane);
+    sink.f.lead = (lane & 7) == 0;
+    sink.f.bit3 = (lane >> 3) & 1;
+    for (int64_t gb = m0 + wave * 64 * P; gb < m1; gb += WAVES * 64 * P) {
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            const int64_t m = gb + q * 64 + lane;
+            const bool live = m < m1;
+#pragma unroll
+            for (int r = 0; r < R; ++r) sink.s[r][q] = (live && m < mr[r]) ? s_in[r * M + m] : 0.0;
+            for (int l = 0; l < d; ++l) L.set_e(l, q, live ? e_in[l * lde + m] : make_double2(1.0, 0.0));
+        }
+        sink.f.c = 0;
+        sink.f.base = 0;
+        for (int it = task.item_begin; it < task.item_end; ++it) {
+            const TaskItem &I = items[it];
+            Pts<P> v = unit<P>();
+            for (int t = 0; t < I.depth; ++t) {
+                Pts<P> e = L.e(I.coord[t]);
+                int n = I.val[t];
+                if (n < 0) {
+#pragma unroll
+                    for (int q = 0; q < P; ++q) e.im[q] = -e.im[q];
+                    n = -n;
+                }
+                for (int k = 0; k < n; ++k) v = cmul(v, e);
+            }
+            typename ProjSinkR<P, R>::Acc none;
+            sink.node(v, none);
+            if (I.full) visit_from<0, CAP, P>(I.depth, v, I.last, I.prod, W, L, sink);
+        }
+        if (sink.f.c) sink.flush();
+    }
+    __syncthreads();
+    double *out = reinterpret_cast<double *>(partial + ((int64_t)blockIdx.y * nrep + task.rep_begin) * R);
+    for (int r = tid; r < task.rep_count * R * 2; r += WAVES * 64) {
+        double sacc = 0.0;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) sacc += accs[w * TM * R * 2 + r];
         out[r] = sacc;
     }
 }
@@ -1313,17 +1418,22 @@ __global__ __launch_bounds__(kPathBlock) void batched_path_kernel(
 // basis traversal, which sits at pass_pos[ft[t]] in the coefficient layout of
 // the instance's pass (a walk containing the instance's).  Coefficients the
 // instance does not have stay as zero-filled.
+// partial: [split][n_part][R] with the instance's node t at index t (R = 1,
+// n_part = nrep_sub: its own projection) or at its node of the pass walk
+// pass_pos[ft[t]] and column slot (R > 1: the pass projection)
 __global__ void reduce_batched_kernel(const double2 *__restrict__ partial, int32_t nsplit,
-                                      int64_t nrep_sub, double M, const int32_t *__restrict__ ft,
+                                      int64_t nrep_sub, int64_t n_part, int32_t R, double M,
+                                      const int32_t *__restrict__ ft,
                                       const int32_t *__restrict__ canon_of_trav,
                                       const int32_t *__restrict__ pass_pos,
                                       double2 *__restrict__ alpha_b_row, int32_t slot,
                                       double *__restrict__ alpha_row, int32_t *__restrict__ bad, int32_t step) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nrep_sub) return;
+    const int64_t pi = R == 1 ? t : (int64_t)pass_pos[ft[t]] * R + slot;
     double sx = 0.0, sy = 0.0;
     for (int s = 0; s < nsplit; ++s) {
-        const double2 p = partial[(int64_t)s * nrep_sub + t];
+        const double2 p = partial[(int64_t)s * n_part * R + pi];
         sx += p.x;
         sy += p.y;
     }
@@ -1615,13 +1725,57 @@ hipError_t launch_batched_path(int db, int cap, const BatchArgs &a, hipStream_t 
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_reduce_batched(const double2 *partial, int32_t nsplit, int64_t nrep_sub, double M,
-                                 const int32_t *ft, const int32_t *canon_of_trav,
+hipError_t launch_reduce_batched(const double2 *partial, int32_t nsplit, int64_t nrep_sub, int64_t n_part,
+                                 int32_t R, double M, const int32_t *ft, const int32_t *canon_of_trav,
                                  const int32_t *pass_pos, double2 *alpha_b_row, int32_t slot,
                                  double *alpha_row, int32_t *bad, int32_t step, hipStream_t s) {
     hipLaunchKernelGGL(reduce_batched_kernel, dim3(blocks_for(nrep_sub, 256)), dim3(256), 0, s, partial,
-                       nsplit, nrep_sub, M, ft, canon_of_trav, pass_pos, alpha_b_row, slot, alpha_row, bad, step);
+                       nsplit, nrep_sub, n_part, R, M, ft, canon_of_trav, pass_pos, alpha_b_row, slot, alpha_row,
+                       bad, step);
     return hipGetLastError();
+}
+
+// pass projection: tasks of kPassTM nodes, kPassWaves waves, two paths per
+// lane up to d = 6 and one above (the accumulators of R responses per node
+// and the phase factors share the LDS: 20 KB per wave)
+int pass_paths_per_lane(int32_t d) { return d <= 6 ? 2 : 1; }
+
+size_t project_pass_lds_bytes(int32_t d) {
+    return (size_t)kPassWaves * ((size_t)kPassTM * kBatchRT * sizeof(double2) +
+                                 (size_t)d * 64 * pass_paths_per_lane(d) * sizeof(double2));
+}
+
+template <int CAP, int P>
+static hipError_t project_pass_t(const Walk &W, const double2 *e, int64_t lde, const double *S, int64_t M,
+                                 const int64_t *m_r, int64_t pps, int32_t ntasks, int32_t nsplit, const Task *tasks,
+                                 const TaskItem *items, double2 *partial, int64_t nrep, hipStream_t s) {
+    const size_t lds = project_pass_lds_bytes(W.d);
+    static size_t granted = kLdsDefault;
+    const auto kern = project_pass_kernel<CAP, P, kBatchRT, kPassWaves, kPassTM>;
+    const hipError_t err = allow_lds((const void *)kern, lds, granted);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(kern, dim3((unsigned)ntasks, (unsigned)nsplit), dim3(kPassWaves * 64), lds, s, W, e, lde, S,
+                       M, m_r, pps, tasks, items, partial, nrep);
+    return hipGetLastError();
+}
+
+hipError_t launch_project_pass(int cap, const Walk &W, const double2 *e, int64_t lde, const double *S, int64_t M,
+                               const int64_t *m_r, int64_t pps, int32_t ntasks, int32_t nsplit, const Task *tasks,
+                               const TaskItem *items, double2 *partial, int64_t nrep, hipStream_t s) {
+    if (project_pass_lds_bytes(W.d) > kLdsMax) return hipErrorInvalidValue;
+    const bool two = pass_paths_per_lane(W.d) == 2;
+#define QR_PASS_CAP(C)                                                                                           \
+    case C:                                                                                                      \
+        return two ? project_pass_t<C, 2>(W, e, lde, S, M, m_r, pps, ntasks, nsplit, tasks, items, partial, nrep, s) \
+                   : project_pass_t<C, 1>(W, e, lde, S, M, m_r, pps, ntasks, nsplit, tasks, items, partial, nrep, s);
+    switch (cap) {
+        QR_PASS_CAP(2)
+        QR_PASS_CAP(4)
+        QR_PASS_CAP(6)
+        QR_PASS_CAP(8)
+    }
+#undef QR_PASS_CAP
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_zero(double *p, int64_t n, hipStream_t s) {

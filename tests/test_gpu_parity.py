@@ -416,6 +416,40 @@ def test_batched_equals_unbatched_full_set(env):
         assert err <= TOL * ref.abs().max().item(), (f, err)
 
 
+def test_batched_shared_pass_projection(env):
+    """Passes whose members fill the pass's set and cloud take the pass
+    projection (all members' responses against one walk of the set): eight
+    full-set members equal qr_solve for their f_a, and a pass with members of
+    smaller sets and clouds (which then take their own projections) beside
+    one of eight equal members agrees with the oracle."""
+    Q, ctx, torch = env
+    w = W.Workload(name="batch-shared", d=3, N=4, T=1.0, sigma=[[0.5 if a == b else 0.0 for b in range(3)]
+                                                                for a in range(3)],
+                   b0=[0.0] * 3, b1=[0.0] * 3, set_kind="hc_1p", level=12, M=3001, driver="sin",
+                   f_a=0.5, sol_A=1.0, sol_c=1.0, sol_p=0.0, sol_w=[1.0, 1.0, 0.0], seed=9)
+    b = Q.Basis(w.d, w.set_kind, w.level)
+    fas = [0.1 * (k + 1) for k in range(8)]
+    say("batched: eight full-set members (pass projection)")
+    a = torch.zeros((len(fas), w.N, b.n_funcs), dtype=torch.float64, device="cuda")
+    ctx.solve_batched(Q.problem_from(w), b, [(f, w.d, w.level, w.M) for f in fas], w.seed, a)
+    torch.cuda.synchronize()
+    for r, f in enumerate(fas):
+        ref = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device="cuda")
+        ctx.solve(Q.problem_from(w.with_(f_a=f)), b, w.M, w.seed, ref)
+        torch.cuda.synchronize()
+        err = (a[r] - ref).abs().max().item()
+        assert err <= TOL * ref.abs().max().item(), (f, err)
+    full_reps = O.enumerate_set(w.d, w.set_kind, w.level)
+    inst = [(f, w.d, w.level, w.M) for f in fas] + [(0.3, 2, 6, 1500), (0.6, 3, 4, 700)]
+    say("batched: shared pass plus a pass of smaller members")
+    a = torch.full((len(inst), w.N, b.n_funcs), 7.0, dtype=torch.float64, device="cuda")
+    ctx.solve_batched(Q.problem_from(w), b, inst, w.seed, a)
+    torch.cuda.synchronize()
+    got = host(a)
+    for r in (0, 7, 8, 9):
+        _check_batched_instance(got[r], w, full_reps, inst[r], w.seed, range(w.N), what=f"instance {r} {inst[r]}")
+
+
 def test_batched_invalid_arguments(env):
     Q, ctx, torch = env
     w = W.D2_TENSOR4
