@@ -273,7 +273,7 @@ def run_learned(args, torch, W, Q):
     print(f"[bench] plain solve {t_plain:.1f} s", file=sys.stderr, flush=True)
     al = torch.zeros_like(a64)
     t0 = time.perf_counter()
-    rep = ctx.solve_learned(prob, b, w.M, w.seed, al, stream=stream)
+    rep = ctx.solve_learned(prob, b, w.M, w.seed, al, stream=stream, reject=0.5)
     torch.cuda.synchronize()
     t_learned = time.perf_counter() - t0
     print(f"[bench] learned solve {t_learned:.1f} s", file=sys.stderr, flush=True)
@@ -304,10 +304,14 @@ def run_learned(args, torch, W, Q):
         "ms_per_step": t_learned * 1e3, "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64+bf16", "data": "synthetic",
         "config": {"workload": LEARNED, "d": w.d, "N": w.N, "n_funcs": b.n_funcs, "M": w.M,
-                   "train_points": 1 << 18, "heldout_points": 1 << 16, "epochs": 8, "gate": 1e-3},
+                   "train_points": 1 << 18, "heldout_points": 1 << 16, "epochs": 8, "gate": 1e-3,
+                   "reject": 0.5},
         "plain_solve_s": t_plain, "learned_solve_s": t_learned,
         "rel_l2_t0": {"plain": rel_err(a64), "learned": rel_err(al)},
         "surrogates_used": sum(r["used"] for r in rep),
+        "epochs_run": [r["epochs_run"] for r in rep[1:]],
+        "learned_equals_plain": bool(torch.equal(al, a64)),
+        "overhead_vs_plain": t_learned / t_plain - 1.0,
         "heldout_rel_l2": {"min": min(r["heldout_rel_l2"] for r in rep[1:]),
                            "max": max(r["heldout_rel_l2"] for r in rep[1:])},
         "eval_2p20_points_ms": {"expansion": t_exp, "network": t_net, "ratio": t_exp / t_net},

@@ -1614,13 +1614,13 @@ extern "C" qr_status qr_mlp_adam(qr_ctx *c, float *params, const float *grad, fl
     return QR_OK;
 }
 
-// Fit the surrogate of ybar_j (row j of alpha_int) for time index j.
-static qr_status fit_surrogate(qr_ctx *c, const qr_problem *p, const qr_basis *b, int32_t j, uint64_t seed,
-                              const qr_learn_opts *o, float *th, double *mu, double *sigma,
-                              qr_learn_report *rep, hipStream_t s) {
+// Fit a network to ybar_j (row j of alpha_int) on the first nt training and
+// nh held-out pairs, `epochs` epochs of mini-batches of B.
+static qr_status fit_pairs(qr_ctx *c, const qr_problem *p, const qr_basis *b, int32_t j, uint64_t seed,
+                           const qr_learn_opts *o, int64_t nt, int64_t nh, int64_t B, int epochs, float *th,
+                           double *mu, double *sigma, qr_learn_report *rep, hipStream_t s) {
     qr_status st;
     const int d = p->d;
-    const int64_t nt = o->train_points, nh = o->heldout_points;
     double *tx = (double *)c->ltx.p, *tt = (double *)c->ltt.p, *hx = (double *)c->lhx.p, *ht = (double *)c->lht.p;
     float *tf = (float *)c->ltf.p, *ff = (float *)c->lff.p, *hf = (float *)c->lhf.p, *hy = (float *)c->lhy.p;
     const double2 *row = (const double2 *)c->alpha_int.p + (int64_t)j * b->ld();
@@ -1650,35 +1650,75 @@ static qr_status fit_surrogate(qr_ctx *c, const qr_problem *p, const qr_basis *b
     QR_HIP(launch_zero((double *)c->lm.p, kMlpParams / 2 + 1, s), "zero_kernel");
     QR_HIP(launch_zero((double *)c->lv.p, kMlpParams / 2 + 1, s), "zero_kernel");
     float *g = (float *)c->lgrad.p, *m = (float *)c->lm.p, *v = (float *)c->lv.p;
-    const int64_t B = o->batch, nb = nt / B;
+    // held-out relative error of the current parameters against the expansion
+    auto heldout = [&](double *err) -> qr_status {
+        for (int64_t p0 = 0; p0 < nh; p0 += kMlpChunk) {
+            const int64_t k = std::min(kMlpChunk, nh - p0);
+            QR_HIP(mlp_fwd(c, th, k, hf + p0 * kMlpIn, hy + p0, s), "mlp forward");
+        }
+        QR_HIP(launch_heldout(nh, hy, ht, mean, sd, (double *)c->mpart.p, s), "heldout_kernel");
+        double ab[2];
+        const qr_status rs = read_partials(c, (nh + 255) / 256, 2, ab, s);
+        if (rs) return rs;
+        *err = ab[1] > 0.0 ? std::sqrt(ab[0] / ab[1]) : INFINITY;
+        return QR_OK;
+    };
+    const int64_t nb = nt / B;
     int64_t step = 0;
-    double last = 0.0;
-    for (int e = 0; e < o->epochs; ++e) {
+    double last = NAN;
+    rep->trained = 1;
+    rep->used = 0;
+    for (int e = 0; e < epochs; ++e) {
         double ep = 0.0;
         for (int64_t bi = 0; bi < nb; ++bi) {
             QR_HIP(mlp_bwd(c, th, B, ff + bi * B * kMlpIn, tf + bi * B, g, s), "mlp backward");
             QR_HIP(launch_adam(kMlpParams, th, g, m, v, ++step, o->lr, s), "adam_kernel");
-            if (e + 1 == o->epochs) {
+            if (e + 1 == epochs) {
                 double l;
                 if ((st = read_partials(c, (B + 255) / 256, 1, &l, s))) return st;
                 ep += l / (double)B;
             }
         }
-        if (e + 1 == o->epochs) last = ep / (double)nb;
+        rep->epochs_run = e + 1;
+        if (e + 1 == epochs) last = ep / (double)nb;
+        if (e == 0 && o->reject > 0.0 && epochs > 1) {
+            // early rejection: far from the gate after the first epoch
+            double err;
+            if ((st = heldout(&err))) return st;
+            if (err > o->reject) {
+                rep->heldout_rel_l2 = err;
+                rep->train_loss = last;
+                return QR_OK;
+            }
+        }
     }
-    // held-out error against the expansion
-    for (int64_t p0 = 0; p0 < nh; p0 += kMlpChunk) {
-        const int64_t k = std::min(kMlpChunk, nh - p0);
-        QR_HIP(mlp_fwd(c, th, k, hf + p0 * kMlpIn, hy + p0, s), "mlp forward");
-    }
-    QR_HIP(launch_heldout(nh, hy, ht, mean, sd, (double *)c->mpart.p, s), "heldout_kernel");
-    double ab[2];
-    if ((st = read_partials(c, (nh + 255) / 256, 2, ab, s))) return st;
-    rep->heldout_rel_l2 = ab[1] > 0.0 ? std::sqrt(ab[0] / ab[1]) : INFINITY;
+    if ((st = heldout(&rep->heldout_rel_l2))) return st;
     rep->train_loss = last;
-    rep->trained = 1;
     rep->used = rep->heldout_rel_l2 <= o->gate ? 1 : 0;
     return QR_OK;
+}
+
+// Fit the surrogate of ybar_j for time index j.  With reject > 0 a screen
+// comes first: one epoch on the first sixteenth of the pairs (the expansion
+// evaluated at 1/16 of the points, which is most of a fit's cost); a network
+// that is then still above `reject` is not fitted further.
+static qr_status fit_surrogate(qr_ctx *c, const qr_problem *p, const qr_basis *b, int32_t j, uint64_t seed,
+                              const qr_learn_opts *o, float *th, double *mu, double *sigma,
+                              qr_learn_report *rep, hipStream_t s) {
+    if (o->reject > 0.0) {
+        const int64_t nt = o->train_points / 16, nh = std::max<int64_t>(1, o->heldout_points / 16);
+        const int64_t B = std::min<int64_t>(o->batch, nt);
+        if (B >= 64 && o->epochs >= 1) {
+            qr_status st = fit_pairs(c, p, b, j, seed, o, nt, nh, B, 1, th, mu, sigma, rep, s);
+            if (st) return st;
+            if (rep->heldout_rel_l2 > o->reject) {
+                rep->used = 0;
+                return QR_OK;
+            }
+        }
+    }
+    return fit_pairs(c, p, b, j, seed, o, o->train_points, o->heldout_points, o->batch, o->epochs, th, mu, sigma, rep,
+                     s);
 }
 
 extern "C" qr_status qr_solve_learned(qr_ctx *c, const qr_problem *p, const qr_basis *bc, int64_t M,
@@ -1687,9 +1727,10 @@ extern "C" qr_status qr_solve_learned(qr_ctx *c, const qr_problem *p, const qr_b
     qr_basis *b = const_cast<qr_basis *>(bc);
     if (!o || !report) return fail(QR_EINVAL, "qr_solve_learned: NULL opts or report");
     if (o->epochs < 0 || o->batch < 64 || o->batch > QR_MLP_MAX_BATCH || o->train_points < o->batch ||
-        o->heldout_points < 1 || !(o->lr > 0.f) || !(o->gate >= 0.0))
+        o->heldout_points < 1 || !(o->lr > 0.f) || !(o->gate >= 0.0) || !(o->reject >= 0.0))
         return fail(QR_EINVAL, "qr_solve_learned: invalid options (epochs >= 0, 64 <= batch <= %d, "
-                               "train_points >= batch, heldout_points >= 1, lr > 0, gate >= 0)", QR_MLP_MAX_BATCH);
+                               "train_points >= batch, heldout_points >= 1, lr > 0, gate >= 0, reject >= 0)",
+                    QR_MLP_MAX_BATCH);
     qr_status st = prepare(c, p, b, M, stream);
     if (st) return st;
     if (!alpha) return fail(QR_EINVAL, "qr_solve_learned: alpha is NULL");
@@ -1723,7 +1764,7 @@ extern "C" qr_status qr_solve_learned(qr_ctx *c, const qr_problem *p, const qr_b
     if ((st = ensure(c, c->lhy, sizeof(float) * (size_t)nh, "held-out pairs"))) return st;
 
     std::vector<double> mu(N, 0.0), sg(N, 1.0);
-    for (int j = 0; j < N; ++j) report[j] = qr_learn_report{0.0, 0.0, 0, 0, 0.0, 1.0};
+    for (int j = 0; j < N; ++j) report[j] = qr_learn_report{0.0, 0.0, 0, 0, 0.0, 1.0, 0};
     const int db = dim_bucket(p->d, p->nbm);
     const int cap = depth_cap(b->max_nnz);
     const Walk W = make_walk(b->kind, b->level, b->d, b->code());

@@ -84,13 +84,14 @@ class Instance(C.Structure):
 class LearnOpts(C.Structure):
     """Options of the learned form (qr_learn_opts)."""
     _fields_ = [("train_points", C.c_int64), ("heldout_points", C.c_int64), ("epochs", C.c_int32),
-                ("batch", C.c_int32), ("lr", C.c_float), ("gate", C.c_double)]
+                ("batch", C.c_int32), ("lr", C.c_float), ("gate", C.c_double), ("reject", C.c_double)]
 
 
 class LearnReport(C.Structure):
     """Per-time-index outcome of the learned form (qr_learn_report)."""
     _fields_ = [("heldout_rel_l2", C.c_double), ("train_loss", C.c_double), ("trained", C.c_int32),
-                ("used", C.c_int32), ("target_mean", C.c_double), ("target_sd", C.c_double)]
+                ("used", C.c_int32), ("target_mean", C.c_double), ("target_sd", C.c_double),
+                ("epochs_run", C.c_int32)]
 
 
 if not os.path.exists(LIB_PATH):
@@ -435,12 +436,14 @@ class Context:
                                 _stream_ptr(stream)))
 
     def solve_learned(self, prob: Problem, basis: Basis, M: int, seed: int, alpha, train_points=1 << 18,
-                      heldout_points=1 << 16, epochs=8, batch=8192, lr=1e-3, gate=1e-3, params=None, stream=None):
+                      heldout_points=1 << 16, epochs=8, batch=8192, lr=1e-3, gate=1e-3, params=None, stream=None,
+                      reject=0.0):
         """Returns the per-time-index reports as a list of dicts; params (float32
         device [N][MLP_NPARAMS], optional) receives the fitted parameters."""
-        o = LearnOpts(train_points, heldout_points, epochs, batch, lr, gate)
+        o = LearnOpts(train_points, heldout_points, epochs, batch, lr, gate, reject)
         rep = (LearnReport * prob.N)()
         _check(_lib.qr_solve_learned(self._h, C.byref(prob), basis.handle, M, seed, C.byref(o), _dptr(alpha),
                                      rep, _fptr(params), _stream_ptr(stream)))
         return [{"heldout_rel_l2": r.heldout_rel_l2, "train_loss": r.train_loss, "trained": bool(r.trained),
-                 "used": bool(r.used), "target_mean": r.target_mean, "target_sd": r.target_sd} for r in rep]
+                 "used": bool(r.used), "target_mean": r.target_mean, "target_sd": r.target_sd,
+                 "epochs_run": r.epochs_run} for r in rep]

@@ -154,6 +154,28 @@ def test_learned_solve_with_closed_gate_is_the_plain_solve(env):
     assert np.abs(got - oref).max() <= 1e-10 * np.abs(oref).max()
 
 
+def test_learned_early_rejection(env):
+    """A cloud of 100 paths for 81 functions: each ybar_j is Monte-Carlo
+    noise, which no network fits.  With reject = 0.5 every fit stops after
+    its first epoch (held-out error above 0.5), none is used, and the result
+    is qr_solve's bit for bit; without it every epoch runs."""
+    Q, ctx, torch = env
+    w = W.D2_TENSOR4.with_(M=100)
+    b = Q.Basis(w.d, w.set_kind, w.level)
+    ref = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device="cuda")
+    ctx.solve(Q.problem_from(w), b, w.M, w.seed, ref)
+    for reject, runs in ((0.5, 1), (0.0, 4)):
+        a = torch.zeros_like(ref)
+        rep = ctx.solve_learned(Q.problem_from(w), b, w.M, w.seed, a, train_points=1 << 12,
+                                heldout_points=1 << 10, epochs=4, batch=1024, reject=reject)
+        torch.cuda.synchronize()
+        say(f"  reject={reject}: " + _report(rep) + " epochs " + " ".join(str(r["epochs_run"]) for r in rep))
+        assert all(r["trained"] and not r["used"] and r["epochs_run"] == runs for r in rep[1:])
+        if reject:
+            assert all(r["heldout_rel_l2"] > 0.5 for r in rep[1:])
+        assert torch.equal(a, ref)
+
+
 def test_learned_solve_uses_the_surrogate_where_it_passes(env):
     """d = 2 tensor set of level 1 (9 functions): the expansions are
     trigonometric polynomials of degree 1, which the network fits within this
@@ -232,7 +254,7 @@ def test_learned_solve_invalid_options(env):
     a = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device="cuda")
     prob = Q.problem_from(w)
     for kw in ({"batch": 32}, {"epochs": -1}, {"train_points": 100, "batch": 1024}, {"heldout_points": 0},
-               {"lr": 0.0}, {"gate": -1.0}):
+               {"lr": 0.0}, {"gate": -1.0}, {"reject": -1.0}):
         with pytest.raises(Q.QrError):
             ctx.solve_learned(prob, b, 100, 0, a, **kw)
     with pytest.raises(Q.QrError) as e:
