@@ -147,6 +147,8 @@ def parse():
                     help="damping exponent q of the plain FP64 solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=30.0)
+    ap.add_argument("--cpu-plan", action="store_true",
+                    help="time the CPU oracle on every configuration (no GPU work) and exit")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device copy of this size (for counter scaling)")
     return ap.parse_args()
@@ -178,6 +180,33 @@ def cpu_baseline(w, target_s: float):
             "sample": f"one backward step i=N-2 with M'={M2} paths (full |Gamma|={nf}); "
                       f"{dt:.1f} s", "seconds": dt, "cpu_model": cpu_model(),
             "full_solve_s_extrapolated": full / rate,
+            "extrapolation": "linear in M |Gamma| N(N+1)/2 basis-evals at the sampled rate"}
+
+
+def cpu_plan(seconds: float):
+    """The oracle on the host cores for every configuration: the d = 2
+    workload's full solve as it stands, and one backward step (i = N-2) of
+    each larger one on a cloud sized to about `seconds`, with the full solve
+    extrapolated linearly in M |Gamma| N(N+1)/2 basis-evals."""
+    import numpy as np
+    import oracle as O
+    import workloads as W
+    legs = []
+    w = W.D2_TENSOR4
+    reps = O.reps_for(w)
+    t0 = time.perf_counter()
+    O.solve(w, reps)
+    dt = time.perf_counter() - t0
+    evals = w.M * O.nfuncs(reps) * w.N * (w.N + 1) / 2
+    legs.append({"workload": w.name, "kind": "full solve", "M": w.M, "seconds": dt, "basis_evals_per_s": evals / dt})
+    print(f"[bench] cpu plan: {w.name} full solve {dt:.2f} s", file=sys.stderr, flush=True)
+    for w in (W.D6_HCMAX16, W.D10_HC1P32_ZRAT, W.D16_HC1P32):
+        r = cpu_baseline(w, seconds)
+        legs.append({"workload": w.name, "kind": "one step i=N-2", "sample": r["sample"], "seconds": r["seconds"],
+                     "basis_evals_per_s": r["value"], "full_solve_s_extrapolated": r["full_solve_s_extrapolated"]})
+        print(f"[bench] cpu plan: {w.name} {r['seconds']:.1f} s", file=sys.stderr, flush=True)
+    return {"metric": "CPU oracle timing plan", "cores": O.num_threads(), "cpu_model": cpu_model(),
+            "kind": "oracle", "legs": legs,
             "extrapolation": "linear in M |Gamma| N(N+1)/2 basis-evals at the sampled rate"}
 
 
@@ -411,6 +440,9 @@ def main():
         print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 "
                                    "(multi-GPU path sharding is a design note, not built)"}))
         sys.exit(2)
+    if args.cpu_plan:
+        print(json.dumps(cpu_plan(args.cpu_seconds / 3)), flush=True)
+        return
     import torch
     import workloads as W
     from paper_2407_21084_amd import qrmc as Q

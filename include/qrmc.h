@@ -303,6 +303,14 @@ qr_status qr_solve_from(qr_ctx *ctx, const qr_problem *prob, const qr_basis *bas
 qr_status qr_eval(qr_ctx *ctx, const qr_basis *basis, const double *alpha_row, int64_t n,
                   const double *x, double *y, double *grad, void *stream);
 
+/* The prediction y_i of the problem at n points from its row of
+ * coefficients: qr_eval, times (1+|x|^2)^{q/2} for the problem's damping
+ * exponent q (eq (yqi)), with the gradient by the product rule,
+ * D (grad ybar + ybar q x / (1+|x|^2)).  Arguments as in qr_eval; with
+ * q = 0 it is qr_eval. */
+qr_status qr_eval_y(qr_ctx *ctx, const qr_problem *prob, const qr_basis *basis, const double *alpha_row,
+                    int64_t n, const double *x, double *y, double *grad, void *stream);
+
 /* ---------------------------------------------------------------------- */
 /* Evaluation without allocation                                           */
 /* ---------------------------------------------------------------------- */
@@ -521,6 +529,26 @@ typedef struct {
  * must not depend on z (QR_ENOTSUP otherwise).  inst: host array of R. */
 qr_status qr_solve_batched(qr_ctx *ctx, const qr_problem *prob, const qr_basis *basis, int32_t R,
                            const qr_instance *inst, uint64_t seed, double *alpha, void *stream);
+
+/* The batched solve as one HIP graph, for callers that repeat it (the same
+ * instances and seed on new data in the same buffers, or serving loops):
+ * qr_batch_graph_create plans the solve like qr_solve_batched, allocates the
+ * device buffers it needs as the graph's own (so later calls on the context
+ * cannot move them), runs the solve once on `stream` (alpha then holds its
+ * result) and captures every launch of it into a graph; each
+ * qr_batch_graph_launch replays the whole backward induction of every pass
+ * with one launch, writing alpha again.  `stream` must not be the null
+ * stream.  The graph reads the basis's device tables and the context's
+ * non-finite record (qr_ctx_numeric_status reports a replay's rows): the
+ * basis and the context must outlive it, and the basis must stay on the
+ * context's device.  qr_batch_graph_destroy synchronises the device and
+ * frees the graph and its buffers (NULL is accepted). */
+typedef struct qr_batch_graph qr_batch_graph; /* opaque, library-owned */
+qr_status qr_batch_graph_create(qr_ctx *ctx, const qr_problem *prob, const qr_basis *basis, int32_t R,
+                                const qr_instance *inst, uint64_t seed, double *alpha, void *stream,
+                                qr_batch_graph **out);
+qr_status qr_batch_graph_launch(qr_batch_graph *graph, void *stream);
+void qr_batch_graph_destroy(qr_batch_graph *graph);
 
 /* Host-side copies of the scalar device routines, for unit tests on
  * machines without a GPU.  qr_host_uniform follows the stream layout above;

@@ -600,17 +600,20 @@ double or_mlp_forward(const double *theta, int nu, int d, const double *x)
  * network_j(x) in place of the expansion. */
 static double or_path_response_ex(const or_problem *P, int64_t nrep, const int32_t *reps, int32_t i,
                                   uint64_t seed, uint64_t m, const double *alpha,
-                                  const double *const *nets, const double *mu, const double *sd);
+                                  const double *const *nets, const double *mu, const double *sd,
+                                  double *first);
 
 double or_path_response(const or_problem *P, int64_t nrep, const int32_t *reps, int32_t i,
                         uint64_t seed, uint64_t m, const double *alpha)
 {
-    return or_path_response_ex(P, nrep, reps, i, seed, m, alpha, NULL, NULL, NULL);
+    return or_path_response_ex(P, nrep, reps, i, seed, m, alpha, NULL, NULL, NULL, NULL);
 }
 
+/* first (if not NULL) receives the term j = i of the driver sum, f(t_i, ...) Delta_i */
 static double or_path_response_ex(const or_problem *P, int64_t nrep, const int32_t *reps, int32_t i,
                                   uint64_t seed, uint64_t m, const double *alpha,
-                                  const double *const *nets, const double *mu, const double *sd)
+                                  const double *const *nets, const double *mu, const double *sd,
+                                  double *first)
 {
     int d = P->d, nbm = P->nbm, N = P->N;
     int64_t nf = or_nfuncs_of(P->basis, nrep);
@@ -641,7 +644,9 @@ static double or_path_response_ex(const or_problem *P, int64_t nrep, const int32
         }
         y = or_trunc(P, y);
         if (need_z) or_sigmaT(P, grad, z);
-        S += (or_fnl(P, P->t[j], x, y, z) + or_msol_h(P, P->t[j], x)) * dt;
+        double term = (or_fnl(P, P->t[j], x, y, z) + or_msol_h(P, P->t[j], x)) * dt;
+        if (j == i && first) *first = term;
+        S += term;
         for (int l = 0; l < d; ++l) x[l] = xn[l];
     }
     S += or_g(P, x);
@@ -718,6 +723,44 @@ int or_backward_step(const or_problem *P, int64_t nrep, const int32_t *reps, int
     return 0;
 }
 
+/* Z of the multistep scheme, eq (MDP:intro:0a), at time index i (q = 0):
+ * with the paths, streams and later rows of or_backward_step, the response
+ * of path m is S^Z_m = g(X_N) + sum_{j=i+1}^{N-1} f_j Delta_j (the driver sum
+ * without its term j = i) times the first Brownian increment
+ * dW_{i,k}(m) / Delta_i (the normals r = d + k of the path's stream), and
+ * alpha_z[k][f] = (1/M) sum_m S^Z_m dW_{i,k}(m) / Delta_i phi_f(X_i^m) for
+ * k < nbm (row-major [nbm][n_funcs]); absum_z likewise, or NULL. */
+int or_backward_step_z(const or_problem *P, int64_t nrep, const int32_t *reps, int32_t i,
+                       int64_t M, uint64_t seed, const double *alpha, double *alpha_z, double *absum_z)
+{
+    if (i < 0 || i >= P->N || M <= 0 || P->damping_q != 0.0) return -1;
+    int d = P->d, nbm = P->nbm;
+    int64_t nf = or_nfuncs_of(P->basis, nrep);
+    double dt = P->t[i + 1] - P->t[i];
+    double *x = (double *)malloc(sizeof(double) * (size_t)(M * d));
+    double *SZ = (double *)malloc(sizeof(double) * (size_t)M);
+    double *r = (double *)malloc(sizeof(double) * (size_t)M);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t m = 0; m < M; ++m) {
+        double first = 0.0;
+        or_start_point(P, seed, i, (uint64_t)m, x + m * d);
+        double S = or_path_response_ex(P, nrep, reps, i, seed, (uint64_t)m, alpha, NULL, NULL, NULL, &first);
+        SZ[m] = S - first;
+    }
+    for (int k = 0; k < nbm; ++k) {
+        for (int64_t m = 0; m < M; ++m) {
+            double dw = sqrt(dt) * or_norm_icdf(or_uniform(seed, 0u, (uint64_t)m, (uint32_t)i, (uint32_t)(d + k)));
+            r[m] = SZ[m] * dw / dt;
+        }
+        or_project(d, P->nu, P->basis, nrep, reps, M, x, r, alpha_z + (int64_t)k * nf,
+                   absum_z ? absum_z + (int64_t)k * nf : NULL);
+    }
+    free(x);
+    free(SZ);
+    free(r);
+    return 0;
+}
+
 /* One backward iteration of the learned form: as or_backward_step, with
  * the surrogate nets[j] (a parameter vector, or NULL for the expansion) and
  * its target scaling mu[j], sd[j] in place of the expansion of ybar_j along
@@ -734,7 +777,7 @@ int or_backward_step_learned(const or_problem *P, int64_t nrep, const int32_t *r
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t m = 0; m < M; ++m) {
         or_start_point(P, seed, i, (uint64_t)m, x + m * d);
-        S[m] = or_path_response_ex(P, nrep, reps, i, seed, (uint64_t)m, alpha, nets, mu, sd);
+        S[m] = or_path_response_ex(P, nrep, reps, i, seed, (uint64_t)m, alpha, nets, mu, sd, NULL);
     }
     or_project(d, P->nu, P->basis, nrep, reps, M, x, S, alpha + (int64_t)i * nf, absum);
     free(x);

@@ -604,6 +604,8 @@ struct qr_ctx {
     Buf S, u, alpha_int, partial, row, alpha_b, tiles, xstate, fcoef, fpartial;
     // cosine basis: the carrier table [N][2R-1] and one carrier row
     Buf calpha, crow;
+    // Z regression: the sums' first terms [M], responses [8][M], cloud sizes [8]
+    Buf zf0, zresp, zm;
     int32_t prec_kernel = QR_PREC_KERNEL_AUTO;
     // surrogate network workspace: activations of up to kMlpChunk rows
     Buf mf, mz1, mh1, mz2, mh2, mdz, mdh, my, mdy, mpart, mwork, mcwork;
@@ -715,7 +717,7 @@ extern "C" void qr_ctx_destroy(qr_ctx *c) {
     hipSetDevice(c->dev);
     hipDeviceSynchronize();
     for (Buf *b : {&c->S, &c->u, &c->alpha_int, &c->partial, &c->row, &c->alpha_b, &c->tiles, &c->xstate, &c->fcoef,
-                   &c->fpartial, &c->calpha, &c->crow, &c->mf, &c->mz1, &c->mh1, &c->mz2, &c->mh2, &c->mdz, &c->mdh, &c->my, &c->mdy, &c->mpart, &c->mwork,
+                   &c->fpartial, &c->calpha, &c->crow, &c->zf0, &c->zresp, &c->zm, &c->mf, &c->mz1, &c->mh1, &c->mz2, &c->mh2, &c->mdz, &c->mdh, &c->my, &c->mdy, &c->mpart, &c->mwork,
                    &c->mcwork, &c->lx, &c->lh, &c->ly, &c->lparams, &c->lgrad, &c->lm, &c->lv, &c->ltx, &c->ltt,
                    &c->ltf, &c->lff, &c->lhx, &c->lht, &c->lhf, &c->lhy})
         if (b->p) hipFree(b->p);
@@ -865,7 +867,7 @@ static int dim_bucket(int32_t d, int32_t nbm) {
 // The device copy of the problem also carries the sampling law of the basis
 // used with it, so the path kernels read it from memory per step instead of
 // keeping it in a register across the basis traversal.
-static qr_status upload_problem(qr_ctx *c, const qr_problem *p, int32_t law, hipStream_t s) {
+static DevProblem make_dev_problem(const qr_problem *p, int32_t law) {
     DevProblem h{};
     h.d = p->d;
     h.nbm = p->nbm;
@@ -895,6 +897,11 @@ static qr_status upload_problem(qr_ctx *c, const qr_problem *p, int32_t law, hip
         sw2 += v * v;
     }
     h.sw2 = sw2;
+    return h;
+}
+
+static qr_status upload_problem(qr_ctx *c, const qr_problem *p, int32_t law, hipStream_t s) {
+    const DevProblem h = make_dev_problem(p, law);
     if (c->prob_valid && std::memcmp(&h, &c->h_prob, sizeof h) == 0) return QR_OK;
     // the previous problem may still be read by queued kernels
     QR_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
@@ -979,14 +986,14 @@ static qr_status project_and_reduce(qr_ctx *c, const qr_basis *b, const double2 
 
 static qr_status run_path(qr_ctx *c, const qr_problem *p, const qr_basis *b, int32_t i, int64_t M,
                           uint64_t seed, const double2 *alpha_int, double *S, double2 *u, double *x0,
-                          hipStream_t s) {
+                          hipStream_t s, double *f0 = nullptr) {
     const bool grad = p->driver == QR_F_ZRAT;
     const int64_t ldx = path_state_ld(M, grad);
     // rows 0..d-1: X_j; row d: u(t_j, X_j) for the Sec. 5 driver
     qr_status st = ensure(c, c->xstate, sizeof(double) * (size_t)(p->d + 1) * ldx, "path state");
     if (st) return st;
     PathArgs a{c->d_prob, make_walk(b->kind, b->level, b->d, b->code()), i, M, seed, alpha_int, b->ld(), S, u, x0,
-               (double *)c->xstate.p, ldx};
+               (double *)c->xstate.p, ldx, f0};
     return timed(c, 0, s, "path_kernel", [&] {
         return launch_path(dim_bucket(p->d, p->nbm), depth_cap(b->max_nnz), p->driver == QR_F_ZRAT,
                            p->damping_q != 0.0, a, s);
@@ -1111,6 +1118,104 @@ extern "C" qr_status qr_solve(qr_ctx *c, const qr_problem *p, const qr_basis *bc
     return solve_f64_from(c, p, const_cast<qr_basis *>(bc), p->N - 1, M, seed, alpha, stream);
 }
 
+namespace {
+void pass_split_plan(const qr_basis *w, int64_t M, int32_t *nsplit, int64_t *pps);
+}  // namespace
+
+// Z rows of time index i (eq (MDP:intro:0a)) from the step just run: its
+// responses S and first terms f0 in the context, the start points' phase
+// factors u; nbm projections, kBatchRT at a time on the basis's pass tasks.
+static qr_status project_z(qr_ctx *c, const qr_problem *p, qr_basis *b, int32_t i, int64_t M, uint64_t seed,
+                           double *alpha_z, hipStream_t s) {
+    qr_status st;
+    if ((st = basis_pass_tasks_on_device(b))) return st;
+    int32_t nsplit;
+    int64_t pps;
+    pass_split_plan(b, M, &nsplit, &pps);
+    if ((st = ensure(c, c->zresp, sizeof(double) * (size_t)M * kBatchRT, "Z responses"))) return st;
+    if ((st = ensure(c, c->zm, sizeof(int64_t) * kBatchRT, "Z cloud sizes"))) return st;
+    if ((st = ensure(c, c->partial, sizeof(double2) * (size_t)nsplit * b->nrep * kBatchRT, "partial"))) return st;
+    QR_HIP(launch_fill_i64((int64_t *)c->zm.p, kBatchRT, M, s), "fill_kernel");
+    const int64_t nf = b->nfc();
+    double *zr = (double *)c->zresp.p;
+    double2 *partial = (double2 *)c->partial.p;
+    for (int32_t k0 = 0; k0 < p->nbm; k0 += kBatchRT) {
+        const int32_t nk = std::min<int32_t>(kBatchRT, p->nbm - k0);
+        QR_HIP(launch_z_responses(c->d_prob, seed, i, M, k0, nk, (const double *)c->S.p, (const double *)c->zf0.p, zr,
+                                  s),
+               "z_responses_kernel");
+        st = timed(c, 1, s, "project_pass_kernel", [&] {
+            return launch_project_pass(depth_cap(b->max_nnz), make_walk(b->kind, b->level, b->d, b->code()),
+                                       (const double2 *)c->u.p, M, zr, M, (const int64_t *)c->zm.p, pps,
+                                       (int32_t)b->ptasks.size(), nsplit, b->d_ptasks, b->d_pitems, partial, b->nrep,
+                                       s);
+        });
+        if (st) return st;
+        for (int32_t r = 0; r < nk; ++r) {
+            st = timed(c, 2, s, "reduce_slot_kernel", [&] {
+                return launch_reduce_slot(partial, nsplit, b->nrep, kBatchRT, r, (double)M, b->d_canon_of_trav,
+                                          alpha_z + ((int64_t)i * p->nbm + k0 + r) * nf, c->d_bad, i, s);
+            });
+            if (st) return st;
+        }
+    }
+    return QR_OK;
+}
+
+static qr_status check_z(const qr_problem *p, const qr_basis *b, const double *alpha_z) {
+    if (!alpha_z) return fail(QR_EINVAL, "Z regression: alpha_z is NULL");
+    if (p->damping_q != 0.0) return fail(QR_ENOTSUP, "Z regression: damping exponent q must be 0");
+    if (b->cos) return fail(QR_ENOTSUP, "Z regression: the cosine basis is not supported");
+    if (project_pass_lds_bytes(p->d) > (size_t)160 * 1024) return fail(QR_ENOTSUP, "Z regression: d=%d", p->d);
+    return QR_OK;
+}
+
+extern "C" qr_status qr_backward_step_z(qr_ctx *c, const qr_problem *p, const qr_basis *bc, int32_t i, int64_t M,
+                                        uint64_t seed, double *alpha, double *alpha_z, void *stream) {
+    qr_basis *b = const_cast<qr_basis *>(bc);
+    qr_status st = prepare(c, p, b, M, stream);
+    if (st) return st;
+    if (!alpha) return fail(QR_EINVAL, "qr_backward_step_z: alpha is NULL");
+    if ((st = check_z(p, b, alpha_z))) return st;
+    if (i < 0 || i >= p->N) return fail(QR_EINVAL, "qr_backward_step_z: i=%d outside [0,%d)", i, p->N);
+    if ((st = ensure(c, c->zf0, sizeof(double) * (size_t)M, "first terms"))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    double2 *ai = (double2 *)c->alpha_int.p;
+    const int64_t nf = b->nfc();
+    st = timed(c, 3, s, "gather_kernel", [&] {
+        return launch_gather(alpha, i + 1, p->N - 1 - i, b->nrep, b->ld(), nf, b->d_canon_of_trav, ai, s);
+    });
+    if (st) return st;
+    double *S = (double *)c->S.p;
+    double2 *u = (double2 *)c->u.p;
+    if ((st = run_path(c, p, b, i, M, seed, ai, S, u, nullptr, s, (double *)c->zf0.p))) return st;
+    if ((st = project_and_reduce(c, b, u, S, M, ai + (int64_t)i * b->ld(), alpha + (int64_t)i * nf, i, s))) return st;
+    return project_z(c, p, b, i, M, seed, alpha_z, s);
+}
+
+extern "C" qr_status qr_solve_z(qr_ctx *c, const qr_problem *p, const qr_basis *bc, int64_t M, uint64_t seed,
+                                double *alpha, double *alpha_z, void *stream) {
+    qr_basis *b = const_cast<qr_basis *>(bc);
+    qr_status st = prepare(c, p, b, M, stream);
+    if (st) return st;
+    if (!alpha) return fail(QR_EINVAL, "qr_solve_z: alpha is NULL");
+    if ((st = check_z(p, b, alpha_z))) return st;
+    if ((st = ensure(c, c->zf0, sizeof(double) * (size_t)M, "first terms"))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    double2 *ai = (double2 *)c->alpha_int.p;
+    const int64_t nf = b->nfc();
+    double *S = (double *)c->S.p;
+    double2 *u = (double2 *)c->u.p;
+    if ((st = numeric_clear(c, s))) return st;
+    for (int32_t i = p->N - 1; i >= 0; --i) {
+        if ((st = run_path(c, p, b, i, M, seed, ai, S, u, nullptr, s, (double *)c->zf0.p))) return st;
+        if ((st = project_and_reduce(c, b, u, S, M, ai + (int64_t)i * b->ld(), alpha + (int64_t)i * nf, i, s)))
+            return st;
+        if ((st = project_z(c, p, b, i, M, seed, alpha_z, s))) return st;
+    }
+    return numeric_read(c, s, nullptr);
+}
+
 extern "C" qr_status qr_path_responses(qr_ctx *c, const qr_problem *p, const qr_basis *bc, int32_t i,
                                        int64_t M, uint64_t seed, const double *alpha, double *s_out,
                                        double *x0, void *stream) {
@@ -1180,6 +1285,16 @@ extern "C" qr_status qr_eval(qr_ctx *c, const qr_basis *bc, const double *alpha_
     QR_HIP(launch_eval(depth_cap(b->max_nnz), grad != nullptr, make_walk(b->kind, b->level, b->d, b->code()), row, x,
                        n, y, grad, s),
            "eval_kernel");
+    return QR_OK;
+}
+
+extern "C" qr_status qr_eval_y(qr_ctx *c, const qr_problem *p, const qr_basis *bc, const double *alpha_row,
+                               int64_t n, const double *x, double *y, double *grad, void *stream) {
+    qr_status st = check_problem(p, bc);
+    if (st) return st;
+    if ((st = qr_eval(c, bc, alpha_row, n, x, y, grad, stream))) return st;
+    if (p->damping_q == 0.0 || n == 0) return QR_OK;
+    QR_HIP(launch_undamp(p->d, p->damping_q, x, n, y, grad, (hipStream_t)stream), "undamp_kernel");
     return QR_OK;
 }
 
@@ -1868,12 +1983,29 @@ void pass_split_plan(const qr_basis *w, int64_t M, int32_t *nsplit, int64_t *pps
 }
 }  // namespace
 
-extern "C" qr_status qr_solve_batched(qr_ctx *c, const qr_problem *p, const qr_basis *bc, int32_t R,
-                                      const qr_instance *inst, uint64_t seed, double *alpha,
-                                      void *stream) {
-    qr_basis *b = const_cast<qr_basis *>(bc);
-    qr_status st = begin(c, stream);
-    if (st) return st;
+namespace {
+// A planned batched solve: each instance's own sub-walk, the passes, and the
+// sizes of the buffers they need.
+struct BatchPlan {
+    std::vector<qr_basis *> own;
+    std::vector<PassPlan> passes;
+    int64_t Mmax = 0, total = 0, partial_max = 0;
+    DevBatch hb{};
+};
+// Device buffers a batched solve reads and writes.
+struct BatchBufs {
+    const DevProblem *prob;
+    const DevBatch *batch;
+    double *S;
+    double2 *u, *ab, *partial;
+};
+}  // namespace
+
+// Validation, passes and device tables of a batched solve (host work and
+// basis uploads only; no workspace is touched).
+static qr_status plan_batched(qr_ctx *c, const qr_problem *p, qr_basis *b, int32_t R, const qr_instance *inst,
+                              const double *alpha, BatchPlan &pl) {
+    qr_status st;
     if ((st = check_problem(p, b))) return st;
     if ((st = check_basis_device(b))) return st;
     if (R < 1 || R > QR_MAX_BATCH) return fail(QR_EINVAL, "qr_solve_batched: R=%d outside [1,%d]", R, QR_MAX_BATCH);
@@ -1883,7 +2015,6 @@ extern "C" qr_status qr_solve_batched(qr_ctx *c, const qr_problem *p, const qr_b
     if (p->damping_q != 0.0) return fail(QR_ENOTSUP, "qr_solve_batched: damping exponent q must be 0");
     if (b->cos) return fail(QR_ENOTSUP, "qr_solve_batched: the cosine basis is not supported");
     if (p->driver == QR_F_PAPER) return fail(QR_ENOTSUP, "qr_solve_batched: the Sec. 5 driver is not supported");
-    int64_t Mmax = 0;
     for (int r = 0; r < R; ++r) {
         const qr_instance &I = inst[r];
         if (I.d < 1 || I.d > p->d) return fail(QR_EINVAL, "instance %d: d=%d outside [1,%d]", r, I.d, p->d);
@@ -1892,16 +2023,16 @@ extern "C" qr_status qr_solve_batched(qr_ctx *c, const qr_problem *p, const qr_b
             return fail(QR_EINVAL, "instance %d: level=%d outside [%d,%d]", r, I.level, lmin, b->level);
         if ((st = check_M(I.M))) return st;
         if (!std::isfinite(I.f_a)) return fail(QR_EINVAL, "instance %d: f_a not finite", r);
-        Mmax = std::max(Mmax, I.M);
+        pl.Mmax = std::max(pl.Mmax, I.M);
     }
-    hipStream_t s = (hipStream_t)stream;
 
     // Passes of up to kBatchRT instances.  A pass walks the set of its first
     // member and simulates its cloud, so the cost of a pass is set by its
     // first member; greedily, the costliest remaining instance opens a pass
     // and takes along the costliest others that fit inside its envelope
     // (d, level and M no larger), which ride at no extra walk cost.
-    std::vector<qr_basis *> own(R);
+    std::vector<qr_basis *> &own = pl.own;
+    own.assign(R, nullptr);
     std::vector<double> cost(R);
     for (int r = 0; r < R; ++r) {
         if ((st = sub_basis(b, inst[r].d, inst[r].level, &own[r]))) return st;
@@ -1910,7 +2041,7 @@ extern "C" qr_status qr_solve_batched(qr_ctx *c, const qr_problem *p, const qr_b
     std::vector<int32_t> rem(R);
     for (int r = 0; r < R; ++r) rem[r] = r;
     std::stable_sort(rem.begin(), rem.end(), [&](int32_t a, int32_t q) { return cost[a] > cost[q]; });
-    std::vector<PassPlan> passes;
+    std::vector<PassPlan> &passes = pl.passes;
     while (!rem.empty()) {
         PassPlan P;
         const qr_instance &H = inst[rem[0]];
@@ -1928,12 +2059,10 @@ extern "C" qr_status qr_solve_batched(qr_ctx *c, const qr_problem *p, const qr_b
         rem.swap(left);
         passes.push_back(std::move(P));
     }
-    const int npass = (int)passes.size();
-    int64_t total = 0, partial_max = 0;
     for (PassPlan &P : passes) {
         if ((st = sub_basis(b, P.d, P.level, &P.walk))) return st;
-        P.off = total;
-        total += (int64_t)p->N * P.walk->ld() * kBatchRT;
+        P.off = pl.total;
+        pl.total += (int64_t)p->N * P.walk->ld() * kBatchRT;
     }
     if ((st = basis_on_device(b, c->dev))) return st;
     for (qr_basis *sb : b->subs)
@@ -1951,50 +2080,46 @@ extern "C" qr_status qr_solve_batched(qr_ctx *c, const qr_problem *p, const qr_b
         if (P.shared) {
             if ((st = basis_pass_tasks_on_device(P.walk))) return st;
             pass_split_plan(P.walk, P.M, &P.nsplit, &P.pps);
-            partial_max = std::max(partial_max, (int64_t)P.nsplit * P.walk->nrep * kBatchRT);
+            pl.partial_max = std::max(pl.partial_max, (int64_t)P.nsplit * P.walk->nrep * kBatchRT);
         } else {
             for (int32_t r : P.members) {
                 int32_t nsplit;
                 int64_t pps;
                 split_plan(own[r], inst[r].M, &nsplit, &pps);
-                partial_max = std::max(partial_max, (int64_t)nsplit * own[r]->nrep);
+                pl.partial_max = std::max(pl.partial_max, (int64_t)nsplit * own[r]->nrep);
             }
         }
     }
-    if ((st = upload_problem(c, p, b->law, s))) return st;
-    if ((st = ensure(c, c->S, sizeof(double) * (size_t)Mmax * kBatchRT, "S"))) return st;
-    if ((st = ensure(c, c->u, sizeof(double2) * (size_t)Mmax * p->d, "phase factors"))) return st;
-    if ((st = ensure(c, c->alpha_b, sizeof(double2) * (size_t)total, "batch coefficients"))) return st;
-    if ((st = ensure(c, c->partial, sizeof(double2) * (size_t)partial_max, "partial"))) return st;
-    if (!c->d_batch) QR_HIP(hipMalloc(&c->d_batch, sizeof(DevBatch)), "hipMalloc(batch)");
-
-    // instance parameters in pass-slot order; queued kernels may read the old ones
-    DevBatch hb{};
+    // instance parameters in pass-slot order
+    const int npass = (int)passes.size();
     for (int ps = 0; ps < npass; ++ps) {
-        hb.count[ps] = (int32_t)passes[ps].members.size();
+        pl.hb.count[ps] = (int32_t)passes[ps].members.size();
         for (size_t k = 0; k < passes[ps].members.size(); ++k) {
-            hb.f_a[ps * kBatchRT + k] = inst[passes[ps].members[k]].f_a;
-            hb.m[ps * kBatchRT + k] = inst[passes[ps].members[k]].M;
+            pl.hb.f_a[ps * kBatchRT + k] = inst[passes[ps].members[k]].f_a;
+            pl.hb.m[ps * kBatchRT + k] = inst[passes[ps].members[k]].M;
         }
     }
-    QR_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
-    QR_HIP(hipMemcpy(c->d_batch, &hb, sizeof hb, hipMemcpyHostToDevice), "hipMemcpy(batch)");
+    return QR_OK;
+}
 
+// Every launch of a planned batched solve, in order, on stream s (kernels
+// only: it can be captured into a graph).
+static qr_status enqueue_batched(qr_ctx *c, const qr_problem *p, const qr_basis *b, int32_t R,
+                                 const qr_instance *inst, const BatchPlan &pl, const BatchBufs &B, uint64_t seed,
+                                 double *alpha, hipStream_t s) {
+    qr_status st;
     const int64_t nf = 2 * b->nrep - 1;
-    double2 *ab = (double2 *)c->alpha_b.p;
-    double *S = (double *)c->S.p;
-    double2 *u = (double2 *)c->u.p;
-    double2 *partial = (double2 *)c->partial.p;
     QR_HIP(launch_zero(alpha, (int64_t)R * p->N * nf, s), "zero_kernel");
-    QR_HIP(launch_zero((double *)ab, 2 * total, s), "zero_kernel");
+    QR_HIP(launch_zero((double *)B.ab, 2 * pl.total, s), "zero_kernel");
     const int db = dim_bucket(p->d, p->nbm);
     if ((st = numeric_clear(c, s))) return st;
+    const int npass = (int)pl.passes.size();
     for (int32_t i = p->N - 1; i >= 0; --i) {
         for (int ps = 0; ps < npass; ++ps) {
-            const PassPlan &P = passes[ps];
+            const PassPlan &P = pl.passes[ps];
             const int64_t ld = P.walk->ld();
-            BatchArgs a{c->d_prob, p->d, c->d_batch, ps, make_walk(b->kind, P.level, P.d, b->law), i, P.M, seed,
-                        ab + P.off, ld, S, u};
+            BatchArgs a{B.prob, p->d, B.batch, ps, make_walk(b->kind, P.level, P.d, b->law), i, P.M, seed,
+                        B.ab + P.off, ld, B.S, B.u};
             st = timed(c, 0, s, "batched_path_kernel",
                        [&] { return launch_batched_path(db, depth_cap(P.walk->max_nnz), a, s); });
             if (st) return st;
@@ -2003,15 +2128,15 @@ extern "C" qr_status qr_solve_batched(qr_ctx *c, const qr_problem *p, const qr_b
                 // and phase factors), then each member's own coefficients from it
                 st = timed(c, 1, s, "project_pass_kernel", [&] {
                     return launch_project_pass(depth_cap(P.walk->max_nnz), make_walk(b->kind, P.level, P.d, b->code()),
-                                               u, P.M, S, P.M, c->d_batch->m + (int64_t)ps * kBatchRT, P.pps,
+                                               B.u, P.M, B.S, P.M, B.batch->m + (int64_t)ps * kBatchRT, P.pps,
                                                (int32_t)P.walk->ptasks.size(), P.nsplit, P.walk->d_ptasks,
-                                               P.walk->d_pitems, partial, P.walk->nrep, s);
+                                               P.walk->d_pitems, B.partial, P.walk->nrep, s);
                 });
                 if (st) return st;
             }
             for (size_t k = 0; k < P.members.size(); ++k) {
                 const int32_t r = P.members[k];
-                const qr_basis *ob = own[r];
+                const qr_basis *ob = pl.own[r];
                 const int64_t Mr = inst[r].M;
                 int32_t nsplit = P.nsplit;
                 if (!P.shared) {
@@ -2019,23 +2144,141 @@ extern "C" qr_status qr_solve_batched(qr_ctx *c, const qr_problem *p, const qr_b
                     int64_t pps;
                     split_plan(ob, Mr, &nsplit, &pps);
                     st = timed(c, 1, s, "project_kernel", [&] {
-                        return launch_project(depth_cap(ob->max_nnz), make_walk(b->kind, ob->level, ob->d, b->code()), u,
-                                              P.M, S + (int64_t)k * P.M, Mr, pps, (int32_t)ob->tasks.size(), nsplit,
-                                              ob->d_tasks, ob->d_items, ob->task_max, partial, ob->nrep, s);
+                        return launch_project(depth_cap(ob->max_nnz), make_walk(b->kind, ob->level, ob->d, b->code()),
+                                              B.u, P.M, B.S + (int64_t)k * P.M, Mr, pps, (int32_t)ob->tasks.size(),
+                                              nsplit, ob->d_tasks, ob->d_items, ob->task_max, B.partial, ob->nrep, s);
                     });
                     if (st) return st;
                 }
                 st = timed(c, 2, s, "reduce_batched_kernel", [&] {
-                    return launch_reduce_batched(partial, nsplit, ob->nrep, P.shared ? P.walk->nrep : ob->nrep,
+                    return launch_reduce_batched(B.partial, nsplit, ob->nrep, P.shared ? P.walk->nrep : ob->nrep,
                                                  P.shared ? kBatchRT : 1, (double)Mr, ob->d_ft, b->d_canon_of_trav,
-                                                 P.walk->d_inv, ab + P.off + (int64_t)i * ld * kBatchRT, (int32_t)k,
+                                                 P.walk->d_inv, B.ab + P.off + (int64_t)i * ld * kBatchRT, (int32_t)k,
                                                  alpha + ((int64_t)r * p->N + i) * nf, c->d_bad, i, s);
                 });
                 if (st) return st;
             }
         }
     }
+    return QR_OK;
+}
+
+extern "C" qr_status qr_solve_batched(qr_ctx *c, const qr_problem *p, const qr_basis *bc, int32_t R,
+                                      const qr_instance *inst, uint64_t seed, double *alpha,
+                                      void *stream) {
+    qr_basis *b = const_cast<qr_basis *>(bc);
+    qr_status st = begin(c, stream);
+    if (st) return st;
+    BatchPlan pl;
+    if ((st = plan_batched(c, p, b, R, inst, alpha, pl))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = upload_problem(c, p, b->law, s))) return st;
+    if ((st = ensure(c, c->S, sizeof(double) * (size_t)pl.Mmax * kBatchRT, "S"))) return st;
+    if ((st = ensure(c, c->u, sizeof(double2) * (size_t)pl.Mmax * p->d, "phase factors"))) return st;
+    if ((st = ensure(c, c->alpha_b, sizeof(double2) * (size_t)pl.total, "batch coefficients"))) return st;
+    if ((st = ensure(c, c->partial, sizeof(double2) * (size_t)pl.partial_max, "partial"))) return st;
+    if (!c->d_batch) QR_HIP(hipMalloc(&c->d_batch, sizeof(DevBatch)), "hipMalloc(batch)");
+    // queued kernels may read the old instance parameters
+    QR_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    QR_HIP(hipMemcpy(c->d_batch, &pl.hb, sizeof pl.hb, hipMemcpyHostToDevice), "hipMemcpy(batch)");
+    const BatchBufs B{c->d_prob, c->d_batch, (double *)c->S.p, (double2 *)c->u.p, (double2 *)c->alpha_b.p,
+                      (double2 *)c->partial.p};
+    if ((st = enqueue_batched(c, p, b, R, inst, pl, B, seed, alpha, s))) return st;
     return numeric_read(c, s, nullptr);
+}
+
+// A batched solve captured into a HIP graph, with device buffers of its own
+// (problem, instance parameters, responses, phase factors, coefficient and
+// partial-sum workspace), so that later calls on the context cannot move
+// what the graph reads.
+struct qr_batch_graph {
+    qr_ctx *ctx = nullptr;
+    int dev = -1;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void *mem[6] = {};
+};
+
+extern "C" void qr_batch_graph_destroy(qr_batch_graph *gr) {
+    if (!gr) return;
+    int cur = 0;
+    hipGetDevice(&cur);
+    hipSetDevice(gr->dev);
+    hipDeviceSynchronize();
+    if (gr->exec) hipGraphExecDestroy(gr->exec);
+    if (gr->graph) hipGraphDestroy(gr->graph);
+    for (void *m : gr->mem) hipFree(m);
+    hipSetDevice(cur);
+    delete gr;
+}
+
+extern "C" qr_status qr_batch_graph_create(qr_ctx *c, const qr_problem *p, const qr_basis *bc, int32_t R,
+                                           const qr_instance *inst, uint64_t seed, double *alpha, void *stream,
+                                           qr_batch_graph **out) {
+    if (!out) return fail(QR_EINVAL, "qr_batch_graph_create: out is NULL");
+    *out = nullptr;
+    if (!stream) return fail(QR_EINVAL, "qr_batch_graph_create: capture needs a stream other than the null stream");
+    qr_basis *b = const_cast<qr_basis *>(bc);
+    qr_status st = begin(c, stream);
+    if (st) return st;
+    BatchPlan pl;
+    if ((st = plan_batched(c, p, b, R, inst, alpha, pl))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    qr_batch_graph *gr = new (std::nothrow) qr_batch_graph();
+    if (!gr) return fail(QR_ENOMEM, "qr_batch_graph_create: out of host memory");
+    gr->ctx = c;
+    gr->dev = c->dev;
+    const size_t bytes[6] = {sizeof(DevProblem), sizeof(DevBatch), sizeof(double) * (size_t)pl.Mmax * kBatchRT,
+                             sizeof(double2) * (size_t)pl.Mmax * p->d, sizeof(double2) * (size_t)pl.total,
+                             sizeof(double2) * (size_t)std::max<int64_t>(pl.partial_max, 1)};
+    for (int k = 0; k < 6; ++k) {
+        if (hipMalloc(&gr->mem[k], bytes[k]) != hipSuccess) {
+            hipGetLastError();
+            qr_batch_graph_destroy(gr);
+            return fail(QR_ENOMEM, "qr_batch_graph_create: cannot allocate %zu bytes", bytes[k]);
+        }
+    }
+    const DevProblem hp = make_dev_problem(p, b->law);
+    if (hipMemcpy(gr->mem[0], &hp, sizeof hp, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(gr->mem[1], &pl.hb, sizeof pl.hb, hipMemcpyHostToDevice) != hipSuccess) {
+        qr_batch_graph_destroy(gr);
+        return fail(QR_EDEVICE, "qr_batch_graph_create: upload failed");
+    }
+    const BatchBufs B{(const DevProblem *)gr->mem[0], (const DevBatch *)gr->mem[1], (double *)gr->mem[2],
+                      (double2 *)gr->mem[3], (double2 *)gr->mem[4], (double2 *)gr->mem[5]};
+    // one eager solve first (kernel attributes set, errors reported eagerly);
+    // then the same launches captured
+    if ((st = enqueue_batched(c, p, b, R, inst, pl, B, seed, alpha, s))) {
+        qr_batch_graph_destroy(gr);
+        return st;
+    }
+    const bool timing = c->timing;
+    c->timing = false;
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        st = enqueue_batched(c, p, b, R, inst, pl, B, seed, alpha, s);
+        hipGraph_t g = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(s, &g);
+        gr->graph = g;
+        if (!st && e2 != hipSuccess) e = e2;
+    }
+    c->timing = timing;
+    if (!st && e == hipSuccess) e = hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0);
+    if (st || e != hipSuccess) {
+        hipGetLastError();
+        qr_batch_graph_destroy(gr);
+        return st ? st : fail(QR_EDEVICE, "qr_batch_graph_create: capture failed (%s)", hipGetErrorString(e));
+    }
+    *out = gr;
+    return QR_OK;
+}
+
+extern "C" qr_status qr_batch_graph_launch(qr_batch_graph *gr, void *stream) {
+    if (!gr) return fail(QR_EINVAL, "qr_batch_graph_launch: graph is NULL");
+    qr_status st = begin(gr->ctx, stream);
+    if (st) return st;
+    QR_HIP(hipGraphLaunch(gr->exec, (hipStream_t)stream), "hipGraphLaunch");
+    return QR_OK;
 }
 
 // ---------------------------------------------------------------------------

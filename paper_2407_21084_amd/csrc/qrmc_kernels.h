@@ -76,12 +76,15 @@ struct PathArgs {
     double *x0;
     double *xs;   // path state [d][ldx], ldx >= path_state_ld(M, grad)
     int64_t ldx;
+    double *f0 = nullptr;  // [M] the driver sum's first term f(t_i, ...) Delta_i, or NULL
 };
 
 hipError_t launch_gather(const double *alpha, int32_t row0, int32_t nrows, int64_t nrep, int64_t ld,
                          int64_t nfuncs, const int32_t *canon_of_trav, double2 *alpha_int,
                          hipStream_t s);
 hipError_t launch_pad(int32_t nrows, int64_t nrep, int64_t ld, double2 *alpha_int, hipStream_t s);
+// y <- y D, grad <- D (grad + y q x / (1+|x|^2)) with D = (1+|x|^2)^{q/2}
+hipError_t launch_undamp(int32_t d, double q, const double *x, int64_t n, double *y, double *grad, hipStream_t s);
 // cosine rows [row0, row0 + nrows) of acos ([.][ncos]) into carrier rows of
 // acar ([.][2 nrep - 1]); one carrier row into one cosine row
 hipError_t launch_cos_expand(const double *acos, int32_t row0, int32_t nrows, int64_t ncos, int64_t nrep,
@@ -122,6 +125,16 @@ hipError_t launch_project_pass(int cap, const Walk &W, const double2 *e, int64_t
                                const int64_t *m_r, int64_t pps, int32_t ntasks, int32_t nsplit, const Task *tasks,
                                const TaskItem *items, double2 *partial, int64_t nrep, hipStream_t s);
 hipError_t launch_zero(double *p, int64_t n, hipStream_t s);
+hipError_t launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s);
+
+// Z of the multistep scheme: responses out[r][m] = (S[m] - f0[m]) dW_{i,k0+r}(m) / Delta_i
+// for r < nk (0 for nk <= r < kBatchRT), dW the first increment of path m's stream
+hipError_t launch_z_responses(const DevProblem *P, uint64_t seed, int32_t i, int64_t M, int32_t k0, int32_t nk,
+                              const double *S, const double *f0, double *out, hipStream_t s);
+// canonical row of response slot `slot` of a pass-projection partial [nsplit][nrep][R]
+hipError_t launch_reduce_slot(const double2 *partial, int32_t nsplit, int64_t nrep, int32_t R, int32_t slot,
+                              double M, const int32_t *canon_of_trav, double *alpha_row, int32_t *bad, int32_t step,
+                              hipStream_t s);
 
 
 // step-major path simulation (learned form); x, u SoA [d][M]

@@ -351,7 +351,7 @@ void path_kernel(
     const DevProblem *__restrict__ P0, const Walk W, const int32_t i, const int64_t M,
     const uint64_t seed, const double2 *__restrict__ alpha_int, const int64_t ld,
     double *__restrict__ S_out, double2 *__restrict__ e_out, double *__restrict__ x_out,
-    double *__restrict__ xg, const int64_t ldx) {
+    double *__restrict__ xg, const int64_t ldx, double *__restrict__ f0_out) {
     extern __shared__ double2 lds[];
     const int tid = threadIdx.x;
     const int d = P0->d, nbm = P0->nbm, N = P0->N;
@@ -485,6 +485,11 @@ void path_kernel(
             const double uc = Pj->driver == QR_F_PAPER ? xg[d * ldx + q * kPathBlock] : 0.0;
             const double f = fnl(Pj, yq, z2[q], uc) + hj[q];
             S[q] = fma(f, dt, S[q]);
+            if (f0_out && j == i) {
+                // the first term, for the Z regression (its responses leave it out)
+                const int64_t m = base + (int64_t)q * kPathBlock;
+                if (m < M) f0_out[m] = S[q];
+            }
         }
     }
 #pragma unroll
@@ -1453,6 +1458,44 @@ __global__ void reduce_batched_kernel(const double2 *__restrict__ partial, int32
     }
 }
 
+// Z of eq (MDP:intro:0a): the multistep sum without its first term, times the
+// first Brownian increment over Delta_i (the normals r = d + k of the stream)
+__global__ void z_responses_kernel(const DevProblem *__restrict__ P, uint64_t seed, int32_t i, int64_t M, int32_t k0,
+                                   int32_t nk, const double *__restrict__ S, const double *__restrict__ f0,
+                                   double *__restrict__ out) {
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    const double dt = P->t[i + 1] - P->t[i];
+    const double sz = (S[m] - f0[m]) / dt;
+    const double sq = sqrt(dt);
+    for (int r = 0; r < kBatchRT; ++r) {
+        double v = 0.0;
+        if (r < nk) v = sz * (sq * norm_icdf(uniform_at(seed, 0u, (uint64_t)m, (uint32_t)i, (uint32_t)(P->d + k0 + r))));
+        out[(int64_t)r * M + m] = v;
+    }
+}
+
+__global__ void reduce_slot_kernel(const double2 *__restrict__ partial, int32_t nsplit, int64_t nrep, int32_t R,
+                                   int32_t slot, double M, const int32_t *__restrict__ canon_of_trav,
+                                   double *__restrict__ alpha_row, int32_t *__restrict__ bad, int32_t step) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nrep) return;
+    double sx = 0.0, sy = 0.0;
+    for (int s = 0; s < nsplit; ++s) {
+        const double2 p = partial[((int64_t)s * nrep + t) * R + slot];
+        sx += p.x;
+        sy += p.y;
+    }
+    if (bad && !(isfinite(sx) && isfinite(sy))) atomicMax(bad, step);
+    if (t == 0) {
+        alpha_row[0] = sx / M;
+    } else {
+        const int64_t c = canon_of_trav[t];
+        alpha_row[2 * c - 1] = M_SQRT2 * (sx / M);
+        alpha_row[2 * c] = M_SQRT2 * (sy / M);
+    }
+}
+
 __global__ void zero_kernel(double *__restrict__ p, int64_t n) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx < n) p[idx] = 0.0;
@@ -1531,6 +1574,27 @@ hipError_t launch_cos_fold(const double *acar_row, int64_t ncos, const int32_t *
     return hipGetLastError();
 }
 
+// y = ybar D and grad y = D (grad ybar + ybar q x / (1+|x|^2)), D = (1+|x|^2)^{q/2}
+// (eq (yqi)), in place at n points (x SoA [d][n]; grad SoA [d][n] or NULL)
+__global__ void undamp_kernel(int32_t d, double q, const double *__restrict__ x, int64_t n, double *__restrict__ y,
+                              double *__restrict__ grad) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    double r2 = 0.0;
+    for (int l = 0; l < d; ++l) r2 = fma(x[l * n + p], x[l * n + p], r2);
+    const double D = pow(1.0 + r2, 0.5 * q), w = q / (1.0 + r2);
+    const double yb = y[p];
+    if (grad)
+        for (int l = 0; l < d; ++l) grad[l * n + p] = D * fma(yb * w, x[l * n + p], grad[l * n + p]);
+    y[p] = yb * D;
+}
+
+hipError_t launch_undamp(int32_t d, double q, const double *x, int64_t n, double *y, double *grad, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(undamp_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, d, q, x, n, y, grad);
+    return hipGetLastError();
+}
+
 hipError_t launch_pad(int32_t nrows, int64_t nrep, int64_t ld, double2 *alpha_int, hipStream_t s) {
     const int64_t total = (int64_t)nrows * (ld - nrep);
     if (total <= 0) return hipSuccess;
@@ -1554,7 +1618,7 @@ static hipError_t path_t(const PathArgs &a, hipStream_t s) {
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((path_kernel<DB, CAP, GRAD, P, DAMP>), dim3(blocks_for(a.M, (int64_t)kPathBlock * P)),
                        dim3(kPathBlock), lds, s, a.P, a.W, a.i, a.M, a.seed, a.alpha_int, a.ld, a.S,
-                       a.e, a.x0, a.xs, a.ldx);
+                       a.e, a.x0, a.xs, a.ldx, a.f0);
     return hipGetLastError();
 }
 
@@ -1776,6 +1840,32 @@ hipError_t launch_project_pass(int cap, const Walk &W, const double2 *e, int64_t
     }
 #undef QR_PASS_CAP
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_z_responses(const DevProblem *P, uint64_t seed, int32_t i, int64_t M, int32_t k0, int32_t nk,
+                              const double *S, const double *f0, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(z_responses_kernel, dim3(blocks_for(M, 256)), dim3(256), 0, s, P, seed, i, M, k0, nk, S, f0,
+                       out);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_slot(const double2 *partial, int32_t nsplit, int64_t nrep, int32_t R, int32_t slot,
+                              double M, const int32_t *canon_of_trav, double *alpha_row, int32_t *bad, int32_t step,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(reduce_slot_kernel, dim3(blocks_for(nrep, 256)), dim3(256), 0, s, partial, nsplit, nrep, R,
+                       slot, M, canon_of_trav, alpha_row, bad, step);
+    return hipGetLastError();
+}
+
+__global__ void fill_i64_kernel(int64_t *__restrict__ p, int64_t n, int64_t v) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < n) p[idx] = v;
+}
+
+hipError_t launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_i64_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
 }
 
 hipError_t launch_zero(double *p, int64_t n, hipStream_t s) {

@@ -52,7 +52,8 @@ EXPORTS = ["qr_last_error", "qr_version", "qr_build_basis", "qr_build_basis_law"
            "qr_mlp_adam", "qr_solve_learned", "qr_solve_batched",
            "qr_basis_upload", "qr_eval_noalloc", "qr_ctx_set_prec_kernel", "qr_basis_factored",
            "qr_ctx_numeric_status", "qr_build_basis_cos", "qr_basis_family_of", "qr_solve_from",
-           "qr_ctx_set_mem_limit", "qr_ctx_mem_held",
+           "qr_ctx_set_mem_limit", "qr_ctx_mem_held", "qr_eval_y",
+           "qr_batch_graph_create", "qr_batch_graph_launch", "qr_batch_graph_destroy",
            "qr_host_uniform", "qr_host_norm_icdf", "qr_host_philox"]
 
 
@@ -116,6 +117,10 @@ _SIGS = {
     "qr_solve_from": (C.c_int, [_P, C.POINTER(Problem), _P, _I32, _I64, _U64, _I32, _P, _P]),
     "qr_ctx_set_mem_limit": (C.c_int, [_P, _I64]),
     "qr_ctx_mem_held": (C.c_int, [_P, C.POINTER(_I64)]),
+    "qr_eval_y": (C.c_int, [_P, C.POINTER(Problem), _P, _P, _I64, _P, _P, _P, _P]),
+    "qr_batch_graph_create": (C.c_int, [_P, C.POINTER(Problem), _P, _I32, C.c_void_p, _U64, _P, _P, C.POINTER(_P)]),
+    "qr_batch_graph_launch": (C.c_int, [_P, _P]),
+    "qr_batch_graph_destroy": (None, [_P]),
     "qr_basis_info": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I32)]),
     "qr_basis_indices": (C.c_int, [_P, _P]),
     "qr_basis_free": (None, [_P]),
@@ -237,6 +242,24 @@ class Basis:
         if h:
             _lib.qr_basis_free(h)
             self._h = None
+
+
+class BatchGraph:
+    """A captured batched solve (qr_batch_graph); keeps its inputs alive."""
+
+    def __init__(self, h, keep):
+        self._h, self._keep = h, keep
+
+    def launch(self, stream):
+        _check(_lib.qr_batch_graph_launch(self._h, _stream_ptr(stream)))
+
+    def close(self):
+        if self._h:
+            _lib.qr_batch_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
 
 
 def make_problem(d, N, T=None, times=None, sigma=None, b0=None, b1=None, driver="sin", f_a=0.0,
@@ -381,6 +404,11 @@ class Context:
         _check(_lib.qr_eval(self._h, basis.handle, _dptr(alpha_row), n, _dptr(x), _dptr(y),
                             _dptr(grad), _stream_ptr(stream)))
 
+    def eval_y(self, prob: Problem, basis: Basis, alpha_row, x, y, grad=None, stream=None):
+        n = y.shape[0]
+        _check(_lib.qr_eval_y(self._h, C.byref(prob), basis.handle, _dptr(alpha_row), n, _dptr(x), _dptr(y),
+                              _dptr(grad), _stream_ptr(stream)))
+
     def basis_upload(self, basis: Basis):
         _check(_lib.qr_basis_upload(self._h, basis.handle))
 
@@ -413,6 +441,18 @@ class Context:
             arr[r].f_a, arr[r].d, arr[r].level, arr[r].M = float(f_a), int(d), int(level), int(M)
         _check(_lib.qr_solve_batched(self._h, C.byref(prob), basis.handle, R, arr, seed, _dptr(alpha),
                                      _stream_ptr(stream)))
+
+    def batch_graph(self, prob: Problem, basis: Basis, instances, seed: int, alpha, stream):
+        """qr_batch_graph_create: solves once (alpha) and returns a BatchGraph
+        whose launch() replays the whole batched solve."""
+        R = len(instances)
+        arr = (Instance * max(R, 1))()
+        for r, (f_a, d, level, M) in enumerate(instances):
+            arr[r].f_a, arr[r].d, arr[r].level, arr[r].M = float(f_a), int(d), int(level), int(M)
+        h = _P()
+        _check(_lib.qr_batch_graph_create(self._h, C.byref(prob), basis.handle, R, C.cast(arr, C.c_void_p), seed,
+                                          _dptr(alpha), _stream_ptr(stream), C.byref(h)))
+        return BatchGraph(h, (prob, basis, arr, alpha))
 
     # -- learned form ---------------------------------------------------------
     def mlp_init(self, params, seed: int, stream=None):

@@ -126,3 +126,36 @@ def test_damping_argument_checks(env):
         ctx.solve_learned(damped, b, 100, 0, a, train_points=1 << 12, heldout_points=1 << 10,
                           epochs=1, batch=1024, gate=0.0)
     assert e.value.status == -6
+
+
+@pytest.mark.parametrize("q", [0.0, 2.1, 5.1])
+@pytest.mark.parametrize("basis", ["fourier", "cosine"])
+def test_eval_y_damped_prediction(env, q, basis):
+    """qr_eval_y: the prediction y = ybar (1+|x|^2)^{q/2} of a damped problem
+    and its gradient by the product rule, against the oracle's eval_y point
+    by point; with q = 0 it is qr_eval."""
+    Q, ctx, torch = env
+    w = (W.paper_benchmark(2, 4, "hc_max", 9, 100) if basis == "cosine" else _zrat(3, q)).with_(damping_q=q)
+    say(f"eval_y q={q} {basis} {w.name}")
+    b = Q.Basis(w.d, w.set_kind, w.level, law=w.law, basis=w.basis)
+    reps = O.reps_for(w)
+    alpha = W.synthetic_alpha(b.n_funcs, 1, seed=13, scale=0.3)[0]
+    n = 300
+    x = W.law_points(n, w.d, w.law, seed=8)
+    y = torch.empty(n, dtype=torch.float64, device="cuda")
+    g = torch.empty((w.d, n), dtype=torch.float64, device="cuda")
+    ctx.eval_y(Q.problem_from(w), b, dev(torch, alpha), dev(torch, x.T), y, g)
+    torch.cuda.synchronize()
+    yg, gg = host(y), host(g).T
+    for p in range(n):
+        ry, rg = O.eval_y(w, reps, alpha, x[p], grad=True)
+        D = (1.0 + float(x[p] @ x[p])) ** (0.5 * q)
+        scale = np.abs(alpha).sum() * 2 ** (w.d / 2) * D
+        assert abs(yg[p] - ry) <= TOL * scale, (p, yg[p], ry)
+        assert np.abs(gg[p] - rg).max() <= TOL * scale * 2 * math.pi * w.level * (1.0 + q), (p, gg[p], rg)
+    if q == 0.0:
+        # the same walk as qr_eval with the gradient (value-only walks sum in another order)
+        y0, g0 = torch.empty_like(y), torch.empty_like(g)
+        ctx.eval(b, dev(torch, alpha), dev(torch, x.T), y0, g0)
+        torch.cuda.synchronize()
+        assert torch.equal(y, y0) and torch.equal(g, g0)

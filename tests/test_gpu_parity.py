@@ -450,6 +450,49 @@ def test_batched_shared_pass_projection(env):
         _check_batched_instance(got[r], w, full_reps, inst[r], w.seed, range(w.N), what=f"instance {r} {inst[r]}")
 
 
+def test_batched_graph_replays_equal_the_eager_solve(env):
+    """qr_batch_graph: the batched solve captured into one graph.  Its
+    creation solves once; every replay, with the program's own eager work
+    (a plain solve and a smaller batched solve on the same context, which
+    grow and reuse its workspace) and synchronisations in between, gives
+    the eager result bit for bit."""
+    Q, ctx, torch = env
+    w = W.Workload(name="batch-graph", d=5, N=4, T=1.0, sigma=[[0.5 if a == b else 0.0 for b in range(5)]
+                                                               for a in range(5)],
+                   b0=[0.0] * 5, b1=[0.0] * 5, set_kind="hc_1p", level=12, M=3000, driver="sin",
+                   f_a=0.5, sol_A=1.0, sol_c=1.0, sol_p=0.0, sol_w=[1.0, 1.0, 0.0, 0.0, 0.0], seed=7)
+    inst = [(0.3, 5, 12, 3000), (0.7, 2, 12, 2000), (0.5, 3, 4, 2500), (0.2, 4, 6, 1000),
+            (0.9, 5, 8, 1), (0.4, 2, 2, 700), (0.6, 5, 12, 129), (0.25, 1, 12, 3000),
+            (0.8, 3, 12, 1500), (0.35, 4, 1, 900)] + [(0.1 * k, 5, 12, 3000) for k in range(1, 9)]
+    say("batched graph: create and replay")
+    b = Q.Basis(w.d, w.set_kind, w.level)
+    prob = Q.problem_from(w)
+    ref = torch.zeros((len(inst), w.N, b.n_funcs), dtype=torch.float64, device="cuda")
+    ctx.solve_batched(prob, b, inst, w.seed, ref)
+    torch.cuda.synchronize()
+    st = torch.cuda.Stream()
+    a = torch.full_like(ref, 7.0)
+    torch.cuda.synchronize()
+    g = ctx.batch_graph(prob, b, inst, w.seed, a, st)
+    st.synchronize()
+    assert torch.equal(a, ref)
+    with pytest.raises(Q.QrError):
+        ctx.batch_graph(prob, b, inst, w.seed, a, None)  # the null stream cannot be captured
+    try:
+        for k in range(3):
+            a.fill_(float(k))
+            other = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device="cuda")
+            ctx.solve(Q.problem_from(w.with_(f_a=0.1 * k)), b, w.M + 17 * k, k, other)
+            small = torch.zeros((2, w.N, b.n_funcs), dtype=torch.float64, device="cuda")
+            ctx.solve_batched(prob, b, inst[:2], k, small)
+            torch.cuda.synchronize()
+            g.launch(st)
+            st.synchronize()
+            assert torch.equal(a, ref), f"replay {k}"
+    finally:
+        g.close()
+
+
 def test_batched_invalid_arguments(env):
     Q, ctx, torch = env
     w = W.D2_TENSOR4

@@ -883,3 +883,50 @@ def test_paper_driver_lemma31_one_step():
         want = (cos_k * (ES * wu)[None, :]).sum(axis=1)
         ok = np.all(np.abs(a - want) <= 5 * sd)
         assert ok == must_pass, (clip, np.max(np.abs(a - want) / sd))
+
+
+def test_z_regression_one_step_stein_identity():
+    """Z of eq (MDP:intro:0a) on one Euler step (d = 1, N = 1, dX = s dW,
+    f = h): the response is g(X_1) dW / Delta with X_1 = X_0 + s dW, and
+    Gaussian integration by parts gives E[g(x + s dW) dW] = s Delta
+    E[g'(x + s dW)] = -s Delta A w sin(w x + p) e^{-s^2 w^2 Delta / 2}, so
+    E[alpha^Z_k] = -s A w e^{-s^2 w^2 Delta / 2} <sin(w . + p), phi_k>_nu
+    (1-D Gauss-Legendre quadrature in u = F(x)).  Every Monte-Carlo
+    coefficient lies within 5 sample standard deviations; an estimate
+    divided by sqrt(Delta) instead of Delta, or of the opposite sign, would
+    not.  (The sum's first term, which the multistep scheme leaves out, has
+    a mean-zero product with dW: leaving it in adds variance, not bias.)"""
+    s, Dl = 0.8, 0.25
+    w = W.Workload(name="z1", d=1, N=1, T=Dl, sigma=[[s]], b0=[0.0], b1=[0.0], set_kind="tensor", level=4,
+                   M=200_000, driver="linear", f_a=0.0, sol_A=1.0, sol_c=1.0, sol_p=0.3, sol_w=[1.3], seed=5)
+    reps = O.reps_for(w)
+    nf = O.nfuncs(reps)
+    alpha = np.zeros((w.N, nf))
+    az, _ = O.backward_step_z(w, reps, 0, w.M, w.seed, alpha)
+    # the same start points and responses, and the first increments of the paths' stream
+    _, _, x, S = O.backward_step(w, reps, 0, w.M, w.seed, alpha.copy(), want_x=True, want_s=True)
+    h0 = O.msol_h(w, 0.0, x)
+    SZ = S - h0 * Dl                                   # g(X_1): the sum without its term j = i
+    dW = np.array([math.sqrt(Dl) * O.norm_icdf(O.uniform(w.seed, 0, m, 0, 1)) for m in range(w.M)])
+    Phi = np.array([O.basis_values(reps, xi) for xi in x])
+    terms = (SZ * dW / Dl)[:, None] * Phi
+    sd = terms.std(axis=0) / math.sqrt(w.M)
+    assert np.abs(az[0] - terms.mean(axis=0)).max() <= 1e-12 * np.abs(terms).mean()
+    # the closed form
+    gl, gw = np.polynomial.legendre.leggauss(600)
+    u, wu = 0.5 * (gl + 1.0), 0.5 * gw
+    xs = np.log(u) - np.log1p(-u)
+    A, wv, p = w.sol_A, w.sol_w[0], w.sol_p
+    f = np.sin(wv * xs + p)
+    exp = np.zeros(nf)
+    exp[0] = np.sum(wu * f)
+    for r in range(1, reps.shape[0]):
+        k = reps[r, 0]
+        exp[2 * r - 1] = np.sum(wu * f * math.sqrt(2.0) * np.cos(2 * math.pi * k * u))
+        exp[2 * r] = np.sum(wu * f * math.sqrt(2.0) * np.sin(2 * math.pi * k * u))
+    exp *= -s * A * wv * math.exp(-0.5 * s * s * wv * wv * Dl)
+    assert np.all(np.abs(az[0] - exp) <= 5 * sd), np.max(np.abs(az[0] - exp) / sd)
+    assert np.abs(exp).max() > 0.2
+    # planted mistakes: the increment over sqrt(Delta), or the wrong sign
+    assert np.any(np.abs(az[0] * math.sqrt(Dl) - exp) > 5 * sd)
+    assert np.any(np.abs(-az[0] - exp) > 5 * sd)
