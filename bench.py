@@ -349,6 +349,69 @@ def run_learned(args, torch, W, Q):
     ctx.close()
 
 
+ZREG = "z-d6"
+
+
+def run_z(args, torch, W, Q):
+    """The gradient component on the d=6 workload (hyperbolic cross 16,
+    169,209 functions, Allen-Cahn, M = 2^20 unless --M): the plain FP64
+    solve, then the solve with the Z regression of eq (MDP:intro:0a), and
+    the relative L2 errors of Y_0 and Z_0 against u(t_0) and sigma^T grad u(t_0)."""
+    dev = torch.device("cuda:0")
+    w = W.D6_HCMAX16.with_(M=args.M or W.D6_HCMAX16.M)
+    ctx = Q.Context(0)
+    b = Q.Basis(w.d, w.set_kind, w.level)
+    prob = Q.problem_from(w)
+    stream = torch.cuda.current_stream()
+    n_test = 1 << 16
+    xt = torch.empty((w.d, n_test), dtype=torch.float64, device=dev)
+    ctx.sample_points(w.d, w.seed, 1, 0, n_test, xt, stream=stream)
+    wv = torch.tensor(w.sol_w, dtype=torch.float64, device=dev)
+    sig = torch.tensor(w.sigma, dtype=torch.float64, device=dev)
+    e0 = math.exp(-w.sol_c * w.T)
+    u0 = w.sol_B + w.sol_A * e0 * torch.cos(wv @ xt + w.sol_p)
+    z0 = sig.T @ (-w.sol_A * e0 * torch.sin(wv @ xt + w.sol_p)[None, :] * wv[:, None])  # [nbm][n]
+
+    def timed_solve(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    a64 = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device=dev)
+    t_plain = timed_solve(lambda: ctx.solve(prob, b, w.M, w.seed, a64, stream))
+    print(f"[bench] plain solve {t_plain:.2f} s", file=sys.stderr, flush=True)
+    az = torch.zeros((w.N, w.nbm, b.n_funcs), dtype=torch.float64, device=dev)
+    ay = torch.zeros_like(a64)
+    ctx.set_timing(True)
+    ctx.reset_timing()
+    t_z = timed_solve(lambda: ctx.solve_z(prob, b, w.M, w.seed, ay, az, stream))
+    ktime = {name: ctx.kernel_time(k)[0] for k, name in enumerate(("path", "projection", "reduction"))}
+    ctx.set_timing(False)
+    print(f"[bench] solve with Z {t_z:.2f} s", file=sys.stderr, flush=True)
+    y = torch.empty(n_test, dtype=torch.float64, device=dev)
+    ctx.eval(b, ay[0].contiguous(), xt, y, stream=stream)
+    ez = torch.empty((w.nbm, n_test), dtype=torch.float64, device=dev)
+    for k in range(w.nbm):
+        ctx.eval(b, az[0, k].contiguous(), xt, ez[k], stream=stream)
+    torch.cuda.synchronize()
+    line = {
+        "metric": "full-solve time with the Z regression vs plain FP64 (d=6)",
+        "value": t_z, "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": t_z * 1e3, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": ZREG, "d": w.d, "nbm": w.nbm, "N": w.N, "n_funcs": b.n_funcs, "M": w.M},
+        "plain_solve_s": t_plain, "z_solve_s": t_z, "overhead_vs_plain": t_z / t_plain - 1.0,
+        "kernel_ms": ktime,
+        "y_equals_plain": bool(torch.equal(ay, a64)),
+        "rel_l2_t0": {"y": float(torch.linalg.norm(y - u0) / torch.linalg.norm(u0)),
+                      "z": float(torch.linalg.norm(ez - z0) / torch.linalg.norm(z0))},
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 def run_batched(args, torch, W, Q):
     """The batched form: 256 instances (d ~ U{2..12}, M in {2^14..2^20},
     level in {8,16,32}, hyperbolic cross prod(1+|k_l|), sin driver with
@@ -449,6 +512,9 @@ def main():
 
     if args.workload == LEARNED:
         run_learned(args, torch, W, Q)
+        return
+    if args.workload == ZREG:
+        run_z(args, torch, W, Q)
         return
     if args.workload == BATCHED:
         if args.precision != "f64":
