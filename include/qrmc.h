@@ -185,8 +185,13 @@ typedef enum {
  *   u(t,x) = B + A exp(-c (T - t)) cos(w.x + p),   g = u(T, .),
  * where h is the source that makes u solve eq (pde) for the chosen driver:
  *   h = -(d_t u + b.grad u + 1/2 tr(sigma sigma^T hess u)) - f_nl(u, sigma^T grad u).
- * Drift b(t,x)_l = b0_l + b1_l x_l, constant diffusion sigma (d x nbm,
- * row-major), z = sigma^T grad_x y.  T = t[N].
+ * Drift b(t,x)_l = b0_l + b1_l x_l + b2_l sin(x_l) and diffusion
+ *   sigma(t,x)_{lk} = (1 + v_l cos(x_l + omega t)) sigma_{lk}
+ * (sigma: d x nbm, row-major; v = sigma_v, omega = sigma_omega), which is
+ * bounded, Lipschitz in x and, for |v_l| < 1 and sigma sigma^T positive
+ * definite, uniformly elliptic (assumption (A_{b,sigma}), Thm "Norm-stability").
+ * With b2 = v = 0 (zero-initialised fields) sigma is constant.
+ * z = sigma(t_{j+1}, X_{j+1})^T grad_x ybar_{j+1} along the paths.  T = t[N].
  * clamp: level L of the truncation T_L applied to y (use INFINITY for none).
  * damping_q: damping exponent q >= 0 of eq (yqi) (at most QR_MAX_DAMPING).
  * With q > 0 the coefficients describe ybar^{(q)}_i = y_i / (1+|x|^2)^{q/2}
@@ -200,8 +205,9 @@ typedef enum {
  * solves the PDE with b = 0, sigma = I, h = 0 (the quadratic term vanishes on
  * u itself, and h computed from the formula above is zero up to rounding).
  * The paths read u(t_j, X_j) at the start of each step.  Only the plain FP64 entry points
- * (qr_backward_step, qr_solve, qr_path_responses) take q > 0; the
- * reduced-precision, batched and learned forms return QR_ENOTSUP.
+ * (qr_backward_step, qr_solve, qr_solve_from in FP64, qr_path_responses)
+ * take q > 0, and those and the Z regression take a non-zero b2 or v; the
+ * reduced-precision, batched and learned forms return QR_ENOTSUP for either.
  * All arrays are inline; entries beyond d / nbm / N are ignored.
  */
 typedef struct {
@@ -219,6 +225,9 @@ typedef struct {
     double sol_w[QR_MAX_D];
     double damping_q;          /* damping exponent q >= 0 (0: none)          */
     double sol_B;              /* constant offset B of u (0 for the family)  */
+    double b2[QR_MAX_D];       /* bounded drift part b2_l sin(x_l)           */
+    double sigma_v[QR_MAX_D];  /* |v_l| < 1: state dependence of row l       */
+    double sigma_omega;        /* time frequency omega of that dependence    */
 } qr_problem;
 
 /* ---------------------------------------------------------------------- */

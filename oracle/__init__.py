@@ -45,6 +45,7 @@ class Problem(C.Structure):
         ("sol_w", C.c_double * MAXD),
         ("damping_q", C.c_double),
         ("sol_B", C.c_double), ("basis", C.c_int32),
+        ("b2", C.c_double * MAXD), ("sigma_v", C.c_double * MAXD), ("sigma_omega", C.c_double),
     ]
 
 
@@ -219,6 +220,10 @@ def problem(w) -> Problem:
     p.damping_q = w.damping_q
     p.sol_B = w.sol_B
     p.basis = BASES[w.basis]
+    for l in range(w.d):
+        p.b2[l] = 0.0 if w.b2 is None else w.b2[l]
+        p.sigma_v[l] = 0.0 if w.sigma_v is None else w.sigma_v[l]
+    p.sigma_omega = w.sigma_omega
     return p
 
 

@@ -78,13 +78,16 @@ typedef struct {
     double f_a;       /* driver parameter a                                */
     double clamp;     /* truncation level L of T_L (INFINITY: none)        */
     double t[OR_MAXN + 1];          /* time grid t_0 < ... < t_N           */
-    double b0[OR_MAXD], b1[OR_MAXD];/* drift b(t,x)_l = b0_l + b1_l x_l    */
-    double sigma[OR_MAXD * OR_MAXD];/* diffusion, d x nbm, row-major       */
+    double b0[OR_MAXD], b1[OR_MAXD];/* drift b(t,x)_l = b0_l + b1_l x_l + b2_l sin x_l */
+    double sigma[OR_MAXD * OR_MAXD];/* diffusion sigma(t,x)_lk = (1 + v_l cos(x_l + omega t)) sigma_lk, d x nbm, row-major */
     double sol_A, sol_c, sol_p;     /* u(t,x) = B + A e^{-c(T-t)} cos(w.x+p) */
     double sol_w[OR_MAXD];
     double damping_q;               /* damping exponent q >= 0 (eq (yqi))  */
     double sol_B;                   /* constant offset B of u              */
     int32_t basis;                  /* 0: Fourier on Z^d, 1: cosine on N^d */
+    double b2[OR_MAXD];             /* bounded drift part                  */
+    double sigma_v[OR_MAXD];        /* state dependence v_l of sigma's row l */
+    double sigma_omega;             /* its time frequency omega            */
 } or_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -449,12 +452,27 @@ static void or_msol_grad(const or_problem *P, double t, const double *x, double 
     for (int l = 0; l < P->d; ++l) g[l] = a * P->sol_w[l];
 }
 
-/* z = sigma^T v  (v a d-vector, z an nbm-vector) */
-static void or_sigmaT(const or_problem *P, const double *v, double *z)
+/* Coefficients of the forward SDE (assumption (A_{b,sigma})): drift
+ * b(t,x)_l and diffusion sigma(t,x)_{lk}.  Bounded in x apart from the
+ * affine part b1_l x_l, Lipschitz in x, and uniformly elliptic when
+ * |v_l| < 1 and the constant sigma is (Thm "Norm-stability"). */
+static double or_drift(const or_problem *P, double t, const double *x, int l)
+{
+    (void)t;
+    return P->b0[l] + P->b1[l] * x[l] + P->b2[l] * sin(x[l]);
+}
+
+static double or_sigma(const or_problem *P, double t, const double *x, int l, int k)
+{
+    return (1.0 + P->sigma_v[l] * cos(x[l] + P->sigma_omega * t)) * P->sigma[l * P->nbm + k];
+}
+
+/* z = sigma(t,x)^T v  (v a d-vector, z an nbm-vector) */
+static void or_sigmaT(const or_problem *P, double t, const double *x, const double *v, double *z)
 {
     for (int k = 0; k < P->nbm; ++k) {
         double s = 0.0;
-        for (int l = 0; l < P->d; ++l) s += P->sigma[l * P->nbm + k] * v[l];
+        for (int l = 0; l < P->d; ++l) s += or_sigma(P, t, x, l, k) * v[l];
         z[k] = s;
     }
 }
@@ -490,14 +508,14 @@ double or_msol_h(const or_problem *P, double t, const double *x)
     /* the offset B drops out of every derivative */
     double dt_u = P->sol_c * (u - P->sol_B);
     double b_grad = 0.0;
-    for (int l = 0; l < d; ++l) b_grad += (P->b0[l] + P->b1[l] * x[l]) * gu[l];
-    /* hess u = -(u - B) w w^T, so 1/2 tr(sigma sigma^T hess u) = -1/2 (u - B) |sigma^T w|^2 */
+    for (int l = 0; l < d; ++l) b_grad += or_drift(P, t, x, l) * gu[l];
+    /* hess u = -(u - B) w w^T, so 1/2 tr(sigma sigma^T hess u) = -1/2 (u - B) |sigma(t,x)^T w|^2 */
     double sw[OR_MAXD];
-    or_sigmaT(P, P->sol_w, sw);
+    or_sigmaT(P, t, x, P->sol_w, sw);
     double sw2 = 0.0;
     for (int k = 0; k < P->nbm; ++k) sw2 += sw[k] * sw[k];
     double diff = -0.5 * (u - P->sol_B) * sw2;
-    or_sigmaT(P, gu, z);
+    or_sigmaT(P, t, x, gu, z);
     return -(dt_u + b_grad + diff) - or_fnl(P, t, x, u, z);
 }
 
@@ -626,11 +644,11 @@ static double or_path_response_ex(const or_problem *P, int64_t nrep, const int32
             uint32_t r = (uint32_t)(d + (j - i) * nbm + k);
             dw[k] = sqrt(dt) * or_norm_icdf(or_uniform(seed, 0u, m, (uint32_t)i, r));
         }
-        /* Euler step, eq (markov:euler) */
+        /* Euler step, eq (markov:euler), coefficients at (t_j, X_j) */
         for (int l = 0; l < d; ++l) {
             double s = 0.0;
-            for (int k = 0; k < nbm; ++k) s += P->sigma[l * nbm + k] * dw[k];
-            xn[l] = x[l] + (P->b0[l] + P->b1[l] * x[l]) * dt + s;
+            for (int k = 0; k < nbm; ++k) s += or_sigma(P, P->t[j], x, l, k) * dw[k];
+            xn[l] = x[l] + or_drift(P, P->t[j], x, l) * dt + s;
         }
         double y;
         int need_z = (P->driver == 3);
@@ -643,7 +661,8 @@ static double or_path_response_ex(const or_problem *P, int64_t nrep, const int32
             if (need_z) or_msol_grad(P, or_T(P), xn, grad);
         }
         y = or_trunc(P, y);
-        if (need_z) or_sigmaT(P, grad, z);
+        /* z_{j+1} = sigma(t_{j+1}, X_{j+1})^T grad ybar_{j+1}(X_{j+1}) */
+        if (need_z) or_sigmaT(P, P->t[j + 1], xn, grad, z);
         double term = (or_fnl(P, P->t[j], x, y, z) + or_msol_h(P, P->t[j], x)) * dt;
         if (j == i && first) *first = term;
         S += term;

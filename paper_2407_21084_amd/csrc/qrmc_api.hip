@@ -825,6 +825,13 @@ static qr_status timed(qr_ctx *c, int which, hipStream_t s, const char *what, F 
 // ---------------------------------------------------------------------------
 // validation and problem upload
 // ---------------------------------------------------------------------------
+// a problem whose drift or diffusion depends on the state (b2 or v non-zero)
+static bool state_dependent(const qr_problem *p) {
+    for (int l = 0; l < p->d; ++l)
+        if (p->b2[l] != 0.0 || p->sigma_v[l] != 0.0) return true;
+    return false;
+}
+
 static qr_status check_problem(const qr_problem *p, const qr_basis *b) {
     if (!p) return fail(QR_EINVAL, "problem is NULL");
     if (p->d < 1 || p->d > QR_MAX_D) return fail(QR_EINVAL, "problem: d=%d outside [1,%d]", p->d, QR_MAX_D);
@@ -842,6 +849,12 @@ static qr_status check_problem(const qr_problem *p, const qr_basis *b) {
             return fail(QR_EINVAL, "problem: time grid not strictly increasing at j=%d", j);
     for (int v = 0; v < p->d * p->nbm; ++v)
         if (!std::isfinite(p->sigma[v])) return fail(QR_EINVAL, "problem: sigma not finite");
+    for (int l = 0; l < p->d; ++l) {
+        if (!std::isfinite(p->b2[l])) return fail(QR_EINVAL, "problem: b2 not finite");
+        if (!(std::fabs(p->sigma_v[l]) < 1.0))
+            return fail(QR_EINVAL, "problem: |sigma_v[%d]| = %g must be < 1 (uniform ellipticity)", l, p->sigma_v[l]);
+    }
+    if (!std::isfinite(p->sigma_omega)) return fail(QR_EINVAL, "problem: sigma_omega not finite");
     if (b && b->d != p->d) return fail(QR_EINVAL, "basis dimension %d != problem dimension %d", b->d, p->d);
     return QR_OK;
 }
@@ -889,6 +902,12 @@ static DevProblem make_dev_problem(const qr_problem *p, int32_t law) {
     h.sol_p = p->sol_p;
     h.sol_B = p->sol_B;
     h.dq = p->damping_q;
+    h.sdep = state_dependent(p) ? 1 : 0;
+    for (int l = 0; l < p->d; ++l) {
+        h.b2[l] = p->b2[l];
+        h.sv[l] = p->sigma_v[l];
+    }
+    h.somega = p->sigma_omega;
     double sw2 = 0.0;
     for (int k = 0; k < p->nbm; ++k) {
         double v = 0.0;
@@ -996,7 +1015,7 @@ static qr_status run_path(qr_ctx *c, const qr_problem *p, const qr_basis *b, int
                (double *)c->xstate.p, ldx, f0};
     return timed(c, 0, s, "path_kernel", [&] {
         return launch_path(dim_bucket(p->d, p->nbm), depth_cap(b->max_nnz), p->driver == QR_F_ZRAT,
-                           p->damping_q != 0.0, a, s);
+                           state_dependent(p) ? 2 : (p->damping_q != 0.0 ? 1 : 0), a, s);
     });
 }
 
@@ -1387,6 +1406,7 @@ static qr_status prepare_prec(qr_ctx *c, const qr_problem *p, qr_basis *b, int64
     qr_status st = prepare(c, p, b, M, stream);
     if (st) return st;
     if (p->damping_q != 0.0) return fail(QR_ENOTSUP, "reduced-precision form: damping exponent q must be 0");
+    if (state_dependent(p)) return fail(QR_ENOTSUP, "reduced-precision form: state-dependent b2 or sigma_v");
     *tp = tile_plan(p, b);
     if ((st = ensure(c, c->tiles, sizeof(uint2) * (size_t)p->N * tp->ld, "coefficient tiles"))) return st;
     // the spare groups are read ahead and never used; keep them defined
@@ -1852,6 +1872,7 @@ extern "C" qr_status qr_solve_learned(qr_ctx *c, const qr_problem *p, const qr_b
     if (p->driver == QR_F_ZRAT)
         return fail(QR_ENOTSUP, "qr_solve_learned: the driver depends on z (the surrogate has no gradient)");
     if (p->damping_q != 0.0) return fail(QR_ENOTSUP, "qr_solve_learned: damping exponent q must be 0");
+    if (state_dependent(p)) return fail(QR_ENOTSUP, "qr_solve_learned: state-dependent b2 or sigma_v");
     if (b->cos) return fail(QR_ENOTSUP, "qr_solve_learned: the cosine basis is not supported");
     if (p->driver == QR_F_PAPER) return fail(QR_ENOTSUP, "qr_solve_learned: the Sec. 5 driver is not supported");
     hipStream_t s = (hipStream_t)stream;
@@ -2013,6 +2034,7 @@ static qr_status plan_batched(qr_ctx *c, const qr_problem *p, qr_basis *b, int32
     if (p->driver == QR_F_ZRAT)
         return fail(QR_ENOTSUP, "qr_solve_batched: the driver depends on z (gradients are not batched)");
     if (p->damping_q != 0.0) return fail(QR_ENOTSUP, "qr_solve_batched: damping exponent q must be 0");
+    if (state_dependent(p)) return fail(QR_ENOTSUP, "qr_solve_batched: state-dependent b2 or sigma_v");
     if (b->cos) return fail(QR_ENOTSUP, "qr_solve_batched: the cosine basis is not supported");
     if (p->driver == QR_F_PAPER) return fail(QR_ENOTSUP, "qr_solve_batched: the Sec. 5 driver is not supported");
     for (int r = 0; r < R; ++r) {

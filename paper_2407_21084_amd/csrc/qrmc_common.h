@@ -205,6 +205,11 @@ struct DevProblem {
     double sol_w[kMaxD];
     double sw[kMaxD];                 // sigma^T w
     double dq;                        // damping exponent q (0: none)
+    // state-dependent coefficients: drift part b2_l sin(x_l), row scale
+    // 1 + sv_l cos(x_l + somega t) of sigma; sdep = 1 iff any is non-zero
+    double b2[kMaxD], sv[kMaxD];
+    double somega;
+    int32_t sdep;
 };
 
 // Index-set rule of the traversal: a node with budget P (the root has P = 1)

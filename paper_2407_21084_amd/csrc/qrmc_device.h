@@ -96,6 +96,11 @@ __device__ __noinline__ double nl_start_damping(const DevProblem *P, uint64_t se
     return pow(1.0 + r2, 0.5 * P->dq);
 }
 __device__ __noinline__ double nl_sin(double a) { return sin(a); }
+// state-dependent coefficients at (t, x_l): .x = 1 + v_l cos(x_l + omega t),
+// the scale of row l of sigma(t,x); .y = b2_l sin(x_l), the bounded drift part
+__device__ __noinline__ double2 nl_state_coef(const DevProblem *P, double t, double xl, int l) {
+    return make_double2(fma(P->sv[l], cos(fma(P->somega, t, xl)), 1.0), P->b2[l] * sin(xl));
+}
 
 // ---------------------------------------------------------------------------
 // Manufactured problem pieces (closed forms of u, g, h; see qrmc.h)
@@ -114,8 +119,8 @@ __device__ __forceinline__ double fnl(const DevProblem *P, double y, double z2, 
     }
 }
 
-// h(t, x) into .x and u(t, x) into .y
-template <int DB>
+// h(t, x) into .x and u(t, x) into .y; SDEP: b and sigma at (t, x)
+template <int DB, bool SDEP = false>
 __device__ __forceinline__ double2 h_source(const DevProblem *P, double t, const double *x, int d) {
     const double E = P->sol_A * nl_exp(-P->sol_c * (P->T - t));
     double th = P->sol_p, bw = 0.0;
@@ -126,13 +131,34 @@ __device__ __forceinline__ double2 h_source(const DevProblem *P, double t, const
             bw = fma(fma(P->b1[l], x[l], P->b0[l]), P->sol_w[l], bw);
         }
     }
+    double sw2 = P->sw2;             // |sigma^T w|^2
+    if constexpr (SDEP) {
+        double rs[DB];
+#pragma unroll
+        for (int l = 0; l < DB; ++l) {
+            rs[l] = 0.0;
+            if (l < d) {
+                const double2 c = nl_state_coef(P, t, x[l], l);
+                rs[l] = c.x;
+                bw = fma(c.y, P->sol_w[l], bw);
+            }
+        }
+        sw2 = 0.0;
+        for (int k = 0; k < P->nbm; ++k) {
+            double v = 0.0;
+#pragma unroll
+            for (int l = 0; l < DB; ++l)
+                if (l < d) v = fma(P->sigma[l * P->nbm + k] * rs[l], P->sol_w[l], v);
+            sw2 = fma(v, v, sw2);
+        }
+    }
     const double2 sc = nl_sincos(th);
     const double sn = sc.x, cs = sc.y;
     const double v = E * cs;         // u - B: the offset drops out of every derivative
     const double u = v + P->sol_B;
     const double gscale = -E * sn;  // grad u = gscale * w
-    const double z2 = gscale * gscale * P->sw2;
-    return make_double2(-(P->sol_c * v + gscale * bw - 0.5 * v * P->sw2) - fnl(P, u, z2, u), u);
+    const double z2 = gscale * gscale * sw2;
+    return make_double2(-(P->sol_c * v + gscale * bw - 0.5 * v * sw2) - fnl(P, u, z2, u), u);
 }
 
 template <int DB>

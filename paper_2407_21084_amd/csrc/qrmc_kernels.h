@@ -92,7 +92,8 @@ hipError_t launch_cos_expand(const double *acos, int32_t row0, int32_t nrows, in
 hipError_t launch_cos_fold(const double *acar_row, int64_t ncos, const int32_t *fold_off, const int32_t *fold_idx,
                            const double *rep_scale, double *acos_row, hipStream_t s);
 // damp: the problem's damping exponent q is non-zero
-hipError_t launch_path(int db, int cap, bool grad, bool damp, const PathArgs &a, hipStream_t s);
+// feat: 0 plain problem, 1 damping q > 0, 2 damping and state-dependent b, sigma
+hipError_t launch_path(int db, int cap, bool grad, int feat, const PathArgs &a, hipStream_t s);
 // tasks must have been cut to proj_shape(W.d).task_max nodes (task_max is checked)
 hipError_t launch_project(int cap, const Walk &W, const double2 *e, int64_t lde, const double *S, int64_t M,
                           int64_t paths_per_split, int32_t ntasks, int32_t nsplit, const Task *tasks,

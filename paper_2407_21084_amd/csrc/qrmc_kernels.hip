@@ -342,9 +342,11 @@ size_t path_lds_bytes(int32_t d, bool grad, int P) {
 #ifndef QRMC_PATH_WAVES_PER_EU
 #define QRMC_PATH_WAVES_PER_EU 3
 #endif
-// DAMP: damping exponent q > 0 (its own instances, so that the undamped
-// kernels carry no code for it).
-template <int DB, int CAP, bool GRAD, int P, bool DAMP>
+// FEAT: 0 the plain problem, 1 a damping exponent q > 0, 2 also the
+// state-dependent drift and diffusion (each its own instances, so that the
+// plain kernels carry no code for either; with q = 0 the damping code is
+// exact: D = 1 and its gradient term vanishes).
+template <int DB, int CAP, bool GRAD, int P, int FEAT>
 __global__ __launch_bounds__(kPathBlock)
 __attribute__((amdgpu_waves_per_eu(QRMC_PATH_WAVES_PER_EU)))
 void path_kernel(
@@ -352,6 +354,7 @@ void path_kernel(
     const uint64_t seed, const double2 *__restrict__ alpha_int, const int64_t ld,
     double *__restrict__ S_out, double2 *__restrict__ e_out, double *__restrict__ x_out,
     double *__restrict__ xg, const int64_t ldx, double *__restrict__ f0_out) {
+    constexpr bool DAMP = FEAT >= 1, SDEP = FEAT == 2;
     extern __shared__ double2 lds[];
     const int tid = threadIdx.x;
     const int d = P0->d, nbm = P0->nbm, N = P0->N;
@@ -401,20 +404,45 @@ void path_kernel(
             for (int l = 0; l < DB; ++l) x[l] = (l < d) ? xg[l * ldx + q * kPathBlock] : 0.0;
             // the source term only needs X_j; the Sec. 5 driver also reads
             // u(t_j, X_j), parked in the path state's row d
-            const double2 hu = h_source<DB>(Pj, tj, x, d);
+            const double2 hu = h_source<DB, SDEP>(Pj, tj, x, d);
             hj[q] = hu.x;
             if (Pj->driver == QR_F_PAPER) xg[d * ldx + q * kPathBlock] = hu.y;
             // Euler step, eq (markov:euler): normals r = d + (j-i) nbm + k
             PhiloxStream rs(seed, 0u, (uint64_t)m, (uint32_t)i, (uint32_t)(d + (j - i) * nbm));
+            if constexpr (SDEP) {
+                // b and sigma at (t_j, X_j): the noise of row l is scaled as a whole
+                double sc[DB], nz[DB];
 #pragma unroll
-            for (int l = 0; l < DB; ++l)
-                if (l < d) x[l] = fma(fma(Pj->b1[l], x[l], Pj->b0[l]), dt, x[l]);
+                for (int l = 0; l < DB; ++l) {
+                    sc[l] = 0.0;
+                    nz[l] = 0.0;
+                    if (l < d) {
+                        const double2 c = nl_state_coef(Pj, tj, x[l], l);
+                        sc[l] = c.x;
+                        x[l] = fma(fma(Pj->b1[l], x[l], Pj->b0[l]) + c.y, dt, x[l]);
+                    }
+                }
 #pragma unroll 1
-            for (int k = 0; k < nbm; ++k) {
-                const double dwk = sq * nl_norm_icdf(rs.next());
+                for (int k = 0; k < nbm; ++k) {
+                    const double dwk = sq * nl_norm_icdf(rs.next());
+#pragma unroll
+                    for (int l = 0; l < DB; ++l)
+                        if (l < d) nz[l] = fma(Pj->sigma[l * nbm + k], dwk, nz[l]);
+                }
 #pragma unroll
                 for (int l = 0; l < DB; ++l)
-                    if (l < d) x[l] = fma(Pj->sigma[l * nbm + k], dwk, x[l]);
+                    if (l < d) x[l] = fma(sc[l], nz[l], x[l]);
+            } else {
+#pragma unroll
+                for (int l = 0; l < DB; ++l)
+                    if (l < d) x[l] = fma(fma(Pj->b1[l], x[l], Pj->b0[l]), dt, x[l]);
+#pragma unroll 1
+                for (int k = 0; k < nbm; ++k) {
+                    const double dwk = sq * nl_norm_icdf(rs.next());
+#pragma unroll
+                    for (int l = 0; l < DB; ++l)
+                        if (l < d) x[l] = fma(Pj->sigma[l * nbm + k], dwk, x[l]);
+                }
             }
 #pragma unroll
             for (int l = 0; l < DB; ++l)
@@ -448,6 +476,8 @@ void path_kernel(
                             const double xv = xg[l * ldx + q * kPathBlock];
                             gx[l] = phase_freq(Pj->nu) * L.g(l, q) * nl_pdf(Pj->nu, xv);
                             if constexpr (DAMP) gx[l] = D.x * fma(y[q] * D.y, xv, gx[l]);
+                            // z = sigma(t_{j+1}, X_{j+1})^T grad y
+                            if constexpr (SDEP) gx[l] *= nl_state_coef(Pj, Pj->t[j + 1], xv, l).x;
                         }
                     }
                     for (int k = 0; k < nbm; ++k) {
@@ -469,6 +499,11 @@ void path_kernel(
                 y[q] = g_term<DB>(Pj, x, d, GRAD ? gx : nullptr);
                 z2[q] = 0.0;
                 if constexpr (GRAD) {
+                    if constexpr (SDEP) {
+#pragma unroll
+                        for (int l = 0; l < DB; ++l)
+                            if (l < d) gx[l] *= nl_state_coef(Pj, Pj->T, x[l], l).x;
+                    }
                     for (int k = 0; k < nbm; ++k) {
                         double zk = 0.0;
 #pragma unroll
@@ -1609,42 +1644,47 @@ int64_t path_state_ld(int64_t M, bool grad) {
     return (M + per - 1) / per * per;
 }
 
-template <int DB, int CAP, bool GRAD, bool DAMP>
+template <int DB, int CAP, bool GRAD, int FEAT>
 static hipError_t path_t(const PathArgs &a, hipStream_t s) {
     constexpr int P = GRAD ? 1 : kPathP;
     const size_t lds = path_lds_bytes(a.W.d, GRAD, P);
     static size_t granted = kLdsDefault;
-    const hipError_t e = allow_lds((const void *)path_kernel<DB, CAP, GRAD, P, DAMP>, lds, granted);
+    const hipError_t e = allow_lds((const void *)path_kernel<DB, CAP, GRAD, P, FEAT>, lds, granted);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((path_kernel<DB, CAP, GRAD, P, DAMP>), dim3(blocks_for(a.M, (int64_t)kPathBlock * P)),
+    hipLaunchKernelGGL((path_kernel<DB, CAP, GRAD, P, FEAT>), dim3(blocks_for(a.M, (int64_t)kPathBlock * P)),
                        dim3(kPathBlock), lds, s, a.P, a.W, a.i, a.M, a.seed, a.alpha_int, a.ld, a.S,
                        a.e, a.x0, a.xs, a.ldx, a.f0);
     return hipGetLastError();
 }
 
-template <int DB, bool GRAD, bool DAMP>
+template <int DB, bool GRAD, int FEAT>
 static hipError_t path_cap(int cap, const PathArgs &a, hipStream_t s) {
     switch (cap) {
-    case 2: return path_t<DB, 2, GRAD, DAMP>(a, s);
-    case 4: return path_t<DB, 4, GRAD, DAMP>(a, s);
-    case 6: if constexpr (DB >= 6) return path_t<DB, 6, GRAD, DAMP>(a, s); break;
-    case 8: if constexpr (DB >= 8) return path_t<DB, 8, GRAD, DAMP>(a, s); break;
+    case 2: return path_t<DB, 2, GRAD, FEAT>(a, s);
+    case 4: return path_t<DB, 4, GRAD, FEAT>(a, s);
+    case 6: if constexpr (DB >= 6) return path_t<DB, 6, GRAD, FEAT>(a, s); break;
+    case 8: if constexpr (DB >= 8) return path_t<DB, 8, GRAD, FEAT>(a, s); break;
     }
     return hipErrorInvalidValue;
 }
 
-template <bool DAMP>
+template <int FEAT>
 static hipError_t path_db(int db, int cap, bool grad, const PathArgs &a, hipStream_t s) {
     switch (db) {
-    case 4: return grad ? path_cap<4, true, DAMP>(cap, a, s) : path_cap<4, false, DAMP>(cap, a, s);
-    case 8: return grad ? path_cap<8, true, DAMP>(cap, a, s) : path_cap<8, false, DAMP>(cap, a, s);
-    case 16: return grad ? path_cap<16, true, DAMP>(cap, a, s) : path_cap<16, false, DAMP>(cap, a, s);
+    case 4: return grad ? path_cap<4, true, FEAT>(cap, a, s) : path_cap<4, false, FEAT>(cap, a, s);
+    case 8: return grad ? path_cap<8, true, FEAT>(cap, a, s) : path_cap<8, false, FEAT>(cap, a, s);
+    case 16: return grad ? path_cap<16, true, FEAT>(cap, a, s) : path_cap<16, false, FEAT>(cap, a, s);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_path(int db, int cap, bool grad, bool damp, const PathArgs &a, hipStream_t s) {
-    return damp ? path_db<true>(db, cap, grad, a, s) : path_db<false>(db, cap, grad, a, s);
+hipError_t launch_path(int db, int cap, bool grad, int feat, const PathArgs &a, hipStream_t s) {
+    switch (feat) {
+    case 0: return path_db<0>(db, cap, grad, a, s);
+    case 1: return path_db<1>(db, cap, grad, a, s);
+    case 2: return path_db<2>(db, cap, grad, a, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <int CAP, int P, int WAVES, int TM>

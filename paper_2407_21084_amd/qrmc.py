@@ -75,6 +75,7 @@ class Problem(C.Structure):
         ("sol_w", C.c_double * MAX_D),
         ("damping_q", C.c_double),
         ("sol_B", C.c_double),
+        ("b2", C.c_double * MAX_D), ("sigma_v", C.c_double * MAX_D), ("sigma_omega", C.c_double),
     ]
 
 
@@ -267,7 +268,7 @@ class BatchGraph:
 
 def make_problem(d, N, T=None, times=None, sigma=None, b0=None, b1=None, driver="sin", f_a=0.0,
                  sol_A=1.0, sol_c=1.0, sol_p=0.0, sol_w=None, clamp=math.inf, damping_q=0.0,
-                 sol_B=0.0) -> Problem:
+                 sol_B=0.0, b2=None, sigma_v=None, sigma_omega=0.0) -> Problem:
     sigma = np.eye(d) if sigma is None else np.asarray(sigma, dtype=np.float64)
     nbm = sigma.shape[1]
     if times is None:
@@ -288,15 +289,22 @@ def make_problem(d, N, T=None, times=None, sigma=None, b0=None, b1=None, driver=
     p.sol_A, p.sol_c, p.sol_p = sol_A, sol_c, sol_p
     p.damping_q = damping_q
     p.sol_B = sol_B
+    for l in range(d):
+        p.b2[l] = 0.0 if b2 is None else b2[l]
+        p.sigma_v[l] = 0.0 if sigma_v is None else sigma_v[l]
+    p.sigma_omega = sigma_omega
     return p
 
 
 def problem_from(w) -> Problem:
     """Marshal any object with the workload attributes (d, N, T, sigma, b0,
-    b1, driver, f_a, sol_*, clamp, optionally damping_q and sol_B) into a qr_problem."""
+    b1, driver, f_a, sol_*, clamp, optionally damping_q, sol_B, b2, sigma_v and
+    sigma_omega) into a qr_problem."""
     return make_problem(w.d, w.N, T=w.T, sigma=w.sigma, b0=w.b0, b1=w.b1, driver=w.driver,
                         f_a=w.f_a, sol_A=w.sol_A, sol_c=w.sol_c, sol_p=w.sol_p, sol_w=w.sol_w,
-                        clamp=w.clamp, damping_q=getattr(w, "damping_q", 0.0), sol_B=getattr(w, "sol_B", 0.0))
+                        clamp=w.clamp, damping_q=getattr(w, "damping_q", 0.0), sol_B=getattr(w, "sol_B", 0.0),
+                        b2=getattr(w, "b2", None), sigma_v=getattr(w, "sigma_v", None),
+                        sigma_omega=getattr(w, "sigma_omega", 0.0))
 
 
 # ---------------------------------------------------------------------------

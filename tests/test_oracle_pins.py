@@ -269,20 +269,26 @@ def test_expansion_gradient_by_finite_differences():
 # manufactured problems: h makes u solve (pde)
 # ---------------------------------------------------------------------------
 
+@pytest.mark.parametrize("state", [False, True], ids=["const-sigma", "sigma-tx"])
 @pytest.mark.parametrize("driver,f_a", [("linear", 0.0), ("sin", 0.5), ("allen_cahn", 0.0),
-                                        ("zrat", -0.05)])
-def test_manufactured_source_solves_pde(driver, f_a):
+                                        ("zrat", -0.05), ("paper", 0.0)])
+def test_manufactured_source_solves_pde(driver, f_a, state):
     """d_t u + b.grad u + 1/2 tr(sigma sigma^T hess u) + f(u, sigma^T grad u) = 0,
-    derivatives by central finite differences of the oracle's u."""
+    derivatives by central finite differences of the oracle's u; with
+    state=True the drift has its bounded part b2 sin(x) and sigma(t,x) scales
+    row l by 1 + v_l cos(x_l + omega t), both taken at the point (t, x)."""
     d = 3
     rng = np.random.default_rng(0)
     sig = (0.3 * rng.standard_normal((d, 2)) + np.eye(d, 2) * 0.5).tolist()
+    extra = dict(b2=[0.4, -0.3, 0.2], sigma_v=[0.5, -0.7, 0.3], sigma_omega=1.7) if state else {}
     w = W.Workload(name="t", d=d, N=4, T=1.0, sigma=sig, b0=[0.1, -0.2, 0.05],
                    b1=[-0.1, 0.2, 0.0], set_kind="tensor", level=1, M=1, driver=driver, f_a=f_a,
-                   sol_A=0.7, sol_c=0.8, sol_p=0.3, sol_w=[1.0, -0.5, 0.25])
-    S = np.array(sig)
+                   sol_A=0.7, sol_c=0.8, sol_p=0.3, sol_w=[1.0, -0.5, 0.25], **extra)
     for t in (0.1, 0.55):
         for x in rng.standard_normal((3, d)):
+            S = np.array(sig)
+            if state:
+                S = (1.0 + np.array(w.sigma_v) * np.cos(x + w.sigma_omega * t))[:, None] * S
             u = lambda tt, xx: O.msol_u(w, tt, xx)[0]
             h = 1e-4
             ut = (u(t + h, x) - u(t - h, x)) / (2 * h)
@@ -295,6 +301,8 @@ def test_manufactured_source_solves_pde(driver, f_a):
                     H[a, b] = (u(t, x + ea + eb) - u(t, x + ea - eb) - u(t, x - ea + eb)
                                + u(t, x - ea - eb)) / (4 * hh * hh)
             b = np.array(w.b0) + np.array(w.b1) * x
+            if state:
+                b = b + np.array(w.b2) * np.sin(x)
             z = S.T @ grad
             y = u(t, x)
             if driver == "linear":
@@ -303,10 +311,78 @@ def test_manufactured_source_solves_pde(driver, f_a):
                 fnl = f_a * math.sin(y)
             elif driver == "allen_cahn":
                 fnl = y - y ** 3
+            elif driver == "paper":
+                fnl = 0.0  # min(1, (y - u)^2) on u itself
             else:
                 fnl = f_a * (z @ z) / (1 + z @ z) + y / (1 + y * y)
             res = ut + b @ grad + 0.5 * np.trace(S @ S.T @ H) + fnl + O.msol_h(w, t, x)[0]
             assert abs(res) < 2e-6
+
+
+def _state_step_expectation(Dl, s0, v, om, b0, b1, b2, A, c, p, wv, a, t_z_at_end=True, gh=80, gl=600):
+    """Lemma 3.1 for one Euler step of d = 1 from t_1 = Dl to T = 2 Dl with
+    the gradient driver f = a z^2/(1+z^2) + y/(1+y^2) + h: returns E[alpha_k]
+    (Fourier basis on Z, |k| <= 4, logistic law).  The inner expectation over
+    the normal increment is Gauss-Hermite, the outer one Gauss-Legendre in
+    u = F(x); u, h and the coefficient functions are written from the PDE."""
+    T, t0 = 2 * Dl, Dl
+    u = lambda t, x: A * np.exp(-c * (T - t)) * np.cos(wv * x + p)
+    ux = lambda t, x: -A * np.exp(-c * (T - t)) * np.sin(wv * x + p) * wv
+    sig = lambda t, x: (1.0 + v * np.cos(x + om * t)) * s0
+    drift = lambda x: b0 + b1 * x + b2 * np.sin(x)
+    fnl = lambda y, z: a * z * z / (1.0 + z * z) + y / (1.0 + y * y)
+
+    def h(t, x):  # -(u_t + b u_x + 1/2 sigma^2 u_xx) - f_nl(u, sigma u_x), u_xx = -wv^2 u
+        uu = u(t, x)
+        return -(c * uu + drift(x) * ux(t, x) - 0.5 * sig(t, x) ** 2 * wv * wv * uu) - fnl(uu, sig(t, x) * ux(t, x))
+
+    gn, gwn = np.polynomial.hermite_e.hermegauss(gh)
+    gwn = gwn / gwn.sum()
+    lg, lw = np.polynomial.legendre.leggauss(gl)
+    uu, wu = 0.5 * (lg + 1.0), 0.5 * lw
+    xs = np.log(uu) - np.log1p(-uu)
+    x1 = xs[:, None] + drift(xs)[:, None] * Dl + sig(t0, xs)[:, None] * math.sqrt(Dl) * gn[None, :]
+    tz = T if t_z_at_end else t0
+    y1 = u(T, x1)
+    z1 = sig(tz, x1) * ux(T, x1)
+    es = ((y1 + fnl(y1, z1) * Dl) * gwn[None, :]).sum(axis=1) + h(t0, xs) * Dl
+    exp = np.zeros(9)
+    exp[0] = np.sum(wu * es)
+    for k in range(1, 5):
+        exp[2 * k - 1] = np.sum(wu * es * math.sqrt(2.0) * np.cos(2 * math.pi * k * uu))
+        exp[2 * k] = np.sum(wu * es * math.sqrt(2.0) * np.sin(2 * math.pi * k * uu))
+    return exp
+
+
+def test_state_dependent_coefficients_one_step_lemma_3_1():
+    """sigma(t,x) and the bounded drift in the Euler step (coefficients at
+    (t_j, X_j)), and z = sigma(t_{j+1}, X_{j+1})^T grad y in the driver: one
+    step of d = 1 from t_1 > 0 (so omega t matters) with the gradient driver.
+    Every Monte-Carlo coefficient lies within 5 sample standard deviations
+    of Lemma 3.1's expectation; the expectation with constant sigma (v = 0),
+    without b2, or with z's sigma taken at t_j instead of t_{j+1} lies
+    outside that band."""
+    Dl, s0, v, om, b0, b1, b2 = 0.25, 0.8, 0.6, 3.0, 0.1, -0.2, 0.7
+    A, c, p, wv, a = 1.0, 0.5, 0.3, 1.3, 4.0
+    w = W.Workload(name="sdep1", d=1, N=2, T=2 * Dl, sigma=[[s0]], b0=[b0], b1=[b1], set_kind="tensor", level=4,
+                   M=400_000, driver="zrat", f_a=a, sol_A=A, sol_c=c, sol_p=p, sol_w=[wv], seed=9,
+                   b2=[b2], sigma_v=[v], sigma_omega=om)
+    reps = O.reps_for(w)
+    nf = O.nfuncs(reps)
+    alpha = np.zeros((w.N, nf))
+    row, _, x, S = O.backward_step(w, reps, 1, w.M, w.seed, alpha.copy(), want_x=True, want_s=True)
+    Phi = np.array([O.basis_values(reps, xi) for xi in x])
+    terms = S[:, None] * Phi
+    sd = terms.std(axis=0) / math.sqrt(w.M)
+    assert np.abs(row - terms.mean(axis=0)).max() <= 1e-12 * np.abs(terms).mean()
+    args = (Dl, s0, v, om, b0, b1, b2, A, c, p, wv, a)
+    exp = _state_step_expectation(*args)
+    assert np.all(np.abs(row - exp) <= 5 * sd), np.max(np.abs(row - exp) / sd)
+    planted = {"v=0": _state_step_expectation(Dl, s0, 0.0, om, b0, b1, b2, A, c, p, wv, a),
+               "b2=0": _state_step_expectation(Dl, s0, v, om, b0, b1, 0.0, A, c, p, wv, a),
+               "z at t_j": _state_step_expectation(*args, t_z_at_end=False)}
+    for name, e in planted.items():
+        assert np.any(np.abs(row - e) > 5 * sd), name
 
 
 # ---------------------------------------------------------------------------

@@ -23,7 +23,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass, field, replace
-from typing import List
+from typing import List, Optional
 
 import numpy as np
 
@@ -57,6 +57,9 @@ class Workload:
     damping_q: float = 0.0
     basis: str = "fourier"      # "cosine": the paper's cosine basis over N^d
     sol_B: float = 0.0          # constant offset of the manufactured solution
+    b2: Optional[List[float]] = None       # bounded drift part b2_l sin(x_l) (None: 0)
+    sigma_v: Optional[List[float]] = None  # sigma(t,x) row scale 1 + v_l cos(x_l + omega t)
+    sigma_omega: float = 0.0
     notes: str = ""
 
     @property
