@@ -257,6 +257,23 @@ extern "C" qr_status qr_build_basis_law(int32_t d, int32_t kind, int32_t level, 
         }
         b->task_max = proj_shape(d).task_max;
         build_tasks(nodes, subtree, b->task_max, b->items, b->tasks);
+        // costliest first (nodes plus the complex products that start each
+        // item from the root): the waves of a projection block walk
+        // consecutive tasks and wait for each other after every batch of paths
+        std::vector<int64_t> cost(b->tasks.size());
+        for (size_t t = 0; t < b->tasks.size(); ++t) {
+            const Task &T = b->tasks[t];
+            int64_t c = T.rep_count;
+            for (int32_t it = T.item_begin; it < T.item_end; ++it)
+                for (int32_t k = 0; k < b->items[it].depth; ++k) c += std::abs(b->items[it].val[k]);
+            cost[t] = c;
+        }
+        std::vector<size_t> by_cost(b->tasks.size());
+        for (size_t t = 0; t < by_cost.size(); ++t) by_cost[t] = t;
+        std::stable_sort(by_cost.begin(), by_cost.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
+        std::vector<Task> sorted(by_cost.size());
+        for (size_t t = 0; t < by_cost.size(); ++t) sorted[t] = b->tasks[by_cost[t]];
+        b->tasks.swap(sorted);
     } catch (const std::bad_alloc &) {
         delete b;
         return fail(QR_ENOMEM, "qr_build_basis: out of host memory");
@@ -966,11 +983,18 @@ extern "C" qr_status qr_ctx_numeric_status(qr_ctx *c, int32_t *step) {
 // ---------------------------------------------------------------------------
 // step pieces
 // ---------------------------------------------------------------------------
+#ifndef QRMC_PROJ_BLOCKS
+#define QRMC_PROJ_BLOCKS 4096
+#endif
+// blocks a projection aims at (many per CU, so that the last round is short)
+constexpr int64_t kProjBlocks = QRMC_PROJ_BLOCKS;
+
 static void split_plan(const qr_basis *b, int64_t M, int32_t *nsplit, int64_t *pps) {
-    const int64_t ntasks = (int64_t)b->tasks.size();
     const ProjShape sh = proj_shape(b->d);
-    const int64_t group = (int64_t)sh.waves * 64 * sh.P;
-    int64_t want = (2048 + ntasks - 1) / ntasks;
+    // blocks are (group of sh.waves tasks) x slice; a slice is walked 64 P paths at a time
+    const int64_t ngroups = std::max<int64_t>(1, ((int64_t)b->tasks.size() + sh.waves - 1) / sh.waves);
+    const int64_t group = (int64_t)64 * sh.P;
+    int64_t want = (kProjBlocks + ngroups - 1) / ngroups;
     const int64_t maxs = std::max<int64_t>(1, (M + 4 * group - 1) / (4 * group));
     want = std::max<int64_t>(1, std::min(want, maxs));
     int64_t per = (M + want - 1) / want;

@@ -689,52 +689,72 @@ struct ProjSinkR {
 };
 
 static size_t project_lds_bytes(int32_t d, int P, int waves, int task_max) {
-    return (size_t)waves * ((size_t)task_max * sizeof(double2) + (size_t)d * 64 * P * sizeof(double2));
+    return (size_t)waves * task_max * 2 * sizeof(double) + (size_t)d * P * 64 * sizeof(double2) +
+           (size_t)P * 64 * sizeof(double);
 }
 
+// Block (group of WAVES tasks, slice of paths): wave w walks task
+// blockIdx.x WAVES + w, and all waves walk the same 64 P paths at a time,
+// whose phase factors and responses the block stages once per batch in LDS
+// (so a slice is read once per group of tasks, not once per task).  Each
+// wave folds its own task's sums (ProjSink) into its accumulators and writes
+// them as the slice's partial sums of that task.  Tasks are ordered by size,
+// so the waves of a block finish a batch at about the same time.
 template <int CAP, int P, int WAVES, int TM>
 __global__ __launch_bounds__(WAVES * 64) void project_kernel(
     const Walk W, const double2 *__restrict__ e_in, const int64_t lde, const double *__restrict__ s_in,
-    const int64_t M, const int64_t paths_per_split, const Task *__restrict__ tasks,
+    const int64_t M, const int64_t paths_per_split, const int32_t ntasks, const Task *__restrict__ tasks,
     const TaskItem *__restrict__ items, double2 *__restrict__ partial, const int64_t nrep) {
     static_assert(TM % 4 == 0, "groups of four nodes must tile a task");
+    constexpr int NT = WAVES * 64, B = 64 * P;
     extern __shared__ double2 lds[];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int d = W.d;
-    double *accs = reinterpret_cast<double *>(lds);  // [WAVES][TM][2]
-    double2 *Es = lds + WAVES * TM;                 // [WAVES][d][P][64]
+    double *accs = reinterpret_cast<double *>(lds);                          // [WAVES][TM][2]
+    double2 *Es = reinterpret_cast<double2 *>(accs + WAVES * TM * 2);         // [d][P][64]
+    double *Ss = reinterpret_cast<double *>(Es + d * B);                     // [P][64]
 
     double *acc = accs + wave * TM * 2;
-    const LanePts<P> L{Es + wave * d * P * 64 + lane, nullptr, 64};
+    const LanePts<P> L{Es + lane, nullptr, 64};
 
-    const Task task = tasks[blockIdx.x];
+    const int32_t t = (int32_t)blockIdx.x * WAVES + wave;
+    const bool active = t < ntasks;  // wave-uniform
+    const Task task = active ? tasks[t] : Task{0, 0, 0, 0};
     const int64_t m0 = (int64_t)blockIdx.y * paths_per_split;
     const int64_t m1 = min(M, m0 + paths_per_split);
 
     for (int r = lane; r < TM * 2; r += 64) acc[r] = 0.0;
-    wave_sync();
 
     ProjSink<P> sink;
     sink.acc = acc;
     sink.slot = fold_slot(lane);
     sink.lead = (lane & 7) == 0;
     sink.bit3 = (lane >> 3) & 1;
-    for (int64_t gb = m0 + wave * 64 * P; gb < m1; gb += WAVES * 64 * P) {
-#pragma unroll
-        for (int q = 0; q < P; ++q) {
-            const int64_t m = gb + q * 64 + lane;
-            const bool live = m < m1;
-            sink.s[q] = live ? s_in[m] : 0.0;
-            for (int l = 0; l < d; ++l) L.set_e(l, q, live ? e_in[l * lde + m] : make_double2(1.0, 0.0));
+    const int ne = d * B;
+    for (int64_t gb = m0; gb < m1; gb += B) {
+        __syncthreads();  // every wave is done with the previous batch
+        // entry j = (l P + q) 64 + lane' holds coordinate l of path gb + q 64 + lane'
+        for (int j = tid; j < ne; j += NT) {
+            const int l = j / B, r = j - l * B;
+            const int64_t m = gb + r;
+            Es[j] = m < m1 ? e_in[l * lde + m] : make_double2(1.0, 0.0);
         }
+        for (int j = tid; j < B; j += NT) {
+            const int64_t m = gb + j;
+            Ss[j] = m < m1 ? s_in[m] : 0.0;
+        }
+        __syncthreads();
+        if (!active) continue;
+#pragma unroll
+        for (int q = 0; q < P; ++q) sink.s[q] = Ss[q * 64 + lane];
         sink.c = 0;
         sink.base = 0;
         for (int it = task.item_begin; it < task.item_end; ++it) {
             const TaskItem &I = items[it];
             Pts<P> v = unit<P>();
-            for (int t = 0; t < I.depth; ++t) {
-                Pts<P> e = L.e(I.coord[t]);
-                int n = I.val[t];
+            for (int k = 0; k < I.depth; ++k) {
+                Pts<P> e = L.e(I.coord[k]);
+                int n = I.val[k];
                 if (n < 0) {
 #pragma unroll
                     for (int q = 0; q < P; ++q) e.im[q] = -e.im[q];
@@ -748,14 +768,10 @@ __global__ __launch_bounds__(WAVES * 64) void project_kernel(
         }
         if (sink.c) sink.flush();
     }
-    __syncthreads();
+    if (!active) return;
+    wave_sync();
     double *out = reinterpret_cast<double *>(partial + (int64_t)blockIdx.y * nrep + task.rep_begin);
-    for (int r = tid; r < task.rep_count * 2; r += WAVES * 64) {
-        double sacc = 0.0;
-#pragma unroll
-        for (int w = 0; w < WAVES; ++w) sacc += accs[w * TM * 2 + r];
-        out[r] = sacc;
-    }
+    for (int r = lane; r < task.rep_count * 2; r += 64) out[r] = acc[r];
 }
 
 // project_pass_kernel: the projection of a batched pass, R members on the pass's
@@ -1695,21 +1711,32 @@ static hipError_t project_t(const Walk &W, const double2 *e, int64_t lde, const 
     static size_t granted = kLdsDefault;
     const hipError_t err = allow_lds((const void *)project_kernel<CAP, P, WAVES, TM>, lds, granted);
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL((project_kernel<CAP, P, WAVES, TM>), dim3((unsigned)ntasks, (unsigned)nsplit),
-                       dim3(WAVES * 64), lds, s, W, e, lde, S, M, pps, tasks, items, partial, nrep);
+    const unsigned groups = (unsigned)((ntasks + WAVES - 1) / WAVES);
+    hipLaunchKernelGGL((project_kernel<CAP, P, WAVES, TM>), dim3(groups, (unsigned)nsplit), dim3(WAVES * 64), lds,
+                       s, W, e, lde, S, M, pps, ntasks, tasks, items, partial, nrep);
     return hipGetLastError();
 }
 
-// The shapes, widest first: eight waves with two paths per lane and tasks of
-// 512 nodes (d <= 6), four waves with tasks of 1024 (d <= 12), then one path
-// per lane.  Larger tasks were measured faster at equal occupancy: fewer
-// restarts of the walk and fewer loads of a cloud slice per node.
-constexpr ProjShape kProjShapes[3] = {{2, 8, 512}, {2, 4, 1024}, {1, 4, 1024}};
+// The shapes (paths per lane, waves, task size), in order of preference; the
+// first whose LDS fits is used.
+#ifndef QRMC_PROJ_SHAPES
+#define QRMC_PROJ_SHAPES {4, 8, 512}, {2, 8, 512}, {1, 8, 512}
+#endif
+constexpr ProjShape kProjShapes[3] = {QRMC_PROJ_SHAPES};
 
 ProjShape proj_shape(int32_t d) {
     for (const ProjShape &p : kProjShapes)
         if (project_lds_bytes(d, p.P, p.waves, p.task_max) <= kLdsMax) return p;
     return kProjShapes[2];
+}
+
+template <int CAP, int I>
+static hipError_t project_i(const Walk &W, const double2 *e, int64_t lde, const double *S, int64_t M, int64_t pps,
+                            int32_t ntasks, int32_t nsplit, const Task *tasks, const TaskItem *items,
+                            double2 *partial, int64_t nrep, hipStream_t s) {
+    constexpr ProjShape p = kProjShapes[I];
+    return project_t<CAP, p.P, p.waves, p.task_max>(W, e, lde, S, M, pps, ntasks, nsplit, tasks, items, partial,
+                                                       nrep, s);
 }
 
 template <int CAP>
@@ -1719,11 +1746,10 @@ static hipError_t project_p(const Walk &W, const double2 *e, int64_t lde, const 
     const ProjShape p = proj_shape(W.d);
     if (task_max != p.task_max || project_lds_bytes(W.d, p.P, p.waves, p.task_max) > kLdsMax)
         return hipErrorInvalidValue;
-    if (p.waves == 8)
-        return project_t<CAP, 2, 8, 512>(W, e, lde, S, M, pps, ntasks, nsplit, tasks, items, partial, nrep, s);
-    if (p.P == 2)
-        return project_t<CAP, 2, 4, 1024>(W, e, lde, S, M, pps, ntasks, nsplit, tasks, items, partial, nrep, s);
-    return project_t<CAP, 1, 4, 1024>(W, e, lde, S, M, pps, ntasks, nsplit, tasks, items, partial, nrep, s);
+    const auto same = [&](const ProjShape &q) { return q.P == p.P && q.waves == p.waves && q.task_max == p.task_max; };
+    if (same(kProjShapes[0])) return project_i<CAP, 0>(W, e, lde, S, M, pps, ntasks, nsplit, tasks, items, partial, nrep, s);
+    if (same(kProjShapes[1])) return project_i<CAP, 1>(W, e, lde, S, M, pps, ntasks, nsplit, tasks, items, partial, nrep, s);
+    return project_i<CAP, 2>(W, e, lde, S, M, pps, ntasks, nsplit, tasks, items, partial, nrep, s);
 }
 
 hipError_t launch_project(int cap, const Walk &W, const double2 *e, int64_t lde, const double *S, int64_t M,
