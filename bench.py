@@ -54,8 +54,10 @@ KERNEL_SOURCES = {
 }
 COUNTED_TRAFFIC = {
     # (workload, precision, M): read bytes, written bytes, sources counted on
-    ("d6-hcmax16-allen-cahn", "bf16", 1 << 20): (1604624755, 260884121,
-        "2b8b7b3c6a29f8a8defeb3c737e45fa1afe2e3f78949faf27f21c2faf9220c8d"),
+    ("d6-hcmax16-allen-cahn", "bf16", 1 << 20): (1604766688, 260522874,
+        "421db16bd2f4b9a7ce77163205370f4ba374ecddd38720fabf6a11b8318df413"),
+    ("d6-hcmax16-allen-cahn", "f64", 1 << 20): (2218054214, 991364864,
+        "1b42d51ca338c43b391bea514909a4a331a8be33ae415b3e263e47a1cc5d3f73"),
 }
 
 

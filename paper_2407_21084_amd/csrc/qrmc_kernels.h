@@ -6,7 +6,10 @@
 namespace qrmc {
 
 constexpr int kPathBlock = 128;   // threads per block of the path / eval kernels
-constexpr int kPathP = 2;         // paths per thread of the value-only path kernel
+#ifndef QRMC_PATH_P
+#define QRMC_PATH_P 2
+#endif
+constexpr int kPathP = QRMC_PATH_P;  // paths per thread of the value-only path kernel
 // Shape of the projection kernel for a basis of dimension d: paths per lane,
 // waves per block and the largest task (consecutive traversal nodes) a block
 // accumulates.  The widest shape whose LDS (the lanes' phase factors and the
