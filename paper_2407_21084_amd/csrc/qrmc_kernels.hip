@@ -142,8 +142,17 @@ __device__ __forceinline__ typename Sink::Acc visit(const Pts<P, R> &parent, con
                         Sink::add(acc, visit<T + 1, CAP, P>(v, l, W.c ? w : Pb, W, L, sink));
                     }
                 }
+                // two leaves per trip, so that the running value alternates
+                // between two registers instead of being copied back each node
+                const int stp = W.a ? 1 : Pb;
 #pragma unroll 1
-                for (; w <= W.L; w += W.a ? 1 : Pb) {
+                for (; w + stp <= W.L; w += 2 * stp) {
+                    const Pts<P, R> v2 = cmul(v, es);
+                    sink.node(v2, acc);
+                    v = cmul(v2, es);
+                    sink.node(v, acc);
+                }
+                if (w <= W.L) {
                     v = cmul(v, es);
                     sink.node(v, acc);
                 }

@@ -217,9 +217,13 @@ def test_batched_law_equals_unbatched(env, law):
         torch.cuda.synchronize()
         err = (a[r] - ref).abs().max().item()
         assert err <= TOL * ref.abs().max().item(), (f, err)
-    oref = O.solve(w.with_(f_a=fas[0]), O.reps_for(w))
+    w0 = w.with_(f_a=fas[0])
+    reps = O.reps_for(w)
+    oref = O.solve(w0, reps)
     got = host(a)[0]
-    assert np.abs(got - oref).max() <= 1e-9 * np.abs(oref).max()
+    for i in (w.N - 1, 0):
+        _, absum, _, _ = O.backward_step(w0, reps, i, w.M, w.seed, oref.copy())
+        assert_alpha(got[i], oref[i], absum, what=f"batched {law} row {i}")
 
 
 @pytest.mark.parametrize("law", LAWS)
