@@ -333,6 +333,17 @@ qr_status qr_solve_z(qr_ctx *ctx, const qr_problem *prob, const qr_basis *basis,
 qr_status qr_eval(qr_ctx *ctx, const qr_basis *basis, const double *alpha_row, int64_t n,
                   const double *x, double *y, double *grad, void *stream);
 
+/* qr_eval (values only) for point sets too small to fill the device one
+ * walk per thread, as the learned form's training pairs are: the basis is
+ * split across blocks (the projection's tasks), each block sums its tasks'
+ * terms for a slice of the points, and the blocks' sums are added in a fixed
+ * order.  Same values as qr_eval up to the order of the additions.
+ * 0 <= n <= 2^17 (QR_EINVAL otherwise); Fourier basis only (QR_ENOTSUP).
+ * Workspace: 16 d n bytes of phase factors and 8 n ceil(tasks / 8) bytes of
+ * group sums, held by the context. */
+qr_status qr_eval_split(qr_ctx *ctx, const qr_basis *basis, const double *alpha_row, int64_t n,
+                        const double *x, double *y, void *stream);
+
 /* The prediction y_i of the problem at n points from its row of
  * coefficients: qr_eval, times (1+|x|^2)^{q/2} for the problem's damping
  * exponent q (eq (yqi)), with the gradient by the product rule,

@@ -623,6 +623,8 @@ struct qr_ctx {
     Buf calpha, crow;
     // Z regression: the sums' first terms [M], responses [8][M], cloud sizes [8]
     Buf zf0, zresp, zm;
+    // evaluation split across blocks: phase factors [d][n], group sums [groups][n]
+    Buf ete, etp;
     int32_t prec_kernel = QR_PREC_KERNEL_AUTO;
     // surrogate network workspace: activations of up to kMlpChunk rows
     Buf mf, mz1, mh1, mz2, mh2, mdz, mdh, my, mdy, mpart, mwork, mcwork;
@@ -734,7 +736,7 @@ extern "C" void qr_ctx_destroy(qr_ctx *c) {
     hipSetDevice(c->dev);
     hipDeviceSynchronize();
     for (Buf *b : {&c->S, &c->u, &c->alpha_int, &c->partial, &c->row, &c->alpha_b, &c->tiles, &c->xstate, &c->fcoef,
-                   &c->fpartial, &c->calpha, &c->crow, &c->zf0, &c->zresp, &c->zm, &c->mf, &c->mz1, &c->mh1, &c->mz2, &c->mh2, &c->mdz, &c->mdh, &c->my, &c->mdy, &c->mpart, &c->mwork,
+                   &c->fpartial, &c->calpha, &c->crow, &c->zf0, &c->zresp, &c->zm, &c->ete, &c->etp, &c->mf, &c->mz1, &c->mh1, &c->mz2, &c->mh2, &c->mdz, &c->mdh, &c->my, &c->mdy, &c->mpart, &c->mwork,
                    &c->mcwork, &c->lx, &c->lh, &c->ly, &c->lparams, &c->lgrad, &c->lm, &c->lv, &c->ltx, &c->ltt,
                    &c->ltf, &c->lff, &c->lhx, &c->lht, &c->lhf, &c->lhy})
         if (b->p) hipFree(b->p);
@@ -1331,6 +1333,58 @@ extern "C" qr_status qr_eval(qr_ctx *c, const qr_basis *bc, const double *alpha_
     return QR_OK;
 }
 
+// Point sets up to this size are evaluated with the basis split across
+// blocks (eval_tasks_kernel); larger ones one walk per thread (eval_kernel),
+// which fills the chip from 2^17 points on.
+constexpr int64_t kEvalTasksMax = (int64_t)1 << 17;
+
+// ybar = row at n points x (SoA [d][n]) into y; value only.
+static qr_status eval_points(qr_ctx *c, const qr_basis *b, const double2 *row, const double *x, int64_t n,
+                             double *y, hipStream_t s) {
+    const int cap = depth_cap(b->max_nnz);
+    const Walk W = make_walk(b->kind, b->level, b->d, b->code());
+    if (n > kEvalTasksMax || eval_tasks_lds(b->d) > (size_t)160 * 1024 || b->tasks.empty())
+        return timed(c, 0, s, "eval_kernel", [&] { return launch_eval(cap, false, W, row, x, n, y, nullptr, s); });
+    const ProjShape sh = proj_shape(b->d);
+    const int64_t ntasks = (int64_t)b->tasks.size();
+    const int64_t groups = (ntasks + sh.waves - 1) / sh.waves;
+    const int64_t B = (int64_t)64 * sh.P;
+    const int64_t want = std::max<int64_t>(1, std::min<int64_t>((kProjBlocks + groups - 1) / groups, (n + B - 1) / B));
+    int64_t pps = (n + want - 1) / want;
+    pps = (pps + B - 1) / B * B;
+    const int32_t nsplit = (int32_t)((n + pps - 1) / pps);
+    qr_status st;
+    if ((st = ensure(c, c->ete, sizeof(double2) * (size_t)b->d * n, "phase factors"))) return st;
+    if ((st = ensure(c, c->etp, sizeof(double) * (size_t)groups * n, "group sums"))) return st;
+    double2 *e = (double2 *)c->ete.p;
+    QR_HIP(launch_x_to_e(b->code(), b->d, x, n, e, s), "x_to_e_kernel");
+    return timed(c, 0, s, "eval_tasks_kernel", [&] {
+        return launch_eval_tasks(cap, W, e, n, pps, (int32_t)ntasks, nsplit, b->d_tasks, b->d_items, b->task_max,
+                                 row, (double *)c->etp.p, y, s);
+    });
+}
+
+extern "C" qr_status qr_eval_split(qr_ctx *c, const qr_basis *bc, const double *alpha_row, int64_t n,
+                                   const double *x, double *y, void *stream) {
+    qr_basis *b = const_cast<qr_basis *>(bc);
+    qr_status st = begin(c, stream);
+    if (st) return st;
+    if ((st = check_basis_device(b))) return st;
+    if (n < 0 || n > kEvalTasksMax) return fail(QR_EINVAL, "qr_eval_split: n=%lld outside [0, %lld]", (long long)n,
+                                                (long long)kEvalTasksMax);
+    if (n == 0) return QR_OK;
+    if (!alpha_row || !x || !y) return fail(QR_EINVAL, "qr_eval_split: NULL argument");
+    if (b->cos) return fail(QR_ENOTSUP, "qr_eval_split: the cosine basis is not supported");
+    if (eval_tasks_lds(b->d) > (size_t)160 * 1024) return fail(QR_ENOTSUP, "qr_eval_split: d=%d", b->d);
+    if ((st = basis_on_device(b, c->dev))) return st;
+    if ((st = ensure(c, c->row, sizeof(double2) * (size_t)b->ld(), "row"))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    double2 *row = (double2 *)c->row.p;
+    QR_HIP(launch_pad(1, b->nrep, b->ld(), row, s), "pad_kernel");
+    QR_HIP(launch_gather(alpha_row, 0, 1, b->nrep, b->ld(), b->nfc(), b->d_canon_of_trav, row, s), "gather_kernel");
+    return eval_points(c, b, row, x, n, y, s);
+}
+
 extern "C" qr_status qr_eval_y(qr_ctx *c, const qr_problem *p, const qr_basis *bc, const double *alpha_row,
                                int64_t n, const double *x, double *y, double *grad, void *stream) {
     qr_status st = check_problem(p, bc);
@@ -1788,10 +1842,8 @@ static qr_status fit_pairs(qr_ctx *c, const qr_problem *p, const qr_basis *b, in
     // pairs (X, ybar_j(X)): training from stream 2, held-out from stream 3, at time index j
     QR_HIP(launch_sample(b->law, d, seed, 2u, j, 0, nt, tx, s), "sample_kernel");
     QR_HIP(launch_sample(b->law, d, seed, 3u, j, 0, nh, hx, s), "sample_kernel");
-    st = timed(c, 0, s, "eval_kernel", [&] { return launch_eval(cap, false, W, row, tx, nt, tt, nullptr, s); });
-    if (st) return st;
-    st = timed(c, 0, s, "eval_kernel", [&] { return launch_eval(cap, false, W, row, hx, nh, ht, nullptr, s); });
-    if (st) return st;
+    if ((st = eval_points(c, b, row, tx, nt, tt, s))) return st;
+    if ((st = eval_points(c, b, row, hx, nh, ht, s))) return st;
     // targets normalised by their mean and standard deviation
     QR_HIP(launch_moments(nt, tt, (double *)c->mpart.p, s), "moments_kernel");
     double mom[2];

@@ -110,6 +110,13 @@ hipError_t launch_set_flag(int32_t *flag, int32_t v, hipStream_t s);
 hipError_t launch_eval(int cap, bool grad, const Walk &W, const double2 *alpha_int_row,
                        const double *x, int64_t n, double *y, double *grad_out, hipStream_t s);
 hipError_t launch_x_to_e(int32_t nu, int32_t d, const double *x, int64_t n, double2 *e, hipStream_t s);
+// ybar at n points with the basis split across blocks (the projection's
+// tasks and shape): e = phase factors [d][n]; partial: ceil(ntasks / waves) x n
+// doubles of workspace; y[n] = sum of the groups in order
+size_t eval_tasks_lds(int32_t d);
+hipError_t launch_eval_tasks(int cap, const Walk &W, const double2 *e, int64_t n, int64_t pps, int32_t ntasks,
+                             int32_t nsplit, const Task *tasks, const TaskItem *items, int32_t task_max,
+                             const double2 *row, double *partial, double *y, hipStream_t s);
 hipError_t launch_sample(int32_t nu, int32_t d, uint64_t seed, uint32_t stream_id, int32_t i, int64_t m0,
                          int64_t n, double *x, hipStream_t s);
 

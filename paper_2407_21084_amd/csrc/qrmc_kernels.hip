@@ -783,6 +783,111 @@ __global__ __launch_bounds__(WAVES * 64) void project_kernel(
     for (int r = lane; r < task.rep_count * 2; r += 64) out[r] = acc[r];
 }
 
+// Evaluation with the basis split across blocks, for point sets too small
+// to fill the chip one walk per thread: block (group of WAVES tasks, slice of
+// points) as in project_kernel; wave w holds the coefficients of task
+// WAVES blockIdx.x + w in LDS and sums, per lane, a_r.x Re + a_r.y Im over the
+// task's nodes for its P points; per batch the waves' sums are added in wave
+// order and written to partial[group][m] (sum_groups_kernel adds the groups).
+template <int P>
+struct TaskEvalSink {
+    static constexpr bool kGrad = false;
+    static constexpr bool kSplit = true;
+    struct Acc {};
+    __device__ __forceinline__ static void add(Acc &, const Acc &) {}
+    const double2 *coef;  // the task's coefficient pairs in LDS, task-local traversal order
+    int n;                // task-local index of the next node (wave-uniform)
+    double y[P];
+    __device__ __forceinline__ void node(const Pts<P> &v, Acc &) {
+        const double2 a = coef[n++];
+#pragma unroll
+        for (int q = 0; q < P; ++q) y[q] = fma(a.x, v.re[q], fma(a.y, v.im[q], y[q]));
+    }
+};
+
+static size_t eval_tasks_lds_bytes(int32_t d, int P, int waves, int task_max) {
+    return (size_t)waves * task_max * sizeof(double2) + (size_t)d * P * 64 * sizeof(double2) +
+           (size_t)waves * P * 64 * sizeof(double);
+}
+
+template <int CAP, int P, int WAVES, int TM>
+__global__ __launch_bounds__(WAVES * 64) void eval_tasks_kernel(
+    const Walk W, const double2 *__restrict__ e_in, const int64_t n, const int64_t points_per_split,
+    const int32_t ntasks, const Task *__restrict__ tasks, const TaskItem *__restrict__ items,
+    const double2 *__restrict__ row, double *__restrict__ partial) {
+    constexpr int NT = WAVES * 64, B = 64 * P;
+    extern __shared__ double2 lds[];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int d = W.d;
+    double2 *cw = lds + wave * TM;                                     // [WAVES][TM]
+    double2 *Es = lds + WAVES * TM;                                    // [d][P][64]
+    double *Ys = reinterpret_cast<double *>(Es + d * B);               // [WAVES][P][64]
+    const LanePts<P> L{Es + lane, nullptr, 64};
+
+    const int32_t t = (int32_t)blockIdx.x * WAVES + wave;
+    const bool active = t < ntasks;  // wave-uniform
+    const Task task = active ? tasks[t] : Task{0, 0, 0, 0};
+    for (int r = lane; r < task.rep_count; r += 64) cw[r] = row[task.rep_begin + r];
+    const int64_t m0 = (int64_t)blockIdx.y * points_per_split;
+    const int64_t m1 = min(n, m0 + points_per_split);
+
+    TaskEvalSink<P> sink;
+    sink.coef = cw;
+    const int ne = d * B;
+    for (int64_t gb = m0; gb < m1; gb += B) {
+        __syncthreads();  // the previous batch's readers of Es and Ys are done
+        for (int j = tid; j < ne; j += NT) {
+            const int l = j / B, r = j - l * B;
+            const int64_t m = gb + r;
+            Es[j] = m < m1 ? e_in[l * n + m] : make_double2(1.0, 0.0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < P; ++q) sink.y[q] = 0.0;
+        if (active) {
+            sink.n = 0;
+            for (int it = task.item_begin; it < task.item_end; ++it) {
+                const TaskItem &I = items[it];
+                Pts<P> v = unit<P>();
+                for (int k = 0; k < I.depth; ++k) {
+                    Pts<P> e = L.e(I.coord[k]);
+                    int nn = I.val[k];
+                    if (nn < 0) {
+#pragma unroll
+                        for (int q = 0; q < P; ++q) e.im[q] = -e.im[q];
+                        nn = -nn;
+                    }
+                    for (int r = 0; r < nn; ++r) v = cmul(v, e);
+                }
+                typename TaskEvalSink<P>::Acc none;
+                sink.node(v, none);
+                if (I.full) visit_from<0, CAP, P>(I.depth, v, I.last, I.prod, W, L, sink);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < P; ++q) Ys[(wave * P + q) * 64 + lane] = sink.y[q];
+        __syncthreads();
+        for (int j = tid; j < B; j += NT) {
+            const int64_t m = gb + j;
+            if (m < m1) {
+                double acc = 0.0;
+#pragma unroll
+                for (int w = 0; w < WAVES; ++w) acc += Ys[w * B + j];
+                partial[(int64_t)blockIdx.x * n + m] = acc;
+            }
+        }
+    }
+}
+
+__global__ void sum_groups_kernel(const double *__restrict__ partial, int32_t ngroups, int64_t n,
+                                  double *__restrict__ y) {
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    double acc = 0.0;
+    for (int32_t g = 0; g < ngroups; ++g) acc += partial[(int64_t)g * n + m];
+    y[m] = acc;
+}
+
 // project_pass_kernel: the projection of a batched pass, R members on the pass's
 // cloud at once (one walk of the pass's set and one read of the phase factors
 // per point for all members): member r's response at path m is S[r M + m]
@@ -1814,6 +1919,56 @@ hipError_t launch_eval(int cap, bool grad, const Walk &W, const double2 *alpha_i
     }
 #undef QR_EVAL_CAP
     return hipErrorInvalidValue;
+}
+
+template <int CAP, int I>
+static hipError_t eval_tasks_i(const Walk &W, const double2 *e, int64_t n, int64_t pps, int32_t ntasks,
+                               int32_t nsplit, const Task *tasks, const TaskItem *items, const double2 *row,
+                               double *partial, hipStream_t s) {
+    constexpr ProjShape p = kProjShapes[I];
+    const size_t lds = eval_tasks_lds_bytes(W.d, p.P, p.waves, p.task_max);
+    static size_t granted = kLdsDefault;
+    const hipError_t err = allow_lds((const void *)eval_tasks_kernel<CAP, p.P, p.waves, p.task_max>, lds, granted);
+    if (err != hipSuccess) return err;
+    const unsigned groups = (unsigned)((ntasks + p.waves - 1) / p.waves);
+    hipLaunchKernelGGL((eval_tasks_kernel<CAP, p.P, p.waves, p.task_max>), dim3(groups, (unsigned)nsplit),
+                       dim3(p.waves * 64), lds, s, W, e, n, pps, ntasks, tasks, items, row, partial);
+    return hipGetLastError();
+}
+
+template <int CAP>
+static hipError_t eval_tasks_p(const Walk &W, const double2 *e, int64_t n, int64_t pps, int32_t ntasks,
+                               int32_t nsplit, const Task *tasks, const TaskItem *items, int32_t task_max,
+                               const double2 *row, double *partial, hipStream_t s) {
+    const ProjShape p = proj_shape(W.d);
+    if (task_max != p.task_max || eval_tasks_lds_bytes(W.d, p.P, p.waves, p.task_max) > kLdsMax)
+        return hipErrorInvalidValue;
+    const auto same = [&](const ProjShape &q) { return q.P == p.P && q.waves == p.waves && q.task_max == p.task_max; };
+    if (same(kProjShapes[0])) return eval_tasks_i<CAP, 0>(W, e, n, pps, ntasks, nsplit, tasks, items, row, partial, s);
+    if (same(kProjShapes[1])) return eval_tasks_i<CAP, 1>(W, e, n, pps, ntasks, nsplit, tasks, items, row, partial, s);
+    return eval_tasks_i<CAP, 2>(W, e, n, pps, ntasks, nsplit, tasks, items, row, partial, s);
+}
+
+size_t eval_tasks_lds(int32_t d) {
+    const ProjShape p = proj_shape(d);
+    return eval_tasks_lds_bytes(d, p.P, p.waves, p.task_max);
+}
+
+hipError_t launch_eval_tasks(int cap, const Walk &W, const double2 *e, int64_t n, int64_t pps, int32_t ntasks,
+                             int32_t nsplit, const Task *tasks, const TaskItem *items, int32_t task_max,
+                             const double2 *row, double *partial, double *y, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipError_t err = hipErrorInvalidValue;
+    switch (cap) {
+    case 2: err = eval_tasks_p<2>(W, e, n, pps, ntasks, nsplit, tasks, items, task_max, row, partial, s); break;
+    case 4: err = eval_tasks_p<4>(W, e, n, pps, ntasks, nsplit, tasks, items, task_max, row, partial, s); break;
+    case 6: err = eval_tasks_p<6>(W, e, n, pps, ntasks, nsplit, tasks, items, task_max, row, partial, s); break;
+    case 8: err = eval_tasks_p<8>(W, e, n, pps, ntasks, nsplit, tasks, items, task_max, row, partial, s); break;
+    }
+    if (err != hipSuccess) return err;
+    const int32_t groups = (ntasks + proj_shape(W.d).waves - 1) / proj_shape(W.d).waves;
+    hipLaunchKernelGGL(sum_groups_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, partial, groups, n, y);
+    return hipGetLastError();
 }
 
 hipError_t launch_x_to_e(int32_t nu, int32_t d, const double *x, int64_t n, double2 *e, hipStream_t s) {

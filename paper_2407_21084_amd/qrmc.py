@@ -54,7 +54,7 @@ EXPORTS = ["qr_last_error", "qr_version", "qr_build_basis", "qr_build_basis_law"
            "qr_ctx_numeric_status", "qr_build_basis_cos", "qr_basis_family_of", "qr_solve_from",
            "qr_ctx_set_mem_limit", "qr_ctx_mem_held", "qr_eval_y",
            "qr_batch_graph_create", "qr_batch_graph_launch", "qr_batch_graph_destroy",
-           "qr_backward_step_z", "qr_solve_z",
+           "qr_backward_step_z", "qr_solve_z", "qr_eval_split",
            "qr_host_uniform", "qr_host_norm_icdf", "qr_host_philox"]
 
 
@@ -133,6 +133,7 @@ _SIGS = {
     "qr_ctx_reset_timing": (C.c_int, [_P]),
     "qr_backward_step": (C.c_int, [_P, C.POINTER(Problem), _P, _I32, _I64, _U64, _P, _P]),
     "qr_solve": (C.c_int, [_P, C.POINTER(Problem), _P, _I64, _U64, _P, _P]),
+    "qr_eval_split": (C.c_int, [_P, _P, _P, _I64, _P, _P, _P]),
     "qr_backward_step_z": (C.c_int, [_P, C.POINTER(Problem), _P, _I32, _I64, _U64, _P, _P, _P]),
     "qr_solve_z": (C.c_int, [_P, C.POINTER(Problem), _P, _I64, _U64, _P, _P, _P]),
     "qr_eval": (C.c_int, [_P, _P, _P, _I64, _P, _P, _P, _P]),
@@ -384,6 +385,12 @@ class Context:
     def solve(self, prob: Problem, basis: Basis, M: int, seed: int, alpha, stream=None):
         _check(_lib.qr_solve(self._h, C.byref(prob), basis.handle, M, seed, _dptr(alpha),
                              _stream_ptr(stream)))
+
+    def eval_split(self, basis: Basis, alpha_row, x, y, stream=None):
+        """qr_eval (values) with the basis split across blocks, for n <= 2^17 points."""
+        n = y.shape[0]
+        _check(_lib.qr_eval_split(self._h, basis.handle, _dptr(alpha_row), n, _dptr(x), _dptr(y),
+                                  _stream_ptr(stream)))
 
     def backward_step_z(self, prob: Problem, basis: Basis, i: int, M: int, seed: int, alpha, alpha_z,
                         stream=None):

@@ -74,6 +74,43 @@ def test_eval(env, d, kind, level, n, grad):
     assert np.abs(host(y) - ry).max() <= TOL * np.abs(alpha).sum()
 
 
+@pytest.mark.parametrize("d,kind,level,n", [(2, "tensor", 4, 1), (2, "tensor", 4, 300), (6, "hc_max", 16, 5000),
+                                            (3, "hc_1p", 12, 257), (10, "hc_1p", 32, 700), (16, "hc_1p", 32, 600),
+                                            (1, "tensor", 0, 33)])
+def test_eval_split(env, d, kind, level, n):
+    """The evaluation with the basis split across blocks (small point sets):
+    the oracle's values, and qr_eval's up to rounding order, on sets of one
+    and of many tasks, ragged batches and a single point."""
+    Q, ctx, torch = env
+    say(f"eval_split d={d} {kind} {level} n={n}")
+    b = Q.Basis(d, kind, level)
+    alpha = W.synthetic_alpha(b.n_funcs, 1, seed=5)[0]
+    x = W.logistic_points(n, d, seed=2)
+    y = torch.empty(n, dtype=torch.float64, device="cuda")
+    ctx.eval_split(b, dev(torch, alpha), dev(torch, x.T), y)
+    y0 = torch.empty_like(y)
+    ctx.eval(b, dev(torch, alpha), dev(torch, x.T), y0)
+    torch.cuda.synchronize()
+    bound = TOL * np.abs(alpha).sum()
+    assert np.abs(host(y) - host(y0)).max() <= bound
+    if b.n_funcs <= 200_000 and n <= 700:
+        reps = O.enumerate_set(d, kind, level)
+        ry = O.evaluate(reps, alpha, x)
+        assert np.abs(host(y) - ry).max() <= bound
+
+
+def test_eval_split_arguments(env):
+    Q, ctx, torch = env
+    b = Q.Basis(2, "tensor", 4)
+    a = torch.zeros(b.n_funcs, dtype=torch.float64, device="cuda")
+    n = (1 << 17) + 1
+    x = torch.zeros((2, n), dtype=torch.float64, device="cuda")
+    y = torch.zeros(n, dtype=torch.float64, device="cuda")
+    with pytest.raises(Q.QrError) as e:
+        ctx.eval_split(b, a, x, y)
+    assert e.value.status == -1
+
+
 # ---------------------------------------------------------------------------
 # path responses and backward steps
 # ---------------------------------------------------------------------------
