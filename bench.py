@@ -308,6 +308,13 @@ def run_learned(args, torch, W, Q):
     torch.cuda.synchronize()
     t_learned = time.perf_counter() - t0
     print(f"[bench] learned solve {t_learned:.1f} s", file=sys.stderr, flush=True)
+    # the same without the screen: every time index runs the full fit
+    af = torch.zeros_like(a64)
+    t0 = time.perf_counter()
+    rep_full = ctx.solve_learned(prob, b, w.M, w.seed, af, stream=stream, reject=0.0)
+    torch.cuda.synchronize()
+    t_full = time.perf_counter() - t0
+    print(f"[bench] learned solve without the screen {t_full:.1f} s", file=sys.stderr, flush=True)
     # cost of one evaluation of ybar_j at 2^20 points: expansion vs network
     n = 1 << 20
     x = torch.empty((w.d, n), dtype=torch.float64, device=dev)
@@ -343,6 +350,11 @@ def run_learned(args, torch, W, Q):
         "epochs_run": [r["epochs_run"] for r in rep[1:]],
         "learned_equals_plain": bool(torch.equal(al, a64)),
         "overhead_vs_plain": t_learned / t_plain - 1.0,
+        "without_screen": {"learned_solve_s": t_full, "overhead_vs_plain": t_full / t_plain - 1.0,
+                           "surrogates_used": sum(r["used"] for r in rep_full),
+                           "equals_plain": bool(torch.equal(af, a64)),
+                           "heldout_rel_l2": {"min": min(r["heldout_rel_l2"] for r in rep_full[1:]),
+                                              "max": max(r["heldout_rel_l2"] for r in rep_full[1:])}},
         "heldout_rel_l2": {"min": min(r["heldout_rel_l2"] for r in rep[1:]),
                            "max": max(r["heldout_rel_l2"] for r in rep[1:])},
         "eval_2p20_points_ms": {"expansion": t_exp, "network": t_net, "ratio": t_exp / t_net},

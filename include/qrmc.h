@@ -505,11 +505,11 @@ typedef struct {
     int32_t batch;          /* pairs per Adam step, <= QR_MLP_MAX_BATCH */
     float lr;               /* Adam step size */
     double gate;            /* use the surrogate iff its held-out relative L2 error <= gate */
-    double reject;          /* > 0: screen each time index first (one epoch on the first
-                               sixteenth of the training and held-out pairs) and stop there,
-                               or after the first epoch of the full fit, when the held-out error
-                               exceeds reject (the network will not pass the gate); 0: always
-                               run the full fit */
+    double reject;          /* > 0: screen each time index first: the fit on the first
+                               1/32 of the training and held-out pairs, all epochs, ended as
+                               soon as its held-out error is <= reject; a screen still above
+                               reject after its last epoch ends the time index (no full fit,
+                               no surrogate); 0: always run the full fit */
 } qr_learn_opts;
 
 typedef struct {
@@ -519,7 +519,7 @@ typedef struct {
     int32_t used;           /* it replaced the expansion along the paths */
     double target_mean;     /* the surrogate predicts (ybar_j - target_mean) / target_sd */
     double target_sd;
-    int32_t epochs_run;     /* epochs run (fewer than requested after an early rejection) */
+    int32_t epochs_run;     /* epochs of the last fit run (the screen's after a rejection) */
 } qr_learn_report;
 
 /* qr_solve (the driver must not depend on z) where, after row j of alpha is

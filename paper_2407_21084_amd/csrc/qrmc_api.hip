@@ -1831,7 +1831,7 @@ extern "C" qr_status qr_mlp_adam(qr_ctx *c, float *params, const float *grad, fl
 // nh held-out pairs, `epochs` epochs of mini-batches of B.
 static qr_status fit_pairs(qr_ctx *c, const qr_problem *p, const qr_basis *b, int32_t j, uint64_t seed,
                            const qr_learn_opts *o, int64_t nt, int64_t nh, int64_t B, int epochs, float *th,
-                           double *mu, double *sigma, qr_learn_report *rep, hipStream_t s) {
+                           double *mu, double *sigma, qr_learn_report *rep, hipStream_t s, bool screen = false) {
     qr_status st;
     const int d = p->d;
     double *tx = (double *)c->ltx.p, *tt = (double *)c->ltt.p, *hx = (double *)c->lhx.p, *ht = (double *)c->lht.p;
@@ -1892,11 +1892,11 @@ static qr_status fit_pairs(qr_ctx *c, const qr_problem *p, const qr_basis *b, in
         }
         rep->epochs_run = e + 1;
         if (e + 1 == epochs) last = ep / (double)nb;
-        if (e == 0 && o->reject > 0.0 && epochs > 1) {
-            // early rejection: far from the gate after the first epoch
+        if (screen && e + 1 < epochs) {
+            // the screen stops as soon as it is within `reject`
             double err;
             if ((st = heldout(&err))) return st;
-            if (err > o->reject) {
+            if (err <= o->reject) {
                 rep->heldout_rel_l2 = err;
                 rep->train_loss = last;
                 return QR_OK;
@@ -1910,17 +1910,21 @@ static qr_status fit_pairs(qr_ctx *c, const qr_problem *p, const qr_basis *b, in
 }
 
 // Fit the surrogate of ybar_j for time index j.  With reject > 0 a screen
-// comes first: one epoch on the first sixteenth of the pairs (the expansion
-// evaluated at 1/16 of the points, which is most of a fit's cost); a network
-// that is then still above `reject` is not fitted further.
+// comes first: the fit on the first 1/kScreenShare of the training and
+// held-out pairs (the expansion evaluated at that share of the points, which
+// is most of a fit's cost), with every epoch, stopping once its held-out
+// error is within `reject`; a network still above `reject` after the last
+// epoch is not fitted further.  A passed screen is followed by the full fit.
+constexpr int64_t kScreenShare = 32;
+
 static qr_status fit_surrogate(qr_ctx *c, const qr_problem *p, const qr_basis *b, int32_t j, uint64_t seed,
                               const qr_learn_opts *o, float *th, double *mu, double *sigma,
                               qr_learn_report *rep, hipStream_t s) {
     if (o->reject > 0.0) {
-        const int64_t nt = o->train_points / 16, nh = std::max<int64_t>(1, o->heldout_points / 16);
+        const int64_t nt = o->train_points / kScreenShare, nh = std::max<int64_t>(1, o->heldout_points / kScreenShare);
         const int64_t B = std::min<int64_t>(o->batch, nt);
         if (B >= 64 && o->epochs >= 1) {
-            qr_status st = fit_pairs(c, p, b, j, seed, o, nt, nh, B, 1, th, mu, sigma, rep, s);
+            qr_status st = fit_pairs(c, p, b, j, seed, o, nt, nh, B, o->epochs, th, mu, sigma, rep, s, true);
             if (st) return st;
             if (rep->heldout_rel_l2 > o->reject) {
                 rep->used = 0;

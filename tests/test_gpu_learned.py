@@ -156,24 +156,48 @@ def test_learned_solve_with_closed_gate_is_the_plain_solve(env):
 
 def test_learned_early_rejection(env):
     """A cloud of 100 paths for 81 functions: each ybar_j is Monte-Carlo
-    noise, which no network fits.  With reject = 0.5 every fit stops after
-    its first epoch (held-out error above 0.5), none is used, and the result
-    is qr_solve's bit for bit; without it every epoch runs."""
+    noise, which no network fits.  With reject = 0.5 every screen (all four
+    epochs on 1/32 of the pairs) ends above 0.5 and no full fit runs, none is
+    used, and the result is qr_solve's bit for bit; without it the full fit
+    runs every epoch."""
     Q, ctx, torch = env
     w = W.D2_TENSOR4.with_(M=100)
     b = Q.Basis(w.d, w.set_kind, w.level)
     ref = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device="cuda")
     ctx.solve(Q.problem_from(w), b, w.M, w.seed, ref)
-    for reject, runs in ((0.5, 1), (0.0, 4)):
+    for reject in (0.5, 0.0):
         a = torch.zeros_like(ref)
-        rep = ctx.solve_learned(Q.problem_from(w), b, w.M, w.seed, a, train_points=1 << 12,
-                                heldout_points=1 << 10, epochs=4, batch=1024, reject=reject)
+        rep = ctx.solve_learned(Q.problem_from(w), b, w.M, w.seed, a, train_points=1 << 13,
+                                heldout_points=1 << 10, epochs=4, batch=256, reject=reject)
         torch.cuda.synchronize()
         say(f"  reject={reject}: " + _report(rep) + " epochs " + " ".join(str(r["epochs_run"]) for r in rep))
-        assert all(r["trained"] and not r["used"] and r["epochs_run"] == runs for r in rep[1:])
+        assert all(r["trained"] and not r["used"] and r["epochs_run"] == 4 for r in rep[1:])
         if reject:
             assert all(r["heldout_rel_l2"] > 0.5 for r in rep[1:])
         assert torch.equal(a, ref)
+
+
+def test_learned_screen_passes_a_learnable_target(env):
+    """A screen that ends within `reject` hands over to the full fit, which
+    is the same fit as without a screen: on the level-1 set of the next test
+    (expansions of degree 1) the screen's fit on 1/32 of the pairs ends at
+    a held-out error of about 0.8 (the full fit reaches 0.04 to 0.09), so
+    with reject = 0.95 every screen passes and the same time indices use
+    their surrogate as without a screen.  (With reject = 0.5 these screens
+    would turn the surrogates away: the screen trades recall for cost.)"""
+    Q, ctx, torch = env
+    w = W.D2_TENSOR4.with_(level=1)
+    b = Q.Basis(w.d, w.set_kind, w.level)
+    used = {}
+    for reject in (0.0, 0.95):
+        a = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device="cuda")
+        rep = ctx.solve_learned(Q.problem_from(w), b, w.M, w.seed, a, train_points=1 << 16,
+                                heldout_points=1 << 14, epochs=40, batch=1024, lr=2e-3, gate=5e-2, reject=reject)
+        torch.cuda.synchronize()
+        say(f"  reject={reject}: " + _report(rep))
+        used[reject] = [j for j, r in enumerate(rep) if r["used"]]
+    assert used[0.0], "no surrogate passed the gate"
+    assert used[0.95] == used[0.0]
 
 
 def test_learned_solve_uses_the_surrogate_where_it_passes(env):
