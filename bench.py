@@ -56,8 +56,8 @@ COUNTED_TRAFFIC = {
     # (workload, precision, M): read bytes, written bytes, sources counted on
     ("d6-hcmax16-allen-cahn", "bf16", 1 << 20): (1604766688, 260522874,
         "421db16bd2f4b9a7ce77163205370f4ba374ecddd38720fabf6a11b8318df413"),
-    ("d6-hcmax16-allen-cahn", "f64", 1 << 20): (2218054214, 991364864,
-        "1b42d51ca338c43b391bea514909a4a331a8be33ae415b3e263e47a1cc5d3f73"),
+    ("d6-hcmax16-allen-cahn", "f64", 1 << 20): (2383270253, 1080467846,
+        "4f8425ce6d0987a6e00923c6f4d447ea941cb9a8faf5f93ade82afc688bc342c"),
 }
 
 
