@@ -484,6 +484,29 @@ def run_batched(args, torch, W, Q):
             ctx.eval(b, a[r, 0].contiguous(), xt, yt, stream=stream)
             rels.append(float(torch.linalg.norm(yt - u0) / torch.linalg.norm(u0)))
     torch.cuda.synchronize()
+    # the same instances solved one by one with qr_solve (each on its own
+    # cloud and basis), on a sample of every 16th: time and error
+    sample = list(range(0, len(insts), 16))
+    t_plain = 0.0
+    rel_plain, rel_batched = [], []
+    for k in sample:
+        w = insts[k]
+        b = Q.Basis(w.d, w.set_kind, w.level)
+        a = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ctx.solve(Q.problem_from(w), b, w.M, w.seed, a, stream)
+        torch.cuda.synchronize()
+        t_plain += time.perf_counter() - t1
+        xt = torch.empty((w.d, n_test), dtype=torch.float64, device=dev)
+        ctx.sample_points(w.d, w.seed, 1, 0, n_test, xt, stream=stream)
+        u0 = math.exp(-1.0) * torch.cos(xt[0] + xt[1])
+        yt = torch.empty(n_test, dtype=torch.float64, device=dev)
+        ctx.eval(b, a[0].contiguous(), xt, yt, stream=stream)
+        torch.cuda.synchronize()
+        rel_plain.append(float(torch.linalg.norm(yt - u0) / torch.linalg.norm(u0)))
+        rel_batched.append(rels[k])
+    print(f"[bench] plain solves of {len(sample)} sampled instances {t_plain:.1f} s", file=sys.stderr, flush=True)
     line = {
         "metric": "basis-evals/s (batched form, 256 instances, FP64)",
         "value": evals * args.steps / elapsed,
@@ -496,6 +519,16 @@ def run_batched(args, torch, W, Q):
                    "evals_per_step": evals},
         "full_solve_s": elapsed / args.steps,
         "rel_l2_t0": {"median": float(np.median(rels)), "max": float(np.max(rels))},
+        "vs_plain_solves": {"sample": f"every 16th instance ({len(sample)} of {len(insts)}), each by qr_solve "
+                                      "on its own basis and cloud",
+                            "plain_s_sample": t_plain,
+                            "plain_s_extrapolated": t_plain * len(insts) / len(sample),
+                            "batched_s": elapsed / args.steps,
+                            "speedup_extrapolated": t_plain * len(insts) / len(sample) / (elapsed / args.steps),
+                            "rel_l2_t0_sample": {"plain_median": float(np.median(rel_plain)),
+                                                 "batched_median": float(np.median(rel_batched)),
+                                                 "plain_max": float(np.max(rel_plain)),
+                                                 "batched_max": float(np.max(rel_batched))}},
         "kernels_ms_per_solve": {"path": path_ms / args.steps, "project": proj_ms / args.steps,
                                  "reduce": red_ms / args.steps},
         "launches_per_step": {"path": path_n // max(1, args.steps), "project": proj_n // max(1, args.steps)},
