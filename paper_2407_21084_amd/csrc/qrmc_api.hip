@@ -1837,8 +1837,6 @@ static qr_status fit_pairs(qr_ctx *c, const qr_problem *p, const qr_basis *b, in
     double *tx = (double *)c->ltx.p, *tt = (double *)c->ltt.p, *hx = (double *)c->lhx.p, *ht = (double *)c->lht.p;
     float *tf = (float *)c->ltf.p, *ff = (float *)c->lff.p, *hf = (float *)c->lhf.p, *hy = (float *)c->lhy.p;
     const double2 *row = (const double2 *)c->alpha_int.p + (int64_t)j * b->ld();
-    const Walk W = make_walk(b->kind, b->level, b->d, b->code());
-    const int cap = depth_cap(b->max_nnz);
     // pairs (X, ybar_j(X)): training from stream 2, held-out from stream 3, at time index j
     QR_HIP(launch_sample(b->law, d, seed, 2u, j, 0, nt, tx, s), "sample_kernel");
     QR_HIP(launch_sample(b->law, d, seed, 3u, j, 0, nh, hx, s), "sample_kernel");
