@@ -612,6 +612,9 @@ struct Timed {
 };
 }  // namespace
 
+// streams of a batched solve (the caller's and three of the context's)
+constexpr int kBatchStreams = 4;
+
 struct qr_ctx {
     int dev = 0;
     hipStream_t last = nullptr;
@@ -625,6 +628,11 @@ struct qr_ctx {
     Buf zf0, zresp, zm;
     // evaluation split across blocks: phase factors [d][n], group sums [groups][n]
     Buf ete, etp;
+    // batched solve: side streams (default priority) with their own responses,
+    // phase factors and partial sums, so that independent passes overlap
+    hipStream_t bstream[kBatchStreams - 1] = {};
+    Buf bS[kBatchStreams - 1], bu[kBatchStreams - 1], bpart[kBatchStreams - 1];
+    hipEvent_t bfork = nullptr, bjoin[kBatchStreams - 1] = {};
     int32_t prec_kernel = QR_PREC_KERNEL_AUTO;
     // surrogate network workspace: activations of up to kMlpChunk rows
     Buf mf, mz1, mh1, mz2, mh2, mdz, mdh, my, mdy, mpart, mwork, mcwork;
@@ -740,6 +748,13 @@ extern "C" void qr_ctx_destroy(qr_ctx *c) {
                    &c->mcwork, &c->lx, &c->lh, &c->ly, &c->lparams, &c->lgrad, &c->lm, &c->lv, &c->ltx, &c->ltt,
                    &c->ltf, &c->lff, &c->lhx, &c->lht, &c->lhf, &c->lhy})
         if (b->p) hipFree(b->p);
+    for (int k = 0; k < kBatchStreams - 1; ++k) {
+        for (Buf *b : {&c->bS[k], &c->bu[k], &c->bpart[k]})
+            if (b->p) hipFree(b->p);
+        if (c->bstream[k]) hipStreamDestroy(c->bstream[k]);
+        if (c->bjoin[k]) hipEventDestroy(c->bjoin[k]);
+    }
+    if (c->bfork) hipEventDestroy(c->bfork);
     hipFree(c->d_prob);
     hipFree(c->d_bad);
     if (c->d_batch) hipFree(c->d_batch);
@@ -2204,19 +2219,32 @@ static qr_status plan_batched(qr_ctx *c, const qr_problem *p, qr_basis *b, int32
 
 // Every launch of a planned batched solve, in order, on stream s (kernels
 // only: it can be captured into a graph).
+// Passes are independent of each other (own members, coefficients and output
+// rows): pass ps runs on streams[ps % K] with that stream's buffers Bk[ps % K]
+// (responses, phase factors, partial sums); all of a pass's steps are on one
+// stream, in order.  streams[0] is the caller's stream; the others wait for
+// it after the clearing and it waits for them at the end (the caller records
+// the events).
 static qr_status enqueue_batched(qr_ctx *c, const qr_problem *p, const qr_basis *b, int32_t R,
-                                 const qr_instance *inst, const BatchPlan &pl, const BatchBufs &B, uint64_t seed,
-                                 double *alpha, hipStream_t s) {
+                                 const qr_instance *inst, const BatchPlan &pl, const BatchBufs *Bk,
+                                 const hipStream_t *streams, int K, uint64_t seed, double *alpha) {
     qr_status st;
     const int64_t nf = 2 * b->nrep - 1;
-    QR_HIP(launch_zero(alpha, (int64_t)R * p->N * nf, s), "zero_kernel");
-    QR_HIP(launch_zero((double *)B.ab, 2 * pl.total, s), "zero_kernel");
+    hipStream_t s0 = streams[0];
+    QR_HIP(launch_zero(alpha, (int64_t)R * p->N * nf, s0), "zero_kernel");
+    QR_HIP(launch_zero((double *)Bk[0].ab, 2 * pl.total, s0), "zero_kernel");
     const int db = dim_bucket(p->d, p->nbm);
-    if ((st = numeric_clear(c, s))) return st;
+    if ((st = numeric_clear(c, s0))) return st;
+    if (K > 1) {
+        QR_HIP(hipEventRecord(c->bfork, s0), "hipEventRecord");
+        for (int k = 1; k < K; ++k) QR_HIP(hipStreamWaitEvent(streams[k], c->bfork, 0), "hipStreamWaitEvent");
+    }
     const int npass = (int)pl.passes.size();
     for (int32_t i = p->N - 1; i >= 0; --i) {
         for (int ps = 0; ps < npass; ++ps) {
             const PassPlan &P = pl.passes[ps];
+            const BatchBufs &B = Bk[ps % K];
+            hipStream_t s = streams[ps % K];
             const int64_t ld = P.walk->ld();
             BatchArgs a{B.prob, p->d, B.batch, ps, make_walk(b->kind, P.level, P.d, b->law), i, P.M, seed,
                         B.ab + P.off, ld, B.S, B.u};
@@ -2260,6 +2288,12 @@ static qr_status enqueue_batched(qr_ctx *c, const qr_problem *p, const qr_basis 
             }
         }
     }
+    if (K > 1) {
+        for (int k = 1; k < K; ++k) {
+            QR_HIP(hipEventRecord(c->bjoin[k - 1], streams[k]), "hipEventRecord");
+            QR_HIP(hipStreamWaitEvent(s0, c->bjoin[k - 1], 0), "hipStreamWaitEvent");
+        }
+    }
     return QR_OK;
 }
 
@@ -2278,12 +2312,32 @@ extern "C" qr_status qr_solve_batched(qr_ctx *c, const qr_problem *p, const qr_b
     if ((st = ensure(c, c->alpha_b, sizeof(double2) * (size_t)pl.total, "batch coefficients"))) return st;
     if ((st = ensure(c, c->partial, sizeof(double2) * (size_t)pl.partial_max, "partial"))) return st;
     if (!c->d_batch) QR_HIP(hipMalloc(&c->d_batch, sizeof(DevBatch)), "hipMalloc(batch)");
-    // queued kernels may read the old instance parameters
+    // queued kernels may read the old instance parameters (on this stream or,
+    // from an earlier batched solve, on the context's side streams)
     QR_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    for (int k = 0; k < kBatchStreams - 1; ++k)
+        if (c->bstream[k]) QR_HIP(hipStreamSynchronize(c->bstream[k]), "hipStreamSynchronize");
     QR_HIP(hipMemcpy(c->d_batch, &pl.hb, sizeof pl.hb, hipMemcpyHostToDevice), "hipMemcpy(batch)");
-    const BatchBufs B{c->d_prob, c->d_batch, (double *)c->S.p, (double2 *)c->u.p, (double2 *)c->alpha_b.p,
+    // one stream per pass up to kBatchStreams, each with its own buffers
+    const int K = std::max(1, std::min<int>(kBatchStreams, (int)pl.passes.size()));
+    BatchBufs Bk[kBatchStreams];
+    hipStream_t ss[kBatchStreams] = {s};
+    Bk[0] = BatchBufs{c->d_prob, c->d_batch, (double *)c->S.p, (double2 *)c->u.p, (double2 *)c->alpha_b.p,
                       (double2 *)c->partial.p};
-    if ((st = enqueue_batched(c, p, b, R, inst, pl, B, seed, alpha, s))) return st;
+    for (int k = 1; k < K; ++k) {
+        if (!c->bstream[k - 1]) {
+            QR_HIP(hipStreamCreateWithFlags(&c->bstream[k - 1], hipStreamNonBlocking), "hipStreamCreate");
+            QR_HIP(hipEventCreateWithFlags(&c->bjoin[k - 1], hipEventDisableTiming), "hipEventCreate");
+        }
+        if ((st = ensure(c, c->bS[k - 1], sizeof(double) * (size_t)pl.Mmax * kBatchRT, "S"))) return st;
+        if ((st = ensure(c, c->bu[k - 1], sizeof(double2) * (size_t)pl.Mmax * p->d, "phase factors"))) return st;
+        if ((st = ensure(c, c->bpart[k - 1], sizeof(double2) * (size_t)pl.partial_max, "partial"))) return st;
+        ss[k] = c->bstream[k - 1];
+        Bk[k] = BatchBufs{c->d_prob, c->d_batch, (double *)c->bS[k - 1].p, (double2 *)c->bu[k - 1].p,
+                          (double2 *)c->alpha_b.p, (double2 *)c->bpart[k - 1].p};
+    }
+    if (K > 1 && !c->bfork) QR_HIP(hipEventCreateWithFlags(&c->bfork, hipEventDisableTiming), "hipEventCreate");
+    if ((st = enqueue_batched(c, p, b, R, inst, pl, Bk, ss, K, seed, alpha))) return st;
     return numeric_read(c, s, nullptr);
 }
 
@@ -2348,7 +2402,7 @@ extern "C" qr_status qr_batch_graph_create(qr_ctx *c, const qr_problem *p, const
                       (double2 *)gr->mem[3], (double2 *)gr->mem[4], (double2 *)gr->mem[5]};
     // one eager solve first (kernel attributes set, errors reported eagerly);
     // then the same launches captured
-    if ((st = enqueue_batched(c, p, b, R, inst, pl, B, seed, alpha, s))) {
+    if ((st = enqueue_batched(c, p, b, R, inst, pl, &B, &s, 1, seed, alpha))) {
         qr_batch_graph_destroy(gr);
         return st;
     }
@@ -2356,7 +2410,7 @@ extern "C" qr_status qr_batch_graph_create(qr_ctx *c, const qr_problem *p, const
     c->timing = false;
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        st = enqueue_batched(c, p, b, R, inst, pl, B, seed, alpha, s);
+        st = enqueue_batched(c, p, b, R, inst, pl, &B, &s, 1, seed, alpha);
         hipGraph_t g = nullptr;
         const hipError_t e2 = hipStreamEndCapture(s, &g);
         gr->graph = g;
