@@ -396,31 +396,34 @@ def run_z(args, torch, W, Q):
     a64 = torch.zeros((w.N, b.n_funcs), dtype=torch.float64, device=dev)
     t_plain = timed_solve(lambda: ctx.solve(prob, b, w.M, w.seed, a64, stream))
     print(f"[bench] plain solve {t_plain:.2f} s", file=sys.stderr, flush=True)
-    az = torch.zeros((w.N, w.nbm, b.n_funcs), dtype=torch.float64, device=dev)
-    ay = torch.zeros_like(a64)
-    ctx.set_timing(True)
-    ctx.reset_timing()
-    t_z = timed_solve(lambda: ctx.solve_z(prob, b, w.M, w.seed, ay, az, stream))
-    ktime = {name: ctx.kernel_time(k)[0] for k, name in enumerate(("path", "projection", "reduction"))}
-    ctx.set_timing(False)
-    print(f"[bench] solve with Z {t_z:.2f} s", file=sys.stderr, flush=True)
-    y = torch.empty(n_test, dtype=torch.float64, device=dev)
-    ctx.eval(b, ay[0].contiguous(), xt, y, stream=stream)
-    ez = torch.empty((w.nbm, n_test), dtype=torch.float64, device=dev)
-    for k in range(w.nbm):
-        ctx.eval(b, az[0, k].contiguous(), xt, ez[k], stream=stream)
-    torch.cuda.synchronize()
+    runs = {}
+    for scheme in ("multistep", "onestep"):
+        az = torch.zeros((w.N, w.nbm, b.n_funcs), dtype=torch.float64, device=dev)
+        ay = torch.zeros_like(a64)
+        ctx.set_timing(True)
+        ctx.reset_timing()
+        t_z = timed_solve(lambda: ctx.solve_z(prob, b, w.M, w.seed, ay, az, scheme=scheme, stream=stream))
+        ktime = {name: ctx.kernel_time(k)[0] for k, name in enumerate(("path", "projection", "reduction"))}
+        ctx.set_timing(False)
+        print(f"[bench] solve with Z ({scheme}) {t_z:.2f} s", file=sys.stderr, flush=True)
+        y = torch.empty(n_test, dtype=torch.float64, device=dev)
+        ctx.eval(b, ay[0].contiguous(), xt, y, stream=stream)
+        ez = torch.empty((w.nbm, n_test), dtype=torch.float64, device=dev)
+        for k in range(w.nbm):
+            ctx.eval(b, az[0, k].contiguous(), xt, ez[k], stream=stream)
+        torch.cuda.synchronize()
+        runs[scheme] = {"z_solve_s": t_z, "overhead_vs_plain": t_z / t_plain - 1.0, "kernel_ms": ktime,
+                        "y_equals_plain": bool(torch.equal(ay, a64)),
+                        "rel_l2_t0": {"y": float(torch.linalg.norm(y - u0) / torch.linalg.norm(u0)),
+                                      "z": float(torch.linalg.norm(ez - z0) / torch.linalg.norm(z0))}}
+    t_z = runs["multistep"]["z_solve_s"]
     line = {
-        "metric": "full-solve time with the Z regression vs plain FP64 (d=6)",
+        "metric": "full-solve time with the Z regression (multistep scheme) vs plain FP64 (d=6)",
         "value": t_z, "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
         "ms_per_step": t_z * 1e3, "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": ZREG, "d": w.d, "nbm": w.nbm, "N": w.N, "n_funcs": b.n_funcs, "M": w.M},
-        "plain_solve_s": t_plain, "z_solve_s": t_z, "overhead_vs_plain": t_z / t_plain - 1.0,
-        "kernel_ms": ktime,
-        "y_equals_plain": bool(torch.equal(ay, a64)),
-        "rel_l2_t0": {"y": float(torch.linalg.norm(y - u0) / torch.linalg.norm(u0)),
-                      "z": float(torch.linalg.norm(ez - z0) / torch.linalg.norm(z0))},
+        "plain_solve_s": t_plain, "schemes": runs,
     }
     print(json.dumps(line), flush=True)
     ctx.close()

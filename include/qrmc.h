@@ -304,26 +304,40 @@ qr_status qr_solve(qr_ctx *ctx, const qr_problem *prob, const qr_basis *basis, i
 qr_status qr_solve_from(qr_ctx *ctx, const qr_problem *prob, const qr_basis *basis, int32_t i_start,
                         int64_t M, uint64_t seed, int32_t precision, double *alpha, void *stream);
 
-/* The backward step with the gradient component: the multistep regression
- * of Z_i, eq (MDP:intro:0a), beside that of Y_i, eq (MDP:intro:0b).  Row i
- * of alpha is written exactly as qr_backward_step writes it, and for each
- * Brownian component k < nbm
+/* Schemes of the Z regression (Sec. 1). */
+typedef enum {
+    QR_Z_MULTISTEP = 0, /* eq (MDP:intro:0a): R_m = S_m without its term j = i */
+    QR_Z_ONESTEP = 1    /* eq (ODP:intro:a): R_m = T_L(ybar_{i+1}(X_{i+1})) - T_L(ybar_{i+1}(X_i)) */
+} qr_z_scheme;
+
+/* The backward step with the gradient component: the regression of Z_i
+ * beside that of Y_i, eq (MDP:intro:0b).  Row i of alpha is written exactly
+ * as qr_backward_step writes it, and for each Brownian component k < nbm
  *   alpha_z[i][k][.] = (1/M) sum_m R_m (W^k_{i+1} - W^k_i)_m / Delta_i phi_.(X_i^m),
- * where R_m is the response S_m of the step without its term j = i and the
- * increment is the one the path took on its first step (the normal r = d + k
- * of stream 0 at time index i, times sqrt(Delta_i)).  Z_i(x) is then
- * sum alpha_z[i][k][.] phi_.(x) (qr_eval on that row), an estimate of
- * sigma^T grad u(t_i, x) whose Monte-Carlo variance grows as 1/Delta_i.
+ * where the increment is the one the path took on its first step (the
+ * normal r = d + k of stream 0 at time index i, times sqrt(Delta_i)) and the
+ * response R_m is, by `scheme`:
+ *   QR_Z_MULTISTEP: S_m of the step without its term j = i, eq (MDP:intro:0a);
+ *     the Monte-Carlo variance carries the whole remaining path and grows as
+ *     1/Delta_i;
+ *   QR_Z_ONESTEP: the value the driver read on the path's first step,
+ *     T_L(ybar_{i+1}(X_{i+1})) (ybar_N = g), less T_L(ybar_{i+1}(X_i)), eq
+ *     (ODP:intro:a); the subtracted term is a function of X_i and leaves the
+ *     conditional expectation unchanged, and for a smooth ybar_{i+1} the
+ *     variance is of order one.  One more evaluation of ybar_{i+1} per path.
+ * Z_i(x) is then sum alpha_z[i][k][.] phi_.(x) (qr_eval on that row), an
+ * estimate of sigma^T grad u(t_i, x).
  * alpha_z: device [N][nbm][n_funcs] canonical order; slice i is written.
- * FP64, Fourier basis and q = 0 only (QR_ENOTSUP otherwise); other
- * arguments and errors as in qr_backward_step. */
+ * FP64, Fourier basis and q = 0 only (QR_ENOTSUP otherwise); an unknown
+ * scheme is QR_EINVAL; other arguments and errors as in qr_backward_step. */
 qr_status qr_backward_step_z(qr_ctx *ctx, const qr_problem *prob, const qr_basis *basis, int32_t i,
-                             int64_t M, uint64_t seed, double *alpha, double *alpha_z, void *stream);
+                             int64_t M, uint64_t seed, int32_t scheme, double *alpha, double *alpha_z,
+                             void *stream);
 
 /* qr_backward_step_z for i = N-1, ..., 0: alpha equals qr_solve's bit for
  * bit and every slice of alpha_z is written. */
 qr_status qr_solve_z(qr_ctx *ctx, const qr_problem *prob, const qr_basis *basis, int64_t M,
-                     uint64_t seed, double *alpha, double *alpha_z, void *stream);
+                     uint64_t seed, int32_t scheme, double *alpha, double *alpha_z, void *stream);
 
 /* Evaluate ybar = sum_k alpha_k phi_k at n points, phi_k = (Fourier
  * function) o F of the basis's sampling law (with a damping exponent q > 0

@@ -80,6 +80,7 @@ def lib():
             "or_solve": (C.c_int, [P, I64, P, I64, U64, P]),
             "or_backward_step_learned": (C.c_int, [P, I64, P, I32, I64, U64, P, P, P, P, P]),
             "or_backward_step_z": (C.c_int, [P, I64, P, I32, I64, U64, P, P, P]),
+            "or_backward_step_z1": (C.c_int, [P, I64, P, I32, I64, U64, P, P, P]),
             "or_mlp_forward": (D, [P, C.c_int, C.c_int, P]),
             "or_sample_points": (None, [C.c_int, C.c_int, U64, U32, I32, I64, I64, P]),
             "or_errors": (None, [P, I64, P, P, U64, I64, P]),
@@ -286,6 +287,21 @@ def backward_step_z(w, reps, i, M, seed, alpha):
                                   _ptr(ab))
     if rc:
         raise ValueError("or_backward_step_z failed")
+    return az, ab
+
+
+def backward_step_z1(w, reps, i, M, seed, alpha):
+    """Z of the one-step scheme, eq (ODP:intro:a), at time index i from the
+    rows i+1.. of alpha ([N][nf]): returns (alpha_z [nbm][nf], abs_z [nbm][nf])."""
+    p = problem(w)
+    reps = np.ascontiguousarray(reps, dtype=np.int32)
+    nf = nfuncs(reps, w.basis)
+    az = np.zeros((w.nbm, nf))
+    ab = np.zeros((w.nbm, nf))
+    rc = lib().or_backward_step_z1(C.byref(p), reps.shape[0], _ptr(reps), i, M, seed, _ptr(_f64(alpha)), _ptr(az),
+                                   _ptr(ab))
+    if rc:
+        raise ValueError("or_backward_step_z1 failed")
     return az, ab
 
 

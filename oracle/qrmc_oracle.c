@@ -26,6 +26,9 @@
  *   - soft truncation T_L: notation (vi) of Sec. 1
  *   - index sets Gamma_F / Gamma_H: Sec. 2.3.3 "Multi-indices sets"
  *   - error indicators MSE_max / MSE_av: Sec. 5, eq (mse)
+ *   - Z by Brownian-weight regression: Sec. 1, eqs (MDP:intro:0a) (multistep)
+ *     and (ODP:intro:a) (one step)
+ *   - state-dependent drift and diffusion: assumption (A_{b,sigma})
  *
  * Where the problem statement used here departs from the paper's own
  * experiments (sampling law, basis, index sets, driver, random generator),
@@ -619,19 +622,20 @@ double or_mlp_forward(const double *theta, int nu, int d, const double *x)
 static double or_path_response_ex(const or_problem *P, int64_t nrep, const int32_t *reps, int32_t i,
                                   uint64_t seed, uint64_t m, const double *alpha,
                                   const double *const *nets, const double *mu, const double *sd,
-                                  double *first);
+                                  double *first, double *y_first);
 
 double or_path_response(const or_problem *P, int64_t nrep, const int32_t *reps, int32_t i,
                         uint64_t seed, uint64_t m, const double *alpha)
 {
-    return or_path_response_ex(P, nrep, reps, i, seed, m, alpha, NULL, NULL, NULL, NULL);
+    return or_path_response_ex(P, nrep, reps, i, seed, m, alpha, NULL, NULL, NULL, NULL, NULL);
 }
 
-/* first (if not NULL) receives the term j = i of the driver sum, f(t_i, ...) Delta_i */
+/* first (if not NULL) receives the term j = i of the driver sum, f(t_i, ...) Delta_i;
+ * y_first the value the driver reads on that step, T_L(ybar_{i+1}(X_{i+1})) (g at i = N-1) */
 static double or_path_response_ex(const or_problem *P, int64_t nrep, const int32_t *reps, int32_t i,
                                   uint64_t seed, uint64_t m, const double *alpha,
                                   const double *const *nets, const double *mu, const double *sd,
-                                  double *first)
+                                  double *first, double *y_first)
 {
     int d = P->d, nbm = P->nbm, N = P->N;
     int64_t nf = or_nfuncs_of(P->basis, nrep);
@@ -661,6 +665,7 @@ static double or_path_response_ex(const or_problem *P, int64_t nrep, const int32
             if (need_z) or_msol_grad(P, or_T(P), xn, grad);
         }
         y = or_trunc(P, y);
+        if (j == i && y_first) *y_first = y;
         /* z_{j+1} = sigma(t_{j+1}, X_{j+1})^T grad ybar_{j+1}(X_{j+1}) */
         if (need_z) or_sigmaT(P, P->t[j + 1], xn, grad, z);
         double term = (or_fnl(P, P->t[j], x, y, z) + or_msol_h(P, P->t[j], x)) * dt;
@@ -763,7 +768,7 @@ int or_backward_step_z(const or_problem *P, int64_t nrep, const int32_t *reps, i
     for (int64_t m = 0; m < M; ++m) {
         double first = 0.0;
         or_start_point(P, seed, i, (uint64_t)m, x + m * d);
-        double S = or_path_response_ex(P, nrep, reps, i, seed, (uint64_t)m, alpha, NULL, NULL, NULL, &first);
+        double S = or_path_response_ex(P, nrep, reps, i, seed, (uint64_t)m, alpha, NULL, NULL, NULL, &first, NULL);
         SZ[m] = S - first;
     }
     for (int k = 0; k < nbm; ++k) {
@@ -776,6 +781,45 @@ int or_backward_step_z(const or_problem *P, int64_t nrep, const int32_t *reps, i
     }
     free(x);
     free(SZ);
+    free(r);
+    return 0;
+}
+
+/* Z of the one-step scheme, eq (ODP:intro:a), at time index i (q = 0): the
+ * response of path m is T_L(ybar_{i+1}(X_{i+1})) - T_L(ybar_{i+1}(X_i))
+ * (ybar_N = g), the value the driver reads on the path's first step less the
+ * same function at the start point; the second term is a function of X_i,
+ * so it leaves the conditional expectation against dW unchanged and removes
+ * most of the variance.  alpha_z as in or_backward_step_z. */
+int or_backward_step_z1(const or_problem *P, int64_t nrep, const int32_t *reps, int32_t i,
+                        int64_t M, uint64_t seed, const double *alpha, double *alpha_z, double *absum_z)
+{
+    if (i < 0 || i >= P->N || M <= 0 || P->damping_q != 0.0) return -1;
+    int d = P->d, nbm = P->nbm;
+    int64_t nf = or_nfuncs_of(P->basis, nrep);
+    double dt = P->t[i + 1] - P->t[i];
+    double *x = (double *)malloc(sizeof(double) * (size_t)(M * d));
+    double *D = (double *)malloc(sizeof(double) * (size_t)M);
+    double *r = (double *)malloc(sizeof(double) * (size_t)M);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t m = 0; m < M; ++m) {
+        double first = 0.0, y1 = 0.0;
+        or_start_point(P, seed, i, (uint64_t)m, x + m * d);
+        (void)or_path_response_ex(P, nrep, reps, i, seed, (uint64_t)m, alpha, NULL, NULL, NULL, &first, &y1);
+        double y0 = (i + 1 < P->N) ? or_eval_y(P, nrep, reps, alpha + (int64_t)(i + 1) * nf, x + m * d, NULL)
+                                   : or_g(P, x + m * d);
+        D[m] = y1 - or_trunc(P, y0);
+    }
+    for (int k = 0; k < nbm; ++k) {
+        for (int64_t m = 0; m < M; ++m) {
+            double dw = sqrt(dt) * or_norm_icdf(or_uniform(seed, 0u, (uint64_t)m, (uint32_t)i, (uint32_t)(d + k)));
+            r[m] = D[m] * dw / dt;
+        }
+        or_project(d, P->nu, P->basis, nrep, reps, M, x, r, alpha_z + (int64_t)k * nf,
+                   absum_z ? absum_z + (int64_t)k * nf : NULL);
+    }
+    free(x);
+    free(D);
     free(r);
     return 0;
 }
@@ -796,7 +840,7 @@ int or_backward_step_learned(const or_problem *P, int64_t nrep, const int32_t *r
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t m = 0; m < M; ++m) {
         or_start_point(P, seed, i, (uint64_t)m, x + m * d);
-        S[m] = or_path_response_ex(P, nrep, reps, i, seed, (uint64_t)m, alpha, nets, mu, sd, NULL);
+        S[m] = or_path_response_ex(P, nrep, reps, i, seed, (uint64_t)m, alpha, nets, mu, sd, NULL, NULL);
     }
     or_project(d, P->nu, P->basis, nrep, reps, M, x, S, alpha + (int64_t)i * nf, absum);
     free(x);

@@ -625,7 +625,7 @@ struct qr_ctx {
     // cosine basis: the carrier table [N][2R-1] and one carrier row
     Buf calpha, crow;
     // Z regression: the sums' first terms [M], responses [8][M], cloud sizes [8]
-    Buf zf0, zresp, zm;
+    Buf zf0, zresp, zm, zx0, zy0;
     // evaluation split across blocks: phase factors [d][n], group sums [groups][n]
     Buf ete, etp;
     // batched solve: side streams (default priority) with their own responses,
@@ -744,7 +744,7 @@ extern "C" void qr_ctx_destroy(qr_ctx *c) {
     hipSetDevice(c->dev);
     hipDeviceSynchronize();
     for (Buf *b : {&c->S, &c->u, &c->alpha_int, &c->partial, &c->row, &c->alpha_b, &c->tiles, &c->xstate, &c->fcoef,
-                   &c->fpartial, &c->calpha, &c->crow, &c->zf0, &c->zresp, &c->zm, &c->ete, &c->etp, &c->mf, &c->mz1, &c->mh1, &c->mz2, &c->mh2, &c->mdz, &c->mdh, &c->my, &c->mdy, &c->mpart, &c->mwork,
+                   &c->fpartial, &c->calpha, &c->crow, &c->zf0, &c->zresp, &c->zm, &c->zx0, &c->zy0, &c->ete, &c->etp, &c->mf, &c->mz1, &c->mh1, &c->mz2, &c->mh2, &c->mdz, &c->mdh, &c->my, &c->mdy, &c->mpart, &c->mwork,
                    &c->mcwork, &c->lx, &c->lh, &c->ly, &c->lparams, &c->lgrad, &c->lm, &c->lv, &c->ltx, &c->ltt,
                    &c->ltf, &c->lff, &c->lhx, &c->lht, &c->lhf, &c->lhy})
         if (b->p) hipFree(b->p);
@@ -1182,11 +1182,12 @@ namespace {
 void pass_split_plan(const qr_basis *w, int64_t M, int32_t *nsplit, int64_t *pps);
 }  // namespace
 
-// Z rows of time index i (eq (MDP:intro:0a)) from the step just run: its
-// responses S and first terms f0 in the context, the start points' phase
-// factors u; nbm projections, kBatchRT at a time on the basis's pass tasks.
+// Z rows of time index i from the step just run: its responses S, first
+// terms and first-step values f0 in the context, the start points' phase
+// factors u (and, for the one-step scheme, the start points X_i in zx0);
+// nbm projections, kBatchRT at a time on the basis's pass tasks.
 static qr_status project_z(qr_ctx *c, const qr_problem *p, qr_basis *b, int32_t i, int64_t M, uint64_t seed,
-                           double *alpha_z, hipStream_t s) {
+                           int32_t scheme, double *alpha_z, hipStream_t s) {
     qr_status st;
     if ((st = basis_pass_tasks_on_device(b))) return st;
     int32_t nsplit;
@@ -1199,10 +1200,27 @@ static qr_status project_z(qr_ctx *c, const qr_problem *p, qr_basis *b, int32_t 
     const int64_t nf = b->nfc();
     double *zr = (double *)c->zresp.p;
     double2 *partial = (double2 *)c->partial.p;
+    const double *y0 = nullptr;
+    if (scheme == QR_Z_ONESTEP) {
+        // ybar_{i+1} (g for i = N-1) at the start points
+        double *zy0 = (double *)c->zy0.p;
+        const double *x0 = (const double *)c->zx0.p;
+        if (i + 1 < p->N) {
+            const double2 *row = (const double2 *)c->alpha_int.p + (int64_t)(i + 1) * b->ld();
+            st = timed(c, 0, s, "eval_kernel", [&] {
+                return launch_eval(depth_cap(b->max_nnz), false, make_walk(b->kind, b->level, b->d, b->code()), row,
+                                   x0, M, zy0, nullptr, s);
+            });
+            if (st) return st;
+        } else {
+            QR_HIP(launch_g_points(dim_bucket(p->d, p->nbm), c->d_prob, x0, M, zy0, s), "g_points_kernel");
+        }
+        y0 = zy0;
+    }
     for (int32_t k0 = 0; k0 < p->nbm; k0 += kBatchRT) {
         const int32_t nk = std::min<int32_t>(kBatchRT, p->nbm - k0);
-        QR_HIP(launch_z_responses(c->d_prob, seed, i, M, k0, nk, (const double *)c->S.p, (const double *)c->zf0.p, zr,
-                                  s),
+        QR_HIP(launch_z_responses(c->d_prob, seed, i, M, k0, nk, (const double *)c->S.p, (const double *)c->zf0.p, y0,
+                                  zr, s),
                "z_responses_kernel");
         st = timed(c, 1, s, "project_pass_kernel", [&] {
             return launch_project_pass(depth_cap(b->max_nnz), make_walk(b->kind, b->level, b->d, b->code()),
@@ -1222,23 +1240,31 @@ static qr_status project_z(qr_ctx *c, const qr_problem *p, qr_basis *b, int32_t 
     return QR_OK;
 }
 
-static qr_status check_z(const qr_problem *p, const qr_basis *b, const double *alpha_z) {
+static qr_status check_z(qr_ctx *c, const qr_problem *p, const qr_basis *b, int64_t M, int32_t scheme,
+                         const double *alpha_z) {
     if (!alpha_z) return fail(QR_EINVAL, "Z regression: alpha_z is NULL");
+    if (scheme != QR_Z_MULTISTEP && scheme != QR_Z_ONESTEP) return fail(QR_EINVAL, "Z regression: scheme %d", scheme);
     if (p->damping_q != 0.0) return fail(QR_ENOTSUP, "Z regression: damping exponent q must be 0");
     if (b->cos) return fail(QR_ENOTSUP, "Z regression: the cosine basis is not supported");
     if (project_pass_lds_bytes(p->d) > (size_t)160 * 1024) return fail(QR_ENOTSUP, "Z regression: d=%d", p->d);
+    qr_status st;
+    if ((st = ensure(c, c->zf0, sizeof(double) * 2 * (size_t)M, "first terms"))) return st;
+    if (scheme == QR_Z_ONESTEP) {
+        if ((st = ensure(c, c->zx0, sizeof(double) * (size_t)p->d * M, "start points"))) return st;
+        if ((st = ensure(c, c->zy0, sizeof(double) * (size_t)M, "start-point values"))) return st;
+    }
     return QR_OK;
 }
 
 extern "C" qr_status qr_backward_step_z(qr_ctx *c, const qr_problem *p, const qr_basis *bc, int32_t i, int64_t M,
-                                        uint64_t seed, double *alpha, double *alpha_z, void *stream) {
+                                        uint64_t seed, int32_t scheme, double *alpha, double *alpha_z,
+                                        void *stream) {
     qr_basis *b = const_cast<qr_basis *>(bc);
     qr_status st = prepare(c, p, b, M, stream);
     if (st) return st;
     if (!alpha) return fail(QR_EINVAL, "qr_backward_step_z: alpha is NULL");
-    if ((st = check_z(p, b, alpha_z))) return st;
     if (i < 0 || i >= p->N) return fail(QR_EINVAL, "qr_backward_step_z: i=%d outside [0,%d)", i, p->N);
-    if ((st = ensure(c, c->zf0, sizeof(double) * (size_t)M, "first terms"))) return st;
+    if ((st = check_z(c, p, b, M, scheme, alpha_z))) return st;
     hipStream_t s = (hipStream_t)stream;
     double2 *ai = (double2 *)c->alpha_int.p;
     const int64_t nf = b->nfc();
@@ -1248,30 +1274,31 @@ extern "C" qr_status qr_backward_step_z(qr_ctx *c, const qr_problem *p, const qr
     if (st) return st;
     double *S = (double *)c->S.p;
     double2 *u = (double2 *)c->u.p;
-    if ((st = run_path(c, p, b, i, M, seed, ai, S, u, nullptr, s, (double *)c->zf0.p))) return st;
+    double *x0 = scheme == QR_Z_ONESTEP ? (double *)c->zx0.p : nullptr;
+    if ((st = run_path(c, p, b, i, M, seed, ai, S, u, x0, s, (double *)c->zf0.p))) return st;
     if ((st = project_and_reduce(c, b, u, S, M, ai + (int64_t)i * b->ld(), alpha + (int64_t)i * nf, i, s))) return st;
-    return project_z(c, p, b, i, M, seed, alpha_z, s);
+    return project_z(c, p, b, i, M, seed, scheme, alpha_z, s);
 }
 
 extern "C" qr_status qr_solve_z(qr_ctx *c, const qr_problem *p, const qr_basis *bc, int64_t M, uint64_t seed,
-                                double *alpha, double *alpha_z, void *stream) {
+                                int32_t scheme, double *alpha, double *alpha_z, void *stream) {
     qr_basis *b = const_cast<qr_basis *>(bc);
     qr_status st = prepare(c, p, b, M, stream);
     if (st) return st;
     if (!alpha) return fail(QR_EINVAL, "qr_solve_z: alpha is NULL");
-    if ((st = check_z(p, b, alpha_z))) return st;
-    if ((st = ensure(c, c->zf0, sizeof(double) * (size_t)M, "first terms"))) return st;
+    if ((st = check_z(c, p, b, M, scheme, alpha_z))) return st;
     hipStream_t s = (hipStream_t)stream;
     double2 *ai = (double2 *)c->alpha_int.p;
     const int64_t nf = b->nfc();
     double *S = (double *)c->S.p;
     double2 *u = (double2 *)c->u.p;
+    double *x0 = scheme == QR_Z_ONESTEP ? (double *)c->zx0.p : nullptr;
     if ((st = numeric_clear(c, s))) return st;
     for (int32_t i = p->N - 1; i >= 0; --i) {
-        if ((st = run_path(c, p, b, i, M, seed, ai, S, u, nullptr, s, (double *)c->zf0.p))) return st;
+        if ((st = run_path(c, p, b, i, M, seed, ai, S, u, x0, s, (double *)c->zf0.p))) return st;
         if ((st = project_and_reduce(c, b, u, S, M, ai + (int64_t)i * b->ld(), alpha + (int64_t)i * nf, i, s)))
             return st;
-        if ((st = project_z(c, p, b, i, M, seed, alpha_z, s))) return st;
+        if ((st = project_z(c, p, b, i, M, seed, scheme, alpha_z, s))) return st;
     }
     return numeric_read(c, s, nullptr);
 }

@@ -79,7 +79,8 @@ struct PathArgs {
     double *x0;
     double *xs;   // path state [d][ldx], ldx >= path_state_ld(M, grad)
     int64_t ldx;
-    double *f0 = nullptr;  // [M] the driver sum's first term f(t_i, ...) Delta_i, or NULL
+    double *f0 = nullptr;  // [2][M]: the driver sum's first term f(t_i, ...) Delta_i and the
+                           // value the driver read on that step, or NULL
 };
 
 hipError_t launch_gather(const double *alpha, int32_t row0, int32_t nrows, int64_t nrep, int64_t ld,
@@ -140,8 +141,13 @@ hipError_t launch_fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s);
 
 // Z of the multistep scheme: responses out[r][m] = (S[m] - f0[m]) dW_{i,k0+r}(m) / Delta_i
 // for r < nk (0 for nk <= r < kBatchRT), dW the first increment of path m's stream
+// Z responses out[r][M] for the Brownian components k0 + r, r < nk: the
+// multistep response (y0 NULL) or the one-step one (y0 = ybar_{i+1} at X_i);
+// f0 [2][M] from the path kernel (first term, value read on the first step)
 hipError_t launch_z_responses(const DevProblem *P, uint64_t seed, int32_t i, int64_t M, int32_t k0, int32_t nk,
-                              const double *S, const double *f0, double *out, hipStream_t s);
+                              const double *S, const double *f0, const double *y0, double *out, hipStream_t s);
+// g at n points x [d][n]
+hipError_t launch_g_points(int db, const DevProblem *P, const double *x, int64_t n, double *y, hipStream_t s);
 // canonical row of response slot `slot` of a pass-projection partial [nsplit][nrep][R]
 hipError_t launch_reduce_slot(const double2 *partial, int32_t nsplit, int64_t nrep, int32_t R, int32_t slot,
                               double M, const int32_t *canon_of_trav, double *alpha_row, int32_t *bad, int32_t step,

@@ -530,9 +530,13 @@ void path_kernel(
             const double f = fnl(Pj, yq, z2[q], uc) + hj[q];
             S[q] = fma(f, dt, S[q]);
             if (f0_out && j == i) {
-                // the first term, for the Z regression (its responses leave it out)
+                // for the Z regression: the first term (the multistep responses
+                // leave it out) and the value the driver read on that step
                 const int64_t m = base + (int64_t)q * kPathBlock;
-                if (m < M) f0_out[m] = S[q];
+                if (m < M) {
+                    f0_out[m] = S[q];
+                    f0_out[M + m] = yq;
+                }
             }
         }
     }
@@ -1627,11 +1631,13 @@ __global__ void reduce_batched_kernel(const double2 *__restrict__ partial, int32
 // first Brownian increment over Delta_i (the normals r = d + k of the stream)
 __global__ void z_responses_kernel(const DevProblem *__restrict__ P, uint64_t seed, int32_t i, int64_t M, int32_t k0,
                                    int32_t nk, const double *__restrict__ S, const double *__restrict__ f0,
-                                   double *__restrict__ out) {
+                                   const double *__restrict__ y0, double *__restrict__ out) {
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= M) return;
     const double dt = P->t[i + 1] - P->t[i];
-    const double sz = (S[m] - f0[m]) / dt;
+    // multistep (y0 NULL): the sum without its first term; one step: the value
+    // the driver read on the first step less T_L(ybar_{i+1}(X_i))
+    const double sz = (y0 ? f0[M + m] - clamp_abs(y0[m], P->clamp) : S[m] - f0[m]) / dt;
     const double sq = sqrt(dt);
     for (int r = 0; r < kBatchRT; ++r) {
         double v = 0.0;
@@ -2073,9 +2079,32 @@ hipError_t launch_project_pass(int cap, const Walk &W, const double2 *e, int64_t
 }
 
 hipError_t launch_z_responses(const DevProblem *P, uint64_t seed, int32_t i, int64_t M, int32_t k0, int32_t nk,
-                              const double *S, const double *f0, double *out, hipStream_t s) {
+                              const double *S, const double *f0, const double *y0, double *out, hipStream_t s) {
     hipLaunchKernelGGL(z_responses_kernel, dim3(blocks_for(M, 256)), dim3(256), 0, s, P, seed, i, M, k0, nk, S, f0,
-                       out);
+                       y0, out);
+    return hipGetLastError();
+}
+
+template <int DB>
+__global__ void g_points_kernel(const DevProblem *__restrict__ P, const double *__restrict__ x, int64_t n,
+                                double *__restrict__ y) {
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    const int d = P->d;
+    double xv[DB];
+#pragma unroll
+    for (int l = 0; l < DB; ++l) xv[l] = l < d ? x[l * n + m] : 0.0;
+    y[m] = g_term<DB>(P, xv, d, nullptr);
+}
+
+hipError_t launch_g_points(int db, const DevProblem *P, const double *x, int64_t n, double *y, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    switch (db) {
+    case 4: hipLaunchKernelGGL(g_points_kernel<4>, dim3(blocks_for(n, 256)), dim3(256), 0, s, P, x, n, y); break;
+    case 8: hipLaunchKernelGGL(g_points_kernel<8>, dim3(blocks_for(n, 256)), dim3(256), 0, s, P, x, n, y); break;
+    case 16: hipLaunchKernelGGL(g_points_kernel<16>, dim3(blocks_for(n, 256)), dim3(256), 0, s, P, x, n, y); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

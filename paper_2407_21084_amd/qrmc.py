@@ -58,6 +58,9 @@ EXPORTS = ["qr_last_error", "qr_version", "qr_build_basis", "qr_build_basis_law"
            "qr_host_uniform", "qr_host_norm_icdf", "qr_host_philox"]
 
 
+Z_SCHEMES = {"multistep": 0, "onestep": 1}
+
+
 class QrError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
@@ -134,8 +137,8 @@ _SIGS = {
     "qr_backward_step": (C.c_int, [_P, C.POINTER(Problem), _P, _I32, _I64, _U64, _P, _P]),
     "qr_solve": (C.c_int, [_P, C.POINTER(Problem), _P, _I64, _U64, _P, _P]),
     "qr_eval_split": (C.c_int, [_P, _P, _P, _I64, _P, _P, _P]),
-    "qr_backward_step_z": (C.c_int, [_P, C.POINTER(Problem), _P, _I32, _I64, _U64, _P, _P, _P]),
-    "qr_solve_z": (C.c_int, [_P, C.POINTER(Problem), _P, _I64, _U64, _P, _P, _P]),
+    "qr_backward_step_z": (C.c_int, [_P, C.POINTER(Problem), _P, _I32, _I64, _U64, _I32, _P, _P, _P]),
+    "qr_solve_z": (C.c_int, [_P, C.POINTER(Problem), _P, _I64, _U64, _I32, _P, _P, _P]),
     "qr_eval": (C.c_int, [_P, _P, _P, _I64, _P, _P, _P, _P]),
     "qr_basis_upload": (C.c_int, [_P, _P]),
     "qr_ctx_set_prec_kernel": (C.c_int, [_P, _I32]),
@@ -393,14 +396,16 @@ class Context:
                                   _stream_ptr(stream)))
 
     def backward_step_z(self, prob: Problem, basis: Basis, i: int, M: int, seed: int, alpha, alpha_z,
-                        stream=None):
-        """Row i of alpha and slice i of alpha_z ([N][nbm][n_funcs]), the Z regression of eq (MDP:intro:0a)."""
-        _check(_lib.qr_backward_step_z(self._h, C.byref(prob), basis.handle, i, M, seed, _dptr(alpha),
-                                       _dptr(alpha_z), _stream_ptr(stream)))
+                        scheme="multistep", stream=None):
+        """Row i of alpha and slice i of alpha_z ([N][nbm][n_funcs]): the Z regression of
+        eq (MDP:intro:0a) (scheme "multistep") or eq (ODP:intro:a) ("onestep")."""
+        _check(_lib.qr_backward_step_z(self._h, C.byref(prob), basis.handle, i, M, seed, Z_SCHEMES.get(scheme, scheme),
+                                       _dptr(alpha), _dptr(alpha_z), _stream_ptr(stream)))
 
-    def solve_z(self, prob: Problem, basis: Basis, M: int, seed: int, alpha, alpha_z, stream=None):
-        _check(_lib.qr_solve_z(self._h, C.byref(prob), basis.handle, M, seed, _dptr(alpha), _dptr(alpha_z),
-                               _stream_ptr(stream)))
+    def solve_z(self, prob: Problem, basis: Basis, M: int, seed: int, alpha, alpha_z, scheme="multistep",
+                stream=None):
+        _check(_lib.qr_solve_z(self._h, C.byref(prob), basis.handle, M, seed, Z_SCHEMES.get(scheme, scheme),
+                               _dptr(alpha), _dptr(alpha_z), _stream_ptr(stream)))
 
     def backward_step_prec(self, prob: Problem, basis: Basis, i: int, M: int, seed: int, precision,
                            alpha, stream=None):

@@ -1006,3 +1006,57 @@ def test_z_regression_one_step_stein_identity():
     # planted mistakes: the increment over sqrt(Delta), or the wrong sign
     assert np.any(np.abs(az[0] * math.sqrt(Dl) - exp) > 5 * sd)
     assert np.any(np.abs(-az[0] - exp) > 5 * sd)
+
+
+def test_z_regression_one_step_scheme_stein_identity():
+    """Z of the one-step scheme, eq (ODP:intro:a), on the problem of the
+    previous test (N = 1, so ybar_1 = g): the response is
+    (g(X_1) - g(X_0)) dW / Delta, whose expectation is the multistep one (g(X_0)
+    is a function of X_0 and dW has mean zero), so every coefficient lies
+    within 5 sample standard deviations of the closed form of the previous
+    test; the sample spread is far below the multistep estimator's, and the
+    estimate with the opposite sign or over sqrt(Delta) fails the band."""
+    s_, Dl = 0.8, 0.25
+    w = W.Workload(name="z1b", d=1, N=1, T=Dl, sigma=[[s_]], b0=[0.0], b1=[0.0], set_kind="tensor", level=4,
+                   M=200_000, driver="linear", f_a=0.0, sol_A=1.0, sol_c=1.0, sol_p=0.3, sol_w=[1.3], seed=5)
+    reps = O.reps_for(w)
+    nf = O.nfuncs(reps)
+    alpha = np.zeros((w.N, nf))
+    az1, _ = O.backward_step_z1(w, reps, 0, w.M, w.seed, alpha)
+    _, _, x, S = O.backward_step(w, reps, 0, w.M, w.seed, alpha.copy(), want_x=True, want_s=True)
+    h0 = O.msol_h(w, 0.0, x)
+    g1 = S - h0 * Dl                                   # g(X_1)
+    g0 = O.msol_u(w, w.T, x)                           # g(X_0)
+    dW = np.array([math.sqrt(Dl) * O.norm_icdf(O.uniform(w.seed, 0, m, 0, 1)) for m in range(w.M)])
+    Phi = np.array([O.basis_values(reps, xi) for xi in x])
+    t1 = ((g1 - g0) * dW / Dl)[:, None] * Phi
+    tm = (g1 * dW / Dl)[:, None] * Phi
+    sd1 = t1.std(axis=0) / math.sqrt(w.M)
+    sdm = tm.std(axis=0) / math.sqrt(w.M)
+    assert np.abs(az1[0] - t1.mean(axis=0)).max() <= 1e-12 * np.abs(t1).mean()
+    gl, gw = np.polynomial.legendre.leggauss(600)
+    u, wu = 0.5 * (gl + 1.0), 0.5 * gw
+    xs = np.log(u) - np.log1p(-u)
+    A, wv, p = w.sol_A, w.sol_w[0], w.sol_p
+    f = np.sin(wv * xs + p)
+    exp = np.zeros(nf)
+    exp[0] = np.sum(wu * f)
+    for r in range(1, reps.shape[0]):
+        k = reps[r, 0]
+        exp[2 * r - 1] = np.sum(wu * f * math.sqrt(2.0) * np.cos(2 * math.pi * k * u))
+        exp[2 * r] = np.sum(wu * f * math.sqrt(2.0) * np.sin(2 * math.pi * k * u))
+    exp *= -s_ * A * wv * math.exp(-0.5 * s_ * s_ * wv * wv * Dl)
+    assert np.all(np.abs(az1[0] - exp) <= 5 * sd1), np.max(np.abs(az1[0] - exp) / sd1)
+    assert np.all(sd1 < sdm), np.max(sd1 / sdm)
+    assert np.any(np.abs(-az1[0] - exp) > 5 * sd1)
+    assert np.any(np.abs(az1[0] * math.sqrt(Dl) - exp) > 5 * sd1)
+    # the spread of the one-step terms shrinks with the step (the response is
+    # an increment of g over sqrt(Delta)), that of the multistep terms does not
+    ws = w.with_(T=0.01, M=20_000)
+    _, _, xs_, Ss = O.backward_step(ws, reps, 0, ws.M, ws.seed, alpha.copy(), want_x=True, want_s=True)
+    g1s = Ss - O.msol_h(ws, 0.0, xs_) * ws.T
+    dWs = np.array([math.sqrt(ws.T) * O.norm_icdf(O.uniform(ws.seed, 0, m, 0, 1)) for m in range(ws.M)])
+    Phis = np.array([O.basis_values(reps, xi) for xi in xs_])
+    r1 = (((g1s - O.msol_u(ws, ws.T, xs_)) * dWs / ws.T)[:, None] * Phis).std(axis=0)
+    rm = ((g1s * dWs / ws.T)[:, None] * Phis).std(axis=0)
+    assert np.all(r1 < 0.25 * rm), np.max(r1 / rm)
