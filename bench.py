@@ -56,8 +56,8 @@ COUNTED_TRAFFIC = {
     # (workload, precision, M): read bytes, written bytes, sources counted on
     ("d6-hcmax16-allen-cahn", "bf16", 1 << 20): (1604766688, 260522874,
         "421db16bd2f4b9a7ce77163205370f4ba374ecddd38720fabf6a11b8318df413"),
-    ("d6-hcmax16-allen-cahn", "f64", 1 << 20): (2383270253, 1080467846,
-        "4f8425ce6d0987a6e00923c6f4d447ea941cb9a8faf5f93ade82afc688bc342c"),
+    ("d6-hcmax16-allen-cahn", "f64", 1 << 20): (2354062624, 1137811482,
+        "6620aabad9b3a9b9dedd5b453d760910011e1eaeeb5275747ec162e91acd51bb"),
 }
 
 
