@@ -145,7 +145,13 @@ PAPER_TABLES = (
     paper_benchmark(2, 100, "hc_max", 30, 2_000_000),
 )
 
-ALL = {w.name: w for w in (D2_TENSOR4, D6_HCMAX16, D10_HC1P32_ZRAT, D16_HC1P32) + PAPER_TABLES}
+# The d=6 workload with state-dependent coefficients: drift -0.1 x + 0.2
+# sin(x_l) and diffusion 0.4 (1 + 0.5 cos(x_l + 2t)) per coordinate; the
+# manufactured source keeps u = exp(-(T-t)) cos(sum x)/2 the solution.
+D6_HCMAX16_SDEP = D6_HCMAX16.with_(name="d6-hcmax16-allen-cahn-sdep", b2=[0.2] * 6, sigma_v=[0.5] * 6,
+                                   sigma_omega=2.0)
+
+ALL = {w.name: w for w in (D2_TENSOR4, D6_HCMAX16, D6_HCMAX16_SDEP, D10_HC1P32_ZRAT, D16_HC1P32) + PAPER_TABLES}
 
 
 def batched_instances(n: int = 256, seed: int = 4):
